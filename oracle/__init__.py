@@ -1,0 +1,229 @@
+"""FP64 CPU oracle for the phase-field FEM step -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never does, and this
+package never imports the product library: the two share no code.
+
+The arithmetic lives in ``pf_oracle.c`` (a plain Q1 element loop, built with
+``gcc -O2 -ffp-contract=off``); this module only marshals NumPy float64 arrays
+into it.  See the header of ``pf_oracle.c`` for what each routine follows in
+the paper (Eqs. 1, 5-6, 9-14, 18 and Supplementary Note 2).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c")]
+
+PERIODIC, NOFLUX = 0, 1
+AC, CH = 0, 1
+F_SYM, F_01 = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared",
+           "-fPIC", "-o", _SO + ".tmp"] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Problem(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("model", ct.c_int32),
+                ("fe", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
+                ("W", ct.c_double), ("kappa", ct.c_double), ("mob", ct.c_double)]
+
+
+@dataclass
+class Problem:
+    """Problem statement: grid, boundary condition, model, free energy, theta."""
+    n: tuple
+    model: int = AC
+    fe: int = F_SYM
+    bc: int = PERIODIC
+    h: float = 1.0
+    W: float = 1.0
+    kappa: float = 1.0
+    mob: float = 1.0
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def nnodes(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def ndof(self) -> int:
+        return (2 if self.model == CH else 1) * self.nnodes
+
+    def _c(self) -> _Problem:
+        n3 = list(self.n) + [1] * (3 - len(self.n))
+        return _Problem(self.dim, self.bc, self.model, self.fe, (ct.c_int64 * 3)(*n3),
+                        self.h, self.W, self.kappa, self.mob)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = ct.CDLL(_SO)
+        P = ct.POINTER(_Problem)
+        D = ct.POINTER(ct.c_double)
+        i64, f64, i32 = ct.c_int64, ct.c_double, ct.c_int
+        sig = {
+            "orc_ndof": (i64, [P]),
+            "orc_lumped_mass": (i32, [P, D]),
+            "orc_energy": (f64, [P, D]),
+            "orc_total_mass": (f64, [P, D]),
+            "orc_residual": (i32, [P, D, D]),
+            "orc_explicit": (i32, [P, f64, i64, D]),
+            "orc_be_residual": (i32, [P, f64, D, D, D]),
+            "orc_jvp": (i32, [P, f64, D, D, D]),
+            "orc_jvp_t": (i32, [P, f64, D, D, D]),
+            "orc_dr_dtheta": (i32, [P, D, D, D]),
+            "orc_linear_solve": (i32, [P, f64, D, i32, D, D, i32, f64]),
+            "orc_newton_be": (i32, [P, f64, D, D, f64, i32, i32, f64,
+                                    ct.POINTER(ct.c_int), D]),
+            "orc_explicit_adjoint": (i32, [P, f64, i64, D, D, D, D]),
+            "orc_newton_adjoint": (i32, [P, f64, D, D, D, D, i32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        if hasattr(_lib, "orc_conv3x3_fwd"):
+            _bind_conv(_lib)
+    return _lib
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _arr(x, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def lumped_mass(p: Problem) -> np.ndarray:
+    m = np.zeros(p.nnodes)
+    lib().orc_lumped_mass(ct.byref(p._c()), _d(m))
+    return m
+
+
+def energy(p: Problem, U) -> float:
+    U = _arr(U)
+    return lib().orc_energy(ct.byref(p._c()), _d(U))
+
+
+def total_mass(p: Problem, U) -> float:
+    U = _arr(U)
+    return lib().orc_total_mass(ct.byref(p._c()), _d(U))
+
+
+def residual(p: Problem, U) -> np.ndarray:
+    """r(U, theta) of Eq. 11 (no mass term; Cahn-Hilliard mu-row holds m mu - g(c))."""
+    U = _arr(U, p.ndof)
+    r = np.zeros(p.ndof)
+    lib().orc_residual(ct.byref(p._c()), _d(U), _d(r))
+    return r
+
+
+def explicit(p: Problem, U, dt: float, nsteps: int) -> np.ndarray:
+    """nsteps of the lumped-mass forward-Euler step (Eq. 12); returns a new array."""
+    U = _arr(U, p.ndof).copy()
+    lib().orc_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U))
+    return U
+
+
+def be_residual(p: Problem, dt: float, Uold, U) -> np.ndarray:
+    Uold, U = _arr(Uold, p.ndof), _arr(U, p.ndof)
+    R = np.zeros(p.ndof)
+    lib().orc_be_residual(ct.byref(p._c()), dt, _d(Uold), _d(U), _d(R))
+    return R
+
+
+def jvp(p: Problem, inv_dt: float, U, v) -> np.ndarray:
+    U, v = _arr(U, p.ndof), _arr(v, p.ndof)
+    out = np.zeros(p.ndof)
+    lib().orc_jvp(ct.byref(p._c()), inv_dt, _d(U), _d(v), _d(out))
+    return out
+
+
+def jvp_t(p: Problem, inv_dt: float, U, w) -> np.ndarray:
+    U, w = _arr(U, p.ndof), _arr(w, p.ndof)
+    out = np.zeros(p.ndof)
+    lib().orc_jvp_t(ct.byref(p._c()), inv_dt, _d(U), _d(w), _d(out))
+    return out
+
+
+def dr_dtheta(p: Problem, U, w) -> np.ndarray:
+    """w^T dr/dtheta for theta = (mobility, kappa, W)."""
+    U, w = _arr(U, p.ndof), _arr(w, p.ndof)
+    g = np.zeros(3)
+    lib().orc_dr_dtheta(ct.byref(p._c()), _d(U), _d(w), _d(g))
+    return g
+
+
+def linear_solve(p: Problem, inv_dt: float, U, b, transpose=False, solver=0, lin_rtol=1e-13):
+    U, b = _arr(U, p.ndof), _arr(b, p.ndof)
+    x = np.zeros(p.ndof)
+    lib().orc_linear_solve(ct.byref(p._c()), inv_dt, _d(U), int(transpose), _d(b), _d(x),
+                           int(solver), lin_rtol)
+    return x
+
+
+def newton_be(p: Problem, dt: float, Uold, U0=None, rtol=1e-8, maxit=20, solver=0,
+              lin_rtol=1e-12):
+    """One backward-Euler step by Newton (Eqs. 13-14). Returns (U, converged, its, hist)."""
+    Uold = _arr(Uold, p.ndof)
+    U = (Uold if U0 is None else _arr(U0, p.ndof)).copy()
+    hist = np.zeros(maxit + 1)
+    its = ct.c_int(0)
+    rc = lib().orc_newton_be(ct.byref(p._c()), dt, _d(Uold), _d(U), rtol, maxit, solver,
+                             lin_rtol, ct.byref(its), _d(hist))
+    return U, rc == 0, its.value, hist[: its.value + 1]
+
+
+def explicit_adjoint(p: Problem, dt: float, nsteps: int, U0, gU):
+    """Discrete adjoint of `explicit`: returns (theta_bar[3], U0_bar)."""
+    U0 = _arr(U0, p.ndof)
+    gU = _arr(gU)
+    tb = np.zeros(3)
+    ub = np.zeros(p.nnodes)
+    lib().orc_explicit_adjoint(ct.byref(p._c()), dt, int(nsteps), _d(U0), _d(gU), _d(tb),
+                               _d(ub))
+    return tb, ub
+
+
+def newton_adjoint(p: Problem, dt: float, U, gU, solver=0):
+    """Adjoint of one BE step at its root U: returns (theta_bar[3], Uold_bar)."""
+    U, gU = _arr(U, p.ndof), _arr(gU, p.ndof)
+    tb = np.zeros(3)
+    ub = np.zeros(p.ndof)
+    lib().orc_newton_adjoint(ct.byref(p._c()), dt, _d(U), _d(gU), _d(ub), _d(tb), int(solver))
+    return tb, ub
+
+
+def _bind_conv(L):  # filled in by the conv oracle section
+    pass
