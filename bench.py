@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Benchmark: explicit Cahn-Hilliard split step on a 2048x2048 periodic grid.
+
+Workload (one GPU): f = W c^2 (1-c)^2 with W = 1, kappa = 2, M = 1, h = 1,
+c0 = 0.5 + U(-0.01, 0.01) (seed 0), dt = 0.01, FP32 fields; 4 194 304 DOF
+(the time-integrated c field).  A step is one fused launch of the HIP kernel
+(residual + lumped-mass forward-Euler update, Eqs. 9-12).  Inputs are resident
+in HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0):
+  metric/value/unit: DOF-steps per second over the timed region,
+  roofline: achieved algorithmic bandwidth of the step kernel vs 8 TB/s,
+  cpu_baseline: the FP64 CPU reference timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE_STEP = 8  # read c, write c (FP32); mu never leaves the chip
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=2048, help="grid side (default: the 2048^2 workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "ch2048_traffic.json"))
+    return ap.parse_args()
+
+
+def cpu_baseline(n, steps):
+    """FP64 oracle on the same workload: `steps` explicit split steps at full size."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2601_06079_amd import inputs as I
+
+    cfg = dict(I.CH2048, n=(n, n))
+    o = O.Problem(n=(n, n), model=O.CH, fe=O.F_01, W=1.0, kappa=2.0, mob=1.0, h=1.0)
+    U0 = I.initial_state(cfg, seed=0, dtype=np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    O.explicit(o, U0, cfg["dt"], steps)
+    el = time.perf_counter() - t0
+    return {"value": n * n * steps / el, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} explicit split steps of the {n}x{n} workload, single-threaded "
+                      f"FP64 element loop ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
+                                   "part of this build (--gpus must be 1)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+
+    n = args.n
+    cfg = dict(I.CH2048, n=(n, n))
+    N = n * n
+    p = S.Problem(n=(n, n), model=A.CAHN_HILLIARD, fe=A.F_01, dtype=torch.float32, W=1.0,
+                  kappa=2.0, mobility=1.0, h=1.0)
+    U = torch.as_tensor(I.initial_state(cfg, seed=0, dtype="float32"), device="cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    dt = cfg["dt"]
+    stream = torch.cuda.current_stream()
+
+    S.step_explicit(p, U, dt, args.warmup, ws)
+    torch.cuda.synchronize()
+
+    # timed region: K steps in one call (the library enqueues K fused launches)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    S.step_explicit(p, U, dt, args.steps, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    value = N * args.steps / (ms_total * 1e-3)
+
+    # per-launch duration of the step kernel: events bracket single-step calls
+    # on the same stream (one fused launch each, plus the mu epilogue kernel
+    # that a single-step call adds; that one is measured and subtracted)
+    reps = 50
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    evm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for i in range(reps):
+        ev[i][0].record(stream)
+        S.step_explicit(p, U, dt, 2, ws)  # two fused launches + one mu epilogue
+        ev[i][1].record(stream)
+        evm[i][0].record(stream)
+        S.step_explicit(p, U, dt, 0, ws)  # the mu epilogue alone
+        evm[i][1].record(stream)
+    torch.cuda.synchronize()
+    two = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+    epi = sorted(a.elapsed_time(b) for a, b in evm)[reps // 2]
+    kern_ms = max(two - epi, 1e-6) / 2.0
+    achieved = BYTES_PER_NODE_STEP * N / (kern_ms * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            t = json.load(open(args.traffic))
+            if t.get("n") == n:
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": "DOF-steps/sec (explicit CH, 4.19M DOF)",
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D Cahn-Hilliard spinodal, {n}x{n} periodic, explicit split step, "
+                               "dt=0.01, W=1, kappa=2, M=1", "dof": N, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_explicit2d<float, CH>", "kernel_ms": kern_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * pf.h -- C ABI of the MI355X (gfx950) phase-field step library libpfhip.so.
+ *
+ * The library evaluates and advances the finite-element phase-field models of
+ * arXiv 2601.06079 on structured 2-D / 3-D grids:
+ *   Allen-Cahn       d eta/dt = -L (f'(eta) - kappa lap eta)              (Sec. 2.1, Eq. 1, Eq. 5)
+ *   Cahn-Hilliard    dc/dt = div(M grad mu), mu = f'(c) - kappa lap c     (Sec. 2.2, Eqs. 9-10)
+ * semi-discretised as M dU/dt + r(U, theta) = 0 (Eq. 11) with Q1 (bi/tri-linear)
+ * Lagrange elements, 2-point Gauss-Legendre quadrature per axis and the
+ * row-sum lumped mass matrix (nodal mass m = h^d on periodic grids).
+ *
+ * Conventions shared by every entry point
+ *   - Fields are contiguous device arrays, node index i + n0*(j + n1*k)
+ *     (x fastest).  Cahn-Hilliard states U hold the c plane at offset 0 and
+ *     the mu plane at offset N (N = number of nodes).  Element type is
+ *     float (PF_F32) or double (PF_F64) as pf_problem.dtype says.
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     on any compute path and never frees caller memory.  Scratch needs are
+ *     reported by pf_workspace_size and passed in as `ws` (device memory,
+ *     256-byte aligned).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All
+ *     work is enqueued on it; calls return before the work finishes unless
+ *     stated otherwise.
+ *   - Return value is a pf_status.  PF_EINVAL is returned before anything is
+ *     enqueued for a malformed problem or argument; pf_last_error() then
+ *     gives a thread-local message.  No C++ exception crosses this ABI.
+ *   - Thread safety: calls on different streams from different host threads
+ *     are independent; concurrent calls that share buffers race.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pf_status {
+    PF_OK = 0,
+    PF_EINVAL = 1,      /* malformed problem or argument; nothing enqueued */
+    PF_EDEVICE = 2,     /* a HIP runtime call failed (message in pf_last_error) */
+    PF_ENOCONV = 3,     /* Newton did not converge; U holds the last iterate */
+    PF_ENONFINITE = 4,  /* a non-finite residual norm was met */
+    PF_EUNSUPPORTED = 5 /* valid request this build does not implement */
+} pf_status;
+
+enum { PF_PERIODIC = 0, PF_NOFLUX = 1 };       /* boundary condition (Supp. Note 3) */
+enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1 };
+enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
+       PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
+enum { PF_F32 = 0, PF_F64 = 1 };
+
+/* Problem statement: grid, boundary condition, model, free energy and the
+ * material parameters theta = (mobility, kappa, W) of Eqs. 1, 5-6, 9-10. */
+typedef struct pf_problem {
+    int32_t dim;      /* 2 or 3 */
+    int32_t bc;       /* PF_PERIODIC (PF_NOFLUX: PF_EUNSUPPORTED in this build) */
+    int32_t model;    /* PF_ALLEN_CAHN or PF_CAHN_HILLIARD */
+    int32_t fe;       /* PF_F_SYM or PF_F_01 */
+    int32_t dtype;    /* PF_F32 or PF_F64 */
+    int32_t reserved; /* must be 0 */
+    int64_t n[3];     /* nodes per axis, each >= 2 (n[2] ignored when dim == 2) */
+    double h;         /* grid spacing > 0 */
+    double W;         /* barrier height of f */
+    double kappa;     /* gradient-energy coefficient */
+    double mobility;  /* L (Allen-Cahn) or M (Cahn-Hilliard) */
+} pf_problem;
+
+/* Operation codes for pf_workspace_size. */
+enum {
+    PF_OP_RESIDUAL = 0,
+    PF_OP_STEP_EXPLICIT = 1,
+    PF_OP_ENERGY = 2,
+    PF_OP_NEWTON = 3,
+    PF_OP_VJP = 4,
+    PF_OP_JVP = 5
+};
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* pf_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int pf_version(void);
+
+/* Launch-shape overrides, process-global (value 0 restores the automatic
+ * choice).  Used by the autotuner; results never depend on them.
+ *   PF_TUNE_STREAM2D_ROWS: rows per wavefront of the fused 2-D explicit kernel. */
+enum { PF_TUNE_STREAM2D_ROWS = 0 };
+int pf_tune_set(int key, int value);
+int pf_tune_get(int key, int* value);
+
+/* Bytes of device scratch `ws` that operation `op` needs for problem p
+ * (0 when none).  Host-only; enqueues nothing. */
+int pf_workspace_size(const pf_problem* p, int op, size_t* bytes);
+
+/* r = r(U, theta) of Eq. 11 (no mass/time term).
+ *   Allen-Cahn:     r = L [ N(eta) + kappa K eta ]
+ *   Cahn-Hilliard:  r_c  = M K mu
+ *                   r_mu = m mu - [ N(c) + kappa K c ]
+ * where N(u)_a = sum_e sum_q |J| f'(u_q) phi_a(q) (Gauss points q) and K is
+ * the Q1 stiffness matrix.  With this r the implicit residual of Eq. 14 is
+ * R = M (U - U_old)/dt + r(U) with mass matrix diag(m) (Allen-Cahn) or
+ * diag(m, 0) (Cahn-Hilliard).  U and r: device, ndof elements, must not
+ * alias.  Asynchronous. */
+int pf_residual(const pf_problem* p, const void* U, void* r, void* stream);
+
+/* nsteps forward-Euler steps of Eq. 12 with the lumped mass, in place on U:
+ *   Allen-Cahn:     eta <- eta - dt r(eta) / m
+ *   Cahn-Hilliard:  mu <- [N(c) + kappa K c] / m, then c <- c - dt M K mu / m
+ *                   (the algebraic mu-row of the split form solved each step);
+ *                   on return the mu plane holds [N(c) + kappa K c]/m of the
+ *                   final c.
+ * ws: device scratch of pf_workspace_size(PF_OP_STEP_EXPLICIT) bytes (one
+ * ping-pong field).  nsteps >= 0, dt > 0.  Asynchronous. */
+int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
+                     void* stream);
+
+/* out[0] = E_h(U) = sum_e sum_q |J| [ f(c_q) + kappa/2 |grad c_q|^2 ]  (Eqs. 5-6)
+ * out[1] = sum_a m_a c_a  (total conserved quantity)
+ * out: device pointer to 2 doubles; accumulation in FP64 with a fixed
+ * reduction order (bitwise reproducible).  ws: pf_workspace_size(PF_OP_ENERGY).
+ * Asynchronous. */
+int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* stream);
+
+/* Jv = (dR/dU) v for R = inv_dt M (U - U_old) + r(U) (Eq. 14; inv_dt = 0
+ * gives dr/dU):
+ *   Allen-Cahn:     Jv = inv_dt m v + L [ N'(eta) v + kappa K v ]
+ *   Cahn-Hilliard:  Jv_c  = inv_dt m v_c + M K v_mu
+ *                   Jv_mu = m v_mu - [ N'(c) v_c + kappa K v_c ]
+ * N'(u) v = sum_e sum_q |J| f''(u_q) v_q phi_a(q).  Matrix-free (the Jacobian
+ * of Sec. 2.3 is never formed).  U, v, Jv: device, ndof elements; Jv must not
+ * alias U or v.  Asynchronous. */
+int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv,
+           void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Backward-Euler Newton step (Eqs. 13-14, Sec. 2.3)                        */
+/* ---------------------------------------------------------------------- */
+enum { PF_PRECOND_NONE = 0, PF_PRECOND_JACOBI = 1 /* point (AC) / 2x2 block (CH) */ };
+
+typedef struct pf_newton_opts {
+    double rtol;            /* stop when ||R||_2 <= rtol ||R(U_initial)||_2 (default 1e-8) */
+    double atol;            /* or ||R||_2 <= atol (default 0) */
+    int32_t max_newton;     /* Newton corrections (default 20) */
+    int32_t gmres_restart;  /* Krylov dimension m of GMRES(m), 1..64 (default 30) */
+    int32_t gmres_max_its;  /* Arnoldi steps per Newton correction (default 600) */
+    int32_t precond;        /* PF_PRECOND_* (default PF_PRECOND_JACOBI) */
+    double lin_rtol_max;    /* inexact-Newton forcing: linear rtol = clamp(0.1 ||R_k||/||R_0||, */
+    double lin_rtol_min;    /*   lin_rtol_min, lin_rtol_max) (defaults 1e-2, 1e-6) */
+    int32_t stagnation;     /* 1: also stop when the FP32 rounding floor is reached (see report) */
+    int32_t reserved;
+} pf_newton_opts;
+
+typedef struct pf_newton_report {
+    int32_t newton_its;      /* corrections applied */
+    int32_t gmres_its;       /* Arnoldi steps over all corrections */
+    int32_t converged;       /* 1 if a stop test passed */
+    int32_t reason;          /* 0 rtol, 1 atol, 2 rounding floor, -1 max_newton, -2 non-finite */
+    double res_norm[33];     /* ||R||_2 per iterate (FP64), entries 0..newton_its (<= 32 kept) */
+} pf_newton_report;
+
+/* Fill opts with the defaults listed above. */
+void pf_newton_default_opts(pf_newton_opts* o);
+
+/* One backward-Euler step: solve R(U) = M (U - U_old)/dt + r(U) = 0 for U by
+ * Newton-Raphson with matrix-free Jacobian-vector products inside restarted,
+ * right-preconditioned GMRES (classical Gram-Schmidt with one
+ * re-orthogonalisation; FP64 dot products and Hessenberg even for PF_F32
+ * fields).  U holds the initial guess on entry and the last iterate on exit.
+ * U_old is not modified.  ws: pf_workspace_size(PF_OP_NEWTON) bytes.
+ * Host-synchronous: returns when the step is done (PF_OK or PF_ENOCONV /
+ * PF_ENONFINITE with rep filled).  rep may be NULL. */
+int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
+                   const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Sensitivities (Eq. 18, Supp. Note 2, Eqs. II.1-II.6)                     */
+/* ---------------------------------------------------------------------- */
+enum { PF_VJP_RESIDUAL = 0, PF_VJP_EXPLICIT_STEP = 1, PF_VJP_NEWTON_STEP = 2 };
+
+/* Vector-Jacobian products of one building block, accumulated into Ubar and
+ * theta_bar (device pointer to 3 doubles: mobility, kappa, W):
+ *   PF_VJP_RESIDUAL:       Ubar += (dr/dU)^T vbar,   theta_bar += (dr/dtheta)^T vbar   at U
+ *   PF_VJP_EXPLICIT_STEP:  for S(U) = one pf_step_explicit step from U:
+ *                          Ubar += (dS/dU)^T vbar,  theta_bar += (dS/dtheta)^T vbar
+ *                          (Cahn-Hilliard: c planes only; mu is a derived output)
+ *   PF_VJP_NEWTON_STEP:    U is the converged root of one backward-Euler step:
+ *                          solve (dR/dU)^T lambda = vbar (GMRES, same opts as
+ *                          the forward step), then Ubar(U_old) += (M/dt) lambda,
+ *                          theta_bar -= (dr/dtheta)^T lambda   (II.5-II.6).
+ * theta_bar accumulates in FP64 with a fixed reduction order.  dt is ignored
+ * for PF_VJP_RESIDUAL.  ws: pf_workspace_size(PF_OP_VJP).  Asynchronous,
+ * except PF_VJP_NEWTON_STEP which is host-synchronous like pf_newton_step. */
+int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* vbar,
+           void* Ubar, double* theta_bar, void* ws, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -1,0 +1,234 @@
+// api.hip -- the extern "C" boundary of libpfhip.so (declared in include/pf.h).
+//
+// Every entry point validates its arguments on the host before anything is
+// enqueued, converts the problem statement into kernel parameters and
+// launches on the caller's stream.  No exception crosses the ABI; errors are
+// reported as pf_status plus a thread-local message.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/pf.h"
+#include "api_internal.hpp"
+#include "kernels.hpp"
+
+namespace pfapi {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return PF_OK;
+}
+
+int validate(const pf_problem* p)
+{
+    if (!p) return fail(PF_EINVAL, "problem is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(PF_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD)
+        return fail(PF_EINVAL, "unknown model %d", p->model);
+    if (p->fe != PF_F_SYM && p->fe != PF_F_01) return fail(PF_EINVAL, "unknown free energy %d", p->fe);
+    if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->reserved != 0) return fail(PF_EINVAL, "reserved field must be 0");
+    long long N = 1;
+    for (int k = 0; k < p->dim; ++k) {
+        if (p->n[k] < 2) return fail(PF_EINVAL, "n[%d] = %lld must be >= 2", k, (long long)p->n[k]);
+        if (p->n[k] > (1ll << 30)) return fail(PF_EINVAL, "n[%d] too large", k);
+        N *= p->n[k];
+        if (N > (1ll << 40)) return fail(PF_EINVAL, "grid too large");
+    }
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(PF_EINVAL, "h must be finite and > 0");
+    if (!std::isfinite(p->W) || !std::isfinite(p->kappa) || !std::isfinite(p->mobility))
+        return fail(PF_EINVAL, "W, kappa and mobility must be finite");
+    if (p->bc == PF_NOFLUX)
+        return fail(PF_EUNSUPPORTED, "no-flux boundaries are not implemented in this build");
+    if (p->bc != PF_PERIODIC) return fail(PF_EINVAL, "unknown boundary condition %d", p->bc);
+    return PF_OK;
+}
+
+int check_ptr(const void* ptr, const pf_problem* p, const char* name)
+{
+    if (!ptr) return fail(PF_EINVAL, "%s is NULL", name);
+    const size_t al = p->dtype == PF_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(ptr) % al)
+        return fail(PF_EINVAL, "%s is not %zu-byte aligned", name, al);
+    return PF_OK;
+}
+
+pfk::Geom geom_of(const pf_problem* p)
+{
+    pfk::Geom g{};
+    g.dim = p->dim;
+    g.N = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = k < p->dim ? (int)p->n[k] : 1;
+        g.N *= g.n[k];
+    }
+    g.h = p->h;
+    return g;
+}
+
+long long ndof(const pf_problem* p)
+{
+    const pfk::Geom g = geom_of(p);
+    return (p->model == PF_CAHN_HILLIARD ? 2 : 1) * g.N;
+}
+
+size_t elem_size(const pf_problem* p) { return p->dtype == PF_F64 ? 8 : 4; }
+
+}  // namespace pfapi
+
+using namespace pfapi;
+
+namespace {
+
+template <typename T>
+int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    T* c = U;
+    T* other = ws;
+    T* cur = c;
+    // the fused 2-D kernel addresses a field with 32-bit buffer offsets
+    const bool fused2d = p->dim == 2 && (size_t)g.N * sizeof(T) < (size_t(1) << 31);
+    if (fused2d) {
+        pfk::Stream2DConfig cfg{stream2d_rows(p)};
+        for (int64_t st = 0; st < nsteps; ++st) {
+            pfk::launch_explicit2d<T>(g, p->model, f, p->kappa, p->mobility, dt, cur, other, cfg, s);
+            std::swap(cur, other);
+        }
+    } else if (p->model == PF_ALLEN_CAHN) {
+        // node-centric path: 3-D, and 2-D fields of 2 GiB or more
+        for (int64_t st = 0; st < nsteps; ++st) {
+            pfk::launch_ac_step<T>(g, f, p->kappa, dt * p->mobility, cur, other, s);
+            std::swap(cur, other);
+        }
+    } else {
+        T* mu = U + g.N;
+        for (int64_t st = 0; st < nsteps; ++st) {
+            pfk::launch_chem<T>(g, f, p->kappa, cur, mu, s);
+            pfk::launch_ch_update<T>(g, dt * p->mobility, cur, mu, other, s);
+            std::swap(cur, other);
+        }
+    }
+    if (int rc = check_launch("explicit step")) return rc;
+    if (cur != c) {
+        if (hipMemcpyAsync(c, cur, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return check_launch("explicit step copy-back");
+    }
+    if (p->model == PF_CAHN_HILLIARD) pfk::launch_chem<T>(g, f, p->kappa, c, U + g.N, s);
+    return check_launch("explicit step");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_last_error.c_str(); }
+
+int pf_version(void) { return 100; }
+
+int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
+{
+    if (int rc = validate(p)) return rc;
+    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+    const pfk::Geom g = geom_of(p);
+    const size_t es = elem_size(p);
+    size_t b = 0;
+    switch (op) {
+        case PF_OP_RESIDUAL:
+        case PF_OP_JVP: b = 0; break;
+        case PF_OP_STEP_EXPLICIT: b = (size_t)g.N * es; break;
+        case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
+        case PF_OP_NEWTON: b = newton_workspace_bytes(p, 30); break;
+        case PF_OP_VJP: b = vjp_workspace_bytes(p); break;
+        default: return fail(PF_EINVAL, "unknown op %d", op);
+    }
+    *bytes = b;
+    return PF_OK;
+}
+
+int pf_residual(const pf_problem* p, const void* U, void* r, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (int rc = check_ptr(r, p, "r")) return rc;
+    if (U == r) return fail(PF_EINVAL, "U and r must not alias");
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        pfk::launch_residual<float>(g, p->model, f, p->kappa, p->mobility, (const float*)U,
+                                    (float*)r, s);
+    else
+        pfk::launch_residual<double>(g, p->model, f, p->kappa, p->mobility, (const double*)U,
+                                     (double*)r, s);
+    return check_launch("pf_residual");
+}
+
+int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
+                     void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (int rc = check_ptr(ws, p, "ws")) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == PF_F32) return step_explicit_t<float>(p, dt, nsteps, (float*)U, (float*)ws, s);
+    return step_explicit_t<double>(p, dt, nsteps, (double*)U, (double*)ws, s);
+}
+
+int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 8) return fail(PF_EINVAL, "ws is NULL or misaligned");
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        pfk::launch_energy<float>(g, f, p->kappa, (const float*)U, (double*)ws, out, s);
+    else
+        pfk::launch_energy<double>(g, f, p->kappa, (const double*)U, (double*)ws, out, s);
+    return check_launch("pf_energy");
+}
+
+int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv, void* stream)
+{
+    if (int rc = validate(p)) return rc;
+    if (!std::isfinite(inv_dt) || inv_dt < 0.0) return fail(PF_EINVAL, "inv_dt must be finite and >= 0");
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (int rc = check_ptr(v, p, "v")) return rc;
+    if (int rc = check_ptr(Jv, p, "Jv")) return rc;
+    if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        pfk::launch_jvp<float>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const float*)U,
+                               (const float*)v, (float*)Jv, s);
+    else
+        pfk::launch_jvp<double>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const double*)U,
+                                (const double*)v, (double*)Jv, s);
+    return check_launch("pf_jvp");
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// k_stream2d.hip -- fused explicit step (Eq. 12) for 2-D periodic grids.
+//
+// Layout of the work.  One 64-lane wavefront owns a strip of 64 consecutive
+// columns (lane = column) and marches upward through a chunk of TY rows,
+// keeping every intermediate in registers:
+//   - x-neighbours come from the adjacent lane through DPP wave shifts (no LDS,
+//     no shared-memory traffic);
+//   - y-neighbours are the previous rows, held in a short register window;
+//   - each input row is read from HBM once per wave, PF rows ahead of use.
+// A strip outputs its 64 - 2H interior columns (H = 1 for Allen-Cahn, 2 for
+// the Cahn-Hilliard split step, whose mu must be known at x +- 1); the H halo
+// lanes on each side recompute what they need.  Chunks overlap by H rows in
+// the same way.  No LDS, no atomics, no inter-wave synchronisation.
+//
+// Per element row (r-1, r) the Q1 quadrature is sum-factorised:
+//   X_r[qx]   = sum_ax B[qx][ax] c(x+ax, r)              (2 values / node)
+//   c_q       = sum_ay B[qy][ay] X_{r-1+ay}[qx]           (4 quad values / element)
+//   G[qx][ay] = sum_qy B[qy][ay] f'(c_q)                  (y-scatter)
+//   N(x, r-1) = sum_qx B[qx][1] Hsum(x-1)[qx] + B[qx][0] Hsum(x)[qx]   (x-scatter)
+// with B = [[GP, GM], [GM, GP]].  The gradient term is the closed Q1 stencil
+// K c = (9 c - sum_{3x3} c) / 3 (2-D, h-independent).
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace pfk {
+namespace {
+
+template <typename T>
+struct Coef {
+    T a1, a2, a3;  // cubic f' with every constant factor folded in
+    T beta;        // multiplies (9 c - box3x3(c))
+    T gamma;       // Cahn-Hilliard: multiplies (9 mu - box3x3(mu))
+};
+
+constexpr int PF = 8;  // rows in flight per wave
+
+// raw buffer access: the row offset is a scalar (one SGPR), the column offset
+// a per-lane VGPR set once, so no per-row address arithmetic runs on the VALU.
+// Out-of-range addresses read 0 and drop stores (the launcher keeps every
+// access in range; this is the hardware's own bounds check on top).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    v2u w;
+    w.x = (unsigned)__double2loint(v);
+    w.y = (unsigned)__double2hiint(v);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
+}
+
+// MODEL 0: Allen-Cahn   out = c - [dt L |J|/m] N'(c) - [dt L kappa/(3m)] (9c - box c)
+// MODEL 1: Cahn-Hilliard mu = [|J|/m] N'(c) + [kappa/(3m)] (9c - box c)
+//                        out = c - [dt M/(3m)] (9 mu - box mu)
+// N' is the quadrature sum with the scaled cubic (a1, a2, a3).
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
+                                                    int nx, int ny, int nstrips, int nwaves, int ty,
+                                                    unsigned bytes, Coef<T> k)
+{
+    constexpr int H = MODEL == 0 ? 1 : 2;
+    constexpr int OUTW = WAVE - 2 * H;
+    const int lane = threadIdx.x & (WAVE - 1);
+    // wave index made provably uniform so that all row bookkeeping stays scalar
+    const int wave = (int)(blockIdx.x * (blockDim.x / WAVE)) +
+                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if (wave >= nwaves) return;  // uniform per wave
+    const int strip = wave % nstrips;
+    const int chunk = wave / nstrips;
+    const int x0 = strip * OUTW;
+    const int xl = x0 - H + lane;
+    int x = xl % nx;
+    if (x < 0) x += nx;
+    const bool out_lane = lane >= H && lane < WAVE - H && xl < nx;
+    const int y0 = chunk * ty;
+    const int y1 = min(y0 + ty, ny);
+    const int iters = (y1 - y0) + 2 * H;  // rows y0-H .. y1+H-1
+    const int rowb = nx * (int)sizeof(T);  // bytes per row
+    const int vx = x * (int)sizeof(T);
+    const auto rin = make_rsrc(in, bytes);
+    const auto rout = make_rsrc(out, bytes);
+
+    const T gp = (T)GP, gm = (T)GM;
+
+    // register window (see the header comment for the pipeline)
+    T c_m1 = 0, c_m2 = 0;        // c at rows r-1, r-2
+    T s3_m1 = 0, s3_m2 = 0;      // 3-point x-sums of c at rows r-1, r-2
+    T xl_m1 = 0, xr_m1 = 0;      // x-interpolated values of row r-1
+    T guL_m1 = 0, guR_m1 = 0;    // upward scatter of element row (r-2, r-1)
+    T mu_m1 = 0;                 // CH: mu at row r-2
+    T s3mu_m1 = 0, s3mu_m2 = 0;  // CH: x-sums of mu at rows r-2, r-3
+
+    // One row of the pipeline: cc is c at the newest row r = y0 - H + t; the
+    // finished output row is y0 - 2H + t (AC: r - 1, CH: r - 2).
+    auto step = [&](T cc, int t, bool store) {
+        const T cl = from_left(cc), cr = from_right(cc);
+        const T s3 = cl + cc + cr;
+        const T d = cr - cc;
+        const T xl_0 = fmaT(gm, d, cc), xr_0 = fmaT(gp, d, cc);
+        const T e0 = xl_0 - xl_m1, e1 = xr_0 - xr_m1;
+        const T FL0 = cubic(fmaT(gm, e0, xl_m1), k.a1, k.a2, k.a3);
+        const T FL1 = cubic(fmaT(gp, e0, xl_m1), k.a1, k.a2, k.a3);
+        const T FR0 = cubic(fmaT(gm, e1, xr_m1), k.a1, k.a2, k.a3);
+        const T FR1 = cubic(fmaT(gp, e1, xr_m1), k.a1, k.a2, k.a3);
+        const T dL = FL0 - FL1, dR = FR0 - FR1;
+        const T gdL = fmaT(gp, dL, FL1), guL = fmaT(gm, dL, FL1);
+        const T gdR = fmaT(gp, dR, FR1), guR = fmaT(gm, dR, FR1);
+        const T HL = guL_m1 + gdL, HR = guR_m1 + gdR;  // node row r-1 complete
+        const T dH = HL - HR;
+        const T pl = fmaT(gp, dH, HR), pr = fmaT(gm, dH, HR);
+        const T Nn = pl + from_left(pr);
+        const T box = s3_m2 + s3_m1 + s3;
+        const T lap = fmaT((T)9, c_m1, -box);
+        T v;
+        if constexpr (MODEL == 0) {
+            v = c_m1 - Nn - k.beta * lap;
+        } else {
+            const T mu = fmaT(k.beta, lap, Nn);  // mu at row r-1
+            const T s3mu = from_left(mu) + mu + from_right(mu);
+            const T boxmu = s3mu_m2 + s3mu_m1 + s3mu;  // around row r-2
+            v = c_m2 - k.gamma * fmaT((T)9, mu_m1, -boxmu);
+            s3mu_m2 = s3mu_m1;
+            s3mu_m1 = s3mu;
+            mu_m1 = mu;
+        }
+        if (store && out_lane) bstore(v, rout, vx, (y0 - 2 * H + t) * rowb);
+        c_m2 = c_m1;
+        c_m1 = cc;
+        s3_m2 = s3_m1;
+        s3_m1 = s3;
+        xl_m1 = xl_0;
+        xr_m1 = xr_0;
+        guL_m1 = guL;
+        guR_m1 = guR;
+    };
+
+    // prefetch ring: slot (t mod PF) holds row y0 - H + t
+    T ring[PF];
+    int rl = y0 - H;
+    while (rl < 0) rl += ny;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        ring[u] = u < iters ? bload<T>(rin, vx, rl * rowb) : (T)0;
+        if (++rl == ny) rl = 0;
+    }
+    // first block: warm-up rows (no store for t < 2H)
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        if (u < iters) {
+            const T cc = ring[u];
+            if (u + PF < iters) {
+                ring[u] = bload<T>(rin, vx, rl * rowb);
+                if (++rl == ny) rl = 0;
+            }
+            step(cc, u, u >= 2 * H);
+        }
+    }
+    // steady state: every row loads PF ahead and stores
+    int t0 = PF;
+    for (; t0 + 2 * PF <= iters; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const T cc = ring[u];
+            ring[u] = bload<T>(rin, vx, rl * rowb);
+            if (++rl == ny) rl = 0;
+            step(cc, t0 + u, true);
+        }
+    }
+    // tail: fewer than 2 PF rows left
+#pragma unroll
+    for (int u = 0; u < 2 * PF; ++u) {
+        const int t = t0 + u;
+        if (t < iters) {
+            const T cc = ring[u % PF];
+            if (t + PF < iters) {
+                ring[u % PF] = bload<T>(rin, vx, rl * rowb);
+                if (++rl == ny) rl = 0;
+            }
+            step(cc, t, true);
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                       double dt, const T* in, T* out, const Stream2DConfig& cfg, hipStream_t s)
+{
+    const int nx = g.n[0], ny = g.n[1];
+    const double h = g.h, m = h * h, detJ = 0.25 * h * h;
+    const int H = model == 0 ? 1 : 2;
+    const int outw = WAVE - 2 * H;
+    const int ty = cfg.ty > 0 ? cfg.ty : 32;
+    const int nstrips = (nx + outw - 1) / outw;
+    const int nchunks = (ny + ty - 1) / ty;
+    const int nwaves = nstrips * nchunks;
+    const int blocks = (nwaves + 3) / 4;
+    const unsigned bytes = (unsigned)((size_t)g.N * sizeof(T));  // caller guarantees < 2^31
+    Coef<T> k{};
+    if (model == 0) {
+        const double sc = dt * mob * detJ / m;
+        k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
+        k.beta = (T)(dt * mob * kappa / (3.0 * m));
+        k_explicit2d<T, 0><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+    } else {
+        const double sc = detJ / m;
+        k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
+        k.beta = (T)(kappa / (3.0 * m));
+        k.gamma = (T)(dt * mob / (3.0 * m));
+        k_explicit2d<T, 1><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+    }
+}
+
+template void launch_explicit2d<float>(const Geom&, int, const FreeEnergy&, double, double, double,
+                                       const float*, float*, const Stream2DConfig&, hipStream_t);
+template void launch_explicit2d<double>(const Geom&, int, const FreeEnergy&, double, double, double,
+                                        const double*, double*, const Stream2DConfig&, hipStream_t);
+
+}  // namespace pfk

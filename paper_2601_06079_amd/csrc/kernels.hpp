@@ -1,0 +1,63 @@
+// kernels.hpp -- host-side launchers of the HIP kernels (internal to libpfhip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// Geometry of a periodic structured grid (x fastest).
+struct Geom {
+    int dim;
+    int n[3];
+    long long N;  // nodes
+    double h;
+};
+
+// Free-energy polynomials with W folded in.
+//   f'(q)  = q (a1 + q (a2 + a3 q))
+//   f''(q) = b0 + q (b1 + b2 q)
+//   fe     = which f for the energy (0: W (q^2-1)^2 / 4, 1: W q^2 (1-q)^2)
+struct FreeEnergy {
+    double a1, a2, a3;
+    double b0, b1, b2;
+    double W;
+    int fe;
+};
+
+FreeEnergy make_free_energy(int fe, double W);
+
+// ---- per-node kernels (k_node.hip); T = float or double ---------------------
+template <typename T>
+void launch_residual(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                     const T* U, T* r, hipStream_t s);
+template <typename T>
+void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s);
+// mu = [N(c) + kappa K c] / m
+template <typename T>
+void launch_chem(const Geom& g, const FreeEnergy& f, double kappa, const T* c, T* mu,
+                 hipStream_t s);
+// c_out = c - dt M K mu / m
+template <typename T>
+void launch_ch_update(const Geom& g, double dtM, const T* c, const T* mu, T* c_out,
+                      hipStream_t s);
+// eta_out = eta - dt r(eta) / m   (Allen-Cahn, any dim)
+template <typename T>
+void launch_ac_step(const Geom& g, const FreeEnergy& f, double kappa, double dtL, const T* eta,
+                    T* eta_out, hipStream_t s);
+// out[0] = E_h, out[1] = sum m c ; partials: 2 * energy_blocks(g) doubles
+template <typename T>
+void launch_energy(const Geom& g, const FreeEnergy& f, double kappa, const T* c, double* partials,
+                   double* out, hipStream_t s);
+int energy_blocks(const Geom& g);
+
+// ---- fused 2-D explicit streaming kernels (k_stream2d.hip) ------------------
+struct Stream2DConfig {
+    int ty;  // rows per wave
+};
+// One explicit step in -> out (out != in).  model 0: Allen-Cahn, 1: Cahn-Hilliard c-plane.
+template <typename T>
+void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                       double dt, const T* in, T* out, const Stream2DConfig& cfg, hipStream_t s);
+
+}  // namespace pfk

@@ -1,0 +1,161 @@
+"""Torch-facing wrappers of the C ABI: same names as include/pf.h, no arithmetic.
+
+Tensors must be contiguous CUDA (HIP) tensors of the problem's dtype.  Every
+call is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _abi as A
+
+
+@dataclass
+class Problem:
+    """Problem statement (see pf_problem in include/pf.h)."""
+    n: tuple
+    model: int = A.ALLEN_CAHN
+    fe: int = A.F_SYM
+    dtype: torch.dtype = torch.float32
+    h: float = 1.0
+    W: float = 1.0
+    kappa: float = 1.0
+    mobility: float = 1.0
+    bc: int = A.PERIODIC
+
+    @property
+    def dim(self):
+        return len(self.n)
+
+    @property
+    def nnodes(self):
+        N = 1
+        for v in self.n:
+            N *= int(v)
+        return N
+
+    @property
+    def ndof(self):
+        return (2 if self.model == A.CAHN_HILLIARD else 1) * self.nnodes
+
+    def c(self) -> A.pf_problem:
+        n3 = [int(v) for v in self.n] + [1] * (3 - len(self.n))
+        return A.pf_problem(self.dim, self.bc, self.model, self.fe,
+                            A.F64 if self.dtype == torch.float64 else A.F32, 0,
+                            (ct.c_int64 * 3)(*n3), float(self.h), float(self.W),
+                            float(self.kappa), float(self.mobility))
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor, p: Problem = None, n: int = None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if p is not None and t.dtype != p.dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, problem says {p.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ct.c_void_p(t.data_ptr())
+
+
+def workspace(p: Problem, op: int, device=None) -> torch.Tensor:
+    nb = ct.c_size_t(0)
+    A.check(A.lib().pf_workspace_size(ct.byref(p.c()), op, ct.byref(nb)))
+    return torch.empty(max(int(nb.value), 8), dtype=torch.uint8,
+                       device=device or torch.device("cuda"))
+
+
+def residual(p: Problem, U: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    r = torch.empty_like(U) if out is None else out
+    A.check(A.lib().pf_residual(ct.byref(p.c()), _ptr(U, p, p.ndof, "U"), _ptr(r, p, p.ndof, "r"),
+                                _stream()))
+    return r
+
+
+def step_explicit(p: Problem, U: torch.Tensor, dt: float, nsteps: int,
+                  ws: torch.Tensor = None) -> torch.Tensor:
+    """nsteps explicit steps in place on U; returns U."""
+    if ws is None:
+        ws = workspace(p, A.OP_STEP_EXPLICIT, U.device)
+    A.check(A.lib().pf_step_explicit(ct.byref(p.c()), float(dt), int(nsteps),
+                                     _ptr(U, p, p.ndof, "U"), ct.c_void_p(ws.data_ptr()),
+                                     _stream()))
+    return U
+
+
+def energy(p: Problem, U: torch.Tensor, ws: torch.Tensor = None,
+           out: torch.Tensor = None) -> torch.Tensor:
+    """Device tensor [E_h, sum m c] (float64)."""
+    if ws is None:
+        ws = workspace(p, A.OP_ENERGY, U.device)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=U.device)
+    A.check(A.lib().pf_energy(ct.byref(p.c()), _ptr(U, p, p.ndof, "U"),
+                              ct.c_void_p(out.data_ptr()), ct.c_void_p(ws.data_ptr()), _stream()))
+    return out
+
+
+def jvp(p: Problem, inv_dt: float, U: torch.Tensor, v: torch.Tensor,
+        out: torch.Tensor = None) -> torch.Tensor:
+    Jv = torch.empty_like(U) if out is None else out
+    A.check(A.lib().pf_jvp(ct.byref(p.c()), float(inv_dt), _ptr(U, p, p.ndof, "U"),
+                           _ptr(v, p, p.ndof, "v"), _ptr(Jv, p, p.ndof, "Jv"), _stream()))
+    return Jv
+
+
+def newton_opts(**kw) -> A.pf_newton_opts:
+    o = A.pf_newton_opts()
+    A.lib().pf_newton_default_opts(ct.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class NewtonReport:
+    newton_its: int
+    gmres_its: int
+    converged: bool
+    reason: int
+    res_norm: list = field(default_factory=list)
+
+
+def newton_step(p: Problem, dt: float, U_old: torch.Tensor, U: torch.Tensor, opts=None,
+                ws: torch.Tensor = None, raise_on_noconv: bool = False) -> NewtonReport:
+    """One backward-Euler step in place on U (initial guess on entry)."""
+    if ws is None:
+        ws = workspace(p, A.OP_NEWTON, U.device)
+    o = opts if opts is not None else newton_opts()
+    rep = A.pf_newton_report()
+    st = A.lib().pf_newton_step(ct.byref(p.c()), float(dt), _ptr(U_old, p, p.ndof, "U_old"),
+                                _ptr(U, p, p.ndof, "U"), ct.byref(o), ct.byref(rep),
+                                ct.c_void_p(ws.data_ptr()), _stream())
+    allow = () if raise_on_noconv else (A.PF_ENOCONV, A.PF_ENONFINITE)
+    A.check(st, allow=allow)
+    k = rep.newton_its
+    return NewtonReport(k, rep.gmres_its, bool(rep.converged), rep.reason,
+                        [rep.res_norm[i] for i in range(min(k, 32) + 1)])
+
+
+def vjp(p: Problem, kind: int, dt: float, U: torch.Tensor, vbar: torch.Tensor,
+        Ubar: torch.Tensor, theta_bar: torch.Tensor, ws: torch.Tensor = None):
+    """Accumulate vector-Jacobian products into Ubar and theta_bar (float64[3])."""
+    if ws is None:
+        ws = workspace(p, A.OP_VJP, U.device)
+    if theta_bar.dtype != torch.float64 or theta_bar.numel() != 3 or not theta_bar.is_cuda:
+        raise ValueError("theta_bar must be a float64 device tensor of 3 entries")
+    A.check(A.lib().pf_vjp(ct.byref(p.c()), int(kind), float(dt), _ptr(U, p, p.ndof, "U"),
+                           _ptr(vbar, p, None, "vbar"), _ptr(Ubar, p, None, "Ubar"),
+                           ct.c_void_p(theta_bar.data_ptr()), ct.c_void_p(ws.data_ptr()),
+                           _stream()))
+
+
+def tune_set(key: int, value: int):
+    A.check(A.lib().pf_tune_set(int(key), int(value)))

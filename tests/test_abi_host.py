@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects malformed requests before touching a GPU."""
+import ctypes as ct
+
+import pytest
+
+from paper_2601_06079_amd import _abi as A
+
+
+@pytest.fixture(scope="module")
+def L():
+    return A.lib()
+
+
+def _prob(**kw):
+    d = dict(dim=2, bc=A.PERIODIC, model=A.CAHN_HILLIARD, fe=A.F_01, dtype=A.F32, reserved=0,
+             n=(64, 48, 1), h=1.0, W=1.0, kappa=2.0, mobility=1.0)
+    d.update(kw)
+    return A.pf_problem(d["dim"], d["bc"], d["model"], d["fe"], d["dtype"], d["reserved"],
+                        (ct.c_int64 * 3)(*d["n"]), d["h"], d["W"], d["kappa"], d["mobility"])
+
+
+def test_exports_every_declared_symbol(L):
+    names = A.exported_symbols()
+    assert "pf_step_explicit" in names and "pf_newton_step" in names and "pf_vjp" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version(L):
+    assert L.pf_version() >= 100
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(dim=4), A.PF_EINVAL), (dict(model=7), A.PF_EINVAL), (dict(fe=9), A.PF_EINVAL),
+    (dict(dtype=3), A.PF_EINVAL), (dict(reserved=1), A.PF_EINVAL), (dict(n=(1, 8, 1)), A.PF_EINVAL),
+    (dict(h=0.0), A.PF_EINVAL), (dict(h=float("nan")), A.PF_EINVAL),
+    (dict(kappa=float("inf")), A.PF_EINVAL), (dict(bc=A.NOFLUX), A.PF_EUNSUPPORTED),
+    (dict(bc=5), A.PF_EINVAL)])
+def test_problem_validation(L, bad, status):
+    p = _prob(**bad)
+    nb = ct.c_size_t(0)
+    assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == status
+    assert L.pf_last_error()  # a message is set
+
+
+def test_argument_validation_before_launch(L):
+    p = _prob()
+    fake = ct.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    assert L.pf_residual(ct.byref(p), None, fake, None) == A.PF_EINVAL
+    assert L.pf_residual(ct.byref(p), fake, fake, None) == A.PF_EINVAL  # aliasing
+    assert L.pf_residual(ct.byref(p), ct.c_void_p(0x1002), ct.c_void_p(0x2000), None) == A.PF_EINVAL
+    assert L.pf_step_explicit(ct.byref(p), 0.0, 1, fake, fake, None) == A.PF_EINVAL
+    assert L.pf_step_explicit(ct.byref(p), 0.01, -1, fake, fake, None) == A.PF_EINVAL
+    assert L.pf_step_explicit(ct.byref(p), float("nan"), 1, fake, fake, None) == A.PF_EINVAL
+    assert L.pf_jvp(ct.byref(p), -1.0, fake, ct.c_void_p(0x2000), ct.c_void_p(0x3000), None) == A.PF_EINVAL
+    assert L.pf_energy(ct.byref(p), fake, None, fake, None) == A.PF_EINVAL
+    assert b"NULL" in L.pf_last_error()
+
+
+def test_workspace_sizes(L):
+    p = _prob()
+    nb = ct.c_size_t(0)
+    assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == A.PF_OK
+    assert nb.value == 64 * 48 * 4
+    assert L.pf_workspace_size(ct.byref(p), A.OP_RESIDUAL, ct.byref(nb)) == A.PF_OK
+    assert nb.value == 0
+    assert L.pf_workspace_size(ct.byref(p), A.OP_ENERGY, ct.byref(nb)) == A.PF_OK
+    assert nb.value >= 16
+    assert L.pf_workspace_size(ct.byref(p), 99, ct.byref(nb)) == A.PF_EINVAL
+
+
+def test_tuning_roundtrip(L):
+    v = ct.c_int(-1)
+    assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, 48) == A.PF_OK
+    assert L.pf_tune_get(A.TUNE_STREAM2D_ROWS, ct.byref(v)) == A.PF_OK and v.value == 48
+    assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, 0) == A.PF_OK
+    assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, -3) == A.PF_EINVAL
+    assert L.pf_tune_set(77, 1) == A.PF_EINVAL
