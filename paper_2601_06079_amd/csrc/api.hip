@@ -108,7 +108,7 @@ int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws,
     // the fused 2-D kernel addresses a field with 32-bit buffer offsets
     const bool fused2d = p->dim == 2 && (size_t)g.N * sizeof(T) < (size_t(1) << 31);
     if (fused2d) {
-        pfk::Stream2DConfig cfg{stream2d_rows(p)};
+        pfk::Stream2DConfig cfg{stream2d_rows(p), stream2d_depth(p)};
         for (int64_t st = 0; st < nsteps; ++st) {
             pfk::launch_explicit2d<T>(g, p->model, f, p->kappa, p->mobility, dt, cur, other, cfg, s);
             std::swap(cur, other);

@@ -19,6 +19,7 @@ size_t elem_size(const pf_problem* p);
 
 // rows per wave of the 2-D streaming kernel for this problem (tuning table)
 int stream2d_rows(const pf_problem* p);
+int stream2d_depth(const pf_problem* p);
 
 size_t newton_workspace_bytes(const pf_problem* p, int restart);
 size_t vjp_workspace_bytes(const pf_problem* p);

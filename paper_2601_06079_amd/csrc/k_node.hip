@@ -1,18 +1,10 @@
-// k_node.hip -- node-centric kernels for 2-D and 3-D periodic Q1 grids.
-//
-// One thread owns one node.  It reads the 3^d neighbourhood of the node and
-// evaluates the node's row of the weak form directly, summing over the 2^d
-// elements that share the node (no atomics, fixed summation order):
-//   nonlinear term  N(u)_a = sum_e sum_q |J| f'(u_q) phi_a(q)        (Eqs. 5-6, 10)
-//   gradient term   (K u)_a = sum_e sum_q |J| grad u_q . grad phi_a   (exact: a closed
-//                   tensor stencil, K = sum_k Khat_k (x) Mhat_others, Khat = [-1 2 -1]/h,
-//                   Mhat = h [1 4 1] / 6)
-// The 4^d quadrature values of the 2^d elements are produced by sum
-// factorisation: interp3to4 along x, then y (then z).
+// k_node.hip -- node-centric kernels for 2-D and 3-D periodic Q1 grids:
+// residual (Eq. 11) and backward-Euler residual (Eq. 14), Jacobian products,
+// preconditioner, chemical potential, node-centric explicit updates, energy.
+// The shared device helpers and the quadrature scheme are in node_common.hpp.
 #include <cmath>
 
-#include "device.hpp"
-#include "kernels.hpp"
+#include "node_common.hpp"
 
 namespace pfk {
 
@@ -33,153 +25,13 @@ FreeEnergy make_free_energy(int fe, double W)
 
 namespace {
 
-template <int D>
-struct NB {
-    static constexpr int K = D == 2 ? 9 : 27;
-};
-
-// Neighbourhood index: (dx+1) + 3 (dy+1) + 9 (dz+1)
-template <typename T, int D>
-__device__ __forceinline__ void gather(const T* __restrict__ u, const Geom& g, int i, int j, int k,
-                                       T out[NB<D>::K])
-{
-    const int xs[3] = {wrap(i - 1, g.n[0]), i, wrap(i + 1, g.n[0])};
-    const int ys[3] = {wrap(j - 1, g.n[1]), j, wrap(j + 1, g.n[1])};
-    if constexpr (D == 2) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) out[a + 3 * b] = u[(long long)ys[b] * g.n[0] + xs[a]];
-    } else {
-        const int zs[3] = {wrap(k - 1, g.n[2]), k, wrap(k + 1, g.n[2])};
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    out[a + 3 * b + 9 * c] =
-                        u[((long long)zs[c] * g.n[1] + ys[b]) * g.n[0] + xs[a]];
-    }
-}
-
-// Unit-coefficient Q1 stiffness row at the centre node (2-D: h-free; 3-D: times h).
-template <typename T, int D>
-__device__ __forceinline__ T stiff(const T* u, T h)
-{
-    if constexpr (D == 2) {
-        T kx[3], mx[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            kx[b] = (T)2 * u[1 + 3 * b] - u[3 * b] - u[2 + 3 * b];
-            mx[b] = (T)4 * u[1 + 3 * b] + u[3 * b] + u[2 + 3 * b];
-        }
-        const T km = kx[0] + (T)4 * kx[1] + kx[2];  // Khat_x (x) Mhat_y
-        const T mk = (T)2 * mx[1] - mx[0] - mx[2];  // Mhat_x (x) Khat_y
-        return (km + mk) * (T)(1.0 / 6.0);
-    } else {
-        T km[3], mk[3], mm[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T kx[3], mx[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const T* r = u + 3 * b + 9 * c;
-                kx[b] = (T)2 * r[1] - r[0] - r[2];
-                mx[b] = (T)4 * r[1] + r[0] + r[2];
-            }
-            km[c] = kx[0] + (T)4 * kx[1] + kx[2];
-            mk[c] = (T)2 * mx[1] - mx[0] - mx[2];
-            mm[c] = mx[0] + (T)4 * mx[1] + mx[2];
-        }
-        const T a = (km[0] + mk[0]) + (T)4 * (km[1] + mk[1]) + (km[2] + mk[2]);  // (..) (x) Mhat_z
-        const T b = (T)2 * mm[1] - mm[0] - mm[2];                              // Mhat Mhat Khat_z
-        return (a + b) * h * (T)(1.0 / 36.0);
-    }
-}
-
-// sum_q w_q F(u_q[, v_q]) over the 4^D quadrature points around the centre node;
-// w = tensor product of (GM, GP, GP, GM).  |J| is applied by the caller.
-template <typename T, int D, bool WITHV, typename Fn>
-__device__ __forceinline__ T quad_sum(const T* u, const T* v, Fn F)
-{
-    if constexpr (D == 2) {
-        T Xu[3][4], Xv[3][4];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            interp3to4(u[3 * b], u[3 * b + 1], u[3 * b + 2], Xu[b]);
-            if constexpr (WITHV) interp3to4(v[3 * b], v[3 * b + 1], v[3 * b + 2], Xv[b]);
-        }
-        T col[4];
-#pragma unroll
-        for (int qx = 0; qx < 4; ++qx) {
-            T qu[4], qv[4], fv[4];
-            interp3to4(Xu[0][qx], Xu[1][qx], Xu[2][qx], qu);
-            if constexpr (WITHV) interp3to4(Xv[0][qx], Xv[1][qx], Xv[2][qx], qv);
-#pragma unroll
-            for (int qy = 0; qy < 4; ++qy) fv[qy] = F(qu[qy], WITHV ? qv[qy] : (T)0);
-            col[qx] = wsum4(fv);
-        }
-        return wsum4(col);
-    } else {
-        T Xu[9][4], Xv[9][4];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            interp3to4(u[3 * r], u[3 * r + 1], u[3 * r + 2], Xu[r]);
-            if constexpr (WITHV) interp3to4(v[3 * r], v[3 * r + 1], v[3 * r + 2], Xv[r]);
-        }
-        T plane[4];
-#pragma unroll
-        for (int qx = 0; qx < 4; ++qx) {
-            T Yu[3][4], Yv[3][4];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                interp3to4(Xu[3 * c][qx], Xu[3 * c + 1][qx], Xu[3 * c + 2][qx], Yu[c]);
-                if constexpr (WITHV)
-                    interp3to4(Xv[3 * c][qx], Xv[3 * c + 1][qx], Xv[3 * c + 2][qx], Yv[c]);
-            }
-            T row[4];
-#pragma unroll
-            for (int qy = 0; qy < 4; ++qy) {
-                T qu[4], qv[4], fv[4];
-                interp3to4(Yu[0][qy], Yu[1][qy], Yu[2][qy], qu);
-                if constexpr (WITHV) interp3to4(Yv[0][qy], Yv[1][qy], Yv[2][qy], qv);
-#pragma unroll
-                for (int qz = 0; qz < 4; ++qz) fv[qz] = F(qu[qz], WITHV ? qv[qz] : (T)0);
-                row[qy] = wsum4(fv);
-            }
-            plane[qx] = wsum4(row);
-        }
-        return wsum4(plane);
-    }
-}
-
-template <int D>
-__device__ __forceinline__ bool node_of(const Geom& g, long long idx, int& i, int& j, int& k)
-{
-    if (idx >= g.N) return false;
-    i = (int)(idx % g.n[0]);
-    long long r = idx / g.n[0];
-    j = (int)(r % g.n[1]);
-    k = D == 3 ? (int)(r / g.n[1]) : 0;
-    return true;
-}
-
-template <typename T>
-struct Cub {
-    T a1, a2, a3;
-    __device__ T operator()(T q, T) const { return cubic(q, a1, a2, a3); }
-};
-template <typename T>
-struct Lin {  // f''(q) v
-    T b0, b1, b2;
-    __device__ T operator()(T q, T v) const { return fmaT(fmaT(b2, q, b1), q, b0) * v; }
-};
-
 // r(U): Allen-Cahn  r = L [N + kappa K u];  Cahn-Hilliard r_c = M K mu, r_mu = m mu - [N(c) + kappa K c]
+// With Uold != nullptr the time term inv_dt m (U - Uold) of Eq. 14 is added to
+// the rows that carry mass (Allen-Cahn eta, Cahn-Hilliard c).
 template <typename T, int D, int MODEL>
-__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, T* __restrict__ r,
-                                                  Geom g, Cub<T> F, T detJ, T kappa, T mob, T m)
+__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const T* __restrict__ Uold,
+                                                  T* __restrict__ r, Geom g, Cub<T> F, T detJ,
+                                                  T kappa, T mob, T m, T inv_dt)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int i, j, k;
@@ -189,18 +41,51 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, T* __
     const T h = (T)g.h;
     const T Nn = detJ * quad_sum<T, D, false>(u, u, F);
     const T Ku = stiff<T, D>(u, h);
+    const T tt = Uold ? inv_dt * m * (u[NB<D>::K / 2] - Uold[idx]) : (T)0;
     if constexpr (MODEL == 0) {
-        r[idx] = mob * (Nn + kappa * Ku);
+        r[idx] = mob * (Nn + kappa * Ku) + tt;
     } else {
         T w[NB<D>::K];
         gather<T, D>(U + g.N, g, i, j, k, w);
-        r[idx] = mob * stiff<T, D>(w, h);
+        r[idx] = mob * stiff<T, D>(w, h) + tt;
         r[g.N + idx] = m * w[NB<D>::K / 2] - (Nn + kappa * Ku);
     }
 }
 
-// Jv for R = inv_dt M (U - U_old) + r(U)
+// (Block-)Jacobi preconditioner of dR/dU at U:
+//   Allen-Cahn:    pinv[a] = 1 / (inv_dt m + L (N'_aa + kappa K_aa))
+//   Cahn-Hilliard: pinv[4a..4a+3] = inverse of [[inv_dt m, M K_aa], [-(N'_aa + kappa K_aa), m]]
+// (row-major), with N'_aa = sum_e sum_q |J| f''(u_q) phi_a(q)^2.
 template <typename T, int D, int MODEL>
+__global__ __launch_bounds__(256) void k_prec(const T* __restrict__ U, T* __restrict__ pinv, Geom g,
+                                              Lin<T> F, T detJ, T kappa, T mob, T m, T inv_dt)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j, k;
+    if (!node_of<D>(g, idx, i, j, k)) return;
+    T u[NB<D>::K];
+    gather<T, D>(U, g, i, j, k, u);
+    const double nd = (double)(detJ * quad_sum_sq<T, D>(u, F));
+    const double kd = (double)stiff_diag<T, D>((T)g.h);
+    if constexpr (MODEL == 0) {
+        pinv[idx] = (T)(1.0 / ((double)inv_dt * m + (double)mob * (nd + (double)kappa * kd)));
+    } else {
+        const double a = (double)inv_dt * m, b = (double)mob * kd;
+        const double c = -(nd + (double)kappa * kd), d = (double)m;
+        const double det = a * d - b * c;
+        T* P = pinv + 4 * idx;
+        P[0] = (T)(d / det);
+        P[1] = (T)(-b / det);
+        P[2] = (T)(-c / det);
+        P[3] = (T)(a / det);
+    }
+}
+
+// Jv for R = inv_dt M (U - U_old) + r(U)
+// TRANS = 1 gives the transpose product w^T dR/dU (differs from J only for
+// Cahn-Hilliard):  [inv_dt m w_c - (N'(c) + kappa K) w_mu ;  M K w_c + m w_mu].
+// ACC = 1 adds the result into Jv instead of overwriting it.
+template <typename T, int D, int MODEL, int TRANS, int ACC>
 __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* __restrict__ V,
                                              T* __restrict__ Jv, Geom g, Lin<T> F, T detJ, T kappa,
                                              T mob, T m, T inv_dt)
@@ -210,18 +95,29 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
     if (!node_of<D>(g, idx, i, j, k)) return;
     T u[NB<D>::K], v[NB<D>::K];
     gather<T, D>(U, g, i, j, k, u);
-    gather<T, D>(V, g, i, j, k, v);
     const T h = (T)g.h;
-    const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
-    const T Kv = stiff<T, D>(v, h);
-    const T vc = v[NB<D>::K / 2];
     if constexpr (MODEL == 0) {
-        Jv[idx] = inv_dt * m * vc + mob * (Nv + kappa * Kv);
+        gather<T, D>(V, g, i, j, k, v);
+        const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
+        const T Kv = stiff<T, D>(v, h);
+        const T out = inv_dt * m * v[NB<D>::K / 2] + mob * (Nv + kappa * Kv);
+        Jv[idx] = ACC ? Jv[idx] + out : out;
     } else {
         T w[NB<D>::K];
-        gather<T, D>(V + g.N, g, i, j, k, w);
-        Jv[idx] = inv_dt * m * vc + mob * stiff<T, D>(w, h);
-        Jv[g.N + idx] = m * w[NB<D>::K / 2] - (Nv + kappa * Kv);
+        gather<T, D>(V, g, i, j, k, v);         // c-plane of the direction
+        gather<T, D>(V + g.N, g, i, j, k, w);   // mu-plane of the direction
+        T oc, om;
+        if constexpr (TRANS == 0) {
+            const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
+            oc = inv_dt * m * v[NB<D>::K / 2] + mob * stiff<T, D>(w, h);
+            om = m * w[NB<D>::K / 2] - (Nv + kappa * stiff<T, D>(v, h));
+        } else {
+            const T Nw = detJ * quad_sum<T, D, true>(u, w, F);
+            oc = inv_dt * m * v[NB<D>::K / 2] - (Nw + kappa * stiff<T, D>(w, h));
+            om = mob * stiff<T, D>(v, h) + m * w[NB<D>::K / 2];
+        }
+        Jv[idx] = ACC ? Jv[idx] + oc : oc;
+        Jv[g.N + idx] = ACC ? Jv[g.N + idx] + om : om;
     }
 }
 
@@ -409,32 +305,55 @@ int energy_blocks(const Geom& g) { return (int)((g.N + EBLK - 1) / EBLK); }
 
 template <typename T>
 void launch_residual(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                     const T* U, T* r, hipStream_t s)
+                     const T* U, T* r, hipStream_t s, const T* Uold, double inv_dt)
 {
     const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
     DIM_SWITCH(g, {
         if (model == 0)
-            k_residual<T, D, 0><<<grid_for(g), 256, 0, s>>>(U, r, g, cub_of<T>(f, 1.0), (T)detJ,
-                                                             (T)kappa, (T)mob, (T)m);
+            k_residual<T, D, 0><<<grid_for(g), 256, 0, s>>>(U, Uold, r, g, cub_of<T>(f, 1.0),
+                                                             (T)detJ, (T)kappa, (T)mob, (T)m,
+                                                             (T)inv_dt);
         else
-            k_residual<T, D, 1><<<grid_for(g), 256, 0, s>>>(U, r, g, cub_of<T>(f, 1.0), (T)detJ,
-                                                             (T)kappa, (T)mob, (T)m);
+            k_residual<T, D, 1><<<grid_for(g), 256, 0, s>>>(U, Uold, r, g, cub_of<T>(f, 1.0),
+                                                             (T)detJ, (T)kappa, (T)mob, (T)m,
+                                                             (T)inv_dt);
     });
 }
 
 template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s)
+                double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans, int acc)
+{
+    const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
+    Lin<T> F{(T)f.b0, (T)f.b1, (T)f.b2};
+#define JVP_L(MODEL, TR, AC)                                                                    \
+    k_jvp<T, D, MODEL, TR, AC><<<grid_for(g), 256, 0, s>>>(U, v, Jv, g, F, (T)detJ, (T)kappa,  \
+                                                           (T)mob, (T)m, (T)inv_dt)
+    DIM_SWITCH(g, {
+        if (model == 0) {
+            if (acc) JVP_L(0, 0, 1); else JVP_L(0, 0, 0);
+        } else if (!trans) {
+            if (acc) JVP_L(1, 0, 1); else JVP_L(1, 0, 0);
+        } else {
+            if (acc) JVP_L(1, 1, 1); else JVP_L(1, 1, 0);
+        }
+    });
+#undef JVP_L
+}
+
+template <typename T>
+void launch_prec(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                 double inv_dt, const T* U, T* pinv, hipStream_t s)
 {
     const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
     Lin<T> F{(T)f.b0, (T)f.b1, (T)f.b2};
     DIM_SWITCH(g, {
         if (model == 0)
-            k_jvp<T, D, 0><<<grid_for(g), 256, 0, s>>>(U, v, Jv, g, F, (T)detJ, (T)kappa, (T)mob,
-                                                        (T)m, (T)inv_dt);
+            k_prec<T, D, 0><<<grid_for(g), 256, 0, s>>>(U, pinv, g, F, (T)detJ, (T)kappa, (T)mob,
+                                                         (T)m, (T)inv_dt);
         else
-            k_jvp<T, D, 1><<<grid_for(g), 256, 0, s>>>(U, v, Jv, g, F, (T)detJ, (T)kappa, (T)mob,
-                                                        (T)m, (T)inv_dt);
+            k_prec<T, D, 1><<<grid_for(g), 256, 0, s>>>(U, pinv, g, F, (T)detJ, (T)kappa, (T)mob,
+                                                         (T)m, (T)inv_dt);
     });
 }
 
@@ -478,9 +397,11 @@ void launch_energy(const Geom& g, const FreeEnergy& f, double kappa, const T* c,
 
 #define INST(T)                                                                                   \
     template void launch_residual<T>(const Geom&, int, const FreeEnergy&, double, double, const T*, \
-                                     T*, hipStream_t);                                            \
+                                     T*, hipStream_t, const T*, double);                          \
     template void launch_jvp<T>(const Geom&, int, const FreeEnergy&, double, double, double,       \
-                                const T*, const T*, T*, hipStream_t);                             \
+                                const T*, const T*, T*, hipStream_t, int, int);                   \
+    template void launch_prec<T>(const Geom&, int, const FreeEnergy&, double, double, double,      \
+                                 const T*, T*, hipStream_t);                                      \
     template void launch_chem<T>(const Geom&, const FreeEnergy&, double, const T*, T*, hipStream_t); \
     template void launch_ch_update<T>(const Geom&, double, const T*, const T*, T*, hipStream_t);   \
     template void launch_ac_step<T>(const Geom&, const FreeEnergy&, double, double, const T*, T*,  \

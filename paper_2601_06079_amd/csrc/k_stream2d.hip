@@ -32,8 +32,6 @@ struct Coef {
     T gamma;       // Cahn-Hilliard: multiplies (9 mu - box3x3(mu))
 };
 
-constexpr int PF = 8;  // rows in flight per wave
-
 // raw buffer access: the row offset is a scalar (one SGPR), the column offset
 // a per-lane VGPR set once, so no per-row address arithmetic runs on the VALU.
 // Out-of-range addresses read 0 and drop stores (the launcher keeps every
@@ -73,7 +71,8 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int v
 // MODEL 1: Cahn-Hilliard mu = [|J|/m] N'(c) + [kappa/(3m)] (9c - box c)
 //                        out = c - [dt M/(3m)] (9 mu - box mu)
 // N' is the quadrature sum with the scaled cubic (a1, a2, a3).
-template <typename T, int MODEL>
+// PF: rows in flight per wave (register prefetch ring depth)
+template <typename T, int MODEL, int PF>
 __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
                                                     int nx, int ny, int nstrips, int nwaves, int ty,
                                                     unsigned bytes, Coef<T> k)
@@ -201,6 +200,18 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     }
 }
 
+template <typename T, int MODEL>
+void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
+                  int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
+{
+    if (depth <= 8)
+        k_explicit2d<T, MODEL, 8><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+    else if (depth <= 16)
+        k_explicit2d<T, MODEL, 16><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+    else
+        k_explicit2d<T, MODEL, 32><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+}
+
 }  // namespace
 
 template <typename T>
@@ -222,13 +233,13 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
         const double sc = dt * mob * detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        k_explicit2d<T, 0><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_depth<T, 0>(cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     } else {
         const double sc = detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(kappa / (3.0 * m));
         k.gamma = (T)(dt * mob / (3.0 * m));
-        k_explicit2d<T, 1><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_depth<T, 1>(cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     }
 }
 

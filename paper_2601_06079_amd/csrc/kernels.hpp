@@ -27,12 +27,19 @@ struct FreeEnergy {
 FreeEnergy make_free_energy(int fe, double W);
 
 // ---- per-node kernels (k_node.hip); T = float or double ---------------------
+// r(U) of Eq. 11; with Uold != nullptr the backward-Euler residual of Eq. 14
 template <typename T>
 void launch_residual(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                     const T* U, T* r, hipStream_t s);
+                     const T* U, T* r, hipStream_t s, const T* Uold = nullptr, double inv_dt = 0.0);
+// Jv = (dR/dU) v (trans: transpose product; acc: Jv += ...)
 template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s);
+                double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans = 0,
+                int acc = 0);
+// (block-)Jacobi inverse of dR/dU at U: N (Allen-Cahn) or 4N (Cahn-Hilliard) values
+template <typename T>
+void launch_prec(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                 double inv_dt, const T* U, T* pinv, hipStream_t s);
 // mu = [N(c) + kappa K c] / m
 template <typename T>
 void launch_chem(const Geom& g, const FreeEnergy& f, double kappa, const T* c, T* mu,
@@ -51,9 +58,26 @@ void launch_energy(const Geom& g, const FreeEnergy& f, double kappa, const T* c,
                    double* out, hipStream_t s);
 int energy_blocks(const Geom& g);
 
+// ---- sensitivities (k_adjoint.hip) -----------------------------------------
+// theta_bar[0..3) += scale * w^T dr/dtheta at U (part: 3 * ceil(N/256) doubles)
+template <typename T>
+void launch_dtheta(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                   const T* U, const T* w, double scale, double* part, double* theta_bar,
+                   hipStream_t s);
+// ubar[0..N) += inv_dt m lam[0..N)
+template <typename T>
+void launch_mass_axpy(const Geom& g, double inv_dt, const T* lam, T* ub, hipStream_t s);
+// one explicit step S at U: ubar += (dS/dU)^T vbar, theta_bar += (dS/dtheta)^T vbar
+// (Cahn-Hilliard: c planes only).  scratch: 2N values.
+template <typename T>
+void launch_vjp_explicit(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                         double dt, const T* U, const T* vbar, T* ubar, T* scratch, double* part,
+                         double* theta_bar, hipStream_t s);
+
 // ---- fused 2-D explicit streaming kernels (k_stream2d.hip) ------------------
 struct Stream2DConfig {
-    int ty;  // rows per wave
+    int ty;     // rows per wave
+    int depth;  // rows in flight per wave (8, 16 or 32)
 };
 // One explicit step in -> out (out != in).  model 0: Allen-Cahn, 1: Cahn-Hilliard c-plane.
 template <typename T>

@@ -1,30 +1,466 @@
-// newton.hip -- backward-Euler Newton step and sensitivities (filled in below).
+// newton.hip -- backward-Euler step by Newton-Raphson with matrix-free GMRES
+// (Eqs. 13-14, Sec. 2.3), and the adjoint solve of that step (Supp. Note 2).
+//
+// Host loop, device data.  All vectors (residual, correction, the Krylov basis,
+// the preconditioner) live in the caller's workspace on the device; every
+// matrix-vector product is the matrix-free Jacobian kernel; every dot product
+// and norm is an FP64 device reduction.  Per Arnoldi step the host reads back
+// one Hessenberg column (<= 2 m + 1 doubles) to apply its Givens rotation and
+// test convergence; the (m+1) x m Hessenberg matrix and the small triangular
+// solve stay on the host in FP64.
+//
+// GMRES(m) variant: right preconditioning (the residual it monitors is the true
+// one), classical Gram-Schmidt with one re-orthogonalisation, x0 = 0, restart
+// from the true residual b - J x.  Inexact Newton: the linear tolerance is
+// clamp(0.1 ||R_k|| / ||R_0||, lin_rtol_min, lin_rtol_max) relative to ||R_k||.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "api_internal.hpp"
+#include "kernels.hpp"
+#include "krylov.hpp"
 
 namespace pfapi {
-size_t newton_workspace_bytes(const pf_problem* p, int restart) { (void)p; (void)restart; return 0; }
-size_t vjp_workspace_bytes(const pf_problem* p) { (void)p; return 0; }
+namespace {
+
+constexpr int MAXM = 32;  // largest restart length
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Workspace layout shared by the forward Newton step and the adjoint solve.
+template <typename T>
+struct NWS {
+    T *R, *x, *w, *z, *b, *V, *pinv;
+    long long ld;
+    double *part, *dev;  // dev: [h1(MAXM+1) | h2(MAXM+1) | nrm(2) | y(MAXM) | misc(8)]
+    size_t bytes;
+};
+
+template <typename T>
+NWS<T> layout(const pf_problem* p, void* base)
+{
+    const pfk::Geom g = geom_of(p);
+    const long long n = ndof(p);
+    NWS<T> L{};
+    L.ld = (n + 63) / 64 * 64;
+    char* c = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* r = c ? c + off : nullptr;
+        off += align256(b);
+        return r;
+    };
+    L.R = (T*)take(n * sizeof(T));
+    L.x = (T*)take(n * sizeof(T));
+    L.w = (T*)take(n * sizeof(T));
+    L.z = (T*)take(n * sizeof(T));
+    L.b = (T*)take(n * sizeof(T));
+    L.V = (T*)take((size_t)(MAXM + 1) * L.ld * sizeof(T));
+    L.pinv = (T*)take((size_t)(p->model == PF_CAHN_HILLIARD ? 4 : 1) * g.N * sizeof(T));
+    const long long nbp = std::max<long long>(pfk::krylov_blocks(n), (g.N + 255) / 256);
+    L.part = (double*)take((size_t)(MAXM + 2) * nbp * sizeof(double) + 64);
+    L.dev = (double*)take(4 * (MAXM + 8) * sizeof(double));
+    L.bytes = off;
+    return L;
+}
+
+enum { DEV_H1 = 0, DEV_H2 = MAXM + 1, DEV_NRM = 2 * (MAXM + 1), DEV_Y = 2 * (MAXM + 1) + 2,
+       DEV_MISC = 3 * (MAXM + 1) + 2 };
+
+struct Opts {
+    double rtol, atol, lmin, lmax;
+    int max_newton, m, max_its, precond, stagnation;
+};
+
+Opts resolve(const pf_newton_opts* o)
+{
+    pf_newton_opts d;
+    pf_newton_default_opts(&d);
+    if (!o) o = &d;
+    Opts r{};
+    r.rtol = o->rtol;
+    r.atol = o->atol;
+    r.lmin = o->lin_rtol_min;
+    r.lmax = o->lin_rtol_max;
+    r.max_newton = o->max_newton;
+    r.m = o->gmres_restart;
+    r.max_its = o->gmres_max_its;
+    r.precond = o->precond;
+    r.stagnation = o->stagnation;
+    return r;
+}
+
+int check_opts(const Opts& o)
+{
+    if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
+        return fail(PF_EINVAL, "rtol/atol must be finite and >= 0");
+    if (o.max_newton < 0 || o.max_newton > 1000) return fail(PF_EINVAL, "max_newton out of range");
+    if (o.m < 1 || o.m > MAXM) return fail(PF_EINVAL, "gmres_restart must be in 1..%d", MAXM);
+    if (o.max_its < 1) return fail(PF_EINVAL, "gmres_max_its must be >= 1");
+    if (o.precond != PF_PRECOND_NONE && o.precond != PF_PRECOND_JACOBI)
+        return fail(PF_EINVAL, "unknown preconditioner");
+    if (!(o.lmin > 0.0) || !(o.lmax >= o.lmin) || !(o.lmax < 1.0))
+        return fail(PF_EINVAL, "need 0 < lin_rtol_min <= lin_rtol_max < 1");
+    return PF_OK;
+}
+
+int d2h(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return check_launch("device-to-host read");
+    return PF_OK;
+}
+
+int h2d(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return check_launch("host-to-device write");
+    return PF_OK;
+}
+
+// The linear operator handed to GMRES: J = dR/dU at U (or its transpose).
+template <typename T>
+struct LinOp {
+    const pf_problem* p;
+    pfk::Geom g;
+    pfk::FreeEnergy f;
+    double inv_dt;
+    const T* U;
+    int trans;
+    void apply(const T* v, T* out, hipStream_t s) const
+    {
+        pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, trans, 0);
+    }
+};
+
+// Solve J x = b (x overwritten, starting from 0) to ||b - J x|| <= tol_abs.
+// The preconditioner (if any) must already be in L.pinv.  Returns PF status;
+// *its receives the Arnoldi steps taken, *res the last residual estimate.
+template <typename T>
+int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool prec,
+          double bnorm, double tol_abs, int* its, double* res, hipStream_t s)
+{
+    const int model = A.p->model;
+    const long long Nn = A.g.N;
+    const T* pinv = prec ? L.pinv : nullptr;
+    const int tr = A.trans;
+    double* dh1 = L.dev + DEV_H1;
+    double* dh2 = L.dev + DEV_H2;
+    double* dnrm = L.dev + DEV_NRM;
+    double* dy = L.dev + DEV_Y;
+    if (hipMemsetAsync(L.x, 0, (size_t)n * sizeof(T), s) != hipSuccess) return check_launch("gmres init");
+    std::vector<double> H((MAXM + 1) * MAXM), cs(MAXM), sn(MAXM), gv(MAXM + 1), y(MAXM);
+    std::vector<double> col(DEV_Y);
+    int total = 0;
+    double beta = bnorm;
+    bool first = true;
+    *res = bnorm;
+    if (bnorm <= tol_abs) {
+        *its = 0;
+        return PF_OK;
+    }
+    for (;;) {
+        // v0 = r / ||r||, z = P^-1 v0 with r = b - J x (= b on the first cycle)
+        if (first) {
+            pfk::kr_norm2<T>(L.b, nullptr, n, L.part, dnrm, s);
+        } else {
+            A.apply(L.x, L.w, s);
+            pfk::kr_rsub<T>(L.b, L.w, n, s);
+            pfk::kr_norm2<T>(L.w, nullptr, n, L.part, dnrm, s);
+            double nn;
+            if (int rc = d2h(&nn, dnrm, sizeof(double), s)) return rc;
+            beta = std::sqrt(nn);
+            *res = beta;
+            if (!std::isfinite(beta)) return fail(PF_ENONFINITE, "GMRES residual is not finite");
+            if (beta <= tol_abs || total >= max_its) break;
+        }
+        pfk::kr_normalize_prec<T>(model, first ? L.b : L.w, dnrm, L.V, L.z, pinv, Nn, 1.0, s, tr);
+        first = false;
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && total < max_its; ++j) {
+            T* vnext = L.V + (long long)(j + 1) * L.ld;
+            A.apply(L.z, L.w, s);
+            pfk::kr_mdot<T>(L.V, L.ld, j + 1, L.w, n, L.part, dh1, 0, s);
+            pfk::kr_axpy_mdot<T>(L.V, L.ld, j + 1, dh1, L.w, n, L.part, dh2, s);
+            pfk::kr_axpy_norm<T>(L.V, L.ld, j + 1, dh2, L.w, n, L.part, dnrm, s);
+            pfk::kr_normalize_prec<T>(model, L.w, dnrm, vnext, L.z, pinv, Nn, 1.0, s, tr);
+            if (int rc = d2h(col.data(), L.dev, col.size() * sizeof(double), s)) return rc;
+            ++total;
+            for (int i = 0; i <= j; ++i) H[i * MAXM + j] = col[DEV_H1 + i] + col[DEV_H2 + i];
+            const double hn = std::sqrt(std::max(col[DEV_NRM], 0.0));
+            H[(j + 1) * MAXM + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * MAXM + j] + sn[i] * H[(i + 1) * MAXM + j];
+                H[(i + 1) * MAXM + j] = -sn[i] * H[i * MAXM + j] + cs[i] * H[(i + 1) * MAXM + j];
+                H[i * MAXM + j] = t;
+            }
+            const double a = H[j * MAXM + j], bb = H[(j + 1) * MAXM + j];
+            const double rr = std::hypot(a, bb);
+            if (!std::isfinite(rr)) return fail(PF_ENONFINITE, "GMRES Hessenberg is not finite");
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? bb / rr : 0.0;
+            H[j * MAXM + j] = rr;
+            H[(j + 1) * MAXM + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            *res = std::fabs(gv[j + 1]);
+            if (*res <= tol_abs || hn == 0.0) {
+                ++j;
+                done = true;
+                break;
+            }
+        }
+        // y = H^-1 g (upper triangular j x j), x += P^-1 V y
+        for (int i = j - 1; i >= 0; --i) {
+            double sum = gv[i];
+            for (int k = i + 1; k < j; ++k) sum -= H[i * MAXM + k] * y[k];
+            y[i] = H[i * MAXM + i] != 0.0 ? sum / H[i * MAXM + i] : 0.0;
+        }
+        if (j > 0) {
+            if (int rc = h2d(dy, y.data(), (size_t)j * sizeof(double), s)) return rc;
+            pfk::kr_update<T>(model, L.V, L.ld, j, dy, pinv, L.x, Nn, s, tr);
+        }
+        if (done || total >= max_its) break;
+    }
+    *its = total;
+    return check_launch("gmres");
+}
+
+template <typename T>
+double eps_of()
+{
+    return sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+}
+
+template <typename T>
+int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
+             pf_newton_report* rep, void* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    const long long n = ndof(p);
+    NWS<T> L = layout<T>(p, ws);
+    const double inv_dt = 1.0 / dt;
+    double* dnrm = L.dev + DEV_NRM;
+    double* dmisc = L.dev + DEV_MISC;
+    pf_newton_report R{};
+    auto residual_norm = [&](double* out) -> int {
+        pfk::launch_residual<T>(g, p->model, f, p->kappa, p->mobility, U, L.R, s, Uold, inv_dt);
+        pfk::kr_norm2<T>(L.R, nullptr, n, L.part, dnrm, s);
+        double nn;
+        if (int rc = d2h(&nn, dnrm, sizeof(double), s)) return rc;
+        *out = std::sqrt(nn);
+        return PF_OK;
+    };
+    double r0;
+    if (int rc = residual_norm(&r0)) return rc;
+    R.res_norm[0] = r0;
+    R.reason = -1;
+    int status = PF_OK;
+    double rk = r0, rprev = r0;
+    if (!std::isfinite(r0)) {
+        R.reason = -2;
+        status = fail(PF_ENONFINITE, "initial residual is not finite");
+    }
+    const LinOp<T> A{p, g, f, inv_dt, U, 0};
+    int k = 0;
+    double dmax = 0.0, umax = 0.0;
+    while (status == PF_OK) {
+        if (rk <= o.rtol * r0) { R.converged = 1; R.reason = 0; break; }
+        if (rk <= o.atol) { R.converged = 1; R.reason = 1; break; }
+        if (o.stagnation && k >= 2 && rk > 0.5 * rprev && dmax <= 8.0 * eps_of<T>() * umax) {
+            R.converged = 1;
+            R.reason = 2;  // rounding floor of the field precision reached
+            break;
+        }
+        if (k >= o.max_newton) break;
+        if (o.precond == PF_PRECOND_JACOBI)
+            pfk::launch_prec<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, L.pinv, s);
+        pfk::kr_scale<T>(L.R, L.b, -1.0, n, s);  // b = -R
+        const double lin = std::min(o.lmax, std::max(o.lmin, 0.1 * rk / r0));
+        int its = 0;
+        double lres = 0.0;
+        if (int rc = gmres<T>(A, L, n, o.m, o.max_its, o.precond == PF_PRECOND_JACOBI, rk, lin * rk,
+                              &its, &lres, s)) {
+            status = rc;
+            R.reason = -2;
+            break;
+        }
+        R.gmres_its += its;
+        pfk::kr_add_maxabs<T>(U, L.x, n, L.part, s);
+        const int nb = pfk::krylov_blocks(n);
+        std::vector<double> mx(2 * nb);
+        if (int rc = d2h(mx.data(), L.part, mx.size() * sizeof(double), s)) return rc;
+        dmax = umax = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            dmax = std::max(dmax, mx[2 * b]);
+            umax = std::max(umax, mx[2 * b + 1]);
+        }
+        rprev = rk;
+        if (int rc = residual_norm(&rk)) return rc;
+        ++k;
+        if (k <= 32) R.res_norm[k] = rk;
+        if (!std::isfinite(rk)) {
+            R.reason = -2;
+            status = fail(PF_ENONFINITE, "Newton residual is not finite");
+        }
+    }
+    (void)dmisc;
+    R.newton_its = k;
+    if (rep) *rep = R;
+    if (status != PF_OK) return status;
+    if (!R.converged)
+        return fail(PF_ENOCONV, "Newton stopped after %d corrections at ||R|| = %.3e (||R0|| = %.3e)",
+                    k, rk, r0);
+    return check_launch("pf_newton_step");
+}
+
+}  // namespace
+
+size_t newton_workspace_bytes(const pf_problem* p, int)
+{
+    return p->dtype == PF_F64 ? layout<double>(p, nullptr).bytes : layout<float>(p, nullptr).bytes;
+}
+
+size_t vjp_workspace_bytes(const pf_problem* p) { return newton_workspace_bytes(p, MAXM); }
+
+template <typename T>
+int vjp_simple_t(const pf_problem* p, int kind, double dt, const T* U, const T* vbar, T* Ubar,
+                 double* theta_bar, void* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    NWS<T> L = layout<T>(p, ws);
+    if (kind == PF_VJP_RESIDUAL) {
+        // Ubar += (dr/dU)^T vbar : the transpose Jacobian product with no time term
+        pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, 0.0, U, vbar, Ubar, s, 1, 1);
+        pfk::launch_dtheta<T>(g, p->model, f, p->kappa, p->mobility, U, vbar, 1.0, L.part,
+                              theta_bar, s);
+    } else {
+        pfk::launch_vjp_explicit<T>(g, p->model, f, p->kappa, p->mobility, dt, U, vbar, Ubar, L.V,
+                                    L.part, theta_bar, s);
+    }
+    return check_launch("pf_vjp");
+}
+
+// Adjoint of one backward-Euler step at its root U (II.5-II.6):
+// solve (dR/dU)^T lambda = vbar, then Uold_bar += (M/dt) lambda on the mass
+// rows and theta_bar -= (dr/dtheta)^T lambda.  lambda is left in the
+// workspace's x vector.
+template <typename T>
+int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, T* Ubar,
+                     double* theta_bar, const Opts& o, void* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    const long long n = ndof(p);
+    NWS<T> L = layout<T>(p, ws);
+    const double inv_dt = 1.0 / dt;
+    if (o.precond == PF_PRECOND_JACOBI)
+        pfk::launch_prec<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, L.pinv, s);
+    if (hipMemcpyAsync(L.b, vbar, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return check_launch("adjoint rhs copy");
+    pfk::kr_norm2<T>(L.b, nullptr, n, L.part, L.dev + DEV_NRM, s);
+    double nn;
+    if (int rc = d2h(&nn, L.dev + DEV_NRM, sizeof(double), s)) return rc;
+    const double bn = std::sqrt(nn);
+    if (!std::isfinite(bn)) return fail(PF_ENONFINITE, "adjoint right-hand side is not finite");
+    const LinOp<T> At{p, g, f, inv_dt, U, 1};
+    int its = 0;
+    double res = 0.0;
+    // the adjoint solve is taken to the field-precision floor, not an inexact-Newton tolerance
+    const double tol = std::max(o.lmin * 1e-2, sizeof(T) == 4 ? 1e-6 : 1e-12) * bn;
+    if (int rc = gmres<T>(At, L, n, o.m, o.max_its * 4, o.precond == PF_PRECOND_JACOBI, bn, tol,
+                          &its, &res, s))
+        return rc;
+    // Ubar (mass rows) += (m/dt) lambda ; theta_bar -= (dr/dtheta)^T lambda
+    pfk::launch_mass_axpy<T>(g, inv_dt, L.x, Ubar, s);
+    pfk::launch_dtheta<T>(g, p->model, f, p->kappa, p->mobility, U, L.x, -1.0, L.part, theta_bar, s);
+    return check_launch("newton adjoint");
+}
+
+template int newton_adjoint_t<float>(const pf_problem*, double, const float*, const float*, float*,
+                                     double*, const Opts&, void*, hipStream_t);
+template int newton_adjoint_t<double>(const pf_problem*, double, const double*, const double*,
+                                      double*, double*, const Opts&, void*, hipStream_t);
+
+int newton_adjoint(const pf_problem* p, double dt, const void* U, const void* vbar, void* Ubar,
+                   double* theta_bar, void* ws, hipStream_t s)
+{
+    const Opts o = resolve(nullptr);
+    if (p->dtype == PF_F32)
+        return newton_adjoint_t<float>(p, dt, (const float*)U, (const float*)vbar, (float*)Ubar,
+                                       theta_bar, o, ws, s);
+    return newton_adjoint_t<double>(p, dt, (const double*)U, (const double*)vbar, (double*)Ubar,
+                                    theta_bar, o, ws, s);
+}
+
 }  // namespace pfapi
 
 using namespace pfapi;
+
 extern "C" {
+
 void pf_newton_default_opts(pf_newton_opts* o)
 {
     if (!o) return;
     *o = pf_newton_opts{};
-    o->rtol = 1e-8; o->atol = 0.0; o->max_newton = 20; o->gmres_restart = 30;
-    o->gmres_max_its = 600; o->precond = PF_PRECOND_JACOBI; o->lin_rtol_max = 1e-2;
-    o->lin_rtol_min = 1e-6; o->stagnation = 1;
+    o->rtol = 1e-8;
+    o->atol = 0.0;
+    o->max_newton = 20;
+    o->gmres_restart = 30;
+    o->gmres_max_its = 600;
+    o->precond = PF_PRECOND_JACOBI;
+    o->lin_rtol_max = 1e-2;
+    o->lin_rtol_min = 1e-6;
+    o->stagnation = 1;
 }
-int pf_newton_step(const pf_problem* p, double, const void*, void*, const pf_newton_opts*,
-                   pf_newton_report*, void*, void*)
+
+int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
+                   const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream)
 {
     if (int rc = validate(p)) return rc;
-    return fail(PF_EUNSUPPORTED, "pf_newton_step: not built yet");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
+    if (int rc = check_ptr(U_old, p, "U_old")) return rc;
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (U == U_old) return fail(PF_EINVAL, "U and U_old must not alias");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+    const Opts o = resolve(opts);
+    if (int rc = check_opts(o)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        return newton_t<float>(p, dt, (const float*)U_old, (float*)U, o, rep, ws, s);
+    return newton_t<double>(p, dt, (const double*)U_old, (double*)U, o, rep, ws, s);
 }
-int pf_vjp(const pf_problem* p, int, double, const void*, const void*, void*, double*, void*, void*)
+
+int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* vbar, void* Ubar,
+           double* theta_bar, void* ws, void* stream)
 {
     if (int rc = validate(p)) return rc;
-    return fail(PF_EUNSUPPORTED, "pf_vjp: not built yet");
+    if (kind != PF_VJP_RESIDUAL && kind != PF_VJP_EXPLICIT_STEP && kind != PF_VJP_NEWTON_STEP)
+        return fail(PF_EINVAL, "unknown vjp kind %d", kind);
+    if (kind != PF_VJP_RESIDUAL && (!(dt > 0.0) || !std::isfinite(dt)))
+        return fail(PF_EINVAL, "dt must be finite and > 0");
+    if (int rc = check_ptr(U, p, "U")) return rc;
+    if (int rc = check_ptr(vbar, p, "vbar")) return rc;
+    if (int rc = check_ptr(Ubar, p, "Ubar")) return rc;
+    if (Ubar == U || Ubar == vbar) return fail(PF_EINVAL, "Ubar must not alias U or vbar");
+    if (!theta_bar || reinterpret_cast<uintptr_t>(theta_bar) % 8)
+        return fail(PF_EINVAL, "theta_bar is NULL or misaligned");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (kind == PF_VJP_NEWTON_STEP) return newton_adjoint(p, dt, U, vbar, Ubar, theta_bar, ws, s);
+    if (p->dtype == PF_F32)
+        return vjp_simple_t<float>(p, kind, dt, (const float*)U, (const float*)vbar, (float*)Ubar,
+                                   theta_bar, ws, s);
+    return vjp_simple_t<double>(p, kind, dt, (const double*)U, (const double*)vbar, (double*)Ubar,
+                                theta_bar, ws, s);
 }
-}
+
+}  // extern "C"

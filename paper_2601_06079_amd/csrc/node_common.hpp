@@ -1,0 +1,215 @@
+// node_common.hpp -- device helpers of the node-centric kernels.
+//
+// One thread owns one node.  It reads the 3^d neighbourhood of the node and
+// evaluates the node's row of the weak form directly, summing over the 2^d
+// elements that share the node (no atomics, fixed summation order):
+//   nonlinear term  N(u)_a = sum_e sum_q |J| f'(u_q) phi_a(q)        (Eqs. 5-6, 10)
+//   gradient term   (K u)_a = sum_e sum_q |J| grad u_q . grad phi_a   (exact: a closed
+//                   tensor stencil, K = sum_k Khat_k (x) Mhat_others, Khat = [-1 2 -1]/h,
+//                   Mhat = h [1 4 1] / 6)
+// The 4^d quadrature values of the 2^d elements are produced by sum
+// factorisation: interp3to4 along x, then y (then z).
+#pragma once
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace pfk {
+namespace {
+
+template <int D>
+struct NB {
+    static constexpr int K = D == 2 ? 9 : 27;
+};
+
+// Neighbourhood index: (dx+1) + 3 (dy+1) + 9 (dz+1)
+template <typename T, int D>
+__device__ __forceinline__ void gather(const T* __restrict__ u, const Geom& g, int i, int j, int k,
+                                       T out[NB<D>::K])
+{
+    const int xs[3] = {wrap(i - 1, g.n[0]), i, wrap(i + 1, g.n[0])};
+    const int ys[3] = {wrap(j - 1, g.n[1]), j, wrap(j + 1, g.n[1])};
+    if constexpr (D == 2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) out[a + 3 * b] = u[(long long)ys[b] * g.n[0] + xs[a]];
+    } else {
+        const int zs[3] = {wrap(k - 1, g.n[2]), k, wrap(k + 1, g.n[2])};
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    out[a + 3 * b + 9 * c] =
+                        u[((long long)zs[c] * g.n[1] + ys[b]) * g.n[0] + xs[a]];
+    }
+}
+
+// Unit-coefficient Q1 stiffness row at the centre node (2-D: h-free; 3-D: times h).
+template <typename T, int D>
+__device__ __forceinline__ T stiff(const T* u, T h)
+{
+    if constexpr (D == 2) {
+        T kx[3], mx[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            kx[b] = (T)2 * u[1 + 3 * b] - u[3 * b] - u[2 + 3 * b];
+            mx[b] = (T)4 * u[1 + 3 * b] + u[3 * b] + u[2 + 3 * b];
+        }
+        const T km = kx[0] + (T)4 * kx[1] + kx[2];  // Khat_x (x) Mhat_y
+        const T mk = (T)2 * mx[1] - mx[0] - mx[2];  // Mhat_x (x) Khat_y
+        return (km + mk) * (T)(1.0 / 6.0);
+    } else {
+        T km[3], mk[3], mm[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T kx[3], mx[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T* r = u + 3 * b + 9 * c;
+                kx[b] = (T)2 * r[1] - r[0] - r[2];
+                mx[b] = (T)4 * r[1] + r[0] + r[2];
+            }
+            km[c] = kx[0] + (T)4 * kx[1] + kx[2];
+            mk[c] = (T)2 * mx[1] - mx[0] - mx[2];
+            mm[c] = mx[0] + (T)4 * mx[1] + mx[2];
+        }
+        const T a = (km[0] + mk[0]) + (T)4 * (km[1] + mk[1]) + (km[2] + mk[2]);  // (..) (x) Mhat_z
+        const T b = (T)2 * mm[1] - mm[0] - mm[2];                              // Mhat Mhat Khat_z
+        return (a + b) * h * (T)(1.0 / 36.0);
+    }
+}
+
+// sum_q w_q F(u_q[, v_q]) over the 4^D quadrature points around the centre node;
+// w = tensor product of (GM, GP, GP, GM).  |J| is applied by the caller.
+template <typename T, int D, bool WITHV, typename Fn>
+__device__ __forceinline__ T quad_sum(const T* u, const T* v, Fn F)
+{
+    if constexpr (D == 2) {
+        T Xu[3][4], Xv[3][4];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            interp3to4(u[3 * b], u[3 * b + 1], u[3 * b + 2], Xu[b]);
+            if constexpr (WITHV) interp3to4(v[3 * b], v[3 * b + 1], v[3 * b + 2], Xv[b]);
+        }
+        T col[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T qu[4], qv[4], fv[4];
+            interp3to4(Xu[0][qx], Xu[1][qx], Xu[2][qx], qu);
+            if constexpr (WITHV) interp3to4(Xv[0][qx], Xv[1][qx], Xv[2][qx], qv);
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) fv[qy] = F(qu[qy], WITHV ? qv[qy] : (T)0);
+            col[qx] = wsum4(fv);
+        }
+        return wsum4(col);
+    } else {
+        T Xu[9][4], Xv[9][4];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            interp3to4(u[3 * r], u[3 * r + 1], u[3 * r + 2], Xu[r]);
+            if constexpr (WITHV) interp3to4(v[3 * r], v[3 * r + 1], v[3 * r + 2], Xv[r]);
+        }
+        T plane[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T Yu[3][4], Yv[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                interp3to4(Xu[3 * c][qx], Xu[3 * c + 1][qx], Xu[3 * c + 2][qx], Yu[c]);
+                if constexpr (WITHV)
+                    interp3to4(Xv[3 * c][qx], Xv[3 * c + 1][qx], Xv[3 * c + 2][qx], Yv[c]);
+            }
+            T row[4];
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) {
+                T qu[4], qv[4], fv[4];
+                interp3to4(Yu[0][qy], Yu[1][qy], Yu[2][qy], qu);
+                if constexpr (WITHV) interp3to4(Yv[0][qy], Yv[1][qy], Yv[2][qy], qv);
+#pragma unroll
+                for (int qz = 0; qz < 4; ++qz) fv[qz] = F(qu[qz], WITHV ? qv[qz] : (T)0);
+                row[qy] = wsum4(fv);
+            }
+            plane[qx] = wsum4(row);
+        }
+        return wsum4(plane);
+    }
+}
+
+// sum_q w_q^2 F(u_q): the diagonal entry sum_e sum_q f''(u_q) phi_a(q)^2 (no |J|)
+template <typename T, int D, typename Fn>
+__device__ __forceinline__ T quad_sum_sq(const T* u, Fn F)
+{
+    const T w2[4] = {(T)(GM * GM), (T)(GP * GP), (T)(GP * GP), (T)(GM * GM)};
+    auto ws = [&](const T v[4]) { return w2[0] * v[0] + w2[1] * v[1] + w2[2] * v[2] + w2[3] * v[3]; };
+    if constexpr (D == 2) {
+        T Xu[3][4];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) interp3to4(u[3 * b], u[3 * b + 1], u[3 * b + 2], Xu[b]);
+        T col[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T qu[4], fv[4];
+            interp3to4(Xu[0][qx], Xu[1][qx], Xu[2][qx], qu);
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) fv[qy] = F(qu[qy], (T)1);
+            col[qx] = ws(fv);
+        }
+        return ws(col);
+    } else {
+        T Xu[9][4];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) interp3to4(u[3 * r], u[3 * r + 1], u[3 * r + 2], Xu[r]);
+        T plane[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T Yu[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) interp3to4(Xu[3 * c][qx], Xu[3 * c + 1][qx], Xu[3 * c + 2][qx], Yu[c]);
+            T row[4];
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) {
+                T qu[4], fv[4];
+                interp3to4(Yu[0][qy], Yu[1][qy], Yu[2][qy], qu);
+#pragma unroll
+                for (int qz = 0; qz < 4; ++qz) fv[qz] = F(qu[qz], (T)1);
+                row[qy] = ws(fv);
+            }
+            plane[qx] = ws(row);
+        }
+        return ws(plane);
+    }
+}
+
+// diagonal entry of the unit Q1 stiffness at any periodic node
+template <typename T, int D>
+__device__ __forceinline__ T stiff_diag(T h)
+{
+    return D == 2 ? (T)(8.0 / 3.0) : (T)(8.0 / 3.0) * h;
+}
+
+template <int D>
+__device__ __forceinline__ bool node_of(const Geom& g, long long idx, int& i, int& j, int& k)
+{
+    if (idx >= g.N) return false;
+    i = (int)(idx % g.n[0]);
+    long long r = idx / g.n[0];
+    j = (int)(r % g.n[1]);
+    k = D == 3 ? (int)(r / g.n[1]) : 0;
+    return true;
+}
+
+template <typename T>
+struct Cub {
+    T a1, a2, a3;
+    __device__ T operator()(T q, T) const { return cubic(q, a1, a2, a3); }
+};
+template <typename T>
+struct Lin {  // f''(q) v
+    T b0, b1, b2;
+    __device__ T operator()(T q, T v) const { return fmaT(fmaT(b2, q, b1), q, b0) * v; }
+};
+
+}  // namespace
+}  // namespace pfk

@@ -14,6 +14,7 @@
 namespace pfapi {
 namespace {
 std::atomic<int> g_rows_override{0};
+std::atomic<int> g_depth_override{0};
 int g_simds = -1;
 std::mutex g_mu;
 
@@ -56,21 +57,37 @@ int stream2d_rows(const pf_problem* p)
     return (int)best_ty;
 }
 
+int stream2d_depth(const pf_problem* p)
+{
+    (void)p;
+    const int ov = g_depth_override.load();
+    return ov > 0 ? ov : 32;
+}
+
 }  // namespace pfapi
 
 using namespace pfapi;
 extern "C" {
 int pf_tune_set(int key, int value)
 {
-    if (key != PF_TUNE_STREAM2D_ROWS) return fail(PF_EINVAL, "unknown tuning key %d", key);
     if (value < 0) return fail(PF_EINVAL, "tuning value must be >= 0");
-    g_rows_override.store(value);
+    if (key == PF_TUNE_STREAM2D_ROWS)
+        g_rows_override.store(value);
+    else if (key == PF_TUNE_STREAM2D_DEPTH)
+        g_depth_override.store(value);
+    else
+        return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
 }
 int pf_tune_get(int key, int* value)
 {
-    if (key != PF_TUNE_STREAM2D_ROWS || !value) return fail(PF_EINVAL, "bad tuning query");
-    *value = g_rows_override.load();
+    if (!value) return fail(PF_EINVAL, "value is NULL");
+    if (key == PF_TUNE_STREAM2D_ROWS)
+        *value = g_rows_override.load();
+    else if (key == PF_TUNE_STREAM2D_DEPTH)
+        *value = g_depth_override.load();
+    else
+        return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
 }
 }

@@ -1,0 +1,180 @@
+"""Backward-Euler Newton step and vector-Jacobian products: HIP vs FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2601_06079_amd import _abi as A
+from paper_2601_06079_amd import inputs as I
+from paper_2601_06079_amd import solver as S
+from tests.gpu_util import announce, dev, host, pair, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+F32, F64 = torch.float32, torch.float64
+
+
+def _ch_state(o, base, amp, seed):
+    c = I.uniform_field(o.n, -amp, amp, seed=seed, base=base)
+    # consistent initial mu = [N(c) + kappa K c]/m (the split step's algebraic row)
+    return O.explicit(o, np.concatenate([c, np.zeros_like(c)]), 1.0, 0)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("model,n", [(O.AC, (12, 10)), (O.CH, (9, 8)), (O.CH, (6, 5, 4)),
+                                     (O.AC, (5, 6, 4))])
+def test_newton_step_matches_oracle(model, n, dtype):
+    announce("newton", model, n, dtype)
+    if model == O.AC:
+        g, o = pair(n, O.AC, O.F_SYM, dtype, W=1.0, kappa=1.0, mob=1.0)
+        Uold = I.uniform_field(n, -0.5, 0.5, seed=3)
+        dt = 0.5
+    else:
+        g, o = pair(n, O.CH, O.F_01, dtype, W=1.0, kappa=2.0, mob=1.0)
+        Uold = _ch_state(o, 0.4, 0.05, 4)
+        dt = 0.5
+    Uold = rounded(Uold, dtype)
+    Ug, Uog = dev(Uold, dtype), dev(Uold, dtype)
+    rtol = 1e-11 if dtype == F64 else 1e-8
+    rep = S.newton_step(g, dt, Uog, Ug, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8))
+    assert rep.converged, rep
+    Uo, conv, its, _ = O.newton_be(o, dt, Uold, rtol=1e-13, maxit=30, solver=0)
+    assert conv
+    tol = 1e-9 if dtype == F64 else 1e-5
+    assert rel_l2(host(Ug), Uo) < tol
+    if model == O.CH:  # mass conserved by the step
+        N = o.nnodes
+        assert abs(host(Ug)[:N].sum() - Uold[:N].sum()) < (1e-10 if dtype == F64 else 1e-4) * N
+
+
+def test_newton_linear_mode_closed_form():
+    """f == 0 Allen-Cahn: backward Euler damps a Fourier mode by 1/(1 + dt L kappa lambda_K)."""
+    n, k, h, dt = (16, 12), (3, 2), 1.0, 0.7
+    th = [2 * np.pi * k[a] / n[a] for a in range(2)]
+    lk = (8 - 2 * np.cos(th[0]) - 2 * np.cos(th[1]) - 4 * np.cos(th[0]) * np.cos(th[1])) / 3
+    X, Y = np.meshgrid(np.arange(n[0]), np.arange(n[1]))
+    mode = np.cos(th[0] * X + th[1] * Y).ravel()
+    g = S.Problem(n=n, model=A.ALLEN_CAHN, fe=A.F_SYM, dtype=F64, W=0.0, kappa=1.5, mobility=0.9)
+    Uo, U = dev(mode, F64), dev(mode, F64)
+    rep = S.newton_step(g, dt, Uo, U, S.newton_opts(rtol=1e-13, lin_rtol_min=1e-12, lin_rtol_max=1e-12))
+    assert rep.converged
+    assert rel_l2(host(U), mode / (1 + dt * 0.9 * 1.5 * lk)) < 1e-11
+
+
+def test_newton_3d_ch_32_cubed_several_steps():
+    """The 3-D Cahn-Hilliard implicit workload's shape at 32^3: 3 steps vs the oracle."""
+    cfg = I.CH3D128
+    n = (32, 32, 32)
+    announce("newton 3d 32^3")
+    g, o = pair(n, O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U0 = rounded(_ch_state(o, cfg["base"], 0.02, 0), F32)
+    Ug = dev(U0, F32)
+    Uo = U0.copy()
+    ws = S.workspace(g, A.OP_NEWTON)
+    for step in range(3):
+        Uold_g = Ug.clone()
+        rep = S.newton_step(g, cfg["dt"], Uold_g, Ug, ws=ws)
+        assert rep.converged, rep
+        Uo, conv, its, hist = O.newton_be(o, cfg["dt"], Uo, rtol=1e-10, maxit=30, solver=1,
+                                          lin_rtol=1e-12)
+        assert conv
+        assert rel_l2(host(Ug)[: o.nnodes], Uo[: o.nnodes]) < 1e-5
+    N = o.nnodes
+    assert abs(host(Ug)[:N].mean() - U0[:N].mean()) < 1e-6
+
+
+def test_newton_3d_ch_128_cubed_full_size_one_step():
+    """Full-size 128^3 (4.19M DOF) step: the oracle checks the root through its own residual."""
+    cfg = I.CH3D128
+    n = cfg["n"]
+    announce("newton 3d 128^3")
+    g, o = pair(n, O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    c0 = I.uniform_field(n, cfg["lo"], cfg["hi"], seed=0, base=cfg["base"]).astype(np.float32)
+    Ug = dev(np.concatenate([c0, np.zeros_like(c0)]), F32)
+    S.step_explicit(g, Ug, 1e-30, 0)  # fills mu = [N(c) + kappa K c]/m (consistent start)
+    Uold = host(Ug)
+    rep = S.newton_step(g, cfg["dt"], Ug.clone(), Ug)
+    assert rep.converged, rep
+    U1 = host(Ug)
+    R0 = np.linalg.norm(O.be_residual(o, cfg["dt"], Uold, Uold))
+    R1 = np.linalg.norm(O.be_residual(o, cfg["dt"], Uold, U1))
+    assert R1 < 1e-3 * R0, (R1, R0, rep)
+    N = o.nnodes
+    assert abs(U1[:N].astype(np.float64).mean() - Uold[:N].astype(np.float64).mean()) < 1e-6
+
+
+def test_newton_reports_nonconvergence():
+    g, o = pair((16, 16), O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U0 = dev(rounded(_ch_state(o, 0.4, 0.05, 1), F32), F32)
+    U = U0.clone()
+    rep = S.newton_step(g, 0.5, U0, U, S.newton_opts(max_newton=1, stagnation=0, rtol=1e-12))
+    assert not rep.converged and rep.newton_its == 1 and rep.reason == -1
+    with pytest.raises(A.PFError) as ei:
+        S.newton_step(g, 0.5, U0, U0.clone(), S.newton_opts(max_newton=1, stagnation=0, rtol=1e-12),
+                      raise_on_noconv=True)
+    assert ei.value.status == A.PF_ENOCONV
+
+
+def test_newton_nonfinite_input():
+    g, o = pair((16, 16), O.AC, O.F_SYM, F32)
+    U = torch.zeros(256, dtype=F32, device="cuda")
+    U[17] = float("nan")
+    rep = S.newton_step(g, 0.5, U.clone(), U)
+    assert not rep.converged and rep.reason == -2
+
+
+# ------------------------------------------------------------- VJP ----------
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("model,n", [(O.AC, (20, 17)), (O.CH, (16, 13)), (O.CH, (5, 6, 7)),
+                                     (O.AC, (6, 5, 4))])
+def test_vjp_residual(model, n, dtype):
+    announce("vjp residual", model, n, dtype)
+    g, o = pair(n, model, O.F_01, dtype, W=1.2, kappa=0.8, mob=1.3)
+    U = rounded(np.random.default_rng(2).uniform(0.2, 0.8, o.ndof), dtype)
+    w = rounded(np.random.default_rng(3).standard_normal(o.ndof), dtype)
+    Ub = torch.zeros(o.ndof, dtype=dtype, device="cuda")
+    tb = torch.zeros(3, dtype=F64, device="cuda")
+    S.vjp(g, A.VJP_RESIDUAL, 1.0, dev(U, dtype), dev(w, dtype), Ub, tb)
+    tol = 1e-11 if dtype == F64 else 1e-5
+    assert rel_l2(host(Ub), O.jvp_t(o, 0.0, U, w)) < tol
+    np.testing.assert_allclose(host(tb), O.dr_dtheta(o, U, w), rtol=tol * 10)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("model,n", [(O.AC, (24, 19)), (O.CH, (18, 15)), (O.AC, (7, 6, 5)),
+                                     (O.CH, (6, 5, 4))])
+def test_vjp_explicit_step(model, n, dtype):
+    announce("vjp explicit", model, n, dtype)
+    g, o = pair(n, model, O.F_01 if model == O.CH else O.F_SYM, dtype, W=1.2, kappa=0.8, mob=1.3)
+    N = o.nnodes
+    base = 0.5 if model == O.CH else 0.0
+    U = rounded(I.uniform_field(n, -0.3, 0.3, seed=5, base=base), dtype)
+    if model == O.CH:
+        U = np.concatenate([U, np.zeros(N)])
+    vb = rounded(np.random.default_rng(6).standard_normal(N), dtype)
+    dt = 0.05
+    Ub = torch.zeros(o.ndof if model == O.AC else N, dtype=dtype, device="cuda")
+    tb = torch.zeros(3, dtype=F64, device="cuda")
+    S.vjp(g, A.VJP_EXPLICIT_STEP, dt, dev(U, dtype), dev(vb, dtype), Ub, tb)
+    tref, uref = O.explicit_adjoint(o, dt, 1, U, vb)
+    tol = 1e-11 if dtype == F64 else 1e-5
+    assert rel_l2(host(Ub)[:N], uref) < tol
+    np.testing.assert_allclose(host(tb), tref, rtol=tol * 100, atol=1e-12 * np.abs(tref).max())
+
+
+@pytest.mark.parametrize("model,n", [(O.AC, (6, 5)), (O.CH, (5, 4)), (O.CH, (3, 3, 4))])
+def test_vjp_newton_step(model, n):
+    announce("vjp newton", model, n)
+    g, o = pair(n, model, O.F_01, F64, W=1.0, kappa=2.0, mob=1.0)
+    if model == O.CH:
+        Uold = _ch_state(o, 0.4, 0.1, 7)
+    else:
+        Uold = I.uniform_field(n, 0.2, 0.8, seed=7)
+    dt = 0.5
+    U, conv, _, _ = O.newton_be(o, dt, Uold, rtol=1e-14, maxit=30, solver=0)
+    w = np.random.default_rng(8).standard_normal(o.ndof)
+    Ub = torch.zeros(o.ndof, dtype=F64, device="cuda")
+    tb = torch.zeros(3, dtype=F64, device="cuda")
+    S.vjp(g, A.VJP_NEWTON_STEP, dt, dev(U, F64), dev(w, F64), Ub, tb)
+    tref, uref = O.newton_adjoint(o, dt, U, w, solver=0)
+    assert rel_l2(host(Ub), uref) < 1e-9
+    np.testing.assert_allclose(host(tb), tref, rtol=1e-8)
