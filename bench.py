@@ -36,7 +36,69 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "ch2048_traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("STEP_DIR", "COPY_DIR", "COPY_MIB"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of the step and of "
+                         "the copy into the traffic record read by the roofline")
     return ap.parse_args()
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_06079_amd", "csrc", "k_stream2d.hip")
+
+
+def kernel_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def calibrate_copy(mib):
+    import torch
+    x = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(20):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read": x.numel() * 4, "bytes_written": x.numel() * 4}))
+
+
+def _counter_means(d):
+    """Mean per dispatch of each (kernel, counter) in a rocprofv3 --pmc output tree."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            key = (r["Kernel_Name"], r["Counter_Name"])
+            acc.setdefault(key, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the step kernel, scaled by the
+    ratio true bytes / counter reading of a plain copy of known size."""
+    step = {}
+    for sub in ("fetch", "write"):
+        step.update(_counter_means(os.path.join(step_dir, sub)))
+    cp = {}
+    for sub in ("fetch", "write"):
+        cp.update(_counter_means(os.path.join(copy_dir, sub)))
+    nbytes = copy_mib * 2 ** 20
+    cf = [v for (k, c), v in cp.items() if c == "FETCH_SIZE" and v * 1024 > 0.5 * nbytes]
+    cw = [v for (k, c), v in cp.items() if c == "WRITE_SIZE" and v * 1024 > 0.5 * nbytes]
+    f_scale = nbytes / (max(cf) * 1024) if cf else 1.0
+    w_scale = nbytes / (max(cw) * 1024) if cw else 1.0
+    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and "k_explicit2d" in k]
+    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and "k_explicit2d" in k]
+    rec = {"n": n, "kernel_src_sha256_16": kernel_hash(),
+           "fetch_kib_raw": kf[0] if kf else None, "write_kib_raw": kw[0] if kw else None,
+           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
+    if kf and kw:
+        rec["bytes_per_launch"] = kf[0] * 1024 * f_scale + kw[0] * 1024 * w_scale
+        rec["algorithmic_bytes_per_launch"] = BYTES_PER_NODE_STEP * n * n
+    out = os.path.join(ROOT, "profiles", "ch2048_traffic.json")
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(n, steps):
@@ -59,6 +121,13 @@ def cpu_baseline(n, steps):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                           int(args.summarize_counters[2]), n=args.n)
+        return
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
                                    "part of this build (--gpus must be 1)"}))
@@ -115,13 +184,14 @@ def main():
     kern_ms = max(two - epi, 1e-6) / 2.0
     achieved = BYTES_PER_NODE_STEP * N / (kern_ms * 1e-3) / 1e9
 
+    # measured HBM bytes per launch, only if taken on this exact kernel source
     traffic = None
     if os.path.exists(args.traffic):
         try:
             t = json.load(open(args.traffic))
-            if t.get("n") == n:
+            if t.get("n") == n and t.get("kernel_src_sha256_16") == kernel_hash():
                 traffic = t.get("bytes_per_launch")
-        except Exception:
+        except (OSError, ValueError):
             traffic = None
 
     out = {

@@ -153,7 +153,11 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
         guR_m1 = guR;
     };
 
-    // prefetch ring: slot (t mod PF) holds row y0 - H + t
+    // prefetch ring: slot (t mod PF) holds row y0 - H + t.  Every row runs the
+    // step unconditionally (rows past the chunk compute values nobody stores),
+    // so the register window never needs merging; only the prefetch and the
+    // store are predicated.  The host picks ty so that iters is a multiple of
+    // PF whenever it can, leaving no idle rows.
     T ring[PF];
     int rl = y0 - H;
     while (rl < 0) rl += ny;
@@ -162,40 +166,24 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
         ring[u] = u < iters ? bload<T>(rin, vx, rl * rowb) : (T)0;
         if (++rl == ny) rl = 0;
     }
-    // first block: warm-up rows (no store for t < 2H)
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        if (u < iters) {
-            const T cc = ring[u];
-            if (u + PF < iters) {
-                ring[u] = bload<T>(rin, vx, rl * rowb);
-                if (++rl == ny) rl = 0;
-            }
-            step(cc, u, u >= 2 * H);
-        }
-    }
-    // steady state: every row loads PF ahead and stores
-    int t0 = PF;
-    for (; t0 + 2 * PF <= iters; t0 += PF) {
+    // The prefetch load itself is unconditional: once the chunk's last row has
+    // been requested the row index stops advancing and the same row is read
+    // again (a cache hit).  A conditional load would make the compiler wait for
+    // it immediately.
+    int rlast = y1 + H - 1;
+    while (rlast >= ny) rlast -= ny;
+    for (int t0 = 0; t0 < iters; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
+            const int t = t0 + u;
             const T cc = ring[u];
             ring[u] = bload<T>(rin, vx, rl * rowb);
-            if (++rl == ny) rl = 0;
-            step(cc, t0 + u, true);
-        }
-    }
-    // tail: fewer than 2 PF rows left
-#pragma unroll
-    for (int u = 0; u < 2 * PF; ++u) {
-        const int t = t0 + u;
-        if (t < iters) {
-            const T cc = ring[u % PF];
-            if (t + PF < iters) {
-                ring[u % PF] = bload<T>(rin, vx, rl * rowb);
+            if (t + PF + 1 < iters) {
                 if (++rl == ny) rl = 0;
+            } else {
+                rl = rlast;
             }
-            step(cc, t, true);
+            step(cc, t, t >= 2 * H && t < iters);
         }
     }
 }
@@ -204,7 +192,9 @@ template <typename T, int MODEL>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
                   int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
 {
-    if (depth <= 8)
+    if (depth <= 4)
+        k_explicit2d<T, MODEL, 4><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+    else if (depth <= 8)
         k_explicit2d<T, MODEL, 8><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     else if (depth <= 16)
         k_explicit2d<T, MODEL, 16><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);

@@ -375,7 +375,7 @@ int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, 
     int its = 0;
     double res = 0.0;
     // the adjoint solve is taken to the field-precision floor, not an inexact-Newton tolerance
-    const double tol = std::max(o.lmin * 1e-2, sizeof(T) == 4 ? 1e-6 : 1e-12) * bn;
+    const double tol = (sizeof(T) == 4 ? 1e-6 : 1e-12) * bn;
     if (int rc = gmres<T>(At, L, n, o.m, o.max_its * 4, o.precond == PF_PRECOND_JACOBI, bn, tol,
                           &its, &res, s))
         return rc;

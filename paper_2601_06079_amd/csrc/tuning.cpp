@@ -1,11 +1,7 @@
-// tuning.cpp -- launch-shape choices for the fused 2-D explicit kernel.
-//
-// The kernel's cost is VALU issue on each SIMD: a wave marching ty rows costs
-// about (ty + 2H) row-steps, and waves that land on the same SIMD serialise.
-// With W waves spread over the S SIMDs of the device, the busiest SIMD runs
-// ceil(W / S) waves, so the step time is proportional to
-//     ceil(W(ty) / S) * (ty + 2H),   W(ty) = strips * ceil(ny / ty).
-// The chooser minimises that over ty; pf_tune_set overrides it.
+// tuning.cpp -- launch-shape choices for the fused 2-D explicit kernel:
+// rows per wavefront (chunk length) and prefetch depth.  Defaults come from
+// measurements on MI355X; pf_tune_set overrides them (the autotuner uses it).
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -43,25 +39,22 @@ int stream2d_rows(const pf_problem* p)
     const long long nx = p->n[0], ny = p->n[1];
     const long long strips = (nx + (64 - 2 * H) - 1) / (64 - 2 * H);
     const long long S = device_simds();
-    long long best_ty = 32, best_cost = -1;
-    for (long long ty = 8; ty <= ny; ++ty) {
-        const long long W = strips * ((ny + ty - 1) / ty);
-        const long long cost = ((W + S - 1) / S) * (ty + 2 * H);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best_ty = ty;
-        }
-        if (ty > 8 && (ny + ty - 1) / ty == 1) break;
-    }
-    if (ny < 8) best_ty = ny;
-    return (int)best_ty;
+    // Measured on MI355X (2048^2 and 16384^2 Cahn-Hilliard): chunks of about
+    // 24 rows (28 rows in flight incl. halo, a multiple of the prefetch depth)
+    // with 2-3 waves per SIMD are fastest; longer chunks lose to fewer waves in
+    // flight, shorter ones to halo recomputation.  Small grids shrink the chunk
+    // until every SIMD has a wave, down to 8 rows.
+    long long ty = 28 - 2 * H;
+    while (ty > 8 && strips * ((ny + ty - 1) / ty) < 2 * S) ty -= 4;
+    if (ty > ny) ty = ny;
+    return (int)std::max<long long>(ty, 1);
 }
 
 int stream2d_depth(const pf_problem* p)
 {
     (void)p;
     const int ov = g_depth_override.load();
-    return ov > 0 ? ov : 32;
+    return ov > 0 ? ov : 4;
 }
 
 }  // namespace pfapi
