@@ -87,8 +87,9 @@ int pf_version(void);
 /* Launch-shape overrides, process-global (value 0 restores the automatic
  * choice).  Used by the autotuner; results never depend on them.
  *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel;
- *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=8, <=16, else 32). */
-enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1 };
+ *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
+ *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4). */
+enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 

@@ -108,9 +108,17 @@ int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws,
     // the fused 2-D kernel addresses a field with 32-bit buffer offsets
     const bool fused2d = p->dim == 2 && (size_t)g.N * sizeof(T) < (size_t(1) << 31);
     if (fused2d) {
-        pfk::Stream2DConfig cfg{stream2d_rows(p), stream2d_depth(p)};
-        for (int64_t st = 0; st < nsteps; ++st) {
+        // launches of ks fused steps, then the remainder one step at a time
+        const int ks = stream2d_fuse(p);
+        pfk::Stream2DConfig cfg{stream2d_rows(p, ks), stream2d_depth(p), ks};
+        pfk::Stream2DConfig one{stream2d_rows(p, 1), stream2d_depth(p), 1};
+        int64_t st = 0;
+        for (; ks > 1 && st + ks <= nsteps; st += ks) {
             pfk::launch_explicit2d<T>(g, p->model, f, p->kappa, p->mobility, dt, cur, other, cfg, s);
+            std::swap(cur, other);
+        }
+        for (; st < nsteps; ++st) {
+            pfk::launch_explicit2d<T>(g, p->model, f, p->kappa, p->mobility, dt, cur, other, one, s);
             std::swap(cur, other);
         }
     } else if (p->model == PF_ALLEN_CAHN) {

@@ -17,8 +17,10 @@ pfk::Geom geom_of(const pf_problem* p);
 long long ndof(const pf_problem* p);
 size_t elem_size(const pf_problem* p);
 
-// rows per wave of the 2-D streaming kernel for this problem (tuning table)
-int stream2d_rows(const pf_problem* p);
+// launch shape of the fused 2-D explicit kernel for this problem (tuning table):
+// steps fused per launch, rows per wave for a given fusion depth, prefetch depth
+int stream2d_fuse(const pf_problem* p);
+int stream2d_rows(const pf_problem* p, int ks);
 int stream2d_depth(const pf_problem* p);
 
 size_t newton_workspace_bytes(const pf_problem* p, int restart);

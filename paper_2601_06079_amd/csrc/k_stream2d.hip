@@ -67,41 +67,16 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int v
     __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
 }
 
-// MODEL 0: Allen-Cahn   out = c - [dt L |J|/m] N'(c) - [dt L kappa/(3m)] (9c - box c)
-// MODEL 1: Cahn-Hilliard mu = [|J|/m] N'(c) + [kappa/(3m)] (9c - box c)
-//                        out = c - [dt M/(3m)] (9 mu - box mu)
-// N' is the quadrature sum with the scaled cubic (a1, a2, a3).
-// PF: rows in flight per wave (register prefetch ring depth)
-template <typename T, int MODEL, int PF>
-__global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
-                                                    int nx, int ny, int nstrips, int nwaves, int ty,
-                                                    unsigned bytes, Coef<T> k)
-{
-    constexpr int H = MODEL == 0 ? 1 : 2;
-    constexpr int OUTW = WAVE - 2 * H;
-    const int lane = threadIdx.x & (WAVE - 1);
-    // wave index made provably uniform so that all row bookkeeping stays scalar
-    const int wave = (int)(blockIdx.x * (blockDim.x / WAVE)) +
-                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (wave >= nwaves) return;  // uniform per wave
-    const int strip = wave % nstrips;
-    const int chunk = wave / nstrips;
-    const int x0 = strip * OUTW;
-    const int xl = x0 - H + lane;
-    int x = xl % nx;
-    if (x < 0) x += nx;
-    const bool out_lane = lane >= H && lane < WAVE - H && xl < nx;
-    const int y0 = chunk * ty;
-    const int y1 = min(y0 + ty, ny);
-    const int iters = (y1 - y0) + 2 * H;  // rows y0-H .. y1+H-1
-    const int rowb = nx * (int)sizeof(T);  // bytes per row
-    const int vx = x * (int)sizeof(T);
-    const auto rin = make_rsrc(in, bytes);
-    const auto rout = make_rsrc(out, bytes);
-
-    const T gp = (T)GP, gm = (T)GM;
-
-    // register window (see the header comment for the pipeline)
+// One explicit step as a row pipeline.  push(cc) takes c of the newest row
+// r (per lane = column) and returns the stepped value of row r - H
+// (H = 1 Allen-Cahn, 2 Cahn-Hilliard); the register window holds the rows
+// in between.  Lane validity shrinks by H lanes per side per stage.
+//   MODEL 0: Allen-Cahn    out = c - [dt L |J|/m] N'(c) - [dt L kappa/(3m)] (9c - box c)
+//   MODEL 1: Cahn-Hilliard mu  = [|J|/m] N'(c) + [kappa/(3m)] (9c - box c)
+//                          out = c - [dt M/(3m)] (9 mu - box mu)
+// N' is the quadrature sum with the scaled cubic (a1, a2, a3); box = 3x3 sum.
+template <typename T, int MODEL>
+struct Stage {
     T c_m1 = 0, c_m2 = 0;        // c at rows r-1, r-2
     T s3_m1 = 0, s3_m2 = 0;      // 3-point x-sums of c at rows r-1, r-2
     T xl_m1 = 0, xr_m1 = 0;      // x-interpolated values of row r-1
@@ -109,9 +84,9 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     T mu_m1 = 0;                 // CH: mu at row r-2
     T s3mu_m1 = 0, s3mu_m2 = 0;  // CH: x-sums of mu at rows r-2, r-3
 
-    // One row of the pipeline: cc is c at the newest row r = y0 - H + t; the
-    // finished output row is y0 - 2H + t (AC: r - 1, CH: r - 2).
-    auto step = [&](T cc, int t, bool store) {
+    __device__ __forceinline__ T push(T cc, const Coef<T>& k)
+    {
+        const T gp = (T)GP, gm = (T)GM;
         const T cl = from_left(cc), cr = from_right(cc);
         const T s3 = cl + cc + cr;
         const T d = cr - cc;
@@ -142,7 +117,6 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
             s3mu_m1 = s3mu;
             mu_m1 = mu;
         }
-        if (store && out_lane) bstore(v, rout, vx, (y0 - 2 * H + t) * rowb);
         c_m2 = c_m1;
         c_m1 = cc;
         s3_m2 = s3_m1;
@@ -151,15 +125,51 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
         xr_m1 = xr_0;
         guL_m1 = guL;
         guR_m1 = guR;
-    };
+        return v;
+    }
+};
 
-    // prefetch ring: slot (t mod PF) holds row y0 - H + t.  Every row runs the
-    // step unconditionally (rows past the chunk compute values nobody stores),
-    // so the register window never needs merging; only the prefetch and the
-    // store are predicated.  The host picks ty so that iters is a multiple of
-    // PF whenever it can, leaving no idle rows.
+// KS explicit steps in one pass (temporal blocking): stage s consumes the rows
+// stage s-1 produces, so a row is read from memory once and written once per
+// KS steps.  Each stage performs exactly the arithmetic of a single-step
+// launch, so the result is bitwise that of KS single steps.
+// PF: rows in flight per wave (register prefetch ring depth).
+template <typename T, int MODEL, int PF, int KS>
+__global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
+                                                    int nx, int ny, int nstrips, int nwaves, int ty,
+                                                    unsigned bytes, Coef<T> k)
+{
+    constexpr int H = MODEL == 0 ? 1 : 2;
+    constexpr int HK = H * KS;            // halo of the whole pass
+    constexpr int OUTW = WAVE - 2 * HK;   // output columns per strip
+    const int lane = threadIdx.x & (WAVE - 1);
+    // wave index made provably uniform so that all row bookkeeping stays scalar
+    const int wave = (int)(blockIdx.x * (blockDim.x / WAVE)) +
+                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if (wave >= nwaves) return;  // uniform per wave
+    const int strip = wave % nstrips;
+    const int chunk = wave / nstrips;
+    const int x0 = strip * OUTW;
+    const int xl = x0 - HK + lane;
+    int x = xl % nx;
+    if (x < 0) x += nx;
+    const bool out_lane = lane >= HK && lane < WAVE - HK && xl < nx;
+    const int y0 = chunk * ty;
+    const int y1 = min(y0 + ty, ny);
+    const int iters = (y1 - y0) + 2 * HK;  // rows y0-HK .. y1+HK-1
+    const int rowb = nx * (int)sizeof(T);  // bytes per row
+    const int vx = x * (int)sizeof(T);
+    const auto rin = make_rsrc(in, bytes);
+    const auto rout = make_rsrc(out, bytes);
+
+    Stage<T, MODEL> st[KS];
+
+    // prefetch ring: slot (t mod PF) holds row y0 - HK + t.  Every row runs the
+    // pipeline unconditionally (rows past the chunk compute values nobody
+    // stores), so the register window never needs merging; only the prefetch
+    // and the store are predicated.
     T ring[PF];
-    int rl = y0 - H;
+    int rl = y0 - HK;
     while (rl < 0) rl += ny;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -170,36 +180,49 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     // been requested the row index stops advancing and the same row is read
     // again (a cache hit).  A conditional load would make the compiler wait for
     // it immediately.
-    int rlast = y1 + H - 1;
+    int rlast = y1 + HK - 1;
     while (rlast >= ny) rlast -= ny;
     for (int t0 = 0; t0 < iters; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = t0 + u;
-            const T cc = ring[u];
+            T v = ring[u];
             ring[u] = bload<T>(rin, vx, rl * rowb);
             if (t + PF + 1 < iters) {
                 if (++rl == ny) rl = 0;
             } else {
                 rl = rlast;
             }
-            step(cc, t, t >= 2 * H && t < iters);
+#pragma unroll
+            for (int sidx = 0; sidx < KS; ++sidx) v = st[sidx].push(v, k);
+            // the last stage just finished row y0 - 2 HK + t
+            if (t >= 2 * HK && t < iters && out_lane) bstore(v, rout, vx, (y0 - 2 * HK + t) * rowb);
         }
     }
 }
 
-template <typename T, int MODEL>
+template <typename T, int MODEL, int KS>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
                   int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
 {
     if (depth <= 4)
-        k_explicit2d<T, MODEL, 4><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     else if (depth <= 8)
-        k_explicit2d<T, MODEL, 8><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
-    else if (depth <= 16)
-        k_explicit2d<T, MODEL, 16><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     else
-        k_explicit2d<T, MODEL, 32><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+}
+
+template <typename T, int MODEL>
+void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
+               int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
+{
+    switch (ks) {
+        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
+        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
+        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
+        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
+    }
 }
 
 }  // namespace
@@ -211,7 +234,8 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
     const int nx = g.n[0], ny = g.n[1];
     const double h = g.h, m = h * h, detJ = 0.25 * h * h;
     const int H = model == 0 ? 1 : 2;
-    const int outw = WAVE - 2 * H;
+    const int ks = cfg.ks >= 1 && cfg.ks <= 4 ? cfg.ks : 1;
+    const int outw = WAVE - 2 * H * ks;
     const int ty = cfg.ty > 0 ? cfg.ty : 32;
     const int nstrips = (nx + outw - 1) / outw;
     const int nchunks = (ny + ty - 1) / ty;
@@ -223,13 +247,13 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
         const double sc = dt * mob * detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        launch_depth<T, 0>(cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     } else {
         const double sc = detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(kappa / (3.0 * m));
         k.gamma = (T)(dt * mob / (3.0 * m));
-        launch_depth<T, 1>(cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
     }
 }
 

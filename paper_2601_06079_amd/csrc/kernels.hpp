@@ -77,9 +77,10 @@ void launch_vjp_explicit(const Geom& g, int model, const FreeEnergy& f, double k
 // ---- fused 2-D explicit streaming kernels (k_stream2d.hip) ------------------
 struct Stream2DConfig {
     int ty;     // rows per wave
-    int depth;  // rows in flight per wave (8, 16 or 32)
+    int depth;  // rows in flight per wave (4, 8 or 16)
+    int ks;     // explicit steps fused per launch (1..4)
 };
-// One explicit step in -> out (out != in).  model 0: Allen-Cahn, 1: Cahn-Hilliard c-plane.
+// cfg.ks explicit steps in -> out (out != in).  model 0: Allen-Cahn, 1: Cahn-Hilliard c-plane.
 template <typename T>
 void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                        double dt, const T* in, T* out, const Stream2DConfig& cfg, hipStream_t s);

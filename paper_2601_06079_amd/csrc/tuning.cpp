@@ -11,6 +11,7 @@ namespace pfapi {
 namespace {
 std::atomic<int> g_rows_override{0};
 std::atomic<int> g_depth_override{0};
+std::atomic<int> g_fuse_override{0};
 int g_simds = -1;
 std::mutex g_mu;
 
@@ -31,21 +32,29 @@ int device_simds()
 }
 }  // namespace
 
-int stream2d_rows(const pf_problem* p)
+int stream2d_fuse(const pf_problem* p)
+{
+    (void)p;
+    const int ov = g_fuse_override.load();
+    // two fused steps measured fastest on MI355X at 2048^2 and 8192^2 (three and
+    // four add more halo recomputation than they save in launches and traffic)
+    return ov > 0 ? std::min(ov, 4) : 2;
+}
+
+int stream2d_rows(const pf_problem* p, int ks)
 {
     const int ov = g_rows_override.load();
     if (ov > 0) return ov;
-    const int H = p->model == PF_CAHN_HILLIARD ? 2 : 1;
+    const int HK = (p->model == PF_CAHN_HILLIARD ? 2 : 1) * ks;
     const long long nx = p->n[0], ny = p->n[1];
-    const long long strips = (nx + (64 - 2 * H) - 1) / (64 - 2 * H);
+    const long long strips = (nx + (64 - 2 * HK) - 1) / (64 - 2 * HK);
     const long long S = device_simds();
-    // Measured on MI355X (2048^2 and 16384^2 Cahn-Hilliard): chunks of about
-    // 24 rows (28 rows in flight incl. halo, a multiple of the prefetch depth)
-    // with 2-3 waves per SIMD are fastest; longer chunks lose to fewer waves in
-    // flight, shorter ones to halo recomputation.  Small grids shrink the chunk
-    // until every SIMD has a wave, down to 8 rows.
-    long long ty = 28 - 2 * H;
-    while (ty > 8 && strips * ((ny + ty - 1) / ty) < 2 * S) ty -= 4;
+    // Measured on MI355X: chunks of up to 48 rows, shortened until every SIMD
+    // has about four waves (latency hiding); the chunk plus its halo is kept a
+    // multiple of the prefetch depth (4) so no wave runs idle rows.
+    long long ty = 48;
+    while ((ty + 2 * HK) % 4) --ty;
+    while (ty > 8 && strips * ((ny + ty - 1) / ty) < 4 * S) ty -= 4;
     if (ty > ny) ty = ny;
     return (int)std::max<long long>(ty, 1);
 }
@@ -68,6 +77,8 @@ int pf_tune_set(int key, int value)
         g_rows_override.store(value);
     else if (key == PF_TUNE_STREAM2D_DEPTH)
         g_depth_override.store(value);
+    else if (key == PF_TUNE_STREAM2D_FUSE)
+        g_fuse_override.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -79,6 +90,8 @@ int pf_tune_get(int key, int* value)
         *value = g_rows_override.load();
     else if (key == PF_TUNE_STREAM2D_DEPTH)
         *value = g_depth_override.load();
+    else if (key == PF_TUNE_STREAM2D_FUSE)
+        *value = g_fuse_override.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

@@ -190,3 +190,26 @@ def test_explicit_launch_shapes_agree(rows):
     finally:
         S.tune_set(A.TUNE_STREAM2D_ROWS, 0)
     assert torch.equal(ref, t)
+
+
+@pytest.mark.parametrize("ks", [2, 3, 4])
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model,n", [(O.AC, (128, 128)), (O.CH, (200, 150)), (O.CH, (61, 37)),
+                                     (O.AC, (5, 7)), (O.CH, (2048, 64))])
+def test_explicit_temporal_blocking_bitwise(ks, dtype, model, n):
+    """ks fused steps per launch give bitwise the field of ks single-step launches."""
+    announce("fused", ks, dtype, model, n)
+    fe = O.F_01 if model == O.CH else O.F_SYM
+    g, o = pair(n, model, fe, dtype, W=1.0, kappa=2.0 if model == O.CH else 1.0, mob=1.0)
+    base = 0.5 if model == O.CH else 0.0
+    U0 = _rand_state(o, -0.05, 0.05, 12, base=base)
+    dt = 0.01 if model == O.CH else 0.1
+    ref = dev(U0, dtype)
+    S.step_explicit(g, ref, dt, 2 * ks + 1)
+    try:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, ks)
+        t = dev(U0, dtype)
+        S.step_explicit(g, t, dt, 2 * ks + 1)
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+    assert torch.equal(ref, t)
