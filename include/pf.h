@@ -198,6 +198,75 @@ enum { PF_VJP_RESIDUAL = 0, PF_VJP_EXPLICIT_STEP = 1, PF_VJP_NEWTON_STEP = 2 };
 int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* vbar,
            void* Ubar, double* theta_bar, void* ws, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Ragged batches of independent 2-D problems (many samples in one launch) */
+/* ---------------------------------------------------------------------- */
+/* One sample of a batch: its own grid and material parameters.  All samples
+ * share the base problem's model, free energy, dtype and (periodic) boundary. */
+typedef struct pf_batch_sample {
+    int64_t offset; /* element offset of this sample's field in the packed arrays */
+    int64_t n[3];   /* nodes per axis (n[2] ignored); each sample < 2 GiB */
+    double h, W, kappa, mobility;
+} pf_batch_sample;
+
+/* Host-side description of a device plan (filled by pf_batch_plan). */
+typedef struct pf_batch_info {
+    int32_t count, n_items, n_vblocks; /* samples, explicit work items, 256-node blocks */
+    int32_t ks, ty, depth;             /* fused steps, rows per wave, prefetch depth */
+    int32_t model, dtype;
+    int64_t total;                     /* elements of each packed array (max offset + nodes) */
+    int64_t plan_bytes;
+    double dt;
+    int64_t off_samples, off_items, off_vmap; /* byte offsets of the plan's tables */
+} pf_batch_info;
+
+/* Bytes of the device plan for these samples with ks fused steps and ty rows
+ * per wave (0 = the largest automatic choice may need).  Host-only. */
+int pf_batch_plan_size(const pf_problem* base, const pf_batch_sample* samples, int count, int ks,
+                       int ty, size_t* bytes);
+
+/* Build the launch plan of a batch (work items of the explicit kernel, per-sample
+ * coefficients for step dt) on the host and copy it to plan_dev (caller-owned
+ * device memory, 256-byte aligned, plan_bytes long).  ks/ty/depth = 0 take the
+ * autotuned choice for this batch shape if pf_batch_autotune ran, else the
+ * defaults.  Sample ranges must not overlap.  Host-synchronous (waits for the
+ * copy).  base supplies dim (2), bc (periodic), model, fe and dtype only. */
+int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+                  int ks, int ty, int depth, void* plan_dev, size_t plan_bytes,
+                  pf_batch_info* info, void* stream);
+
+/* Workspace of a batched call: PF_OP_STEP_EXPLICIT (one packed field) or
+ * PF_OP_VJP (one packed field + FP64 partials). */
+int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes);
+
+/* nsteps explicit steps (Eq. 12) of every sample, one launch per info->ks steps
+ * for the whole batch.  traj == NULL: in place on U (nsteps a multiple of ks;
+ * ws one packed field); elements of U outside every sample are unspecified on
+ * return.  traj != NULL: one step per launch, U is only read, and the state
+ * after step k (k = 1..nsteps) is written to traj + (k-1) * info->total.
+ * Allen-Cahn and the Cahn-Hilliard c plane (mu is not produced).  Asynchronous. */
+int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps, void* U,
+                             void* ws, void* traj, void* stream);
+
+/* Adjoint of nsteps batched Allen-Cahn explicit steps (Supp. Note 2 applied
+ * step by step).  states + k * info->total holds the input of step k+1
+ * (k = 0..nsteps-1).  On entry lam holds dO/dU of the final state; on return
+ * dO/dU of the first input.  theta_bar (device, count x 3 doubles: mobility,
+ * kappa, W per sample) is accumulated, FP64, fixed reduction order.
+ * ws: pf_batch_workspace_size(PF_OP_VJP).  Asynchronous. */
+int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
+                            const void* states, void* lam, double* theta_bar, void* ws,
+                            void* stream);
+
+/* Launch-shape autotuner: times the batched explicit kernel for every
+ * (ks, ty, depth) candidate with HIP events on U_scratch (overwritten) and ws,
+ * keeps the fastest per step, records it for later pf_batch_plan calls with
+ * zero shape arguments, and leaves its plan in plan_dev / *best.
+ * plan_bytes should be pf_batch_plan_size(..., 3, 16, ...).  Host-synchronous. */
+int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+                      void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
+                      pf_batch_info* best, double* best_us_per_step, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,7 +108,7 @@ def lib():
             fn = getattr(_lib, name)
             fn.restype = res
             fn.argtypes = args
-        if hasattr(_lib, "orc_conv3x3_fwd"):
+        if hasattr(_lib, "orc_nn"):
             _bind_conv(_lib)
     return _lib
 
@@ -225,5 +225,51 @@ def newton_adjoint(p: Problem, dt: float, U, gU, solver=0):
     return tb, ub
 
 
-def _bind_conv(L):  # filled in by the conv oracle section
-    pass
+def _bind_conv(L):
+    D = ct.POINTER(ct.c_double)
+    L.orc_bf16.restype = ct.c_double
+    L.orc_bf16.argtypes = [ct.c_double]
+    L.orc_nn_nparams.restype = ct.c_int64
+    L.orc_nn_nparams.argtypes = []
+    L.orc_nn.restype = ct.c_double
+    L.orc_nn.argtypes = [ct.c_int, ct.c_int, ct.c_int, D, D, D, D, D, ct.c_int, D, D]
+    L.orc_adam.restype = None
+    L.orc_adam.argtypes = [ct.c_int64, D, D, D, D, ct.c_double, ct.c_double, ct.c_double,
+                           ct.c_double, ct.c_int]
+
+
+def bf16(x: float) -> float:
+    """Round to the nearest bfloat16, ties to even."""
+    return lib().orc_bf16(float(x))
+
+
+def nn_nparams() -> int:
+    return int(lib().orc_nn_nparams())
+
+
+NN_LAYOUT = [("W1", (3, 3, 3, 32)), ("b1", (32,)), ("W2", (3, 3, 32, 32)), ("b2", (32,)),
+             ("W3", (3, 3, 32, 32)), ("b3", (32,)), ("W4", (3, 3, 32, 1)), ("b4", (1,))]
+
+
+def nn(c, M, kappa, params, target=None, round_bf16=True, grad=False):
+    """Surrogate forward (and parameter gradient of the loss). Arrays [B, H, W].
+    Returns (c_hat, loss, grad or None)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    B, H, W = c.shape
+    M = np.ascontiguousarray(np.broadcast_to(M, c.shape), dtype=np.float64)
+    kap = np.ascontiguousarray(np.broadcast_to(kappa, c.shape), dtype=np.float64)
+    p = _arr(params, nn_nparams())
+    chat = np.zeros_like(c)
+    t = None if target is None else np.ascontiguousarray(target, dtype=np.float64)
+    g = np.zeros(nn_nparams()) if grad else None
+    loss = lib().orc_nn(B, H, W, _d(c), _d(M), _d(kap), _d(t) if t is not None else None, _d(p),
+                        int(round_bf16), _d(chat), _d(g) if g is not None else None)
+    return chat, loss, g
+
+
+def adam(p, m, v, g, lr, b1, b2, eps, t):
+    """One bias-corrected Adam step in place on FP64 arrays p, m, v."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _arr(g, p.size)
+    lib().orc_adam(p.size, _d(p), _d(m), _d(v), _d(g), lr, b1, b2, eps, int(t))

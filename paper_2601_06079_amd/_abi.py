@@ -45,6 +45,19 @@ class pf_newton_report(ct.Structure):
                 ("res_norm", ct.c_double * 33)]
 
 
+class pf_batch_sample(ct.Structure):
+    _fields_ = [("offset", ct.c_int64), ("n", ct.c_int64 * 3), ("h", ct.c_double),
+                ("W", ct.c_double), ("kappa", ct.c_double), ("mobility", ct.c_double)]
+
+
+class pf_batch_info(ct.Structure):
+    _fields_ = [("count", ct.c_int32), ("n_items", ct.c_int32), ("n_vblocks", ct.c_int32),
+                ("ks", ct.c_int32), ("ty", ct.c_int32), ("depth", ct.c_int32),
+                ("model", ct.c_int32), ("dtype", ct.c_int32), ("total", ct.c_int64),
+                ("plan_bytes", ct.c_int64), ("dt", ct.c_double), ("off_samples", ct.c_int64),
+                ("off_items", ct.c_int64), ("off_vmap", ct.c_int64)]
+
+
 class PFError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"pf status {status}: {msg}")

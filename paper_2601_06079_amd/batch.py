@@ -1,0 +1,216 @@
+"""Ragged batches of 2-D problems (one launch for all samples) and the
+checkpointed adjoint of a batched explicit trajectory.
+
+Marshalling and bookkeeping only: every step and every adjoint step runs in
+the HIP kernels behind pf_step_explicit_batched / pf_vjp_explicit_batched.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _bind():
+    L = A.lib()
+    P = ct.POINTER(A.pf_problem)
+    S = ct.POINTER(A.pf_batch_sample)
+    I = ct.POINTER(A.pf_batch_info)
+    vp, i32, i64, f64 = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_double
+    sig = {
+        "pf_batch_plan_size": (i32, [P, S, i32, i32, i32, ct.POINTER(ct.c_size_t)]),
+        "pf_batch_plan": (i32, [P, S, i32, f64, i32, i32, i32, vp, ct.c_size_t, I, vp]),
+        "pf_batch_workspace_size": (i32, [I, i32, ct.POINTER(ct.c_size_t)]),
+        "pf_step_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp]),
+        "pf_vjp_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp, vp]),
+        "pf_batch_autotune": (i32, [P, S, i32, f64, vp, vp, vp, ct.c_size_t, I,
+                                    ct.POINTER(ct.c_double), vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Batch:
+    """A packed batch of square-or-rectangular periodic 2-D problems.
+
+    sizes: list of (nx, ny); theta: (count, 3) array of (mobility, kappa, W).
+    Sample fields are packed back to back, each starting on a 64-element
+    boundary.
+    """
+
+    def __init__(self, sizes, theta, dt, model=A.ALLEN_CAHN, fe=A.F_SYM, dtype=torch.float32,
+                 h=1.0, ks=0, ty=0, depth=0, device="cuda"):
+        self.L = _bind()
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.count = len(self.sizes)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.dt = float(dt)
+        self.base = A.pf_problem(2, A.PERIODIC, model, fe, A.F64 if dtype == torch.float64 else A.F32,
+                                 0, (ct.c_int64 * 3)(2, 2, 1), h, 1.0, 1.0, 1.0)
+        self.offsets = []
+        off = 0
+        for nx, ny in self.sizes:
+            self.offsets.append(off)
+            off += (nx * ny + 63) // 64 * 64
+        self.total_alloc = off
+        self.h = float(h)
+        self.set_theta(theta, ks=ks, ty=ty, depth=depth)
+
+    def _samples(self, theta):
+        th = np.asarray(theta, dtype=np.float64).reshape(self.count, 3)
+        arr = (A.pf_batch_sample * self.count)()
+        for i, ((nx, ny), o) in enumerate(zip(self.sizes, self.offsets)):
+            arr[i] = A.pf_batch_sample(o, (ct.c_int64 * 3)(nx, ny, 1), self.h, th[i, 2], th[i, 1],
+                                       th[i, 0])
+        return arr
+
+    def set_theta(self, theta, ks=0, ty=0, depth=0):
+        """(Re)build the device plan for parameters theta (count x 3: mobility, kappa, W)."""
+        self.theta = np.asarray(theta, dtype=np.float64).reshape(self.count, 3).copy()
+        self.samples = self._samples(self.theta)
+        nb = ct.c_size_t(0)
+        A.check(self.L.pf_batch_plan_size(ct.byref(self.base), self.samples, self.count, 4, 8,
+                                          ct.byref(nb)))
+        self.plan = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.info = A.pf_batch_info()
+        A.check(self.L.pf_batch_plan(ct.byref(self.base), self.samples, self.count, self.dt, ks, ty,
+                                     depth, ct.c_void_p(self.plan.data_ptr()), self.plan.numel(),
+                                     ct.byref(self.info), _stream()))
+        # a single-step plan for trajectory mode and step counts that are not a multiple of ks
+        self.info1 = A.pf_batch_info()
+        self.plan1 = torch.empty_like(self.plan)
+        A.check(self.L.pf_batch_plan(ct.byref(self.base), self.samples, self.count, self.dt, 1,
+                                     self.info.ty, self.info.depth,
+                                     ct.c_void_p(self.plan1.data_ptr()), self.plan1.numel(),
+                                     ct.byref(self.info1), _stream()))
+
+    @property
+    def total(self):
+        return int(self.info.total)
+
+    def empty(self):
+        return torch.zeros(self.total, dtype=self.dtype, device=self.device)
+
+    def pack(self, fields):
+        U = self.empty()
+        for (nx, ny), o, f in zip(self.sizes, self.offsets, fields):
+            U[o:o + nx * ny] = torch.as_tensor(np.asarray(f).ravel(), dtype=self.dtype)
+        return U
+
+    def views(self, U):
+        return [U[o:o + nx * ny] for (nx, ny), o in zip(self.sizes, self.offsets)]
+
+    def workspace(self, op):
+        nb = ct.c_size_t(0)
+        A.check(self.L.pf_batch_workspace_size(ct.byref(self.info), op, ct.byref(nb)))
+        return torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+
+    def step(self, U, nsteps, ws=None, traj=None):
+        """nsteps explicit steps of every sample in place on U (or into traj)."""
+        if ws is None:
+            ws = self.workspace(A.OP_STEP_EXPLICIT)
+        if traj is not None:
+            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info1),
+                                                    ct.c_void_p(self.plan1.data_ptr()), int(nsteps),
+                                                    ct.c_void_p(U.data_ptr()), None,
+                                                    ct.c_void_p(traj.data_ptr()), _stream()))
+            return traj
+        ks = int(self.info.ks)
+        main = (int(nsteps) // ks) * ks
+        if main:
+            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
+                                                    main, ct.c_void_p(U.data_ptr()),
+                                                    ct.c_void_p(ws.data_ptr()), None, _stream()))
+        if nsteps - main:
+            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info1),
+                                                    ct.c_void_p(self.plan1.data_ptr()), int(nsteps - main),
+                                                    ct.c_void_p(U.data_ptr()), ct.c_void_p(ws.data_ptr()),
+                                                    None, _stream()))
+        return U
+
+    def vjp(self, states, lam, theta_bar, nsteps, ws=None):
+        """Adjoint of nsteps steps whose inputs are states[k]; lam in/out, theta_bar += ."""
+        if ws is None:
+            ws = self.workspace(A.OP_VJP)
+        A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info1), ct.c_void_p(self.plan1.data_ptr()),
+                                               int(nsteps), ct.c_void_p(states.data_ptr()),
+                                               ct.c_void_p(lam.data_ptr()),
+                                               ct.c_void_p(theta_bar.data_ptr()),
+                                               ct.c_void_p(ws.data_ptr()), _stream()))
+
+    def autotune(self, U_scratch):
+        """Time every launch shape on U_scratch (overwritten); keep the fastest."""
+        ws = self.workspace(A.OP_STEP_EXPLICIT)
+        us = ct.c_double(0.0)
+        info = A.pf_batch_info()
+        A.check(self.L.pf_batch_autotune(ct.byref(self.base), self.samples, self.count, self.dt,
+                                         ct.c_void_p(U_scratch.data_ptr()), ct.c_void_p(ws.data_ptr()),
+                                         ct.c_void_p(self.plan.data_ptr()), self.plan.numel(),
+                                         ct.byref(info), ct.byref(us), _stream()))
+        self.info = info
+        self.set_theta(self.theta, ks=info.ks, ty=info.ty, depth=info.depth)
+        return dict(ks=info.ks, ty=info.ty, depth=info.depth, us_per_step=us.value)
+
+
+class BatchedExplicitRun(torch.autograd.Function):
+    """U_N = S^N(U_0; theta) for a batch, with a hand-written adjoint.
+
+    Forward keeps a snapshot every `every` steps; backward walks the segments in
+    reverse, recomputes each segment's states from its snapshot (trajectory
+    mode) and applies the batched step adjoint to them, accumulating the
+    per-sample gradient of theta = (mobility, kappa, W) in FP64 (Supp. Note 2,
+    Eqs. II.5-II.6, one constraint per step).
+    """
+
+    @staticmethod
+    def forward(ctx, theta, U0, batch, nsteps, every):
+        if nsteps % every:
+            raise ValueError("nsteps must be a multiple of the checkpoint interval")
+        batch.set_theta(theta.detach().cpu().numpy(), ks=batch.info.ks, ty=batch.info.ty,
+                        depth=batch.info.depth)
+        ws = batch.workspace(A.OP_STEP_EXPLICIT)
+        U = U0.detach().clone()
+        snaps = []
+        for _ in range(nsteps // every):
+            snaps.append(U.clone())
+            batch.step(U, every, ws)
+        ctx.batch, ctx.snaps, ctx.every = batch, snaps, every
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        b, every = ctx.batch, ctx.every
+        lam = gU.detach().to(b.dtype).contiguous().clone()
+        tb = torch.zeros(b.count * 3, dtype=torch.float64, device=b.device)
+        seg = torch.empty((every, b.total), dtype=b.dtype, device=b.device)
+        ws = b.workspace(A.OP_VJP)
+        for snap in reversed(ctx.snaps):
+            seg[0].copy_(snap)
+            if every > 1:
+                b.step(seg[0], every - 1, traj=seg[1])
+            b.vjp(seg, lam, tb, every, ws)
+        return tb.view(b.count, 3), lam, None, None, None
+
+
+def explicit_run(theta, U0, batch, nsteps, every=100):
+    """Differentiable batched explicit trajectory (see BatchedExplicitRun)."""
+    return BatchedExplicitRun.apply(theta, U0, batch, nsteps, every)
+
+
+def per_sample_mse(batch, U, targets):
+    """sum over samples of mean over nodes (U_s - target_s)^2 (FP64 accumulation)."""
+    tot = 0.0
+    for u, t in zip(batch.views(U), batch.views(targets)):
+        tot = tot + ((u.double() - t.double()) ** 2).mean()
+    return tot

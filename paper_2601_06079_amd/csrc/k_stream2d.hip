@@ -129,26 +129,21 @@ struct Stage {
     }
 };
 
-// KS explicit steps in one pass (temporal blocking): stage s consumes the rows
-// stage s-1 produces, so a row is read from memory once and written once per
-// KS steps.  Each stage performs exactly the arithmetic of a single-step
-// launch, so the result is bitwise that of KS single steps.
-// PF: rows in flight per wave (register prefetch ring depth).
+// KS explicit steps of one (strip, chunk) work item (temporal blocking):
+// stage s consumes the rows stage s-1 produces, so a row is read from memory
+// once and written once per KS steps.  Each stage performs exactly the
+// arithmetic of a single-step launch, so the result is bitwise that of KS
+// single steps.  PF: rows in flight per wave (register prefetch ring depth).
+// Must be called by a whole wave with wave-uniform arguments.
 template <typename T, int MODEL, int PF, int KS>
-__global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
-                                                    int nx, int ny, int nstrips, int nwaves, int ty,
-                                                    unsigned bytes, Coef<T> k)
+__device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                            int ny, int strip, int chunk, int ty, unsigned bytes,
+                                            const Coef<T>& k)
 {
     constexpr int H = MODEL == 0 ? 1 : 2;
     constexpr int HK = H * KS;            // halo of the whole pass
     constexpr int OUTW = WAVE - 2 * HK;   // output columns per strip
     const int lane = threadIdx.x & (WAVE - 1);
-    // wave index made provably uniform so that all row bookkeeping stays scalar
-    const int wave = (int)(blockIdx.x * (blockDim.x / WAVE)) +
-                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (wave >= nwaves) return;  // uniform per wave
-    const int strip = wave % nstrips;
-    const int chunk = wave / nstrips;
     const int x0 = strip * OUTW;
     const int xl = x0 - HK + lane;
     int x = xl % nx;
@@ -201,6 +196,42 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     }
 }
 
+// wave index made provably uniform so that all row bookkeeping stays scalar
+__device__ __forceinline__ int uniform_wave()
+{
+    return (int)(blockIdx.x * (blockDim.x / WAVE)) +
+           __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+}
+
+template <typename T, int MODEL, int PF, int KS>
+__global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
+                                                    int nx, int ny, int nstrips, int nwaves, int ty,
+                                                    unsigned bytes, Coef<T> k)
+{
+    const int wave = uniform_wave();
+    if (wave >= nwaves) return;  // uniform per wave
+    stream_item<T, MODEL, PF, KS>(in, out, nx, ny, wave % nstrips, wave / nstrips, ty, bytes, k);
+}
+
+// Ragged batch: wave w processes work item items[w] = (sample, strip, chunk)
+// of a batch of independent problems packed in one array (see BatchSample).
+template <typename T, int MODEL, int PF, int KS>
+__global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict__ in,
+                                                            T* __restrict__ out,
+                                                            const BatchSample* __restrict__ smp,
+                                                            const BatchItem* __restrict__ items,
+                                                            int n_items, int ty)
+{
+    const int wave = uniform_wave();
+    if (wave >= n_items) return;
+    const BatchItem it = items[wave];
+    const BatchSample& sm = smp[it.sample];
+    const Coef<T> k{(T)sm.a1, (T)sm.a2, (T)sm.a3, (T)sm.beta, (T)sm.gamma};
+    const unsigned bytes = (unsigned)((long long)sm.nx * sm.ny * (long long)sizeof(T));
+    stream_item<T, MODEL, PF, KS>(in + sm.offset, out + sm.offset, sm.nx, sm.ny, it.strip, it.chunk,
+                                  ty, bytes, k);
+}
+
 template <typename T, int MODEL, int KS>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
                   int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
@@ -226,6 +257,46 @@ void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out
 }
 
 }  // namespace
+
+template <typename T, int MODEL, int KS>
+void launch_batched_depth(int depth, int blocks, hipStream_t s, const T* in, T* out,
+                          const BatchSample* smp, const BatchItem* items, int n_items, int ty)
+{
+    if (depth <= 4)
+        k_explicit2d_batched<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+    else if (depth <= 8)
+        k_explicit2d_batched<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+    else
+        k_explicit2d_batched<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+}
+
+template <typename T>
+void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample* smp,
+                               const BatchItem* items, int n_items, const Stream2DConfig& cfg,
+                               hipStream_t s)
+{
+    const int blocks = (n_items + 3) / 4;
+#define BATCHED_KS(MODEL)                                                                          \
+    switch (cfg.ks) {                                                                              \
+        case 1: launch_batched_depth<T, MODEL, 1>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
+        case 2: launch_batched_depth<T, MODEL, 2>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
+        case 3: launch_batched_depth<T, MODEL, 3>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
+        default: launch_batched_depth<T, MODEL, 4>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
+    }
+    if (model == 0) {
+        BATCHED_KS(0)
+    } else {
+        BATCHED_KS(1)
+    }
+#undef BATCHED_KS
+}
+
+template void launch_explicit2d_batched<float>(int, const float*, float*, const BatchSample*,
+                                               const BatchItem*, int, const Stream2DConfig&,
+                                               hipStream_t);
+template void launch_explicit2d_batched<double>(int, const double*, double*, const BatchSample*,
+                                                const BatchItem*, int, const Stream2DConfig&,
+                                                hipStream_t);
 
 template <typename T>
 void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,

@@ -26,6 +26,20 @@ struct FreeEnergy {
 
 FreeEnergy make_free_energy(int fe, double W);
 
+// ---- ragged batches: device plan entries (written by the host, batch.cpp) -----
+struct BatchSample {
+    long long offset;          // element offset of the sample in the packed arrays
+    int nx, ny;                // nodes per axis
+    int nstrips, first_item;   // explicit-kernel work items of this sample
+    int first_vblock, nvblock; // node-kernel blocks of this sample (256 nodes each)
+    int fe, reserved;          // free energy (0: W (c^2-1)^2/4, 1: W c^2 (1-c)^2)
+    double a1, a2, a3, beta, gamma;  // fused-kernel coefficients (dt folded in)
+    double W, kappa, mob, h, dt;     // raw parameters (sensitivities)
+};
+struct BatchItem {
+    int sample, strip, chunk, pad;
+};
+
 // ---- per-node kernels (k_node.hip); T = float or double ---------------------
 // r(U) of Eq. 11; with Uold != nullptr the backward-Euler residual of Eq. 14
 template <typename T>
@@ -84,5 +98,21 @@ struct Stream2DConfig {
 template <typename T>
 void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                        double dt, const T* in, T* out, const Stream2DConfig& cfg, hipStream_t s);
+
+// ---- ragged batch kernels ------------------------------------------------------
+// cfg.ks explicit steps of every sample: one launch for the whole batch
+template <typename T>
+void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample* smp,
+                               const BatchItem* items, int n_items, const Stream2DConfig& cfg,
+                               hipStream_t s);
+// Allen-Cahn explicit-step adjoint for every sample (k_adjoint.hip):
+//   lam_out = lam_in - (dt/m) J_r(eta)^T lam_in ;
+//   part[b][0..3) += -(dt/m) lam_in^T dr/dtheta over block b's nodes
+template <typename T>
+void launch_vjp_ac_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
+                           const int* vmap, int nvblocks, double* part, hipStream_t s);
+// theta_bar[s][0..3) += sum of part over sample s's blocks (fixed order)
+void launch_batch_reduce(const double* part, const BatchSample* smp, int count, double* theta_bar,
+                         hipStream_t s);
 
 }  // namespace pfk

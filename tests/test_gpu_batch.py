@@ -1,0 +1,166 @@
+"""Ragged batches and the checkpointed batched adjoint: HIP vs single-problem
+launches, the FP64 oracle, and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2601_06079_amd import _abi as A
+from paper_2601_06079_amd import batch as B
+from paper_2601_06079_amd import inputs as I
+from paper_2601_06079_amd import solver as S
+from tests.gpu_util import announce, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+F32, F64 = torch.float32, torch.float64
+
+
+def _batch(sizes, theta, dtype, model=A.ALLEN_CAHN, fe=A.F_SYM, dt=0.05, **kw):
+    return B.Batch(sizes, theta, dt, model=model, fe=fe, dtype=dtype, **kw)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model", [A.ALLEN_CAHN, A.CAHN_HILLIARD])
+def test_batched_equals_single_problems(dtype, model):
+    announce("batched vs single", dtype, model)
+    sizes = [(128, 128), (200, 133), (37, 301), (64, 8), (511, 257)]
+    rng = np.random.default_rng(3)
+    theta = np.exp(rng.uniform(np.log(0.5), np.log(2.0), (len(sizes), 3)))
+    fe = A.F_01 if model == A.CAHN_HILLIARD else A.F_SYM
+    dt = 0.01 if model == A.CAHN_HILLIARD else 0.05
+    b = _batch(sizes, theta, dtype, model=model, fe=fe, dt=dt)
+    base = 0.5 if model == A.CAHN_HILLIARD else 0.0
+    fields = [I.uniform_field(s, -0.05, 0.05, seed=i, base=base) for i, s in enumerate(sizes)]
+    U = b.pack(fields)
+    b.step(U, 7)
+    for (nx, ny), th, f, got in zip(sizes, theta, fields, b.views(U)):
+        p = S.Problem(n=(nx, ny), model=model, fe=fe, dtype=dtype, W=th[2], kappa=th[1],
+                      mobility=th[0])
+        u = torch.as_tensor(f, dtype=dtype, device="cuda")
+        if model == A.CAHN_HILLIARD:
+            u = torch.cat([u, torch.zeros_like(u)])
+        S.step_explicit(p, u, dt, 7)
+        assert torch.equal(got, u[: nx * ny])
+
+
+def test_batched_trajectory_mode():
+    sizes = [(96, 80), (130, 64)]
+    b = _batch(sizes, [[1.0, 1.2, 0.8], [0.7, 1.5, 1.1]], F32)
+    U0 = b.pack([I.uniform_field(s, -0.05, 0.05, seed=i) for i, s in enumerate(sizes)])
+    traj = torch.empty((5, b.total), dtype=F32, device="cuda")
+    b.step(U0, 5, traj=traj[0])
+    U = U0.clone()
+    for k in range(5):
+        b.step(U, 1)
+        for a, c in zip(b.views(U), b.views(traj[k])):
+            assert torch.equal(a, c)
+
+
+def test_batched_vjp_matches_oracle_adjoint():
+    announce("batched vjp vs oracle")
+    sizes = [(12, 10), (9, 14), (16, 16)]
+    theta = np.array([[1.2, 0.8, 1.3], [0.6, 1.7, 0.9], [1.9, 0.5, 1.6]])
+    dt, N = 0.05, 30
+    b = _batch(sizes, theta, F64, dt=dt)
+    fields = [I.uniform_field(s, -0.5, 0.5, seed=10 + i) for i, s in enumerate(sizes)]
+    targets = [I.uniform_field(s, -0.5, 0.5, seed=20 + i) for i, s in enumerate(sizes)]
+    U0 = b.pack(fields)
+    th = torch.tensor(theta, dtype=F64, device="cuda", requires_grad=True)
+    U0.requires_grad_(True)
+    UN = B.explicit_run(th, U0, b, N, every=10)
+    loss = B.per_sample_mse(b, UN, b.pack(targets))
+    loss.backward()
+    for i, (s, f, t) in enumerate(zip(sizes, fields, targets)):
+        o = O.Problem(n=s, model=O.AC, fe=O.F_SYM, W=theta[i, 2], kappa=theta[i, 1], mob=theta[i, 0])
+        uN = O.explicit(o, f, dt, N)
+        tb, ub = O.explicit_adjoint(o, dt, N, f, 2 * (uN - t) / uN.size)
+        np.testing.assert_allclose(host(th.grad[i]), tb, rtol=1e-10, atol=1e-14)
+        assert rel_l2(host(b.views(U0.grad)[i]), ub) < 1e-10
+
+
+def test_checkpointed_adjoint_bitwise_equals_stored_trajectory():
+    sizes = [(64, 48), (33, 70)]
+    theta = np.array([[1.0, 1.1, 0.9], [1.3, 0.7, 1.2]])
+    b = _batch(sizes, theta, F32)
+    U0 = b.pack([I.uniform_field(s, -0.05, 0.05, seed=i) for i, s in enumerate(sizes)])
+    tgt = b.pack([I.uniform_field(s, -0.5, 0.5, seed=5 + i) for i, s in enumerate(sizes)])
+    grads = []
+    for every in (10, 40):
+        th = torch.tensor(theta, dtype=F64, device="cuda", requires_grad=True)
+        UN = B.explicit_run(th, U0, b, 40, every=every)
+        B.per_sample_mse(b, UN, tgt).backward()
+        grads.append(th.grad.clone())
+    assert torch.equal(grads[0], grads[1])
+
+
+def _c4_batch(dtype, count=64, nsteps=2000):
+    sizes, theta, hidden, fields = I.batch_samples(count=count, seed=0)
+    sizes = [(int(n), int(n)) for n in sizes]
+    b = _batch(sizes, theta, dtype, dt=0.05)
+    return b, sizes, theta, hidden, fields
+
+
+def test_calibration_workload_adjoint_vs_central_fd_fp64():
+    """64 ragged Allen-Cahn samples 128^2..512^2, 2000 steps, checkpoint every 100:
+    FP64 adjoint gradient vs central differences (eps = 1e-6 theta), all samples
+    perturbed together (they are independent)."""
+    announce("C4 adjoint vs FD fp64")
+    b, sizes, theta, hidden, fields = _c4_batch(F64)
+    nsteps, every = 2000, 100
+    U0 = b.pack(fields)
+    bt = _batch(sizes, hidden, F64, dt=0.05)
+    tgt = U0.clone()
+    bt.step(tgt, nsteps)
+    th = torch.tensor(theta, dtype=F64, device="cuda", requires_grad=True)
+    UN = B.explicit_run(th, U0, b, nsteps, every=every)
+    loss = B.per_sample_mse(b, UN, tgt)
+    loss.backward()
+    g = host(th.grad)
+
+    def per_sample_losses(th_np):
+        bb = _batch(sizes, th_np, F64, dt=0.05)
+        U = U0.clone()
+        bb.step(U, nsteps)
+        return np.array([float(((u - t) ** 2).mean()) for u, t in zip(bb.views(U), bb.views(tgt))])
+
+    for k in range(3):
+        eps = 1e-6 * theta[:, k]
+        tp, tm = theta.copy(), theta.copy()
+        tp[:, k] += eps
+        tm[:, k] -= eps
+        fd = (per_sample_losses(tp) - per_sample_losses(tm)) / (2 * eps)
+        rel = np.abs(g[:, k] - fd) / np.maximum(np.abs(fd), 1e-300)
+        assert np.max(rel) < 1e-4, (k, np.max(rel))
+
+
+def test_calibration_workload_fp32_gradient_reported():
+    """The FP32 run of the same workload: its gradient is reported against the FP64 one
+    (not gated at 1e-4: FP32 rounding over 2000 steps)."""
+    b64, sizes, theta, hidden, fields = _c4_batch(F64, count=8)
+    b32 = _batch(sizes, theta, F32, dt=0.05)
+    out = []
+    for b in (b64, b32):
+        U0 = b.pack(fields)
+        tgt = U0.clone()
+        _batch(sizes, hidden, b.dtype, dt=0.05).step(tgt, 2000)
+        th = torch.tensor(theta, dtype=F64, device="cuda", requires_grad=True)
+        B.per_sample_mse(b, B.explicit_run(th, U0, b, 2000, every=100), tgt).backward()
+        out.append(host(th.grad))
+    rel = np.abs(out[1] - out[0]) / np.abs(out[0])
+    print("fp32 vs fp64 gradient relative error: max", rel.max(), "median", np.median(rel))
+    assert np.median(rel) < 1e-1
+
+
+def test_autotune_picks_a_valid_shape_with_identical_results():
+    sizes = [(int(n), int(n)) for n in (128, 300, 512, 200)]
+    theta = np.ones((4, 3))
+    b = _batch(sizes, theta, F32)
+    U0 = b.pack([I.uniform_field(s, -0.05, 0.05, seed=i) for i, s in enumerate(sizes)])
+    ref = U0.clone()
+    b.step(ref, 12)
+    res = b.autotune(U0.clone())
+    assert res["ks"] in (1, 2, 3) and res["us_per_step"] > 0
+    U = U0.clone()
+    b.step(U, 12)
+    for a, c in zip(b.views(U), b.views(ref)):
+        assert torch.equal(a, c)
