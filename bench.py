@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE_STEP = 8  # read c, write c (FP32); mu never leaves the chip
+BYTES_PER_NODE_STEP = 8  # read c, write c (FP32) per launch; mu never leaves the chip
 
 
 def parse():
@@ -134,6 +134,8 @@ def main():
         sys.exit(2)
     import torch
 
+    import ctypes as ct
+
     from paper_2601_06079_amd import _abi as A
     from paper_2601_06079_amd import inputs as I
     from paper_2601_06079_amd import solver as S
@@ -163,26 +165,26 @@ def main():
     ms_per_step = ms_total / args.steps
     value = N * args.steps / (ms_total * 1e-3)
 
-    # per-launch duration of the step kernel: events bracket single-step calls
-    # on the same stream (one fused launch each, plus the mu epilogue kernel
-    # that a single-step call adds; that one is measured and subtracted)
-    reps = 50
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
+    # Average duration of one launch of the dominant kernel over the timed region:
+    # the K steps ran as back-to-back launches of the fused kernel (ks steps each)
+    # plus one chemical-potential epilogue, measured separately and subtracted.
+    ks_, ty_, dp_ = ct.c_int(0), ct.c_int(0), ct.c_int(0)
+    A.check(A.lib().pf_launch_shape(ct.byref(p.c()), ct.byref(ks_), ct.byref(ty_), ct.byref(dp_)))
+    ks = ks_.value
+    reps = 20
     evm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(reps)]
     for i in range(reps):
-        ev[i][0].record(stream)
-        S.step_explicit(p, U, dt, 2, ws)  # two fused launches + one mu epilogue
-        ev[i][1].record(stream)
         evm[i][0].record(stream)
         S.step_explicit(p, U, dt, 0, ws)  # the mu epilogue alone
         evm[i][1].record(stream)
     torch.cuda.synchronize()
-    two = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
-    epi = sorted(a.elapsed_time(b) for a, b in evm)[reps // 2]
-    kern_ms = max(two - epi, 1e-6) / 2.0
+    epi = sorted(a_.elapsed_time(b_) for a_, b_ in evm)[reps // 2]
+    launches = args.steps // ks + args.steps % ks
+    kern_ms = max(ms_total - epi, 1e-6) / launches
+    # one fused launch reads c once and writes c once: 8 B per node per launch
     achieved = BYTES_PER_NODE_STEP * N / (kern_ms * 1e-3) / 1e9
+    effective = BYTES_PER_NODE_STEP * N * args.steps / (ms_total * 1e-3) / 1e9
 
     # measured HBM bytes per launch, only if taken on this exact kernel source
     traffic = None
@@ -211,7 +213,8 @@ def main():
                                "dt=0.01, W=1, kappa=2, M=1", "dof": N, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_explicit2d<float, CH>", "kernel_ms": kern_ms},
+                     "kernel": f"k_explicit2d<float, CH, 4, {ks}> ({ks} fused steps per launch)",
+                     "kernel_ms": kern_ms, "effective_gbs_per_step": effective},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)

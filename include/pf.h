@@ -92,6 +92,9 @@ int pf_version(void);
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
+/* The launch shape pf_step_explicit uses for p (2-D): steps fused per launch,
+ * rows per wavefront, prefetch depth.  Host-only. */
+int pf_launch_shape(const pf_problem* p, int* ks, int* ty, int* depth);
 
 /* Bytes of device scratch `ws` that operation `op` needs for problem p
  * (0 when none).  Host-only; enqueues nothing. */
@@ -251,11 +254,17 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
 /* Adjoint of nsteps batched Allen-Cahn explicit steps (Supp. Note 2 applied
  * step by step).  states + k * info->total holds the input of step k+1
  * (k = 0..nsteps-1).  On entry lam holds dO/dU of the final state; on return
- * dO/dU of the first input.  theta_bar (device, count x 3 doubles: mobility,
- * kappa, W per sample) is accumulated, FP64, fixed reduction order.
- * ws: pf_batch_workspace_size(PF_OP_VJP).  Asynchronous. */
+ * dO/dU of the first input.  Sensitivities of theta = (mobility, kappa, W)
+ * accumulate per 256-node block in FP64 partials kept in ws; with
+ * PF_VJP_BEGIN the partials are zeroed first, with PF_VJP_END they are summed
+ * (fixed order) into theta_bar (device, count x 3 doubles).  A trajectory
+ * processed in segments (checkpointing) with BEGIN on the first call and END
+ * on the last gives bitwise the gradient of one call over all steps.
+ * ws: pf_batch_workspace_size(PF_OP_VJP), kept between the calls of one
+ * trajectory.  Asynchronous. */
+enum { PF_VJP_BEGIN = 1, PF_VJP_END = 2 };
 int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
-                            const void* states, void* lam, double* theta_bar, void* ws,
+                            const void* states, void* lam, double* theta_bar, void* ws, int flags,
                             void* stream);
 
 /* Launch-shape autotuner: times the batched explicit kernel for every
@@ -266,6 +275,46 @@ int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t
 int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                       void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
                       pf_batch_info* best, double* best_us_per_step, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned K-step surrogate for 2-D Cahn-Hilliard (added by this library;  */
+/* the paper has no learned component).  BF16 matrix-core kernels with     */
+/* FP32 accumulation; FP32 master parameters.                              */
+/* ---------------------------------------------------------------------- */
+/* Network: a0 = (c, M, kappa) per pixel; three 3x3 periodic convolutions of
+ * width 32 with bias and relu; a 3x3 convolution to one channel d;
+ * c_hat = c + d - mean(d) per sample (mass conserved exactly).
+ * Parameters (FP32, this order): W1 [3][3][3][32], b1 [32], W2 [3][3][32][32],
+ * b2 [32], W3 [3][3][32][32], b3 [32], W4 [3][3][32], b4 [1]; W[ky][kx][cin][cout]
+ * multiplies the input at (y + ky - 1, x + kx - 1).  Inputs, weights and hidden
+ * activations (and their gradients) are rounded to bfloat16, ties to even. */
+int pf_nn_param_count(void);
+
+/* Workspace bytes for B samples of H x W pixels (W a multiple of 32). */
+int pf_nn_workspace_size(int B, int H, int W, size_t* bytes);
+
+/* c_hat [B, H, W] from c [B, H, W], M [B], kappa [B] (all FP32 device). */
+int pf_nn_forward(const float* params, int B, int H, int W, const float* c, const float* M,
+                  const float* kappa, float* c_hat, void* ws, void* stream);
+
+/* Forward and backward: grad (FP32 device, pf_nn_param_count values) = dL/dparams of
+ * L = sum_b mean_p (c_hat - target)^2; loss (device, B doubles, may be NULL) gets
+ * each sample's mean squared error.  Asynchronous. */
+int pf_nn_backward(const float* params, int B, int H, int W, const float* c, const float* M,
+                   const float* kappa, const float* target, double* loss, float* grad, void* ws,
+                   void* stream);
+
+/* One bias-corrected Adam step (step count t >= 1) on params with moments m, v. */
+int pf_nn_adam(float* params, float* m, float* v, const float* grad, int t, double lr,
+               double beta1, double beta2, double eps, void* stream);
+
+/* Residual check of a surrogate jump c_prev -> c_hat over K steps of size dt, given
+ * c_step = one explicit step of c_hat (so (c_hat - c_step)/dt = M K mu(c_hat)/m).
+ * Per sample, out[3 b + 0] = ||R_BE|| / ||m (c_hat - c_prev)/(K dt)|| with the
+ * backward-Euler residual R_BE of Eq. 14 for the jump; out[3 b + 1] =
+ * sum (c_hat - c_prev); out[3 b + 2] = ||c_hat - c_prev|| / (K dt).  FP64 sums. */
+int pf_nn_check(int B, int H, int W, const float* c_hat, const float* c_prev, const float* c_step,
+                double K_dt, double dt, double* out, void* ws, void* stream);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ def _bind():
         "pf_batch_plan": (i32, [P, S, i32, f64, i32, i32, i32, vp, ct.c_size_t, I, vp]),
         "pf_batch_workspace_size": (i32, [I, i32, ct.POINTER(ct.c_size_t)]),
         "pf_step_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp]),
-        "pf_vjp_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp, vp]),
+        "pf_vjp_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp, i32, vp]),
         "pf_batch_autotune": (i32, [P, S, i32, f64, vp, vp, vp, ct.c_size_t, I,
                                     ct.POINTER(ct.c_double), vp]),
     }
@@ -139,15 +139,17 @@ class Batch:
                                                     None, _stream()))
         return U
 
-    def vjp(self, states, lam, theta_bar, nsteps, ws=None):
-        """Adjoint of nsteps steps whose inputs are states[k]; lam in/out, theta_bar += ."""
+    def vjp(self, states, lam, theta_bar, nsteps, ws=None, begin=True, end=True):
+        """Adjoint of nsteps steps whose inputs are states[k]; lam in/out, theta_bar +=
+        (begin: zero the FP64 partials in ws first; end: reduce them into theta_bar)."""
         if ws is None:
             ws = self.workspace(A.OP_VJP)
+        flags = (1 if begin else 0) | (2 if end else 0)
         A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info1), ct.c_void_p(self.plan1.data_ptr()),
                                                int(nsteps), ct.c_void_p(states.data_ptr()),
                                                ct.c_void_p(lam.data_ptr()),
                                                ct.c_void_p(theta_bar.data_ptr()),
-                                               ct.c_void_p(ws.data_ptr()), _stream()))
+                                               ct.c_void_p(ws.data_ptr()), flags, _stream()))
 
     def autotune(self, U_scratch):
         """Time every launch shape on U_scratch (overwritten); keep the fastest."""
@@ -195,11 +197,12 @@ class BatchedExplicitRun(torch.autograd.Function):
         tb = torch.zeros(b.count * 3, dtype=torch.float64, device=b.device)
         seg = torch.empty((every, b.total), dtype=b.dtype, device=b.device)
         ws = b.workspace(A.OP_VJP)
-        for snap in reversed(ctx.snaps):
+        nseg = len(ctx.snaps)
+        for i, snap in enumerate(reversed(ctx.snaps)):
             seg[0].copy_(snap)
             if every > 1:
                 b.step(seg[0], every - 1, traj=seg[1])
-            b.vjp(seg, lam, tb, every, ws)
+            b.vjp(seg, lam, tb, every, ws, begin=(i == 0), end=(i == nseg - 1))
         return tb.view(b.count, 3), lam, None, None, None
 
 

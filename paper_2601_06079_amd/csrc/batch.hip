@@ -304,7 +304,7 @@ int batched_steps_t(const pf_batch_info* info, const void* plan, int64_t nsteps,
 
 template <typename T>
 int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, const T* states,
-                  T* lam, double* theta_bar, void* ws, hipStream_t s)
+                  T* lam, double* theta_bar, void* ws, int flags, hipStream_t s)
 {
     const char* pb = static_cast<const char*>(plan);
     const auto* smp = reinterpret_cast<const pfk::BatchSample*>(pb + info->off_samples);
@@ -312,14 +312,15 @@ int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, c
     const long long total = info->total;
     T* other = static_cast<T*>(ws);
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + align256((size_t)total * sizeof(T)));
-    if (hipMemsetAsync(part, 0, (size_t)info->n_vblocks * 3 * sizeof(double), s) != hipSuccess)
+    if ((flags & PF_VJP_BEGIN) &&
+        hipMemsetAsync(part, 0, (size_t)info->n_vblocks * 3 * sizeof(double), s) != hipSuccess)
         return check_launch("batched vjp init");
     T* cur = lam;
     for (int64_t k = nsteps - 1; k >= 0; --k) {
         pfk::launch_vjp_ac_batched<T>(states + k * total, cur, other, smp, vmap, info->n_vblocks, part, s);
         std::swap(cur, other);
     }
-    pfk::launch_batch_reduce(part, smp, info->count, theta_bar, s);
+    if (flags & PF_VJP_END) pfk::launch_batch_reduce(part, smp, info->count, theta_bar, s);
     if (int rc = check_launch("pf_vjp_explicit_batched")) return rc;
     if (cur != lam && hipMemcpyAsync(lam, cur, (size_t)total * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return check_launch("batched vjp copy-back");
@@ -349,7 +350,8 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
 }
 
 int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
-                            const void* states, void* lam, double* theta_bar, void* ws, void* stream)
+                            const void* states, void* lam, double* theta_bar, void* ws, int flags,
+                            void* stream)
 {
     if (int rc = check_info(info, plan)) return rc;
     if (info->model != PF_ALLEN_CAHN)
@@ -357,10 +359,13 @@ int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t
     if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
     if (!states || !lam || !ws || !theta_bar) return fail(PF_EINVAL, "NULL pointer argument");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+    if (flags & ~(PF_VJP_BEGIN | PF_VJP_END)) return fail(PF_EINVAL, "unknown flags");
     hipStream_t s = (hipStream_t)stream;
     if (info->dtype == PF_F32)
-        return batched_vjp_t<float>(info, plan, nsteps, (const float*)states, (float*)lam, theta_bar, ws, s);
-    return batched_vjp_t<double>(info, plan, nsteps, (const double*)states, (double*)lam, theta_bar, ws, s);
+        return batched_vjp_t<float>(info, plan, nsteps, (const float*)states, (float*)lam, theta_bar,
+                                    ws, flags, s);
+    return batched_vjp_t<double>(info, plan, nsteps, (const double*)states, (double*)lam, theta_bar,
+                                 ws, flags, s);
 }
 
 int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,

@@ -1,0 +1,664 @@
+// k_nn.hip -- convolutional surrogate on BF16 matrix cores (a learned component
+// this library adds; the paper has none).
+//
+// Network (width 32, 3x3 periodic convolutions, NHWC activations):
+//   a0 = (c, M, kappa, 0 ... 0)                      16 channels, bf16
+//   a_l = bf16(relu(conv(a_{l-1}; W_l) + b_l)), l = 1..3   32 channels, bf16
+//   d = conv(a_3; W_4) + b_4                          1 channel, fp32
+//   c_hat = c + d - mean(d)                           per sample (exact mass)
+// Loss: sum over samples of mean_p (c_hat - target)^2.
+//
+// Hidden layers and their input-gradient (dgrad) and weight-gradient (wgrad)
+// products run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
+//   forward/dgrad: a 64-lane wave computes 32 pixels x 32 channels; its
+//     A operand (pixels x input channels of one tap) is read from an LDS tile of
+//     (4+2) rows x (32+2) pixels, its B operand (the weights of that tap) is
+//     held in registers for the whole block.  K = 9 taps x Cin.
+//   wgrad: dW[tap] (Cin x Cout) = sum over pixels of a_in(p + tap) g_out(p)^T,
+//     K = pixels; every block accumulates a fixed stride of pixel tiles in
+//     registers (split-K) and writes one FP32 partial; a second kernel sums the
+//     partials in block order (bitwise reproducible).
+// The 32 -> 1 output layer (2.9% of the flops) runs on the VALU.
+//
+// MFMA operand layout (32x32x16): lane l supplies A[l % 32][8 (l / 32) + j] and
+// B[8 (l / 32) + j][l % 32] for j = 0..7, and receives
+// C[8 (i / 4) + 4 (l / 32) + (i % 4)][l % 32] in accumulator i = 0..15.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.hpp"
+#include "nn.hpp"
+
+namespace pfk {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16;
+
+constexpr int TW = 32;        // pixels per wave row
+constexpr int TR = 4;         // rows per block (one per wave)
+constexpr int NBLK = 256;
+
+// fp32 -> bf16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ u16 bf16_bits(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(u16 b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// LDS tile: (TR + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by 8 bytes
+template <int CIN>
+struct Tile {
+    static constexpr int PSTRIDE = CIN * 2 + 8;  // bytes per pixel in LDS
+    static constexpr int BYTES = (TR + 2) * (TW + 2) * PSTRIDE;
+};
+
+// stage the halo tile of rows y0-1 .. y0+TR, pixels x0-1 .. x0+TW (periodic)
+template <int CIN>
+__device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, int H, int W, int y0,
+                                           int x0, unsigned char* lds)
+{
+    constexpr int CHUNKS = CIN * 2 / 16;  // 16-byte chunks per pixel
+    constexpr int TOTAL = (TR + 2) * (TW + 2) * CHUNKS;
+    for (int t = threadIdx.x; t < TOTAL; t += NBLK) {
+        const int ch = t % CHUNKS, pix = t / CHUNKS;
+        const int px = pix % (TW + 2), ry = pix / (TW + 2);
+        const int gy = wrapi(y0 - 1 + ry, H), gx = wrapi(x0 - 1 + px, W);
+        const uint4 v = *reinterpret_cast<const uint4*>(
+            act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
+        *reinterpret_cast<uint4*>(lds + (ry * (TW + 2) + px) * Tile<CIN>::PSTRIDE + ch * 16) = v;
+    }
+}
+
+// MODE 0: out = bf16(relu(acc + bias))          (forward, hidden layers)
+// MODE 1: out = bf16(acc * (mask[p][co] > 0))    (dgrad: relu mask of the layer input)
+// wfrag: B fragments [9][CIN/16][64 lanes][8] bf16 for this layer/use
+template <int CIN, int MODE>
+__global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
+                                                    const u16* __restrict__ wfrag,
+                                                    const float* __restrict__ bias,
+                                                    const u16* __restrict__ mask,
+                                                    u16* __restrict__ out, int B, int H, int W)
+{
+    constexpr int KS = CIN / 16;
+    __shared__ __align__(16) unsigned char lds[Tile<CIN>::BYTES];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = W / TW, tiles_y = (H + TR - 1) / TR;
+    int t = blockIdx.x;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int b = t / tiles_y;
+    const int x0 = tx * TW, y0 = ty * TR;
+    stage_tile<CIN>(in, b, H, W, y0, x0, lds);
+    // this lane's weight fragments for every (tap, k-slice)
+    bf16x8 bw[9 * KS];
+#pragma unroll
+    for (int q = 0; q < 9 * KS; ++q)
+        bw[q] = *reinterpret_cast<const bf16x8*>(wfrag + ((size_t)q * 64 + lane) * 8);
+    __syncthreads();
+    const int y = y0 + wv;
+    if (y >= H) return;
+    f32x16 acc = {};
+    const int m = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row wv + dy, pixel m + dx
+        const unsigned char* rowp = lds + ((wv + dy) * (TW + 2) + (m + dx)) * Tile<CIN>::PSTRIDE;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
+        }
+    }
+    const int co = m;
+    const float bco = MODE == 0 ? bias[co] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
+        const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
+        float v = acc[i];
+        if (MODE == 0) {
+            v = fmaxf(v + bco, 0.0f);
+        } else {
+            v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
+        }
+        out[pidx * 32 + co] = bf16_bits(v);
+    }
+}
+
+// wgrad of a hidden layer: part[block][tap][ci][co] = sum over this block's pixel
+// tiles of a_in(p + tap)[ci] g(p)[co]; partb[block][co] = sum g(p)[co].
+// CIN = 16 (first layer, channels 16..31 of the M tile are zero) or 32.
+template <int CIN>
+__global__ __launch_bounds__(NBLK) void k_wgrad_mfma(const u16* __restrict__ ain,
+                                                     const u16* __restrict__ g, float* __restrict__ part,
+                                                     float* __restrict__ partb, int B, int H, int W)
+{
+    __shared__ __align__(16) unsigned char la[Tile<CIN>::BYTES];
+    __shared__ __align__(16) u16 lg[TR * TW * 32 + 8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 31, kh = lane >> 5;
+    const int tiles_x = W / TW, tiles_y = (H + TR - 1) / TR;
+    const int ntiles = tiles_x * tiles_y * B;
+    // wave wv owns taps wv, wv + 4, wv + 8
+    f32x16 acc[3] = {{}, {}, {}};
+    float db = 0.0f;
+    for (int t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
+        int t = t0;
+        const int tx = t % tiles_x;
+        t /= tiles_x;
+        const int ty = t % tiles_y;
+        const int b = t / tiles_y;
+        const int x0 = tx * TW, y0 = ty * TR;
+        __syncthreads();
+        stage_tile<CIN>(ain, b, H, W, y0, x0, la);
+        for (int q = threadIdx.x; q < TR * TW * 4; q += NBLK) {  // 16-byte chunks of g
+            const int ch = q & 3, pix = q >> 2;
+            const int r = pix / TW, px = pix % TW;
+            uint4 v = {0, 0, 0, 0};
+            if (y0 + r < H)
+                v = *reinterpret_cast<const uint4*>(g + ((((size_t)b * H + y0 + r) * W + x0 + px) * 32 + ch * 8));
+            *reinterpret_cast<uint4*>(lg + pix * 32 + ch * 8) = v;
+        }
+        __syncthreads();
+        // K loop over the tile's 128 pixels, 16 at a time (rows past H hold g = 0)
+#pragma unroll 1
+        for (int k0 = 0; k0 < TR * TW; k0 += 16) {
+            // B operand: g[pixel k0 + 8 kh + j][co = m]
+            bf16x8 bg;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const u16 bits = lg[(k0 + 8 * kh + j) * 32 + m];
+                bg[j] = __builtin_bit_cast(__bf16, bits);
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int tap = wv + 4 * s;
+                if (tap < 9) {
+                    const int dy = tap / 3, dx = tap % 3;
+                    bf16x8 aa;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int p = k0 + 8 * kh + j;  // pixel of the tile: row p / TW, column p % TW
+                        const int r = p / TW, px = p % TW;
+                        u16 bits = 0;
+                        if (m < CIN)
+                            bits = *reinterpret_cast<const u16*>(
+                                la + ((r + dy) * (TW + 2) + px + dx) * Tile<CIN>::PSTRIDE + m * 2);
+                        aa[j] = __builtin_bit_cast(__bf16, bits);
+                    }
+                    acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bg, acc[s], 0, 0, 0);
+                }
+            }
+        }
+        if (wv == 0 && lane < 32)
+            for (int p = 0; p < TR * TW; ++p) db += bf16_val(lg[p * 32 + lane]);
+    }
+    // write this block's partial: C[ci][co] tile per tap
+    float* pb = part + (size_t)blockIdx.x * 9 * 32 * 32;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int tap = wv + 4 * s;
+        if (tap < 9)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int ci = 8 * (i >> 2) + 4 * kh + (i & 3);
+                pb[((size_t)tap * 32 + ci) * 32 + m] = acc[s][i];
+            }
+    }
+    if (wv == 0 && lane < 32) partb[(size_t)blockIdx.x * 32 + lane] = db;
+}
+
+// out[i] = sum over blocks of part[block][i]  (i < n), fixed order
+__global__ __launch_bounds__(NBLK) void k_sum_partials(const float* __restrict__ part, int nb,
+                                                       int n, float* __restrict__ out)
+{
+    const int i = blockIdx.x * NBLK + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += (double)part[(size_t)b * n + i];
+    out[i] = (float)s;
+}
+
+// a0 = bf16 (c, M, kappa, 0 x 13) per pixel
+__global__ __launch_bounds__(NBLK) void k_pack_input(const float* __restrict__ c,
+                                                     const float* __restrict__ Mv,
+                                                     const float* __restrict__ kv, u16* __restrict__ a0,
+                                                     int B, int HW)
+{
+    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
+    if (p >= (size_t)B * HW) return;
+    const int b = (int)(p / HW);
+    u16 v[16] = {};
+    v[0] = bf16_bits(c[p]);
+    v[1] = bf16_bits(Mv[b]);
+    v[2] = bf16_bits(kv[b]);
+    uint4* dst = reinterpret_cast<uint4*>(a0 + p * 16);
+    dst[0] = *reinterpret_cast<uint4*>(&v[0]);
+    dst[1] = *reinterpret_cast<uint4*>(&v[8]);
+}
+
+// FP32 master parameters -> bf16 B fragments.  Hidden layer l, use u (0 forward, 1 dgrad):
+//   forward: B[k = 16 ks + j'][n = co] = W[tap][ci = 16 ks + j'][co]
+//   dgrad:   B[k = 16 ks + j'][n = ci] = W[8 - tap][ci' = ... ] with the roles of ci, co swapped
+// frag layout [tap][ks][lane][8]: lane supplies k = 16 ks + 8 (lane / 32) + j, n = lane % 32.
+__global__ __launch_bounds__(NBLK) void k_prep_weights(const float* __restrict__ params,
+                                                       NNOffsets off, u16* __restrict__ frag,
+                                                       NNFragOffsets fo, u16* __restrict__ w4)
+{
+    const int t = blockIdx.x * NBLK + threadIdx.x;
+    // hidden layers: 3 forward fragments (cin 16/32/32) + 2 dgrad fragments (layers 2, 3)
+    const int n1 = 9 * 1 * 64 * 8, n2 = 9 * 2 * 64 * 8;
+    if (t < n1) {  // layer 1 forward, CIN padded 3 -> 16
+        const int j = t & 7, lane = (t >> 3) & 63, tap = t / (64 * 8);
+        const int k = 8 * (lane >> 5) + j, co = lane & 31;
+        const float w = k < 3 ? params[off.w1 + (tap * 3 + k) * 32 + co] : 0.0f;
+        frag[fo.f1 + t] = bf16_bits(w);
+        return;
+    }
+    int u = t - n1;
+    for (int l = 0; l < 2; ++l) {       // layers 2, 3 forward
+        if (u < n2) {
+            const int j = u & 7, lane = (u >> 3) & 63, q = u / (64 * 8);
+            const int tap = q / 2, ks = q % 2;
+            const int ci = 16 * ks + 8 * (lane >> 5) + j, co = lane & 31;
+            const size_t wo = (l == 0 ? off.w2 : off.w3) + ((size_t)tap * 32 + ci) * 32 + co;
+            frag[(l == 0 ? fo.f2 : fo.f3) + u] = bf16_bits(params[wo]);
+            return;
+        }
+        u -= n2;
+    }
+    for (int l = 0; l < 2; ++l) {       // layers 2, 3 dgrad: out channel = ci, k = co, tap flipped
+        if (u < n2) {
+            const int j = u & 7, lane = (u >> 3) & 63, q = u / (64 * 8);
+            const int tap = q / 2, ks = q % 2;
+            const int co = 16 * ks + 8 * (lane >> 5) + j, ci = lane & 31;
+            const size_t wo = (l == 0 ? off.w2 : off.w3) + ((size_t)(8 - tap) * 32 + ci) * 32 + co;
+            frag[(l == 0 ? fo.d2 : fo.d3) + u] = bf16_bits(params[wo]);
+            return;
+        }
+        u -= n2;
+    }
+    if (u < 9 * 32) w4[u] = bf16_bits(params[off.w4 + u]);
+}
+
+// output layer forward: d[p] = b4 + sum_tap sum_ci W4[tap][ci] a3[p + tap][ci]  (fp32)
+__global__ __launch_bounds__(NBLK) void k_out_fwd(const u16* __restrict__ a3, const u16* __restrict__ w4,
+                                                  const float* __restrict__ params, NNOffsets off,
+                                                  float* __restrict__ d, int B, int H, int W)
+{
+    __shared__ float sw[9 * 32];
+    for (int i = threadIdx.x; i < 9 * 32; i += NBLK) sw[i] = bf16_val(w4[i]);
+    __syncthreads();
+    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
+    const size_t HW = (size_t)H * W;
+    if (p >= (size_t)B * HW) return;
+    const int b = (int)(p / HW), r = (int)(p % HW), y = r / W, x = r % W;
+    float s = params[off.b4];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = wrapi(y + tap / 3 - 1, H), xx = wrapi(x + tap % 3 - 1, W);
+        const u16* ap = a3 + (((size_t)b * H + yy) * W + xx) * 32;
+        for (int ci = 0; ci < 32; ci += 8) {
+            const uint4 v = *reinterpret_cast<const uint4*>(ap + ci);
+            const u16* e = reinterpret_cast<const u16*>(&v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s = fmaf(sw[tap * 32 + ci + j], bf16_val(e[j]), s);
+        }
+    }
+    d[p] = s;
+}
+
+// per-sample partial sums of x over blocks of NBLK pixels: part[b * nbs + blk]
+__global__ __launch_bounds__(NBLK) void k_sample_sum(const float* __restrict__ x, int HW,
+                                                     double* __restrict__ part)
+{
+    const int nbs = (HW + NBLK - 1) / NBLK;
+    const int b = blockIdx.x / nbs, blk = blockIdx.x % nbs;
+    const int i = blk * NBLK + threadIdx.x;
+    double v = i < HW ? (double)x[(size_t)b * HW + i] : 0.0;
+    __shared__ double sh[NBLK];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = NBLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(NBLK) void k_sample_mean(const double* __restrict__ part, int nbs,
+                                                      int HW, double* __restrict__ mean)
+{
+    const int b = blockIdx.x;
+    __shared__ double sh[NBLK];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nbs; i += NBLK) a += part[(size_t)b * nbs + i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = NBLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mean[b] = sh[0] / (double)HW;
+}
+
+// c_hat = c + d - mean(d); with a target also g = 2 (c_hat - t)/HW and the squared error r2
+__global__ __launch_bounds__(NBLK) void k_project(const float* __restrict__ c, const float* __restrict__ d,
+                                                  const double* __restrict__ mean, const float* __restrict__ tgt,
+                                                  float* __restrict__ chat, float* __restrict__ g,
+                                                  float* __restrict__ r2, int B, int HW)
+{
+    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
+    if (p >= (size_t)B * HW) return;
+    const int b = (int)(p / HW);
+    const float ch = c[p] + (float)((double)d[p] - mean[b]);
+    chat[p] = ch;
+    if (tgt) {
+        const float r = ch - tgt[p];
+        g[p] = 2.0f * r / (float)HW;
+        r2[p] = r * r;
+    }
+}
+
+// g <- g - mean(g) (backward of the mass projection)
+__global__ __launch_bounds__(NBLK) void k_center(float* __restrict__ g, const double* __restrict__ mean,
+                                                 int B, int HW)
+{
+    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
+    if (p >= (size_t)B * HW) return;
+    g[p] = (float)((double)g[p] - mean[p / HW]);
+}
+
+// output layer dgrad: ga3[p][ci] = bf16( (a3[p][ci] > 0) * sum_tap W4[tap][ci] g[p - off(tap)] )
+__global__ __launch_bounds__(NBLK) void k_out_dgrad(const u16* __restrict__ a3, const u16* __restrict__ w4,
+                                                    const float* __restrict__ g, u16* __restrict__ ga3,
+                                                    int B, int H, int W)
+{
+    __shared__ float sw[9 * 32];
+    for (int i = threadIdx.x; i < 9 * 32; i += NBLK) sw[i] = bf16_val(w4[i]);
+    __syncthreads();
+    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
+    const size_t HW = (size_t)H * W;
+    if (p >= (size_t)B * HW) return;
+    const int b = (int)(p / HW), r = (int)(p % HW), y = r / W, x = r % W;
+    float gin[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = wrapi(y - (tap / 3 - 1), H), xx = wrapi(x - (tap % 3 - 1), W);
+        gin[tap] = g[((size_t)b * H + yy) * W + xx];
+    }
+    const u16* ap = a3 + p * 32;
+    u16 outv[32];
+#pragma unroll
+    for (int ci = 0; ci < 32; ++ci) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) sum = fmaf(sw[tap * 32 + ci], gin[tap], sum);
+        outv[ci] = bf16_bits(bf16_val(ap[ci]) > 0.0f ? sum : 0.0f);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(ga3 + p * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = *reinterpret_cast<uint4*>(&outv[8 * q]);
+}
+
+// output layer wgrad: thread t < 288 owns dW4[tap = t / 32][ci = t % 32], thread 288
+// owns db4; block k sums pixels k, k + gridDim.x, ... ; part[block][289]
+constexpr int OWG = 320;
+__global__ __launch_bounds__(OWG) void k_out_wgrad(const u16* __restrict__ a3, const float* __restrict__ g,
+                                                   float* __restrict__ part, int B, int H, int W)
+{
+    const int t = threadIdx.x;
+    const size_t HW = (size_t)H * W, P = (size_t)B * HW;
+    const int tap = t / 32, ci = t % 32;
+    float acc = 0.0f;
+    if (t < 289) {
+        for (size_t p = blockIdx.x; p < P; p += gridDim.x) {
+            const float gp = g[p];
+            if (t == 288) {
+                acc += gp;
+            } else {
+                const int b = (int)(p / HW), r = (int)(p % HW), y = r / W, x = r % W;
+                const int yy = wrapi(y + tap / 3 - 1, H), xx = wrapi(x + tap % 3 - 1, W);
+                acc = fmaf(bf16_val(a3[(((size_t)b * H + yy) * W + xx) * 32 + ci]), gp, acc);
+            }
+        }
+        part[(size_t)blockIdx.x * 289 + t] = acc;
+    }
+}
+
+// Adam on FP32 masters (bias-corrected; Kingma & Ba)
+__global__ __launch_bounds__(NBLK) void k_adam(float* __restrict__ p, float* __restrict__ m,
+                                               float* __restrict__ v, const float* __restrict__ g, int n,
+                                               float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * NBLK + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Residual check of a surrogate jump (per sample, [B, HW] arrays, FP64 sums):
+//   part[3 (b nbs + blk) + 0] += sum ((c_hat - c_prev)/(K dt) + (c_hat - c_step)/dt)^2
+//   part[... + 1]             += sum ((c_hat - c_prev)/(K dt))^2
+//   part[... + 2]             += sum (c_hat - c_prev)
+// where c_step is one explicit step of c_hat, so (c_hat - c_step)/dt = M K mu(c_hat)/m and
+// the first sum is the squared backward-Euler residual of the jump divided by m.
+__global__ __launch_bounds__(NBLK) void k_check_sums(const float* __restrict__ chat,
+                                                     const float* __restrict__ cprev,
+                                                     const float* __restrict__ cstep, int HW,
+                                                     double inv_kdt, double inv_dt,
+                                                     double* __restrict__ part)
+{
+    const int nbs = (HW + NBLK - 1) / NBLK;
+    const int b = blockIdx.x / nbs, blk = blockIdx.x % nbs;
+    const int i = blk * NBLK + threadIdx.x;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (i < HW) {
+        const size_t p = (size_t)b * HW + i;
+        const double dj = (double)chat[p] - (double)cprev[p];
+        const double rt = dj * inv_kdt + ((double)chat[p] - (double)cstep[p]) * inv_dt;
+        v0 = rt * rt;
+        v1 = dj * inv_kdt * dj * inv_kdt;
+        v2 = dj;
+    }
+    __shared__ double sh[3][NBLK];
+    sh[0][threadIdx.x] = v0;
+    sh[1][threadIdx.x] = v1;
+    sh[2][threadIdx.x] = v2;
+    __syncthreads();
+    for (int s = NBLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[3 * (size_t)blockIdx.x + q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(NBLK) void k_check_final(const double* __restrict__ part, int nbs,
+                                                      double* __restrict__ out)
+{
+    const int b = blockIdx.x;
+    __shared__ double sh[3][NBLK];
+    for (int q = 0; q < 3; ++q) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < nbs; i += NBLK) a += part[3 * ((size_t)b * nbs + i) + q];
+        sh[q][threadIdx.x] = a;
+    }
+    __syncthreads();
+    for (int s = NBLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[3 * b + 0] = sqrt(sh[0][0]) / fmax(sqrt(sh[1][0]), 1e-300);  // rho
+        out[3 * b + 1] = sh[2][0];                                        // sum (c_hat - c_prev)
+        out[3 * b + 2] = sqrt(sh[1][0]);                                  // ||jump|| / (K dt)
+    }
+}
+
+// first-layer weight gradient: dW1[tap][ci][co] = tile[tap][ci][co] for ci < 3
+__global__ __launch_bounds__(NBLK) void k_extract_w1(const float* __restrict__ tile, float* __restrict__ dw1)
+{
+    const int i = blockIdx.x * NBLK + threadIdx.x;
+    if (i >= 9 * 3 * 32) return;
+    const int co = i % 32, ci = (i / 32) % 3, tap = i / 96;
+    dw1[i] = tile[(tap * 32 + ci) * 32 + co];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void nn_check(const float* chat, const float* cprev, const float* cstep, int B, int HW, double kdt,
+              double dt, double* part, double* out, hipStream_t s)
+{
+    const int nbs = (HW + NBLK - 1) / NBLK;
+    k_check_sums<<<B * nbs, NBLK, 0, s>>>(chat, cprev, cstep, HW, 1.0 / kdt, 1.0 / dt, part);
+    k_check_final<<<B, NBLK, 0, s>>>(part, nbs, out);
+}
+
+void nn_extract_w1(const float* tile, float* dw1, hipStream_t s)
+{
+    k_extract_w1<<<(9 * 3 * 32 + NBLK - 1) / NBLK, NBLK, 0, s>>>(tile, dw1);
+}
+
+NNOffsets nn_offsets()
+{
+    NNOffsets o{};
+    int k = 0;
+    o.w1 = k; k += 9 * 3 * 32;
+    o.b1 = k; k += 32;
+    o.w2 = k; k += 9 * 32 * 32;
+    o.b2 = k; k += 32;
+    o.w3 = k; k += 9 * 32 * 32;
+    o.b3 = k; k += 32;
+    o.w4 = k; k += 9 * 32;
+    o.b4 = k; k += 1;
+    o.total = k;
+    return o;
+}
+
+NNFragOffsets nn_frag_offsets()
+{
+    NNFragOffsets f{};
+    const int n1 = 9 * 64 * 8, n2 = 9 * 2 * 64 * 8;
+    f.f1 = 0;
+    f.f2 = n1;
+    f.f3 = n1 + n2;
+    f.d2 = n1 + 2 * n2;
+    f.d3 = n1 + 3 * n2;
+    f.total = n1 + 4 * n2;
+    return f;
+}
+
+int nn_wgrad_blocks(int B, int H, int W)
+{
+    const long long tiles = (long long)B * ((H + TR - 1) / TR) * (W / TW);
+    return (int)(tiles < 1024 ? tiles : 1024);
+}
+
+int nn_conv_blocks(int B, int H, int W) { return B * ((H + TR - 1) / TR) * (W / TW); }
+
+void nn_prep_weights(const float* params, u16* frag, u16* w4, hipStream_t s)
+{
+    const NNFragOffsets fo = nn_frag_offsets();
+    const int n = fo.total + 9 * 32;
+    k_prep_weights<<<(n + NBLK - 1) / NBLK, NBLK, 0, s>>>(params, nn_offsets(), frag, fo, w4);
+}
+
+void nn_pack_input(const float* c, const float* M, const float* kappa, u16* a0, int B, int HW,
+                   hipStream_t s)
+{
+    const size_t n = (size_t)B * HW;
+    k_pack_input<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(c, M, kappa, a0, B, HW);
+}
+
+void nn_conv(int layer, int mode, const u16* in, const u16* frag, const float* bias, const u16* mask,
+             u16* out, int B, int H, int W, hipStream_t s)
+{
+    const unsigned nb = (unsigned)nn_conv_blocks(B, H, W);
+    if (layer == 1)
+        k_conv_mfma<16, 0><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+    else if (mode == 0)
+        k_conv_mfma<32, 0><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+    else
+        k_conv_mfma<32, 1><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+}
+
+void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb, int B, int H, int W,
+              hipStream_t s)
+{
+    const int nb = nn_wgrad_blocks(B, H, W);
+    if (layer == 1)
+        k_wgrad_mfma<16><<<nb, NBLK, 0, s>>>(ain, g, part, partb, B, H, W);
+    else
+        k_wgrad_mfma<32><<<nb, NBLK, 0, s>>>(ain, g, part, partb, B, H, W);
+}
+
+void nn_sum_partials(const float* part, int nb, int n, float* out, hipStream_t s)
+{
+    k_sum_partials<<<(n + NBLK - 1) / NBLK, NBLK, 0, s>>>(part, nb, n, out);
+}
+
+void nn_out_fwd(const u16* a3, const u16* w4, const float* params, float* d, int B, int H, int W,
+                hipStream_t s)
+{
+    const size_t n = (size_t)B * H * W;
+    k_out_fwd<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(a3, w4, params, nn_offsets(), d, B, H, W);
+}
+
+void nn_sample_mean(const float* x, double* part, double* mean, int B, int HW, hipStream_t s)
+{
+    const int nbs = (HW + NBLK - 1) / NBLK;
+    k_sample_sum<<<B * nbs, NBLK, 0, s>>>(x, HW, part);
+    k_sample_mean<<<B, NBLK, 0, s>>>(part, nbs, HW, mean);
+}
+
+void nn_project(const float* c, const float* d, const double* mean, const float* tgt, float* chat,
+                float* g, float* r2, int B, int HW, hipStream_t s)
+{
+    const size_t n = (size_t)B * HW;
+    k_project<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(c, d, mean, tgt, chat, g, r2, B, HW);
+}
+
+void nn_center(float* g, const double* mean, int B, int HW, hipStream_t s)
+{
+    const size_t n = (size_t)B * HW;
+    k_center<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(g, mean, B, HW);
+}
+
+int nn_out_wgrad_blocks(int B, int H, int W)
+{
+    const long long P = (long long)B * H * W;
+    return (int)(P < 1024 ? P : 1024);
+}
+
+void nn_out_bwd(const u16* a3, const u16* w4, const float* g, u16* ga3, float* part, int B, int H,
+                int W, hipStream_t s)
+{
+    const size_t n = (size_t)B * H * W;
+    k_out_dgrad<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(a3, w4, g, ga3, B, H, W);
+    k_out_wgrad<<<nn_out_wgrad_blocks(B, H, W), OWG, 0, s>>>(a3, g, part, B, H, W);
+}
+
+void nn_adam(float* p, float* m, float* v, const float* g, int n, int t, double lr, double b1,
+             double b2, double eps, hipStream_t s)
+{
+    const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+    k_adam<<<(n + NBLK - 1) / NBLK, NBLK, 0, s>>>(p, m, v, g, n, (float)lr, (float)b1, (float)b2,
+                                                  (float)eps, (float)c1, (float)c2);
+}
+
+}  // namespace pfk

@@ -1,0 +1,176 @@
+// nn_api.hip -- C ABI of the convolutional surrogate and of its residual check.
+#include <cmath>
+#include <cstring>
+
+#include "api_internal.hpp"
+#include "krylov.hpp"
+#include "nn.hpp"
+
+namespace pfapi {
+namespace {
+
+inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct NNWS {
+    unsigned short *a0, *a1, *a2, *a3, *ga, *gb, *frag, *w4;
+    float *d, *chat, *g, *r2, *part, *partb, *tile;
+    double *spart, *mean, *mean2;
+    size_t bytes;
+};
+
+NNWS nn_layout(int B, int H, int W, void* base)
+{
+    NNWS L{};
+    char* c = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* r = c ? c + off : nullptr;
+        off += al(b);
+        return r;
+    };
+    const size_t P = (size_t)B * H * W;
+    const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
+    L.a0 = (unsigned short*)take(P * 16 * 2);
+    L.a1 = (unsigned short*)take(P * 32 * 2);
+    L.a2 = (unsigned short*)take(P * 32 * 2);
+    L.a3 = (unsigned short*)take(P * 32 * 2);
+    L.ga = (unsigned short*)take(P * 32 * 2);
+    L.gb = (unsigned short*)take(P * 32 * 2);
+    L.frag = (unsigned short*)take((size_t)fo.total * 2);
+    L.w4 = (unsigned short*)take(9 * 32 * 2);
+    L.d = (float*)take(P * 4);
+    L.chat = (float*)take(P * 4);
+    L.g = (float*)take(P * 4);
+    L.r2 = (float*)take(P * 4);
+    const size_t nwg = (size_t)pfk::nn_wgrad_blocks(B, H, W), nog = (size_t)pfk::nn_out_wgrad_blocks(B, H, W);
+    L.part = (float*)take(std::max(nwg * 9 * 32 * 32, nog * 289) * 4);
+    L.partb = (float*)take(nwg * 32 * 4);
+    L.tile = (float*)take(9 * 32 * 32 * 4);
+    const size_t nbs = ((size_t)H * W + 255) / 256;
+    L.spart = (double*)take((size_t)B * nbs * 3 * 8);
+    L.mean = (double*)take((size_t)B * 8);
+    L.mean2 = (double*)take((size_t)B * 8);
+    L.bytes = off;
+    return L;
+}
+
+int check_shape(int B, int H, int W)
+{
+    if (B < 1 || H < 1 || W < 32) return fail(PF_EINVAL, "need B >= 1, H >= 1, W >= 32");
+    if (W % 32) return fail(PF_EINVAL, "W must be a multiple of 32 (got %d)", W);
+    if ((long long)B * H * W >= (1ll << 31) / 64) return fail(PF_EINVAL, "batch too large");
+    return PF_OK;
+}
+
+// the forward pass, leaving a0..a3 and d in the workspace
+void forward(const float* params, int B, int H, int W, const float* c, const float* M,
+             const float* kappa, const float* target, NNWS& L, hipStream_t s)
+{
+    const pfk::NNOffsets o = pfk::nn_offsets();
+    const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
+    const int HW = H * W;
+    pfk::nn_prep_weights(params, L.frag, L.w4, s);
+    pfk::nn_pack_input(c, M, kappa, L.a0, B, HW, s);
+    pfk::nn_conv(1, 0, L.a0, L.frag + fo.f1, params + o.b1, nullptr, L.a1, B, H, W, s);
+    pfk::nn_conv(2, 0, L.a1, L.frag + fo.f2, params + o.b2, nullptr, L.a2, B, H, W, s);
+    pfk::nn_conv(3, 0, L.a2, L.frag + fo.f3, params + o.b3, nullptr, L.a3, B, H, W, s);
+    pfk::nn_out_fwd(L.a3, L.w4, params, L.d, B, H, W, s);
+    pfk::nn_sample_mean(L.d, L.spart, L.mean, B, HW, s);
+    pfk::nn_project(c, L.d, L.mean, target, L.chat, L.g, L.r2, B, HW, s);
+}
+
+}  // namespace
+}  // namespace pfapi
+
+using namespace pfapi;
+
+extern "C" {
+
+int pf_nn_param_count(void) { return pfk::nn_offsets().total; }
+
+int pf_nn_workspace_size(int B, int H, int W, size_t* bytes)
+{
+    if (int rc = check_shape(B, H, W)) return rc;
+    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+    *bytes = nn_layout(B, H, W, nullptr).bytes;
+    return PF_OK;
+}
+
+int pf_nn_forward(const float* params, int B, int H, int W, const float* c, const float* M,
+                  const float* kappa, float* chat, void* ws, void* stream)
+{
+    if (int rc = check_shape(B, H, W)) return rc;
+    if (!params || !c || !M || !kappa || !chat || !ws) return fail(PF_EINVAL, "NULL pointer argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    NNWS L = nn_layout(B, H, W, ws);
+    forward(params, B, H, W, c, M, kappa, nullptr, L, s);
+    if (hipMemcpyAsync(chat, L.chat, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return check_launch("pf_nn_forward copy");
+    return check_launch("pf_nn_forward");
+}
+
+int pf_nn_backward(const float* params, int B, int H, int W, const float* c, const float* M,
+                   const float* kappa, const float* target, double* loss, float* grad, void* ws,
+                   void* stream)
+{
+    if (int rc = check_shape(B, H, W)) return rc;
+    if (!params || !c || !M || !kappa || !target || !grad || !ws)
+        return fail(PF_EINVAL, "NULL pointer argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    NNWS L = nn_layout(B, H, W, ws);
+    const pfk::NNOffsets o = pfk::nn_offsets();
+    const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
+    const int HW = H * W;
+    forward(params, B, H, W, c, M, kappa, target, L, s);
+    if (loss) pfk::nn_sample_mean(L.r2, L.spart, loss, B, HW, s);  // per-sample MSE
+    // backward of the mass projection: g <- g - mean(g)
+    pfk::nn_sample_mean(L.g, L.spart, L.mean2, B, HW, s);
+    pfk::nn_center(L.g, L.mean2, B, HW, s);
+    // output layer
+    pfk::nn_out_bwd(L.a3, L.w4, L.g, L.ga, L.part, B, H, W, s);
+    pfk::nn_sum_partials(L.part, pfk::nn_out_wgrad_blocks(B, H, W), 289, grad + o.w4, s);
+    const int nwg = pfk::nn_wgrad_blocks(B, H, W);
+    // layer 3: ga = d pre3
+    pfk::nn_wgrad(3, L.a2, L.ga, L.part, L.partb, B, H, W, s);
+    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w3, s);
+    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b3, s);
+    pfk::nn_conv(3, 1, L.ga, L.frag + fo.d3, nullptr, L.a2, L.gb, B, H, W, s);  // gb = d pre2
+    // layer 2
+    pfk::nn_wgrad(2, L.a1, L.gb, L.part, L.partb, B, H, W, s);
+    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w2, s);
+    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b2, s);
+    pfk::nn_conv(2, 1, L.gb, L.frag + fo.d2, nullptr, L.a1, L.ga, B, H, W, s);  // ga = d pre1
+    // layer 1 (input channels padded 3 -> 16)
+    pfk::nn_wgrad(1, L.a0, L.ga, L.part, L.partb, B, H, W, s);
+    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, L.tile, s);
+    pfk::nn_extract_w1(L.tile, grad + o.w1, s);
+    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b1, s);
+    return check_launch("pf_nn_backward");
+}
+
+int pf_nn_check(int B, int H, int W, const float* chat, const float* c_prev, const float* c_step,
+                double K_dt, double dt, double* out, void* ws, void* stream)
+{
+    if (int rc = check_shape(B, H, W)) return rc;
+    if (!chat || !c_prev || !c_step || !out || !ws) return fail(PF_EINVAL, "NULL pointer argument");
+    if (!(K_dt > 0.0) || !(dt > 0.0)) return fail(PF_EINVAL, "K_dt and dt must be > 0");
+    NNWS L = nn_layout(B, H, W, ws);
+    pfk::nn_check(chat, c_prev, c_step, B, H * W, K_dt, dt, L.spart, out, (hipStream_t)stream);
+    return check_launch("pf_nn_check");
+}
+
+int pf_nn_adam(float* params, float* m, float* v, const float* grad, int t, double lr, double beta1,
+               double beta2, double eps, void* stream)
+{
+    if (!params || !m || !v || !grad) return fail(PF_EINVAL, "NULL pointer argument");
+    if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+        !(eps > 0.0))
+        return fail(PF_EINVAL, "bad Adam hyper-parameters");
+    pfk::nn_adam(params, m, v, grad, pfk::nn_offsets().total, t, lr, beta1, beta2, eps,
+                 (hipStream_t)stream);
+    return check_launch("pf_nn_adam");
+}
+
+}  // extern "C"

@@ -83,6 +83,16 @@ int pf_tune_set(int key, int value)
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
 }
+int pf_launch_shape(const pf_problem* p, int* ks, int* ty, int* depth)
+{
+    if (int rc = validate(p)) return rc;
+    if (!ks || !ty || !depth) return fail(PF_EINVAL, "NULL output pointer");
+    *ks = stream2d_fuse(p);
+    *ty = stream2d_rows(p, *ks);
+    *depth = stream2d_depth(p);
+    return PF_OK;
+}
+
 int pf_tune_get(int key, int* value)
 {
     if (!value) return fail(PF_EINVAL, "value is NULL");
