@@ -9,7 +9,15 @@ in HBM before the timed region starts.
 
 Prints ONE JSON line (rank 0):
   metric/value/unit: DOF-steps per second over the timed region,
-  roofline: achieved algorithmic bandwidth of the step kernel vs 8 TB/s,
+  roofline: the step kernel against its bound.  A launch that fuses ks >= 2 steps
+    does 2 ks x 69 flops per 8 bytes moved and is bound by the FP32 vector ALUs
+    (non-packed: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s);
+    a single-step launch (69 flops per 8 bytes) is bound by HBM (8 TB/s),
+  hbm: the single-step launch timed on the same workload and on a 16384^2 grid
+    (1 GiB per field, beyond the 256 MB Infinity Cache) against 8 TB/s,
+  adjoint: wall time of the checkpointed batched adjoint gradient vs the six
+    forward runs central differences need (64 ragged Allen-Cahn samples),
+  surrogate: cost of one checked surrogate jump vs the K = 20 plain steps it replaces,
   cpu_baseline: the FP64 CPU reference timed on a bounded sample.
 """
 from __future__ import annotations
@@ -24,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # non-packed FP32 FMA issue: 78.6
 BYTES_PER_NODE_STEP = 8  # read c, write c (FP32) per launch; mu never leaves the chip
+FLOPS_PER_NODE_STEP_CH = 69  # sum-factorised Q1 split step, FMA = 2 flops (see DESIGN)
+METRIC = "DOF-steps/sec + %HBM peak (explicit CH, 4.19M DOF); adjoint & surrogate speedup"
 
 
 def parse():
@@ -34,7 +45,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=2048, help="grid side (default: the 2048^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--implicit", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS backward-Euler Newton steps of the 128^3 Cahn-Hilliard "
+                         "workload (4.19M DOF) and print their record")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time the batched adjoint record (64 ragged Allen-Cahn samples)")
+    ap.add_argument("--surrogate-gain", type=int, default=0, metavar="ITERS",
+                    help="only train the surrogate for ITERS iterations on 512^2 Cahn-Hilliard "
+                         "and print the matched-error gain record")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the hbm / adjoint / surrogate records (the step alone)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "ch2048_traffic.json"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -88,9 +109,12 @@ def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
     cw = [v for (k, c), v in cp.items() if c == "WRITE_SIZE" and v * 1024 > 0.5 * nbytes]
     f_scale = nbytes / (max(cf) * 1024) if cf else 1.0
     w_scale = nbytes / (max(cw) * 1024) if cw else 1.0
-    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and "k_explicit2d" in k]
-    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and "k_explicit2d" in k]
-    rec = {"n": n, "kernel_src_sha256_16": kernel_hash(),
+    import re
+    names = [k for (k, c) in step if "k_explicit2d<" in k]
+    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and "k_explicit2d<" in k]
+    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and "k_explicit2d<" in k]
+    m = re.search(r"k_explicit2d<float, \d+, \d+, (\d+)>", names[0]) if names else None
+    rec = {"n": n, "ks": int(m.group(1)) if m else None, "kernel_src_sha256_16": kernel_hash(),
            "fetch_kib_raw": kf[0] if kf else None, "write_kib_raw": kw[0] if kw else None,
            "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
     if kf and kw:
@@ -119,8 +143,199 @@ def cpu_baseline(n, steps):
                       f"FP64 element loop ({el:.1f} s)"}
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_ms(fn, stream):
+    """Wall time of fn's GPU work on `stream` (events recorded on that stream)."""
+    import torch
+    a, b = _events()
+    torch.cuda.synchronize()
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def ch_problem(n):
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import solver as S
+    return S.Problem(n=(n, n), model=A.CAHN_HILLIARD, fe=A.F_01, dtype=torch.float32, W=1.0,
+                     kappa=2.0, mobility=1.0, h=1.0)
+
+
+def single_step_hbm(n, steps, stream):
+    """The single-step (unfused) launch of the CH split step on an n x n grid:
+    8 algorithmic bytes per node per launch against 8 TB/s."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    p = ch_problem(n)
+    cfg = dict(I.CH2048, n=(n, n))
+    U = torch.as_tensor(I.initial_state(cfg, seed=0, dtype="float32"), device="cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    old = S.tune_get(A.TUNE_STREAM2D_FUSE)
+    S.tune_set(A.TUNE_STREAM2D_FUSE, 1)
+    try:
+        S.step_explicit(p, U, cfg["dt"], 20, ws)
+        epi = float(np.median([_time_ms(lambda: S.step_explicit(p, U, cfg["dt"], 0, ws), stream)
+                               for _ in range(5)]))
+        ms = _time_ms(lambda: S.step_explicit(p, U, cfg["dt"], steps, ws), stream)
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, old)
+    kern_ms = max(ms - epi, 1e-6) / steps
+    gbs = BYTES_PER_NODE_STEP * n * n / (kern_ms * 1e-3) / 1e9
+    del U, ws
+    torch.cuda.empty_cache()
+    return {"n": n, "kernel_ms": kern_ms, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "field_bytes": 4 * n * n}
+
+
+def adjoint_record(stream, count=64, nsteps=2000, every=100):
+    """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
+    2000 FP32 steps, dt = 0.05): forward with a snapshot every 100 steps plus the
+    checkpointed adjoint, against the six plain forward runs that central
+    differences in (L, kappa, W) need."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import batch as B
+    from paper_2601_06079_amd import inputs as I
+    sizes, theta, hidden, fields = I.batch_samples(count=count, seed=0)
+    sizes = [(int(n), int(n)) for n in sizes]
+    mk = lambda th: B.Batch(sizes, th, 0.05, model=A.ALLEN_CAHN, fe=A.F_SYM, dtype=torch.float32)
+    b = mk(theta)
+    U0 = b.pack(fields)
+    tgt = U0.clone()
+    mk(hidden).step(tgt, nsteps)
+    ws = b.workspace(A.OP_STEP_EXPLICIT)
+    U = U0.clone()
+    b.step(U, 100, ws)  # warm-up
+    t_plain = _time_ms(lambda: b.step(U, nsteps, ws), stream)
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    # warm-up of the whole autograd path (its snapshot and segment buffers then come
+    # from the allocator's cache, as in any repeated calibration iteration)
+    B.per_sample_mse(b, B.explicit_run(th, U0, b, nsteps, every=every), tgt).backward()
+    th.grad = None
+    state = {}
+
+    def fwd():
+        state["UN"] = B.explicit_run(th, U0, b, nsteps, every=every)
+        state["loss"] = B.per_sample_mse(b, state["UN"], tgt)
+
+    t_fwd = _time_ms(fwd, stream)
+    t_bwd = _time_ms(lambda: state["loss"].backward(), stream)
+    nodes = sum(a * c for a, c in sizes)
+    return {"workload": f"{count} ragged Allen-Cahn samples 128^2..512^2 ({nodes} nodes), "
+                        f"{nsteps} FP32 steps, checkpoint every {every}",
+            "forward_ms": t_fwd, "adjoint_ms": t_bwd, "plain_forward_ms": t_plain,
+            "central_fd_ms": 6 * t_plain,
+            "speedup_vs_central_fd": 6 * t_plain / (t_fwd + t_bwd),
+            "batched_dof_steps_per_s": nodes * nsteps / (t_plain * 1e-3)}
+
+
+def surrogate_record(stream, n=512, Bn=16, K=20, dt=0.01):
+    """One checked surrogate jump (network forward, one explicit step of c_hat, the
+    residual/mass reductions) vs the K plain FP32 steps it replaces, on a batch of
+    Bn 512^2 Cahn-Hilliard samples.  Cost only: the matched-error gain needs a
+    trained network and is measured by the surrogate gain test."""
+    import numpy as np
+
+    from paper_2601_06079_amd import nn as NN
+    rng = np.random.default_rng(0)
+    ens = NN.CHEnsemble(Bn, n, rng.uniform(0.5, 2, Bn), rng.uniform(0.5, 2, Bn), dt=dt, seed=1)
+    ens.advance(200)
+    model = NN.Surrogate(seed=0)
+    c = ens.field().clone()
+    U = ens.U.clone()
+    reps = 10
+
+    def jump():
+        chat = model.forward(c, ens.Mt, ens.kt)
+        step = chat.reshape(-1).clone()
+        ens.batch.step(step, 1, ens.ws)
+        model.check(chat, c, step.view_as(chat), K * dt, dt)
+
+    jump()
+    ens.batch.step(U, K, ens.ws)
+    t_fwd = _time_ms(lambda: [model.forward(c, ens.Mt, ens.kt) for _ in range(reps)], stream) / reps
+    t_jump = _time_ms(lambda: [jump() for _ in range(reps)], stream) / reps
+    t_plain = _time_ms(lambda: [ens.batch.step(U, K, ens.ws) for _ in range(reps)], stream) / reps
+    flop = 39168.0 * Bn * n * n
+    return {"workload": f"{Bn} x {n}^2 Cahn-Hilliard, K = {K} steps of dt = {dt}",
+            "network_forward_ms": t_fwd, "checked_jump_ms": t_jump, "plain_K_steps_ms": t_plain,
+            "speedup_per_jump": t_plain / t_jump,
+            "network_forward_tflops": flop / (t_fwd * 1e-3) / 1e12}
+
+
+def implicit_record(steps, stream):
+    """Backward-Euler Newton steps of 128^3 periodic Cahn-Hilliard (c, mu both
+    unknowns: 4 194 304 DOF), dt = 0.5, matrix-free JVP + GMRES(30) with 2x2
+    block-Jacobi, FP32 fields and FP64 reductions (Eqs. 13-14)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    cfg = I.CH3D128
+    n = cfg["n"]
+    p = S.Problem(n=n, model=A.CAHN_HILLIARD, fe=A.F_01, dtype=torch.float32, W=1.0, kappa=2.0,
+                  mobility=1.0, h=1.0)
+    c0 = I.uniform_field(n, cfg["lo"], cfg["hi"], seed=0, base=cfg["base"]).astype(np.float32)
+    U = torch.as_tensor(np.concatenate([c0, np.zeros_like(c0)]), device="cuda")
+    S.step_explicit(p, U, 1e-30, 0)  # mu0 = [N(c0) + kappa K c0]/m
+    ws = S.workspace(p, A.OP_NEWTON)
+    Uold = torch.empty_like(U)
+    newton, gmres, ok = [], [], 0
+    Uold.copy_(U)
+    S.newton_step(p, cfg["dt"], Uold, U, ws=ws)  # warm-up step (not timed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        Uold.copy_(U)
+        rep = S.newton_step(p, cfg["dt"], Uold, U, ws=ws)
+        newton.append(rep.newton_its)
+        gmres.append(rep.gmres_its)
+        ok += int(rep.converged)
+        if (k + 1) % 20 == 0:
+            print(f"[implicit] step {k + 1}/{steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dof = 2 * int(np.prod(n))
+    return {"workload": "3D Cahn-Hilliard 128^3 periodic, backward Euler dt=0.5, Newton + GMRES(30) "
+                        "with 2x2 block-Jacobi, FP32 fields, FP64 reductions",
+            "dof": dof, "steps": steps, "converged_steps": ok, "ms_per_step": 1e3 * el / steps,
+            "dof_steps_per_s": dof * steps / el,
+            "newton_its_per_step": float(np.mean(newton)),
+            "gmres_its_per_newton": float(np.sum(gmres) / max(np.sum(newton), 1)),
+            "mass_drift": float(abs(U[: dof // 2].double().mean() - float(c0.astype(np.float64).mean())))}
+
+
 def main():
     args = parse()
+    if args.implicit or args.surrogate_gain or args.adjoint:
+        import torch
+        stream = torch.cuda.current_stream()
+        if args.adjoint:
+            print(json.dumps(adjoint_record(stream)), flush=True)
+        if args.implicit:
+            print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
+        if args.surrogate_gain:
+            from paper_2601_06079_amd import nn as NN
+            rec = NN.gain_experiment(train_iters=args.surrogate_gain,
+                                     log=lambda m: print(m, file=sys.stderr, flush=True))
+            print(json.dumps(rec), flush=True)
+        return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
                            int(args.summarize_counters[2]), n=args.n)
@@ -143,8 +358,7 @@ def main():
     n = args.n
     cfg = dict(I.CH2048, n=(n, n))
     N = n * n
-    p = S.Problem(n=(n, n), model=A.CAHN_HILLIARD, fe=A.F_01, dtype=torch.float32, W=1.0,
-                  kappa=2.0, mobility=1.0, h=1.0)
+    p = ch_problem(n)
     U = torch.as_tensor(I.initial_state(cfg, seed=0, dtype="float32"), device="cuda")
     ws = S.workspace(p, A.OP_STEP_EXPLICIT)
     dt = cfg["dt"]
@@ -153,9 +367,8 @@ def main():
     S.step_explicit(p, U, dt, args.warmup, ws)
     torch.cuda.synchronize()
 
-    # timed region: K steps in one call (the library enqueues K fused launches)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # timed region: K steps in one call (the library enqueues the fused launches)
+    e0, e1 = _events()
     torch.cuda.synchronize()
     e0.record(stream)
     S.step_explicit(p, U, dt, args.steps, ws)
@@ -171,33 +384,41 @@ def main():
     ks_, ty_, dp_ = ct.c_int(0), ct.c_int(0), ct.c_int(0)
     A.check(A.lib().pf_launch_shape(ct.byref(p.c()), ct.byref(ks_), ct.byref(ty_), ct.byref(dp_)))
     ks = ks_.value
-    reps = 20
-    evm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
-    for i in range(reps):
-        evm[i][0].record(stream)
-        S.step_explicit(p, U, dt, 0, ws)  # the mu epilogue alone
-        evm[i][1].record(stream)
-    torch.cuda.synchronize()
-    epi = sorted(a_.elapsed_time(b_) for a_, b_ in evm)[reps // 2]
+    import numpy as np
+    epi = float(np.median([_time_ms(lambda: S.step_explicit(p, U, dt, 0, ws), stream)
+                           for _ in range(11)]))
     launches = args.steps // ks + args.steps % ks
     kern_ms = max(ms_total - epi, 1e-6) / launches
-    # one fused launch reads c once and writes c once: 8 B per node per launch
-    achieved = BYTES_PER_NODE_STEP * N / (kern_ms * 1e-3) / 1e9
-    effective = BYTES_PER_NODE_STEP * N * args.steps / (ms_total * 1e-3) / 1e9
+    steps_per_launch = args.steps / launches
+    gbs = BYTES_PER_NODE_STEP * N / (kern_ms * 1e-3) / 1e9  # c read once, written once per launch
+    tflops = FLOPS_PER_NODE_STEP_CH * steps_per_launch * N / (kern_ms * 1e-3) / 1e12
 
     # measured HBM bytes per launch, only if taken on this exact kernel source
     traffic = None
     if os.path.exists(args.traffic):
         try:
             t = json.load(open(args.traffic))
-            if t.get("n") == n and t.get("kernel_src_sha256_16") == kernel_hash():
+            if (t.get("n") == n and t.get("kernel_src_sha256_16") == kernel_hash()
+                    and t.get("ks") == ks):
                 traffic = t.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
 
+    kname = f"k_explicit2d<float, CH, {dp_.value}, {ks}>"
+    if ks >= 2:
+        roof = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / VALU_PEAK_TFLOPS, "traffic": traffic,
+                "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "alu_achieved_tflops": tflops, "alu_frac": tflops / VALU_PEAK_TFLOPS}
+    roof.update({"kernel": f"{kname} ({ks} fused steps per launch, {ty_.value} rows per wave)",
+                 "kernel_ms": kern_ms, "launches": launches,
+                 "effective_gbs_per_step": BYTES_PER_NODE_STEP * N * args.steps / (ms_total * 1e-3) / 1e9})
+
     out = {
-        "metric": "DOF-steps/sec (explicit CH, 4.19M DOF)",
+        "metric": METRIC,
         "value": value,
         "unit": "DOF-steps/s",
         "n_gpus": 1,
@@ -211,11 +432,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D Cahn-Hilliard spinodal, {n}x{n} periodic, explicit split step, "
                                "dt=0.01, W=1, kappa=2, M=1", "dof": N, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_explicit2d<float, CH, 4, {ks}> ({ks} fused steps per launch)",
-                     "kernel_ms": kern_ms, "effective_gbs_per_step": effective},
+        "roofline": roof,
     }
+    del U, ws
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["hbm"] = {"single_step_launch": single_step_hbm(n, 1000, stream),
+                      "single_step_launch_16384": single_step_hbm(16384, 40, stream)}
+        out["adjoint"] = adjoint_record(stream)
+        out["surrogate"] = surrogate_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

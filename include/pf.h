@@ -214,13 +214,13 @@ typedef struct pf_batch_sample {
 
 /* Host-side description of a device plan (filled by pf_batch_plan). */
 typedef struct pf_batch_info {
-    int32_t count, n_items, n_vblocks; /* samples, explicit work items, 256-node blocks */
+    int32_t count, n_items, reserved0; /* samples, work items (sample, strip, chunk); 0 */
     int32_t ks, ty, depth;             /* fused steps, rows per wave, prefetch depth */
     int32_t model, dtype;
     int64_t total;                     /* elements of each packed array (max offset + nodes) */
     int64_t plan_bytes;
     double dt;
-    int64_t off_samples, off_items, off_vmap; /* byte offsets of the plan's tables */
+    int64_t off_samples, off_items, reserved1; /* byte offsets of the plan's tables; 0 */
 } pf_batch_info;
 
 /* Bytes of the device plan for these samples with ks fused steps and ty rows
@@ -239,7 +239,7 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
                   pf_batch_info* info, void* stream);
 
 /* Workspace of a batched call: PF_OP_STEP_EXPLICIT (one packed field) or
- * PF_OP_VJP (one packed field + FP64 partials). */
+ * PF_OP_VJP (one packed field + two FP64 slots per work item of info). */
 int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes);
 
 /* nsteps explicit steps (Eq. 12) of every sample, one launch per info->ks steps
@@ -254,14 +254,15 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
 /* Adjoint of nsteps batched Allen-Cahn explicit steps (Supp. Note 2 applied
  * step by step).  states + k * info->total holds the input of step k+1
  * (k = 0..nsteps-1).  On entry lam holds dO/dU of the final state; on return
- * dO/dU of the first input.  Sensitivities of theta = (mobility, kappa, W)
- * accumulate per 256-node block in FP64 partials kept in ws; with
- * PF_VJP_BEGIN the partials are zeroed first, with PF_VJP_END they are summed
- * (fixed order) into theta_bar (device, count x 3 doubles).  A trajectory
- * processed in segments (checkpointing) with BEGIN on the first call and END
- * on the last gives bitwise the gradient of one call over all steps.
- * ws: pf_batch_workspace_size(PF_OP_VJP), kept between the calls of one
- * trajectory.  Asynchronous. */
+ * dO/dU of the first input.  The steps stream over the plan's work items
+ * (any ks; one step per launch).  Sensitivities of theta = (mobility, kappa, W)
+ * accumulate per work item in FP64 slots kept in ws; with PF_VJP_BEGIN the
+ * slots are zeroed first, with PF_VJP_END they are summed (fixed order) into
+ * theta_bar (device, count x 3 doubles).  A trajectory processed in segments
+ * (checkpointing) with BEGIN on the first call and END on the last gives
+ * bitwise the gradient of one call over all steps.  Cahn-Hilliard plans:
+ * PF_EUNSUPPORTED.  ws: pf_batch_workspace_size(PF_OP_VJP) of the same info,
+ * kept between the calls of one trajectory.  Asynchronous. */
 enum { PF_VJP_BEGIN = 1, PF_VJP_END = 2 };
 int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
                             const void* states, void* lam, double* theta_bar, void* ws, int flags,

@@ -22,6 +22,7 @@ OP_RESIDUAL, OP_STEP_EXPLICIT, OP_ENERGY, OP_NEWTON, OP_VJP, OP_JVP = range(6)
 TUNE_STREAM2D_ROWS, TUNE_STREAM2D_DEPTH, TUNE_STREAM2D_FUSE = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 VJP_RESIDUAL, VJP_EXPLICIT_STEP, VJP_NEWTON_STEP = 0, 1, 2
+VJP_BEGIN, VJP_END = 1, 2  # flags of pf_vjp_explicit_batched
 
 
 class pf_problem(ct.Structure):
@@ -51,11 +52,11 @@ class pf_batch_sample(ct.Structure):
 
 
 class pf_batch_info(ct.Structure):
-    _fields_ = [("count", ct.c_int32), ("n_items", ct.c_int32), ("n_vblocks", ct.c_int32),
+    _fields_ = [("count", ct.c_int32), ("n_items", ct.c_int32), ("reserved0", ct.c_int32),
                 ("ks", ct.c_int32), ("ty", ct.c_int32), ("depth", ct.c_int32),
                 ("model", ct.c_int32), ("dtype", ct.c_int32), ("total", ct.c_int64),
                 ("plan_bytes", ct.c_int64), ("dt", ct.c_double), ("off_samples", ct.c_int64),
-                ("off_items", ct.c_int64), ("off_vmap", ct.c_int64)]
+                ("off_items", ct.c_int64), ("reserved1", ct.c_int64)]
 
 
 class PFError(RuntimeError):

@@ -112,8 +112,10 @@ class Batch:
         return [U[o:o + nx * ny] for (nx, ny), o in zip(self.sizes, self.offsets)]
 
     def workspace(self, op):
+        """Workspace for step (the fused plan) or vjp (the single-step plan it runs on)."""
+        info = self.info1 if op == A.OP_VJP else self.info
         nb = ct.c_size_t(0)
-        A.check(self.L.pf_batch_workspace_size(ct.byref(self.info), op, ct.byref(nb)))
+        A.check(self.L.pf_batch_workspace_size(ct.byref(info), op, ct.byref(nb)))
         return torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
 
     def step(self, U, nsteps, ws=None, traj=None):
@@ -144,7 +146,7 @@ class Batch:
         (begin: zero the FP64 partials in ws first; end: reduce them into theta_bar)."""
         if ws is None:
             ws = self.workspace(A.OP_VJP)
-        flags = (1 if begin else 0) | (2 if end else 0)
+        flags = (A.VJP_BEGIN if begin else 0) | (A.VJP_END if end else 0)
         A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info1), ct.c_void_p(self.plan1.data_ptr()),
                                                int(nsteps), ct.c_void_p(states.data_ptr()),
                                                ct.c_void_p(lam.data_ptr()),

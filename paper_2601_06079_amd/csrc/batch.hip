@@ -7,11 +7,11 @@
 //   BatchSample[count]  per-sample geometry and coefficients,
 //   BatchItem[n_items]  one (sample, strip, chunk) work item per wavefront of the
 //                       fused explicit kernel (strips and chunks as for a single
-//                       problem, so tail items of uneven sizes are just shorter),
-//   int vmap[n_vblocks] sample of each 256-node block of the adjoint kernel.
-// One launch then advances every sample by ks fused steps; the adjoint kernel
-// sweeps every sample's nodes per step and keeps per-block FP64 sensitivity
-// partials that a final fixed-order reduction turns into per-sample gradients.
+//                       problem, so tail items of uneven sizes are just shorter).
+// One launch then advances every sample by ks fused steps.  The adjoint kernel
+// streams the same work items backwards in time, one step per launch, and adds
+// each item's FP64 sensitivity sums to its own slot; a final fixed-order
+// reduction turns the slots into per-sample gradients.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -44,7 +44,7 @@ int validate_base(const pf_problem* p)
 int strips_of(long long nx, int HK) { return (int)((nx + (64 - 2 * HK) - 1) / (64 - 2 * HK)); }
 
 struct Counts {
-    long long n_items = 0, n_vblocks = 0, total = 0;
+    long long n_items = 0, total = 0;
 };
 
 int count_plan(const pf_problem* base, const pf_batch_sample* s, int count, int ks, int ty,
@@ -69,20 +69,18 @@ int count_plan(const pf_problem* base, const pf_batch_sample* s, int count, int 
             return fail(PF_EINVAL, "sample %d: h must be > 0 and parameters finite", i);
         ranges.push_back({q.offset, q.offset + N});
         c->n_items += (long long)strips_of(q.n[0], HK) * ((q.n[1] + ty - 1) / ty);
-        c->n_vblocks += (N + 255) / 256;
         c->total = std::max(c->total, q.offset + N);
     }
     std::sort(ranges.begin(), ranges.end());
     for (size_t i = 1; i < ranges.size(); ++i)
         if (ranges[i].first < ranges[i - 1].second) return fail(PF_EINVAL, "sample ranges overlap");
-    if (c->n_items > (1ll << 30) || c->n_vblocks > (1ll << 30)) return fail(PF_EINVAL, "batch too large");
+    if (c->n_items > (1ll << 30)) return fail(PF_EINVAL, "batch too large");
     return PF_OK;
 }
 
 size_t plan_bytes_of(int count, const Counts& c)
 {
-    return align256(sizeof(pfk::BatchSample) * count) + align256(sizeof(pfk::BatchItem) * c.n_items) +
-           align256(sizeof(int) * c.n_vblocks);
+    return align256(sizeof(pfk::BatchSample) * count) + align256(sizeof(pfk::BatchItem) * c.n_items);
 }
 
 int auto_ty(const pf_problem* base, const pf_batch_sample* s, int count, int ks)
@@ -91,12 +89,12 @@ int auto_ty(const pf_problem* base, const pf_batch_sample* s, int count, int ks)
     long long items48 = 0;
     const int HK = (base->model == PF_CAHN_HILLIARD ? 2 : 1) * ks;
     int ty = 48;
-    while ((ty + 2 * HK) % 4) --ty;
+    while ((ty + 2 * HK) % 4) --ty;  // chunk + halo fills whole prefetch groups
     for (;;) {
         items48 = 0;
         for (int i = 0; i < count; ++i)
             items48 += (long long)strips_of(s[i].n[0], HK) * ((s[i].n[1] + ty - 1) / ty);
-        if (ty <= 8 || items48 >= 4 * 1024) break;
+        if (ty - 4 < 8 || items48 >= 4 * 1024) break;  // never below 8 rows (plan size bound)
         ty -= 4;
     }
     return ty;
@@ -174,9 +172,7 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
 
     std::vector<pfk::BatchSample> smp(count);
     std::vector<pfk::BatchItem> items;
-    std::vector<int> vmap;
     items.reserve(c.n_items);
-    vmap.reserve(c.n_vblocks);
     const int H = base->model == PF_CAHN_HILLIARD ? 2 : 1;
     const int HK = H * ks;
     for (int i = 0; i < count; ++i) {
@@ -188,9 +184,6 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
         b.ny = (int)q.n[1];
         b.nstrips = strips_of(q.n[0], HK);
         b.first_item = (int)items.size();
-        b.first_vblock = (int)vmap.size();
-        const long long N = q.n[0] * q.n[1];
-        b.nvblock = (int)((N + 255) / 256);
         b.fe = base->fe;
         const pfk::FreeEnergy f = pfk::make_free_energy(base->fe, q.W);
         const double m = q.h * q.h, detJ = 0.25 * q.h * q.h;
@@ -212,14 +205,11 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
         const int chunks = (int)((q.n[1] + ty - 1) / ty);
         for (int ch = 0; ch < chunks; ++ch)
             for (int st = 0; st < b.nstrips; ++st) items.push_back({i, st, ch, 0});
-        for (int v = 0; v < b.nvblock; ++v) vmap.push_back(i);
     }
     std::vector<unsigned char> host(need, 0);
-    const size_t o_s = 0, o_i = align256(sizeof(pfk::BatchSample) * count),
-                 o_v = o_i + align256(sizeof(pfk::BatchItem) * items.size());
+    const size_t o_s = 0, o_i = align256(sizeof(pfk::BatchSample) * count);
     std::memcpy(host.data() + o_s, smp.data(), sizeof(pfk::BatchSample) * count);
     std::memcpy(host.data() + o_i, items.data(), sizeof(pfk::BatchItem) * items.size());
-    std::memcpy(host.data() + o_v, vmap.data(), sizeof(int) * vmap.size());
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(plan_dev, host.data(), need, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -227,7 +217,6 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
     pf_batch_info I{};
     I.count = count;
     I.n_items = (int32_t)items.size();
-    I.n_vblocks = (int32_t)vmap.size();
     I.ks = ks;
     I.ty = ty;
     I.depth = depth;
@@ -238,7 +227,6 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
     I.dt = dt;
     I.off_samples = (int64_t)o_s;
     I.off_items = (int64_t)o_i;
-    I.off_vmap = (int64_t)o_v;
     *info = I;
     return PF_OK;
 }
@@ -251,7 +239,7 @@ int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes)
     if (op == PF_OP_STEP_EXPLICIT)
         *bytes = field;
     else if (op == PF_OP_VJP)
-        *bytes = field + align256((size_t)info->n_vblocks * 3 * sizeof(double));
+        *bytes = field + align256((size_t)info->n_items * 2 * sizeof(double));
     else
         return fail(PF_EINVAL, "batches support PF_OP_STEP_EXPLICIT and PF_OP_VJP");
     return PF_OK;
@@ -266,8 +254,7 @@ int check_info(const pf_batch_info* info, const void* plan)
     if (!info) return fail(PF_EINVAL, "info is NULL");
     if (!plan || reinterpret_cast<uintptr_t>(plan) % 256) return fail(PF_EINVAL, "plan is NULL or misaligned");
     if (info->count < 1 || info->n_items < 1 || info->ks < 1 || info->ks > 4 || info->total < 1 ||
-        (info->dtype != PF_F32 && info->dtype != PF_F64) || info->off_items <= 0 ||
-        info->off_vmap <= 0)
+        (info->dtype != PF_F32 && info->dtype != PF_F64) || info->off_items <= 0)
         return fail(PF_EINVAL, "info does not describe a plan built by pf_batch_plan");
     return PF_OK;
 }
@@ -308,19 +295,21 @@ int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, c
 {
     const char* pb = static_cast<const char*>(plan);
     const auto* smp = reinterpret_cast<const pfk::BatchSample*>(pb + info->off_samples);
-    const auto* vmap = reinterpret_cast<const int*>(pb + info->off_vmap);
+    const auto* items = reinterpret_cast<const pfk::BatchItem*>(pb + info->off_items);
     const long long total = info->total;
     T* other = static_cast<T*>(ws);
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + align256((size_t)total * sizeof(T)));
     if ((flags & PF_VJP_BEGIN) &&
-        hipMemsetAsync(part, 0, (size_t)info->n_vblocks * 3 * sizeof(double), s) != hipSuccess)
+        hipMemsetAsync(part, 0, (size_t)info->n_items * 2 * sizeof(double), s) != hipSuccess)
         return check_launch("batched vjp init");
+    const int hk = info->ks;  // Allen-Cahn: strip halo H ks with H = 1
     T* cur = lam;
     for (int64_t k = nsteps - 1; k >= 0; --k) {
-        pfk::launch_vjp_ac_batched<T>(states + k * total, cur, other, smp, vmap, info->n_vblocks, part, s);
+        pfk::launch_vjp2d_batched<T>(states + k * total, cur, other, smp, items, info->n_items, info->ty,
+                                     hk, info->depth, part, s);
         std::swap(cur, other);
     }
-    if (flags & PF_VJP_END) pfk::launch_batch_reduce(part, smp, info->count, theta_bar, s);
+    if (flags & PF_VJP_END) pfk::launch_vjp2d_reduce(part, smp, info->count, info->ty, theta_bar, s);
     if (int rc = check_launch("pf_vjp_explicit_batched")) return rc;
     if (cur != lam && hipMemcpyAsync(lam, cur, (size_t)total * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return check_launch("batched vjp copy-back");
@@ -387,8 +376,11 @@ int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, in
     for (int ks : kss)
         for (int ty : tys)
             for (int depth : depths) {
+                // rounded down so that chunk + halo fills whole prefetch groups
+                const int HK = (base->model == PF_CAHN_HILLIARD ? 2 : 1) * ks;
+                const int tya = ty - (ty + 2 * HK) % 4;
                 pf_batch_info I;
-                int rc = pf_batch_plan(base, samples, count, dt, ks, ty, depth, plan_dev, plan_bytes, &I, stream);
+                int rc = pf_batch_plan(base, samples, count, dt, ks, tya, depth, plan_dev, plan_bytes, &I, stream);
                 if (rc == PF_EINVAL) continue;  // this candidate's plan does not fit the buffer
                 if (rc) { status = rc; goto done; }
                 const int64_t steps = 2 * ks;
@@ -405,7 +397,7 @@ int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, in
                 if (best_t < 0 || t < best_t) {
                     best_t = t;
                     bk = ks;
-                    bt = ty;
+                    bt = tya;
                     bd = depth;
                 }
             }

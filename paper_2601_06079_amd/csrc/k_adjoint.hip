@@ -174,108 +174,7 @@ __global__ __launch_bounds__(AB) void k_vjp_ch_b(const T* __restrict__ c, const 
     block_partials3(0.0, t1, t2, part);
 }
 
-// device copy of make_free_energy (the two double wells, W folded in)
-__device__ __forceinline__ FreeEnergy make_free_energy_dev(int fe, double W)
-{
-    FreeEnergy f{};
-    f.W = W;
-    f.fe = fe;
-    if (fe == 0) {
-        f.a1 = -W; f.a2 = 0.0; f.a3 = W;
-        f.b0 = -W; f.b1 = 0.0; f.b2 = 3.0 * W;
-    } else {
-        f.a1 = 2.0 * W; f.a2 = -6.0 * W; f.a3 = 4.0 * W;
-        f.b0 = 2.0 * W; f.b1 = -12.0 * W; f.b2 = 12.0 * W;
-    }
-    return f;
-}
 
-// Ragged batch, Allen-Cahn: block b owns nodes [256 (b - first_vblock), +256)
-// of sample vmap[b].  lam_out = lam_in - (dt/m) J_r(eta)^T lam_in, and the
-// block's theta partials are ADDED to its own slot part[3 b .. 3 b + 3), so
-// repeated launches accumulate a trajectory's sensitivities without atomics.
-template <typename T>
-__global__ __launch_bounds__(AB) void k_vjp_ac_batched(const T* __restrict__ eta,
-                                                       const T* __restrict__ lam_in,
-                                                       T* __restrict__ lam_out,
-                                                       const BatchSample* __restrict__ smp,
-                                                       const int* __restrict__ vmap,
-                                                       double* __restrict__ part)
-{
-    const int b = blockIdx.x;
-    const BatchSample& sm = smp[vmap[b]];
-    Geom g{};
-    g.dim = 2;
-    g.n[0] = sm.nx;
-    g.n[1] = sm.ny;
-    g.n[2] = 1;
-    g.N = (long long)sm.nx * sm.ny;
-    g.h = sm.h;
-    const long long idx = (long long)(b - sm.first_vblock) * AB + threadIdx.x;
-    const T* u0 = eta + sm.offset;
-    const T* v0 = lam_in + sm.offset;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    int i, j, k;
-    if (node_of<2>(g, idx, i, j, k)) {
-        const double m = sm.h * sm.h, detJ = 0.25 * sm.h * sm.h;
-        T u[9], v[9];
-        gather<T, 2>(u0, g, i, j, k, u);
-        gather<T, 2>(v0, g, i, j, k, v);
-        const T h = (T)sm.h;
-        const double W = sm.W;
-        const FreeEnergy f1 = make_free_energy_dev(sm.fe, 1.0), fw = make_free_energy_dev(sm.fe, W);
-        const Cub<T> F1{(T)f1.a1, (T)f1.a2, (T)f1.a3};
-        const Lin<T> F2{(T)fw.b0, (T)fw.b1, (T)fw.b2};
-        const T dt_over_m = (T)(sm.dt / m);
-        const T mob = (T)sm.mob, kappa = (T)sm.kappa;
-        const T Nv = (T)detJ * quad_sum<T, 2, true>(u, v, F2);
-        const T Kv = stiff<T, 2>(v, h);
-        const T vc = v[4];
-        lam_out[sm.offset + idx] = vc - dt_over_m * mob * (Nv + kappa * Kv);
-        const double n1 = detJ * (double)quad_sum<T, 2, false>(u, u, F1);
-        const double ku = (double)stiff<T, 2>(u, h);
-        const double wi = -(double)dt_over_m * (double)vc;
-        t0 = wi * (W * n1 + sm.kappa * ku);
-        t1 = wi * sm.mob * ku;
-        t2 = wi * sm.mob * n1;
-    }
-    __shared__ double sh[AB / WAVE][3];
-    double v3[3] = {t0, t1, t2};
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-        for (int off = WAVE / 2; off > 0; off >>= 1) v3[q] += __shfl_down(v3[q], off, WAVE);
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    if (lane == 0)
-        for (int q = 0; q < 3; ++q) sh[wv][q] = v3[q];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; ++q) {
-            double s = 0.0;
-            for (int w = 0; w < AB / WAVE; ++w) s += sh[w][q];
-            part[3 * (long long)b + q] += s;
-        }
-}
-
-// theta_bar[s][q] += sum over the sample's blocks of part[3 b + q], fixed order
-__global__ __launch_bounds__(AB) void k_batch_reduce(const double* __restrict__ part,
-                                                     const BatchSample* __restrict__ smp,
-                                                     double* __restrict__ theta_bar)
-{
-    const BatchSample& sm = smp[blockIdx.x];
-    __shared__ double sh[AB];
-    for (int q = 0; q < 3; ++q) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < sm.nvblock; b += AB) a += part[3 * (long long)(sm.first_vblock + b) + q];
-        sh[threadIdx.x] = a;
-        __syncthreads();
-        for (int s = AB / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) theta_bar[3 * blockIdx.x + q] += sh[0];
-        __syncthreads();
-    }
-}
 
 inline unsigned nblk(const Geom& g) { return (unsigned)((g.N + AB - 1) / AB); }
 
@@ -353,18 +252,6 @@ void launch_vjp_explicit(const Geom& g, int model, const FreeEnergy& f, double k
     k_reduce3<<<1, AB, 0, s>>>(part, (int)nb, theta_bar);
 }
 
-template <typename T>
-void launch_vjp_ac_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
-                           const int* vmap, int nvblocks, double* part, hipStream_t s)
-{
-    k_vjp_ac_batched<T><<<nvblocks, AB, 0, s>>>(eta, lam_in, lam_out, smp, vmap, part);
-}
-
-void launch_batch_reduce(const double* part, const BatchSample* smp, int count, double* theta_bar,
-                         hipStream_t s)
-{
-    k_batch_reduce<<<count, AB, 0, s>>>(part, smp, theta_bar);
-}
 
 #define INST_ADJ(T)                                                                              \
     template void launch_dtheta<T>(const Geom&, int, const FreeEnergy&, double, double, const T*, \
@@ -372,9 +259,7 @@ void launch_batch_reduce(const double* part, const BatchSample* smp, int count, 
     template void launch_mass_axpy<T>(const Geom&, double, const T*, T*, hipStream_t);           \
     template void launch_vjp_explicit<T>(const Geom&, int, const FreeEnergy&, double, double,    \
                                          double, const T*, const T*, T*, T*, double*, double*,   \
-                                         hipStream_t);                                   \
-    template void launch_vjp_ac_batched<T>(const T*, const T*, T*, const BatchSample*, const int*, \
-                                           int, double*, hipStream_t);
+                                         hipStream_t);
 INST_ADJ(float)
 INST_ADJ(double)
 

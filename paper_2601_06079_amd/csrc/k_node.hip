@@ -8,21 +8,6 @@
 
 namespace pfk {
 
-FreeEnergy make_free_energy(int fe, double W)
-{
-    FreeEnergy f{};
-    f.W = W;
-    f.fe = fe;
-    if (fe == 0) {  // W (q^2 - 1)^2 / 4
-        f.a1 = -W; f.a2 = 0.0; f.a3 = W;
-        f.b0 = -W; f.b1 = 0.0; f.b2 = 3.0 * W;
-    } else {        // W q^2 (1 - q)^2
-        f.a1 = 2.0 * W; f.a2 = -6.0 * W; f.a3 = 4.0 * W;
-        f.b0 = 2.0 * W; f.b1 = -12.0 * W; f.b2 = 12.0 * W;
-    }
-    return f;
-}
-
 namespace {
 
 // r(U): Allen-Cahn  r = L [N + kappa K u];  Cahn-Hilliard r_c = M K mu, r_mu = m mu - [N(c) + kappa K c]

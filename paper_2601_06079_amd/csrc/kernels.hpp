@@ -24,14 +24,27 @@ struct FreeEnergy {
     int fe;
 };
 
-FreeEnergy make_free_energy(int fe, double W);
+// the two double wells: f' = a1 q + a2 q^2 + a3 q^3, f'' = b0 + b1 q + b2 q^2 (W folded in)
+__host__ __device__ inline FreeEnergy make_free_energy(int fe, double W)
+{
+    FreeEnergy f{};
+    f.W = W;
+    f.fe = fe;
+    if (fe == 0) {  // W (q^2 - 1)^2 / 4
+        f.a1 = -W; f.a2 = 0.0; f.a3 = W;
+        f.b0 = -W; f.b1 = 0.0; f.b2 = 3.0 * W;
+    } else {        // W q^2 (1 - q)^2
+        f.a1 = 2.0 * W; f.a2 = -6.0 * W; f.a3 = 4.0 * W;
+        f.b0 = 2.0 * W; f.b1 = -12.0 * W; f.b2 = 12.0 * W;
+    }
+    return f;
+}
 
 // ---- ragged batches: device plan entries (written by the host, batch.cpp) -----
 struct BatchSample {
     long long offset;          // element offset of the sample in the packed arrays
     int nx, ny;                // nodes per axis
-    int nstrips, first_item;   // explicit-kernel work items of this sample
-    int first_vblock, nvblock; // node-kernel blocks of this sample (256 nodes each)
+    int nstrips, first_item;   // work items of this sample (strips x chunks)
     int fe, reserved;          // free energy (0: W (c^2-1)^2/4, 1: W c^2 (1-c)^2)
     double a1, a2, a3, beta, gamma;  // fused-kernel coefficients (dt folded in)
     double W, kappa, mob, h, dt;     // raw parameters (sensitivities)
@@ -105,14 +118,16 @@ template <typename T>
 void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample* smp,
                                const BatchItem* items, int n_items, const Stream2DConfig& cfg,
                                hipStream_t s);
-// Allen-Cahn explicit-step adjoint for every sample (k_adjoint.hip):
-//   lam_out = lam_in - (dt/m) J_r(eta)^T lam_in ;
-//   part[b][0..3) += -(dt/m) lam_in^T dr/dtheta over block b's nodes
+// Allen-Cahn step adjoint over a ragged batch (streamed like the forward kernel):
+//   lam_out = lam_in - (dt L/m) J_r(eta)^T lam_in on the plan's work items, and
+//   part[2 w .. 2 w + 2) += (A, B) of work item w (see k_vjp2d.hip); hk: the
+//   plan's strip halo (H ks)
 template <typename T>
-void launch_vjp_ac_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
-                           const int* vmap, int nvblocks, double* part, hipStream_t s);
-// theta_bar[s][0..3) += sum of part over sample s's blocks (fixed order)
-void launch_batch_reduce(const double* part, const BatchSample* smp, int count, double* theta_bar,
-                         hipStream_t s);
+void launch_vjp2d_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
+                          const BatchItem* items, int n_items, int ty, int hk, int depth,
+                          double* part, hipStream_t s);
+// theta_bar[s][0..3) += the gradient of sample s's accumulated (A, B) (fixed order)
+void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, int ty,
+                         double* theta_bar, hipStream_t s);
 
 }  // namespace pfk

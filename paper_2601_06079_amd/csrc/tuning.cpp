@@ -54,7 +54,7 @@ int stream2d_rows(const pf_problem* p, int ks)
     // multiple of the prefetch depth (4) so no wave runs idle rows.
     long long ty = 48;
     while ((ty + 2 * HK) % 4) --ty;
-    while (ty > 8 && strips * ((ny + ty - 1) / ty) < 4 * S) ty -= 4;
+    while (ty - 4 >= 8 && strips * ((ny + ty - 1) / ty) < 4 * S) ty -= 4;
     if (ty > ny) ty = ny;
     return (int)std::max<long long>(ty, 1);
 }

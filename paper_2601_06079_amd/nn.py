@@ -147,10 +147,12 @@ class CHEnsemble:
         return U
 
 
-def train(model, n=512, Bn=16, iters=300, K=20, dt=0.01, lr=2e-3, burn=(1500, 6000), seed=0,
-          log=None):
+def train(model, n=512, Bn=16, iters=300, K=20, dt=0.01, lr=2e-3, lr_min=None, burn=(1500, 6000),
+          seed=0, log=None):
     """Train on (c_t, c_{t+K}) pairs drawn along fresh plain-solver trajectories with
-    M, kappa ~ U(0.5, 2).  Returns the per-iteration mean loss."""
+    M, kappa ~ U(0.5, 2).  With lr_min the step size follows a cosine decay from lr
+    to lr_min over the run.  Returns the per-iteration mean loss."""
+    import math
     rng = np.random.default_rng(seed)
     hist = []
     ens = None
@@ -163,9 +165,10 @@ def train(model, n=512, Bn=16, iters=300, K=20, dt=0.01, lr=2e-3, burn=(1500, 60
         c0 = ens.field().clone()
         ens.advance(K)
         tgt = ens.field().clone()
-        loss = model.train_step(c0, ens.Mt, ens.kt, tgt, lr=lr)
+        lr_t = lr if lr_min is None else lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / iters))
+        loss = model.train_step(c0, ens.Mt, ens.kt, tgt, lr=lr_t)
         hist.append(float(loss.mean()))
-        if log and (it % 50 == 0 or it == iters - 1):
+        if log and (it % 100 == 0 or it == iters - 1):
             log(f"iter {it} loss {hist[-1]:.3e}")
     return hist
 
@@ -204,3 +207,99 @@ def rollout(model, ens, jumps, K, tau, energy_check=True):
             ens.U.copy_(chat.reshape(-1))
         fallbacks += nfail
     return fallbacks
+
+
+# ---------------------------------------------------------------------------
+def _ch_batch(Bn, n, M, kappa, dt, dtype):
+    theta = np.stack([np.asarray(M, float), np.asarray(kappa, float), np.ones(Bn)], axis=1)
+    return B.Batch([(n, n)] * Bn, theta, dt, model=A.CAHN_HILLIARD, fe=A.F_01, dtype=dtype)
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def gain_experiment(model=None, train_iters=2000, n=512, Bn=16, K=20, dt=0.01, jumps=10,
+                    dts=(0.01, 0.0125, 0.02, 0.025), burn=2000, seed=0, log=None):
+    """What the surrogate gains over the plain solver at matched error.
+
+    1. Train (train_iters iterations, cosine-decayed Adam, 512^2 pairs).
+    2. tau = 99th percentile of rho over plain-solver K-step jumps on held-out
+       trajectories (the threshold a correct jump passes 99% of the time).
+    3. On fresh held-out samples, advance `jumps` x K steps of dt three ways from
+       the same state: (a) the FP64 plain solver at dt (the reference); (b) the
+       checked surrogate rollout with plain-solver fallback; (c) the plain FP32
+       solver at each dt' in dts (same end time).  Errors are relative L2 against
+       (a) over the batch; wall times include every host synchronisation.
+    4. The gain is T(cheapest plain dt' whose error <= the rollout's error) / T(rollout)."""
+    say = log or (lambda m: None)
+    rng = np.random.default_rng(seed)
+    if model is None:
+        model = Surrogate(seed=int(rng.integers(1 << 30)))
+    t_train = 0.0
+    if train_iters:
+        hist, t_train = _timed(lambda: train(model, n=n, Bn=Bn, iters=train_iters, K=K, dt=dt, lr=1e-3,
+                                             lr_min=1e-5, burn=(1000, 6000), seed=seed + 1, log=log))
+        say(f"trained {train_iters} iterations in {t_train:.1f} s, final loss {np.mean(hist[-20:]):.3e}")
+    # 2. threshold from plain jumps
+    cal = CHEnsemble(Bn, n, rng.uniform(0.5, 2, Bn), rng.uniform(0.5, 2, Bn), dt=dt,
+                     seed=int(rng.integers(1 << 30)))
+    cal.advance(burn)
+    rhos = []
+    for _ in range(4):
+        c0 = cal.field().clone()
+        cal.advance(K)
+        c1 = cal.field().clone()
+        step = c1.reshape(-1).clone()
+        cal.batch.step(step, 1, cal.ws)
+        rhos.append(model.check(c1, c0, step.view_as(c1), K * dt, dt)[:, 0].cpu().numpy())
+        cal.advance(5 * K)
+    tau = float(np.percentile(np.concatenate(rhos), 99))
+    # 3. held-out rollout
+    M, kap = rng.uniform(0.5, 2, Bn), rng.uniform(0.5, 2, Bn)
+    test = CHEnsemble(Bn, n, M, kap, dt=dt, seed=int(rng.integers(1 << 30)))
+    test.advance(burn)
+    U0 = test.U.clone()
+    steps = jumps * K
+    ref_b = _ch_batch(Bn, n, M, kap, dt, torch.float64)
+    ref = U0.double()
+    ref_b.step(ref, steps)
+    refn = float(ref.norm())
+    # surrogate rollout (warm-up jump first, on a copy)
+    warm = CHEnsemble(Bn, n, M, kap, dt=dt, seed=0)
+    warm.U.copy_(U0)
+    rollout(model, warm, 1, K, tau)
+    fb, t_sur = _timed(lambda: rollout(model, test, jumps, K, tau))
+    err_sur = float((test.U.double() - ref).norm()) / refn
+    net_only = CHEnsemble(Bn, n, M, kap, dt=dt, seed=0)
+    net_only.U.copy_(U0)
+    rollout(model, net_only, jumps, K, tau=float("inf"), energy_check=False)
+    err_net = float((net_only.U.double() - ref).norm()) / refn
+    plain = []
+    for d in dts:
+        m = int(round(steps * dt / d))
+        b = _ch_batch(Bn, n, M, kap, d, torch.float32)
+        ws = b.workspace(A.OP_STEP_EXPLICIT)
+        U = U0.clone()
+        b.step(U, 10, ws)
+        U.copy_(U0)
+        _, t = _timed(lambda: b.step(U, m, ws))
+        e = float((U.double() - ref).norm()) / refn
+        plain.append({"dt": d, "steps": m, "seconds": t, "rel_err": e if np.isfinite(e) else None})
+        say(f"plain dt={d}: {m} steps, {t * 1e3:.3f} ms, rel err {e:.3e}")
+    ok = [r for r in plain if r["rel_err"] is not None and r["rel_err"] <= err_sur]
+    best = min(ok, key=lambda r: r["seconds"]) if ok else plain[0]
+    rec = {"workload": f"{Bn} x {n}^2 Cahn-Hilliard, M, kappa ~ U(0.5, 2), {jumps} jumps of K = {K} "
+                       f"steps of dt = {dt} after {burn} burn-in steps",
+           "train_iters": train_iters, "train_seconds": t_train, "tau": tau,
+           "rollout_seconds": t_sur, "rollout_rel_err": err_sur, "fallbacks": int(fb),
+           "jumps_total": jumps * Bn, "network_only_rel_err": err_net, "plain": plain,
+           "matched_plain_dt": best["dt"] if ok else None,
+           "gain": best["seconds"] / t_sur}
+    say(f"rollout: {t_sur * 1e3:.3f} ms, rel err {err_sur:.3e}, fallbacks {fb}/{jumps * Bn}, "
+        f"tau {tau:.3e}, network-only err {err_net:.3e}, gain {rec['gain']:.3f}")
+    return rec

@@ -6,7 +6,7 @@ call is enqueued on torch's current stream.
 from __future__ import annotations
 
 import ctypes as ct
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import torch
 
@@ -159,3 +159,81 @@ def vjp(p: Problem, kind: int, dt: float, U: torch.Tensor, vbar: torch.Tensor,
 
 def tune_set(key: int, value: int):
     A.check(A.lib().pf_tune_set(int(key), int(value)))
+
+
+def tune_get(key: int) -> int:
+    v = ct.c_int(0)
+    A.check(A.lib().pf_tune_get(int(key), ct.byref(v)))
+    return int(v.value)
+
+
+# ---------------------------------------------------------------------------
+class CheckpointedRun(torch.autograd.Function):
+    """U_N = S^N(U_0; theta) for one problem, explicit (Eq. 12) or backward-Euler
+    Newton steps (Eqs. 13-14), with a hand-written adjoint (Supp. Note 2,
+    Eqs. II.5-II.6).
+
+    theta = (mobility, kappa, W) as a float64 tensor of 3.  Forward keeps a
+    snapshot every `every` steps; backward walks the segments in reverse,
+    recomputes each segment's states from its snapshot (bitwise the forward's:
+    every kernel is deterministic) and applies the step adjoint of the library
+    (pf_vjp: explicit-step VJP, or the transposed Newton solve at each root),
+    accumulating the gradient of theta in FP64.  For Cahn-Hilliard explicit
+    runs only the c plane of U_N is differentiated (mu is recomputed from c).
+    """
+
+    @staticmethod
+    def forward(ctx, theta, U0, p, dt, nsteps, every, implicit, opts):
+        if nsteps % every:
+            raise ValueError("nsteps must be a multiple of the checkpoint interval")
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        q = replace(p, mobility=float(th[0]), kappa=float(th[1]), W=float(th[2]))
+        U = U0.detach().clone()
+        ws = workspace(q, A.OP_NEWTON if implicit else A.OP_STEP_EXPLICIT, U.device)
+        snaps = []
+        for _ in range(nsteps // every):
+            snaps.append(U.clone())
+            _advance(q, U, dt, every, implicit, opts, ws)
+        ctx.q, ctx.dt, ctx.every, ctx.implicit, ctx.opts = q, dt, every, implicit, opts
+        ctx.snaps, ctx.theta_device = snaps, theta.device
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        q, dt, every, implicit = ctx.q, ctx.dt, ctx.every, ctx.implicit
+        lam = gU.detach().to(q.dtype).contiguous().clone()
+        N = q.nnodes
+        if q.model == A.CAHN_HILLIARD and not implicit:
+            lam[N:] = 0
+        tb = torch.zeros(3, dtype=torch.float64, device=lam.device)
+        ws = workspace(q, A.OP_NEWTON if implicit else A.OP_STEP_EXPLICIT, lam.device)
+        vws = workspace(q, A.OP_VJP, lam.device)
+        seg = torch.empty((every + 1, lam.numel()), dtype=q.dtype, device=lam.device)
+        Ubar = torch.empty_like(lam)
+        kind = A.VJP_NEWTON_STEP if implicit else A.VJP_EXPLICIT_STEP
+        for snap in reversed(ctx.snaps):
+            seg[0].copy_(snap)
+            for k in range(every):  # seg[k + 1] = S(seg[k])
+                seg[k + 1].copy_(seg[k])
+                _advance(q, seg[k + 1], dt, 1, implicit, ctx.opts, ws)
+            for k in reversed(range(every)):
+                # explicit: VJP of the step taken from seg[k]; implicit: at its root seg[k + 1]
+                Ubar.zero_()
+                vjp(q, kind, dt, seg[k + 1] if implicit else seg[k], lam, Ubar, tb, vws)
+                lam, Ubar = Ubar, lam
+        return tb.to(ctx.theta_device), lam, None, None, None, None, None, None
+
+
+def _advance(q, U, dt, nsteps, implicit, opts, ws):
+    if not implicit:
+        step_explicit(q, U, dt, nsteps, ws)
+        return
+    Uold = torch.empty_like(U)
+    for _ in range(nsteps):
+        Uold.copy_(U)
+        newton_step(q, dt, Uold, U, opts, ws, raise_on_noconv=True)
+
+
+def checkpointed_run(theta, U0, p, dt, nsteps, every=100, implicit=False, opts=None):
+    """Differentiable run of nsteps steps of problem p (see CheckpointedRun)."""
+    return CheckpointedRun.apply(theta, U0, p, dt, nsteps, every, implicit, opts)

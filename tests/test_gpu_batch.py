@@ -78,6 +78,37 @@ def test_batched_vjp_matches_oracle_adjoint():
         assert rel_l2(host(b.views(U0.grad)[i]), ub) < 1e-10
 
 
+def test_batched_vjp_independent_of_plan_shape():
+    """The adjoint streams over whatever plan it is given: a fused plan (ks = 2,
+    narrower strips, other chunks) gives bitwise the same lam as the single-step
+    plan, and theta_bar to FP64 rounding (its slot sums run in another order)."""
+    import ctypes as ct
+    sizes = [(70, 50), (33, 90), (128, 64), (9, 200)]
+    theta = np.array([[1.2, 0.8, 1.3], [0.6, 1.7, 0.9], [1.9, 0.5, 1.6], [1.0, 1.1, 0.7]])
+    b = _batch(sizes, theta, F64, ks=2, ty=13)
+    rng = np.random.default_rng(8)
+    nsteps = 5
+    states = torch.as_tensor(rng.uniform(-0.8, 0.8, (nsteps, b.total)), dtype=F64, device="cuda")
+    lam0 = torch.as_tensor(rng.standard_normal(b.total), dtype=F64, device="cuda")
+    out = []
+    for info, plan in ((b.info, b.plan), (b.info1, b.plan1)):
+        assert info.ks == (2 if plan is b.plan else 1)
+        nb = ct.c_size_t(0)
+        A.check(b.L.pf_batch_workspace_size(ct.byref(info), A.OP_VJP, ct.byref(nb)))
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        lam = lam0.clone()
+        tb = torch.zeros(b.count * 3, dtype=F64, device="cuda")
+        A.check(b.L.pf_vjp_explicit_batched(ct.byref(info), ct.c_void_p(plan.data_ptr()), nsteps,
+                                            ct.c_void_p(states.data_ptr()), ct.c_void_p(lam.data_ptr()),
+                                            ct.c_void_p(tb.data_ptr()), ct.c_void_p(ws.data_ptr()),
+                                            A.VJP_BEGIN | A.VJP_END,
+                                            ct.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        out.append((lam, tb))
+    for (nx, ny), o in zip(sizes, b.offsets):
+        assert torch.equal(out[0][0][o:o + nx * ny], out[1][0][o:o + nx * ny])
+    np.testing.assert_allclose(host(out[0][1]), host(out[1][1]), rtol=1e-12, atol=1e-14)
+
+
 def test_checkpointed_adjoint_bitwise_equals_stored_trajectory():
     sizes = [(64, 48), (33, 70)]
     theta = np.array([[1.0, 1.1, 0.9], [1.3, 0.7, 1.2]])
@@ -103,7 +134,13 @@ def _c4_batch(dtype, count=64, nsteps=2000):
 def test_calibration_workload_adjoint_vs_central_fd_fp64():
     """64 ragged Allen-Cahn samples 128^2..512^2, 2000 steps, checkpoint every 100:
     FP64 adjoint gradient vs central differences (eps = 1e-6 theta), all samples
-    perturbed together (they are independent)."""
+    perturbed together (they are independent).
+
+    The 2000-step coarsening run is very sensitive to kappa and W: for a few samples
+    the O(eps^2) truncation error of the eps = 1e-6 central difference alone exceeds
+    1e-4 (it falls 100x per 10x smaller eps, i.e. it is truncation, not adjoint
+    error).  One Richardson step with eps/2 cancels the eps^2 term; that
+    extrapolated difference is held to 1e-4 and the plain one to 1e-3."""
     announce("C4 adjoint vs FD fp64")
     b, sizes, theta, hidden, fields = _c4_batch(F64)
     nsteps, every = 2000, 100
@@ -123,14 +160,23 @@ def test_calibration_workload_adjoint_vs_central_fd_fp64():
         bb.step(U, nsteps)
         return np.array([float(((u - t) ** 2).mean()) for u, t in zip(bb.views(U), bb.views(tgt))])
 
-    for k in range(3):
-        eps = 1e-6 * theta[:, k]
+    def central(k, eps):
         tp, tm = theta.copy(), theta.copy()
         tp[:, k] += eps
         tm[:, k] -= eps
-        fd = (per_sample_losses(tp) - per_sample_losses(tm)) / (2 * eps)
-        rel = np.abs(g[:, k] - fd) / np.maximum(np.abs(fd), 1e-300)
-        assert np.max(rel) < 1e-4, (k, np.max(rel))
+        return (per_sample_losses(tp) - per_sample_losses(tm)) / (2 * eps)
+
+    for k in range(3):
+        eps = 1e-6 * theta[:, k]
+        fd1 = central(k, eps)
+        fd2 = central(k, eps / 2)
+        fdr = (4 * fd2 - fd1) / 3
+        rel1 = np.abs(g[:, k] - fd1) / np.abs(fd1)
+        relr = np.abs(g[:, k] - fdr) / np.abs(fdr)
+        print(f"[c4] theta_{k}: max rel vs central(1e-6) {rel1.max():.2e}, "
+              f"vs Richardson {relr.max():.2e}", flush=True)
+        assert np.max(relr) < 1e-4, (k, np.max(relr))
+        assert np.max(rel1) < 1e-3, (k, np.max(rel1))
 
 
 def test_calibration_workload_fp32_gradient_reported():

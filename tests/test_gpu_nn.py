@@ -31,8 +31,77 @@ def _params(seed):
     return NN.init_params(seed, out_scale=1.0).astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("shape", [(2, 8, 32), (1, 13, 64), (3, 4, 96)])
+def _dyadic(seed, Bn, H, W):
+    """Inputs and weights on coarse power-of-two grids, so that every sum either side
+    forms is exact in FP32 whatever its order (checked by _exact_bound), and every
+    hidden activation is a multiple of 1/16 that bf16 rounds the same way on both
+    sides.  c in {0, 1/4, ..., 1}; M, kappa in {1/2, 1, 3/2, 2}; W1 in {0, +-1/4};
+    W2, W3 sparse in {0, +-1}; W4 sparse in {0, +-2^-10}; biases in (1/16) Z."""
+    r = np.random.default_rng(seed)
+    c = r.integers(0, 5, (Bn, H, W)) / 4.0
+    M = r.integers(1, 5, Bn) / 2.0
+    k = r.integers(1, 5, Bn) / 2.0
+    parts = []
+    for name, shp in NN.LAYOUT:
+        n = int(np.prod(shp))
+        if name == "W1":
+            v = r.integers(-1, 2, n) / 4.0
+        elif name in ("W2", "W3"):
+            v = r.choice([-1.0, 0.0, 1.0], n, p=[1 / 32, 15 / 16, 1 / 32])
+        elif name == "W4":
+            v = r.choice([-1.0, 0.0, 1.0], n, p=[1 / 16, 7 / 8, 1 / 16]) * 2.0 ** -10
+        elif name == "b4":
+            v = np.zeros(n)
+        else:
+            v = r.integers(-8, 9, n) / 16.0
+        parts.append(v)
+    return c, M, k, np.concatenate(parts)
+
+
+def _exact_bound(p):
+    """Largest (sum of |terms|) / (grid of the terms) over the four layers: below 2^24
+    every partial sum is a multiple of the grid that FP32 holds exactly."""
+    off, blocks = 0, {}
+    for name, shp in NN.LAYOUT:
+        n = int(np.prod(shp))
+        blocks[name] = p[off:off + n].reshape(shp)
+        off += n
+    amax = np.array([1.0, 2.0, 2.0])  # max |a0| per input channel (c, M, kappa)
+    grid, worst = 0.25, 0.0           # grid of a0 (c: 1/4; M, kappa: 1/2)
+    for l, wgrid in ((1, 0.25), (2, 1.0), (3, 1.0), (4, 2.0 ** -10)):
+        w = np.abs(blocks[f"W{l}"]).reshape(9, -1, blocks[f"W{l}"].shape[-1])
+        b = np.abs(blocks[f"b{l}"])
+        s = np.einsum("tic,i->c", w, amax) + b
+        grid = min(grid * wgrid, 1.0 / 16 if l < 4 else grid * wgrid)
+        worst = max(worst, float(s.max()) / grid)
+        amax = np.full(32, float(s.max()) * (1 + 2.0 ** -8))  # bf16 rounding may round up
+    return worst
+
+
+@pytest.mark.parametrize("shape", [(2, 8, 64), (1, 5, 32), (3, 4, 96), (1, 13, 160)])
+def test_forward_exact_dyadic(shape):
+    """Exact arithmetic on both sides: the GPU forward equals the oracle's up to the
+    final FP32 rounding of c_hat (pins every tap, channel and tile index)."""
+    announce("nn forward exact", shape)
+    Bn, H, W = shape
+    c, M, k, p = _dyadic(11 + H, Bn, H, W)
+    assert _exact_bound(p) < 2.0 ** 24
+    model = NN.Surrogate(params=p)
+    got = host(model.forward(_dev(c.astype(np.float32)), _dev(M.astype(np.float32)),
+                             _dev(k.astype(np.float32))))
+    ref, _, _ = O.nn(c, M[:, None, None] * np.ones_like(c), k[:, None, None] * np.ones_like(c),
+                     p, round_bf16=True)
+    d_ref = ref - c
+    assert np.std(d_ref) > 1e-3  # the network is not trivially zero
+    assert np.max(np.abs((got - c) - d_ref)) <= 4e-7 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("shape", [(2, 8, 32), (1, 13, 64), (3, 4, 96), (2, 64, 128)])
 def test_forward_matches_oracle(shape):
+    """Random weights: the two sides sum in different orders, so an activation that
+    lies within FP32 noise of a bf16 rounding boundary can round one ulp apart (one
+    such flip moves d by ~|W4| 2^-8 |a| over up to 7x7 pixels).  The tolerance
+    covers a few flips on a small grid; the exact test above pins the indexing."""
     announce("nn forward", shape)
     Bn, H, W = shape
     c, M, k, _ = _inputs(Bn, H, W, 1)
@@ -41,7 +110,7 @@ def test_forward_matches_oracle(shape):
     got = host(model.forward(_dev(c), _dev(M), _dev(k)))
     ref, _, _ = O.nn(c.astype(np.float64), M[:, None, None].astype(np.float64),
                      k[:, None, None].astype(np.float64), p, round_bf16=True)
-    assert rel_l2(got - c, ref - c) < 1e-3
+    assert rel_l2(got - c, ref - c) < (1e-3 if Bn * H * W >= 8192 else 5e-3)
     # exact mass per sample (the projection), to FP32 rounding of the field
     assert np.max(np.abs(got.mean(axis=(1, 2)) - c.astype(np.float64).mean(axis=(1, 2)))) < 1e-6
 
@@ -62,8 +131,14 @@ def test_backward_matches_oracle(shape):
     off = 0
     for name, shp in NN.LAYOUT:
         n = int(np.prod(shp))
-        err = rel_l2(g[off:off + n], gref[off:off + n])
-        assert err < 5e-3, (name, err)
+        if name == "b4":
+            # c_hat does not depend on the output bias (the mean is subtracted): the
+            # exact gradient is 0 and both sides return rounding noise
+            assert abs(g[off]) <= 1e-6 * np.linalg.norm(gref[off - 288:off])
+            assert abs(gref[off]) <= 1e-12 * np.linalg.norm(gref[off - 288:off])
+        else:
+            err = rel_l2(g[off:off + n], gref[off:off + n])
+            assert err < 5e-3, (name, err)
         off += n
 
 
@@ -127,3 +202,18 @@ def test_forced_fallback_equals_plain_solver_bitwise():
     b.advance(3 * K)
     assert fb == 3 * Bn
     assert torch.equal(a.U, b.U)
+
+
+def test_gain_protocol_small():
+    """The matched-error gain protocol on a small case: its invariants, not its
+    outcome (the full 512^2 figure is a benchmark record)."""
+    announce("nn gain protocol")
+    rec = NN.gain_experiment(train_iters=60, n=128, Bn=4, jumps=3, burn=400, seed=3)
+    assert 0 <= rec["fallbacks"] <= rec["jumps_total"] == 12
+    assert rec["tau"] > 0 and np.isfinite(rec["rollout_rel_err"]) and rec["gain"] > 0
+    p0 = rec["plain"][0]
+    assert p0["dt"] == 0.01 and p0["rel_err"] < 1e-4  # FP32 vs the FP64 reference, same dt
+    if rec["fallbacks"] == rec["jumps_total"]:
+        # every jump rejected: the rollout is the plain FP32 solver at dt, bit for bit
+        assert rec["rollout_rel_err"] == p0["rel_err"]
+    assert all(r["rel_err"] is None or r["rel_err"] < 1e-2 for r in rec["plain"])
