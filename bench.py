@@ -199,6 +199,26 @@ def single_step_hbm(n, steps, stream):
             "frac": gbs / HBM_PEAK_GBS, "field_bytes": 4 * n * n}
 
 
+def ac128_record(stream, steps=1000):
+    """The 128^2 periodic Allen-Cahn workload in FP64 (f = (c^2-1)^2/4, kappa = L = 1,
+    dt = 0.1): one call of `steps` explicit steps."""
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    cfg = I.AC128
+    p = S.Problem(n=cfg["n"], model=A.ALLEN_CAHN, fe=A.F_SYM, dtype=torch.float64, W=1.0, kappa=1.0,
+                  mobility=1.0, h=1.0)
+    U = torch.as_tensor(I.initial_state(cfg, seed=0), device="cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    S.step_explicit(p, U.clone(), cfg["dt"], 100, ws)
+    ms = _time_ms(lambda: S.step_explicit(p, U, cfg["dt"], steps, ws), stream)
+    n = p.nnodes
+    return {"workload": "2D Allen-Cahn 128x128 periodic, FP64, explicit dt=0.1", "steps": steps,
+            "ms_per_step": ms / steps, "dof_steps_per_s": n * steps / (ms * 1e-3)}
+
+
 def adjoint_record(stream, count=64, nsteps=2000, every=100):
     """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
     2000 FP32 steps, dt = 0.05): forward with a snapshot every 100 steps plus the
@@ -439,6 +459,7 @@ def main():
     if not args.no_extras:
         out["hbm"] = {"single_step_launch": single_step_hbm(n, 1000, stream),
                       "single_step_launch_16384": single_step_hbm(16384, 40, stream)}
+        out["ac128_fp64"] = ac128_record(stream)
         out["adjoint"] = adjoint_record(stream)
         out["surrogate"] = surrogate_record(stream)
     if not args.no_cpu_baseline:
