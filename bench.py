@@ -110,10 +110,11 @@ def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
     f_scale = nbytes / (max(cf) * 1024) if cf else 1.0
     w_scale = nbytes / (max(cw) * 1024) if cw else 1.0
     import re
-    names = [k for (k, c) in step if "k_explicit2d<" in k]
-    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and "k_explicit2d<" in k]
-    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and "k_explicit2d<" in k]
-    m = re.search(r"k_explicit2d<float, \d+, \d+, (\d+)>", names[0]) if names else None
+    pat = re.compile(r"k_explicit2d<float, \d+, \d+, (\d+)>")
+    names = [k for (k, c) in step if pat.search(k)]
+    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and pat.search(k)]
+    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and pat.search(k)]
+    m = pat.search(names[0]) if names else None
     rec = {"n": n, "ks": int(m.group(1)) if m else None, "kernel_src_sha256_16": kernel_hash(),
            "fetch_kib_raw": kf[0] if kf else None, "write_kib_raw": kw[0] if kw else None,
            "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}

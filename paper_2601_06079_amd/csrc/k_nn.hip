@@ -10,10 +10,12 @@
 //
 // Hidden layers and their input-gradient (dgrad) and weight-gradient (wgrad)
 // products run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
-//   forward/dgrad: a 64-lane wave computes 32 pixels x 32 channels; its
-//     A operand (pixels x input channels of one tap) is read from an LDS tile of
-//     (4+2) rows x (32+2) pixels, its B operand (the weights of that tap) is
-//     held in registers for the whole block.  K = 9 taps x Cin.
+//   forward/dgrad: a block stages an LDS tile of (CR+2) rows x (32+2) pixels;
+//     each of its 4 waves computes CR/4 rows of 32 pixels x 32 channels, its A
+//     operand (pixels x input channels of one tap) read from the tile, its B
+//     operand (the weights of that tap) held in registers for all its rows.
+//     K = 9 taps x Cin.  (CR = 4 measured fastest: 16-row tiles cut weight and
+//     halo traffic but raise register use and lower occupancy.)
 //   wgrad: dW[tap] (Cin x Cout) = sum over pixels of a_in(p + tap) g_out(p)^T,
 //     K = pixels; every block accumulates a fixed stride of pixel tiles in
 //     registers (split-K) and writes one FP32 partial; a second kernel sums the
@@ -38,7 +40,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16;
 
 constexpr int TW = 32;        // pixels per wave row
-constexpr int TR = 4;         // rows per block (one per wave)
+constexpr int TR = 4;         // rows per wgrad tile (one per wave)
+constexpr int CR = 4;         // rows per forward/dgrad tile (CR / 4 per wave)
 constexpr int NBLK = 256;
 
 // fp32 -> bf16 bits, round to nearest even (finite inputs)
@@ -52,27 +55,27 @@ __device__ __forceinline__ float bf16_val(u16 b) { return __uint_as_float((unsig
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// LDS tile: (TR + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by 8 bytes
-template <int CIN>
+// LDS tile: (ROWS + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by 8 bytes
+template <int CIN, int ROWS = TR>
 struct Tile {
     static constexpr int PSTRIDE = CIN * 2 + 8;  // bytes per pixel in LDS
-    static constexpr int BYTES = (TR + 2) * (TW + 2) * PSTRIDE;
+    static constexpr int BYTES = (ROWS + 2) * (TW + 2) * PSTRIDE;
 };
 
-// stage the halo tile of rows y0-1 .. y0+TR, pixels x0-1 .. x0+TW (periodic)
-template <int CIN>
+// stage the halo tile of rows y0-1 .. y0+ROWS, pixels x0-1 .. x0+TW (periodic)
+template <int CIN, int ROWS = TR>
 __device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, int H, int W, int y0,
                                            int x0, unsigned char* lds)
 {
     constexpr int CHUNKS = CIN * 2 / 16;  // 16-byte chunks per pixel
-    constexpr int TOTAL = (TR + 2) * (TW + 2) * CHUNKS;
+    constexpr int TOTAL = (ROWS + 2) * (TW + 2) * CHUNKS;
     for (int t = threadIdx.x; t < TOTAL; t += NBLK) {
         const int ch = t % CHUNKS, pix = t / CHUNKS;
         const int px = pix % (TW + 2), ry = pix / (TW + 2);
         const int gy = wrapi(y0 - 1 + ry, H), gx = wrapi(x0 - 1 + px, W);
         const uint4 v = *reinterpret_cast<const uint4*>(
             act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
-        *reinterpret_cast<uint4*>(lds + (ry * (TW + 2) + px) * Tile<CIN>::PSTRIDE + ch * 16) = v;
+        *reinterpret_cast<uint4*>(lds + (ry * (TW + 2) + px) * Tile<CIN, ROWS>::PSTRIDE + ch * 16) = v;
     }
 }
 
@@ -87,49 +90,53 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
                                                     u16* __restrict__ out, int B, int H, int W)
 {
     constexpr int KS = CIN / 16;
-    __shared__ __align__(16) unsigned char lds[Tile<CIN>::BYTES];
+    constexpr int PS = Tile<CIN, CR>::PSTRIDE;
+    __shared__ __align__(16) unsigned char lds[Tile<CIN, CR>::BYTES];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tiles_x = W / TW, tiles_y = (H + TR - 1) / TR;
+    const int tiles_x = W / TW, tiles_y = (H + CR - 1) / CR;
     int t = blockIdx.x;
     const int tx = t % tiles_x;
     t /= tiles_x;
     const int ty = t % tiles_y;
     const int b = t / tiles_y;
-    const int x0 = tx * TW, y0 = ty * TR;
-    stage_tile<CIN>(in, b, H, W, y0, x0, lds);
-    // this lane's weight fragments for every (tap, k-slice)
+    const int x0 = tx * TW, y0 = ty * CR;
+    stage_tile<CIN, CR>(in, b, H, W, y0, x0, lds);
+    // this lane's weight fragments for every (tap, k-slice), kept for all rows
     bf16x8 bw[9 * KS];
 #pragma unroll
     for (int q = 0; q < 9 * KS; ++q)
         bw[q] = *reinterpret_cast<const bf16x8*>(wfrag + ((size_t)q * 64 + lane) * 8);
     __syncthreads();
-    const int y = y0 + wv;
-    if (y >= H) return;
-    f32x16 acc = {};
     const int m = lane & 31, kh = lane >> 5;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row wv + dy, pixel m + dx
-        const unsigned char* rowp = lds + ((wv + dy) * (TW + 2) + (m + dx)) * Tile<CIN>::PSTRIDE;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
-        }
-    }
     const int co = m;
     const float bco = MODE == 0 ? bias[co] : 0.0f;
+    for (int j = 0; j < CR / 4; ++j) {
+        const int rt = wv + 4 * j;  // tile row of this wave's output row
+        const int y = y0 + rt;
+        if (y >= H) break;          // uniform per wave; later rows are further down
+        f32x16 acc = {};
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
-        const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
-        float v = acc[i];
-        if (MODE == 0) {
-            v = fmaxf(v + bco, 0.0f);
-        } else {
-            v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row rt + dy, pixel m + dx
+            const unsigned char* rowp = lds + ((rt + dy) * (TW + 2) + (m + dx)) * PS;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
+            }
         }
-        out[pidx * 32 + co] = bf16_bits(v);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
+            const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
+            float v = acc[i];
+            if (MODE == 0) {
+                v = fmaxf(v + bco, 0.0f);
+            } else {
+                v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
+            }
+            out[pidx * 32 + co] = bf16_bits(v);
+        }
     }
 }
 
@@ -216,15 +223,25 @@ __global__ __launch_bounds__(NBLK) void k_wgrad_mfma(const u16* __restrict__ ain
     if (wv == 0 && lane < 32) partb[(size_t)blockIdx.x * 32 + lane] = db;
 }
 
-// out[i] = sum over blocks of part[block][i]  (i < n), fixed order
+// out[i] = sum over blocks of part[block][i]  (i < n), fixed order: a block
+// owns 32 columns; its 8 thread groups sum every 8th partial row (coalesced
+// 128-byte row segments), then one fixed 8-way combine.
 __global__ __launch_bounds__(NBLK) void k_sum_partials(const float* __restrict__ part, int nb,
                                                        int n, float* __restrict__ out)
 {
-    const int i = blockIdx.x * NBLK + threadIdx.x;
-    if (i >= n) return;
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + c;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += (double)part[(size_t)b * n + i];
-    out[i] = (float)s;
+    if (i < n)
+        for (int b = grp; b < nb; b += NBLK / 32) s += (double)part[(size_t)b * n + i];
+    __shared__ double sh[NBLK / 32][32];
+    sh[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && i < n) {
+        double t = 0.0;
+        for (int q = 0; q < NBLK / 32; ++q) t += sh[q][c];
+        out[i] = (float)t;
+    }
 }
 
 // a0 = bf16 (c, M, kappa, 0 x 13) per pixel
@@ -408,29 +425,52 @@ __global__ __launch_bounds__(NBLK) void k_out_dgrad(const u16* __restrict__ a3, 
     for (int q = 0; q < 4; ++q) dst[q] = *reinterpret_cast<uint4*>(&outv[8 * q]);
 }
 
-// output layer wgrad: thread t < 288 owns dW4[tap = t / 32][ci = t % 32], thread 288
-// owns db4; block k sums pixels k, k + gridDim.x, ... ; part[block][289]
-constexpr int OWG = 320;
-__global__ __launch_bounds__(OWG) void k_out_wgrad(const u16* __restrict__ a3, const float* __restrict__ g,
-                                                   float* __restrict__ part, int B, int H, int W)
+// output layer wgrad: part[block][tap * 32 + ci] = sum over the block's pixel
+// tiles of a3(p + tap)[ci] g(p), part[block][288] = sum g(p).  Each tile's a3
+// halo and g are staged in LDS; thread t owns output t and (t < 33) t + 256.
+__global__ __launch_bounds__(NBLK) void k_out_wgrad(const u16* __restrict__ a3, const float* __restrict__ g,
+                                                    float* __restrict__ part, int B, int H, int W)
 {
-    const int t = threadIdx.x;
-    const size_t HW = (size_t)H * W, P = (size_t)B * HW;
-    const int tap = t / 32, ci = t % 32;
-    float acc = 0.0f;
-    if (t < 289) {
-        for (size_t p = blockIdx.x; p < P; p += gridDim.x) {
-            const float gp = g[p];
-            if (t == 288) {
-                acc += gp;
-            } else {
-                const int b = (int)(p / HW), r = (int)(p % HW), y = r / W, x = r % W;
-                const int yy = wrapi(y + tap / 3 - 1, H), xx = wrapi(x + tap % 3 - 1, W);
-                acc = fmaf(bf16_val(a3[(((size_t)b * H + yy) * W + xx) * 32 + ci]), gp, acc);
-            }
+    __shared__ __align__(16) unsigned char la[Tile<32>::BYTES];
+    __shared__ float lg[TR * TW];
+    const int tiles_x = W / TW, tiles_y = (H + TR - 1) / TR;
+    const int ntiles = tiles_x * tiles_y * B;
+    const int o0 = threadIdx.x, o1 = threadIdx.x + NBLK;  // o0 < 256: tap 0..7; o1: tap 8 or db4
+    const int dy0 = (o0 / 32) / 3, dx0 = (o0 / 32) % 3, ci0 = o0 % 32;
+    const int ci1 = o1 % 32;
+    float acc0 = 0.0f, acc1 = 0.0f;
+    for (int t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
+        int t = t0;
+        const int tx = t % tiles_x;
+        t /= tiles_x;
+        const int ty = t % tiles_y;
+        const int b = t / tiles_y;
+        const int x0 = tx * TW, y0 = ty * TR;
+        __syncthreads();
+        stage_tile<32>(a3, b, H, W, y0, x0, la);
+        for (int q = threadIdx.x; q < TR * TW; q += NBLK) {
+            const int r = q / TW, px = q % TW;
+            lg[q] = y0 + r < H ? g[((size_t)b * H + y0 + r) * W + x0 + px] : 0.0f;  // rows past H add 0
         }
-        part[(size_t)blockIdx.x * 289 + t] = acc;
+        __syncthreads();
+        // every address below is a per-thread base plus a compile-time offset
+        const unsigned char* b0 = la + (dy0 * (TW + 2) + dx0) * Tile<32>::PSTRIDE + ci0 * 2;
+        const unsigned char* b1 = la + (2 * (TW + 2) + 2) * Tile<32>::PSTRIDE + ci1 * 2;
+#pragma unroll
+        for (int r = 0; r < TR; ++r)
+#pragma unroll
+            for (int px = 0; px < TW; ++px) {
+                const float gp = lg[r * TW + px];
+                const int off = (r * (TW + 2) + px) * Tile<32>::PSTRIDE;
+                acc0 = fmaf(bf16_val(*reinterpret_cast<const u16*>(b0 + off)), gp, acc0);
+                if (o1 < 288)
+                    acc1 = fmaf(bf16_val(*reinterpret_cast<const u16*>(b1 + off)), gp, acc1);
+                else
+                    acc1 += gp;  // o1 == 288: db4 (threads past 288 never store acc1)
+            }
     }
+    part[(size_t)blockIdx.x * 289 + o0] = acc0;
+    if (o1 < 289) part[(size_t)blockIdx.x * 289 + o1] = acc1;
 }
 
 // Adam on FP32 masters (bias-corrected; Kingma & Ba)
@@ -569,7 +609,7 @@ int nn_wgrad_blocks(int B, int H, int W)
     return (int)(tiles < 1024 ? tiles : 1024);
 }
 
-int nn_conv_blocks(int B, int H, int W) { return B * ((H + TR - 1) / TR) * (W / TW); }
+int nn_conv_blocks(int B, int H, int W) { return B * ((H + CR - 1) / CR) * (W / TW); }
 
 void nn_prep_weights(const float* params, u16* frag, u16* w4, hipStream_t s)
 {
@@ -609,7 +649,7 @@ void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb
 
 void nn_sum_partials(const float* part, int nb, int n, float* out, hipStream_t s)
 {
-    k_sum_partials<<<(n + NBLK - 1) / NBLK, NBLK, 0, s>>>(part, nb, n, out);
+    k_sum_partials<<<(n + 31) / 32, NBLK, 0, s>>>(part, nb, n, out);
 }
 
 void nn_out_fwd(const u16* a3, const u16* w4, const float* params, float* d, int B, int H, int W,
@@ -639,18 +679,14 @@ void nn_center(float* g, const double* mean, int B, int HW, hipStream_t s)
     k_center<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(g, mean, B, HW);
 }
 
-int nn_out_wgrad_blocks(int B, int H, int W)
-{
-    const long long P = (long long)B * H * W;
-    return (int)(P < 1024 ? P : 1024);
-}
+int nn_out_wgrad_blocks(int B, int H, int W) { return nn_wgrad_blocks(B, H, W); }
 
 void nn_out_bwd(const u16* a3, const u16* w4, const float* g, u16* ga3, float* part, int B, int H,
                 int W, hipStream_t s)
 {
     const size_t n = (size_t)B * H * W;
     k_out_dgrad<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(a3, w4, g, ga3, B, H, W);
-    k_out_wgrad<<<nn_out_wgrad_blocks(B, H, W), OWG, 0, s>>>(a3, g, part, B, H, W);
+    k_out_wgrad<<<nn_out_wgrad_blocks(B, H, W), NBLK, 0, s>>>(a3, g, part, B, H, W);
 }
 
 void nn_adam(float* p, float* m, float* v, const float* g, int n, int t, double lr, double b1,
