@@ -270,8 +270,9 @@ inline unsigned grid1(long long n) { return (unsigned)((n + KB - 1) / KB); }
 
 int krylov_blocks(long long n)
 {
+    // up to 4096 partial-sum blocks (16 waves per SIMD requested at 4 M entries)
     long long b = (n + KB - 1) / KB;
-    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
 template <typename T>

@@ -453,21 +453,21 @@ __global__ __launch_bounds__(NBLK) void k_out_wgrad(const u16* __restrict__ a3, 
             lg[q] = y0 + r < H ? g[((size_t)b * H + y0 + r) * W + x0 + px] : 0.0f;  // rows past H add 0
         }
         __syncthreads();
-        // every address below is a per-thread base plus a compile-time offset
         const unsigned char* b0 = la + (dy0 * (TW + 2) + dx0) * Tile<32>::PSTRIDE + ci0 * 2;
         const unsigned char* b1 = la + (2 * (TW + 2) + 2) * Tile<32>::PSTRIDE + ci1 * 2;
-#pragma unroll
-        for (int r = 0; r < TR; ++r)
-#pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const unsigned char* r0 = b0 + r * (TW + 2) * Tile<32>::PSTRIDE;
+            const unsigned char* r1 = b1 + r * (TW + 2) * Tile<32>::PSTRIDE;
+#pragma unroll 8
             for (int px = 0; px < TW; ++px) {
                 const float gp = lg[r * TW + px];
-                const int off = (r * (TW + 2) + px) * Tile<32>::PSTRIDE;
-                acc0 = fmaf(bf16_val(*reinterpret_cast<const u16*>(b0 + off)), gp, acc0);
+                acc0 = fmaf(bf16_val(*reinterpret_cast<const u16*>(r0 + px * Tile<32>::PSTRIDE)), gp, acc0);
                 if (o1 < 288)
-                    acc1 = fmaf(bf16_val(*reinterpret_cast<const u16*>(b1 + off)), gp, acc1);
+                    acc1 = fmaf(bf16_val(*reinterpret_cast<const u16*>(r1 + px * Tile<32>::PSTRIDE)), gp, acc1);
                 else
                     acc1 += gp;  // o1 == 288: db4 (threads past 288 never store acc1)
             }
+        }
     }
     part[(size_t)blockIdx.x * 289 + o0] = acc0;
     if (o1 < 289) part[(size_t)blockIdx.x * 289 + o1] = acc1;

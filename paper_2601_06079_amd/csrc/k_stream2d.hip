@@ -1,7 +1,7 @@
 // k_stream2d.hip -- fused explicit step (Eq. 12) for 2-D periodic grids.
 //
 // Layout of the work.  One 64-lane wavefront owns a strip of 64 consecutive
-// columns (lane = column) and marches upward through a chunk of TY rows,
+// columns (lane = column) and marches upward through a chunk of rows,
 // keeping every intermediate in registers:
 //   - x-neighbours come from the adjacent lane through DPP wave shifts (no LDS,
 //     no shared-memory traffic);
@@ -103,7 +103,7 @@ struct Stage {
 // Must be called by a whole wave with wave-uniform arguments.
 template <typename T, int MODEL, int PF, int KS>
 __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restrict__ out, int nx,
-                                            int ny, int strip, int chunk, int ty, unsigned bytes,
+                                            int ny, int strip, int y0, int y1, unsigned bytes,
                                             const Coef<T>& k)
 {
     constexpr int H = MODEL == 0 ? 1 : 2;
@@ -115,8 +115,6 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     int x = xl % nx;
     if (x < 0) x += nx;
     const bool out_lane = lane >= HK && lane < WAVE - HK && xl < nx;
-    const int y0 = chunk * ty;
-    const int y1 = min(y0 + ty, ny);
     const int iters = (y1 - y0) + 2 * HK;  // rows y0-HK .. y1+HK-1
     const int rowb = nx * (int)sizeof(T);  // bytes per row
     const int vx = x * (int)sizeof(T);
@@ -164,12 +162,16 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
 
 template <typename T, int MODEL, int PF, int KS>
 __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
-                                                    int nx, int ny, int nstrips, int nwaves, int ty,
+                                                    int nx, int ny, int nstrips, int nwaves, int nchunks,
                                                     unsigned bytes, Coef<T> k)
 {
     const int wave = uniform_wave();
     if (wave >= nwaves) return;  // uniform per wave
-    stream_item<T, MODEL, PF, KS>(in, out, nx, ny, wave % nstrips, wave / nstrips, ty, bytes, k);
+    // balanced chunks: chunk c of a strip owns rows [c ny / nchunks, (c + 1) ny / nchunks)
+    const int chunk = wave / nstrips;
+    const int y0 = (int)((long long)chunk * ny / nchunks);
+    const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
+    stream_item<T, MODEL, PF, KS>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
 }
 
 // Ragged batch: wave w processes work item items[w] = (sample, strip, chunk)
@@ -187,31 +189,32 @@ __global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict_
     const BatchSample& sm = smp[it.sample];
     const Coef<T> k{(T)sm.a1, (T)sm.a2, (T)sm.a3, (T)sm.beta, (T)sm.gamma};
     const unsigned bytes = (unsigned)((long long)sm.nx * sm.ny * (long long)sizeof(T));
-    stream_item<T, MODEL, PF, KS>(in + sm.offset, out + sm.offset, sm.nx, sm.ny, it.strip, it.chunk,
-                                  ty, bytes, k);
+    const int y0 = it.chunk * ty;
+    stream_item<T, MODEL, PF, KS>(in + sm.offset, out + sm.offset, sm.nx, sm.ny, it.strip, y0,
+                                  min(y0 + ty, sm.ny), bytes, k);
 }
 
 template <typename T, int MODEL, int KS>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-                  int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
+                  int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k)
 {
     if (depth <= 4)
-        k_explicit2d<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     else if (depth <= 8)
-        k_explicit2d<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     else
-        k_explicit2d<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        k_explicit2d<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
 }
 
 template <typename T, int MODEL>
 void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-               int nstrips, int nwaves, int ty, unsigned bytes, const Coef<T>& k)
+               int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k)
 {
     switch (ks) {
-        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
-        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
-        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
-        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k); break;
+        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
+        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
+        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
+        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
     }
 }
 
@@ -277,13 +280,13 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
         const double sc = dt * mob * detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     } else {
         const double sc = detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(kappa / (3.0 * m));
         k.gamma = (T)(dt * mob / (3.0 * m));
-        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, ty, bytes, k);
+        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     }
 }
 

@@ -49,13 +49,15 @@ int stream2d_rows(const pf_problem* p, int ks)
     const long long nx = p->n[0], ny = p->n[1];
     const long long strips = (nx + (64 - 2 * HK) - 1) / (64 - 2 * HK);
     const long long S = device_simds();
-    // Measured on MI355X: chunks of up to 48 rows, shortened until every SIMD
-    // has about four waves (latency hiding); the chunk plus its halo is kept a
-    // multiple of the prefetch depth (4) so no wave runs idle rows.
-    long long ty = 48;
-    while ((ty + 2 * HK) % 4) --ty;
-    while (ty - 4 >= 8 && strips * ((ny + ty - 1) / ty) < 4 * S) ty -= 4;
-    if (ty > ny) ty = ny;
+    // The launch splits each strip into balanced chunks (sizes differ by at most
+    // one row).  Measured on MI355X: enough chunks for about four waves per SIMD
+    // hide latency, and stopping just below a whole number of waves per SIMD
+    // avoids a partly filled last round.  Chunks are never shorter than 8 rows;
+    // beyond 48 rows the grid has so many rounds that 48 is used.
+    long long nch = std::max<long long>(1, 4 * S / strips);
+    nch = std::min(nch, std::max<long long>(1, ny / 8));
+    long long ty = (ny + nch - 1) / nch;
+    if (ty > 48) ty = 48;
     return (int)std::max<long long>(ty, 1);
 }
 

@@ -96,6 +96,21 @@ def test_forward_exact_dyadic(shape):
     assert np.max(np.abs((got - c) - d_ref)) <= 4e-7 * max(1.0, np.max(np.abs(ref)))
 
 
+def test_forward_exact_dyadic_full_size():
+    """One sample of the surrogate workload's full size (512 x 512) in exact
+    arithmetic: every tile of the launch the benchmark uses, against the oracle."""
+    announce("nn forward exact 512^2")
+    c, M, k, p = _dyadic(5, 1, 512, 512)
+    assert _exact_bound(p) < 2.0 ** 24
+    model = NN.Surrogate(params=p)
+    got = host(model.forward(_dev(c.astype(np.float32)), _dev(M.astype(np.float32)),
+                             _dev(k.astype(np.float32))))
+    ref, _, _ = O.nn(c, M[:, None, None] * np.ones_like(c), k[:, None, None] * np.ones_like(c),
+                     p, round_bf16=True)
+    assert np.std(ref - c) > 1e-3
+    assert np.max(np.abs((got - c) - (ref - c))) <= 4e-7 * max(1.0, np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("shape", [(2, 8, 32), (1, 13, 64), (3, 4, 96), (2, 64, 128)])
 def test_forward_matches_oracle(shape):
     """Random weights: the two sides sum in different orders, so an activation that
