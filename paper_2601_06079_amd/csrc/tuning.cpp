@@ -52,12 +52,14 @@ int stream2d_rows(const pf_problem* p, int ks)
     // The launch splits each strip into balanced chunks (sizes differ by at most
     // one row).  Measured on MI355X: enough chunks for about four waves per SIMD
     // hide latency, and stopping just below a whole number of waves per SIMD
-    // avoids a partly filled last round.  Chunks are never shorter than 8 rows;
-    // beyond 48 rows the grid has so many rounds that 48 is used.
+    // avoids a partly filled last round.  Chunks are never shorter than 8 rows.
+    // Longer chunks mean a grid of many rounds, where the measured best is 32
+    // rows for single steps and 48 for fused ones.
     long long nch = std::max<long long>(1, 4 * S / strips);
     nch = std::min(nch, std::max<long long>(1, ny / 8));
     long long ty = (ny + nch - 1) / nch;
-    if (ty > 48) ty = 48;
+    const long long tmax = ks == 1 ? 32 : 48;
+    if (ty > tmax) ty = tmax;
     return (int)std::max<long long>(ty, 1);
 }
 
