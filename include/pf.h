@@ -245,8 +245,10 @@ int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes);
 /* nsteps explicit steps (Eq. 12) of every sample, one launch per info->ks steps
  * for the whole batch.  traj == NULL: in place on U (nsteps a multiple of ks;
  * ws one packed field); elements of U outside every sample are unspecified on
- * return.  traj != NULL: one step per launch, U is only read, and the state
- * after step k (k = 1..nsteps) is written to traj + (k-1) * info->total.
+ * return.  traj != NULL: U is only read, and the state after step k
+ * (k = 1..nsteps) is written to traj + (k-1) * info->total; with a plan built for
+ * ks >= 2 each launch advances two steps and writes both states (bitwise those
+ * of single steps).
  * Allen-Cahn and the Cahn-Hilliard c plane (mu is not produced).  Asynchronous. */
 int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps, void* U,
                              void* ws, void* traj, void* stream);
@@ -254,13 +256,16 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
 /* Adjoint of nsteps batched Allen-Cahn explicit steps (Supp. Note 2 applied
  * step by step).  states + k * info->total holds the input of step k+1
  * (k = 0..nsteps-1).  On entry lam holds dO/dU of the final state; on return
- * dO/dU of the first input.  The steps stream over the plan's work items
- * (any ks; one step per launch).  Sensitivities of theta = (mobility, kappa, W)
+ * dO/dU of the first input.  The steps stream over the plan's work items, two
+ * steps per launch when the plan was built for ks >= 2 (paired from the last
+ * step; lam is bitwise that of single steps), else one.  Sensitivities of
+ * theta = (mobility, kappa, W)
  * accumulate per work item in FP64 slots kept in ws; with PF_VJP_BEGIN the
  * slots are zeroed first, with PF_VJP_END they are summed (fixed order) into
  * theta_bar (device, count x 3 doubles).  A trajectory processed in segments
  * (checkpointing) with BEGIN on the first call and END on the last gives
- * bitwise the gradient of one call over all steps.  Cahn-Hilliard plans:
+ * bitwise the gradient of one call over all steps (with a ks >= 2 plan: when
+ * every segment has an even number of steps).  Cahn-Hilliard plans:
  * PF_EUNSUPPORTED.  ws: pf_batch_workspace_size(PF_OP_VJP) of the same info,
  * kept between the calls of one trajectory.  Asynchronous. */
 enum { PF_VJP_BEGIN = 1, PF_VJP_END = 2 };

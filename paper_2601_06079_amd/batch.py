@@ -112,8 +112,8 @@ class Batch:
         return [U[o:o + nx * ny] for (nx, ny), o in zip(self.sizes, self.offsets)]
 
     def workspace(self, op):
-        """Workspace for step (the fused plan) or vjp (the single-step plan it runs on)."""
-        info = self.info1 if op == A.OP_VJP else self.info
+        """Workspace of step or vjp on the fused plan."""
+        info = self.info
         nb = ct.c_size_t(0)
         A.check(self.L.pf_batch_workspace_size(ct.byref(info), op, ct.byref(nb)))
         return torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
@@ -122,9 +122,9 @@ class Batch:
         """nsteps explicit steps of every sample in place on U (or into traj)."""
         if ws is None:
             ws = self.workspace(A.OP_STEP_EXPLICIT)
-        if traj is not None:
-            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info1),
-                                                    ct.c_void_p(self.plan1.data_ptr()), int(nsteps),
+        if traj is not None:  # the fused plan: two states per launch when ks >= 2
+            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info),
+                                                    ct.c_void_p(self.plan.data_ptr()), int(nsteps),
                                                     ct.c_void_p(U.data_ptr()), None,
                                                     ct.c_void_p(traj.data_ptr()), _stream()))
             return traj
@@ -143,11 +143,14 @@ class Batch:
 
     def vjp(self, states, lam, theta_bar, nsteps, ws=None, begin=True, end=True):
         """Adjoint of nsteps steps whose inputs are states[k]; lam in/out, theta_bar +=
-        (begin: zero the FP64 partials in ws first; end: reduce them into theta_bar)."""
+        (begin: zero the FP64 partials in ws first; end: reduce them into theta_bar).
+        Segments of one trajectory give bitwise the one-call gradient when each
+        has an even number of steps."""
         if ws is None:
             ws = self.workspace(A.OP_VJP)
         flags = (A.VJP_BEGIN if begin else 0) | (A.VJP_END if end else 0)
-        A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info1), ct.c_void_p(self.plan1.data_ptr()),
+        # the fused plan: two adjoint steps per launch when it was built for ks >= 2
+        A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
                                                int(nsteps), ct.c_void_p(states.data_ptr()),
                                                ct.c_void_p(lam.data_ptr()),
                                                ct.c_void_p(theta_bar.data_ptr()),

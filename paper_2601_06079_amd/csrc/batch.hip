@@ -268,8 +268,17 @@ int batched_steps_t(const pf_batch_info* info, const void* plan, int64_t nsteps,
     const auto* items = reinterpret_cast<const pfk::BatchItem*>(pb + info->off_items);
     const long long total = info->total;
     if (traj) {
+        // pairs of steps fused where the plan's strips leave room (ks >= 2), each
+        // launch writing both states; a lone last step runs alone (the plan's
+        // narrower strips cover every column for a single-step launch too)
         const pfk::Stream2DConfig one{info->ty, info->depth, 1};
-        for (int64_t k = 0; k < nsteps; ++k) {
+        int64_t k = 0;
+        for (; info->ks >= 2 && k + 2 <= nsteps; k += 2) {
+            const T* in = k == 0 ? U : traj + (k - 1) * total;
+            pfk::launch_explicit2d_batched<T>(info->model, in, traj + (k + 1) * total, smp, items,
+                                              info->n_items, one, s, traj + k * total);
+        }
+        for (; k < nsteps; ++k) {
             const T* in = k == 0 ? U : traj + (k - 1) * total;
             pfk::launch_explicit2d_batched<T>(info->model, in, traj + k * total, smp, items,
                                               info->n_items, one, s);
@@ -303,11 +312,16 @@ int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, c
         hipMemsetAsync(part, 0, (size_t)info->n_items * 2 * sizeof(double), s) != hipSuccess)
         return check_launch("batched vjp init");
     const int hk = info->ks;  // Allen-Cahn: strip halo H ks with H = 1
+    // two adjoint steps per launch where the plan's strips leave room (hk >= 2),
+    // paired from the last step down; a lone first step runs alone
     T* cur = lam;
-    for (int64_t k = nsteps - 1; k >= 0; --k) {
-        pfk::launch_vjp2d_batched<T>(states + k * total, cur, other, smp, items, info->n_items, info->ty,
-                                     hk, info->depth, part, s);
+    for (int64_t k = nsteps - 1; k >= 0;) {
+        const int two = hk >= 2 && k >= 1;
+        pfk::launch_vjp2d_batched<T>(states + k * total, states + (two ? k - 1 : k) * total, cur,
+                                     other, smp, items, info->n_items, info->ty, hk, info->depth,
+                                     two ? 2 : 1, part, s);
         std::swap(cur, other);
+        k -= two ? 2 : 1;
     }
     if (flags & PF_VJP_END) pfk::launch_vjp2d_reduce(part, smp, info->count, info->ty, theta_bar, s);
     if (int rc = check_launch("pf_vjp_explicit_batched")) return rc;

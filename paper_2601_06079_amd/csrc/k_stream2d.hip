@@ -101,10 +101,10 @@ struct Stage {
 // arithmetic of a single-step launch, so the result is bitwise that of KS
 // single steps.  PF: rows in flight per wave (register prefetch ring depth).
 // Must be called by a whole wave with wave-uniform arguments.
-template <typename T, int MODEL, int PF, int KS>
+template <typename T, int MODEL, int PF, int KS, bool MID = false>
 __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restrict__ out, int nx,
                                             int ny, int strip, int y0, int y1, unsigned bytes,
-                                            const Coef<T>& k)
+                                            const Coef<T>& k, T* __restrict__ mid = nullptr)
 {
     constexpr int H = MODEL == 0 ? 1 : 2;
     constexpr int HK = H * KS;            // halo of the whole pass
@@ -120,6 +120,7 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     const int vx = x * (int)sizeof(T);
     const auto rin = make_rsrc(in, bytes);
     const auto rout = make_rsrc(out, bytes);
+    const auto rmid = make_rsrc(MID ? mid : out, bytes);
 
     Stage<T, MODEL> st[KS];
 
@@ -152,8 +153,15 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
             } else {
                 rl = rlast;
             }
+            v = st[0].push(v, k);
+            if constexpr (MID) {
+                // trajectory mode: the first stage's row y0 - HK - H + t is the state
+                // after one step (bitwise a single-step launch's)
+                if (t >= HK + H && t < HK + H + (y1 - y0) && out_lane)
+                    bstore(v, rmid, vx, (y0 - HK - H + t) * rowb);
+            }
 #pragma unroll
-            for (int sidx = 0; sidx < KS; ++sidx) v = st[sidx].push(v, k);
+            for (int sidx = 1; sidx < KS; ++sidx) v = st[sidx].push(v, k);
             // the last stage just finished row y0 - 2 HK + t
             if (t >= 2 * HK && t < iters && out_lane) bstore(v, rout, vx, (y0 - 2 * HK + t) * rowb);
         }
@@ -176,12 +184,12 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
 
 // Ragged batch: wave w processes work item items[w] = (sample, strip, chunk)
 // of a batch of independent problems packed in one array (see BatchSample).
-template <typename T, int MODEL, int PF, int KS>
+template <typename T, int MODEL, int PF, int KS, bool MID = false>
 __global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict__ in,
                                                             T* __restrict__ out,
                                                             const BatchSample* __restrict__ smp,
                                                             const BatchItem* __restrict__ items,
-                                                            int n_items, int ty)
+                                                            int n_items, int ty, T* __restrict__ mid)
 {
     const int wave = uniform_wave();
     if (wave >= n_items) return;
@@ -190,8 +198,8 @@ __global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict_
     const Coef<T> k{(T)sm.a1, (T)sm.a2, (T)sm.a3, (T)sm.beta, (T)sm.gamma};
     const unsigned bytes = (unsigned)((long long)sm.nx * sm.ny * (long long)sizeof(T));
     const int y0 = it.chunk * ty;
-    stream_item<T, MODEL, PF, KS>(in + sm.offset, out + sm.offset, sm.nx, sm.ny, it.strip, y0,
-                                  min(y0 + ty, sm.ny), bytes, k);
+    stream_item<T, MODEL, PF, KS, MID>(in + sm.offset, out + sm.offset, sm.nx, sm.ny, it.strip, y0,
+                                       min(y0 + ty, sm.ny), bytes, k, MID ? mid + sm.offset : nullptr);
 }
 
 template <typename T, int MODEL, int KS>
@@ -220,30 +228,35 @@ void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out
 
 }  // namespace
 
-template <typename T, int MODEL, int KS>
+template <typename T, int MODEL, int KS, bool MID>
 void launch_batched_depth(int depth, int blocks, hipStream_t s, const T* in, T* out,
-                          const BatchSample* smp, const BatchItem* items, int n_items, int ty)
+                          const BatchSample* smp, const BatchItem* items, int n_items, int ty, T* mid)
 {
     if (depth <= 4)
-        k_explicit2d_batched<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+        k_explicit2d_batched<T, MODEL, 4, KS, MID><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty, mid);
     else if (depth <= 8)
-        k_explicit2d_batched<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+        k_explicit2d_batched<T, MODEL, 8, KS, MID><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty, mid);
     else
-        k_explicit2d_batched<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty);
+        k_explicit2d_batched<T, MODEL, 16, KS, MID><<<blocks, 256, 0, s>>>(in, out, smp, items, n_items, ty, mid);
 }
 
 template <typename T>
 void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample* smp,
                                const BatchItem* items, int n_items, const Stream2DConfig& cfg,
-                               hipStream_t s)
+                               hipStream_t s, T* mid)
 {
     const int blocks = (n_items + 3) / 4;
-#define BATCHED_KS(MODEL)                                                                          \
-    switch (cfg.ks) {                                                                              \
-        case 1: launch_batched_depth<T, MODEL, 1>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
-        case 2: launch_batched_depth<T, MODEL, 2>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
-        case 3: launch_batched_depth<T, MODEL, 3>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
-        default: launch_batched_depth<T, MODEL, 4>(cfg.depth, blocks, s, in, out, smp, items, n_items, cfg.ty); break; \
+    const int d = cfg.depth, ty = cfg.ty;
+#define BATCHED_KS(MODEL)                                                                                  \
+    if (mid) {                                                                                             \
+        launch_batched_depth<T, MODEL, 2, true>(d, blocks, s, in, out, smp, items, n_items, ty, mid);      \
+    } else {                                                                                               \
+        switch (cfg.ks) {                                                                                  \
+            case 1: launch_batched_depth<T, MODEL, 1, false>(d, blocks, s, in, out, smp, items, n_items, ty, nullptr); break; \
+            case 2: launch_batched_depth<T, MODEL, 2, false>(d, blocks, s, in, out, smp, items, n_items, ty, nullptr); break; \
+            case 3: launch_batched_depth<T, MODEL, 3, false>(d, blocks, s, in, out, smp, items, n_items, ty, nullptr); break; \
+            default: launch_batched_depth<T, MODEL, 4, false>(d, blocks, s, in, out, smp, items, n_items, ty, nullptr); break; \
+        }                                                                                                  \
     }
     if (model == 0) {
         BATCHED_KS(0)
@@ -255,10 +268,10 @@ void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample
 
 template void launch_explicit2d_batched<float>(int, const float*, float*, const BatchSample*,
                                                const BatchItem*, int, const Stream2DConfig&,
-                                               hipStream_t);
+                                               hipStream_t, float*);
 template void launch_explicit2d_batched<double>(int, const double*, double*, const BatchSample*,
                                                 const BatchItem*, int, const Stream2DConfig&,
-                                                hipStream_t);
+                                                hipStream_t, double*);
 
 template <typename T>
 void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,

@@ -108,14 +108,18 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// One work item: lam over the chunk's rows of the strip, and this wave's
-// (A, B).  hk: the plan's strip halo (its strips output 64 - 2 hk columns).
+// One work item of KS (1 or 2) adjoint steps: lam over the chunk's rows of the
+// strip, and this wave's (A, B) summed over the KS steps.  With KS = 2 the
+// first stage maps (eta_hi, lam_in) = (eta_k, lam_{k+1}) to lam_k row by row
+// and the second maps (eta_lo, lam_k) = (eta_{k-1}, lam_k) to lam_{k-1}, one
+// row behind, so lam_k never leaves registers (temporal blocking in reverse).
+// hk: the plan's strip halo (its strips output 64 - 2 hk columns; hk >= KS).
 // Must be called by a whole wave with wave-uniform arguments.
-template <typename T, int PF>
-__device__ __forceinline__ void vjp_item(const T* __restrict__ eta, const T* __restrict__ lam_in,
-                                         T* __restrict__ lam_out, int nx, int ny, int strip,
-                                         int chunk, int ty, int hk, unsigned bytes,
-                                         const VjpCoef<T>& k, double& A, double& B)
+template <typename T, int PF, int KS>
+__device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* __restrict__ eta_lo,
+                                         const T* __restrict__ lam_in, T* __restrict__ lam_out,
+                                         int nx, int ny, int strip, int chunk, int ty, int hk,
+                                         unsigned bytes, const VjpCoef<T>& k, double& A, double& B)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int xl = strip * (WAVE - 2 * hk) - hk + lane;
@@ -124,54 +128,72 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta, const T* __r
     const bool out_lane = lane >= hk && lane < WAVE - hk && xl < nx;
     const int y0 = chunk * ty;
     const int y1 = min(y0 + ty, ny);
-    const int iters = (y1 - y0) + 2;  // rows y0-1 .. y1
+    const int iters = (y1 - y0) + 2 * KS;  // rows y0-KS .. y1+KS-1
     const int rowb = nx * (int)sizeof(T);
     const int vx = x * (int)sizeof(T);
-    const auto re = make_rsrc(eta, bytes);
+    const auto rh = make_rsrc(eta_hi, bytes);
+    const auto rlo = make_rsrc(KS == 2 ? eta_lo : eta_hi, bytes);
     const auto rl = make_rsrc(lam_in, bytes);
     const auto ro = make_rsrc(lam_out, bytes);
-    VjpStage<T> st;
-    T ringe[PF], ringl[PF];
-    int row = y0 - 1;
-    if (row < 0) row += ny;
+    VjpStage<T> st[KS];
+    T ringh[PF], ringl[PF], ringo[PF];
+    int row = y0 - KS;
+    while (row < 0) row += ny;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-        ringe[u] = u < iters ? bload<T>(re, vx, row * rowb) : (T)0;
+        ringh[u] = u < iters ? bload<T>(rh, vx, row * rowb) : (T)0;
         ringl[u] = u < iters ? bload<T>(rl, vx, row * rowb) : (T)0;
+        if constexpr (KS == 2) ringo[u] = u < iters ? bload<T>(rlo, vx, row * rowb) : (T)0;
         if (++row == ny) row = 0;
     }
-    int rlast = y1;
-    if (rlast >= ny) rlast -= ny;
+    int rlast = y1 + KS - 1;
+    while (rlast >= ny) rlast -= ny;
+    T elo_prev = 0;  // eta_lo of the row before the current one (KS = 2)
     double accA = 0.0, accB = 0.0;
     for (int t0 = 0; t0 < iters; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = t0 + u;
-            const T ve = ringe[u], vl = ringl[u];
+            const T vh = ringh[u], vl = ringl[u];
+            T vo = 0;
             // unconditional prefetch (past the chunk the last row is re-read)
-            ringe[u] = bload<T>(re, vx, row * rowb);
+            ringh[u] = bload<T>(rh, vx, row * rowb);
             ringl[u] = bload<T>(rl, vx, row * rowb);
+            if constexpr (KS == 2) {
+                vo = ringo[u];
+                ringo[u] = bload<T>(rlo, vx, row * rowb);
+            }
             if (t + PF + 1 < iters) {
                 if (++row == ny) row = 0;
             } else {
                 row = rlast;
             }
+            // stage 0 finishes row y0 - KS - 1 + t (and the element row above it)
             T a, b;
-            const T v = st.push(ve, vl, k, a, b);
-            // the stage just finished row y0 - 2 + t and element row (y0 - 2 + t, y0 - 1 + t)
-            if (t >= 2 && t < iters) {
-                if (out_lane) bstore(v, ro, vx, (y0 - 2 + t) * rowb);
+            T v = st[0].push(vh, vl, k, a, b);
+            if (t >= KS + 1 && t < (y1 - y0) + KS + 1) {
                 accA += (double)a;
                 accB += (double)b;
             }
+            if constexpr (KS == 2) {
+                // stage 1 finishes row y0 - 4 + t from lam_k of row y0 - 3 + t
+                v = st[1].push(elo_prev, v, k, a, b);
+                elo_prev = vo;
+                if (t >= 4 && t < iters) {
+                    accA += (double)a;
+                    accB += (double)b;
+                }
+            }
+            if (t >= 2 * KS && t < iters && out_lane) bstore(v, ro, vx, (y0 - 2 * KS + t) * rowb);
         }
     }
     A = out_lane ? accA : 0.0;
     B = out_lane ? accB : 0.0;
 }
 
-template <typename T, int PF>
-__global__ __launch_bounds__(256) void k_vjp2d_batched(const T* __restrict__ eta,
+template <typename T, int PF, int KS>
+__global__ __launch_bounds__(256) void k_vjp2d_batched(const T* __restrict__ eta_hi,
+                                                       const T* __restrict__ eta_lo,
                                                        const T* __restrict__ lam_in,
                                                        T* __restrict__ lam_out,
                                                        const BatchSample* __restrict__ smp,
@@ -189,8 +211,8 @@ __global__ __launch_bounds__(256) void k_vjp2d_batched(const T* __restrict__ eta
                        (T)f1.a3, (T)(sm.dt * sm.mob * sm.kappa / (3.0 * m))};
     const unsigned bytes = (unsigned)((long long)sm.nx * sm.ny * (long long)sizeof(T));
     double A, B;
-    vjp_item<T, PF>(eta + sm.offset, lam_in + sm.offset, lam_out + sm.offset, sm.nx, sm.ny,
-                    it.strip, it.chunk, ty, hk, bytes, k, A, B);
+    vjp_item<T, PF, KS>(eta_hi + sm.offset, eta_lo + sm.offset, lam_in + sm.offset,
+                        lam_out + sm.offset, sm.nx, sm.ny, it.strip, it.chunk, ty, hk, bytes, k, A, B);
     A = wave_sum(A);
     B = wave_sum(B);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -236,15 +258,25 @@ __global__ __launch_bounds__(RB) void k_vjp2d_reduce(const double* __restrict__ 
 }  // namespace
 
 template <typename T>
-void launch_vjp2d_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
-                          const BatchItem* items, int n_items, int ty, int hk, int depth,
-                          double* part, hipStream_t s)
+void launch_vjp2d_batched(const T* eta_hi, const T* eta_lo, const T* lam_in, T* lam_out,
+                          const BatchSample* smp, const BatchItem* items, int n_items, int ty, int hk,
+                          int depth, int ksteps, double* part, hipStream_t s)
 {
     const int blocks = (n_items + 3) / 4;
-    if (depth <= 4)
-        k_vjp2d_batched<T, 4><<<blocks, 256, 0, s>>>(eta, lam_in, lam_out, smp, items, n_items, ty, hk, part);
-    else
-        k_vjp2d_batched<T, 8><<<blocks, 256, 0, s>>>(eta, lam_in, lam_out, smp, items, n_items, ty, hk, part);
+#define VJP_LAUNCH(PF, KS) \
+    k_vjp2d_batched<T, PF, KS><<<blocks, 256, 0, s>>>(eta_hi, eta_lo, lam_in, lam_out, smp, items, n_items, ty, hk, part)
+    if (ksteps == 2) {
+        if (depth <= 4)
+            VJP_LAUNCH(4, 2);
+        else
+            VJP_LAUNCH(8, 2);
+    } else {
+        if (depth <= 4)
+            VJP_LAUNCH(4, 1);
+        else
+            VJP_LAUNCH(8, 1);
+    }
+#undef VJP_LAUNCH
 }
 
 void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, int ty,
@@ -253,9 +285,11 @@ void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, 
     k_vjp2d_reduce<<<count, RB, 0, s>>>(part, smp, ty, theta_bar);
 }
 
-template void launch_vjp2d_batched<float>(const float*, const float*, float*, const BatchSample*,
-                                          const BatchItem*, int, int, int, int, double*, hipStream_t);
-template void launch_vjp2d_batched<double>(const double*, const double*, double*, const BatchSample*,
-                                           const BatchItem*, int, int, int, int, double*, hipStream_t);
+template void launch_vjp2d_batched<float>(const float*, const float*, const float*, float*,
+                                          const BatchSample*, const BatchItem*, int, int, int, int,
+                                          int, double*, hipStream_t);
+template void launch_vjp2d_batched<double>(const double*, const double*, const double*, double*,
+                                           const BatchSample*, const BatchItem*, int, int, int, int,
+                                           int, double*, hipStream_t);
 
 }  // namespace pfk

@@ -113,19 +113,22 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
                        double dt, const T* in, T* out, const Stream2DConfig& cfg, hipStream_t s);
 
 // ---- ragged batch kernels ------------------------------------------------------
-// cfg.ks explicit steps of every sample: one launch for the whole batch
+// cfg.ks explicit steps of every sample: one launch for the whole batch.  With
+// mid != nullptr two steps are fused and the state after the first is also
+// written to mid (trajectory mode; cfg.ks is ignored).
 template <typename T>
 void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample* smp,
                                const BatchItem* items, int n_items, const Stream2DConfig& cfg,
-                               hipStream_t s);
-// Allen-Cahn step adjoint over a ragged batch (streamed like the forward kernel):
-//   lam_out = lam_in - (dt L/m) J_r(eta)^T lam_in on the plan's work items, and
-//   part[2 w .. 2 w + 2) += (A, B) of work item w (see k_vjp2d.hip); hk: the
-//   plan's strip halo (H ks)
+                               hipStream_t s, T* mid = nullptr);
+// Allen-Cahn step adjoint over a ragged batch (streamed like the forward kernel),
+// ksteps (1 or 2 <= hk) steps per launch: lam_out = S_lo^T S_hi^T lam_in with
+// S^T lam = lam - (dt L/m) J_r(eta)^T lam at eta_hi (= eta_k) and, for two
+// steps, eta_lo (= eta_{k-1}); part[2 w .. 2 w + 2) += (A, B) of work item w
+// (see k_vjp2d.hip); hk: the plan's strip halo (H ks)
 template <typename T>
-void launch_vjp2d_batched(const T* eta, const T* lam_in, T* lam_out, const BatchSample* smp,
-                          const BatchItem* items, int n_items, int ty, int hk, int depth,
-                          double* part, hipStream_t s);
+void launch_vjp2d_batched(const T* eta_hi, const T* eta_lo, const T* lam_in, T* lam_out,
+                          const BatchSample* smp, const BatchItem* items, int n_items, int ty, int hk,
+                          int depth, int ksteps, double* part, hipStream_t s);
 // theta_bar[s][0..3) += the gradient of sample s's accumulated (A, B) (fixed order)
 void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, int ty,
                          double* theta_bar, hipStream_t s);
