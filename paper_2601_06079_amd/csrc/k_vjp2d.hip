@@ -266,10 +266,10 @@ void launch_vjp2d_batched(const T* eta_hi, const T* eta_lo, const T* lam_in, T* 
 #define VJP_LAUNCH(PF, KS) \
     k_vjp2d_batched<T, PF, KS><<<blocks, 256, 0, s>>>(eta_hi, eta_lo, lam_in, lam_out, smp, items, n_items, ty, hk, part)
     if (ksteps == 2) {
-        if (depth <= 4)
-            VJP_LAUNCH(4, 2);
-        else
-            VJP_LAUNCH(8, 2);
+        // three streamed fields: a 2-row ring keeps enough loads in flight and
+        // the register count low enough for four waves per SIMD
+        VJP_LAUNCH(2, 2);
+        (void)depth;
     } else {
         if (depth <= 4)
             VJP_LAUNCH(4, 1);
