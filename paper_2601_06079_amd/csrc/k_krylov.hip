@@ -9,9 +9,11 @@
 //
 // Classical Gram-Schmidt with one re-orthogonalisation (CGS2) is fused into
 // three sweeps over the Krylov basis V (k vectors, leading dimension ld):
-//   k_mdot        h1 = V^T w
-//   k_axpy_mdot   w <- w - V h1 and, in the same sweep, h2 = V^T w
-//   k_axpy_norm   w <- w - V h2 and ||w||^2
+//   k_dots            h1 = V^T w
+//   k_axpy_dots       w <- w - V h1 and, in the same sweep, h2 = V^T w, ||w||^2
+//   k_axpy_normalize  w <- w - V h2, whose norm is sqrt(||w||^2 - ||h2||^2)
+//                     without another pass; the normalised vector is stored
+//                     as the next basis vector and the preconditioner applied.
 #include <cmath>
 
 #include "device.hpp"
@@ -46,82 +48,202 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
         }
 }
 
-// h[i] partials: part[i * nb + block] = sum over this block's entries of V_i . w
-template <typename T>
-__global__ __launch_bounds__(KB) void k_mdot(const T* __restrict__ V, long long ld, int k,
+// ---- Gram-Schmidt sweeps ----------------------------------------------------
+// Each lane streams VW consecutive entries per load (16 bytes: 4 floats or 2
+// doubles) of w and of every basis vector; the column loop is unrolled to KMAX
+// (>= k) so that all loads of one chunk are in flight together.  Columns
+// i >= k re-load column k - 1 (a cache hit) and are masked out, which keeps
+// the unrolled loop free of branches.
+
+template <typename T, int VW>
+struct alignas(VW * sizeof(T)) Pack {
+    T v[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Pack<T, VW> ldp(const T* p)
+{
+    return *reinterpret_cast<const Pack<T, VW>*>(p);
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void stp(T* p, const Pack<T, VW>& x)
+{
+    *reinterpret_cast<Pack<T, VW>*>(p) = x;
+}
+
+// write the block sums of acc[0..cnt) to part[i * nb + block]
+template <int NV>
+__device__ __forceinline__ void store_partials(double (&acc)[NV], int cnt, double* __restrict__ part)
+{
+    const int nb = gridDim.x;
+#pragma unroll
+    for (int c0 = 0; c0 < NV; c0 += 8) {
+        double a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = c0 + i < NV ? acc[c0 + i] : 0.0;
+        block_sum<8>(a);
+        if (threadIdx.x == 0)
+            for (int i = 0; i < 8 && c0 + i < cnt; ++i) part[(long long)(c0 + i) * nb + blockIdx.x] = a[i];
+        __syncthreads();
+    }
+}
+
+// part[i * nb + block] = this block's share of V_i . w  (i < k <= KMAX)
+template <typename T, int KMAX, int VW>
+__global__ __launch_bounds__(KB) void k_dots(const T* __restrict__ V, long long ld, int k,
                                              const T* __restrict__ w, long long n,
                                              double* __restrict__ part)
 {
-    const int nb = gridDim.x;
-    for (int c0 = 0; c0 < k; c0 += 8) {
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)nb * KB) {
-            const double we = (double)w[e];
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (c0 + i < k) acc[i] = fma((double)V[(c0 + i) * ld + e], we, acc[i]);
-        }
-        block_sum<8>(acc);
-        if (threadIdx.x == 0)
-            for (int i = 0; i < 8 && c0 + i < k; ++i) part[(long long)(c0 + i) * nb + blockIdx.x] = acc[i];
-        __syncthreads();
-    }
-}
-
-// w <- w - sum_i h[i] V_i ; then part[i] = V_i . w  (KMAX >= k)
-template <typename T, int KMAX>
-__global__ __launch_bounds__(KB) void k_axpy_mdot(const T* __restrict__ V, long long ld, int k,
-                                                  const double* __restrict__ h, T* __restrict__ w,
-                                                  long long n, double* __restrict__ part)
-{
-    const int nb = gridDim.x;
     double acc[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) acc[i] = 0.0;
-    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)nb * KB) {
-        T v[KMAX];
-        double s = (double)w[e];
+    const long long nv = n / VW;
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
+        const Pack<T, VW> wv = ldp<T, VW>(w + e * VW);
+        Pack<T, VW> vv[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) vv[i] = ldp<T, VW>(V + (i < k ? i : k - 1) * ld + e * VW);
 #pragma unroll
         for (int i = 0; i < KMAX; ++i)
-            if (i < k) {
-                v[i] = V[i * ld + e];
-                s = fma(-h[i], (double)v[i], s);
-            }
-        const T wn = (T)s;
-        w[e] = wn;
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i)
-            if (i < k) acc[i] = fma((double)v[i], (double)wn, acc[i]);
+            for (int l = 0; l < VW; ++l) acc[i] = fma((double)vv[i].v[l], (double)wv.v[l], acc[i]);
     }
-    // reduce in groups of 8 to bound shared memory
-#pragma unroll
-    for (int c0 = 0; c0 < KMAX; c0 += 8) {
-        double a[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = acc[c0 + i];
-        block_sum<8>(a);
-        if (threadIdx.x == 0)
-            for (int i = 0; i < 8 && c0 + i < k; ++i) part[(long long)(c0 + i) * nb + blockIdx.x] = a[i];
-        __syncthreads();
-    }
+    store_partials<KMAX>(acc, k, part);
 }
 
-// w <- w - sum_i h[i] V_i ; part[0] = ||w||^2
-template <typename T>
-__global__ __launch_bounds__(KB) void k_axpy_norm(const T* __restrict__ V, long long ld, int k,
+// w <- w - V h ; part[i * nb + block] = share of V_i . w (i < k), part[k * nb + block] = share of ||w||^2
+template <typename T, int KMAX, int VW>
+__global__ __launch_bounds__(KB) void k_axpy_dots(const T* __restrict__ V, long long ld, int k,
                                                   const double* __restrict__ h, T* __restrict__ w,
                                                   long long n, double* __restrict__ part)
 {
-    double acc[1] = {0.0};
-    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-        double s = (double)w[e];
-        for (int i = 0; i < k; ++i) s = fma(-h[i], (double)V[i * ld + e], s);
-        const T wn = (T)s;
-        w[e] = wn;
-        acc[0] = fma((double)wn, (double)wn, acc[0]);
+    double hh[KMAX], acc[KMAX + 1];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        hh[i] = i < k ? h[i] : 0.0;
+        acc[i] = 0.0;
     }
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    acc[KMAX] = 0.0;
+    const long long nv = n / VW;
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
+        Pack<T, VW> wv = ldp<T, VW>(w + e * VW);
+        Pack<T, VW> vv[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) vv[i] = ldp<T, VW>(V + (i < k ? i : k - 1) * ld + e * VW);
+#pragma unroll
+        for (int l = 0; l < VW; ++l) {
+            double s = (double)wv.v[l];
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i) s = fma(-hh[i], (double)vv[i].v[l], s);
+            wv.v[l] = (T)s;
+        }
+        stp<T, VW>(w + e * VW, wv);
+#pragma unroll
+        for (int l = 0; l < VW; ++l) {
+            const double wn = (double)wv.v[l];
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i) acc[i] = fma((double)vv[i].v[l], wn, acc[i]);
+            acc[KMAX] = fma(wn, wn, acc[KMAX]);
+        }
+    }
+    // move ||w||^2 to slot k so that the partial columns are contiguous
+    double out[KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= KMAX; ++i) out[i] = i < k ? acc[i] : (i == k ? acc[KMAX] : 0.0);
+    store_partials<KMAX + 1>(out, k + 1, part);
+}
+
+// x[0..VW) -= V h over one chunk of one plane (columns masked as above)
+template <typename T, int KMAX, int VW>
+__device__ __forceinline__ void axpy_chunk(const T* __restrict__ V, long long ld, int k,
+                                           const double (&hh)[KMAX], long long off, double (&x)[VW])
+{
+    Pack<T, VW> vv[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) vv[i] = ldp<T, VW>(V + (i < k ? i : k - 1) * ld + off);
+#pragma unroll
+    for (int l = 0; l < VW; ++l)
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) x[l] = fma(-hh[i], (double)vv[i].v[l], x[l]);
+}
+
+// Last CGS2 sweep fused with the normalisation and the preconditioner:
+//   w'' = w - V h  (h: the k second-pass coefficients; sums[k] = ||w||^2),
+//   ||w''||^2 = ||w||^2 - ||h||^2  (h is the projection of w on V),
+//   v = w'' / ||w''||  -> vnext,   z = P^-1 v.
+// nrm2[0] receives ||w''||^2.  Node-indexed: VW nodes per lane, planes at
+// offset N (MODEL 1: the c and mu planes with per-node 2x2 blocks).
+template <typename T, int KMAX, int VW, int MODEL>
+__global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, long long ld, int k,
+                                                       const double* __restrict__ sums,
+                                                       const T* __restrict__ w, T* __restrict__ vnext,
+                                                       T* __restrict__ z, const T* __restrict__ pinv,
+                                                       long long N, int tr, double* __restrict__ nrm2)
+{
+    double hh[KMAX];
+    double hsq = 0.0;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        hh[i] = i < k ? sums[i] : 0.0;
+        hsq = fma(hh[i], hh[i], hsq);
+    }
+    const double nn = sums[k] - hsq;
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) nrm2[0] = nn > 0.0 ? nn : 0.0;
+    const long long nv = N / VW;
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
+        const long long o = e * VW;
+        double xc[VW];
+        {
+            const Pack<T, VW> wv = ldp<T, VW>(w + o);
+#pragma unroll
+            for (int l = 0; l < VW; ++l) xc[l] = (double)wv.v[l];
+        }
+        axpy_chunk<T, KMAX, VW>(V, ld, k, hh, o, xc);
+        Pack<T, VW> vc;
+#pragma unroll
+        for (int l = 0; l < VW; ++l) vc.v[l] = (T)((T)xc[l] * inv);
+        stp<T, VW>(vnext + o, vc);
+        if constexpr (MODEL == 0) {
+            Pack<T, VW> zc;
+            if (pinv) {
+                const Pack<T, VW> pv = ldp<T, VW>(pinv + o);
+#pragma unroll
+                for (int l = 0; l < VW; ++l) zc.v[l] = vc.v[l] * pv.v[l];
+            } else {
+                zc = vc;
+            }
+            stp<T, VW>(z + o, zc);
+        } else {
+            double xm[VW];
+            {
+                const Pack<T, VW> wv = ldp<T, VW>(w + N + o);
+#pragma unroll
+                for (int l = 0; l < VW; ++l) xm[l] = (double)wv.v[l];
+            }
+            axpy_chunk<T, KMAX, VW>(V, ld, k, hh, N + o, xm);
+            Pack<T, VW> vm;
+#pragma unroll
+            for (int l = 0; l < VW; ++l) vm.v[l] = (T)((T)xm[l] * inv);
+            stp<T, VW>(vnext + N + o, vm);
+            Pack<T, VW> zc, zm;
+            if (pinv) {
+#pragma unroll
+                for (int l = 0; l < VW; ++l) {
+                    const T* P = pinv + 4 * (o + l);
+                    const T p01 = tr ? P[2] : P[1], p10 = tr ? P[1] : P[2];
+                    zc.v[l] = P[0] * vc.v[l] + p01 * vm.v[l];
+                    zm.v[l] = p10 * vc.v[l] + P[3] * vm.v[l];
+                }
+            } else {
+                zc = vc;
+                zm = vm;
+            }
+            stp<T, VW>(z + o, zc);
+            stp<T, VW>(z + N + o, zm);
+        }
+    }
 }
 
 // part[block] = partial ||x||^2 (x = a - b when b != nullptr)
@@ -270,43 +392,66 @@ inline unsigned grid1(long long n) { return (unsigned)((n + KB - 1) / KB); }
 
 int krylov_blocks(long long n)
 {
-    // up to 4096 partial-sum blocks (16 waves per SIMD requested at 4 M entries)
-    long long b = (n + KB - 1) / KB;
-    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+    // at least 16 entries per thread, at most 1024 partial-sum blocks (4 per CU)
+    long long b = (n + 16 * KB - 1) / (16 * KB);
+    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
+namespace {
+
+// 16-byte lanes when every plane offset keeps that alignment, else scalar lanes
 template <typename T>
-void kr_mdot(const T* V, long long ld, int k, const T* w, long long n, double* part, double* out,
-             int accumulate, hipStream_t s)
+bool wide_ok(long long N)
 {
-    const int nb = krylov_blocks(n);
-    k_mdot<T><<<nb, KB, 0, s>>>(V, ld, k, w, n, part);
-    k_reduce_cols<<<k, KB, 0, s>>>(part, nb, k, out, accumulate);
+    return N % (long long)(16 / sizeof(T)) == 0;
 }
 
-template <typename T>
-void kr_axpy_mdot(const T* V, long long ld, int k, const double* h, T* w, long long n, double* part,
-                  double* out, hipStream_t s)
+template <typename T, int KMAX, int VW>
+void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
+            long long N, long long n, double* part, double* dh1, double* dh2, double* dnrm, int tr,
+            hipStream_t s)
 {
     const int nb = krylov_blocks(n);
-    if (k <= 8)
-        k_axpy_mdot<T, 8><<<nb, KB, 0, s>>>(V, ld, k, h, w, n, part);
-    else if (k <= 16)
-        k_axpy_mdot<T, 16><<<nb, KB, 0, s>>>(V, ld, k, h, w, n, part);
-    else if (k <= 32)
-        k_axpy_mdot<T, 32><<<nb, KB, 0, s>>>(V, ld, k, h, w, n, part);
+    k_dots<T, KMAX, VW><<<nb, KB, 0, s>>>(V, ld, k, w, n, part);
+    k_reduce_cols<<<k, KB, 0, s>>>(part, nb, k, dh1, 0);
+    k_axpy_dots<T, KMAX, VW><<<nb, KB, 0, s>>>(V, ld, k, dh1, w, n, part);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb, k + 1, dh2, 0);
+    const int nbn = krylov_blocks(N);
+    if (model == 0)
+        k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, dh2, w, vnext, z, pinv, N, tr, dnrm);
     else
-        k_axpy_mdot<T, 72><<<nb, KB, 0, s>>>(V, ld, k, h, w, n, part);
-    k_reduce_cols<<<k, KB, 0, s>>>(part, nb, k, out, 0);
+        k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, dh2, w, vnext, z, pinv, N, tr, dnrm);
 }
 
-template <typename T>
-void kr_axpy_norm(const T* V, long long ld, int k, const double* h, T* w, long long n, double* part,
-                  double* out, hipStream_t s)
+template <typename T, int VW>
+void cgs2_v(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
+            long long N, long long n, double* part, double* dh1, double* dh2, double* dnrm, int tr,
+            hipStream_t s)
 {
-    const int nb = krylov_blocks(n);
-    k_axpy_norm<T><<<nb, KB, 0, s>>>(V, ld, k, h, w, n, part);
-    k_reduce_cols<<<1, KB, 0, s>>>(part, nb, 1, out, 0);
+#define PF_CGS2(KM) cgs2_k<T, KM, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s)
+    if (k <= 4) PF_CGS2(4);
+    else if (k <= 8) PF_CGS2(8);
+    else if (k <= 12) PF_CGS2(12);
+    else if (k <= 16) PF_CGS2(16);
+    else if (k <= 24) PF_CGS2(24);
+    else PF_CGS2(32);
+#undef PF_CGS2
+}
+
+}  // namespace
+
+template <typename T>
+int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
+            long long N, double* part, double* dh1, double* dh2, double* dnrm, hipStream_t s, int tr)
+{
+    if (k < 1 || k > KR_MAXK) return -1;
+    const long long n = (model == 0 ? 1 : 2) * N;
+    constexpr int VW = 16 / sizeof(T);
+    if (wide_ok<T>(N))
+        cgs2_v<T, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s);
+    else
+        cgs2_v<T, 1>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s);
+    return 0;
 }
 
 template <typename T>
@@ -356,12 +501,8 @@ void kr_add_maxabs(T* x, const T* y, long long n, double* part, hipStream_t s)
 }
 
 #define INST_KR(T)                                                                              \
-    template void kr_mdot<T>(const T*, long long, int, const T*, long long, double*, double*, int, \
-                             hipStream_t);                                                      \
-    template void kr_axpy_mdot<T>(const T*, long long, int, const double*, T*, long long, double*, \
-                                  double*, hipStream_t);                                        \
-    template void kr_axpy_norm<T>(const T*, long long, int, const double*, T*, long long, double*, \
-                                  double*, hipStream_t);                                        \
+    template int kr_cgs2<T>(int, const T*, long long, int, T*, T*, T*, const T*, long long, double*, \
+                            double*, double*, double*, hipStream_t, int);                       \
     template void kr_norm2<T>(const T*, const T*, long long, double*, double*, hipStream_t);     \
     template void kr_normalize_prec<T>(int, const T*, const double*, T*, T*, const T*, long long, \
                                        double, hipStream_t, int);                               \

@@ -7,18 +7,18 @@ namespace pfk {
 // number of partial-sum blocks used for vectors of length n (fixed per n)
 int krylov_blocks(long long n);
 
-// out[0..k) (+)= V^T w ; part: k * krylov_blocks(n) doubles
+// largest basis handled by one Gram-Schmidt step
+constexpr int KR_MAXK = 32;
+// One Arnoldi orthogonalisation (CGS2) of w against the k basis vectors V
+// (N nodes, 1 plane for model 0, 2 for model 1; leading dimension ld):
+//   dh1[0..k) = V^T w, w <- w - V dh1, dh2[0..k) = V^T w, dh2[k] = ||w||^2,
+//   dnrm[0] = ||w - V dh2||^2, vnext = (w - V dh2) / sqrt(dnrm[0]) (0 if that is 0),
+//   z = P^-1 vnext.  w is left after the first correction.  part: (k + 1) *
+//   krylov_blocks(n) doubles.  Returns -1 (nothing launched) for k outside 1..KR_MAXK.
 template <typename T>
-void kr_mdot(const T* V, long long ld, int k, const T* w, long long n, double* part, double* out,
-             int accumulate, hipStream_t s);
-// w -= V h ; out[0..k) = V^T w
-template <typename T>
-void kr_axpy_mdot(const T* V, long long ld, int k, const double* h, T* w, long long n, double* part,
-                  double* out, hipStream_t s);
-// w -= V h ; out[0] = ||w||^2
-template <typename T>
-void kr_axpy_norm(const T* V, long long ld, int k, const double* h, T* w, long long n, double* part,
-                  double* out, hipStream_t s);
+int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
+            long long N, double* part, double* dh1, double* dh2, double* dnrm, hipStream_t s,
+            int tr = 0);
 // out[0] = ||a - b||^2 (b may be null)
 template <typename T>
 void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s);

@@ -5,9 +5,11 @@
 // the preconditioner) live in the caller's workspace on the device; every
 // matrix-vector product is the matrix-free Jacobian kernel; every dot product
 // and norm is an FP64 device reduction.  Per Arnoldi step the host reads back
-// one Hessenberg column (<= 2 m + 1 doubles) to apply its Givens rotation and
+// one Hessenberg column (<= 2 m + 3 doubles) to apply its Givens rotation and
 // test convergence; the (m+1) x m Hessenberg matrix and the small triangular
-// solve stay on the host in FP64.
+// solve stay on the host in FP64.  The read is pipelined: the next Arnoldi step
+// is queued before the host waits for the current column, so the device never
+// idles on the round trip; a step queued past convergence is discarded.
 //
 // GMRES(m) variant: right preconditioning (the residual it monitors is the true
 // one), classical Gram-Schmidt with one re-orthogonalisation, x0 = 0, restart
@@ -67,6 +69,36 @@ NWS<T> layout(const pf_problem* p, void* base)
 
 enum { DEV_H1 = 0, DEV_H2 = MAXM + 1, DEV_NRM = 2 * (MAXM + 1), DEV_Y = 2 * (MAXM + 1) + 2,
        DEV_MISC = 3 * (MAXM + 1) + 2 };
+
+// Pinned host slots for the Hessenberg columns, two per host thread and device
+// (allocated on first use and kept until the process ends), and the events that
+// mark each slot's copy.
+struct ColReadback {
+    double* host = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+int col_readback(ColReadback** out)
+{
+    static_assert(MAXM <= pfk::KR_MAXK, "restart length beyond the Gram-Schmidt kernels");
+    thread_local ColReadback rb[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(PF_EDEVICE, "no usable current device for the GMRES readback");
+    ColReadback& r = rb[dev];
+    if (!r.host) {
+        double* h = nullptr;
+        hipError_t e = hipHostMalloc((void**)&h, 2 * DEV_Y * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return fail(PF_EDEVICE, "pinned GMRES readback buffer: %s", hipGetErrorString(e));
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return fail(PF_EDEVICE, "GMRES readback event: %s", hipGetErrorString(e));
+        }
+        r.host = h;
+    }
+    *out = &r;
+    return PF_OK;
+}
 
 struct Opts {
     double rtol, atol, lmin, lmax;
@@ -153,7 +185,8 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
     double* dy = L.dev + DEV_Y;
     if (hipMemsetAsync(L.x, 0, (size_t)n * sizeof(T), s) != hipSuccess) return check_launch("gmres init");
     std::vector<double> H((MAXM + 1) * MAXM), cs(MAXM), sn(MAXM), gv(MAXM + 1), y(MAXM);
-    std::vector<double> col(DEV_Y);
+    ColReadback* rb = nullptr;
+    if (int rc = col_readback(&rb)) return rc;
     int total = 0;
     double beta = bnorm;
     bool first = true;
@@ -181,16 +214,29 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
         first = false;
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
+        // Arnoldi step i: w = J z_i, orthogonalise, v_{i+1} and z_{i+1}; its
+        // column goes to pinned slot i % 2
+        auto enqueue = [&](int i) -> int {
+            A.apply(L.z, L.w, s);
+            if (pfk::kr_cgs2<T>(model, L.V, L.ld, i + 1, L.w, L.V + (long long)(i + 1) * L.ld, L.z, pinv,
+                                Nn, L.part, dh1, dh2, dnrm, s, tr))
+                return fail(PF_EINVAL, "Gram-Schmidt basis of %d vectors", i + 1);
+            double* slot = rb->host + (i & 1) * DEV_Y;
+            if (hipMemcpyAsync(slot, L.dev, DEV_Y * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipEventRecord(rb->ev[i & 1], s) != hipSuccess)
+                return check_launch("GMRES column readback");
+            return PF_OK;
+        };
         int j = 0;
         bool done = false;
-        for (; j < m && total < max_its; ++j) {
-            T* vnext = L.V + (long long)(j + 1) * L.ld;
-            A.apply(L.z, L.w, s);
-            pfk::kr_mdot<T>(L.V, L.ld, j + 1, L.w, n, L.part, dh1, 0, s);
-            pfk::kr_axpy_mdot<T>(L.V, L.ld, j + 1, dh1, L.w, n, L.part, dh2, s);
-            pfk::kr_axpy_norm<T>(L.V, L.ld, j + 1, dh2, L.w, n, L.part, dnrm, s);
-            pfk::kr_normalize_prec<T>(model, L.w, dnrm, vnext, L.z, pinv, Nn, 1.0, s, tr);
-            if (int rc = d2h(col.data(), L.dev, col.size() * sizeof(double), s)) return rc;
+        const int steps = std::min(m, max_its - total);
+        if (steps > 0)
+            if (int rc = enqueue(0)) return rc;
+        for (; j < steps; ++j) {
+            if (j + 1 < steps)
+                if (int rc = enqueue(j + 1)) return rc;
+            if (hipEventSynchronize(rb->ev[j & 1]) != hipSuccess) return check_launch("GMRES column wait");
+            const double* col = rb->host + (j & 1) * DEV_Y;
             ++total;
             for (int i = 0; i <= j; ++i) H[i * MAXM + j] = col[DEV_H1 + i] + col[DEV_H2 + i];
             const double hn = std::sqrt(std::max(col[DEV_NRM], 0.0));
@@ -202,7 +248,10 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
             }
             const double a = H[j * MAXM + j], bb = H[(j + 1) * MAXM + j];
             const double rr = std::hypot(a, bb);
-            if (!std::isfinite(rr)) return fail(PF_ENONFINITE, "GMRES Hessenberg is not finite");
+            if (!std::isfinite(rr)) {
+                hipStreamSynchronize(s);
+                return fail(PF_ENONFINITE, "GMRES Hessenberg is not finite");
+            }
             cs[j] = rr > 0.0 ? a / rr : 1.0;
             sn[j] = rr > 0.0 ? bb / rr : 0.0;
             H[j * MAXM + j] = rr;
