@@ -88,8 +88,10 @@ int pf_version(void);
  * choice).  Used by the autotuner; results never depend on them.
  *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel;
  *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
- *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4). */
-enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2 };
+ *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
+ *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product. */
+enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
+       PF_TUNE_JVP3D_PLANES = 3 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 /* The launch shape pf_step_explicit uses for p (2-D): steps fused per launch,

@@ -14,6 +14,7 @@
 //   k_axpy_normalize  w <- w - V h2, whose norm is sqrt(||w||^2 - ||h2||^2)
 //                     without another pass; the normalised vector is stored
 //                     as the next basis vector and the preconditioner applied.
+#include <algorithm>
 #include <cmath>
 
 #include "device.hpp"
@@ -406,17 +407,40 @@ bool wide_ok(long long N)
     return N % (long long)(16 / sizeof(T)) == 0;
 }
 
+// Blocks of `kernel` that fit on the device at once (its occupancy times the CU
+// count), queried once per kernel.  A sweep launched on more blocks than that
+// runs a partial second round; fewer, longer-running blocks stream the same bytes.
+template <typename K>
+int resident_blocks(K kernel)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, KB, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1 << 30;  // no cap
+    }
+    return (per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+}
+
 template <typename T, int KMAX, int VW>
 void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
             long long N, long long n, double* part, double* dh1, double* dh2, double* dnrm, int tr,
             hipStream_t s)
 {
+    static const int cap_dots = resident_blocks(k_dots<T, KMAX, VW>);
+    static const int cap_axpy = resident_blocks(k_axpy_dots<T, KMAX, VW>);
+    static const int cap_norm0 = resident_blocks(k_axpy_normalize<T, KMAX, VW, 0>);
+    static const int cap_norm1 = resident_blocks(k_axpy_normalize<T, KMAX, VW, 1>);
+    const int cap_norm = model == 0 ? cap_norm0 : cap_norm1;
     const int nb = krylov_blocks(n);
-    k_dots<T, KMAX, VW><<<nb, KB, 0, s>>>(V, ld, k, w, n, part);
-    k_reduce_cols<<<k, KB, 0, s>>>(part, nb, k, dh1, 0);
-    k_axpy_dots<T, KMAX, VW><<<nb, KB, 0, s>>>(V, ld, k, dh1, w, n, part);
-    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb, k + 1, dh2, 0);
-    const int nbn = krylov_blocks(N);
+    const int nb1 = std::min(nb, cap_dots), nb2 = std::min(nb, cap_axpy);
+    k_dots<T, KMAX, VW><<<nb1, KB, 0, s>>>(V, ld, k, w, n, part);
+    k_reduce_cols<<<k, KB, 0, s>>>(part, nb1, k, dh1, 0);
+    k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, dh1, w, n, part);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, dh2, 0);
+    const long long chunks = (N / VW + KB - 1) / KB;
+    const int nbn = (int)std::max<long long>(1, std::min<long long>(chunks, cap_norm));
     if (model == 0)
         k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, dh2, w, vnext, z, pinv, N, tr, dnrm);
     else

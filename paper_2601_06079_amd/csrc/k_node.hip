@@ -309,6 +309,10 @@ template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                 double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans, int acc)
 {
+    if (g.dim == 3 && !acc) {
+        launch_jvp3d<T>(g, model, f, kappa, mob, inv_dt, U, v, Jv, s, trans);
+        return;
+    }
     const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
     Lin<T> F{(T)f.b0, (T)f.b1, (T)f.b2};
 #define JVP_L(MODEL, TR, AC)                                                                    \

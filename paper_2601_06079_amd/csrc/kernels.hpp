@@ -63,6 +63,12 @@ template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                 double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans = 0,
                 int acc = 0);
+// z-planes per block of launch_jvp3d set by pf_tune_set (0: automatic)
+int tune_jvp3d_planes();
+// 3-D Jv (acc = 0) by element-wise sum factorisation through z-marching LDS tiles
+template <typename T>
+void launch_jvp3d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                  double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans);
 // (block-)Jacobi inverse of dR/dU at U: N (Allen-Cahn) or 4N (Cahn-Hilliard) values
 template <typename T>
 void launch_prec(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,

@@ -45,7 +45,9 @@ NWS<T> layout(const pf_problem* p, void* base)
     const pfk::Geom g = geom_of(p);
     const long long n = ndof(p);
     NWS<T> L{};
-    L.ld = (n + 63) / 64 * 64;
+    // basis columns 256-byte aligned and 1280 bytes off a power-of-two stride, so that
+    // the k streams of a Gram-Schmidt sweep do not start on the same HBM channel
+    L.ld = (n + 63) / 64 * 64 + 1280 / (long long)sizeof(T);
     char* c = static_cast<char*>(base);
     size_t off = 0;
     auto take = [&](size_t b) {

@@ -12,6 +12,7 @@ namespace {
 std::atomic<int> g_rows_override{0};
 std::atomic<int> g_depth_override{0};
 std::atomic<int> g_fuse_override{0};
+std::atomic<int> g_jvp3d_planes{0};
 int g_simds = -1;
 std::mutex g_mu;
 
@@ -72,6 +73,10 @@ int stream2d_depth(const pf_problem* p)
 
 }  // namespace pfapi
 
+namespace pfk {
+int tune_jvp3d_planes() { return pfapi::g_jvp3d_planes.load(); }
+}  // namespace pfk
+
 using namespace pfapi;
 extern "C" {
 int pf_tune_set(int key, int value)
@@ -83,6 +88,8 @@ int pf_tune_set(int key, int value)
         g_depth_override.store(value);
     else if (key == PF_TUNE_STREAM2D_FUSE)
         g_fuse_override.store(value);
+    else if (key == PF_TUNE_JVP3D_PLANES)
+        g_jvp3d_planes.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -106,6 +113,8 @@ int pf_tune_get(int key, int* value)
         *value = g_depth_override.load();
     else if (key == PF_TUNE_STREAM2D_FUSE)
         *value = g_fuse_override.load();
+    else if (key == PF_TUNE_JVP3D_PLANES)
+        *value = g_jvp3d_planes.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

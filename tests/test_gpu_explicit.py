@@ -213,3 +213,21 @@ def test_explicit_temporal_blocking_bitwise(ks, dtype, model, n):
     finally:
         S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
     assert torch.equal(ref, t)
+
+
+@pytest.mark.parametrize("planes", [1, 3, 7, 40])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+def test_jvp3d_plane_counts_agree(planes, model):
+    """The 3-D Jacobian product is bitwise independent of the z-planes per block."""
+    announce("jvp3d planes", planes, model)
+    g, o = pair((33, 17, 29), model, O.F_01, F32, h=1.0, W=1.0, kappa=2.0, mob=0.8)
+    U = dev(_rand_state(o, 0.2, 0.8, seed=21), F32)
+    v = dev(np.random.default_rng(22).standard_normal(o.ndof), F32)
+    ref = S.jvp(g, 2.0, U, v)
+    try:
+        S.tune_set(A.TUNE_JVP3D_PLANES, planes)
+        out = S.jvp(g, 2.0, U, v)
+    finally:
+        S.tune_set(A.TUNE_JVP3D_PLANES, 0)
+    assert torch.equal(ref, out)
+    assert rel_l2(host(out), O.jvp(o, 2.0, host(U).astype(np.float64), host(v).astype(np.float64))) < 1e-5
