@@ -180,7 +180,8 @@ __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, 
                                                        const double* __restrict__ sums,
                                                        const T* __restrict__ w, T* __restrict__ vnext,
                                                        T* __restrict__ z, const T* __restrict__ pinv,
-                                                       long long N, int tr, double* __restrict__ nrm2)
+                                                       long long N, int tr, double* __restrict__ nrm2,
+                                                       double* __restrict__ nrm2_host)
 {
     double hh[KMAX];
     double hsq = 0.0;
@@ -191,7 +192,10 @@ __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, 
     }
     const double nn = sums[k] - hsq;
     const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) nrm2[0] = nn > 0.0 ? nn : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        nrm2[0] = nn > 0.0 ? nn : 0.0;
+        if (nrm2_host) __hip_atomic_store(nrm2_host, nn > 0.0 ? nn : 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     const long long nv = N / VW;
     for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
         const long long o = e * VW;
@@ -262,15 +266,22 @@ __global__ __launch_bounds__(KB) void k_norm2(const T* __restrict__ a, const T* 
 }
 
 // out[i] (op)= sum_b part[i * nb + b], one block per i, fixed order
+// (host: optional host-mapped copy of out, written with system-scope stores so
+// that the host reads it once the kernel has completed)
 __global__ __launch_bounds__(KB) void k_reduce_cols(const double* __restrict__ part, int nb, int k,
-                                                    double* __restrict__ out, int accumulate)
+                                                    double* __restrict__ out, int accumulate,
+                                                    double* __restrict__ host = nullptr)
 {
     const int i = blockIdx.x;
     if (i >= k) return;
     double a[1] = {0.0};
     for (int b = threadIdx.x; b < nb; b += KB) a[0] += part[(long long)i * nb + b];
     block_sum<1>(a);
-    if (threadIdx.x == 0) out[i] = accumulate ? out[i] + a[0] : a[0];
+    if (threadIdx.x == 0) {
+        const double r = accumulate ? out[i] + a[0] : a[0];
+        out[i] = r;
+        if (host) __hip_atomic_store(host + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // v = w / sqrt(nrm2[0]) (0 when the norm is 0);  z = P^-1 v
@@ -387,6 +398,37 @@ __global__ __launch_bounds__(KB) void k_add_maxabs(T* __restrict__ x, const T* _
     }
 }
 
+// out[0] = max_b part[2b], out[1] = max_b part[2b+1]; one block (host: optional
+// host-mapped copy, system-scope stores)
+__global__ __launch_bounds__(KB) void k_max_pairs(const double* __restrict__ part, int nb,
+                                                  double* __restrict__ out, double* __restrict__ host)
+{
+    __shared__ double s0[KB], s1[KB];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += KB) {
+        a = fmax(a, part[2 * i]);
+        b = fmax(b, part[2 * i + 1]);
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = KB / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + st]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = s1[0];
+        if (host) {
+            __hip_atomic_store(host, s0[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(host + 1, s1[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 inline unsigned grid1(long long n) { return (unsigned)((n + KB - 1) / KB); }
 
 }  // namespace
@@ -425,8 +467,7 @@ int resident_blocks(K kernel)
 
 template <typename T, int KMAX, int VW>
 void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
-            long long N, long long n, double* part, double* dh1, double* dh2, double* dnrm, int tr,
-            hipStream_t s)
+            long long N, long long n, double* part, const KrOut& o, int tr, hipStream_t s)
 {
     static const int cap_dots = resident_blocks(k_dots<T, KMAX, VW>);
     static const int cap_axpy = resident_blocks(k_axpy_dots<T, KMAX, VW>);
@@ -436,23 +477,24 @@ void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
     const int nb = krylov_blocks(n);
     const int nb1 = std::min(nb, cap_dots), nb2 = std::min(nb, cap_axpy);
     k_dots<T, KMAX, VW><<<nb1, KB, 0, s>>>(V, ld, k, w, n, part);
-    k_reduce_cols<<<k, KB, 0, s>>>(part, nb1, k, dh1, 0);
-    k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, dh1, w, n, part);
-    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, dh2, 0);
+    k_reduce_cols<<<k, KB, 0, s>>>(part, nb1, k, o.h1, 0, o.host_h1);
+    k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, o.h1, w, n, part);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, o.h2, 0, o.host_h2);
     const long long chunks = (N / VW + KB - 1) / KB;
     const int nbn = (int)std::max<long long>(1, std::min<long long>(chunks, cap_norm));
     if (model == 0)
-        k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, dh2, w, vnext, z, pinv, N, tr, dnrm);
+        k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+                                                            o.nrm2, o.host_nrm2);
     else
-        k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, dh2, w, vnext, z, pinv, N, tr, dnrm);
+        k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+                                                            o.nrm2, o.host_nrm2);
 }
 
 template <typename T, int VW>
 void cgs2_v(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
-            long long N, long long n, double* part, double* dh1, double* dh2, double* dnrm, int tr,
-            hipStream_t s)
+            long long N, long long n, double* part, const KrOut& o, int tr, hipStream_t s)
 {
-#define PF_CGS2(KM) cgs2_k<T, KM, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s)
+#define PF_CGS2(KM) cgs2_k<T, KM, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, o, tr, s)
     if (k <= 4) PF_CGS2(4);
     else if (k <= 8) PF_CGS2(8);
     else if (k <= 12) PF_CGS2(12);
@@ -466,24 +508,25 @@ void cgs2_v(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
 
 template <typename T>
 int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
-            long long N, double* part, double* dh1, double* dh2, double* dnrm, hipStream_t s, int tr)
+            long long N, double* part, const KrOut& o, hipStream_t s, int tr)
 {
     if (k < 1 || k > KR_MAXK) return -1;
     const long long n = (model == 0 ? 1 : 2) * N;
     constexpr int VW = 16 / sizeof(T);
     if (wide_ok<T>(N))
-        cgs2_v<T, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s);
+        cgs2_v<T, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, o, tr, s);
     else
-        cgs2_v<T, 1>(model, V, ld, k, w, vnext, z, pinv, N, n, part, dh1, dh2, dnrm, tr, s);
+        cgs2_v<T, 1>(model, V, ld, k, w, vnext, z, pinv, N, n, part, o, tr, s);
     return 0;
 }
 
 template <typename T>
-void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s)
+void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s,
+              double* host)
 {
     const int nb = krylov_blocks(n);
     k_norm2<T><<<nb, KB, 0, s>>>(a, b, n, part);
-    k_reduce_cols<<<1, KB, 0, s>>>(part, nb, 1, out, 0);
+    k_reduce_cols<<<1, KB, 0, s>>>(part, nb, 1, out, 0, host);
 }
 
 template <typename T>
@@ -519,22 +562,25 @@ void kr_scale(const T* x, T* y, double alpha, long long n, hipStream_t s)
 }
 
 template <typename T>
-void kr_add_maxabs(T* x, const T* y, long long n, double* part, hipStream_t s)
+void kr_add_maxabs(T* x, const T* y, long long n, double* part, double* out, hipStream_t s,
+                   double* host)
 {
-    k_add_maxabs<T><<<krylov_blocks(n), KB, 0, s>>>(x, y, n, part);
+    const int nb = krylov_blocks(n);
+    k_add_maxabs<T><<<nb, KB, 0, s>>>(x, y, n, part);
+    k_max_pairs<<<1, KB, 0, s>>>(part, nb, out, host);
 }
 
 #define INST_KR(T)                                                                              \
     template int kr_cgs2<T>(int, const T*, long long, int, T*, T*, T*, const T*, long long, double*, \
-                            double*, double*, double*, hipStream_t, int);                       \
-    template void kr_norm2<T>(const T*, const T*, long long, double*, double*, hipStream_t);     \
+                            const KrOut&, hipStream_t, int);                                     \
+    template void kr_norm2<T>(const T*, const T*, long long, double*, double*, hipStream_t, double*); \
     template void kr_normalize_prec<T>(int, const T*, const double*, T*, T*, const T*, long long, \
                                        double, hipStream_t, int);                               \
     template void kr_update<T>(int, const T*, long long, int, const double*, const T*, T*,       \
                                long long, hipStream_t, int);                                    \
     template void kr_rsub<T>(const T*, T*, long long, hipStream_t);                              \
     template void kr_scale<T>(const T*, T*, double, long long, hipStream_t);                     \
-    template void kr_add_maxabs<T>(T*, const T*, long long, double*, hipStream_t);
+    template void kr_add_maxabs<T>(T*, const T*, long long, double*, double*, hipStream_t, double*);
 INST_KR(float)
 INST_KR(double)
 

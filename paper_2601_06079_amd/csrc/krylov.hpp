@@ -9,19 +9,26 @@ int krylov_blocks(long long n);
 
 // largest basis handled by one Gram-Schmidt step
 constexpr int KR_MAXK = 32;
+// Outputs of one Gram-Schmidt step: device buffers (h1, h2: KR_MAXK + 1
+// doubles, nrm2: 1), and optional host-mapped copies of the same values
+// (written with system-scope stores; null to skip).
+struct KrOut {
+    double *h1, *h2, *nrm2;
+    double *host_h1, *host_h2, *host_nrm2;
+};
 // One Arnoldi orthogonalisation (CGS2) of w against the k basis vectors V
 // (N nodes, 1 plane for model 0, 2 for model 1; leading dimension ld):
-//   dh1[0..k) = V^T w, w <- w - V dh1, dh2[0..k) = V^T w, dh2[k] = ||w||^2,
-//   dnrm[0] = ||w - V dh2||^2, vnext = (w - V dh2) / sqrt(dnrm[0]) (0 if that is 0),
+//   h1[0..k) = V^T w, w <- w - V h1, h2[0..k) = V^T w, h2[k] = ||w||^2,
+//   nrm2[0] = ||w - V h2||^2, vnext = (w - V h2) / sqrt(nrm2[0]) (0 if that is 0),
 //   z = P^-1 vnext.  w is left after the first correction.  part: (k + 1) *
 //   krylov_blocks(n) doubles.  Returns -1 (nothing launched) for k outside 1..KR_MAXK.
 template <typename T>
 int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
-            long long N, double* part, double* dh1, double* dh2, double* dnrm, hipStream_t s,
-            int tr = 0);
-// out[0] = ||a - b||^2 (b may be null)
+            long long N, double* part, const KrOut& o, hipStream_t s, int tr = 0);
+// out[0] = ||a - b||^2 (b may be null); host: optional host-mapped copy
 template <typename T>
-void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s);
+void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s,
+              double* host = nullptr);
 // v = sign * w / sqrt(nrm2[0]) ; z = P^-1 v (pinv null: identity; z null: skipped;
 // tr = 1: transposed 2x2 blocks).  N = nodes (the vectors hold 1 or 2 planes).
 template <typename T>
@@ -37,8 +44,10 @@ void kr_rsub(const T* b, T* w, long long n, hipStream_t s);
 // y = alpha x
 template <typename T>
 void kr_scale(const T* x, T* y, double alpha, long long n, hipStream_t s);
-// x += y ; part[2b] = max|y|, part[2b+1] = max|x| per block (krylov_blocks(n) blocks)
+// x += y ; out[0] = max|y|, out[1] = max|x| (part: 2 krylov_blocks(n) doubles;
+// host: optional host-mapped copy of out)
 template <typename T>
-void kr_add_maxabs(T* x, const T* y, long long n, double* part, hipStream_t s);
+void kr_add_maxabs(T* x, const T* y, long long n, double* part, double* out, hipStream_t s,
+                   double* host = nullptr);
 
 }  // namespace pfk

@@ -73,12 +73,25 @@ enum { DEV_H1 = 0, DEV_H2 = MAXM + 1, DEV_NRM = 2 * (MAXM + 1), DEV_Y = 2 * (MAX
        DEV_MISC = 3 * (MAXM + 1) + 2 };
 
 // Pinned host slots for the Hessenberg columns, two per host thread and device
-// (allocated on first use and kept until the process ends), and the events that
-// mark each slot's copy.
+// (allocated on first use and kept until the process ends; the Gram-Schmidt
+// kernels store into them directly), and the events that mark each slot's step.
+// Layout (doubles): [slot 0: DEV_Y | slot 1: DEV_Y | y: MAXM | scalars: 8].
 struct ColReadback {
-    double* host = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    double* host = nullptr;      // host address of the slots
+    double* host_dev = nullptr;  // the same memory as the device addresses it
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // slot 0, slot 1, scalars
+    double* y() const { return host + 2 * DEV_Y; }
+    double* scal() const { return host + 2 * DEV_Y + MAXM; }
+    double* scal_dev() const { return host_dev + 2 * DEV_Y + MAXM; }
+    // wait for the scalars written by kernels queued so far on s
+    int wait_scalars(hipStream_t s) const
+    {
+        if (hipEventRecord(ev[2], s) != hipSuccess || hipEventSynchronize(ev[2]) != hipSuccess)
+            return check_launch("scalar readback");
+        return PF_OK;
+    }
 };
+constexpr size_t RB_DOUBLES = 2 * DEV_Y + MAXM + 8;
 
 int col_readback(ColReadback** out)
 {
@@ -90,13 +103,17 @@ int col_readback(ColReadback** out)
     ColReadback& r = rb[dev];
     if (!r.host) {
         double* h = nullptr;
-        hipError_t e = hipHostMalloc((void**)&h, 2 * DEV_Y * sizeof(double), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void**)&h, RB_DOUBLES * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return fail(PF_EDEVICE, "pinned GMRES readback buffer: %s", hipGetErrorString(e));
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 3; ++i) {
             e = hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming);
             if (e != hipSuccess) return fail(PF_EDEVICE, "GMRES readback event: %s", hipGetErrorString(e));
         }
+        double* hd = nullptr;
+        e = hipHostGetDevicePointer((void**)&hd, h, 0);
+        if (e != hipSuccess) return fail(PF_EDEVICE, "GMRES readback mapping: %s", hipGetErrorString(e));
         r.host = h;
+        r.host_dev = hd;
     }
     *out = &r;
     return PF_OK;
@@ -144,14 +161,6 @@ int d2h(void* dst, const void* src, size_t bytes, hipStream_t s)
     if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return check_launch("device-to-host read");
-    return PF_OK;
-}
-
-int h2d(void* dst, const void* src, size_t bytes, hipStream_t s)
-{
-    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return check_launch("host-to-device write");
     return PF_OK;
 }
 
@@ -204,10 +213,9 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
         } else {
             A.apply(L.x, L.w, s);
             pfk::kr_rsub<T>(L.b, L.w, n, s);
-            pfk::kr_norm2<T>(L.w, nullptr, n, L.part, dnrm, s);
-            double nn;
-            if (int rc = d2h(&nn, dnrm, sizeof(double), s)) return rc;
-            beta = std::sqrt(nn);
+            pfk::kr_norm2<T>(L.w, nullptr, n, L.part, dnrm, s, rb->scal_dev());
+            if (int rc = rb->wait_scalars(s)) return rc;
+            beta = std::sqrt(rb->scal()[0]);
             *res = beta;
             if (!std::isfinite(beta)) return fail(PF_ENONFINITE, "GMRES residual is not finite");
             if (beta <= tol_abs || total >= max_its) break;
@@ -220,13 +228,12 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
         // column goes to pinned slot i % 2
         auto enqueue = [&](int i) -> int {
             A.apply(L.z, L.w, s);
+            double* slot = rb->host_dev + (i & 1) * DEV_Y;
+            const pfk::KrOut out{dh1, dh2, dnrm, slot + DEV_H1, slot + DEV_H2, slot + DEV_NRM};
             if (pfk::kr_cgs2<T>(model, L.V, L.ld, i + 1, L.w, L.V + (long long)(i + 1) * L.ld, L.z, pinv,
-                                Nn, L.part, dh1, dh2, dnrm, s, tr))
+                                Nn, L.part, out, s, tr))
                 return fail(PF_EINVAL, "Gram-Schmidt basis of %d vectors", i + 1);
-            double* slot = rb->host + (i & 1) * DEV_Y;
-            if (hipMemcpyAsync(slot, L.dev, DEV_Y * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipEventRecord(rb->ev[i & 1], s) != hipSuccess)
-                return check_launch("GMRES column readback");
+            if (hipEventRecord(rb->ev[i & 1], s) != hipSuccess) return check_launch("GMRES column readback");
             return PF_OK;
         };
         int j = 0;
@@ -274,7 +281,11 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
             y[i] = H[i * MAXM + i] != 0.0 ? sum / H[i * MAXM + i] : 0.0;
         }
         if (j > 0) {
-            if (int rc = h2d(dy, y.data(), (size_t)j * sizeof(double), s)) return rc;
+            // pinned source: the copy is asynchronous; the host rewrites y only after
+            // waiting on work queued behind it
+            std::copy(y.begin(), y.begin() + j, rb->y());
+            if (hipMemcpyAsync(dy, rb->y(), (size_t)j * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+                return check_launch("GMRES solution coefficients");
             pfk::kr_update<T>(model, L.V, L.ld, j, dy, pinv, L.x, Nn, s, tr);
         }
         if (done || total >= max_its) break;
@@ -301,12 +312,14 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
     double* dnrm = L.dev + DEV_NRM;
     double* dmisc = L.dev + DEV_MISC;
     pf_newton_report R{};
+    ColReadback* rb = nullptr;
+    if (int rc = col_readback(&rb)) return rc;
+    // ||R(U)||, read back together with whatever scalars were queued before it
     auto residual_norm = [&](double* out) -> int {
         pfk::launch_residual<T>(g, p->model, f, p->kappa, p->mobility, U, L.R, s, Uold, inv_dt);
-        pfk::kr_norm2<T>(L.R, nullptr, n, L.part, dnrm, s);
-        double nn;
-        if (int rc = d2h(&nn, dnrm, sizeof(double), s)) return rc;
-        *out = std::sqrt(nn);
+        pfk::kr_norm2<T>(L.R, nullptr, n, L.part, dnrm, s, rb->scal_dev());
+        if (int rc = rb->wait_scalars(s)) return rc;
+        *out = std::sqrt(rb->scal()[0]);
         return PF_OK;
     };
     double r0;
@@ -344,17 +357,11 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
             break;
         }
         R.gmres_its += its;
-        pfk::kr_add_maxabs<T>(U, L.x, n, L.part, s);
-        const int nb = pfk::krylov_blocks(n);
-        std::vector<double> mx(2 * nb);
-        if (int rc = d2h(mx.data(), L.part, mx.size() * sizeof(double), s)) return rc;
-        dmax = umax = 0.0;
-        for (int b = 0; b < nb; ++b) {
-            dmax = std::max(dmax, mx[2 * b]);
-            umax = std::max(umax, mx[2 * b + 1]);
-        }
+        pfk::kr_add_maxabs<T>(U, L.x, n, L.part, dmisc, s, rb->scal_dev() + 1);
         rprev = rk;
         if (int rc = residual_norm(&rk)) return rc;
+        dmax = rb->scal()[1];
+        umax = rb->scal()[2];
         ++k;
         if (k <= 32) R.res_norm[k] = rk;
         if (!std::isfinite(rk)) {
@@ -362,7 +369,6 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
             status = fail(PF_ENONFINITE, "Newton residual is not finite");
         }
     }
-    (void)dmisc;
     R.newton_its = k;
     if (rep) *rep = R;
     if (status != PF_OK) return status;
