@@ -481,6 +481,7 @@ def main():
         out["ac128_fp64"] = ac128_record(stream)
         out["adjoint"] = adjoint_record(stream)
         out["surrogate"] = surrogate_record(stream)
+        out["implicit_ch3d128"] = implicit_record(20, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)
