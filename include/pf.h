@@ -53,10 +53,13 @@ enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
 enum { PF_F32 = 0, PF_F64 = 1 };
 
 /* Problem statement: grid, boundary condition, model, free energy and the
- * material parameters theta = (mobility, kappa, W) of Eqs. 1, 5-6, 9-10. */
+ * material parameters theta = (mobility, kappa, W) of Eqs. 1, 5-6, 9-10.
+ * Periodic grids have n elements per axis (domain length n h); no-flux grids
+ * (the natural boundary condition of the weak form, Supp. Note 3) have n - 1,
+ * and the lumped mass of a node on b boundary faces is h^dim / 2^b. */
 typedef struct pf_problem {
     int32_t dim;      /* 2 or 3 */
-    int32_t bc;       /* PF_PERIODIC (PF_NOFLUX: PF_EUNSUPPORTED in this build) */
+    int32_t bc;       /* PF_PERIODIC or PF_NOFLUX (natural boundary; batches: periodic only) */
     int32_t model;    /* PF_ALLEN_CAHN or PF_CAHN_HILLIARD */
     int32_t fe;       /* PF_F_SYM or PF_F_01 */
     int32_t dtype;    /* PF_F32 or PF_F64 */
@@ -85,7 +88,9 @@ const char* pf_last_error(void);
 int pf_version(void);
 
 /* Launch-shape overrides, process-global (value 0 restores the automatic
- * choice).  Used by the autotuner; results never depend on them.
+ * choice).  Used by the autotuner; results never depend on them, except that on
+ * no-flux grids the steps fused per launch change boundary-adjacent values in
+ * the last bits (a fused stage evaluates the reflected ghost rows).
  *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel;
  *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);

@@ -55,9 +55,8 @@ int validate(const pf_problem* p)
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(PF_EINVAL, "h must be finite and > 0");
     if (!std::isfinite(p->W) || !std::isfinite(p->kappa) || !std::isfinite(p->mobility))
         return fail(PF_EINVAL, "W, kappa and mobility must be finite");
-    if (p->bc == PF_NOFLUX)
-        return fail(PF_EUNSUPPORTED, "no-flux boundaries are not implemented in this build");
-    if (p->bc != PF_PERIODIC) return fail(PF_EINVAL, "unknown boundary condition %d", p->bc);
+    if (p->bc != PF_PERIODIC && p->bc != PF_NOFLUX)
+        return fail(PF_EINVAL, "unknown boundary condition %d", p->bc);
     return PF_OK;
 }
 
@@ -80,6 +79,7 @@ pfk::Geom geom_of(const pf_problem* p)
         g.N *= g.n[k];
     }
     g.h = p->h;
+    g.bc = p->bc == PF_NOFLUX ? 1 : 0;
     return g;
 }
 

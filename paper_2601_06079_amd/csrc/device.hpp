@@ -95,4 +95,22 @@ __host__ __device__ __forceinline__ int wrap(int i, int n)
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Node index i (any integer) reflected about the end nodes 0 and n - 1 (n >= 2):
+// the even extension of a no-flux grid, period 2 (n - 1).
+__host__ __device__ __forceinline__ int reflect(int i, int n)
+{
+    const int p = 2 * (n - 1);
+    i %= p;
+    if (i < 0) i += p;
+    return i < n ? i : p - i;
+}
+
+// No-flux grids by reflection.  On the even extension of a field about the end
+// nodes, every ghost element is the mirror image of a real element and adds the
+// same contribution to the boundary node.  So at a node on b boundary faces the
+// periodic-style node formula applied to reflected neighbours gives 2^b times
+// the no-flux row (and the periodic lumped mass is 2^b times the no-flux one);
+// dividing by 2^b restores the row, and ratios such as r/m need no correction.
+__host__ __device__ __forceinline__ int edge_count(int i, int n) { return (i == 0) + (i == n - 1); }
+
 }  // namespace pfk

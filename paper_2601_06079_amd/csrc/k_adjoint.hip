@@ -71,6 +71,7 @@ __global__ __launch_bounds__(AB) void k_dtheta(const T* __restrict__ U, const T*
         const T h = (T)g.h;
         const double n1 = (double)(detJ * quad_sum<T, D, false>(u, u, F1));
         const double ku = (double)stiff<T, D>(u, h);
+        scale /= bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
         if constexpr (MODEL == 0) {
             const double wi = scale * (double)w[idx];
             t0 = wi * ((double)W * n1 + (double)kappa * ku);
@@ -88,18 +89,24 @@ __global__ __launch_bounds__(AB) void k_dtheta(const T* __restrict__ U, const T*
     block_partials3(t0, t1, t2, part);
 }
 
-// Ubar[a] += inv_dt m lambda[a] on the first N entries (the rows with mass)
-template <typename T>
+// Ubar[a] += inv_dt m_a lambda[a] on the first N entries (the rows with mass);
+// c = inv_dt h^d, m_a = h^d / 2^b on a no-flux grid
+template <typename T, int D>
 __global__ __launch_bounds__(AB) void k_mass_axpy(const T* __restrict__ lam, T* __restrict__ ub,
-                                                  long long N, T c)
+                                                  Geom g, T c)
 {
-    const long long i = (long long)blockIdx.x * AB + threadIdx.x;
-    if (i < N) ub[i] += c * lam[i];
+    const long long idx = (long long)blockIdx.x * AB + threadIdx.x;
+    int i, j, k;
+    if (!node_of<D>(g, idx, i, j, k)) return;
+    ub[idx] += c / (T)bfactor<D>(g, i, j, k) * lam[idx];
 }
 
 // Allen-Cahn explicit step S(eta) = eta - dt r(eta)/m:
 //   Ubar += vbar - (dt/m) J_r(eta) vbar   (J_r symmetric)
 //   theta partials of -(dt/m) vbar^T dr/dtheta
+// On a no-flux grid (m_a = h^d / 2^b, rows = reflected rows / 2^b) the first line
+// is vbar - (dt/h^d) [J_reflected (2^b vbar)] / 2^b and the theta partials use the
+// reflected rows unscaled.
 template <typename T, int D>
 __global__ __launch_bounds__(AB) void k_vjp_ac_step(const T* __restrict__ eta,
                                                     const T* __restrict__ vb, T* __restrict__ ub,
@@ -113,12 +120,13 @@ __global__ __launch_bounds__(AB) void k_vjp_ac_step(const T* __restrict__ eta,
     if (node_of<D>(g, idx, i, j, k)) {
         T u[NB<D>::K], v[NB<D>::K];
         gather<T, D>(eta, g, i, j, k, u);
-        gather<T, D>(vb, g, i, j, k, v);
+        gather<T, D, true>(vb, g, i, j, k, v);
         const T h = (T)g.h;
         const T Nv = detJ * quad_sum<T, D, true>(u, v, F2);
         const T Kv = stiff<T, D>(v, h);
-        const T vc = v[NB<D>::K / 2];
-        ub[idx] += vc - dt_over_m * mob * (Nv + kappa * Kv);
+        const T vc = vb[idx];
+        const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);
+        ub[idx] += vc - dt_over_m * mob * (Nv + kappa * Kv) * ib;
         const double n1 = (double)(detJ * quad_sum<T, D, false>(u, u, F1));
         const double ku = (double)stiff<T, D>(u, h);
         const double wi = -(double)dt_over_m * (double)vc;
@@ -130,6 +138,8 @@ __global__ __launch_bounds__(AB) void k_vjp_ac_step(const T* __restrict__ eta,
 }
 
 // Cahn-Hilliard split step S(c) = c - dt M^-1 [M_mob K] M^-1 A(c), A = W N_1 + kappa K.
+// On a no-flux grid pass a applies K to 2^b vbar and pass b divides its rows by 2^b
+// (t itself is (M dt / h^2d) K_reflected(2^b vbar), with no further factor).
 // Pass a: t = mob K (dt vbar / m) / m ; theta_M partial -sum (dt vbar/m) (K mu), mu = A(c)/m
 template <typename T, int D>
 __global__ __launch_bounds__(AB) void k_vjp_ch_a(const T* __restrict__ mu, const T* __restrict__ vb,
@@ -141,11 +151,11 @@ __global__ __launch_bounds__(AB) void k_vjp_ch_a(const T* __restrict__ mu, const
     int i, j, k;
     if (node_of<D>(g, idx, i, j, k)) {
         T v[NB<D>::K], w[NB<D>::K];
-        gather<T, D>(vb, g, i, j, k, v);
+        gather<T, D, true>(vb, g, i, j, k, v);  // 2^b vbar on no-flux grids
         gather<T, D>(mu, g, i, j, k, w);
         const T h = (T)g.h;
         t[idx] = mob * dt_over_m * stiff<T, D>(v, h) * inv_m;
-        t0 = -(double)dt_over_m * (double)v[NB<D>::K / 2] * (double)stiff<T, D>(w, h);
+        t0 = -(double)dt_over_m * (double)vb[idx] * (double)stiff<T, D>(w, h);
     }
     block_partials3(t0, 0.0, 0.0, part);
 }
@@ -165,9 +175,10 @@ __global__ __launch_bounds__(AB) void k_vjp_ch_b(const T* __restrict__ c, const 
         gather<T, D>(c, g, i, j, k, u);
         gather<T, D>(t, g, i, j, k, v);
         const T h = (T)g.h;
-        const T At = detJ * quad_sum<T, D, true>(u, v, F2) + kappa * stiff<T, D>(v, h);
+        const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
+        const T At = (detJ * quad_sum<T, D, true>(u, v, F2) + kappa * stiff<T, D>(v, h)) * ib;
         ub[idx] += vb[idx] - At;
-        const double ti = (double)v[NB<D>::K / 2];
+        const double ti = (double)v[NB<D>::K / 2] * (double)ib;
         t1 = -ti * (double)stiff<T, D>(u, h);
         t2 = -ti * (double)(detJ * quad_sum<T, D, false>(u, u, F1));
     }
@@ -219,7 +230,7 @@ template <typename T>
 void launch_mass_axpy(const Geom& g, double inv_dt, const T* lam, T* ub, hipStream_t s)
 {
     const double m = std::pow(g.h, g.dim);
-    k_mass_axpy<T><<<nblk(g), AB, 0, s>>>(lam, ub, g.N, (T)(inv_dt * m));
+    DIM_SWITCH(g, { k_mass_axpy<T, D><<<nblk(g), AB, 0, s>>>(lam, ub, g, (T)(inv_dt * m)); });
 }
 
 template <typename T>

@@ -5,7 +5,8 @@
 // its 8 elements; every point is thus evaluated 8 times.  Here every element is
 // evaluated once per tile:
 //   - a block owns 15 x 15 output columns (x, y) and a run of tz planes in z;
-//   - the 17 x 17 node patch (one halo node on each side) of every z-plane is
+//   - the 17 x 17 node patch (one halo node on each side, wrapped on periodic
+//     grids, reflected about the end nodes on no-flux grids) of every z-plane is
 //     staged in LDS; the 16 x 16 elements of each slab between two planes are
 //     computed one per thread: nodal c and v interpolated to the 8 Gauss points
 //     (three 1-D passes), f''(c_q) v_q |J| formed there and scattered back to the
@@ -163,13 +164,13 @@ __global__ __launch_bounds__(NT) void k_jvp3d(const T* __restrict__ U, const T* 
         const int q = t + k * NT;
         const int f = q < NF * PA ? q / PA : -1;
         const int r = q % PA;
-        const int gx = ((x0 - 1 + r % PT) % n0 + n0) % n0;
-        const int gy = ((y0 - 1 + r / PT) % n1 + n1) % n1;
+        const int gx = g.bc ? reflect(x0 - 1 + r % PT, n0) : ((x0 - 1 + r % PT) % n0 + n0) % n0;
+        const int gy = g.bc ? reflect(y0 - 1 + r / PT, n1) : ((y0 - 1 + r / PT) % n1 + n1) % n1;
         ld_src[k] = f < 0 ? U : (f == 0 ? U : (f == 1 ? V : V + g.N)) + (long long)gy * n0 + gx;
         ld_l[k] = f < 0 ? NF * PA : q;
     }
     auto fetch = [&](int p, T (&buf)[NLD]) {
-        const long long zo = (long long)(((p % n2) + n2) % n2) * plane;
+        const long long zo = (long long)(g.bc ? reflect(p, n2) : ((p % n2) + n2) % n2) * plane;
 #pragma unroll
         for (int k = 0; k < NLD; ++k) buf[k] = ld_src[k][zo];
     };
@@ -234,19 +235,24 @@ __global__ __launch_bounds__(NT) void k_jvp3d(const T* __restrict__ U, const T* 
                     const int e = (iy + 1 - ay) * ET + (ix + 1 - ax);
                     nv += et[slot ^ 1][ay * 2 + ax][e] + eb[ay * 2 + ax][e];
                 }
-            const long long o = (long long)(z0 + it - 2) * plane + (long long)(y0 + iy) * n0 + x0 + ix;
+            const int zc = z0 + it - 2;
+            const long long o = (long long)zc * plane + (long long)(y0 + iy) * n0 + x0 + ix;
+            // no-flux: the reflected rows are 2^b times the node's row
+            T ib = (T)1;
+            if (g.bc)
+                ib = (T)1 / (T)(1 << (edge_count(x0 + ix, n0) + edge_count(y0 + iy, n1) + edge_count(zc, n2)));
             if constexpr (MODEL == 0) {
                 const T kv = ring[0].stiff(h36);
-                Jv[o] = inv_dt * m * ring[0].c[1] + mob * (nv + kappa * kv);
+                Jv[o] = (inv_dt * m * ring[0].c[1] + mob * (nv + kappa * kv)) * ib;
             } else {
                 const T kc = ring[0].stiff(h36), km = ring[1].stiff(h36);
                 const T vc = ring[0].c[1], vm = ring[1].c[1];
                 if constexpr (TRANS == 0) {
-                    Jv[o] = inv_dt * m * vc + mob * km;
-                    Jv[g.N + o] = m * vm - (nv + kappa * kc);
+                    Jv[o] = (inv_dt * m * vc + mob * km) * ib;
+                    Jv[g.N + o] = (m * vm - (nv + kappa * kc)) * ib;
                 } else {
-                    Jv[o] = inv_dt * m * vc - (nv + kappa * km);
-                    Jv[g.N + o] = mob * kc + m * vm;
+                    Jv[o] = (inv_dt * m * vc - (nv + kappa * km)) * ib;
+                    Jv[g.N + o] = (mob * kc + m * vm) * ib;
                 }
             }
         }

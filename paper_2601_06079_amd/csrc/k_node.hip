@@ -27,13 +27,14 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const
     const T Nn = detJ * quad_sum<T, D, false>(u, u, F);
     const T Ku = stiff<T, D>(u, h);
     const T tt = Uold ? inv_dt * m * (u[NB<D>::K / 2] - Uold[idx]) : (T)0;
+    const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
-        r[idx] = mob * (Nn + kappa * Ku) + tt;
+        r[idx] = (mob * (Nn + kappa * Ku) + tt) * ib;
     } else {
         T w[NB<D>::K];
         gather<T, D>(U + g.N, g, i, j, k, w);
-        r[idx] = mob * stiff<T, D>(w, h) + tt;
-        r[g.N + idx] = m * w[NB<D>::K / 2] - (Nn + kappa * Ku);
+        r[idx] = (mob * stiff<T, D>(w, h) + tt) * ib;
+        r[g.N + idx] = (m * w[NB<D>::K / 2] - (Nn + kappa * Ku)) * ib;
     }
 }
 
@@ -52,11 +53,12 @@ __global__ __launch_bounds__(256) void k_prec(const T* __restrict__ U, T* __rest
     gather<T, D>(U, g, i, j, k, u);
     const double nd = (double)(detJ * quad_sum_sq<T, D>(u, F));
     const double kd = (double)stiff_diag<T, D>((T)g.h);
+    const double ib = 1.0 / bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
-        pinv[idx] = (T)(1.0 / ((double)inv_dt * m + (double)mob * (nd + (double)kappa * kd)));
+        pinv[idx] = (T)(1.0 / (ib * ((double)inv_dt * m + (double)mob * (nd + (double)kappa * kd))));
     } else {
-        const double a = (double)inv_dt * m, b = (double)mob * kd;
-        const double c = -(nd + (double)kappa * kd), d = (double)m;
+        const double a = ib * (double)inv_dt * m, b = ib * (double)mob * kd;
+        const double c = -ib * (nd + (double)kappa * kd), d = ib * (double)m;
         const double det = a * d - b * c;
         T* P = pinv + 4 * idx;
         P[0] = (T)(d / det);
@@ -81,11 +83,12 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
     T u[NB<D>::K], v[NB<D>::K];
     gather<T, D>(U, g, i, j, k, u);
     const T h = (T)g.h;
+    const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
         gather<T, D>(V, g, i, j, k, v);
         const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
         const T Kv = stiff<T, D>(v, h);
-        const T out = inv_dt * m * v[NB<D>::K / 2] + mob * (Nv + kappa * Kv);
+        const T out = (inv_dt * m * v[NB<D>::K / 2] + mob * (Nv + kappa * Kv)) * ib;
         Jv[idx] = ACC ? Jv[idx] + out : out;
     } else {
         T w[NB<D>::K];
@@ -101,6 +104,8 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
             oc = inv_dt * m * v[NB<D>::K / 2] - (Nw + kappa * stiff<T, D>(w, h));
             om = mob * stiff<T, D>(v, h) + m * w[NB<D>::K / 2];
         }
+        oc *= ib;
+        om *= ib;
         Jv[idx] = ACC ? Jv[idx] + oc : oc;
         Jv[g.N + idx] = ACC ? Jv[g.N + idx] + om : om;
     }
@@ -144,7 +149,8 @@ __global__ __launch_bounds__(256) void k_ac_step(const T* __restrict__ eta, T* _
 }
 
 // ---- energy and mass ---------------------------------------------------------
-// Each thread owns the element whose lower corner is its node.
+// Each thread owns the element whose lower corner is its node (none past the upper
+// boundary of a no-flux grid) and the mass term of its node.
 __device__ __forceinline__ double f_local(int fe, double W, double q)
 {
     if (fe == 0) {
@@ -216,6 +222,12 @@ __global__ __launch_bounds__(EBLK) void k_energy(const T* __restrict__ c, double
                                      0.5 * kappa * (gx * gx + gy * gy + gz * gz));
                     }
             ms = h * h * h * u[0][0][0];
+        }
+        // no-flux: the element exists only below the upper boundary; lumped mass h^d / 2^b
+        if (g.bc) {
+            const bool elem = i + 1 < g.n[0] && j + 1 < g.n[1] && (D == 2 || k + 1 < g.n[2]);
+            if (!elem) e = 0.0;
+            ms /= bfactor<D>(g, i, j, k);
         }
     }
     // block reduction, fixed order: wave shuffle tree, then waves in order

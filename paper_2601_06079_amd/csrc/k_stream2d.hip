@@ -101,7 +101,10 @@ struct Stage {
 // arithmetic of a single-step launch, so the result is bitwise that of KS
 // single steps.  PF: rows in flight per wave (register prefetch ring depth).
 // Must be called by a whole wave with wave-uniform arguments.
-template <typename T, int MODEL, int PF, int KS, bool MID = false>
+// MIRROR: no-flux grid, read through the even extension about the end rows and
+// columns (reflect); the lumped update r/m of a boundary node is then exactly the
+// interior formula (see reflect in device.hpp), for every fused stage.
+template <typename T, int MODEL, int PF, int KS, bool MID = false, bool MIRROR = false>
 __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restrict__ out, int nx,
                                             int ny, int strip, int y0, int y1, unsigned bytes,
                                             const Coef<T>& k, T* __restrict__ mid = nullptr)
@@ -112,8 +115,13 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     const int lane = threadIdx.x & (WAVE - 1);
     const int x0 = strip * OUTW;
     const int xl = x0 - HK + lane;
-    int x = xl % nx;
-    if (x < 0) x += nx;
+    int x;
+    if constexpr (MIRROR) {
+        x = reflect(xl, nx);
+    } else {
+        x = xl % nx;
+        if (x < 0) x += nx;
+    }
     const bool out_lane = lane >= HK && lane < WAVE - HK && xl < nx;
     const int iters = (y1 - y0) + 2 * HK;  // rows y0-HK .. y1+HK-1
     const int rowb = nx * (int)sizeof(T);  // bytes per row
@@ -129,19 +137,37 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     // stores), so the register window never needs merging; only the prefetch
     // and the store are predicated.
     T ring[PF];
-    int rl = y0 - HK;
-    while (rl < 0) rl += ny;
+    // periodic: rl is the physical row and wraps; MIRROR: lr is the logical row
+    // and rl its reflection
+    int lr = y0 - HK;
+    int rl = lr;
+    if constexpr (MIRROR) {
+        rl = reflect(lr, ny);
+    } else {
+        while (rl < 0) rl += ny;
+    }
+    auto advance = [&]() {
+        if constexpr (MIRROR) {
+            rl = reflect(++lr, ny);
+        } else {
+            if (++rl == ny) rl = 0;
+        }
+    };
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         ring[u] = u < iters ? bload<T>(rin, vx, rl * rowb) : (T)0;
-        if (++rl == ny) rl = 0;
+        advance();
     }
     // The prefetch load itself is unconditional: once the chunk's last row has
     // been requested the row index stops advancing and the same row is read
     // again (a cache hit).  A conditional load would make the compiler wait for
     // it immediately.
     int rlast = y1 + HK - 1;
-    while (rlast >= ny) rlast -= ny;
+    if constexpr (MIRROR) {
+        rlast = reflect(rlast, ny);
+    } else {
+        while (rlast >= ny) rlast -= ny;
+    }
     for (int t0 = 0; t0 < iters; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -149,7 +175,7 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
             T v = ring[u];
             ring[u] = bload<T>(rin, vx, rl * rowb);
             if (t + PF + 1 < iters) {
-                if (++rl == ny) rl = 0;
+                advance();
             } else {
                 rl = rlast;
             }
@@ -168,7 +194,7 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     }
 }
 
-template <typename T, int MODEL, int PF, int KS>
+template <typename T, int MODEL, int PF, int KS, bool MIRROR = false>
 __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
                                                     int nx, int ny, int nstrips, int nwaves, int nchunks,
                                                     unsigned bytes, Coef<T> k)
@@ -179,7 +205,7 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     const int chunk = wave / nstrips;
     const int y0 = (int)((long long)chunk * ny / nchunks);
     const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
-    stream_item<T, MODEL, PF, KS>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
+    stream_item<T, MODEL, PF, KS, false, MIRROR>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
 }
 
 // Ragged batch: wave w processes work item items[w] = (sample, strip, chunk)
@@ -204,9 +230,11 @@ __global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict_
 
 template <typename T, int MODEL, int KS>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-                  int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k)
+                  int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc)
 {
-    if (depth <= 4)
+    if (bc)  // no-flux grids: one prefetch depth
+        k_explicit2d<T, MODEL, 4, KS, true><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+    else if (depth <= 4)
         k_explicit2d<T, MODEL, 4, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     else if (depth <= 8)
         k_explicit2d<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
@@ -216,13 +244,13 @@ void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int
 
 template <typename T, int MODEL>
 void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-               int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k)
+               int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc)
 {
     switch (ks) {
-        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
-        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
-        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
-        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k); break;
+        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
+        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
+        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
+        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
     }
 }
 
@@ -293,13 +321,13 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
         const double sc = dt * mob * detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
     } else {
         const double sc = detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(kappa / (3.0 * m));
         k.gamma = (T)(dt * mob / (3.0 * m));
-        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
     }
 }
 

@@ -5,12 +5,14 @@
 
 namespace pfk {
 
-// Geometry of a periodic structured grid (x fastest).
+// Geometry of a structured grid (x fastest).  bc 0: periodic; bc 1: no-flux
+// (natural boundary, n - 1 elements per axis).
 struct Geom {
     int dim;
     int n[3];
     long long N;  // nodes
     double h;
+    int bc;
 };
 
 // Free-energy polynomials with W folded in.

@@ -21,28 +21,64 @@ struct NB {
     static constexpr int K = D == 2 ? 9 : 27;
 };
 
-// Neighbourhood index: (dx+1) + 3 (dy+1) + 9 (dz+1)
-template <typename T, int D>
+// neighbour i + d (d = -1, +1) of node i on an axis of n nodes: periodic wrap,
+// or reflection about the end node on a no-flux grid
+__device__ __forceinline__ int nbr(int i, int d, int n, int bc)
+{
+    const int t = i + d;
+    if (bc) return t < 0 ? 1 : (t >= n ? n - 2 : t);
+    return t < 0 ? t + n : (t >= n ? t - n : t);
+}
+
+// 2^b for a node on b boundary faces of a no-flux grid (1 on periodic grids)
+template <int D>
+__device__ __forceinline__ int bfactor(const Geom& g, int i, int j, int k)
+{
+    if (!g.bc) return 1;
+    int b = (i == 0 || i == g.n[0] - 1) + (j == 0 || j == g.n[1] - 1);
+    if (D == 3) b += (k == 0 || k == g.n[2] - 1);
+    return 1 << b;
+}
+
+// Neighbourhood index: (dx+1) + 3 (dy+1) + 9 (dz+1).  SCALED multiplies every
+// gathered value by its node's 2^b (used where an operator acts on D u).
+template <typename T, int D, bool SCALED = false>
 __device__ __forceinline__ void gather(const T* __restrict__ u, const Geom& g, int i, int j, int k,
                                        T out[NB<D>::K])
 {
-    const int xs[3] = {wrap(i - 1, g.n[0]), i, wrap(i + 1, g.n[0])};
-    const int ys[3] = {wrap(j - 1, g.n[1]), j, wrap(j + 1, g.n[1])};
+    const int xs[3] = {nbr(i, -1, g.n[0], g.bc), i, nbr(i, 1, g.n[0], g.bc)};
+    const int ys[3] = {nbr(j, -1, g.n[1], g.bc), j, nbr(j, 1, g.n[1], g.bc)};
+    T fx[3] = {(T)1, (T)1, (T)1}, fy[3] = {(T)1, (T)1, (T)1}, fz[3] = {(T)1, (T)1, (T)1};
+    if (SCALED && g.bc) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            fx[a] = (T)(1 << edge_count(xs[a], g.n[0]));
+            fy[a] = (T)(1 << edge_count(ys[a], g.n[1]));
+        }
+    }
     if constexpr (D == 2) {
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) out[a + 3 * b] = u[(long long)ys[b] * g.n[0] + xs[a]];
+            for (int a = 0; a < 3; ++a) {
+                out[a + 3 * b] = u[(long long)ys[b] * g.n[0] + xs[a]];
+                if (SCALED) out[a + 3 * b] *= fx[a] * fy[b];
+            }
     } else {
-        const int zs[3] = {wrap(k - 1, g.n[2]), k, wrap(k + 1, g.n[2])};
+        const int zs[3] = {nbr(k, -1, g.n[2], g.bc), k, nbr(k, 1, g.n[2], g.bc)};
+        if (SCALED && g.bc)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fz[c] = (T)(1 << edge_count(zs[c], g.n[2]));
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
+                for (int a = 0; a < 3; ++a) {
                     out[a + 3 * b + 9 * c] =
                         u[((long long)zs[c] * g.n[1] + ys[b]) * g.n[0] + xs[a]];
+                    if (SCALED) out[a + 3 * b + 9 * c] *= fx[a] * fy[b] * fz[c];
+                }
     }
 }
 

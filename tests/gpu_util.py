@@ -9,10 +9,11 @@ from paper_2601_06079_amd import solver as S
 DEV = "cuda"
 
 
-def pair(n, model, fe, dtype, h=1.0, W=1.0, kappa=1.0, mob=1.0):
+def pair(n, model, fe, dtype, h=1.0, W=1.0, kappa=1.0, mob=1.0, bc=O.PERIODIC):
     """The same problem for the GPU library and for the oracle."""
-    g = S.Problem(n=tuple(n), model=model, fe=fe, dtype=dtype, h=h, W=W, kappa=kappa, mobility=mob)
-    o = O.Problem(n=tuple(n), model=model, fe=fe, h=h, W=W, kappa=kappa, mob=mob)
+    g = S.Problem(n=tuple(n), model=model, fe=fe, dtype=dtype, h=h, W=W, kappa=kappa, mobility=mob,
+                  bc=A.NOFLUX if bc == O.NOFLUX else A.PERIODIC)
+    o = O.Problem(n=tuple(n), model=model, fe=fe, h=h, W=W, kappa=kappa, mob=mob, bc=bc)
     return g, o
 
 

@@ -35,8 +35,7 @@ def test_version(L):
     (dict(dim=4), A.PF_EINVAL), (dict(model=7), A.PF_EINVAL), (dict(fe=9), A.PF_EINVAL),
     (dict(dtype=3), A.PF_EINVAL), (dict(reserved=1), A.PF_EINVAL), (dict(n=(1, 8, 1)), A.PF_EINVAL),
     (dict(h=0.0), A.PF_EINVAL), (dict(h=float("nan")), A.PF_EINVAL),
-    (dict(kappa=float("inf")), A.PF_EINVAL), (dict(bc=A.NOFLUX), A.PF_EUNSUPPORTED),
-    (dict(bc=5), A.PF_EINVAL)])
+    (dict(kappa=float("inf")), A.PF_EINVAL), (dict(bc=5), A.PF_EINVAL)])
 def test_problem_validation(L, bad, status):
     p = _prob(**bad)
     nb = ct.c_size_t(0)
@@ -77,3 +76,10 @@ def test_tuning_roundtrip(L):
     assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, 0) == A.PF_OK
     assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, -3) == A.PF_EINVAL
     assert L.pf_tune_set(77, 1) == A.PF_EINVAL
+
+
+def test_noflux_problem_accepted(L):
+    """No-flux grids are valid single-problem input (batches stay periodic-only)."""
+    p = _prob(bc=A.NOFLUX)
+    nb = ct.c_size_t(0)
+    assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == A.PF_OK
