@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c")]
+_SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c"),
+        os.path.join(_HERE, "coupled_oracle.c")]
 
 PERIODIC, NOFLUX = 0, 1
 AC, CH = 0, 1
@@ -110,6 +111,8 @@ def lib():
             fn.argtypes = args
         if hasattr(_lib, "orc_nn"):
             _bind_conv(_lib)
+        if hasattr(_lib, "orc_cp_residual"):
+            _bind_coupled(_lib)
     return _lib
 
 
@@ -273,3 +276,88 @@ def adam(p, m, v, g, lr, b1, b2, eps, t):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _arr(g, p.size)
     lib().orc_adam(p.size, _d(p), _d(m), _d(v), _d(g), lr, b1, b2, eps, int(t))
+
+
+# ---------------------------------------------------------------------------
+# Coupled Allen-Cahn / Cahn-Hilliard model (Eq. 7 with the polynomials of
+# Supplementary Note 3); states are [c ; mu ; eta].  See coupled_oracle.c.
+class _CpProblem(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
+                ("Mc", ct.c_double), ("Meta", ct.c_double), ("kappa", ct.c_double)]
+
+
+@dataclass
+class CoupledProblem:
+    n: tuple
+    bc: int = PERIODIC
+    h: float = 1.0
+    Mc: float = 1.0
+    Meta: float = 150.0
+    kappa: float = 0.3
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def nnodes(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def ndof(self) -> int:
+        return 3 * self.nnodes
+
+    def _c(self) -> _CpProblem:
+        n3 = list(self.n) + [1] * (3 - len(self.n))
+        return _CpProblem(self.dim, self.bc, (ct.c_int64 * 3)(*n3), self.h, self.Mc, self.Meta,
+                          self.kappa)
+
+
+def _bind_coupled(L):
+    P = ct.POINTER(_CpProblem)
+    D = ct.POINTER(ct.c_double)
+    f64 = ct.c_double
+    for name in ("orc_cp_fa", "orc_cp_dfa", "orc_cp_fb", "orc_cp_dfb", "orc_cp_h", "orc_cp_dh"):
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = f64, [f64]
+    for name, res, args in (("orc_cp_lumped_mass", ct.c_int, [P, D]),
+                            ("orc_cp_residual", ct.c_int, [P, D, D]),
+                            ("orc_cp_explicit", ct.c_int, [P, f64, ct.c_int64, D]),
+                            ("orc_cp_energy", f64, [P, D]),
+                            ("orc_cp_total_mass", f64, [P, D])):
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = res, args
+
+
+def cp_poly(name: str, x: float) -> float:
+    """The benchmark polynomials: fa, dfa, fb, dfb, h, dh."""
+    return getattr(lib(), "orc_cp_" + name)(float(x))
+
+
+def cp_lumped_mass(p: CoupledProblem) -> np.ndarray:
+    m = np.zeros(p.nnodes)
+    lib().orc_cp_lumped_mass(ct.byref(p._c()), _d(m))
+    return m
+
+
+def cp_residual(p: CoupledProblem, U) -> np.ndarray:
+    U = _arr(U, p.ndof)
+    r = np.zeros(p.ndof)
+    lib().orc_cp_residual(ct.byref(p._c()), _d(U), _d(r))
+    return r
+
+
+def cp_explicit(p: CoupledProblem, U, dt: float, nsteps: int) -> np.ndarray:
+    U = _arr(U, p.ndof).copy()
+    lib().orc_cp_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U))
+    return U
+
+
+def cp_energy(p: CoupledProblem, U) -> float:
+    U = _arr(U, p.ndof)
+    return lib().orc_cp_energy(ct.byref(p._c()), _d(U))
+
+
+def cp_total_mass(p: CoupledProblem, U) -> float:
+    U = _arr(U)
+    return lib().orc_cp_total_mass(ct.byref(p._c()), _d(U))
