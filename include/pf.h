@@ -47,7 +47,16 @@ typedef enum pf_status {
 } pf_status;
 
 enum { PF_PERIODIC = 0, PF_NOFLUX = 1 };       /* boundary condition (Supp. Note 3) */
-enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1 };
+enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1,
+       PF_COUPLED = 2 }; /* coupled Allen-Cahn / Cahn-Hilliard of Eq. 7 with the benchmark
+                          * free energies of Supp. Note 3 (fe and W are ignored):
+                          *   f_a(c) = -1.6704 - 4.776c + 5.1622c^2 - 2.7375c^3 + 1.3687c^4,
+                          *   f_b(c) = 5.0c^2 - 5.9746c - 1.5924,
+                          *   h(eta) = 10 eta^3 - 15 eta^4 + 6 eta^5;
+                          * states [c ; mu ; eta], mobility = M_c, mobility_eta = M_eta,
+                          * kappa = kappa_eta (no composition gradient energy).  Supported by
+                          * pf_residual, pf_step_explicit and pf_energy; the others return
+                          * PF_EUNSUPPORTED. */
 enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
        PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
 enum { PF_F32 = 0, PF_F64 = 1 };
@@ -68,7 +77,8 @@ typedef struct pf_problem {
     double h;         /* grid spacing > 0 */
     double W;         /* barrier height of f */
     double kappa;     /* gradient-energy coefficient */
-    double mobility;  /* L (Allen-Cahn) or M (Cahn-Hilliard) */
+    double mobility;  /* L (Allen-Cahn) or M (Cahn-Hilliard); M_c (coupled) */
+    double mobility_eta; /* coupled model: M_eta (ignored by the other models) */
 } pf_problem;
 
 /* Operation codes for pf_workspace_size. */
@@ -114,8 +124,11 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes);
  * where N(u)_a = sum_e sum_q |J| f'(u_q) phi_a(q) (Gauss points q) and K is
  * the Q1 stiffness matrix.  With this r the implicit residual of Eq. 14 is
  * R = M (U - U_old)/dt + r(U) with mass matrix diag(m) (Allen-Cahn) or
- * diag(m, 0) (Cahn-Hilliard).  U and r: device, ndof elements, must not
- * alias.  Asynchronous. */
+ * diag(m, 0) (Cahn-Hilliard).
+ *   Coupled (Eq. 7):  r_c   = M_c K mu
+ *                     r_mu  = m mu - sum_e sum_q |J| [f_a'(c_q)(1 - h(eta_q)) + f_b'(c_q) h(eta_q)] phi_a
+ *                     r_eta = M_eta [ sum_e sum_q |J| (f_b - f_a)(c_q) h'(eta_q) phi_a + kappa K eta ]
+ * U and r: device, ndof elements (N, 2N or 3N), must not alias.  Asynchronous. */
 int pf_residual(const pf_problem* p, const void* U, void* r, void* stream);
 
 /* nsteps forward-Euler steps of Eq. 12 with the lumped mass, in place on U:
@@ -124,12 +137,18 @@ int pf_residual(const pf_problem* p, const void* U, void* r, void* stream);
  *                   (the algebraic mu-row of the split form solved each step);
  *                   on return the mu plane holds [N(c) + kappa K c]/m of the
  *                   final c.
+ *   Coupled:        mu <- g(c, eta)/m and eta <- eta - dt r_eta(c, eta)/m from the
+ *                   old state, then c <- c - dt M_c K mu / m; on return the mu
+ *                   plane holds g/m of the final state.
  * ws: device scratch of pf_workspace_size(PF_OP_STEP_EXPLICIT) bytes (one
- * ping-pong field).  nsteps >= 0, dt > 0.  Asynchronous. */
+ * ping-pong field; two for the coupled model).  nsteps >= 0, dt > 0.
+ * Asynchronous. */
 int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
                      void* stream);
 
 /* out[0] = E_h(U) = sum_e sum_q |J| [ f(c_q) + kappa/2 |grad c_q|^2 ]  (Eqs. 5-6)
+ *          (coupled model: [f_a(c_q)(1 - h(eta_q)) + f_b(c_q) h(eta_q) + kappa/2 |grad eta_q|^2],
+ *          Eq. 7, with U the whole [c ; mu ; eta] state)
  * out[1] = sum_a m_a c_a  (total conserved quantity)
  * out: device pointer to 2 doubles; accumulation in FP64 with a fixed
  * reduction order (bitwise reproducible).  ws: pf_workspace_size(PF_OP_ENERGY).

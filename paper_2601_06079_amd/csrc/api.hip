@@ -40,9 +40,12 @@ int validate(const pf_problem* p)
 {
     if (!p) return fail(PF_EINVAL, "problem is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(PF_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
-    if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD)
+    if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD && p->model != PF_COUPLED)
         return fail(PF_EINVAL, "unknown model %d", p->model);
-    if (p->fe != PF_F_SYM && p->fe != PF_F_01) return fail(PF_EINVAL, "unknown free energy %d", p->fe);
+    if (p->model == PF_COUPLED && !std::isfinite(p->mobility_eta))
+        return fail(PF_EINVAL, "mobility_eta must be finite");
+    if (p->model != PF_COUPLED && p->fe != PF_F_SYM && p->fe != PF_F_01)
+        return fail(PF_EINVAL, "unknown free energy %d", p->fe);
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
     if (p->reserved != 0) return fail(PF_EINVAL, "reserved field must be 0");
     long long N = 1;
@@ -86,7 +89,7 @@ pfk::Geom geom_of(const pf_problem* p)
 long long ndof(const pf_problem* p)
 {
     const pfk::Geom g = geom_of(p);
-    return (p->model == PF_CAHN_HILLIARD ? 2 : 1) * g.N;
+    return (p->model == PF_COUPLED ? 3 : p->model == PF_CAHN_HILLIARD ? 2 : 1) * g.N;
 }
 
 size_t elem_size(const pf_problem* p) { return p->dtype == PF_F64 ? 8 : 4; }
@@ -97,9 +100,34 @@ using namespace pfapi;
 
 namespace {
 
+// coupled model: node-centric path, ws = [c ping-pong field | eta ping-pong field]
+template <typename T>
+int step_coupled_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    T* c = U;
+    T* mu = U + g.N;
+    T* eta = U + 2 * g.N;
+    T *cc = c, *co = ws, *ec = eta, *eo = ws + g.N;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        pfk::launch_cp_mu_eta<T>(g, p->kappa, dt * p->mobility_eta, cc, ec, mu, eo, s);
+        pfk::launch_ch_update<T>(g, dt * p->mobility, cc, mu, co, s);
+        std::swap(cc, co);
+        std::swap(ec, eo);
+    }
+    if (cc != c) {
+        if (hipMemcpyAsync(c, cc, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(eta, ec, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return check_launch("coupled step copy-back");
+    }
+    pfk::launch_cp_mu_eta<T>(g, p->kappa, 0.0, c, eta, mu, (T*)nullptr, s);
+    return check_launch("coupled explicit step");
+}
+
 template <typename T>
 int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
+    if (p->model == PF_COUPLED) return step_coupled_t<T>(p, dt, nsteps, U, ws, s);
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     T* c = U;
@@ -162,10 +190,14 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
     switch (op) {
         case PF_OP_RESIDUAL:
         case PF_OP_JVP: b = 0; break;
-        case PF_OP_STEP_EXPLICIT: b = (size_t)g.N * es; break;
+        case PF_OP_STEP_EXPLICIT: b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : 1); break;
         case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
-        case PF_OP_NEWTON: b = newton_workspace_bytes(p, 30); break;
-        case PF_OP_VJP: b = vjp_workspace_bytes(p); break;
+        case PF_OP_NEWTON:
+        case PF_OP_VJP:
+            if (p->model == PF_COUPLED)
+                return fail(PF_EUNSUPPORTED, "coupled model: explicit steps, residual and energy only");
+            b = op == PF_OP_NEWTON ? newton_workspace_bytes(p, 30) : vjp_workspace_bytes(p);
+            break;
         default: return fail(PF_EINVAL, "unknown op %d", op);
     }
     *bytes = b;
@@ -181,6 +213,15 @@ int pf_residual(const pf_problem* p, const void* U, void* r, void* stream)
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_COUPLED) {
+        if (p->dtype == PF_F32)
+            pfk::launch_cp_residual<float>(g, p->kappa, p->mobility, p->mobility_eta, (const float*)U,
+                                           (float*)r, s);
+        else
+            pfk::launch_cp_residual<double>(g, p->kappa, p->mobility, p->mobility_eta,
+                                            (const double*)U, (double*)r, s);
+        return check_launch("pf_residual");
+    }
     if (p->dtype == PF_F32)
         pfk::launch_residual<float>(g, p->model, f, p->kappa, p->mobility, (const float*)U,
                                     (float*)r, s);
@@ -212,6 +253,13 @@ int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* s
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_COUPLED) {
+        if (p->dtype == PF_F32)
+            pfk::launch_cp_energy<float>(g, p->kappa, (const float*)U, (double*)ws, out, s);
+        else
+            pfk::launch_cp_energy<double>(g, p->kappa, (const double*)U, (double*)ws, out, s);
+        return check_launch("pf_energy");
+    }
     if (p->dtype == PF_F32)
         pfk::launch_energy<float>(g, f, p->kappa, (const float*)U, (double*)ws, out, s);
     else
@@ -227,6 +275,7 @@ int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, voi
     if (int rc = check_ptr(v, p, "v")) return rc;
     if (int rc = check_ptr(Jv, p, "Jv")) return rc;
     if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
+    if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_jvp: coupled model not implemented");
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;

@@ -291,6 +291,11 @@ Cub<T> cub_of(const FreeEnergy& f, double scale)
 
 int energy_blocks(const Geom& g) { return (int)((g.N + EBLK - 1) / EBLK); }
 
+void launch_reduce_pairs(const double* part, int nb, double* out, hipStream_t s)
+{
+    k_reduce_pairs<<<1, 256, 0, s>>>(part, nb, out);
+}
+
 #define DIM_SWITCH(g, ...)         \
     if ((g).dim == 2) {            \
         constexpr int D = 2;       \

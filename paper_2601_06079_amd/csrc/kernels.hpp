@@ -93,6 +93,23 @@ void launch_energy(const Geom& g, const FreeEnergy& f, double kappa, const T* c,
                    double* out, hipStream_t s);
 int energy_blocks(const Geom& g);
 
+// out[0] = sum_b part[2b], out[1] = sum_b part[2b+1] (one block, fixed order)
+void launch_reduce_pairs(const double* part, int nb, double* out, hipStream_t s);
+
+// ---- coupled Allen-Cahn / Cahn-Hilliard (k_coupled.hip); states [c ; mu ; eta] --
+// mu = g(c, eta)/m; with eta_out != nullptr also eta_out = eta - dt M_eta r_eta/M_eta/m
+template <typename T>
+void launch_cp_mu_eta(const Geom& g, double kappa, double dt_Meta, const T* c, const T* eta, T* mu,
+                      T* eta_out, hipStream_t s);
+// r = [M_c K mu ; m mu - g(c, eta) ; M_eta (s(c, eta) + kappa K eta)]
+template <typename T>
+void launch_cp_residual(const Geom& g, double kappa, double Mc, double Meta, const T* U, T* r,
+                        hipStream_t s);
+// out[0] = E_h(c, eta), out[1] = sum m c; partials: 2 * energy_blocks(g) doubles
+template <typename T>
+void launch_cp_energy(const Geom& g, double kappa, const T* U, double* partials, double* out,
+                      hipStream_t s);
+
 // ---- sensitivities (k_adjoint.hip) -----------------------------------------
 // theta_bar[0..3) += scale * w^T dr/dtheta at U (part: 3 * ceil(N/256) doubles)
 template <typename T>

@@ -25,6 +25,7 @@ class Problem:
     kappa: float = 1.0
     mobility: float = 1.0
     bc: int = A.PERIODIC
+    mobility_eta: float = 0.0  # coupled model: M_eta
 
     @property
     def dim(self):
@@ -39,14 +40,14 @@ class Problem:
 
     @property
     def ndof(self):
-        return (2 if self.model == A.CAHN_HILLIARD else 1) * self.nnodes
+        return {A.CAHN_HILLIARD: 2, A.COUPLED: 3}.get(self.model, 1) * self.nnodes
 
     def c(self) -> A.pf_problem:
         n3 = [int(v) for v in self.n] + [1] * (3 - len(self.n))
         return A.pf_problem(self.dim, self.bc, self.model, self.fe,
                             A.F64 if self.dtype == torch.float64 else A.F32, 0,
                             (ct.c_int64 * 3)(*n3), float(self.h), float(self.W),
-                            float(self.kappa), float(self.mobility))
+                            float(self.kappa), float(self.mobility), float(self.mobility_eta))
 
 
 def _stream():
