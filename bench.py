@@ -34,7 +34,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # non-packed FP32 FMA issue: 78.6
 BYTES_PER_NODE_STEP = 8  # read c, write c (FP32) per launch; mu never leaves the chip
-FLOPS_PER_NODE_STEP_CH = 69  # sum-factorised Q1 split step, FMA = 2 flops (see DESIGN)
+FLOPS_PER_NODE_STEP_CH = 69
+# coupled model, per node-step with every Gauss point evaluated once (FMA = 2):
+# interpolation of c and eta 30, the two sources at 4 points 144 (f_a 8, f_a' 6, f_b 4,
+# f_b' 2, h 7, h' 4, combinations 5), scatters 36, mu/eta'/c' updates 19
+FLOPS_PER_NODE_STEP_COUPLED = 229  # sum-factorised Q1 split step, FMA = 2 flops (see DESIGN)
 METRIC = "DOF-steps/sec + %HBM peak (explicit CH, 4.19M DOF); adjoint & surrogate speedup"
 
 
@@ -48,6 +52,9 @@ def parse():
     ap.add_argument("--n", type=int, default=2048, help="grid side (default: the 2048^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--coupled", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS explicit steps of the 1024^2 coupled Allen-Cahn/"
+                         "Cahn-Hilliard benchmark shape and print their record")
     ap.add_argument("--implicit", type=int, default=0, metavar="STEPS",
                     help="only time STEPS backward-Euler Newton steps of the 128^3 Cahn-Hilliard "
                          "workload (4.19M DOF) and print their record")
@@ -222,6 +229,35 @@ def ac128_record(stream, steps=1000):
             "ms_per_step": ms / steps, "dof_steps_per_s": n * steps / (ms * 1e-3)}
 
 
+def coupled_record(stream, n=1024, steps=2000):
+    """Coupled Allen-Cahn / Cahn-Hilliard benchmark shape (Eq. 7, Supp. Note 3):
+    [0, 100]^2 with n^2 nodes, no-flux, M_c = 1, M_eta = 150, kappa_eta = 0.3, FP32,
+    explicit steps at dt = 5e-7 (the explicit limit of the c-equation at h = 100/1023).
+    DOF = 2 n^2 (c and eta are time-integrated; mu is the algebraic row)."""
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    cfg = I.COUPLED
+    p = S.Problem(n=(n, n), model=A.COUPLED, dtype=torch.float32, h=cfg["L"] / (n - 1),
+                  kappa=cfg["kappa"], mobility=cfg["Mc"], mobility_eta=cfg["Meta"], bc=A.NOFLUX)
+    U = torch.as_tensor(I.coupled_state(n, seed=0, dtype="float32"), device="cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    S.step_explicit(p, U, 5e-7, 200, ws)  # warm-up
+    ms = _time_ms(lambda: S.step_explicit(p, U, 5e-7, steps, ws), stream)
+    dof = 2 * n * n
+    tflops = FLOPS_PER_NODE_STEP_COUPLED * n * n * steps / (ms * 1e-3) / 1e12
+    return {"workload": f"coupled Allen-Cahn/Cahn-Hilliard {n}x{n} on [0,100]^2, no-flux, "
+                        "M_c=1, M_eta=150, kappa_eta=0.3, FP32 explicit dt=5e-7",
+            "dof": dof, "steps": steps, "ms_per_step": ms / steps,
+            "dof_steps_per_s": dof * steps / (ms * 1e-3),
+            "roofline": {"bound": "alu", "kernel": "k_cp_explicit2d<float, no-flux>",
+                         "flops_per_node_step": FLOPS_PER_NODE_STEP_COUPLED, "achieved": tflops,
+                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
+                         "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
+
+
 def adjoint_record(stream, count=64, nsteps=2000, every=100):
     """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
     2000 FP32 steps, dt = 0.05): forward with a snapshot every 100 steps plus the
@@ -362,13 +398,15 @@ def implicit_record(steps, stream):
 
 def main():
     args = parse()
-    if args.implicit or args.surrogate_gain or args.adjoint:
+    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled:
         import torch
         stream = torch.cuda.current_stream()
         if args.adjoint:
             print(json.dumps(adjoint_record(stream)), flush=True)
         if args.implicit:
             print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
+        if args.coupled:
+            print(json.dumps(coupled_record(stream, steps=args.coupled)), flush=True)
         if args.surrogate_gain:
             from paper_2601_06079_amd import nn as NN
             rec = NN.gain_experiment(train_iters=args.surrogate_gain,
@@ -482,6 +520,7 @@ def main():
         out["adjoint"] = adjoint_record(stream)
         out["surrogate"] = surrogate_record(stream)
         out["implicit_ch3d128"] = implicit_record(20, stream)
+        out["coupled_1024"] = coupled_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -4,6 +4,7 @@
 // enqueued, converts the problem statement into kernel parameters and
 // launches on the caller's stream.  No exception crosses the ABI; errors are
 // reported as pf_status plus a thread-local message.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -109,9 +110,17 @@ int step_coupled_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, 
     T* mu = U + g.N;
     T* eta = U + 2 * g.N;
     T *cc = c, *co = ws, *ec = eta, *eo = ws + g.N;
+    // 2-D: the fused streaming kernel (32-bit buffer offsets); else node-centric kernels
+    const bool fused2d = p->dim == 2 && (size_t)g.N * sizeof(T) < (size_t(1) << 31);
+    const int rows = stream2d_rows(p, 1);
     for (int64_t st = 0; st < nsteps; ++st) {
-        pfk::launch_cp_mu_eta<T>(g, p->kappa, dt * p->mobility_eta, cc, ec, mu, eo, s);
-        pfk::launch_ch_update<T>(g, dt * p->mobility, cc, mu, co, s);
+        if (fused2d) {
+            pfk::launch_cp_explicit2d<T>(g, p->kappa, p->mobility, p->mobility_eta, dt, cc, ec, co, eo,
+                                         rows, s);
+        } else {
+            pfk::launch_cp_mu_eta<T>(g, p->kappa, dt * p->mobility_eta, cc, ec, mu, eo, s);
+            pfk::launch_ch_update<T>(g, dt * p->mobility, cc, mu, co, s);
+        }
         std::swap(cc, co);
         std::swap(ec, eo);
     }

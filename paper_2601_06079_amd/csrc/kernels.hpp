@@ -105,6 +105,11 @@ void launch_cp_mu_eta(const Geom& g, double kappa, double dt_Meta, const T* c, c
 template <typename T>
 void launch_cp_residual(const Geom& g, double kappa, double Mc, double Meta, const T* U, T* r,
                         hipStream_t s);
+// one fused explicit step of the coupled model on a 2-D grid (k_stream_cp.hip):
+// (c_in, e_in) -> (c_out, e_out); rows: rows per wavefront (0: 32)
+template <typename T>
+void launch_cp_explicit2d(const Geom& g, double kappa, double Mc, double Meta, double dt, const T* c_in,
+                          const T* e_in, T* c_out, T* e_out, int rows, hipStream_t s);
 // out[0] = E_h(c, eta), out[1] = sum m c; partials: 2 * energy_blocks(g) doubles
 template <typename T>
 void launch_cp_energy(const Geom& g, double kappa, const T* U, double* partials, double* out,

@@ -46,7 +46,7 @@ int stream2d_rows(const pf_problem* p, int ks)
 {
     const int ov = g_rows_override.load();
     if (ov > 0) return ov;
-    const int HK = (p->model == PF_CAHN_HILLIARD ? 2 : 1) * ks;
+    const int HK = (p->model == PF_ALLEN_CAHN ? 1 : 2) * ks;  // Cahn-Hilliard and coupled: 2 per step
     const long long nx = p->n[0], ny = p->n[1];
     const long long strips = (nx + (64 - 2 * HK) - 1) / (64 - 2 * HK);
     const long long S = device_simds();
@@ -56,7 +56,10 @@ int stream2d_rows(const pf_problem* p, int ks)
     // avoids a partly filled last round.  Chunks are never shorter than 8 rows.
     // Longer chunks mean a grid of many rounds, where the measured best is 32
     // rows for single steps and 48 for fused ones.
-    long long nch = std::max<long long>(1, 4 * S / strips);
+    // (coupled model: six, measured at 512^2..2048^2; its pipeline is VALU-bound and
+    // light on registers)
+    const long long waves = p->model == PF_COUPLED ? 6 : 4;
+    long long nch = std::max<long long>(1, waves * S / strips);
     nch = std::min(nch, std::max<long long>(1, ny / 8));
     long long ty = (ny + nch - 1) / nch;
     const long long tmax = ks == 1 ? 32 : 48;

@@ -59,3 +59,27 @@ def batch_samples(count=64, nmin=128, nmax=512, seed=0):
     hidden = np.exp(rng.uniform(np.log(0.5), np.log(2.0), size=(count, 3)))
     fields = [rng.uniform(-0.05, 0.05, int(s) * int(s)) for s in sizes]
     return sizes, theta, hidden, fields
+
+
+# Coupled Allen-Cahn / Cahn-Hilliard benchmark shape: the square [0, 100]^2 with
+# n nodes per axis (h = 100 / (n - 1)), no-flux boundaries, M_c = 1, M_eta = 150,
+# kappa_eta = 0.3.  Initial state: discs of the second phase (eta ~ 1) with a
+# diffuse edge of width 2, in a matrix (eta ~ 0); c = 0.04 + 0.12 eta plus
+# N(0, 0.005^2) noise; mu plane zero.  (The paper's own initial condition is a
+# figure, not data; this is a stand-in of the same kind.)
+COUPLED = dict(L=100.0, Mc=1.0, Meta=150.0, kappa=0.3, discs=((50.0, 50.0, 20.0),
+                                                               (20.0, 25.0, 8.0),
+                                                               (78.0, 70.0, 12.0)))
+
+
+def coupled_state(n, seed=0, dtype=np.float64):
+    """[c ; mu ; eta] on an n x n grid over [0, L]^2 (see COUPLED)."""
+    L = COUPLED["L"]
+    h = L / (n - 1)
+    X, Y = np.meshgrid(np.arange(n) * h, np.arange(n) * h)
+    eta = np.zeros((n, n))
+    for (x0, y0, r0) in COUPLED["discs"]:
+        eta = np.maximum(eta, 0.5 * (1.0 - np.tanh((np.hypot(X - x0, Y - y0) - r0) / 2.0)))
+    rng = np.random.default_rng(seed)
+    c = 0.04 + 0.12 * eta + 0.005 * rng.standard_normal((n, n))
+    return np.concatenate([c.ravel(), np.zeros(n * n), eta.ravel()]).astype(dtype)
