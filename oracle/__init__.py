@@ -317,20 +317,25 @@ def _bind_coupled(L):
     P = ct.POINTER(_CpProblem)
     D = ct.POINTER(ct.c_double)
     f64 = ct.c_double
-    for name in ("orc_cp_fa", "orc_cp_dfa", "orc_cp_fb", "orc_cp_dfb", "orc_cp_h", "orc_cp_dh"):
+    for name in ("orc_cp_fa", "orc_cp_dfa", "orc_cp_fb", "orc_cp_dfb", "orc_cp_h", "orc_cp_dh",
+                 "orc_cp_d2fa", "orc_cp_d2fb", "orc_cp_d2h"):
         fn = getattr(L, name)
         fn.restype, fn.argtypes = f64, [f64]
     for name, res, args in (("orc_cp_lumped_mass", ct.c_int, [P, D]),
                             ("orc_cp_residual", ct.c_int, [P, D, D]),
                             ("orc_cp_explicit", ct.c_int, [P, f64, ct.c_int64, D]),
                             ("orc_cp_energy", f64, [P, D]),
-                            ("orc_cp_total_mass", f64, [P, D])):
+                            ("orc_cp_total_mass", f64, [P, D]),
+                            ("orc_cp_be_residual", ct.c_int, [P, f64, D, D, D]),
+                            ("orc_cp_jvp", ct.c_int, [P, f64, D, D, D]),
+                            ("orc_cp_newton_be", ct.c_int, [P, f64, D, D, f64, ct.c_int,
+                                                            ct.POINTER(ct.c_int)])):
         fn = getattr(L, name)
         fn.restype, fn.argtypes = res, args
 
 
 def cp_poly(name: str, x: float) -> float:
-    """The benchmark polynomials: fa, dfa, fb, dfb, h, dh."""
+    """The benchmark polynomials: fa, dfa, d2fa, fb, dfb, d2fb, h, dh, d2h."""
     return getattr(lib(), "orc_cp_" + name)(float(x))
 
 
@@ -361,3 +366,26 @@ def cp_energy(p: CoupledProblem, U) -> float:
 def cp_total_mass(p: CoupledProblem, U) -> float:
     U = _arr(U)
     return lib().orc_cp_total_mass(ct.byref(p._c()), _d(U))
+
+
+def cp_be_residual(p: CoupledProblem, dt: float, Uold, U) -> np.ndarray:
+    Uold, U = _arr(Uold, p.ndof), _arr(U, p.ndof)
+    R = np.zeros(p.ndof)
+    lib().orc_cp_be_residual(ct.byref(p._c()), dt, _d(Uold), _d(U), _d(R))
+    return R
+
+
+def cp_jvp(p: CoupledProblem, inv_dt: float, U, v) -> np.ndarray:
+    U, v = _arr(U, p.ndof), _arr(v, p.ndof)
+    Jv = np.zeros(p.ndof)
+    lib().orc_cp_jvp(ct.byref(p._c()), inv_dt, _d(U), _d(v), _d(Jv))
+    return Jv
+
+
+def cp_newton_be(p: CoupledProblem, dt: float, Uold, U0=None, rtol=1e-12, maxit=30):
+    """One backward-Euler step by Newton with dense LU (small grids). Returns (U, converged, its)."""
+    Uold = _arr(Uold, p.ndof)
+    U = (Uold if U0 is None else _arr(U0, p.ndof)).copy()
+    its = ct.c_int(0)
+    rc = lib().orc_cp_newton_be(ct.byref(p._c()), dt, _d(Uold), _d(U), rtol, maxit, ct.byref(its))
+    return U, rc == 0, its.value

@@ -281,3 +281,162 @@ double orc_cp_total_mass(const orc_cp_problem* p, const double* U)
     free(m);
     return s;
 }
+
+/* ------------------------------------------------------------------------ */
+/* backward Euler (Eqs. 13-14) for the coupled model                         */
+/* ------------------------------------------------------------------------ */
+/* second derivatives of the benchmark polynomials */
+double orc_cp_d2fa(double c) { return 2.0 * 5.1622 - 6.0 * 2.7375 * c + 12.0 * 1.3687 * c * c; }
+double orc_cp_d2fb(double c) { (void)c; return 10.0; }
+double orc_cp_d2h(double e) { return 60.0 * e - 180.0 * e * e + 120.0 * e * e * e; }
+
+/* R = M (U - U_old)/dt + r(U), mass on the c and eta rows */
+int orc_cp_be_residual(const orc_cp_problem* p, double dt, const double* Uold, const double* U,
+                       double* R)
+{
+    const int64_t N = cp_nnodes(p);
+    double* m = (double*)malloc((size_t)N * sizeof(double));
+    orc_cp_lumped_mass(p, m);
+    orc_cp_residual(p, U, R);
+    for (int64_t i = 0; i < N; ++i) {
+        R[i] += m[i] * (U[i] - Uold[i]) / dt;
+        R[2 * N + i] += m[i] * (U[2 * N + i] - Uold[2 * N + i]) / dt;
+    }
+    free(m);
+    return 0;
+}
+
+/* Jv = (dR/dU) v, R = inv_dt M (U - U_old) + r(U):
+ *   Jv_c   = inv_dt m v_c + M_c K v_mu
+ *   Jv_mu  = m v_mu - sum_q |J| [g_cc v_c,q + g_ce v_eta,q] phi_a
+ *   Jv_eta = inv_dt m v_eta + M_eta [ sum_q |J| (g_ce v_c,q + s_ee v_eta,q) phi_a + kappa K v_eta ]
+ * with g_cc = f_a''(1 - h) + f_b'' h, g_ce = (f_b' - f_a') h', s_ee = (f_b - f_a) h''. */
+int orc_cp_jvp(const orc_cp_problem* p, double inv_dt, const double* U, const double* v, double* Jv)
+{
+    const int64_t N = cp_nnodes(p);
+    const double *c = U, *eta = U + 2 * N;
+    const double *vc = v, *vm = v + N, *ve = v + 2 * N;
+    cp_ref R;
+    cp_ref_build(&R, p->dim, p->h);
+    double* m = (double*)malloc((size_t)N * sizeof(double));
+    orc_cp_lumped_mass(p, m);
+    memset(Jv, 0, (size_t)(3 * N) * sizeof(double));
+    cp_stiffness(p, vm, Jv); /* K v_mu into the c rows */
+    int64_t E[3], idx[8];
+    CP_FOR_EACH_ELEMENT(p, E)
+    {
+        cp_elem_nodes(p, E, R.nv, idx);
+        for (int q = 0; q < R.nv; ++q) {
+            double cq = 0.0, eq = 0.0, vcq = 0.0, veq = 0.0, gv[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < R.nv; ++a) {
+                cq += R.phi[q][a] * c[idx[a]];
+                eq += R.phi[q][a] * eta[idx[a]];
+                vcq += R.phi[q][a] * vc[idx[a]];
+                veq += R.phi[q][a] * ve[idx[a]];
+                for (int k = 0; k < R.d; ++k) gv[k] += R.grad[q][a][k] * ve[idx[a]];
+            }
+            const double h = orc_cp_h(eq), dh = orc_cp_dh(eq), d2h = orc_cp_d2h(eq);
+            const double gcc = orc_cp_d2fa(cq) * (1.0 - h) + orc_cp_d2fb(cq) * h;
+            const double gce = (orc_cp_dfb(cq) - orc_cp_dfa(cq)) * dh;
+            const double see = (orc_cp_fb(cq) - orc_cp_fa(cq)) * d2h;
+            for (int a = 0; a < R.nv; ++a) {
+                double gg = 0.0;
+                for (int k = 0; k < R.d; ++k) gg += gv[k] * R.grad[q][a][k];
+                Jv[N + idx[a]] -= R.detJ * (gcc * vcq + gce * veq) * R.phi[q][a];
+                Jv[2 * N + idx[a]] +=
+                    p->Meta * R.detJ * ((gce * vcq + see * veq) * R.phi[q][a] + p->kappa * gg);
+            }
+        }
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        Jv[i] = p->Mc * Jv[i] + inv_dt * m[i] * vc[i];
+        Jv[N + i] += m[i] * vm[i];
+        Jv[2 * N + i] += inv_dt * m[i] * ve[i];
+    }
+    free(m);
+    return 0;
+}
+
+/* dense LU with partial pivoting, in place; x <- A^-1 b.  Returns 0 or -1 (singular). */
+static int cp_dense_solve(int64_t n, double* A, double* b)
+{
+    int64_t* piv = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t pr = k;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[pr * n + k])) pr = i;
+        if (A[pr * n + k] == 0.0) {
+            free(piv);
+            return -1;
+        }
+        piv[k] = pr;
+        if (pr != k) {
+            for (int64_t j = 0; j < n; ++j) {
+                const double t = A[k * n + j];
+                A[k * n + j] = A[pr * n + j];
+                A[pr * n + j] = t;
+            }
+            const double t = b[k];
+            b[k] = b[pr];
+            b[pr] = t;
+        }
+        for (int64_t i = k + 1; i < n; ++i) {
+            const double l = A[i * n + k] / A[k * n + k];
+            A[i * n + k] = l;
+            for (int64_t j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int64_t j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
+        b[i] = s / A[i * n + i];
+    }
+    free(piv);
+    return 0;
+}
+
+/* One backward-Euler step by Newton from U (initial guess, in place), dense LU of
+ * the assembled Jacobian (columns from orc_cp_jvp on unit vectors): small grids
+ * only.  Stops at ||R|| <= rtol ||R(U_start)||.  Returns 0 when converged. */
+int orc_cp_newton_be(const orc_cp_problem* p, double dt, const double* Uold, double* U, double rtol,
+                     int maxit, int* its)
+{
+    const int64_t n = 3 * cp_nnodes(p);
+    double* R = (double*)malloc((size_t)n * sizeof(double));
+    double* A = (double*)malloc((size_t)(n * n) * sizeof(double));
+    double* e = (double*)calloc((size_t)n, sizeof(double));
+    double* col = (double*)malloc((size_t)n * sizeof(double));
+    int k = 0, rc = -1;
+    orc_cp_be_residual(p, dt, Uold, U, R);
+    double r0 = 0.0;
+    for (int64_t i = 0; i < n; ++i) r0 += R[i] * R[i];
+    r0 = sqrt(r0);
+    double rk = r0;
+    for (; k <= maxit; ++k) {
+        if (rk <= rtol * r0 || rk == 0.0) {
+            rc = 0;
+            break;
+        }
+        if (k == maxit) break;
+        for (int64_t j = 0; j < n; ++j) {
+            e[j] = 1.0;
+            orc_cp_jvp(p, 1.0 / dt, U, e, col);
+            e[j] = 0.0;
+            for (int64_t i = 0; i < n; ++i) A[i * n + j] = col[i];
+        }
+        for (int64_t i = 0; i < n; ++i) R[i] = -R[i];
+        if (cp_dense_solve(n, A, R)) break;
+        for (int64_t i = 0; i < n; ++i) U[i] += R[i];
+        orc_cp_be_residual(p, dt, Uold, U, R);
+        rk = 0.0;
+        for (int64_t i = 0; i < n; ++i) rk += R[i] * R[i];
+        rk = sqrt(rk);
+    }
+    if (its) *its = k;
+    free(col);
+    free(e);
+    free(A);
+    free(R);
+    return rc;
+}

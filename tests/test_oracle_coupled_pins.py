@@ -125,3 +125,66 @@ def test_explicit_conserves_composition_and_decreases_energy(n, bc):
     V = O.cp_explicit(p, U, 2e-3, 20)
     assert O.cp_total_mass(p, V) == pytest.approx(m0, rel=1e-13)
     assert O.cp_energy(p, V) < e0
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [(4, 3), (2, 3, 2)])
+def test_coupled_jvp_is_the_residual_derivative(n, bc):
+    """Brute force: J v equals the central difference of the backward-Euler residual."""
+    p = O.CoupledProblem(n=n, bc=bc, h=0.8, Mc=1.2, Meta=2.0, kappa=0.4)
+    U = _rand_state(p, 6)
+    Uold = _rand_state(p, 7)
+    v = np.random.default_rng(8).standard_normal(p.ndof)
+    dt, e = 0.3, 1e-6
+    fd = (O.cp_be_residual(p, dt, Uold, U + e * v) - O.cp_be_residual(p, dt, Uold, U - e * v)) / (2 * e)
+    np.testing.assert_allclose(O.cp_jvp(p, 1.0 / dt, U, v), fd, rtol=1e-7, atol=1e-7)
+
+
+def test_coupled_jacobian_mixed_blocks_are_transposes():
+    """d r_mu / d eta = -(1/M_eta) (d r_eta / d c)^T: both are the mixed second
+    derivative of the discrete energy."""
+    p = O.CoupledProblem(n=(5, 4), bc=O.NOFLUX, h=0.9, Meta=3.0)
+    N = p.nnodes
+    U = _rand_state(p, 9)
+    rng = np.random.default_rng(10)
+    a, b = rng.standard_normal(N), rng.standard_normal(N)
+    z = np.zeros(N)
+    # w_mu^T (dr_mu/deta) v_eta  and  w_eta^T (dr_eta/dc) v_c  with w, v swapped
+    left = a @ O.cp_jvp(p, 0.0, U, np.concatenate([z, z, b]))[N:2 * N]
+    right = b @ O.cp_jvp(p, 0.0, U, np.concatenate([a, z, z]))[2 * N:]
+    assert left == pytest.approx(-right / p.Meta, rel=1e-12)
+
+
+def test_coupled_backward_euler_mode_closed_form():
+    """eta = 1: the backward-Euler step damps a composition mode by
+    1 / (1 + dt M_c lam_K 10 s_M / m) (the explicit factor's implicit counterpart)."""
+    n, k, h, dt = (8, 6), (1, 2), 1.1, 0.05
+    p = O.CoupledProblem(n=n, h=h, Mc=0.7, Meta=2.0, kappa=0.3)
+    th = [2 * np.pi * k[i] / n[i] for i in range(2)]
+    X, Y = np.meshgrid(np.arange(n[0]), np.arange(n[1]))
+    mode = np.cos(th[0] * X + th[1] * Y).ravel()
+    N = p.nnodes
+    cbar, A = 0.3, 0.02
+    Uold = np.concatenate([cbar + A * mode, np.zeros(N), np.ones(N)])
+    U, conv, _ = O.cp_newton_be(p, dt, Uold, rtol=1e-13)
+    assert conv
+    lam = (8 - 2 * np.cos(th[0]) - 2 * np.cos(th[1]) - 4 * np.cos(th[0]) * np.cos(th[1])) / 3
+    sM = (2 + np.cos(th[0])) * (2 + np.cos(th[1])) / 9
+    A1 = A / (1 + dt * p.Mc * lam * 10.0 * sM / h ** 2)
+    np.testing.assert_allclose(U[:N], cbar + A1 * mode, atol=1e-12)
+    np.testing.assert_allclose(U[2 * N:], 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_coupled_newton_root_conserves_composition(bc):
+    p = O.CoupledProblem(n=(6, 5), bc=bc, h=1.0, Mc=1.0, Meta=150.0, kappa=0.3)
+    rng = np.random.default_rng(0)
+    N = p.nnodes
+    eta = rng.uniform(0, 1, N)
+    c = 0.04 + 0.12 * eta + 0.005 * rng.standard_normal(N)
+    Uold = O.cp_explicit(p, np.concatenate([c, np.zeros(N), eta]), 1e-3, 0)
+    U, conv, its = O.cp_newton_be(p, 0.01, Uold, rtol=1e-12)
+    assert conv and its <= 8
+    assert np.abs(O.cp_be_residual(p, 0.01, Uold, U)).max() < 1e-11
+    assert O.cp_total_mass(p, U) == pytest.approx(O.cp_total_mass(p, Uold), rel=1e-13)
+    assert O.cp_energy(p, U) < O.cp_energy(p, Uold)
