@@ -258,6 +258,44 @@ def coupled_record(stream, n=1024, steps=2000):
                          "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
 
 
+def coupled_implicit_record(stream, n=512, steps=20, dt=0.01):
+    """The coupled benchmark shape with backward-Euler steps: 512^2, no-flux, dt = 0.01,
+    Newton + GMRES(30) with 3x3 block Jacobi, FP32 fields, FP64 reductions."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    cfg = I.COUPLED
+    p = S.Problem(n=(n, n), model=A.COUPLED, dtype=torch.float32, h=cfg["L"] / (n - 1),
+                  kappa=cfg["kappa"], mobility=cfg["Mc"], mobility_eta=cfg["Meta"], bc=A.NOFLUX)
+    U = torch.as_tensor(I.coupled_state(n, seed=0, dtype="float32"), device="cuda")
+    S.step_explicit(p, U, 1e-9, 0)  # mu consistent with (c, eta)
+    ws = S.workspace(p, A.OP_NEWTON)
+    Uold = torch.empty_like(U)
+    Uold.copy_(U)
+    S.newton_step(p, dt, Uold, U, ws=ws)  # warm-up step (not timed)
+    torch.cuda.synchronize()
+    newton, gmres, ok = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Uold.copy_(U)
+        rep = S.newton_step(p, dt, Uold, U, ws=ws)
+        newton.append(rep.newton_its)
+        gmres.append(rep.gmres_its)
+        ok += int(rep.converged)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dof = 2 * n * n
+    return {"workload": f"coupled Allen-Cahn/Cahn-Hilliard {n}x{n} on [0,100]^2, no-flux, backward "
+                        f"Euler dt={dt}, Newton + GMRES(30) with 3x3 block-Jacobi, FP32 fields",
+            "dof": dof, "unknowns": 3 * n * n, "steps": steps, "converged_steps": ok,
+            "ms_per_step": 1e3 * el / steps, "dof_steps_per_s": dof * steps / el,
+            "newton_its_per_step": float(np.mean(newton)),
+            "gmres_its_per_newton": float(np.sum(gmres) / max(np.sum(newton), 1))}
+
+
 def adjoint_record(stream, count=64, nsteps=2000, every=100):
     """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
     2000 FP32 steps, dt = 0.05): forward with a snapshot every 100 steps plus the
@@ -407,6 +445,7 @@ def main():
             print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
         if args.coupled:
             print(json.dumps(coupled_record(stream, steps=args.coupled)), flush=True)
+            print(json.dumps(coupled_implicit_record(stream)), flush=True)
         if args.surrogate_gain:
             from paper_2601_06079_amd import nn as NN
             rec = NN.gain_experiment(train_iters=args.surrogate_gain,
@@ -521,6 +560,7 @@ def main():
         out["surrogate"] = surrogate_record(stream)
         out["implicit_ch3d128"] = implicit_record(20, stream)
         out["coupled_1024"] = coupled_record(stream)
+        out["coupled_implicit_512"] = coupled_implicit_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -55,8 +55,9 @@ enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1,
                           *   h(eta) = 10 eta^3 - 15 eta^4 + 6 eta^5;
                           * states [c ; mu ; eta], mobility = M_c, mobility_eta = M_eta,
                           * kappa = kappa_eta (no composition gradient energy).  Supported by
-                          * pf_residual, pf_step_explicit and pf_energy; the others return
-                          * PF_EUNSUPPORTED. */
+                          * pf_residual, pf_step_explicit, pf_energy, pf_jvp and
+                          * pf_newton_step (3x3 block-Jacobi); pf_vjp and the batch calls
+                          * return PF_EUNSUPPORTED. */
 enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
        PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
 enum { PF_F32 = 0, PF_F64 = 1 };

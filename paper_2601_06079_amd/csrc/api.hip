@@ -201,11 +201,10 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
         case PF_OP_JVP: b = 0; break;
         case PF_OP_STEP_EXPLICIT: b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : 1); break;
         case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
-        case PF_OP_NEWTON:
+        case PF_OP_NEWTON: b = newton_workspace_bytes(p, 30); break;
         case PF_OP_VJP:
-            if (p->model == PF_COUPLED)
-                return fail(PF_EUNSUPPORTED, "coupled model: explicit steps, residual and energy only");
-            b = op == PF_OP_NEWTON ? newton_workspace_bytes(p, 30) : vjp_workspace_bytes(p);
+            if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: no adjoint in this build");
+            b = vjp_workspace_bytes(p);
             break;
         default: return fail(PF_EINVAL, "unknown op %d", op);
     }
@@ -284,10 +283,18 @@ int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, voi
     if (int rc = check_ptr(v, p, "v")) return rc;
     if (int rc = check_ptr(Jv, p, "Jv")) return rc;
     if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
-    if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_jvp: coupled model not implemented");
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_COUPLED) {
+        if (p->dtype == PF_F32)
+            pfk::launch_cp_jvp<float>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, (const float*)U,
+                                      (const float*)v, (float*)Jv, s);
+        else
+            pfk::launch_cp_jvp<double>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt,
+                                       (const double*)U, (const double*)v, (double*)Jv, s);
+        return check_launch("pf_jvp");
+    }
     if (p->dtype == PF_F32)
         pfk::launch_jvp<float>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const float*)U,
                                (const float*)v, (float*)Jv, s);

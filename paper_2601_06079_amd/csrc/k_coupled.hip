@@ -88,10 +88,12 @@ __global__ __launch_bounds__(256) void k_cp_mu_eta(const T* __restrict__ c, cons
 }
 
 // r = [M_c K mu ;  m mu - g(c, eta) ;  M_eta (s(c, eta) + kappa K eta)], rows / 2^b on
-// no-flux grids
+// no-flux grids; with Uold the backward-Euler time term inv_dt m (U - Uold) is added
+// to the c and eta rows (Eq. 14)
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cp_residual(const T* __restrict__ U, T* __restrict__ r, Geom g,
-                                                     T detJ, T m, T kappa, T Mc, T Meta)
+__global__ __launch_bounds__(256) void k_cp_residual(const T* __restrict__ U, const T* __restrict__ Uold,
+                                                     T* __restrict__ r, Geom g, T detJ, T m, T kappa,
+                                                     T Mc, T Meta, T inv_dt)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int i, j, k;
@@ -104,9 +106,170 @@ __global__ __launch_bounds__(256) void k_cp_residual(const T* __restrict__ U, T*
     const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);
     const T gsrc = detJ * quad_sum<T, D, true>(u, e, MuSrc<T>{});
     const T s = detJ * quad_sum<T, D, true>(u, e, EtaSrc<T>{});
-    r[idx] = Mc * stiff<T, D>(w, h) * ib;
+    const T tc = Uold ? inv_dt * m * (u[NB<D>::K / 2] - Uold[idx]) : (T)0;
+    const T te = Uold ? inv_dt * m * (e[NB<D>::K / 2] - Uold[2 * g.N + idx]) : (T)0;
+    r[idx] = (Mc * stiff<T, D>(w, h) + tc) * ib;
     r[g.N + idx] = (m * w[NB<D>::K / 2] - gsrc) * ib;
-    r[2 * g.N + idx] = Meta * (s + kappa * stiff<T, D>(e, h)) * ib;
+    r[2 * g.N + idx] = (Meta * (s + kappa * stiff<T, D>(e, h)) + te) * ib;
+}
+
+// second derivatives of the local energy density f_a(c)(1 - h) + f_b(c) h
+template <typename T>
+__device__ __forceinline__ void hessian(T c, T e, T& gcc, T& gce, T& see)
+{
+    const T h = hfun(e), dh = dhfun(e);
+    const T d2h = (T)60 * e * fmaT(fmaT((T)2, e, (T)-3), e, (T)1);  // 60e - 180e^2 + 120e^3
+    const T d2fa = fmaT(fmaT((T)(12 * 1.3687), c, (T)(-6 * 2.7375)), c, (T)(2 * 5.1622));
+    gcc = fmaT((T)10 - d2fa, h, d2fa);
+    gce = (dfb(c) - dfa(c)) * dh;
+    see = (fb(c) - fa(c)) * d2h;
+}
+
+// sum over the 4^D quadrature points around the centre node (weights as quad_sum)
+// of the two Hessian-direction products
+//   S1 = g_cc vc + g_ce ve  (mu row),  S2 = g_ce vc + s_ee ve  (eta row)
+template <typename T, int D>
+__device__ __forceinline__ void hess_sums(const T* c, const T* e, const T* vc, const T* ve, T& S1, T& S2)
+{
+    auto pt = [](T cq, T eq, T vcq, T veq, T& a, T& b) {
+        T gcc, gce, see;
+        hessian(cq, eq, gcc, gce, see);
+        a = fmaT(gcc, vcq, gce * veq);
+        b = fmaT(gce, vcq, see * veq);
+    };
+    if constexpr (D == 2) {
+        T X[4][3][4];  // [field][row][qx]
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            interp3to4(c[3 * b], c[3 * b + 1], c[3 * b + 2], X[0][b]);
+            interp3to4(e[3 * b], e[3 * b + 1], e[3 * b + 2], X[1][b]);
+            interp3to4(vc[3 * b], vc[3 * b + 1], vc[3 * b + 2], X[2][b]);
+            interp3to4(ve[3 * b], ve[3 * b + 1], ve[3 * b + 2], X[3][b]);
+        }
+        T col1[4], col2[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T q[4][4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) interp3to4(X[f][0][qx], X[f][1][qx], X[f][2][qx], q[f]);
+            T a[4], bb[4];
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) pt(q[0][qy], q[1][qy], q[2][qy], q[3][qy], a[qy], bb[qy]);
+            col1[qx] = wsum4(a);
+            col2[qx] = wsum4(bb);
+        }
+        S1 = wsum4(col1);
+        S2 = wsum4(col2);
+    } else {
+        T X[4][9][4];  // [field][row (y,z)][qx]
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            interp3to4(c[3 * r], c[3 * r + 1], c[3 * r + 2], X[0][r]);
+            interp3to4(e[3 * r], e[3 * r + 1], e[3 * r + 2], X[1][r]);
+            interp3to4(vc[3 * r], vc[3 * r + 1], vc[3 * r + 2], X[2][r]);
+            interp3to4(ve[3 * r], ve[3 * r + 1], ve[3 * r + 2], X[3][r]);
+        }
+        T pl1[4], pl2[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T Y[4][3][4];  // [field][z][qy]
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int zc = 0; zc < 3; ++zc)
+                    interp3to4(X[f][3 * zc][qx], X[f][3 * zc + 1][qx], X[f][3 * zc + 2][qx], Y[f][zc]);
+            T row1[4], row2[4];
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) {
+                T q[4][4];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) interp3to4(Y[f][0][qy], Y[f][1][qy], Y[f][2][qy], q[f]);
+                T a[4], bb[4];
+#pragma unroll
+                for (int qz = 0; qz < 4; ++qz) pt(q[0][qz], q[1][qz], q[2][qz], q[3][qz], a[qz], bb[qz]);
+                row1[qy] = wsum4(a);
+                row2[qy] = wsum4(bb);
+            }
+            pl1[qx] = wsum4(row1);
+            pl2[qx] = wsum4(row2);
+        }
+        S1 = wsum4(pl1);
+        S2 = wsum4(pl2);
+    }
+}
+
+// Jv of R = inv_dt M (U - Uold) + r(U) at U, rows / 2^b on no-flux grids:
+//   Jv_c   = inv_dt m v_c + M_c K v_mu
+//   Jv_mu  = m v_mu - |J| S1
+//   Jv_eta = inv_dt m v_eta + M_eta (|J| S2 + kappa K v_eta)
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cp_jvp(const T* __restrict__ U, const T* __restrict__ V,
+                                                T* __restrict__ Jv, Geom g, T detJ, T m, T kappa, T Mc,
+                                                T Meta, T inv_dt)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j, k;
+    if (!node_of<D>(g, idx, i, j, k)) return;
+    T u[NB<D>::K], e[NB<D>::K], vc[NB<D>::K], vm[NB<D>::K], ve[NB<D>::K];
+    gather<T, D>(U, g, i, j, k, u);
+    gather<T, D>(U + 2 * g.N, g, i, j, k, e);
+    gather<T, D>(V, g, i, j, k, vc);
+    gather<T, D>(V + g.N, g, i, j, k, vm);
+    gather<T, D>(V + 2 * g.N, g, i, j, k, ve);
+    const T h = (T)g.h;
+    const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);
+    T S1, S2;
+    hess_sums<T, D>(u, e, vc, ve, S1, S2);
+    constexpr int C = NB<D>::K / 2;
+    Jv[idx] = (inv_dt * m * vc[C] + Mc * stiff<T, D>(vm, h)) * ib;
+    Jv[g.N + idx] = (m * vm[C] - detJ * S1) * ib;
+    Jv[2 * g.N + idx] = (inv_dt * m * ve[C] + Meta * (detJ * S2 + kappa * stiff<T, D>(ve, h))) * ib;
+}
+
+// 3x3 block-Jacobi inverse of dR/dU at each node (row-major, 9 values per node):
+//   [[inv_dt m, M_c K_aa, 0], [-|J| Dcc, m, -|J| Dce], [M_eta |J| Dce, 0, inv_dt m + M_eta (|J| Dee + kappa K_aa)]]
+// with D.. = sum_q (second derivative at q) phi_a(q)^2; rows / 2^b on no-flux grids.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cp_prec(const T* __restrict__ U, T* __restrict__ pinv, Geom g,
+                                                 T detJ, T m, T kappa, T Mc, T Meta, T inv_dt)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j, k;
+    if (!node_of<D>(g, idx, i, j, k)) return;
+    T u[NB<D>::K], e[NB<D>::K];
+    gather<T, D>(U, g, i, j, k, u);
+    gather<T, D>(U + 2 * g.N, g, i, j, k, e);
+    struct Gcc { __device__ T operator()(T c, T ee) const { T a, b, d; hessian(c, ee, a, b, d); return a; } };
+    struct Gce { __device__ T operator()(T c, T ee) const { T a, b, d; hessian(c, ee, a, b, d); return b; } };
+    struct See { __device__ T operator()(T c, T ee) const { T a, b, d; hessian(c, ee, a, b, d); return d; } };
+    // quad_sum_sq evaluates F(u_q, 1); the second field is needed here, so the
+    // squared-weight sums are formed with a two-field quadrature of F(c, eta) * 1
+    const double dcc = (double)detJ * (double)quad_sum_sq2<T, D>(u, e, Gcc{});
+    const double dce = (double)detJ * (double)quad_sum_sq2<T, D>(u, e, Gce{});
+    const double dee = (double)detJ * (double)quad_sum_sq2<T, D>(u, e, See{});
+    const double kd = (double)stiff_diag<T, D>((T)g.h);
+    const double ib = 1.0 / bfactor<D>(g, i, j, k);
+    double A[3][3] = {{(double)inv_dt * m, (double)Mc * kd, 0.0},
+                      {-dcc, (double)m, -dce},
+                      {(double)Meta * dce, 0.0, (double)inv_dt * m + (double)Meta * (dee + (double)kappa * kd)}};
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) A[r][cc] *= ib;
+    // inverse by cofactors
+    const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    const double id = 1.0 / det;
+    T* P = pinv + 9 * idx;
+    P[0] = (T)(c00 * id);
+    P[1] = (T)((A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id);
+    P[2] = (T)((A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id);
+    P[3] = (T)(c01 * id);
+    P[4] = (T)((A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id);
+    P[5] = (T)((A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id);
+    P[6] = (T)(c02 * id);
+    P[7] = (T)((A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id);
+    P[8] = (T)((A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id);
 }
 
 // ---- energy and mass (FP64): each thread owns the element whose lower corner is
@@ -220,12 +383,34 @@ void launch_cp_mu_eta(const Geom& g, double kappa, double dt_Meta, const T* c, c
 
 template <typename T>
 void launch_cp_residual(const Geom& g, double kappa, double Mc, double Meta, const T* U, T* r,
-                        hipStream_t s)
+                        hipStream_t s, const T* Uold, double inv_dt)
 {
     const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
     CP_DIM(g, {
-        k_cp_residual<T, D><<<blocks_for(g), 256, 0, s>>>(U, r, g, (T)detJ, (T)m, (T)kappa, (T)Mc,
-                                                           (T)Meta);
+        k_cp_residual<T, D><<<blocks_for(g), 256, 0, s>>>(U, Uold, r, g, (T)detJ, (T)m, (T)kappa, (T)Mc,
+                                                           (T)Meta, (T)inv_dt);
+    });
+}
+
+template <typename T>
+void launch_cp_jvp(const Geom& g, double kappa, double Mc, double Meta, double inv_dt, const T* U,
+                   const T* v, T* Jv, hipStream_t s)
+{
+    const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
+    CP_DIM(g, {
+        k_cp_jvp<T, D><<<blocks_for(g), 256, 0, s>>>(U, v, Jv, g, (T)detJ, (T)m, (T)kappa, (T)Mc,
+                                                      (T)Meta, (T)inv_dt);
+    });
+}
+
+template <typename T>
+void launch_cp_prec(const Geom& g, double kappa, double Mc, double Meta, double inv_dt, const T* U,
+                    T* pinv, hipStream_t s)
+{
+    const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
+    CP_DIM(g, {
+        k_cp_prec<T, D><<<blocks_for(g), 256, 0, s>>>(U, pinv, g, (T)detJ, (T)m, (T)kappa, (T)Mc,
+                                                       (T)Meta, (T)inv_dt);
     });
 }
 
@@ -242,7 +427,11 @@ void launch_cp_energy(const Geom& g, double kappa, const T* U, double* partials,
     template void launch_cp_mu_eta<T>(const Geom&, double, double, const T*, const T*, T*, T*,     \
                                       hipStream_t);                                                \
     template void launch_cp_residual<T>(const Geom&, double, double, double, const T*, T*,         \
-                                        hipStream_t);                                              \
+                                        hipStream_t, const T*, double);                            \
+    template void launch_cp_jvp<T>(const Geom&, double, double, double, double, const T*, const T*, \
+                                   T*, hipStream_t);                                               \
+    template void launch_cp_prec<T>(const Geom&, double, double, double, double, const T*, T*,     \
+                                    hipStream_t);                                                  \
     template void launch_cp_energy<T>(const Geom&, double, const T*, double*, double*, hipStream_t);
 INST_CP(float)
 INST_CP(double)

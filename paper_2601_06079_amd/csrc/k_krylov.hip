@@ -174,7 +174,8 @@ __device__ __forceinline__ void axpy_chunk(const T* __restrict__ V, long long ld
 //   ||w''||^2 = ||w||^2 - ||h||^2  (h is the projection of w on V),
 //   v = w'' / ||w''||  -> vnext,   z = P^-1 v.
 // nrm2[0] receives ||w''||^2.  Node-indexed: VW nodes per lane, planes at
-// offset N (MODEL 1: the c and mu planes with per-node 2x2 blocks).
+// offset N (MODEL 1: the c and mu planes with per-node 2x2 blocks; MODEL 2: the
+// three planes of the coupled model with 3x3 blocks).
 template <typename T, int KMAX, int VW, int MODEL>
 __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, long long ld, int k,
                                                        const double* __restrict__ sums,
@@ -220,6 +221,40 @@ __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, 
                 zc = vc;
             }
             stp<T, VW>(z + o, zc);
+        } else if constexpr (MODEL == 2) {
+            // three planes (coupled model), 3x3 blocks
+            Pack<T, VW> vv[3];
+            vv[0] = vc;
+#pragma unroll
+            for (int f = 1; f < 3; ++f) {
+                double xf[VW];
+                const Pack<T, VW> wv = ldp<T, VW>(w + f * N + o);
+#pragma unroll
+                for (int l = 0; l < VW; ++l) xf[l] = (double)wv.v[l];
+                axpy_chunk<T, KMAX, VW>(V, ld, k, hh, f * N + o, xf);
+#pragma unroll
+                for (int l = 0; l < VW; ++l) vv[f].v[l] = (T)((T)xf[l] * inv);
+                stp<T, VW>(vnext + f * N + o, vv[f]);
+            }
+            Pack<T, VW> zz[3];
+#pragma unroll
+            for (int l = 0; l < VW; ++l) {
+                if (pinv) {
+                    const T* P = pinv + 9 * (o + l);
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        T acc = (T)0;
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) acc += (tr ? P[3 * cc + r] : P[3 * r + cc]) * vv[cc].v[l];
+                        zz[r].v[l] = acc;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) zz[r].v[l] = vv[r].v[l];
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) stp<T, VW>(z + f * N + o, zz[f]);
         } else {
             double xm[VW];
             {
@@ -301,6 +336,27 @@ __global__ __launch_bounds__(KB) void k_normalize_prec(const T* __restrict__ w,
         const T vi = (T)((double)w[i] * inv);
         v[i] = vi;
         if (z) z[i] = pinv ? vi * pinv[i] : vi;
+    } else if constexpr (MODEL == 2) {
+        T vv[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            vv[f] = (T)((double)w[f * N + i] * inv);
+            v[f * N + i] = vv[f];
+        }
+        if (z) {
+            const T* P = pinv ? pinv + 9 * i : nullptr;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                T acc = (T)0;
+                if (P) {
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) acc += (tr ? P[3 * cc + r] : P[3 * r + cc]) * vv[cc];
+                } else {
+                    acc = vv[r];
+                }
+                z[r * N + i] = acc;
+            }
+        }
     } else {
         const T vc = (T)((double)w[i] * inv), vm = (T)((double)w[N + i] * inv);
         v[i] = vc;
@@ -333,6 +389,26 @@ __global__ __launch_bounds__(KB) void k_update(const T* __restrict__ V, long lon
         for (int j = 0; j < k; ++j) s = fma(y[j], (double)V[j * ld + i], s);
         const T t = (T)s;
         x[i] += pinv ? t * pinv[i] : t;
+    } else if constexpr (MODEL == 2) {
+        T t[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            double sf = 0.0;
+            for (int j = 0; j < k; ++j) sf = fma(y[j], (double)V[j * ld + f * N + i], sf);
+            t[f] = (T)sf;
+        }
+        const T* P = pinv ? pinv + 9 * i : nullptr;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            T acc = (T)0;
+            if (P) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) acc += (tr ? P[3 * cc + r] : P[3 * r + cc]) * t[cc];
+            } else {
+                acc = t[r];
+            }
+            x[r * N + i] += acc;
+        }
     } else {
         double sc = 0.0, sm = 0.0;
         for (int j = 0; j < k; ++j) {
@@ -473,7 +549,8 @@ void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
     static const int cap_axpy = resident_blocks(k_axpy_dots<T, KMAX, VW>);
     static const int cap_norm0 = resident_blocks(k_axpy_normalize<T, KMAX, VW, 0>);
     static const int cap_norm1 = resident_blocks(k_axpy_normalize<T, KMAX, VW, 1>);
-    const int cap_norm = model == 0 ? cap_norm0 : cap_norm1;
+    static const int cap_norm2 = resident_blocks(k_axpy_normalize<T, KMAX, VW, 2>);
+    const int cap_norm = model == 0 ? cap_norm0 : (model == 1 ? cap_norm1 : cap_norm2);
     const int nb = krylov_blocks(n);
     const int nb1 = std::min(nb, cap_dots), nb2 = std::min(nb, cap_axpy);
     k_dots<T, KMAX, VW><<<nb1, KB, 0, s>>>(V, ld, k, w, n, part);
@@ -485,8 +562,11 @@ void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
     if (model == 0)
         k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
                                                             o.nrm2, o.host_nrm2);
-    else
+    else if (model == 1)
         k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+                                                            o.nrm2, o.host_nrm2);
+    else
+        k_axpy_normalize<T, KMAX, VW, 2><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
                                                             o.nrm2, o.host_nrm2);
 }
 
@@ -511,7 +591,7 @@ int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
             long long N, double* part, const KrOut& o, hipStream_t s, int tr)
 {
     if (k < 1 || k > KR_MAXK) return -1;
-    const long long n = (model == 0 ? 1 : 2) * N;
+    const long long n = (model == 0 ? 1 : model == 1 ? 2 : 3) * N;
     constexpr int VW = 16 / sizeof(T);
     if (wide_ok<T>(N))
         cgs2_v<T, VW>(model, V, ld, k, w, vnext, z, pinv, N, n, part, o, tr, s);
@@ -535,8 +615,10 @@ void kr_normalize_prec(int model, const T* w, const double* nrm2, T* v, T* z, co
 {
     if (model == 0)
         k_normalize_prec<T, 0><<<grid1(N), KB, 0, s>>>(w, nrm2, v, z, pinv, N, sign, tr);
-    else
+    else if (model == 1)
         k_normalize_prec<T, 1><<<grid1(N), KB, 0, s>>>(w, nrm2, v, z, pinv, N, sign, tr);
+    else
+        k_normalize_prec<T, 2><<<grid1(N), KB, 0, s>>>(w, nrm2, v, z, pinv, N, sign, tr);
 }
 
 template <typename T>
@@ -545,8 +627,10 @@ void kr_update(int model, const T* V, long long ld, int k, const double* y, cons
 {
     if (model == 0)
         k_update<T, 0><<<grid1(N), KB, 0, s>>>(V, ld, k, y, pinv, x, N, tr);
-    else
+    else if (model == 1)
         k_update<T, 1><<<grid1(N), KB, 0, s>>>(V, ld, k, y, pinv, x, N, tr);
+    else
+        k_update<T, 2><<<grid1(N), KB, 0, s>>>(V, ld, k, y, pinv, x, N, tr);
 }
 
 template <typename T>

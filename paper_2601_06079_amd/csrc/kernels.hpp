@@ -101,10 +101,18 @@ void launch_reduce_pairs(const double* part, int nb, double* out, hipStream_t s)
 template <typename T>
 void launch_cp_mu_eta(const Geom& g, double kappa, double dt_Meta, const T* c, const T* eta, T* mu,
                       T* eta_out, hipStream_t s);
-// r = [M_c K mu ; m mu - g(c, eta) ; M_eta (s(c, eta) + kappa K eta)]
+// r = [M_c K mu ; m mu - g(c, eta) ; M_eta (s(c, eta) + kappa K eta)] (+ inv_dt M (U - Uold))
 template <typename T>
 void launch_cp_residual(const Geom& g, double kappa, double Mc, double Meta, const T* U, T* r,
-                        hipStream_t s);
+                        hipStream_t s, const T* Uold = nullptr, double inv_dt = 0.0);
+// Jv of the backward-Euler residual (inv_dt = 0: of r)
+template <typename T>
+void launch_cp_jvp(const Geom& g, double kappa, double Mc, double Meta, double inv_dt, const T* U,
+                   const T* v, T* Jv, hipStream_t s);
+// 3x3 block-Jacobi inverse (9 values per node, row-major)
+template <typename T>
+void launch_cp_prec(const Geom& g, double kappa, double Mc, double Meta, double inv_dt, const T* U,
+                    T* pinv, hipStream_t s);
 // one fused explicit step of the coupled model on a 2-D grid (k_stream_cp.hip):
 // (c_in, e_in) -> (c_out, e_out); rows: rows per wavefront (0: 32)
 template <typename T>

@@ -17,7 +17,7 @@ struct KrOut {
     double *host_h1, *host_h2, *host_nrm2;
 };
 // One Arnoldi orthogonalisation (CGS2) of w against the k basis vectors V
-// (N nodes, 1 plane for model 0, 2 for model 1; leading dimension ld):
+// (N nodes, 1 plane for model 0, 2 for model 1, 3 for model 2; leading dimension ld):
 //   h1[0..k) = V^T w, w <- w - V h1, h2[0..k) = V^T w, h2[k] = ||w||^2,
 //   nrm2[0] = ||w - V h2||^2, vnext = (w - V h2) / sqrt(nrm2[0]) (0 if that is 0),
 //   z = P^-1 vnext.  w is left after the first correction.  part: (k + 1) *
@@ -30,7 +30,8 @@ template <typename T>
 void kr_norm2(const T* a, const T* b, long long n, double* part, double* out, hipStream_t s,
               double* host = nullptr);
 // v = sign * w / sqrt(nrm2[0]) ; z = P^-1 v (pinv null: identity; z null: skipped;
-// tr = 1: transposed 2x2 blocks).  N = nodes (the vectors hold 1 or 2 planes).
+// tr = 1: transposed blocks).  N = nodes (the vectors hold 1, 2 or 3 planes; blocks
+// 1x1, 2x2 or 3x3 per node).
 template <typename T>
 void kr_normalize_prec(int model, const T* w, const double* nrm2, T* v, T* z, const T* pinv,
                        long long N, double sign, hipStream_t s, int tr = 0);

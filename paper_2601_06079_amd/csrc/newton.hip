@@ -61,7 +61,8 @@ NWS<T> layout(const pf_problem* p, void* base)
     L.z = (T*)take(n * sizeof(T));
     L.b = (T*)take(n * sizeof(T));
     L.V = (T*)take((size_t)(MAXM + 1) * L.ld * sizeof(T));
-    L.pinv = (T*)take((size_t)(p->model == PF_CAHN_HILLIARD ? 4 : 1) * g.N * sizeof(T));
+    L.pinv = (T*)take((size_t)(p->model == PF_COUPLED ? 9 : p->model == PF_CAHN_HILLIARD ? 4 : 1) * g.N *
+                      sizeof(T));
     const long long nbp = std::max<long long>(pfk::krylov_blocks(n), (g.N + 255) / 256);
     L.part = (double*)take((size_t)(MAXM + 2) * nbp * sizeof(double) + 64);
     L.dev = (double*)take(4 * (MAXM + 8) * sizeof(double));
@@ -175,7 +176,10 @@ struct LinOp {
     int trans;
     void apply(const T* v, T* out, hipStream_t s) const
     {
-        pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, trans, 0);
+        if (p->model == PF_COUPLED)
+            pfk::launch_cp_jvp<T>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, U, v, out, s);
+        else
+            pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, trans, 0);
     }
 };
 
@@ -316,7 +320,10 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
     if (int rc = col_readback(&rb)) return rc;
     // ||R(U)||, read back together with whatever scalars were queued before it
     auto residual_norm = [&](double* out) -> int {
-        pfk::launch_residual<T>(g, p->model, f, p->kappa, p->mobility, U, L.R, s, Uold, inv_dt);
+        if (p->model == PF_COUPLED)
+            pfk::launch_cp_residual<T>(g, p->kappa, p->mobility, p->mobility_eta, U, L.R, s, Uold, inv_dt);
+        else
+            pfk::launch_residual<T>(g, p->model, f, p->kappa, p->mobility, U, L.R, s, Uold, inv_dt);
         pfk::kr_norm2<T>(L.R, nullptr, n, L.part, dnrm, s, rb->scal_dev());
         if (int rc = rb->wait_scalars(s)) return rc;
         *out = std::sqrt(rb->scal()[0]);
@@ -344,8 +351,12 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
             break;
         }
         if (k >= o.max_newton) break;
-        if (o.precond == PF_PRECOND_JACOBI)
-            pfk::launch_prec<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, L.pinv, s);
+        if (o.precond == PF_PRECOND_JACOBI) {
+            if (p->model == PF_COUPLED)
+                pfk::launch_cp_prec<T>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, U, L.pinv, s);
+            else
+                pfk::launch_prec<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, L.pinv, s);
+        }
         pfk::kr_scale<T>(L.R, L.b, -1.0, n, s);  // b = -R
         const double lin = std::min(o.lmax, std::max(o.lmin, 0.1 * rk / r0));
         int its = 0;
@@ -483,7 +494,6 @@ int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
                    const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream)
 {
     if (int rc = validate(p)) return rc;
-    if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_newton_step: coupled model not implemented");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
     if (int rc = check_ptr(U_old, p, "U_old")) return rc;
     if (int rc = check_ptr(U, p, "U")) return rc;

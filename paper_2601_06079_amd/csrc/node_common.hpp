@@ -218,6 +218,63 @@ __device__ __forceinline__ T quad_sum_sq(const T* u, Fn F)
     }
 }
 
+// sum_q w_q^2 F(u_q, v_q) over the 4^D points (w = phi of the centre node): the
+// diagonal entry of a two-field second-derivative operator (no |J|)
+template <typename T, int D, typename Fn>
+__device__ __forceinline__ T quad_sum_sq2(const T* u, const T* v, Fn F)
+{
+    const T w2[4] = {(T)(GM * GM), (T)(GP * GP), (T)(GP * GP), (T)(GM * GM)};
+    auto ws = [&](const T x[4]) { return w2[0] * x[0] + w2[1] * x[1] + w2[2] * x[2] + w2[3] * x[3]; };
+    if constexpr (D == 2) {
+        T Xu[3][4], Xv[3][4];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            interp3to4(u[3 * b], u[3 * b + 1], u[3 * b + 2], Xu[b]);
+            interp3to4(v[3 * b], v[3 * b + 1], v[3 * b + 2], Xv[b]);
+        }
+        T col[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T qu[4], qv[4], fv[4];
+            interp3to4(Xu[0][qx], Xu[1][qx], Xu[2][qx], qu);
+            interp3to4(Xv[0][qx], Xv[1][qx], Xv[2][qx], qv);
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) fv[qy] = F(qu[qy], qv[qy]);
+            col[qx] = ws(fv);
+        }
+        return ws(col);
+    } else {
+        T Xu[9][4], Xv[9][4];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            interp3to4(u[3 * r], u[3 * r + 1], u[3 * r + 2], Xu[r]);
+            interp3to4(v[3 * r], v[3 * r + 1], v[3 * r + 2], Xv[r]);
+        }
+        T plane[4];
+#pragma unroll
+        for (int qx = 0; qx < 4; ++qx) {
+            T Yu[3][4], Yv[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                interp3to4(Xu[3 * c][qx], Xu[3 * c + 1][qx], Xu[3 * c + 2][qx], Yu[c]);
+                interp3to4(Xv[3 * c][qx], Xv[3 * c + 1][qx], Xv[3 * c + 2][qx], Yv[c]);
+            }
+            T row[4];
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) {
+                T qu[4], qv[4], fv[4];
+                interp3to4(Yu[0][qy], Yu[1][qy], Yu[2][qy], qu);
+                interp3to4(Yv[0][qy], Yv[1][qy], Yv[2][qy], qv);
+#pragma unroll
+                for (int qz = 0; qz < 4; ++qz) fv[qz] = F(qu[qz], qv[qz]);
+                row[qy] = ws(fv);
+            }
+            plane[qx] = ws(row);
+        }
+        return ws(plane);
+    }
+}
+
 // diagonal entry of the unit Q1 stiffness at any periodic node
 template <typename T, int D>
 __device__ __forceinline__ T stiff_diag(T h)

@@ -91,12 +91,10 @@ def test_coupled_model_entry_points(L):
     nb = ct.c_size_t(0)
     assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == A.PF_OK
     assert nb.value == 2 * 64 * 48 * 4  # two ping-pong fields (c, eta)
-    assert L.pf_workspace_size(ct.byref(p), A.OP_NEWTON, ct.byref(nb)) == A.PF_EUNSUPPORTED
+    assert L.pf_workspace_size(ct.byref(p), A.OP_NEWTON, ct.byref(nb)) == A.PF_OK
+    assert L.pf_workspace_size(ct.byref(p), A.OP_VJP, ct.byref(nb)) == A.PF_EUNSUPPORTED
     fake = [ct.c_void_p(0x1000 * (i + 1)) for i in range(4)]
     tb = (ct.c_double * 3)()
-    assert L.pf_jvp(ct.byref(p), 1.0, fake[0], fake[1], fake[2], None) == A.PF_EUNSUPPORTED
-    assert L.pf_newton_step(ct.byref(p), 0.1, fake[0], fake[1], None, None, fake[2],
-                            None) == A.PF_EUNSUPPORTED
     assert L.pf_vjp(ct.byref(p), A.VJP_RESIDUAL, 0.1, fake[0], fake[1], fake[2], tb, fake[3],
                     None) == A.PF_EUNSUPPORTED
     q = _prob(model=A.COUPLED, fe=9)  # the coupled model ignores fe

@@ -111,3 +111,74 @@ def test_coupled_benchmark_sampled_parity_full_size():
         assert rel_l2(a, b) < 1e-6
         # the 3-step update is ~1e-4 of the field: FP32 storage rounding alone is ~1e-3 of it
         assert rel_l2(a - u0, b - u0) < 1e-2
+
+
+# ------------------------------------------------------------ implicit -------
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("n", [(5, 7), (64, 48), (3, 4, 5), (12, 10, 9)])
+def test_coupled_jvp(n, dtype, bc):
+    announce("coupled jvp", n, dtype, bc)
+    g, o = cpair(n, dtype, bc, h=0.9, Mc=1.1, Meta=3.0, kappa=0.4)
+    U = rounded(_state(o, 13), dtype)
+    v = rounded(np.random.default_rng(14).standard_normal(o.ndof), dtype)
+    N = o.nnodes
+    for inv_dt in (0.0, 2.0):
+        Jv = host(S.jvp(g, inv_dt, dev(U, dtype), dev(v, dtype)))
+        ref = O.cp_jvp(o, inv_dt, U, v)
+        for k in range(3):
+            assert rel_l2(Jv[k * N:(k + 1) * N], ref[k * N:(k + 1) * N]) < TOL[dtype] * 10
+
+
+def _smooth_state(o, seed):
+    """a diffuse disc of the second phase with composition noise, mu consistent"""
+    n = o.n
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*[np.arange(k) * o.h for k in reversed(n)], indexing="ij")
+    r2 = sum((x - 0.5 * k * o.h) ** 2 for x, k in zip(grids, reversed(n)))
+    eta = (0.5 * (1 - np.tanh((np.sqrt(r2) - 0.25 * min(n) * o.h) / 2.0))).ravel()
+    c = 0.04 + 0.12 * eta + 0.005 * rng.standard_normal(eta.size)
+    return O.cp_explicit(o, np.concatenate([c, np.zeros_like(c), eta]), 1e-9, 0)
+
+
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("n", [(8, 7), (12, 10), (4, 5, 4)])
+def test_coupled_newton_matches_oracle(n, dtype, bc):
+    announce("coupled newton", n, dtype, bc)
+    g, o = cpair(n, dtype, bc)
+    Uold = rounded(_smooth_state(o, 3), dtype)
+    dt = 0.01
+    Ug, Uog = dev(Uold, dtype), dev(Uold, dtype)
+    rtol = 1e-11 if dtype == F64 else 1e-7
+    rep = S.newton_step(g, dt, Uog, Ug, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8))
+    assert rep.converged, rep
+    Uo, conv, _ = O.cp_newton_be(o, dt, Uold, rtol=1e-13)
+    assert conv
+    N = o.nnodes
+    tol = 1e-9 if dtype == F64 else 1e-5
+    for k in range(3):
+        assert rel_l2(host(Ug)[k * N:(k + 1) * N], Uo[k * N:(k + 1) * N]) < tol * (100 if k == 1 else 1)
+    m0 = O.cp_total_mass(o, Uold)
+    assert abs(O.cp_total_mass(o, host(Ug)) - m0) < (1e-10 if dtype == F64 else 1e-5) * abs(m0)
+
+
+def test_coupled_newton_benchmark_shape_several_steps():
+    """256^2 benchmark shape, 5 backward-Euler steps at dt = 0.01: every step
+    converges, composition is conserved and the energy decreases."""
+    n = 256
+    cfg = I.COUPLED
+    g, o = cpair((n, n), F32, O.NOFLUX, h=cfg["L"] / (n - 1), Mc=cfg["Mc"], Meta=cfg["Meta"],
+                 kappa=cfg["kappa"])
+    U = dev(I.coupled_state(n, seed=0), F32)
+    S.step_explicit(g, U, 1e-9, 0)  # consistent mu
+    e = [host(S.energy(g, U))]
+    ws = S.workspace(g, A.OP_NEWTON)
+    Uold = torch.empty_like(U)
+    for _ in range(5):
+        Uold.copy_(U)
+        rep = S.newton_step(g, 0.01, Uold, U, ws=ws)
+        assert rep.converged, rep
+        e.append(host(S.energy(g, U)))
+    assert abs(e[-1][1] - e[0][1]) < 1e-5 * abs(e[0][1])
+    assert all(b[0] <= a[0] for a, b in zip(e, e[1:]))
