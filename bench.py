@@ -119,7 +119,7 @@ def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
     f_scale = nbytes / (max(cf) * 1024) if cf else 1.0
     w_scale = nbytes / (max(cw) * 1024) if cw else 1.0
     import re
-    pat = re.compile(r"k_explicit2d<float, \d+, \d+, (\d+)>")
+    pat = re.compile(r"k_explicit2d<float, \d+, \d+, (\d+)(?:, (?:true|false))?>")
     names = [k for (k, c) in step if pat.search(k)]
     kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and pat.search(k)]
     kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and pat.search(k)]
