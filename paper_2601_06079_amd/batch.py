@@ -173,26 +173,39 @@ class Batch:
 class BatchedExplicitRun(torch.autograd.Function):
     """U_N = S^N(U_0; theta) for a batch, with a hand-written adjoint.
 
-    Forward keeps a snapshot every `every` steps; backward walks the segments in
-    reverse, recomputes each segment's states from its snapshot (trajectory
-    mode) and applies the batched step adjoint to them, accumulating the
-    per-sample gradient of theta = (mobility, kappa, W) in FP64 (Supp. Note 2,
-    Eqs. II.5-II.6, one constraint per step).
+    every = k: forward keeps a snapshot every k steps; backward walks the segments
+    in reverse, recomputes each segment's states from its snapshot (trajectory
+    mode) and applies the batched step adjoint to them.
+    every = None: forward writes the whole trajectory (N states) in device memory
+    as it runs (trajectory mode), and backward applies the adjoint to it directly,
+    with no recomputation; on a 288 GB device this holds, e.g., 2000 states of a
+    7.6 M-node batch (61 GB in FP32).
+    Either way the per-sample gradient of theta = (mobility, kappa, W) accumulates
+    in FP64 (Supp. Note 2, Eqs. II.5-II.6, one constraint per step), and both give
+    bitwise the same gradient for even checkpoint intervals.
     """
 
     @staticmethod
     def forward(ctx, theta, U0, batch, nsteps, every):
-        if nsteps % every:
+        if every is not None and nsteps % every:
             raise ValueError("nsteps must be a multiple of the checkpoint interval")
         batch.set_theta(theta.detach().cpu().numpy(), ks=batch.info.ks, ty=batch.info.ty,
                         depth=batch.info.depth)
+        ctx.batch, ctx.every, ctx.nsteps = batch, every, nsteps
+        if every is None:
+            traj = torch.empty((nsteps + 1, batch.total), dtype=batch.dtype, device=U0.device)
+            traj[0].copy_(U0.detach())
+            if nsteps:
+                batch.step(traj[0], nsteps, traj=traj[1])
+            ctx.traj = traj
+            return traj[nsteps].clone()
         ws = batch.workspace(A.OP_STEP_EXPLICIT)
         U = U0.detach().clone()
         snaps = []
         for _ in range(nsteps // every):
             snaps.append(U.clone())
             batch.step(U, every, ws)
-        ctx.batch, ctx.snaps, ctx.every = batch, snaps, every
+        ctx.snaps = snaps
         return U
 
     @staticmethod
@@ -200,8 +213,13 @@ class BatchedExplicitRun(torch.autograd.Function):
         b, every = ctx.batch, ctx.every
         lam = gU.detach().to(b.dtype).contiguous().clone()
         tb = torch.zeros(b.count * 3, dtype=torch.float64, device=b.device)
-        seg = torch.empty((every, b.total), dtype=b.dtype, device=b.device)
         ws = b.workspace(A.OP_VJP)
+        if every is None:
+            if ctx.nsteps:
+                b.vjp(ctx.traj, lam, tb, ctx.nsteps, ws, begin=True, end=True)
+            ctx.traj = None
+            return tb.view(b.count, 3), lam, None, None, None
+        seg = torch.empty((every, b.total), dtype=b.dtype, device=b.device)
         nseg = len(ctx.snaps)
         for i, snap in enumerate(reversed(ctx.snaps)):
             seg[0].copy_(snap)
@@ -211,8 +229,19 @@ class BatchedExplicitRun(torch.autograd.Function):
         return tb.view(b.count, 3), lam, None, None, None
 
 
-def explicit_run(theta, U0, batch, nsteps, every=100):
-    """Differentiable batched explicit trajectory (see BatchedExplicitRun)."""
+def trajectory_fits(batch, nsteps, reserve=0.8):
+    """True when nsteps + 1 states of the batch fit in `reserve` of the free device memory."""
+    free, _ = torch.cuda.mem_get_info(batch.device)
+    es = torch.empty((), dtype=batch.dtype).element_size()
+    return (nsteps + 1) * batch.total * es <= reserve * free
+
+
+def explicit_run(theta, U0, batch, nsteps, every="auto"):
+    """Differentiable batched explicit trajectory (see BatchedExplicitRun).
+    every: checkpoint interval, None to keep the whole trajectory, or "auto" (the
+    whole trajectory when it fits in device memory, else a snapshot every 100)."""
+    if every == "auto":
+        every = None if trajectory_fits(batch, nsteps) else 100
     return BatchedExplicitRun.apply(theta, U0, batch, nsteps, every)
 
 

@@ -115,13 +115,19 @@ def test_checkpointed_adjoint_bitwise_equals_stored_trajectory():
     b = _batch(sizes, theta, F32)
     U0 = b.pack([I.uniform_field(s, -0.05, 0.05, seed=i) for i, s in enumerate(sizes)])
     tgt = b.pack([I.uniform_field(s, -0.5, 0.5, seed=5 + i) for i, s in enumerate(sizes)])
-    grads = []
-    for every in (10, 40):
+    grads, finals = [], []
+    for every in (10, 40, None):  # None: the whole trajectory kept, no recomputation
         th = torch.tensor(theta, dtype=F64, device="cuda", requires_grad=True)
         UN = B.explicit_run(th, U0, b, 40, every=every)
         B.per_sample_mse(b, UN, tgt).backward()
         grads.append(th.grad.clone())
+        finals.append(UN.detach().clone())
     assert torch.equal(grads[0], grads[1])
+    assert torch.equal(grads[0], grads[2])
+    assert torch.equal(finals[0], finals[2])
+    plain = U0.clone()
+    b.step(plain, 40)
+    assert torch.equal(finals[2], plain)
 
 
 def _c4_batch(dtype, count=64, nsteps=2000):
