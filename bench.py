@@ -258,6 +258,49 @@ def coupled_record(stream, n=1024, steps=2000):
                          "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
 
 
+def implicit2d_record(stream, model, n, steps=10, dt=0.05):
+    """The paper's 2-D implicit benchmark shapes (backward Euler, Newton + GMRES(30)
+    with block Jacobi, FP32 fields): [0, 100]^2 with n^2 nodes, no-flux,
+    f' = 4c(c-1)(c-1/2) (W = 1), M = 1, kappa = 2 (Allen-Cahn) or 1.5 (Cahn-Hilliard);
+    initial field 0.5 + U(-0.05, 0.05).  dt = 0.05: block-Jacobi GMRES iterations grow
+    with dt kappa / h^2 (34 per Newton iteration at 2048^2, 57 at dt = 0.2)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    ch = model == A.CAHN_HILLIARD
+    p = S.Problem(n=(n, n), model=model, fe=A.F_01, dtype=torch.float32, W=1.0,
+                  kappa=1.5 if ch else 2.0, mobility=1.0, h=100.0 / (n - 1), bc=A.NOFLUX)
+    c0 = I.uniform_field((n, n), -0.05, 0.05, seed=0, base=0.5).astype(np.float32)
+    U = torch.as_tensor(np.concatenate([c0, np.zeros_like(c0)]) if ch else c0, device="cuda")
+    if ch:
+        S.step_explicit(p, U, 1e-30, 0)  # mu0
+    ws = S.workspace(p, A.OP_NEWTON)
+    Uold = torch.empty_like(U)
+    Uold.copy_(U)
+    S.newton_step(p, dt, Uold, U, ws=ws)  # warm-up (not timed)
+    torch.cuda.synchronize()
+    newton, gmres, ok = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Uold.copy_(U)
+        rep = S.newton_step(p, dt, Uold, U, ws=ws)
+        newton.append(rep.newton_its)
+        gmres.append(rep.gmres_its)
+        ok += int(rep.converged)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    name = "Cahn-Hilliard" if ch else "Allen-Cahn"
+    dof = n * n
+    return {"workload": f"2D {name} {n}x{n} on [0,100]^2, no-flux, backward Euler dt={dt}, "
+                        "Newton + GMRES(30) with block-Jacobi, FP32 fields",
+            "dof": dof, "steps": steps, "converged_steps": ok, "ms_per_step": 1e3 * el / steps,
+            "dof_steps_per_s": dof * steps / el, "newton_its_per_step": float(np.mean(newton)),
+            "gmres_its_per_newton": float(np.sum(gmres) / max(np.sum(newton), 1))}
+
+
 def coupled_implicit_record(stream, n=512, steps=20, dt=0.01):
     """The coupled benchmark shape with backward-Euler steps: 512^2, no-flux, dt = 0.01,
     Newton + GMRES(30) with 3x3 block Jacobi, FP32 fields, FP64 reductions."""
@@ -463,6 +506,9 @@ def main():
             print(json.dumps(adjoint_record(stream)), flush=True)
         if args.implicit:
             print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
+            from paper_2601_06079_amd import _abi as A
+            print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048)), flush=True)
+            print(json.dumps(implicit2d_record(stream, A.CAHN_HILLIARD, 512)), flush=True)
         if args.coupled:
             print(json.dumps(coupled_record(stream, steps=args.coupled)), flush=True)
             print(json.dumps(coupled_implicit_record(stream)), flush=True)
@@ -581,6 +627,9 @@ def main():
         out["implicit_ch3d128"] = implicit_record(20, stream)
         out["coupled_1024"] = coupled_record(stream)
         out["coupled_implicit_512"] = coupled_implicit_record(stream)
+        from paper_2601_06079_amd import _abi as A
+        out["implicit_ac2048_2d"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5)
+        out["implicit_ch512_2d"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)
