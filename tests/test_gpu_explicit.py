@@ -231,3 +231,33 @@ def test_jvp3d_plane_counts_agree(planes, model):
         S.tune_set(A.TUNE_JVP3D_PLANES, 0)
     assert torch.equal(ref, out)
     assert rel_l2(host(out), O.jvp(o, 2.0, host(U).astype(np.float64), host(v).astype(np.float64))) < 1e-5
+
+
+@pytest.mark.parametrize("reps", [181, 182])
+def test_explicit_largest_fields_tiled(reps):
+    """The largest 2-D fields: 23168^2 FP32 (2 147 024 896 bytes, the streaming
+    kernel at the top of its 32-bit offset range) and 23296^2 (beyond 2 GiB: the
+    node-centric path).  A periodic field that repeats a 128^2 pattern stays a
+    repetition of it, so every node of the big result must equal the 128^2 oracle
+    result tiled."""
+    announce("CH largest fields, tiled", reps)
+    p_small = 128
+    n = p_small * reps
+    assert (n * n * 4 < 2 ** 31) == (reps == 181)
+    g, o = pair((p_small, p_small), O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U0 = rounded(I.initial_state(dict(I.CH2048, n=(p_small, p_small)), seed=3), F32)
+    ref = torch.as_tensor(O.explicit(o, U0, 0.01, 2), dtype=F32, device="cuda")
+    N = p_small * p_small
+    gb = S.Problem(n=(n, n), model=A.CAHN_HILLIARD, fe=A.F_01, dtype=F32, W=1.0, kappa=2.0,
+                   mobility=1.0)
+    c = torch.as_tensor(U0[:N].astype(np.float32), device="cuda").view(p_small, p_small)
+    U = torch.zeros(2 * n * n, dtype=F32, device="cuda")
+    U[: n * n].view(n, n).copy_(c.repeat(reps, reps))
+    S.step_explicit(gb, U, 0.01, 2)
+    for plane in range(2):
+        got = U[plane * n * n:(plane + 1) * n * n].view(n, n)
+        want = ref[plane * N:(plane + 1) * N].view(p_small, p_small).repeat(reps, reps)
+        err = torch.linalg.vector_norm((got - want).double()) / torch.linalg.vector_norm(want.double())
+        assert float(err) < (1e-5 if plane == 0 else 1e-4), (plane, float(err))
+    del U
+    torch.cuda.empty_cache()
