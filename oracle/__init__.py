@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c"),
-        os.path.join(_HERE, "coupled_oracle.c")]
+        os.path.join(_HERE, "coupled_oracle.c"), os.path.join(_HERE, "elastic_oracle.c")]
 
 PERIODIC, NOFLUX = 0, 1
 AC, CH = 0, 1
@@ -113,6 +113,8 @@ def lib():
             _bind_conv(_lib)
         if hasattr(_lib, "orc_cp_residual"):
             _bind_coupled(_lib)
+        if hasattr(_lib, "orc_el_apply"):
+            _bind_elastic(_lib)
     return _lib
 
 
@@ -389,3 +391,117 @@ def cp_newton_be(p: CoupledProblem, dt: float, Uold, U0=None, rtol=1e-12, maxit=
     its = ct.c_int(0)
     rc = lib().orc_cp_newton_be(ct.byref(p._c()), dt, _d(Uold), _d(U), rtol, maxit, ct.byref(its))
     return U, rc == 0, its.value
+
+
+# ---------------------------------------------------------------------------
+# Eshelby inclusion: small-strain linear elasticity with a dilatational
+# eigenstrain (Eqs. 3-4, Supplementary Note 3 Eq. III.1).  Displacements are
+# [u_x ; u_y ; (u_z)].  See elastic_oracle.c.
+class _ElProblem(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("sym", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
+                ("E", ct.c_double), ("nu", ct.c_double), ("m", ct.c_double), ("a", ct.c_double),
+                ("l", ct.c_double)]
+
+
+@dataclass
+class ElasticProblem:
+    n: tuple
+    h: float = 1.0
+    E: float = 22.5
+    nu: float = 0.3
+    m: float = 0.01
+    a: float = 20.0
+    l: float = 0.5
+    sym: int = 1
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def nnodes(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def ndof(self) -> int:
+        return self.dim * self.nnodes
+
+    def _c(self) -> _ElProblem:
+        n3 = list(self.n) + [1] * (3 - len(self.n))
+        return _ElProblem(self.dim, self.sym, (ct.c_int64 * 3)(*n3), self.h, self.E, self.nu,
+                          self.m, self.a, self.l)
+
+
+def _bind_elastic(L):
+    P = ct.POINTER(_ElProblem)
+    D = ct.POINTER(ct.c_double)
+    f64, i32 = ct.c_double, ct.c_int
+    for name, res, args in (("orc_el_eigen", f64, [P, f64]),
+                            ("orc_el_free", i32, [P, ct.c_int64, i32]),
+                            ("orc_el_apply", i32, [P, D, D]),
+                            ("orc_el_rhs", i32, [P, D]),
+                            ("orc_el_volume_weights", i32, [P, D]),
+                            ("orc_el_solve", i32, [P, D, f64, i32]),
+                            ("orc_el_sensitivity", i32, [P, D, f64, i32, D, D]),
+                            ("orc_el_objective", f64, [P, D, D]),
+                            ("orc_el_eigen_integral", f64, [P])):
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = res, args
+
+
+def el_eigen(p: ElasticProblem, r: float) -> float:
+    """The diagonal eigenstrain at distance r from the origin corner."""
+    return lib().orc_el_eigen(ct.byref(p._c()), float(r))
+
+
+def el_free_mask(p: ElasticProblem) -> np.ndarray:
+    """1.0 where a displacement component is free, 0.0 where a symmetry plane fixes it."""
+    L, c = lib(), p._c()
+    return np.array([L.orc_el_free(ct.byref(c), a, comp) for comp in range(p.dim)
+                     for a in range(p.nnodes)], dtype=np.float64)
+
+
+def el_apply(p: ElasticProblem, u) -> np.ndarray:
+    """K u with identity rows on the fixed components."""
+    u = _arr(u, p.ndof)
+    y = np.zeros(p.ndof)
+    lib().orc_el_apply(ct.byref(p._c()), _d(u), _d(y))
+    return y
+
+
+def el_rhs(p: ElasticProblem) -> np.ndarray:
+    f = np.zeros(p.ndof)
+    lib().orc_el_rhs(ct.byref(p._c()), _d(f))
+    return f
+
+
+def el_volume_weights(p: ElasticProblem) -> np.ndarray:
+    g = np.zeros(p.ndof)
+    lib().orc_el_volume_weights(ct.byref(p._c()), _d(g))
+    return g
+
+
+def el_solve(p: ElasticProblem, rtol=1e-12, maxit=100000):
+    """Equilibrium displacement by CG. Returns (u, iterations or -1)."""
+    u = np.zeros(p.ndof)
+    it = lib().orc_el_solve(ct.byref(p._c()), _d(u), rtol, maxit)
+    return u, it
+
+
+def el_sensitivity(p: ElasticProblem, g=None, rtol=1e-12, maxit=100000):
+    """(O, dO/dE, dO/dnu, u, ok) for O = g . u (g = None: the volume change)."""
+    out = np.zeros(3)
+    u = np.zeros(p.ndof)
+    gp = None if g is None else _d(_arr(g, p.ndof))
+    rc = lib().orc_el_sensitivity(ct.byref(p._c()), gp, rtol, maxit, _d(out), _d(u))
+    return out[0], out[1], out[2], u, rc == 0
+
+
+def el_objective(p: ElasticProblem, u, g=None) -> float:
+    u = _arr(u, p.ndof)
+    gp = None if g is None else _d(_arr(g, p.ndof))
+    return lib().orc_el_objective(ct.byref(p._c()), gp, _d(u))
+
+
+def el_eigen_integral(p: ElasticProblem) -> float:
+    return lib().orc_el_eigen_integral(ct.byref(p._c()))
