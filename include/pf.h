@@ -105,9 +105,10 @@ int pf_version(void);
  *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel;
  *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
- *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product. */
+ *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product;
+ *   PF_TUNE_EL_PLANES:      z-planes (2-D: rows) per wave of the elasticity operator. */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
-       PF_TUNE_JVP3D_PLANES = 3 };
+       PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 /* The launch shape pf_step_explicit uses for p (2-D): steps fused per launch,
@@ -308,6 +309,79 @@ int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t
 int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                       void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
                       pf_batch_info* best, double* best_us_per_step, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Eshelby inclusion: linear elasticity with an eigenstrain (Eqs. 3-4,      */
+/* Supp. Note 3 Eq. III.1) and its (E, nu) sensitivities (Eq. 18, Eq. 21)   */
+/* ---------------------------------------------------------------------- */
+/* Small-strain equilibrium div sigma = 0 with sigma = C : (eps(u) - eps0), C
+ * isotropic with Young's modulus E and Poisson's ratio nu (Lame constants
+ * lam = E nu / ((1 + nu)(1 - 2 nu)), mu = E / (2 (1 + nu))), and the
+ * dilatational eigenstrain eps0 = e0(r) I with
+ *     e0(r) = m (1/2 - 1/2 tanh(l (r - a))),  r = distance from the origin,
+ * which is m inside the inclusion of radius a and 0 far outside (the printed
+ * formula has "+" before the tanh, which would put the misfit outside the
+ * inclusion; the library follows the text: m is the misfit inside).
+ * Grid [0, (n-1) h]^dim with n - 1 vector Q1 elements per axis, 2-point Gauss
+ * quadrature (eps0 evaluated at the Gauss points); dim 2 is plane strain with
+ * an in-plane eigenstrain.  The inclusion sits at the origin corner: symmetry
+ * planes through the origin (u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
+ * z = 0) and traction-free outer faces.  Fields hold dim components, component
+ * c of node i at c N + i (N nodes, node index i + n0 (j + n1 k)); vectors must
+ * be 16-byte aligned.  The fixed components are identity rows of K whose
+ * inputs do not act on the free rows, so K is symmetric positive definite. */
+typedef struct pf_elastic {
+    int32_t dim;    /* 2 (plane strain) or 3 */
+    int32_t dtype;  /* PF_F32 or PF_F64 (fields); CG scalars and dot products are FP64 */
+    int64_t n[3];   /* nodes per axis, each >= 2 (n[2] ignored when dim == 2) */
+    double h;       /* grid spacing > 0 */
+    double E, nu;   /* E > 0, -1 < nu < 0.5 */
+    double m, a, l; /* misfit magnitude, inclusion radius, interface sharpness */
+} pf_elastic;
+
+typedef struct pf_el_report {
+    int32_t iterations; /* CG iterations */
+    int32_t converged;  /* 1 if ||r|| <= rtol ||b|| (recursively updated residual) */
+    int32_t status;     /* 1 converged, 2 iteration limit, 3 breakdown, 4 non-finite */
+    int32_t reserved;
+    double res_norm;    /* final ||r||_2 */
+    double rhs_norm;    /* ||b||_2 */
+} pf_el_report;
+
+/* Workspace bytes for pf_el_solve, pf_el_objective and pf_el_sensitivity
+ * (seven fields plus FP64 partial sums). */
+int pf_el_workspace_size(const pf_elastic* p, size_t* bytes);
+
+/* y = K u (the stiffness of Eqs. 3-4 with the identity rows above).  u, y
+ * device, distinct.  Asynchronous. */
+int pf_el_apply(const pf_elastic* p, const void* u, void* y, void* stream);
+
+/* f = the eigenstrain load: f_i(a) = sum over elements and Gauss points of
+ * |J| (dim lam + 2 mu) e0(|x_q|) d_i phi_a(x_q); 0 on the fixed components.
+ * Evaluated in FP64.  Asynchronous. */
+int pf_el_rhs(const pf_elastic* p, void* f, void* stream);
+
+/* Solve K u = b by conjugate gradients from u = 0 until ||r|| <= rtol ||b||
+ * or maxit iterations; b = NULL solves for the eigenstrain load.  b's entries
+ * on the fixed components are copied into u.  Host-synchronous; returns PF_OK,
+ * PF_ENOCONV (u holds the last iterate) or PF_ENONFINITE; rep may be NULL. */
+int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,
+                pf_el_report* rep, void* ws, void* stream);
+
+/* out[0] (device double) = g . u, accumulated in FP64 in a fixed order;
+ * g = NULL selects the volume change int div u dV of Eq. 21 (the outward
+ * face-normal component of u weighted by each node's face share).
+ * Asynchronous. */
+int pf_el_objective(const pf_elastic* p, const void* g, const void* u, double* out, void* ws,
+                    void* stream);
+
+/* Sensitivities of O = g . u (g = NULL: the volume change) at the equilibrium u
+ * (as returned by pf_el_solve) with respect to theta = (E, nu), by the adjoint
+ * method of Eq. 18: solve K lambda = g (fixed components of g ignored), then
+ * dO/dtheta = lambda . (df/dtheta - dK/dtheta u).  out (host, 3 doubles) =
+ * {O, dO/dE, dO/dnu}.  Host-synchronous; the adjoint solve uses rtol / maxit. */
+int pf_el_sensitivity(const pf_elastic* p, const void* g, const void* u, double* out, double rtol,
+                      int32_t maxit, pf_el_report* rep, void* ws, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Learned K-step surrogate for 2-D Cahn-Hilliard (added by this library;  */

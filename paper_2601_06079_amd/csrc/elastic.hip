@@ -1,0 +1,1016 @@
+// elastic.hip -- the Eshelby-inclusion benchmark: small-strain linear elasticity
+// with a dilatational eigenstrain (Eqs. 3-4; eigenstrain of Supp. Note 3,
+// Eq. III.1), vector Q1 elements, solved matrix-free by conjugate gradients.
+//
+// Operator.  With one homogeneous isotropic stiffness (Lame constants lam, mu)
+// the Q1 stiffness block that couples displacement component j of node b to
+// equation i of node a is
+//     K_ij = lam P_ij + mu P_ji + mu delta_ij (P_xx + P_yy + P_zz),
+//     P_ij(a, b) = integral of d_i phi_a d_j phi_b,
+// and on a structured grid every P_ij is a Kronecker product of three 1-D
+// three-point operators (the 2-point Gauss rule is exact for them):
+//     mass        M = (1/6, 2/3, 1/6) h
+//     stiffness   A = (-1, 2, -1) / h
+//     row-derivative    R = integral phi_a' phi_b = ( 1/2, 0, -1/2)
+//     column-derivative C = integral phi_a phi_b' = (-1/2, 0,  1/2)
+// (interior values; a node on the first or last plane of an axis keeps only the
+// half that comes from its one element there).  P_ij takes A on axis i when
+// i == j, R on axis i and C on axis j when i != j, and M on the other axes.
+//
+// Kernel k_el_apply.  One wave covers 64 consecutive nodes of an x-y plane
+// (x fastest; 62 outputs, lanes 0 and 63 are halo) and marches along z over a
+// chunk of planes.  Per plane it loads the three displacement components of
+// its own column at rows y-1, y, y+1 (9 coalesced loads), reduces them with
+// the four y-operators (12 row sums), keeps three planes of row sums in
+// registers, combines them with the z-operators of the output plane into the
+// per-column quantities each x-operator needs, and finishes the x-direction
+// through DPP wave shifts.  Boundary nodes need no separate path: the 1-D
+// operators of a node are built from two flags (element below / above exists),
+// per lane for x and y and per wave for z.  About 150 FMA per node.
+//
+// Boundary conditions (the benchmark's quarter / octant model): symmetry on the
+// planes through the origin (u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
+// z = 0) as identity rows with those inputs masked out, so K stays symmetric
+// positive definite; the other faces are traction-free (the natural boundary).
+// In 2-D (plane strain) the kernel's y-axis is degenerate and the problem's y
+// axis plays the marching axis.
+//
+// Solver.  Conjugate gradients in the one-reduction form of Chronopoulos and
+// Gear: per iteration one apply w = K r fused with the per-block partial sums of
+// gamma = r.r and delta = w.r (FP64), then one streaming update in which every
+// block reduces those partials in the same fixed order, forms alpha and beta
+// and applies p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s.  No
+// grid-wide fence or atomic is needed (an agent-scope release per block costs
+// an L2 write-back on this multi-XCD part).  The host only polls the iteration
+// count and residual through pinned memory; iterations enqueued after
+// convergence return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/pf.h"
+#include "api_internal.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace pfel {
+
+using pfk::WAVE;
+
+constexpr int EL_BLOCK = 256;
+constexpr int EL_WAVES = EL_BLOCK / WAVE;
+constexpr int EL_OUT = WAVE - 2;  // outputs per wave
+constexpr int EL_MAX_PARTS = 8192;
+
+// device-side CG state (FP64), two slots in the workspace: iteration i reads
+// slot i & 1 and writes slot (i + 1) & 1, so no kernel reads what it writes
+enum { S_GAMMA_OLD = 0, S_ALPHA_OLD, S_TOL2, S_ITS, S_DONE, S_MAXIT, S_GAMMA, S_COUNT };
+constexpr int S_SLOT = 8;  // doubles per slot
+// host-visible mirror: its, done, gamma, gamma0
+enum { H_ITS = 0, H_DONE, H_GAMMA, H_GAMMA0, H_COUNT };
+enum { DONE_NO = 0, DONE_CONVERGED = 1, DONE_MAXIT = 2, DONE_BREAKDOWN = 3, DONE_NONFINITE = 4 };
+
+struct Grid {
+    int dim;
+    int nx, ny, nz;  // kernel axes: x = lanes, y = row axis (1 in 2-D), z = marching axis
+    long long N;     // nodes
+    long long P;     // nodes per plane (nx * ny)
+    int coff[3];     // component plane offsets in units of N (kernel comps x, y, z); -1 = absent
+    double h;
+};
+
+Grid grid_of(const pf_elastic* p)
+{
+    Grid g{};
+    g.dim = p->dim;
+    g.h = p->h;
+    g.nx = (int)p->n[0];
+    if (p->dim == 3) {
+        g.ny = (int)p->n[1];
+        g.nz = (int)p->n[2];
+        g.coff[0] = 0;
+        g.coff[1] = 1;
+        g.coff[2] = 2;
+    } else {
+        g.ny = 1;
+        g.nz = (int)p->n[1];
+        g.coff[0] = 0;
+        g.coff[1] = -1;
+        g.coff[2] = 1;
+    }
+    g.P = (long long)g.nx * g.ny;
+    g.N = g.P * g.nz;
+    return g;
+}
+
+// 1-D operators of one node along one axis; lo / hi: the element below / above exists
+template <typename T>
+struct Fac {
+    T m[3], a[3], r[3], c[3];
+};
+
+template <typename T>
+__device__ __forceinline__ Fac<T> fac(bool lo, bool hi)
+{
+    const T L = lo ? T(1) : T(0), H = hi ? T(1) : T(0);
+    Fac<T> f;
+    f.m[0] = L * T(1.0 / 6.0);
+    f.m[1] = (L + H) * T(1.0 / 3.0);
+    f.m[2] = H * T(1.0 / 6.0);
+    f.a[0] = -L;
+    f.a[1] = L + H;
+    f.a[2] = -H;
+    f.r[0] = L * T(0.5);
+    f.r[1] = (L - H) * T(0.5);
+    f.r[2] = -H * T(0.5);
+    f.c[0] = -L * T(0.5);
+    f.c[1] = (L - H) * T(0.5);
+    f.c[2] = H * T(0.5);
+    return f;
+}
+
+template <typename T>
+__device__ __forceinline__ T tap3(const T w[3], T a, T b, T c)
+{
+    return pfk::fmaT(w[0], a, pfk::fmaT(w[1], b, w[2] * c));
+}
+
+// row sums of one component on one plane: [M, A, R, C] along y, and the raw value
+template <typename T>
+struct RS {
+    T s[4];
+};
+
+// wave-interleaved block -> logical block map: the hardware hands consecutive
+// blocks to the eight XCDs in turn; give each XCD a contiguous range so that
+// neighbouring segments (which share rows) meet in the same L2
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return xcd * q + min(xcd, r) + idx;
+}
+
+template <typename T>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh)
+{
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, WAVE);
+        b += __shfl_down(b, off, WAVE);
+    }
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    if (l == 0) {
+        sh[2 * w] = a;
+        sh[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0.0;
+        b = 0.0;
+        for (int i = 0; i < EL_WAVES; ++i) {
+            a += sh[2 * i];
+            b += sh[2 * i + 1];
+        }
+    }
+}
+
+struct CgArgs {
+    double* part;        // 2 doubles per block of the apply
+    const double* state; // the CG state slot this iteration reads (S_DONE)
+};
+
+// y = K u (ident: identity rows on the fixed components, else zero rows).
+// CG: u is the residual r, y is w = K r; each block stores its partial sums of
+// r.r and w.r (the update kernel reduces them).
+template <typename T, int D, bool CG>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T scale, int ident,
+                                                      const T* __restrict__ u, T* __restrict__ y,
+                                                      int tz, int nseg, int nwaves, CgArgs cg)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    if (CG && cg.state[S_DONE] != 0.0) return;
+    const int lane = threadIdx.x % WAVE;
+    const int wv = xcd_block(blockIdx.x, gridDim.x) * EL_WAVES + threadIdx.x / WAVE;
+    double pg = 0.0, pd = 0.0;
+    if (wv < nwaves) {
+        const int seg = wv % nseg, chunk = wv / nseg;
+        const long long q0 = (long long)seg * EL_OUT - 1 + lane;
+        const bool out_lane = lane >= 1 && lane <= EL_OUT && q0 >= 0 && q0 < g.P;
+        const long long q = q0 < 0 ? 0 : (q0 >= g.P ? g.P - 1 : q0);
+        const int x = (int)(q % g.nx), yr = (int)(q / g.nx);
+        const Fac<T> fx = fac<T>(x > 0, x < g.nx - 1);
+        const Fac<T> fy = fac<T>(yr > 0, yr < g.ny - 1);
+        const long long qm = (D == 3 && yr > 0) ? q - g.nx : q;
+        const long long qp = (D == 3 && yr < g.ny - 1) ? q + g.nx : q;
+        const long long N = g.N, P = g.P;
+        const T* ux = u + (long long)g.coff[0] * N;
+        const T* uy = D == 3 ? u + (long long)g.coff[1] * N : u;
+        const T* uz = u + (long long)g.coff[2] * N;
+        const T zx = x == 0 ? T(0) : T(1);             // u_x fixed on x = 0
+        const T zym = (yr - 1 == 0) ? T(0) : T(1);      // u_y fixed on y = 0 (row y-1)
+        const T zy0 = (yr == 0) ? T(0) : T(1);          // (row y)
+
+        const T lm2 = lam + T(2) * mu;
+        // three planes of row sums (k-1, k, k+1) and raw values of plane k, k+1
+        RS<T> rx[3], ry[3], rz[3];
+        T raw[2][3];
+        auto load = [&](int kz, RS<T>& ox, RS<T>& oy, RS<T>& oz, T* rv) {
+            if (kz < 0 || kz >= g.nz) {
+                for (int i = 0; i < 4; ++i) ox.s[i] = oy.s[i] = oz.s[i] = T(0);
+                rv[0] = rv[1] = rv[2] = T(0);
+                return;
+            }
+            const long long o = (long long)kz * P;
+            const T zz = kz == 0 ? T(0) : T(1);  // u_z fixed on z = 0
+            const T x0 = ux[o + q], z0 = uz[o + q];
+            rv[0] = x0;
+            rv[2] = z0;
+            if (D == 3) {
+                const T xm = ux[o + qm], xp = ux[o + qp];
+                const T y0 = uy[o + q], ym = uy[o + qm], yp = uy[o + qp];
+                const T zm = uz[o + qm], zp = uz[o + qp];
+                rv[1] = y0;
+                const T a0 = xm * zx, a1 = x0 * zx, a2 = xp * zx;
+                const T b0 = ym * zym, b1 = y0 * zy0, b2 = yp;
+                const T c0 = zm * zz, c1 = z0 * zz, c2 = zp * zz;
+                ox.s[0] = tap3(fy.m, a0, a1, a2);
+                ox.s[1] = tap3(fy.a, a0, a1, a2);
+                ox.s[2] = tap3(fy.r, a0, a1, a2);
+                ox.s[3] = tap3(fy.c, a0, a1, a2);
+                oy.s[0] = tap3(fy.m, b0, b1, b2);
+                oy.s[1] = tap3(fy.a, b0, b1, b2);
+                oy.s[2] = tap3(fy.r, b0, b1, b2);
+                oy.s[3] = tap3(fy.c, b0, b1, b2);
+                oz.s[0] = tap3(fy.m, c0, c1, c2);
+                oz.s[1] = tap3(fy.a, c0, c1, c2);
+                oz.s[2] = tap3(fy.r, c0, c1, c2);
+                oz.s[3] = tap3(fy.c, c0, c1, c2);
+            } else {
+                rv[1] = T(0);
+                ox.s[0] = x0 * zx;
+                oz.s[0] = z0 * zz;
+                ox.s[1] = ox.s[2] = ox.s[3] = T(0);
+                oz.s[1] = oz.s[2] = oz.s[3] = T(0);
+                for (int i = 0; i < 4; ++i) oy.s[i] = T(0);
+            }
+        };
+        const int k0 = chunk * tz, k1 = min(g.nz, k0 + tz);
+        load(k0 - 1, rx[0], ry[0], rz[0], raw[0]);
+        load(k0, rx[1], ry[1], rz[1], raw[0]);
+        for (int k = k0; k < k1; ++k) {
+            load(k + 1, rx[2], ry[2], rz[2], raw[1]);
+            const Fac<T> fz = fac<T>(k > 0, k < g.nz - 1);
+            // Q_c^{FG}: y-operator F (row sums), z-operator G over the three planes
+            auto Q = [&](const RS<T>* r, int F, const T* G) {
+                return tap3(G, r[0].s[F], r[1].s[F], r[2].s[F]);
+            };
+            enum { M = 0, A = 1, R = 2, C = 3 };
+            T SA0, SM0, SR0, SC0, SA2, SM2, SR2, SC2, SA1 = T(0), SM1 = T(0), SR1 = T(0), SC1 = T(0);
+            {
+                const T q0MM = Q(rx, M, fz.m), q0MA = Q(rx, M, fz.a), q0MR = Q(rx, M, fz.r),
+                        q0MC = Q(rx, M, fz.c);
+                const T q2MM = Q(rz, M, fz.m), q2MA = Q(rz, M, fz.a), q2MR = Q(rz, M, fz.r),
+                        q2MC = Q(rz, M, fz.c);
+                SA0 = lm2 * q0MM;
+                SM0 = mu * q0MA;
+                SR0 = lam * q2MC;
+                SC0 = mu * q2MR;
+                SM2 = lm2 * q2MA;
+                SA2 = mu * q2MM;
+                SC2 = lam * q0MR;
+                SR2 = mu * q0MC;
+                if (D == 3) {
+                    const T q0AM = Q(rx, A, fz.m), q0RM = Q(rx, R, fz.m), q0CM = Q(rx, C, fz.m);
+                    const T q1MM = Q(ry, M, fz.m), q1AM = Q(ry, A, fz.m), q1MA = Q(ry, M, fz.a),
+                            q1CM = Q(ry, C, fz.m), q1RM = Q(ry, R, fz.m), q1CR = Q(ry, C, fz.r),
+                            q1RC = Q(ry, R, fz.c);
+                    const T q2AM = Q(rz, A, fz.m), q2RC = Q(rz, R, fz.c), q2CR = Q(rz, C, fz.r);
+                    SM0 = mu * (q0AM + q0MA);
+                    SR0 = lam * (q1CM + q2MC);
+                    SC0 = mu * (q1RM + q2MR);
+                    SM1 = lm2 * q1AM + mu * q1MA + lam * q2RC + mu * q2CR;
+                    SA1 = mu * q1MM;
+                    SC1 = lam * q0RM;
+                    SR1 = mu * q0CM;
+                    SM2 = lm2 * q2MA + mu * q2AM + lam * q1CR + mu * q1RC;
+                }
+            }
+            auto xsum = [&](T sa, T sm, T sr, T sc) {
+                T acc = pfk::fmaT(fx.a[1], sa, pfk::fmaT(fx.m[1], sm, pfk::fmaT(fx.r[1], sr, fx.c[1] * sc)));
+                acc = pfk::fmaT(fx.a[0], pfk::from_left(sa), acc);
+                acc = pfk::fmaT(fx.m[0], pfk::from_left(sm), acc);
+                acc = pfk::fmaT(fx.r[0], pfk::from_left(sr), acc);
+                acc = pfk::fmaT(fx.c[0], pfk::from_left(sc), acc);
+                acc = pfk::fmaT(fx.a[2], pfk::from_right(sa), acc);
+                acc = pfk::fmaT(fx.m[2], pfk::from_right(sm), acc);
+                acc = pfk::fmaT(fx.r[2], pfk::from_right(sr), acc);
+                acc = pfk::fmaT(fx.c[2], pfk::from_right(sc), acc);
+                return acc * scale;
+            };
+            const T w0 = xsum(SA0, SM0, SR0, SC0);
+            const T w2 = xsum(SA2, SM2, SR2, SC2);
+            T w1 = T(0);
+            if (D == 3) w1 = xsum(SA1, SM1, SR1, SC1);
+            if (out_lane) {
+                const long long o = (long long)k * P + q;
+                const T r0 = raw[0][0], r1 = raw[0][1], r2 = raw[0][2];
+                const T y0 = x == 0 ? (ident ? r0 : T(0)) : w0;
+                const T y2 = k == 0 ? (ident ? r2 : T(0)) : w2;
+                y[(long long)g.coff[0] * N + o] = y0;
+                y[(long long)g.coff[2] * N + o] = y2;
+                T y1 = T(0);
+                if (D == 3) {
+                    y1 = yr == 0 ? (ident ? r1 : T(0)) : w1;
+                    y[(long long)g.coff[1] * N + o] = y1;
+                }
+                if (CG) {
+                    pg += (double)r0 * r0 + (double)r2 * r2 + (D == 3 ? (double)r1 * r1 : 0.0);
+                    pd += (double)y0 * r0 + (double)y2 * r2 + (D == 3 ? (double)y1 * r1 : 0.0);
+                }
+            }
+            rx[0] = rx[1];
+            rx[1] = rx[2];
+            ry[0] = ry[1];
+            ry[1] = ry[2];
+            rz[0] = rz[1];
+            rz[1] = rz[2];
+            raw[0][0] = raw[1][0];
+            raw[0][1] = raw[1][1];
+            raw[0][2] = raw[1][2];
+        }
+    }
+    if (!CG) return;
+    block_sum2<T>(pg, pd, sh);
+    if (threadIdx.x == 0) {
+        cg.part[2 * blockIdx.x] = pg;
+        cg.part[2 * blockIdx.x + 1] = pd;
+    }
+}
+
+// One CG iteration's scalar step and vector update.  Every block reduces the
+// apply's partial sums in the same fixed order (so all blocks agree bit for
+// bit), forms gamma = r.r, delta = w.r and
+//     beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old)
+// (beta = 0 on the first iteration), stops on ||r||^2 <= rtol^2 ||b||^2, the
+// iteration limit, a non-positive denominator or a non-finite value, and else
+// updates p = r + beta p;  s = w + beta s;  x += alpha p;  r -= alpha s.
+// Block 0 writes the next state slot and the host mirror.
+template <typename T>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_cg_update(long long n, const double* __restrict__ part, int nparts,
+                                                          const double* __restrict__ sin, double* __restrict__ sout,
+                                                          double* host, T* __restrict__ x, T* __restrict__ r,
+                                                          T* __restrict__ p, T* __restrict__ s,
+                                                          const T* __restrict__ w)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    __shared__ double sc[2];
+    if (sin[S_DONE] != 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x < S_SLOT) sout[threadIdx.x] = sin[threadIdx.x];
+        return;
+    }
+    double ga = 0.0, de = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += EL_BLOCK) {
+        ga += part[2 * i];
+        de += part[2 * i + 1];
+    }
+    block_sum2<T>(ga, de, sh);
+    if (threadIdx.x == 0) {
+        const double its = sin[S_ITS];
+        const double tol2 = its == 0.0 ? sin[S_TOL2] * ga : sin[S_TOL2];
+        double done = DONE_NO, alpha = 0.0, beta = 0.0;
+        if (!(std::isfinite(ga) && std::isfinite(de))) {
+            done = DONE_NONFINITE;
+        } else if (ga <= tol2) {
+            done = DONE_CONVERGED;
+        } else if (its >= sin[S_MAXIT]) {
+            done = DONE_MAXIT;
+        } else {
+            beta = its == 0.0 ? 0.0 : ga / sin[S_GAMMA_OLD];
+            const double den = its == 0.0 ? de : de - beta * ga / sin[S_ALPHA_OLD];
+            if (!(den > 0.0)) done = DONE_BREAKDOWN;
+            else alpha = ga / den;
+        }
+        sc[0] = done == DONE_NO ? alpha : 0.0;
+        sc[1] = done == DONE_NO ? beta : 0.0;
+        if (blockIdx.x == 0) {
+            sout[S_GAMMA_OLD] = done == DONE_NO ? ga : sin[S_GAMMA_OLD];
+            sout[S_ALPHA_OLD] = done == DONE_NO ? alpha : sin[S_ALPHA_OLD];
+            sout[S_TOL2] = tol2;
+            sout[S_ITS] = done == DONE_NO ? its + 1.0 : its;
+            sout[S_DONE] = done;
+            sout[S_MAXIT] = sin[S_MAXIT];
+            sout[S_GAMMA] = ga;
+            if (its == 0.0)
+                __hip_atomic_store(&host[H_GAMMA0], ga, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host[H_GAMMA], ga, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host[H_ITS], done == DONE_NO ? its + 1.0 : its, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host[H_DONE], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    __syncthreads();
+    const T alpha = (T)sc[0], beta = (T)sc[1];
+    if (sc[0] == 0.0) return;  // stopped (alpha > 0 on every real iteration)
+    constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const long long nv = n / VW;
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < nv; i += stride) {
+        V rv = reinterpret_cast<const V*>(r)[i], pv = reinterpret_cast<const V*>(p)[i];
+        V sv = reinterpret_cast<const V*>(s)[i], wv = reinterpret_cast<const V*>(w)[i];
+        V xv = reinterpret_cast<const V*>(x)[i];
+        T* R = reinterpret_cast<T*>(&rv);
+        T* Pp = reinterpret_cast<T*>(&pv);
+        T* S = reinterpret_cast<T*>(&sv);
+        T* W = reinterpret_cast<T*>(&wv);
+        T* X = reinterpret_cast<T*>(&xv);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            Pp[j] = pfk::fmaT(beta, Pp[j], R[j]);
+            S[j] = pfk::fmaT(beta, S[j], W[j]);
+            X[j] = pfk::fmaT(alpha, Pp[j], X[j]);
+            R[j] = pfk::fmaT(-alpha, S[j], R[j]);
+        }
+        reinterpret_cast<V*>(p)[i] = pv;
+        reinterpret_cast<V*>(s)[i] = sv;
+        reinterpret_cast<V*>(x)[i] = xv;
+        reinterpret_cast<V*>(r)[i] = rv;
+    }
+    for (long long i = nv * VW + blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride) {
+        const T pn = pfk::fmaT(beta, p[i], r[i]);
+        const T sn = pfk::fmaT(beta, s[i], w[i]);
+        p[i] = pn;
+        s[i] = sn;
+        x[i] = pfk::fmaT(alpha, pn, x[i]);
+        r[i] = pfk::fmaT(-alpha, sn, r[i]);
+    }
+}
+
+// Eigenstrain load f_i(a) = sum over the node's elements and their Gauss points
+// of |J| coef e0(|x_q|) d_i phi_a(x_q), e0 of Eq. III.1; zero on fixed components.
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_rhs(Grid g, double coef, double m, double a, double l,
+                                                    T* __restrict__ f)
+{
+    const long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
+    if (i >= g.N) return;
+    int idx[3];
+    int n[3];
+    // problem axes (not kernel axes): 2-D uses (x, y), 3-D (x, y, z)
+    n[0] = g.nx;
+    n[1] = D == 3 ? g.ny : g.nz;
+    n[2] = D == 3 ? g.nz : 1;
+    idx[0] = (int)(i % n[0]);
+    idx[1] = (int)((i / n[0]) % n[1]);
+    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    const double h = g.h;
+    const double gq = 0.57735026918962576451;  // 1/sqrt(3)
+    const double detJ = D == 3 ? 0.125 * h * h * h : 0.25 * h * h;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < (1 << D); ++e) {
+        // element whose local node bit b_k (0 = lower, 1 = upper) on axis k is e's bit
+        int el[3];
+        bool ok = true;
+        for (int k = 0; k < D; ++k) {
+            const int b = (e >> k) & 1;
+            el[k] = idx[k] - b;
+            if (el[k] < 0 || el[k] >= n[k] - 1) ok = false;
+        }
+        if (!ok) continue;
+        for (int qp = 0; qp < (1 << D); ++qp) {
+            double r2 = 0.0, val[3], der[3];
+            for (int k = 0; k < D; ++k) {
+                const int qb = (qp >> k) & 1, b = (e >> k) & 1;
+                const double xi = qb ? gq : -gq;  // reference coordinate in [-1, 1]
+                const double xk = h * (el[k] + 0.5 * (1.0 + xi));
+                r2 += xk * xk;
+                const double sgn = b ? 1.0 : -1.0;
+                val[k] = 0.5 * (1.0 + sgn * xi);
+                der[k] = sgn / h;
+            }
+            const double e0 = m * (0.5 - 0.5 * tanh(l * (sqrt(r2) - a)));
+            const double w = detJ * coef * e0;
+            for (int c = 0; c < D; ++c) {
+                double gc = der[c];
+                for (int k = 0; k < D; ++k)
+                    if (k != c) gc *= val[k];
+                acc[c] += w * gc;
+            }
+        }
+    }
+    for (int c = 0; c < D; ++c) f[c * g.N + i] = idx[c] == 0 ? T(0) : (T)acc[c];
+}
+
+// volume-change weights: integral of d_i phi_a over the body, i.e. the outward
+// face normal times the face share of the node (nonzero on the far faces only)
+template <int D>
+__device__ __forceinline__ double vol_weight(const int* idx, const int* n, int c, double h)
+{
+    if (idx[c] == 0 || idx[c] != n[c] - 1) return 0.0;
+    double w = 1.0;
+    for (int k = 0; k < D; ++k)
+        if (k != c) w *= (idx[k] == 0 || idx[k] == n[k] - 1) ? 0.5 * h : h;
+    return w;
+}
+
+// partial sums of g . u (g == nullptr: the volume-change weights), one per block
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_dot(Grid g, const T* __restrict__ gw, const T* __restrict__ u,
+                                                    double* __restrict__ part)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    int n[3];
+    n[0] = g.nx;
+    n[1] = D == 3 ? g.ny : g.nz;
+    n[2] = D == 3 ? g.nz : 1;
+    double acc = 0.0, dummy = 0.0;
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < g.N; i += stride) {
+        int idx[3];
+        idx[0] = (int)(i % n[0]);
+        idx[1] = (int)((i / n[0]) % n[1]);
+        idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+        for (int c = 0; c < D; ++c) {
+            const double wc = gw ? (double)gw[c * g.N + i] : vol_weight<D>(idx, n, c, g.h);
+            acc += wc * (double)u[c * g.N + i];
+        }
+    }
+    block_sum2<T>(acc, dummy, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// one block: out[0] = sum of part[0..nb) in a fixed order
+__global__ void __launch_bounds__(EL_BLOCK) k_el_sum(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ out)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += EL_BLOCK) a += part[i];
+    block_sum2<float>(a, b, sh);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+// CG state initialisation: slot 0 (slot 1 cleared) and the host mirror
+__global__ void k_el_cg_init(double* state, double* host, double rtol2, double maxit)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int i = 0; i < 2 * S_SLOT; ++i) state[i] = 0.0;
+        state[S_ALPHA_OLD] = 1.0;
+        state[S_TOL2] = rtol2;
+        state[S_MAXIT] = maxit;
+        for (int i = 0; i < H_COUNT; ++i)
+            __hip_atomic_store(&host[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_fill(long long n, T* __restrict__ a, const T* __restrict__ src)
+{
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride)
+        a[i] = src ? src[i] : T(0);
+}
+
+// dst = src with the fixed components zeroed (src == nullptr: the volume-change weights)
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_weights(Grid g, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
+    if (i >= g.N) return;
+    int n[3], idx[3];
+    n[0] = g.nx;
+    n[1] = D == 3 ? g.ny : g.nz;
+    n[2] = D == 3 ? g.nz : 1;
+    idx[0] = (int)(i % n[0]);
+    idx[1] = (int)((i / n[0]) % n[1]);
+    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    for (int c = 0; c < D; ++c) {
+        const long long o = c * g.N + i;
+        dst[o] = idx[c] == 0 ? T(0) : (src ? src[o] : (T)vol_weight<D>(idx, n, c, g.h));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+struct ApplyShape {
+    int tz, nseg, nwaves, blocks;
+};
+
+ApplyShape apply_shape(const Grid& g)
+{
+    ApplyShape s{};
+    s.nseg = (int)((g.P + EL_OUT - 1) / EL_OUT);
+    // about 4096 waves (four per SIMD), chunks of 4..64 planes
+    long long want = ((long long)g.nz * s.nseg + 4095) / 4096;
+    int tz = (int)std::min<long long>(64, std::max<long long>(4, want));
+    if (pfk::tune_el_planes() > 0) tz = pfk::tune_el_planes();
+    tz = std::min(tz, g.nz);
+    s.tz = tz;
+    const int nchunk = (g.nz + tz - 1) / tz;
+    s.nwaves = s.nseg * nchunk;
+    s.blocks = (s.nwaves + EL_WAVES - 1) / EL_WAVES;
+    return s;
+}
+
+template <typename T>
+void launch_apply(const Grid& g, double lam, double mu, int ident, const T* u, T* y, const CgArgs* cg,
+                  hipStream_t st)
+{
+    const ApplyShape s = apply_shape(g);
+    const T scale = (T)(g.dim == 3 ? g.h : 1.0);
+    CgArgs a = cg ? *cg : CgArgs{nullptr, nullptr};
+    if (g.dim == 3) {
+        if (cg)
+            k_el_apply<T, 3, true><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
+                                                                  s.nseg, s.nwaves, a);
+        else
+            k_el_apply<T, 3, false><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
+                                                                   s.nseg, s.nwaves, a);
+    } else {
+        if (cg)
+            k_el_apply<T, 2, true><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
+                                                                  s.nseg, s.nwaves, a);
+        else
+            k_el_apply<T, 2, false><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
+                                                                   s.nseg, s.nwaves, a);
+    }
+}
+
+int stream_blocks(long long n)
+{
+    return (int)std::min<long long>(2048, std::max<long long>(1, (n + 4 * EL_BLOCK - 1) / (4 * EL_BLOCK)));
+}
+
+template <typename T>
+void launch_rhs(const Grid& g, double coef, const pf_elastic* p, T* f, hipStream_t st)
+{
+    const int blocks = (int)((g.N + EL_BLOCK - 1) / EL_BLOCK);
+    if (g.dim == 3)
+        k_el_rhs<T, 3><<<blocks, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f);
+    else
+        k_el_rhs<T, 2><<<blocks, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f);
+}
+
+constexpr int DOT_BLOCKS = 1024;
+
+template <typename T>
+void launch_dot(const Grid& g, const T* gw, const T* u, double* part, double* out, hipStream_t st)
+{
+    const int blocks = (int)std::min<long long>(DOT_BLOCKS, (g.N + EL_BLOCK - 1) / EL_BLOCK);
+    if (g.dim == 3)
+        k_el_dot<T, 3><<<blocks, EL_BLOCK, 0, st>>>(g, gw, u, part);
+    else
+        k_el_dot<T, 2><<<blocks, EL_BLOCK, 0, st>>>(g, gw, u, part);
+    k_el_sum<<<1, EL_BLOCK, 0, st>>>(part, blocks, out);
+}
+
+void lame(const pf_elastic* p, double* lam, double* mu)
+{
+    *lam = p->E * p->nu / ((1.0 + p->nu) * (1.0 - 2.0 * p->nu));
+    *mu = p->E / (2.0 * (1.0 + p->nu));
+}
+
+int validate(const pf_elastic* p)
+{
+    using pfapi::fail;
+    if (!p) return fail(PF_EINVAL, "elastic problem is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(PF_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
+    long long N = 1, P = 1;
+    for (int k = 0; k < p->dim; ++k) {
+        if (p->n[k] < 2) return fail(PF_EINVAL, "n[%d] = %lld must be >= 2", k, (long long)p->n[k]);
+        if (p->n[k] > (1ll << 30)) return fail(PF_EINVAL, "n[%d] too large", k);
+        N *= p->n[k];
+        if (k < p->dim - 1) P *= p->n[k];
+    }
+    if (N * p->dim > (1ll << 38)) return fail(PF_EINVAL, "grid too large");
+    if (P > (1ll << 31) - 64) return fail(PF_EINVAL, "an x-y plane holds too many nodes");
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(PF_EINVAL, "h must be finite and > 0");
+    if (!(p->E > 0.0) || !std::isfinite(p->E)) return fail(PF_EINVAL, "E must be finite and > 0");
+    if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(PF_EINVAL, "nu must lie in (-1, 0.5)");
+    if (!std::isfinite(p->m) || !std::isfinite(p->a) || !std::isfinite(p->l))
+        return fail(PF_EINVAL, "m, a and l must be finite");
+    return PF_OK;
+}
+
+long long ndof(const pf_elastic* p)
+{
+    long long N = 1;
+    for (int k = 0; k < p->dim; ++k) N *= p->n[k];
+    return N * p->dim;
+}
+
+size_t esz(const pf_elastic* p) { return p->dtype == PF_F64 ? 8 : 4; }
+
+int check_vec(const void* v, const pf_elastic* p, const char* name)
+{
+    if (!v) return pfapi::fail(PF_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(v) % 16)
+        return pfapi::fail(PF_EINVAL, "%s must be 16-byte aligned", name);
+    (void)p;
+    return PF_OK;
+}
+
+// workspace: CG vectors r, p, s, w, then (sensitivity) lambda, g, t; partials; CG state
+struct Ws {
+    void* r;
+    void* p;
+    void* s;
+    void* w;
+    void* lam;
+    void* g;
+    void* t;
+    double* part;
+    double* scal;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t ws_bytes(const pf_elastic* p, Ws* out, void* base)
+{
+    const size_t vb = align256((size_t)ndof(p) * esz(p));
+    char* b = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void* q = b ? b + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    Ws w{};
+    w.r = take(vb);
+    w.p = take(vb);
+    w.s = take(vb);
+    w.w = take(vb);
+    w.lam = take(vb);
+    w.g = take(vb);
+    w.t = take(vb);
+    w.part = (double*)take(sizeof(double) * 2 * EL_MAX_PARTS);
+    w.scal = (double*)take(sizeof(double) * (2 * S_SLOT + 8));
+    if (out) *out = w;
+    return off;
+}
+
+struct HostMirror {
+    double* host = nullptr;
+    double* dev = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+int host_mirror(HostMirror** out)
+{
+    thread_local HostMirror hm[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return pfapi::fail(PF_EDEVICE, "no usable current device for the CG readback");
+    HostMirror& m = hm[dev];
+    if (!m.host) {
+        double* h = nullptr;
+        hipError_t e = hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "pinned CG readback: %s", hipGetErrorString(e));
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&m.ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "CG readback event: %s", hipGetErrorString(e));
+        }
+        double* d = nullptr;
+        e = hipHostGetDevicePointer((void**)&d, h, 0);
+        if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "CG readback mapping: %s", hipGetErrorString(e));
+        m.host = h;
+        m.dev = d;
+    }
+    *out = &m;
+    return PF_OK;
+}
+
+// CG on K x = b (b already in W.r); x is overwritten.  Host-synchronous.
+template <typename T>
+int cg_solve(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit, pf_el_report* rep,
+             hipStream_t st)
+{
+    double lam, mu;
+    lame(p, &lam, &mu);
+    HostMirror* hm = nullptr;
+    if (int rc = host_mirror(&hm)) return rc;
+    const long long n = ndof(p);
+    const int sb = stream_blocks(n);
+    k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, x, nullptr);
+    k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, (T*)W.p, nullptr);
+    k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, (T*)W.s, nullptr);
+    k_el_cg_init<<<1, 64, 0, st>>>(W.scal, hm->dev, rtol * rtol, (double)maxit);
+    if (int rc = pfapi::check_launch("CG setup")) return rc;
+    const ApplyShape shp = apply_shape(g);
+    if (shp.blocks > EL_MAX_PARTS) return pfapi::fail(PF_EINVAL, "grid too large for the CG reduction");
+    const int ub = std::min(sb, 1024);
+    // enqueue batches of iterations; poll the previous batch while the next runs
+    int batch = 8, enq = 0, slot = 0;
+    bool pending = false;
+    double done = 0.0, its = 0.0, gam = 0.0, gam0 = 0.0;
+    for (;;) {
+        const int nb = std::min(batch, maxit + 1 - enq);
+        for (int i = 0; i < nb; ++i) {
+            const int it = enq + i;
+            double* sin = W.scal + S_SLOT * (it & 1);
+            double* sout = W.scal + S_SLOT * ((it + 1) & 1);
+            const CgArgs cg{W.part, sin};
+            launch_apply<T>(g, lam, mu, 1, (const T*)W.r, (T*)W.w, &cg, st);
+            k_el_cg_update<T><<<ub, EL_BLOCK, 0, st>>>(n, W.part, shp.blocks, sin, sout, hm->dev, x, (T*)W.r,
+                                                       (T*)W.p, (T*)W.s, (const T*)W.w);
+        }
+        enq += nb;
+        if (int rc = pfapi::check_launch("CG iteration")) return rc;
+        if (hipEventRecord(hm->ev[slot], st) != hipSuccess) return pfapi::check_launch("CG event");
+        if (pending) {
+            if (hipEventSynchronize(hm->ev[slot ^ 1]) != hipSuccess) return pfapi::check_launch("CG wait");
+            done = *(volatile double*)&hm->host[H_DONE];
+            if (done != 0.0) break;
+        }
+        pending = true;
+        slot ^= 1;
+        if (enq > maxit) {
+            if (hipEventSynchronize(hm->ev[slot ^ 1]) != hipSuccess) return pfapi::check_launch("CG wait");
+            break;
+        }
+        batch = std::min(batch * 2, 64);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return pfapi::check_launch("CG sync");
+    done = *(volatile double*)&hm->host[H_DONE];
+    its = *(volatile double*)&hm->host[H_ITS];
+    gam = *(volatile double*)&hm->host[H_GAMMA];
+    gam0 = *(volatile double*)&hm->host[H_GAMMA0];
+    if (rep) {
+        rep->iterations = (int32_t)its;
+        rep->converged = done == DONE_CONVERGED;
+        rep->status = (int32_t)done;
+        rep->reserved = 0;
+        rep->res_norm = std::sqrt(std::max(gam, 0.0));
+        rep->rhs_norm = std::sqrt(std::max(gam0, 0.0));
+    }
+    if (done == DONE_NONFINITE) return pfapi::fail(PF_ENONFINITE, "CG met a non-finite value");
+    if (done != DONE_CONVERGED)
+        return pfapi::fail(PF_ENOCONV, "CG stopped after %d iterations without reaching rtol (status %d)",
+                           (int)its, (int)done);
+    return PF_OK;
+}
+
+template <typename T>
+int solve_t(const pf_elastic* p, const void* b, void* u, double rtol, int maxit, pf_el_report* rep,
+            const Ws& W, hipStream_t st)
+{
+    const Grid g = grid_of(p);
+    double lam, mu;
+    lame(p, &lam, &mu);
+    const long long n = ndof(p);
+    if (b)
+        k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)b);
+    else
+        launch_rhs<T>(g, p->dim * lam + 2.0 * mu, p, (T*)W.r, st);
+    return cg_solve<T>(p, g, (T*)u, W, rtol, maxit, rep, st);
+}
+
+// Sensitivities of O = g . u with respect to (E, nu) at the equilibrium u:
+// adjoint K lam_a = g (K is symmetric), then with K = lam K_l + mu K_m and
+// f = (d lam + 2 mu) f1 (f1: the load for unit coefficient)
+//   dO/dlam = lam_a . (d f1 - K_l u),   dO/dmu = lam_a . (2 f1 - K_m u),
+// mapped to (E, nu) by the chain rule.
+template <typename T>
+int sensitivity_t(const pf_elastic* p, const void* gw, const void* u, double* out, double rtol, int maxit,
+                  pf_el_report* rep, const Ws& W, hipStream_t st)
+{
+    const Grid g = grid_of(p);
+    const long long n = ndof(p);
+    const int bl = (int)((g.N + EL_BLOCK - 1) / EL_BLOCK);
+    if (g.dim == 3)
+        k_el_weights<T, 3><<<bl, EL_BLOCK, 0, st>>>(g, (const T*)gw, (T*)W.g);
+    else
+        k_el_weights<T, 2><<<bl, EL_BLOCK, 0, st>>>(g, (const T*)gw, (T*)W.g);
+    k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)W.g);
+    if (int rc = pfapi::check_launch("adjoint set-up")) return rc;
+    if (int rc = cg_solve<T>(p, g, (T*)W.lam, W, rtol, maxit, rep, st)) return rc;
+    double* dots = W.scal + 2 * S_SLOT;  // 4 device doubles after the CG state
+    double* part = W.part;
+    launch_dot<T>(g, (const T*)W.g, (const T*)u, part, dots + 0, st);
+    launch_rhs<T>(g, 1.0, p, (T*)W.t, st);
+    launch_dot<T>(g, (const T*)W.lam, (const T*)W.t, part, dots + 1, st);
+    launch_apply<T>(g, 1.0, 0.0, 0, (const T*)u, (T*)W.t, nullptr, st);
+    launch_dot<T>(g, (const T*)W.lam, (const T*)W.t, part, dots + 2, st);
+    launch_apply<T>(g, 0.0, 1.0, 0, (const T*)u, (T*)W.t, nullptr, st);
+    launch_dot<T>(g, (const T*)W.lam, (const T*)W.t, part, dots + 3, st);
+    if (int rc = pfapi::check_launch("sensitivity")) return rc;
+    double h[4];
+    if (hipMemcpyAsync(h, dots, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return pfapi::check_launch("sensitivity readback");
+    const double d = p->dim, E = p->E, nu = p->nu;
+    const double dl = d * h[1] - h[2], dm = 2.0 * h[1] - h[3];
+    const double D = (1.0 + nu) * (1.0 - 2.0 * nu);
+    out[0] = h[0];
+    out[1] = dl * (nu / D) + dm * (1.0 / (2.0 * (1.0 + nu)));
+    out[2] = dl * (E * (1.0 + 2.0 * nu * nu) / (D * D)) + dm * (-E / (2.0 * (1.0 + nu) * (1.0 + nu)));
+    return PF_OK;
+}
+
+}  // namespace pfel
+
+using namespace pfel;
+using pfapi::fail;
+
+extern "C" {
+
+int pf_el_workspace_size(const pf_elastic* p, size_t* bytes)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+    *bytes = ws_bytes(p, nullptr, nullptr);
+    return PF_OK;
+}
+
+int pf_el_apply(const pf_elastic* p, const void* u, void* y, void* stream)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (int rc = check_vec(u, p, "u")) return rc;
+    if (int rc = check_vec(y, p, "y")) return rc;
+    if (u == y) return fail(PF_EINVAL, "u and y must not alias");
+    const Grid g = grid_of(p);
+    double lam, mu;
+    lame(p, &lam, &mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        launch_apply<float>(g, lam, mu, 1, (const float*)u, (float*)y, nullptr, st);
+    else
+        launch_apply<double>(g, lam, mu, 1, (const double*)u, (double*)y, nullptr, st);
+    return pfapi::check_launch("pf_el_apply");
+}
+
+int pf_el_rhs(const pf_elastic* p, void* f, void* stream)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (int rc = check_vec(f, p, "f")) return rc;
+    const Grid g = grid_of(p);
+    double lam, mu;
+    lame(p, &lam, &mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        launch_rhs<float>(g, p->dim * lam + 2.0 * mu, p, (float*)f, st);
+    else
+        launch_rhs<double>(g, p->dim * lam + 2.0 * mu, p, (double*)f, st);
+    return pfapi::check_launch("pf_el_rhs");
+}
+
+int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit, pf_el_report* rep,
+                void* ws, void* stream)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (b)
+        if (int rc = check_vec(b, p, "b")) return rc;
+    if (int rc = check_vec(u, p, "u")) return rc;
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
+    if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
+    if (b == u) return fail(PF_EINVAL, "b and u must not alias");
+    Ws W;
+    ws_bytes(p, &W, ws);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dtype == PF_F32) return solve_t<float>(p, b, u, rtol, maxit, rep, W, st);
+    return solve_t<double>(p, b, u, rtol, maxit, rep, W, st);
+}
+
+int pf_el_objective(const pf_elastic* p, const void* gw, const void* u, double* out, void* ws, void* stream)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (gw)
+        if (int rc = check_vec(gw, p, "g")) return rc;
+    if (int rc = check_vec(u, p, "u")) return rc;
+    if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+    Ws W;
+    ws_bytes(p, &W, ws);
+    const Grid g = grid_of(p);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dtype == PF_F32)
+        launch_dot<float>(g, (const float*)gw, (const float*)u, W.part, out, st);
+    else
+        launch_dot<double>(g, (const double*)gw, (const double*)u, W.part, out, st);
+    return pfapi::check_launch("pf_el_objective");
+}
+
+int pf_el_sensitivity(const pf_elastic* p, const void* gw, const void* u, double* out, double rtol, int32_t maxit,
+                      pf_el_report* rep, void* ws, void* stream)
+{
+    if (int rc = pfel::validate(p)) return rc;
+    if (gw)
+        if (int rc = check_vec(gw, p, "g")) return rc;
+    if (int rc = check_vec(u, p, "u")) return rc;
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
+    if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
+    Ws W;
+    ws_bytes(p, &W, ws);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dtype == PF_F32) return sensitivity_t<float>(p, gw, u, out, rtol, maxit, rep, W, st);
+    return sensitivity_t<double>(p, gw, u, out, rtol, maxit, rep, W, st);
+}
+
+}  // extern "C"

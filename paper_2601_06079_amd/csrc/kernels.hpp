@@ -67,6 +67,7 @@ void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, dou
                 int acc = 0);
 // z-planes per block of launch_jvp3d set by pf_tune_set (0: automatic)
 int tune_jvp3d_planes();
+int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = automatic)
 // 3-D Jv (acc = 0) by element-wise sum factorisation through z-marching LDS tiles
 template <typename T>
 void launch_jvp3d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,

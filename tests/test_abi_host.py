@@ -99,3 +99,44 @@ def test_coupled_model_entry_points(L):
                     None) == A.PF_EUNSUPPORTED
     q = _prob(model=A.COUPLED, fe=9)  # the coupled model ignores fe
     assert L.pf_workspace_size(ct.byref(q), A.OP_RESIDUAL, ct.byref(nb)) == A.PF_OK
+
+
+def _el(**kw):
+    from paper_2601_06079_amd import elastic as EL
+    d = dict(dim=3, dtype=A.F32, n=(9, 8, 7), h=1.0, E=22.5, nu=0.3, m=0.01, a=3.0, l=0.5)
+    d.update(kw)
+    return EL.pf_elastic(d["dim"], d["dtype"], (ct.c_int64 * 3)(*d["n"]), d["h"], d["E"], d["nu"],
+                         d["m"], d["a"], d["l"])
+
+
+def test_elastic_validation_before_launch(L):
+    """The elasticity entry points (Eshelby inclusion) reject malformed problems
+    and arguments before anything is enqueued."""
+    from paper_2601_06079_amd import elastic as EL
+    EL._lib()
+    nb = ct.c_size_t(0)
+    p = _el()
+    assert L.pf_el_workspace_size(ct.byref(p), ct.byref(nb)) == A.PF_OK
+    vec = 9 * 8 * 7 * 3 * 4
+    assert nb.value >= 7 * vec
+    for bad in (dict(dim=1), dict(dtype=4), dict(n=(1, 8, 7)), dict(h=0.0), dict(E=-1.0),
+                dict(nu=0.5), dict(nu=-1.0), dict(m=float("nan")), dict(l=float("inf"))):
+        assert L.pf_el_workspace_size(ct.byref(_el(**bad)), ct.byref(nb)) == A.PF_EINVAL, bad
+    fake, fake2 = ct.c_void_p(0x1000), ct.c_void_p(0x2000)
+    assert L.pf_el_apply(ct.byref(p), fake, fake, None) == A.PF_EINVAL  # aliasing
+    assert L.pf_el_apply(ct.byref(p), ct.c_void_p(0x1004), fake2, None) == A.PF_EINVAL  # alignment
+    assert L.pf_el_apply(ct.byref(p), None, fake2, None) == A.PF_EINVAL
+    rep = EL.pf_el_report()
+    assert L.pf_el_solve(ct.byref(p), None, fake, 0.0, 10, ct.byref(rep), fake2, None) == A.PF_EINVAL
+    assert L.pf_el_solve(ct.byref(p), None, fake, 1e-6, 0, ct.byref(rep), fake2, None) == A.PF_EINVAL
+    assert L.pf_el_solve(ct.byref(p), None, fake, 1e-6, 10, ct.byref(rep), ct.c_void_p(0x2010),
+                         None) == A.PF_EINVAL  # workspace alignment
+    out = (ct.c_double * 3)()
+    assert L.pf_el_sensitivity(ct.byref(p), None, fake, None, 1e-6, 10, None, fake2, None) == A.PF_EINVAL
+    assert L.pf_el_objective(ct.byref(p), None, fake, None, fake2, None) == A.PF_EINVAL
+    assert L.pf_el_sensitivity(ct.byref(_el(E=0.0)), None, fake, out, 1e-6, 10, None, fake2,
+                               None) == A.PF_EINVAL
+    v = ct.c_int(-1)
+    assert L.pf_tune_set(EL.TUNE_EL_PLANES, 12) == A.PF_OK
+    assert L.pf_tune_get(EL.TUNE_EL_PLANES, ct.byref(v)) == A.PF_OK and v.value == 12
+    assert L.pf_tune_set(EL.TUNE_EL_PLANES, 0) == A.PF_OK
