@@ -39,6 +39,9 @@ FLOPS_PER_NODE_STEP_CH = 69
 # interpolation of c and eta 30, the two sources at 4 points 144 (f_a 8, f_a' 6, f_b 4,
 # f_b' 2, h 7, h' 4, combinations 5), scatters 36, mu/eta'/c' updates 19
 FLOPS_PER_NODE_STEP_COUPLED = 229  # sum-factorised Q1 split step, FMA = 2 flops (see DESIGN)
+# elasticity operator per node (FMA = 2): 3-D row sums 60, z-combinations 105, x-operator
+# sums 27, x-assembly 72; 2-D: z-combinations 40, sums 8, x-assembly 48
+FLOPS_PER_NODE_ELASTIC = {3: 264, 2: 96}
 METRIC = "DOF-steps/sec + %HBM peak (explicit CH, 4.19M DOF); adjoint & surrogate speedup"
 
 
@@ -58,6 +61,8 @@ def parse():
     ap.add_argument("--implicit", type=int, default=0, metavar="STEPS",
                     help="only time STEPS backward-Euler Newton steps of the 128^3 Cahn-Hilliard "
                          "workload (4.19M DOF) and print their record")
+    ap.add_argument("--eshelby", action="store_true",
+                    help="only time the Eshelby-inclusion solves (129^3 and 1025^2) and print their records")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the batched adjoint record (64 ragged Allen-Cahn samples)")
     ap.add_argument("--surrogate-gain", type=int, default=0, metavar="ITERS",
@@ -339,6 +344,73 @@ def coupled_implicit_record(stream, n=512, steps=20, dt=0.01):
             "gmres_its_per_newton": float(np.sum(gmres) / max(np.sum(newton), 1))}
 
 
+def eshelby_record(stream, n=(129, 129, 129), rtol=1e-6, reps=50):
+    """The Eshelby-inclusion benchmark (Eqs. 3-4, Eq. III.1): [0, 100]^dim with the
+    given nodes per axis, E = 22.5, nu = 0.3, dilatational misfit m = 0.01 inside
+    radius a = 20 (interface l = 0.5), symmetry planes through the origin and
+    traction-free outer faces; FP32 fields, CG (FP64 scalars) to rtol.  One solve,
+    its volume change and the adjoint (E, nu) sensitivities, plus the operator
+    kernel alone (reps launches replayed from a HIP graph, timed with events on the
+    stream)."""
+    import torch
+
+    from paper_2601_06079_amd import elastic as EL
+    dim = len(n)
+    p = EL.ElasticProblem(n=tuple(n), h=100.0 / (n[0] - 1), dtype=torch.float32)
+    ws = EL.workspace(p)
+    u = torch.empty(p.ndof, dtype=torch.float32, device="cuda")
+    EL.el_solve(p, out=u, rtol=rtol, ws=ws)  # warm-up (not timed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep = EL.el_solve(p, out=u, rtol=rtol, ws=ws)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    vol = float(EL.el_objective(p, u, ws=ws).item())
+    t0 = time.perf_counter()
+    (O, dE, dnu), arep = EL.el_sensitivity(p, u, rtol=rtol, ws=ws)
+    sens_s = time.perf_counter() - t0
+    # the operator alone: `reps` launches captured in one HIP graph and replayed
+    # (no host launch overhead between them), timed with events on the stream
+    v = torch.randn(p.ndof, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(v)
+    for _ in range(5):
+        EL.el_apply(p, v, out=y)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(reps):
+            EL.el_apply(p, v, out=y)
+    graph.replay()
+    torch.cuda.synchronize()
+    ms = _time_ms(graph.replay, stream)
+    apply_ms = ms / reps
+    del graph
+    N = p.nnodes
+    tflops = FLOPS_PER_NODE_ELASTIC[dim] * N / (apply_ms * 1e-3) / 1e12
+    apply_gbs = 2 * 4 * p.ndof / (apply_ms * 1e-3) / 1e9
+    it_ms = 1e3 * solve_s / max(rep.iterations, 1)
+    upd_ms = max(it_ms - apply_ms, 1e-6)
+    upd_gbs = 36 * p.ndof / (upd_ms * 1e-3) / 1e9
+    del ws, u, v, y
+    torch.cuda.empty_cache()
+    shape = "x".join(str(k) for k in n)
+    return {"workload": f"Eshelby inclusion {shape} nodes on [0,100]^{dim}"
+                        f"{' (plane strain)' if dim == 2 else ''}, E=22.5, nu=0.3, m=0.01, a=20, l=0.5, "
+                        f"symmetry + traction-free, FP32 fields, CG to rtol {rtol:g}",
+            "dof": p.ndof, "solve_ms": 1e3 * solve_s, "cg_iterations": rep.iterations,
+            "converged": bool(rep.converged), "ms_per_iteration": it_ms,
+            "volume_change": vol, "sensitivity": {"dV_dE": dE, "dV_dnu": dnu, "ms": 1e3 * sens_s,
+                                                  "adjoint_iterations": arep.iterations},
+            "operator": {"kernel": f"k_el_apply<float, {dim}>", "us_per_launch": 1e3 * apply_ms,
+                         "bound": "alu", "flops_per_node": FLOPS_PER_NODE_ELASTIC[dim],
+                         "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / VALU_PEAK_TFLOPS, "hbm_gbs": apply_gbs},
+            "update": {"kernel": "k_el_cg_update<float> (per iteration minus the operator; "
+                                 "includes launch gaps)", "ms": upd_ms, "bound": "hbm",
+                       "bytes_per_dof": 36, "achieved": upd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": upd_gbs / HBM_PEAK_GBS}}
+
+
 def adjoint_record(stream, count=64, nsteps=2000, every=100):
     """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
     2000 FP32 steps, dt = 0.05): forward plus the hand-written adjoint, against the
@@ -499,9 +571,12 @@ def implicit_record(steps, stream):
 
 def main():
     args = parse()
-    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled:
+    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby:
         import torch
         stream = torch.cuda.current_stream()
+        if args.eshelby:
+            print(json.dumps(eshelby_record(stream)), flush=True)
+            print(json.dumps(eshelby_record(stream, n=(1025, 1025))), flush=True)
         if args.adjoint:
             print(json.dumps(adjoint_record(stream)), flush=True)
         if args.implicit:
@@ -630,6 +705,7 @@ def main():
         from paper_2601_06079_amd import _abi as A
         out["implicit_ac2048_2d"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5)
         out["implicit_ch512_2d"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5)
+        out["eshelby_129"] = eshelby_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

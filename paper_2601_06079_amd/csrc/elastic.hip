@@ -54,6 +54,7 @@
 #include "api_internal.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "stream2d.hpp"
 
 namespace pfel {
 
@@ -131,16 +132,32 @@ __device__ __forceinline__ Fac<T> fac(bool lo, bool hi)
     return f;
 }
 
+// lane i receives lane i-1 (left) / i+1 (right); lanes without a source get 0.
+// bound_ctrl zeroing leaves no old value to initialise, so the move can fold into
+// the VOP2 FMA that consumes it.
+__device__ __forceinline__ float nb_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), pfk::DPP_WAVE_SHR1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float nb_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), pfk::DPP_WAVE_SHL1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double nb_left(double v) { return pfk::from_left(v); }
+__device__ __forceinline__ double nb_right(double v) { return pfk::from_right(v); }
+
 template <typename T>
 __device__ __forceinline__ T tap3(const T w[3], T a, T b, T c)
 {
     return pfk::fmaT(w[0], a, pfk::fmaT(w[1], b, w[2] * c));
 }
 
-// row sums of one component on one plane: [M, A, R, C] along y, and the raw value
+// one plane of a column as the operator needs it: the y-operator row sums
+// [M, A, R, C] of each component and the raw (unmasked) own values
 template <typename T>
-struct RS {
-    T s[4];
+struct Plane {
+    T s[3][4];
+    T raw[3];
 };
 
 // wave-interleaved block -> logical block map: the hardware hands consecutive
@@ -187,92 +204,109 @@ struct CgArgs {
 template <typename T, int D, bool CG>
 __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T scale, int ident,
                                                       const T* __restrict__ u, T* __restrict__ y,
-                                                      int tz, int nseg, int nwaves, CgArgs cg)
+                                                      int tz, int nseg, int nitems, CgArgs cg)
 {
     __shared__ double sh[2 * EL_WAVES];
     if (CG && cg.state[S_DONE] != 0.0) return;
     const int lane = threadIdx.x % WAVE;
-    const int wv = xcd_block(blockIdx.x, gridDim.x) * EL_WAVES + threadIdx.x / WAVE;
+    // wave-uniform work item (kept in scalar registers: plane loop, z-operators and
+    // plane base addresses are then scalar)
+    const int wv = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * EL_WAVES +
+                                                  (int)(threadIdx.x / WAVE));
     double pg = 0.0, pd = 0.0;
-    if (wv < nwaves) {
-        const int seg = wv % nseg, chunk = wv / nseg;
+    // work items (segment, chunk of planes), grid-strided over at most the
+    // resident waves
+    for (int item = wv; item < nitems; item += (int)gridDim.x * EL_WAVES) {
+        const int seg = item % nseg, chunk = item / nseg;
         const long long q0 = (long long)seg * EL_OUT - 1 + lane;
         const bool out_lane = lane >= 1 && lane <= EL_OUT && q0 >= 0 && q0 < g.P;
-        const long long q = q0 < 0 ? 0 : (q0 >= g.P ? g.P - 1 : q0);
-        const int x = (int)(q % g.nx), yr = (int)(q / g.nx);
+        const int q = (int)(q0 < 0 ? 0 : (q0 >= g.P ? g.P - 1 : q0));
+        const int x = q % g.nx, yr = q / g.nx;
         const Fac<T> fx = fac<T>(x > 0, x < g.nx - 1);
         const Fac<T> fy = fac<T>(yr > 0, yr < g.ny - 1);
-        const long long qm = (D == 3 && yr > 0) ? q - g.nx : q;
-        const long long qp = (D == 3 && yr < g.ny - 1) ? q + g.nx : q;
+        // byte offsets inside a plane (planes hold < 2^29 nodes)
+        const unsigned ob = (unsigned)q * sizeof(T);
+        const unsigned obm = (unsigned)((D == 3 && yr > 0) ? q - g.nx : q) * sizeof(T);
+        const unsigned obp = (unsigned)((D == 3 && yr < g.ny - 1) ? q + g.nx : q) * sizeof(T);
         const long long N = g.N, P = g.P;
-        const T* ux = u + (long long)g.coff[0] * N;
-        const T* uy = D == 3 ? u + (long long)g.coff[1] * N : u;
-        const T* uz = u + (long long)g.coff[2] * N;
-        const T zx = x == 0 ? T(0) : T(1);             // u_x fixed on x = 0
-        const T zym = (yr - 1 == 0) ? T(0) : T(1);      // u_y fixed on y = 0 (row y-1)
-        const T zy0 = (yr == 0) ? T(0) : T(1);          // (row y)
-
+        const char* ux = reinterpret_cast<const char*>(u + (long long)g.coff[0] * N);
+        const char* uy = reinterpret_cast<const char*>(D == 3 ? u + (long long)g.coff[1] * N : u);
+        const char* uz = reinterpret_cast<const char*>(u + (long long)g.coff[2] * N);
+        const T zx = x == 0 ? T(0) : T(1);         // u_x fixed on x = 0
+        const T zym = (yr - 1 == 0) ? T(0) : T(1);  // u_y fixed on y = 0 (row y-1)
+        const T zy0 = (yr == 0) ? T(0) : T(1);      // (row y)
         const T lm2 = lam + T(2) * mu;
-        // three planes of row sums (k-1, k, k+1) and raw values of plane k, k+1
-        RS<T> rx[3], ry[3], rz[3];
-        T raw[2][3];
-        auto load = [&](int kz, RS<T>& ox, RS<T>& oy, RS<T>& oz, T* rv) {
-            if (kz < 0 || kz >= g.nz) {
-                for (int i = 0; i < 4; ++i) ox.s[i] = oy.s[i] = oz.s[i] = T(0);
-                rv[0] = rv[1] = rv[2] = T(0);
-                return;
-            }
-            const long long o = (long long)kz * P;
-            const T zz = kz == 0 ? T(0) : T(1);  // u_z fixed on z = 0
-            const T x0 = ux[o + q], z0 = uz[o + q];
-            rv[0] = x0;
-            rv[2] = z0;
+        constexpr int NL = D == 3 ? 9 : 2;
+        // loads of one plane through a buffer descriptor of that plane (scalar
+        // set-up; the lane offsets are the only per-lane address state).  A plane
+        // index beyond the grid is clamped to the edge plane: its values only meet
+        // z-operator weights that are zero there (kz is wave-uniform).
+        const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(T));
+        auto issue = [&](int kz, T* L) {
+            kz = kz < 0 ? 0 : (kz >= g.nz ? g.nz - 1 : kz);
+            const long long pb = (long long)kz * P * (long long)sizeof(T);
+            const auto rx = pfk::make_rsrc(ux + pb, plane_bytes);
+            const auto rz = pfk::make_rsrc(uz + pb, plane_bytes);
             if (D == 3) {
-                const T xm = ux[o + qm], xp = ux[o + qp];
-                const T y0 = uy[o + q], ym = uy[o + qm], yp = uy[o + qp];
-                const T zm = uz[o + qm], zp = uz[o + qp];
-                rv[1] = y0;
-                const T a0 = xm * zx, a1 = x0 * zx, a2 = xp * zx;
-                const T b0 = ym * zym, b1 = y0 * zy0, b2 = yp;
-                const T c0 = zm * zz, c1 = z0 * zz, c2 = zp * zz;
-                ox.s[0] = tap3(fy.m, a0, a1, a2);
-                ox.s[1] = tap3(fy.a, a0, a1, a2);
-                ox.s[2] = tap3(fy.r, a0, a1, a2);
-                ox.s[3] = tap3(fy.c, a0, a1, a2);
-                oy.s[0] = tap3(fy.m, b0, b1, b2);
-                oy.s[1] = tap3(fy.a, b0, b1, b2);
-                oy.s[2] = tap3(fy.r, b0, b1, b2);
-                oy.s[3] = tap3(fy.c, b0, b1, b2);
-                oz.s[0] = tap3(fy.m, c0, c1, c2);
-                oz.s[1] = tap3(fy.a, c0, c1, c2);
-                oz.s[2] = tap3(fy.r, c0, c1, c2);
-                oz.s[3] = tap3(fy.c, c0, c1, c2);
+                const auto ry = pfk::make_rsrc(uy + pb, plane_bytes);
+                L[0] = pfk::bload<T>(rx, (int)obm, 0);
+                L[1] = pfk::bload<T>(rx, (int)ob, 0);
+                L[2] = pfk::bload<T>(rx, (int)obp, 0);
+                L[3] = pfk::bload<T>(ry, (int)obm, 0);
+                L[4] = pfk::bload<T>(ry, (int)ob, 0);
+                L[5] = pfk::bload<T>(ry, (int)obp, 0);
+                L[6] = pfk::bload<T>(rz, (int)obm, 0);
+                L[7] = pfk::bload<T>(rz, (int)ob, 0);
+                L[8] = pfk::bload<T>(rz, (int)obp, 0);
             } else {
-                rv[1] = T(0);
-                ox.s[0] = x0 * zx;
-                oz.s[0] = z0 * zz;
-                ox.s[1] = ox.s[2] = ox.s[3] = T(0);
-                oz.s[1] = oz.s[2] = oz.s[3] = T(0);
-                for (int i = 0; i < 4; ++i) oy.s[i] = T(0);
+                L[0] = pfk::bload<T>(rx, (int)ob, 0);
+                L[1] = pfk::bload<T>(rz, (int)ob, 0);
             }
         };
-        const int k0 = chunk * tz, k1 = min(g.nz, k0 + tz);
-        load(k0 - 1, rx[0], ry[0], rz[0], raw[0]);
-        load(k0, rx[1], ry[1], rz[1], raw[0]);
-        for (int k = k0; k < k1; ++k) {
-            load(k + 1, rx[2], ry[2], rz[2], raw[1]);
+        // row sums of a loaded plane; ZMASK: the plane may be z = 0 (u_z fixed there)
+        auto rows = [&](const T* L, int kz, Plane<T>& o, bool zmask) {
+            if (D == 3) {
+                o.raw[0] = L[1];
+                o.raw[1] = L[4];
+                o.raw[2] = L[7];
+                const T zz = (zmask && kz == 0) ? T(0) : T(1);
+                const T a0 = L[0] * zx, a1 = L[1] * zx, a2 = L[2] * zx;
+                const T b0 = L[3] * zym, b1 = L[4] * zy0, b2 = L[5];
+                T c0 = L[6], c1 = L[7], c2 = L[8];
+                if (zmask) {
+                    c0 *= zz;
+                    c1 *= zz;
+                    c2 *= zz;
+                }
+                o.s[0][0] = tap3(fy.m, a0, a1, a2);
+                o.s[0][1] = tap3(fy.a, a0, a1, a2);
+                o.s[0][2] = tap3(fy.r, a0, a1, a2);
+                o.s[0][3] = tap3(fy.c, a0, a1, a2);
+                o.s[1][0] = tap3(fy.m, b0, b1, b2);
+                o.s[1][1] = tap3(fy.a, b0, b1, b2);
+                o.s[1][2] = tap3(fy.r, b0, b1, b2);
+                o.s[1][3] = tap3(fy.c, b0, b1, b2);
+                o.s[2][0] = tap3(fy.m, c0, c1, c2);
+                o.s[2][1] = tap3(fy.a, c0, c1, c2);
+                o.s[2][2] = tap3(fy.r, c0, c1, c2);
+                o.s[2][3] = tap3(fy.c, c0, c1, c2);
+            } else {
+                o.raw[0] = L[0];
+                o.raw[1] = T(0);
+                o.raw[2] = L[1];
+                o.s[0][0] = L[0] * zx;
+                o.s[2][0] = (zmask && kz == 0) ? T(0) : L[1];
+            }
+        };
+        // outputs of plane k from the row sums of planes k-1, k, k+1
+        auto emit = [&](int k, const Plane<T>& A_, const Plane<T>& B_, const Plane<T>& C_) {
             const Fac<T> fz = fac<T>(k > 0, k < g.nz - 1);
-            // Q_c^{FG}: y-operator F (row sums), z-operator G over the three planes
-            auto Q = [&](const RS<T>* r, int F, const T* G) {
-                return tap3(G, r[0].s[F], r[1].s[F], r[2].s[F]);
-            };
             enum { M = 0, A = 1, R = 2, C = 3 };
+            auto Q = [&](int c, int F, const T* G) { return tap3(G, A_.s[c][F], B_.s[c][F], C_.s[c][F]); };
             T SA0, SM0, SR0, SC0, SA2, SM2, SR2, SC2, SA1 = T(0), SM1 = T(0), SR1 = T(0), SC1 = T(0);
             {
-                const T q0MM = Q(rx, M, fz.m), q0MA = Q(rx, M, fz.a), q0MR = Q(rx, M, fz.r),
-                        q0MC = Q(rx, M, fz.c);
-                const T q2MM = Q(rz, M, fz.m), q2MA = Q(rz, M, fz.a), q2MR = Q(rz, M, fz.r),
-                        q2MC = Q(rz, M, fz.c);
+                const T q0MM = Q(0, M, fz.m), q0MA = Q(0, M, fz.a), q0MR = Q(0, M, fz.r), q0MC = Q(0, M, fz.c);
+                const T q2MM = Q(2, M, fz.m), q2MA = Q(2, M, fz.a), q2MR = Q(2, M, fz.r), q2MC = Q(2, M, fz.c);
                 SA0 = lm2 * q0MM;
                 SM0 = mu * q0MA;
                 SR0 = lam * q2MC;
@@ -282,31 +316,31 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T sc
                 SC2 = lam * q0MR;
                 SR2 = mu * q0MC;
                 if (D == 3) {
-                    const T q0AM = Q(rx, A, fz.m), q0RM = Q(rx, R, fz.m), q0CM = Q(rx, C, fz.m);
-                    const T q1MM = Q(ry, M, fz.m), q1AM = Q(ry, A, fz.m), q1MA = Q(ry, M, fz.a),
-                            q1CM = Q(ry, C, fz.m), q1RM = Q(ry, R, fz.m), q1CR = Q(ry, C, fz.r),
-                            q1RC = Q(ry, R, fz.c);
-                    const T q2AM = Q(rz, A, fz.m), q2RC = Q(rz, R, fz.c), q2CR = Q(rz, C, fz.r);
+                    const T q0AM = Q(0, A, fz.m), q0RM = Q(0, R, fz.m), q0CM = Q(0, C, fz.m);
+                    const T q1MM = Q(1, M, fz.m), q1AM = Q(1, A, fz.m), q1MA = Q(1, M, fz.a),
+                            q1CM = Q(1, C, fz.m), q1RM = Q(1, R, fz.m), q1CR = Q(1, C, fz.r),
+                            q1RC = Q(1, R, fz.c);
+                    const T q2AM = Q(2, A, fz.m), q2RC = Q(2, R, fz.c), q2CR = Q(2, C, fz.r);
                     SM0 = mu * (q0AM + q0MA);
                     SR0 = lam * (q1CM + q2MC);
                     SC0 = mu * (q1RM + q2MR);
-                    SM1 = lm2 * q1AM + mu * q1MA + lam * q2RC + mu * q2CR;
+                    SM1 = pfk::fmaT(lm2, q1AM, pfk::fmaT(mu, q1MA, pfk::fmaT(lam, q2RC, mu * q2CR)));
                     SA1 = mu * q1MM;
                     SC1 = lam * q0RM;
                     SR1 = mu * q0CM;
-                    SM2 = lm2 * q2MA + mu * q2AM + lam * q1CR + mu * q1RC;
+                    SM2 = pfk::fmaT(lm2, q2MA, pfk::fmaT(mu, q2AM, pfk::fmaT(lam, q1CR, mu * q1RC)));
                 }
             }
             auto xsum = [&](T sa, T sm, T sr, T sc) {
                 T acc = pfk::fmaT(fx.a[1], sa, pfk::fmaT(fx.m[1], sm, pfk::fmaT(fx.r[1], sr, fx.c[1] * sc)));
-                acc = pfk::fmaT(fx.a[0], pfk::from_left(sa), acc);
-                acc = pfk::fmaT(fx.m[0], pfk::from_left(sm), acc);
-                acc = pfk::fmaT(fx.r[0], pfk::from_left(sr), acc);
-                acc = pfk::fmaT(fx.c[0], pfk::from_left(sc), acc);
-                acc = pfk::fmaT(fx.a[2], pfk::from_right(sa), acc);
-                acc = pfk::fmaT(fx.m[2], pfk::from_right(sm), acc);
-                acc = pfk::fmaT(fx.r[2], pfk::from_right(sr), acc);
-                acc = pfk::fmaT(fx.c[2], pfk::from_right(sc), acc);
+                acc = pfk::fmaT(nb_left(sa), fx.a[0], acc);
+                acc = pfk::fmaT(nb_left(sm), fx.m[0], acc);
+                acc = pfk::fmaT(nb_left(sr), fx.r[0], acc);
+                acc = pfk::fmaT(nb_left(sc), fx.c[0], acc);
+                acc = pfk::fmaT(nb_right(sa), fx.a[2], acc);
+                acc = pfk::fmaT(nb_right(sm), fx.m[2], acc);
+                acc = pfk::fmaT(nb_right(sr), fx.r[2], acc);
+                acc = pfk::fmaT(nb_right(sc), fx.c[2], acc);
                 return acc * scale;
             };
             const T w0 = xsum(SA0, SM0, SR0, SC0);
@@ -315,7 +349,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T sc
             if (D == 3) w1 = xsum(SA1, SM1, SR1, SC1);
             if (out_lane) {
                 const long long o = (long long)k * P + q;
-                const T r0 = raw[0][0], r1 = raw[0][1], r2 = raw[0][2];
+                const T r0 = B_.raw[0], r1 = B_.raw[1], r2 = B_.raw[2];
                 const T y0 = x == 0 ? (ident ? r0 : T(0)) : w0;
                 const T y2 = k == 0 ? (ident ? r2 : T(0)) : w2;
                 y[(long long)g.coff[0] * N + o] = y0;
@@ -330,15 +364,29 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T sc
                     pd += (double)y0 * r0 + (double)y2 * r2 + (D == 3 ? (double)y1 * r1 : 0.0);
                 }
             }
-            rx[0] = rx[1];
-            rx[1] = rx[2];
-            ry[0] = ry[1];
-            ry[1] = ry[2];
-            rz[0] = rz[1];
-            rz[1] = rz[2];
-            raw[0][0] = raw[1][0];
-            raw[0][1] = raw[1][1];
-            raw[0][2] = raw[1][2];
+        };
+        const int k0 = chunk * tz, k1 = min(g.nz, k0 + tz);
+        Plane<T> pA, pB, pC;
+        T L[NL];
+        issue(k0 - 1, L);
+        rows(L, k0 - 1, pA, true);
+        issue(k0, L);
+        rows(L, k0, pB, true);
+        issue(k0 + 1, L);
+        // three-way unrolled plane loop: the ring roles rotate statically (no moves);
+        // the loads of the plane after next are in flight while a plane is emitted
+        for (int k = k0; k < k1; k += 3) {
+            rows(L, k + 1, pC, false);
+            issue(k + 2, L);
+            emit(k, pA, pB, pC);
+            if (k + 1 >= k1) break;
+            rows(L, k + 2, pA, false);
+            issue(k + 3, L);
+            emit(k + 1, pB, pC, pA);
+            if (k + 2 >= k1) break;
+            rows(L, k + 3, pB, false);
+            issue(k + 4, L);
+            emit(k + 2, pC, pA, pB);
         }
     }
     if (!CG) return;
@@ -596,47 +644,85 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_weights(Grid g, const T* __rest
 // host side
 
 struct ApplyShape {
-    int tz, nseg, nwaves, blocks;
+    int tz, nseg, nwaves, blocks;  // nwaves: work items (segment, chunk)
 };
 
-ApplyShape apply_shape(const Grid& g)
+// Resident waves of a kernel (its occupancy times the CU count), queried once.
+template <typename K>
+int resident_waves(K kernel)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, EL_BLOCK, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 4096;
+    }
+    return std::max(1, per_cu) * std::max(1, cus) * EL_WAVES;
+}
+
+// Planes per work item: each item pays two warm-up planes and the grid holds at
+// most the resident waves, which loop over the items; pick the chunk length that
+// minimises (items per wave) x (planes + 2) (measured on MI355X: a grid just over
+// one round of resident waves runs ~1.3x slower than one just under it).
+ApplyShape apply_shape(const Grid& g, int slots)
 {
     ApplyShape s{};
     s.nseg = (int)((g.P + EL_OUT - 1) / EL_OUT);
-    // about 4096 waves (four per SIMD), chunks of 4..64 planes
-    long long want = ((long long)g.nz * s.nseg + 4095) / 4096;
-    int tz = (int)std::min<long long>(64, std::max<long long>(4, want));
+    int tz = 1;
+    long long best = -1;
+    for (int t = 2; t <= 64; ++t) {
+        const long long items = (long long)s.nseg * ((g.nz + t - 1) / t);
+        const long long cost = ((items + slots - 1) / slots) * (std::min(t, g.nz) + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            tz = t;
+        }
+    }
     if (pfk::tune_el_planes() > 0) tz = pfk::tune_el_planes();
     tz = std::min(tz, g.nz);
+    while ((long long)s.nseg * ((g.nz + tz - 1) / tz) > (1ll << 30)) ++tz;  // item index fits an int
     s.tz = tz;
-    const int nchunk = (g.nz + tz - 1) / tz;
-    s.nwaves = s.nseg * nchunk;
-    s.blocks = (s.nwaves + EL_WAVES - 1) / EL_WAVES;
+    const long long items = (long long)s.nseg * ((g.nz + tz - 1) / tz);
+    s.nwaves = (int)items;
+    const long long waves = std::min<long long>(items, slots);
+    s.blocks = (int)((waves + EL_WAVES - 1) / EL_WAVES);
     return s;
+}
+
+template <typename T, int D, bool CG>
+ApplyShape apply_shape_for(const Grid& g)
+{
+    static const int slots = resident_waves(k_el_apply<T, D, CG>);
+    return apply_shape(g, slots);
 }
 
 template <typename T>
 void launch_apply(const Grid& g, double lam, double mu, int ident, const T* u, T* y, const CgArgs* cg,
                   hipStream_t st)
 {
-    const ApplyShape s = apply_shape(g);
     const T scale = (T)(g.dim == 3 ? g.h : 1.0);
     CgArgs a = cg ? *cg : CgArgs{nullptr, nullptr};
+    auto go = [&](auto kernel, const ApplyShape& s) {
+        kernel<<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz, s.nseg, s.nwaves, a);
+    };
     if (g.dim == 3) {
         if (cg)
-            k_el_apply<T, 3, true><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
-                                                                  s.nseg, s.nwaves, a);
+            go(k_el_apply<T, 3, true>, apply_shape_for<T, 3, true>(g));
         else
-            k_el_apply<T, 3, false><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
-                                                                   s.nseg, s.nwaves, a);
+            go(k_el_apply<T, 3, false>, apply_shape_for<T, 3, false>(g));
     } else {
         if (cg)
-            k_el_apply<T, 2, true><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
-                                                                  s.nseg, s.nwaves, a);
+            go(k_el_apply<T, 2, true>, apply_shape_for<T, 2, true>(g));
         else
-            k_el_apply<T, 2, false><<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz,
-                                                                   s.nseg, s.nwaves, a);
+            go(k_el_apply<T, 2, false>, apply_shape_for<T, 2, false>(g));
     }
+}
+
+template <typename T>
+ApplyShape cg_apply_shape(const Grid& g)
+{
+    return g.dim == 3 ? apply_shape_for<T, 3, true>(g) : apply_shape_for<T, 2, true>(g);
 }
 
 int stream_blocks(long long n)
@@ -687,7 +773,7 @@ int validate(const pf_elastic* p)
         if (k < p->dim - 1) P *= p->n[k];
     }
     if (N * p->dim > (1ll << 38)) return fail(PF_EINVAL, "grid too large");
-    if (P > (1ll << 31) - 64) return fail(PF_EINVAL, "an x-y plane holds too many nodes");
+    if (P >= (1ll << 28)) return fail(PF_EINVAL, "an x-y plane (2-D: a row) holds too many nodes");
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(PF_EINVAL, "h must be finite and > 0");
     if (!(p->E > 0.0) || !std::isfinite(p->E)) return fail(PF_EINVAL, "E must be finite and > 0");
     if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(PF_EINVAL, "nu must lie in (-1, 0.5)");
@@ -800,7 +886,7 @@ int cg_solve(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol,
     k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, (T*)W.s, nullptr);
     k_el_cg_init<<<1, 64, 0, st>>>(W.scal, hm->dev, rtol * rtol, (double)maxit);
     if (int rc = pfapi::check_launch("CG setup")) return rc;
-    const ApplyShape shp = apply_shape(g);
+    const ApplyShape shp = cg_apply_shape<T>(g);
     if (shp.blocks > EL_MAX_PARTS) return pfapi::fail(PF_EINVAL, "grid too large for the CG reduction");
     const int ub = std::min(sb, 1024);
     // enqueue batches of iterations; poll the previous batch while the next runs

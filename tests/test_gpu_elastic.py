@@ -31,7 +31,7 @@ def pair(n, dtype, **kw):
     return g, o
 
 
-SHAPES_2D = [(2, 2), (7, 5), (62, 3), (63, 9), (130, 17), (200, 4), (3, 70)]
+SHAPES_2D = [(2, 2), (7, 5), (62, 3), (63, 9), (130, 17), (200, 4), (3, 70), (1500, 400)]
 SHAPES_3D = [(2, 2, 2), (5, 4, 3), (9, 7, 14), (65, 3, 5), (17, 33, 20), (31, 2, 40)]
 
 
@@ -48,10 +48,12 @@ def test_apply_matches_oracle(n, dtype):
     assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("planes", [1, 3, 64])
-def test_apply_independent_of_chunking(planes):
-    """The z-chunk length changes only which wave computes a node, not how."""
-    g, _ = pair((40, 9, 23), torch.float32)
+@pytest.mark.parametrize("n,planes", [((40, 9, 23), 1), ((40, 9, 23), 3), ((40, 9, 23), 64),
+                                      ((300, 300, 60), 1), ((3000, 700), 2)])
+def test_apply_independent_of_chunking(n, planes):
+    """The z-chunk length changes only which wave computes a node, not how; the
+    larger grids have more work items than resident waves (grid-stride loop)."""
+    g, _ = pair(n, torch.float32)
     u = torch.randn(g.ndof, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
     base = EL.el_apply(g, u)
     L = A.lib()
