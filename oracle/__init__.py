@@ -43,7 +43,11 @@ def build(force: bool = True) -> str:
 class _Problem(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("model", ct.c_int32),
                 ("fe", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
-                ("W", ct.c_double), ("kappa", ct.c_double), ("mob", ct.c_double)]
+                ("W", ct.c_double), ("kappa", ct.c_double), ("mob", ct.c_double),
+                ("mass", ct.c_int32), ("pad", ct.c_int32)]
+
+
+LUMPED, CONSISTENT = 0, 1
 
 
 @dataclass
@@ -57,6 +61,7 @@ class Problem:
     W: float = 1.0
     kappa: float = 1.0
     mob: float = 1.0
+    mass: int = LUMPED  # CONSISTENT: Gauss-integrated mass in the implicit path
 
     @property
     def dim(self) -> int:
@@ -73,7 +78,7 @@ class Problem:
     def _c(self) -> _Problem:
         n3 = list(self.n) + [1] * (3 - len(self.n))
         return _Problem(self.dim, self.bc, self.model, self.fe, (ct.c_int64 * 3)(*n3),
-                        self.h, self.W, self.kappa, self.mob)
+                        self.h, self.W, self.kappa, self.mob, self.mass, 0)
 
 
 _lib = None
@@ -157,7 +162,8 @@ def residual(p: Problem, U) -> np.ndarray:
 def explicit(p: Problem, U, dt: float, nsteps: int) -> np.ndarray:
     """nsteps of the lumped-mass forward-Euler step (Eq. 12); returns a new array."""
     U = _arr(U, p.ndof).copy()
-    lib().orc_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U))
+    if lib().orc_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U)) != 0:
+        raise ValueError("explicit steps need the lumped mass")
     return U
 
 
@@ -216,8 +222,9 @@ def explicit_adjoint(p: Problem, dt: float, nsteps: int, U0, gU):
     gU = _arr(gU)
     tb = np.zeros(3)
     ub = np.zeros(p.nnodes)
-    lib().orc_explicit_adjoint(ct.byref(p._c()), dt, int(nsteps), _d(U0), _d(gU), _d(tb),
-                               _d(ub))
+    if lib().orc_explicit_adjoint(ct.byref(p._c()), dt, int(nsteps), _d(U0), _d(gU), _d(tb),
+                                  _d(ub)) != 0:
+        raise ValueError("explicit steps need the lumped mass")
     return tb, ub
 
 

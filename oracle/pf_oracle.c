@@ -20,7 +20,9 @@
  * readings below are the ones this project adopts):
  *   - Q1 (bi/tri-linear) elements on a uniform grid of spacing h,
  *   - 2-point Gauss-Legendre quadrature per axis for every integral,
- *   - row-sum lumped mass everywhere M appears,
+ *   - row-sum lumped mass everywhere M appears, or (mass = 1, implicit path only)
+ *     the consistent mass M_ab = sum_e sum_q detJ phi_a(q) phi_b(q) in the time
+ *     term and the Cahn-Hilliard mu-row (every term Gauss-integrated),
  *   - periodic (n elements per axis) or no-flux (n-1 elements, natural BC).
  * Node index = i + n0*(j + n1*k) (x fastest).  Cahn-Hilliard states are laid
  * out as [c (N values) ; mu (N values)].
@@ -51,6 +53,8 @@ typedef struct {
     double W;      /* barrier height */
     double kappa;  /* gradient-energy coefficient */
     double mob;    /* mobility: L (Allen-Cahn) or M (Cahn-Hilliard) */
+    int32_t mass;  /* 0: lumped mass; 1: consistent mass (implicit path only) */
+    int32_t pad;
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -250,6 +254,34 @@ int orc_lumped_mass(const orc_problem* p, double* m)
     return 0;
 }
 
+/* out = M v on one field: the lumped mass m_a v_a (mass == 0), or the consistent
+ * mass (mass == 1), sum_e sum_q detJ phi_a(q) phi_b(q) v_b, the Gauss-integrated
+ * int phi_a v_h. */
+static void apply_mass(const orc_problem* p, const double* v, double* out)
+{
+    int64_t N = orc_nnodes(p);
+    if (p->mass == 0) {
+        double* m = (double*)malloc((size_t)N * sizeof(double));
+        orc_lumped_mass(p, m);
+        for (int64_t i = 0; i < N; ++i) out[i] = m[i] * v[i];
+        free(m);
+        return;
+    }
+    orc_ref R;
+    ref_build(&R, p->dim, p->h);
+    int64_t E[3], idx[8];
+    memset(out, 0, (size_t)N * sizeof(double));
+    FOR_EACH_ELEMENT(p, E)
+    {
+        elem_nodes(p, E, R.nv, idx);
+        for (int q = 0; q < R.nv; ++q) {
+            double vq = 0.0;
+            for (int b = 0; b < R.nv; ++b) vq += R.phi[q][b] * v[idx[b]];
+            for (int a = 0; a < R.nv; ++a) out[idx[a]] += R.detJ * R.phi[q][a] * vq;
+        }
+    }
+}
+
 /* discrete free energy E_h = sum_e sum_q detJ [ f(c_q) + kappa/2 |grad c_q|^2 ]  [Eqs. 5-6] */
 double orc_energy(const orc_problem* p, const double* U)
 {
@@ -306,13 +338,11 @@ int orc_residual(const orc_problem* p, const double* U, double* r)
     double* rm = r + N;
     memset(r, 0, (size_t)(2 * N) * sizeof(double));
     assemble_first(p, p->W, mu, 0.0, p->mob, rc);
-    double* m = (double*)malloc((size_t)N * sizeof(double));
-    orc_lumped_mass(p, m);
     double* g = (double*)calloc((size_t)N, sizeof(double));
     assemble_first(p, p->W, c, 1.0, p->kappa, g);
-    for (int64_t i = 0; i < N; ++i) rm[i] = m[i] * mu[i] - g[i];
+    apply_mass(p, mu, rm);
+    for (int64_t i = 0; i < N; ++i) rm[i] -= g[i];
     free(g);
-    free(m);
     return 0;
 }
 
@@ -327,6 +357,7 @@ int orc_residual(const orc_problem* p, const double* U, double* r)
  * On return the Cahn-Hilliard mu plane holds [N(c)+kappa K c]/m of the final c. */
 int orc_explicit(const orc_problem* p, double dt, int64_t nsteps, double* U)
 {
+    if (p->mass != 0) return -2; /* a consistent mass needs a solve: implicit path only */
     int64_t N = orc_nnodes(p);
     double* m = (double*)malloc((size_t)N * sizeof(double));
     double* t = (double*)malloc((size_t)N * sizeof(double));
@@ -359,16 +390,19 @@ int orc_explicit(const orc_problem* p, double dt, int64_t nsteps, double* U)
 /* implicit (backward Euler) residual, Jacobian products   [Eqs. 13-14]       */
 /* ------------------------------------------------------------------------ */
 
-/* R = M (U - U_old)/dt + r(U); for Cahn-Hilliard the mass block is diag(m, 0). */
+/* R = M (U - U_old)/dt + r(U); for Cahn-Hilliard the mass block is diag(M, 0). */
 int orc_be_residual(const orc_problem* p, double dt, const double* Uold, const double* U,
                     double* R)
 {
     int64_t N = orc_nnodes(p);
     orc_residual(p, U, R);
-    double* m = (double*)malloc((size_t)N * sizeof(double));
-    orc_lumped_mass(p, m);
-    for (int64_t i = 0; i < N; ++i) R[i] += m[i] * (U[i] - Uold[i]) / dt;
-    free(m);
+    double* d = (double*)malloc((size_t)N * sizeof(double));
+    double* t = (double*)malloc((size_t)N * sizeof(double));
+    for (int64_t i = 0; i < N; ++i) d[i] = U[i] - Uold[i];
+    apply_mass(p, d, t);
+    for (int64_t i = 0; i < N; ++i) R[i] += t[i] / dt;
+    free(t);
+    free(d);
     return 0;
 }
 
@@ -379,24 +413,27 @@ int orc_be_residual(const orc_problem* p, double dt, const double* Uold, const d
 int orc_jvp(const orc_problem* p, double inv_dt, const double* U, const double* v, double* Jv)
 {
     int64_t N = orc_nnodes(p);
-    double* m = (double*)malloc((size_t)N * sizeof(double));
-    orc_lumped_mass(p, m);
+    double* mv = (double*)malloc((size_t)N * sizeof(double));
+    apply_mass(p, v, mv); /* M v (first field) */
     if (p->model == ORC_AC) {
         memset(Jv, 0, (size_t)N * sizeof(double));
         assemble_second(p, p->W, U, v, p->mob, p->mob * p->kappa, Jv);
-        for (int64_t i = 0; i < N; ++i) Jv[i] += inv_dt * m[i] * v[i];
+        for (int64_t i = 0; i < N; ++i) Jv[i] += inv_dt * mv[i];
     } else {
         memset(Jv, 0, (size_t)(2 * N) * sizeof(double));
         double* a = (double*)calloc((size_t)N, sizeof(double));
+        double* mw = (double*)malloc((size_t)N * sizeof(double));
+        apply_mass(p, v + N, mw);
         assemble_second(p, p->W, U, v + N, 0.0, p->mob, Jv); /* M K v_mu */
         assemble_second(p, p->W, U, v, 1.0, p->kappa, a);    /* N'(c) v_c + kappa K v_c */
         for (int64_t i = 0; i < N; ++i) {
-            Jv[i] += inv_dt * m[i] * v[i];
-            Jv[N + i] = m[i] * v[N + i] - a[i];
+            Jv[i] += inv_dt * mv[i];
+            Jv[N + i] = mw[i] - a[i];
         }
+        free(mw);
         free(a);
     }
-    free(m);
+    free(mv);
     return 0;
 }
 
@@ -407,18 +444,21 @@ int orc_jvp_t(const orc_problem* p, double inv_dt, const double* U, const double
 {
     if (p->model == ORC_AC) return orc_jvp(p, inv_dt, U, w, Jtw);
     int64_t N = orc_nnodes(p);
-    double* m = (double*)malloc((size_t)N * sizeof(double));
-    orc_lumped_mass(p, m);
+    double* mc = (double*)malloc((size_t)N * sizeof(double));
+    double* mw = (double*)malloc((size_t)N * sizeof(double));
+    apply_mass(p, w, mc);     /* the mass is symmetric: M^T w = M w */
+    apply_mass(p, w + N, mw);
     memset(Jtw, 0, (size_t)(2 * N) * sizeof(double));
     double* a = (double*)calloc((size_t)N, sizeof(double));
     assemble_second(p, p->W, U, w + N, 1.0, p->kappa, a);      /* A w_mu */
     assemble_second(p, p->W, U, w, 0.0, p->mob, Jtw + N);       /* M K w_c */
     for (int64_t i = 0; i < N; ++i) {
-        Jtw[i] = inv_dt * m[i] * w[i] - a[i];
-        Jtw[N + i] += m[i] * w[N + i];
+        Jtw[i] = inv_dt * mc[i] - a[i];
+        Jtw[N + i] += mw[i];
     }
     free(a);
-    free(m);
+    free(mw);
+    free(mc);
     return 0;
 }
 
@@ -742,6 +782,7 @@ int orc_newton_be(const orc_problem* p, double dt, const double* Uold, double* U
 int orc_explicit_adjoint(const orc_problem* p, double dt, int64_t nsteps, const double* U0,
                          const double* gU, double* theta_bar, double* U0_bar)
 {
+    if (p->mass != 0) return -2; /* explicit path: lumped mass only */
     int64_t N = orc_nnodes(p);
     double* traj = (double*)malloc((size_t)(nsteps + 1) * (size_t)N * sizeof(double));
     double* m = (double*)malloc((size_t)N * sizeof(double));
@@ -821,10 +862,10 @@ int orc_newton_adjoint(const orc_problem* p, double dt, const double* U, const d
     int64_t n = orc_ndof(p), N = orc_nnodes(p);
     double* lam = (double*)malloc((size_t)n * sizeof(double));
     double* m = (double*)malloc((size_t)N * sizeof(double));
-    orc_lumped_mass(p, m);
     orc_linear_solve(p, 1.0 / dt, U, 1, gU, lam, solver, 1e-13);
     memset(Uold_bar, 0, (size_t)n * sizeof(double));
-    for (int64_t i = 0; i < N; ++i) Uold_bar[i] = m[i] * lam[i] / dt;
+    apply_mass(p, lam, m); /* (M/dt)^T lam on the mass rows; M is symmetric */
+    for (int64_t i = 0; i < N; ++i) Uold_bar[i] = m[i] / dt;
     double g[3];
     orc_dr_dtheta(p, U, lam, g);
     for (int k = 0; k < 3; ++k) theta_bar[k] = -g[k];
