@@ -263,7 +263,7 @@ def coupled_record(stream, n=1024, steps=2000):
                          "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
 
 
-def implicit2d_record(stream, model, n, steps=10, dt=0.05):
+def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0):
     """The paper's 2-D implicit benchmark shapes (backward Euler, Newton + GMRES(30)
     with block Jacobi, FP32 fields): [0, 100]^2 with n^2 nodes, no-flux,
     f' = 4c(c-1)(c-1/2) (W = 1), M = 1, kappa = 2 (Allen-Cahn) or 1.5 (Cahn-Hilliard);
@@ -277,11 +277,11 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05):
     from paper_2601_06079_amd import solver as S
     ch = model == A.CAHN_HILLIARD
     p = S.Problem(n=(n, n), model=model, fe=A.F_01, dtype=torch.float32, W=1.0,
-                  kappa=1.5 if ch else 2.0, mobility=1.0, h=100.0 / (n - 1), bc=A.NOFLUX)
+                  kappa=1.5 if ch else 2.0, mobility=1.0, h=100.0 / (n - 1), bc=A.NOFLUX, mass=mass)
     c0 = I.uniform_field((n, n), -0.05, 0.05, seed=0, base=0.5).astype(np.float32)
     U = torch.as_tensor(np.concatenate([c0, np.zeros_like(c0)]) if ch else c0, device="cuda")
     if ch:
-        S.step_explicit(p, U, 1e-30, 0)  # mu0
+        S.step_explicit(S.Problem(**{**p.__dict__, "mass": 0}), U, 1e-30, 0)  # mu0 (lumped row)
     ws = S.workspace(p, A.OP_NEWTON)
     Uold = torch.empty_like(U)
     Uold.copy_(U)
@@ -299,7 +299,8 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05):
     el = time.perf_counter() - t0
     name = "Cahn-Hilliard" if ch else "Allen-Cahn"
     dof = n * n
-    return {"workload": f"2D {name} {n}x{n} on [0,100]^2, no-flux, backward Euler dt={dt}, "
+    mname = "consistent mass (all terms Gauss-integrated)" if mass else "lumped mass"
+    return {"workload": f"2D {name} {n}x{n} on [0,100]^2, no-flux, backward Euler dt={dt}, {mname}, "
                         "Newton + GMRES(30) with block-Jacobi, FP32 fields",
             "dof": dof, "steps": steps, "converged_steps": ok, "ms_per_step": 1e3 * el / steps,
             "dof_steps_per_s": dof * steps / el, "newton_its_per_step": float(np.mean(newton)),
@@ -584,6 +585,10 @@ def main():
             from paper_2601_06079_amd import _abi as A
             print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048)), flush=True)
             print(json.dumps(implicit2d_record(stream, A.CAHN_HILLIARD, 512)), flush=True)
+            print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5,
+                                               mass=A.MASS_CONSISTENT)), flush=True)
+            print(json.dumps(implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5,
+                                               mass=A.MASS_CONSISTENT)), flush=True)
         if args.coupled:
             print(json.dumps(coupled_record(stream, steps=args.coupled)), flush=True)
             print(json.dumps(coupled_implicit_record(stream)), flush=True)
@@ -705,6 +710,8 @@ def main():
         from paper_2601_06079_amd import _abi as A
         out["implicit_ac2048_2d"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5)
         out["implicit_ch512_2d"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5)
+        out["implicit_ch512_2d_consistent"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5,
+                                                                mass=A.MASS_CONSISTENT)
         out["eshelby_129"] = eshelby_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)

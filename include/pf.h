@@ -61,6 +61,17 @@ enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1,
 enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
        PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
 enum { PF_F32 = 0, PF_F64 = 1 };
+/* Mass matrix of the implicit path.  PF_MASS_LUMPED: the row-sum lumped mass
+ * everywhere (the default; required by the explicit step, its adjoint and the
+ * batches).  PF_MASS_CONSISTENT: every term of the weak form Gauss-integrated,
+ * so the backward-Euler time term M (U - U_old)/dt and the Cahn-Hilliard
+ * mu-row M mu carry M_ab = int phi_a phi_b (Eqs. 11, 13-14); supported by
+ * pf_residual, pf_jvp, pf_newton_step and pf_vjp (PF_VJP_RESIDUAL,
+ * PF_VJP_NEWTON_STEP) for Allen-Cahn and Cahn-Hilliard; the explicit step,
+ * PF_VJP_EXPLICIT_STEP, the batches and the coupled model return
+ * PF_EUNSUPPORTED.  Energies and sum m c are the same for both (the row sums of
+ * the consistent mass are the lumped mass). */
+enum { PF_MASS_LUMPED = 0, PF_MASS_CONSISTENT = 1 };
 
 /* Problem statement: grid, boundary condition, model, free energy and the
  * material parameters theta = (mobility, kappa, W) of Eqs. 1, 5-6, 9-10.
@@ -73,7 +84,7 @@ typedef struct pf_problem {
     int32_t model;    /* PF_ALLEN_CAHN or PF_CAHN_HILLIARD */
     int32_t fe;       /* PF_F_SYM or PF_F_01 */
     int32_t dtype;    /* PF_F32 or PF_F64 */
-    int32_t reserved; /* must be 0 */
+    int32_t mass;     /* PF_MASS_LUMPED (0) or PF_MASS_CONSISTENT (implicit path) */
     int64_t n[3];     /* nodes per axis, each >= 2 (n[2] ignored when dim == 2) */
     double h;         /* grid spacing > 0 */
     double W;         /* barrier height of f */

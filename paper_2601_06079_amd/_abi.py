@@ -18,6 +18,7 @@ PERIODIC, NOFLUX = 0, 1
 ALLEN_CAHN, CAHN_HILLIARD, COUPLED = 0, 1, 2
 F_SYM, F_01 = 0, 1
 F32, F64 = 0, 1
+MASS_LUMPED, MASS_CONSISTENT = 0, 1
 OP_RESIDUAL, OP_STEP_EXPLICIT, OP_ENERGY, OP_NEWTON, OP_VJP, OP_JVP = range(6)
 TUNE_STREAM2D_ROWS, TUNE_STREAM2D_DEPTH, TUNE_STREAM2D_FUSE, TUNE_JVP3D_PLANES = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
@@ -27,7 +28,7 @@ VJP_BEGIN, VJP_END = 1, 2  # flags of pf_vjp_explicit_batched
 
 class pf_problem(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("model", ct.c_int32),
-                ("fe", ct.c_int32), ("dtype", ct.c_int32), ("reserved", ct.c_int32),
+                ("fe", ct.c_int32), ("dtype", ct.c_int32), ("mass", ct.c_int32),
                 ("n", ct.c_int64 * 3), ("h", ct.c_double), ("W", ct.c_double),
                 ("kappa", ct.c_double), ("mobility", ct.c_double), ("mobility_eta", ct.c_double)]
 

@@ -48,7 +48,10 @@ int validate(const pf_problem* p)
     if (p->model != PF_COUPLED && p->fe != PF_F_SYM && p->fe != PF_F_01)
         return fail(PF_EINVAL, "unknown free energy %d", p->fe);
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
-    if (p->reserved != 0) return fail(PF_EINVAL, "reserved field must be 0");
+    if (p->mass != PF_MASS_LUMPED && p->mass != PF_MASS_CONSISTENT)
+        return fail(PF_EINVAL, "unknown mass matrix %d", p->mass);
+    if (p->mass == PF_MASS_CONSISTENT && p->model == PF_COUPLED)
+        return fail(PF_EUNSUPPORTED, "the coupled model uses the lumped mass only");
     long long N = 1;
     for (int k = 0; k < p->dim; ++k) {
         if (p->n[k] < 2) return fail(PF_EINVAL, "n[%d] = %lld must be >= 2", k, (long long)p->n[k]);
@@ -84,6 +87,7 @@ pfk::Geom geom_of(const pf_problem* p)
     }
     g.h = p->h;
     g.bc = p->bc == PF_NOFLUX ? 1 : 0;
+    g.cm = p->mass == PF_MASS_CONSISTENT ? 1 : 0;
     return g;
 }
 
@@ -199,7 +203,10 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
     switch (op) {
         case PF_OP_RESIDUAL:
         case PF_OP_JVP: b = 0; break;
-        case PF_OP_STEP_EXPLICIT: b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : 1); break;
+        case PF_OP_STEP_EXPLICIT:
+            if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
+            b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : 1);
+            break;
         case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
         case PF_OP_NEWTON: b = newton_workspace_bytes(p, 30); break;
         case PF_OP_VJP:
@@ -247,6 +254,8 @@ int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, vo
     if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
     if (int rc = check_ptr(U, p, "U")) return rc;
     if (int rc = check_ptr(ws, p, "ws")) return rc;
+    if (p->mass != PF_MASS_LUMPED)
+        return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass (a consistent mass needs a solve)");
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == PF_F32) return step_explicit_t<float>(p, dt, nsteps, (float*)U, (float*)ws, s);
     return step_explicit_t<double>(p, dt, nsteps, (double*)U, (double*)ws, s);

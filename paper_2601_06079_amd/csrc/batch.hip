@@ -39,6 +39,7 @@ int validate_base(const pf_problem* p)
     if (p->fe != PF_F_SYM && p->fe != PF_F_01) return fail(PF_EINVAL, "unknown free energy %d", p->fe);
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
     if (p->bc != PF_PERIODIC) return fail(PF_EUNSUPPORTED, "batches support periodic grids only");
+    if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "batches use the lumped mass only");
     return PF_OK;
 }
 

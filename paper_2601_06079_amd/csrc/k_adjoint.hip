@@ -89,16 +89,23 @@ __global__ __launch_bounds__(AB) void k_dtheta(const T* __restrict__ U, const T*
     block_partials3(t0, t1, t2, part);
 }
 
-// Ubar[a] += inv_dt m_a lambda[a] on the first N entries (the rows with mass);
-// c = inv_dt h^d, m_a = h^d / 2^b on a no-flux grid
+// Ubar[a] += inv_dt (M lambda)[a] on the first N entries (the rows with mass);
+// c = inv_dt h^d, lumped m_a = h^d / 2^b on a no-flux grid; g.cm: the consistent
+// mass (symmetric, so M^T lambda = M lambda), inv_dt passed as cdt
 template <typename T, int D>
 __global__ __launch_bounds__(AB) void k_mass_axpy(const T* __restrict__ lam, T* __restrict__ ub,
-                                                  Geom g, T c)
+                                                  Geom g, T c, T cdt)
 {
     const long long idx = (long long)blockIdx.x * AB + threadIdx.x;
     int i, j, k;
     if (!node_of<D>(g, idx, i, j, k)) return;
-    ub[idx] += c / (T)bfactor<D>(g, i, j, k) * lam[idx];
+    if (g.cm) {
+        T l[NB<D>::K];
+        gather<T, D>(lam, g, i, j, k, l);
+        ub[idx] += cdt * cmass<T, D>(l, (T)g.h) / (T)bfactor<D>(g, i, j, k);
+    } else {
+        ub[idx] += c / (T)bfactor<D>(g, i, j, k) * lam[idx];
+    }
 }
 
 // Allen-Cahn explicit step S(eta) = eta - dt r(eta)/m:
@@ -230,7 +237,7 @@ template <typename T>
 void launch_mass_axpy(const Geom& g, double inv_dt, const T* lam, T* ub, hipStream_t s)
 {
     const double m = std::pow(g.h, g.dim);
-    DIM_SWITCH(g, { k_mass_axpy<T, D><<<nblk(g), AB, 0, s>>>(lam, ub, g, (T)(inv_dt * m)); });
+    DIM_SWITCH(g, { k_mass_axpy<T, D><<<nblk(g), AB, 0, s>>>(lam, ub, g, (T)(inv_dt * m), (T)inv_dt); });
 }
 
 template <typename T>

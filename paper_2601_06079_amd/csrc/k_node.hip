@@ -12,7 +12,8 @@ namespace {
 
 // r(U): Allen-Cahn  r = L [N + kappa K u];  Cahn-Hilliard r_c = M K mu, r_mu = m mu - [N(c) + kappa K c]
 // With Uold != nullptr the time term inv_dt m (U - Uold) of Eq. 14 is added to
-// the rows that carry mass (Allen-Cahn eta, Cahn-Hilliard c).
+// the rows that carry mass (Allen-Cahn eta, Cahn-Hilliard c).  g.cm: the
+// consistent mass (3^d stencil) replaces m in the time term and the mu-row.
 template <typename T, int D, int MODEL>
 __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const T* __restrict__ Uold,
                                                   T* __restrict__ r, Geom g, Cub<T> F, T detJ,
@@ -26,7 +27,18 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const
     const T h = (T)g.h;
     const T Nn = detJ * quad_sum<T, D, false>(u, u, F);
     const T Ku = stiff<T, D>(u, h);
-    const T tt = Uold ? inv_dt * m * (u[NB<D>::K / 2] - Uold[idx]) : (T)0;
+    T tt = (T)0;
+    if (Uold) {
+        if (g.cm) {
+            T uo[NB<D>::K];
+            gather<T, D>(Uold, g, i, j, k, uo);
+#pragma unroll
+            for (int q = 0; q < NB<D>::K; ++q) uo[q] = u[q] - uo[q];
+            tt = inv_dt * cmass<T, D>(uo, h);
+        } else {
+            tt = inv_dt * m * (u[NB<D>::K / 2] - Uold[idx]);
+        }
+    }
     const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
         r[idx] = (mob * (Nn + kappa * Ku) + tt) * ib;
@@ -34,7 +46,8 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const
         T w[NB<D>::K];
         gather<T, D>(U + g.N, g, i, j, k, w);
         r[idx] = (mob * stiff<T, D>(w, h) + tt) * ib;
-        r[g.N + idx] = (m * w[NB<D>::K / 2] - (Nn + kappa * Ku)) * ib;
+        const T mw = g.cm ? cmass<T, D>(w, h) : m * w[NB<D>::K / 2];
+        r[g.N + idx] = (mw - (Nn + kappa * Ku)) * ib;
     }
 }
 
@@ -71,7 +84,9 @@ __global__ __launch_bounds__(256) void k_prec(const T* __restrict__ U, T* __rest
 // Jv for R = inv_dt M (U - U_old) + r(U)
 // TRANS = 1 gives the transpose product w^T dR/dU (differs from J only for
 // Cahn-Hilliard):  [inv_dt m w_c - (N'(c) + kappa K) w_mu ;  M K w_c + m w_mu].
-// ACC = 1 adds the result into Jv instead of overwriting it.
+// ACC = 1 adds the result into Jv instead of overwriting it.  g.cm: the
+// (symmetric) consistent mass replaces m.  The preconditioner keeps the lumped
+// mass as its approximation of the mass blocks.
 template <typename T, int D, int MODEL, int TRANS, int ACC>
 __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* __restrict__ V,
                                              T* __restrict__ Jv, Geom g, Lin<T> F, T detJ, T kappa,
@@ -88,21 +103,24 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
         gather<T, D>(V, g, i, j, k, v);
         const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
         const T Kv = stiff<T, D>(v, h);
-        const T out = (inv_dt * m * v[NB<D>::K / 2] + mob * (Nv + kappa * Kv)) * ib;
+        const T mv = g.cm ? cmass<T, D>(v, h) : m * v[NB<D>::K / 2];
+        const T out = (inv_dt * mv + mob * (Nv + kappa * Kv)) * ib;
         Jv[idx] = ACC ? Jv[idx] + out : out;
     } else {
         T w[NB<D>::K];
         gather<T, D>(V, g, i, j, k, v);         // c-plane of the direction
         gather<T, D>(V + g.N, g, i, j, k, w);   // mu-plane of the direction
         T oc, om;
+        const T mv = g.cm ? cmass<T, D>(v, h) : m * v[NB<D>::K / 2];
+        const T mw = g.cm ? cmass<T, D>(w, h) : m * w[NB<D>::K / 2];
         if constexpr (TRANS == 0) {
             const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
-            oc = inv_dt * m * v[NB<D>::K / 2] + mob * stiff<T, D>(w, h);
-            om = m * w[NB<D>::K / 2] - (Nv + kappa * stiff<T, D>(v, h));
+            oc = inv_dt * mv + mob * stiff<T, D>(w, h);
+            om = mw - (Nv + kappa * stiff<T, D>(v, h));
         } else {
             const T Nw = detJ * quad_sum<T, D, true>(u, w, F);
-            oc = inv_dt * m * v[NB<D>::K / 2] - (Nw + kappa * stiff<T, D>(w, h));
-            om = mob * stiff<T, D>(v, h) + m * w[NB<D>::K / 2];
+            oc = inv_dt * mv - (Nw + kappa * stiff<T, D>(w, h));
+            om = mob * stiff<T, D>(v, h) + mw;
         }
         oc *= ib;
         om *= ib;
@@ -326,7 +344,7 @@ template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                 double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans, int acc)
 {
-    if (g.dim == 3 && !acc) {
+    if (g.dim == 3 && !acc && !g.cm) {
         launch_jvp3d<T>(g, model, f, kappa, mob, inv_dt, U, v, Jv, s, trans);
         return;
     }

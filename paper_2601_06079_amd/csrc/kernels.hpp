@@ -13,6 +13,7 @@ struct Geom {
     long long N;  // nodes
     double h;
     int bc;
+    int cm;  // 1: consistent mass in the implicit-path kernels (residual, JVP, adjoint)
 };
 
 // Free-energy polynomials with W folded in.

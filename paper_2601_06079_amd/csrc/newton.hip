@@ -516,6 +516,8 @@ int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* 
         return fail(PF_EINVAL, "unknown vjp kind %d", kind);
     if (kind != PF_VJP_RESIDUAL && (!(dt > 0.0) || !std::isfinite(dt)))
         return fail(PF_EINVAL, "dt must be finite and > 0");
+    if (kind == PF_VJP_EXPLICIT_STEP && p->mass != PF_MASS_LUMPED)
+        return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
     if (int rc = check_ptr(U, p, "U")) return rc;
     if (int rc = check_ptr(vbar, p, "vbar")) return rc;
     if (int rc = check_ptr(Ubar, p, "Ubar")) return rc;

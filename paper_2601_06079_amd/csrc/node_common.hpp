@@ -276,6 +276,32 @@ __device__ __forceinline__ T quad_sum_sq2(const T* u, const T* v, Fn F)
 }
 
 // diagonal entry of the unit Q1 stiffness at any periodic node
+// Consistent Q1 mass on a gathered 3^d neighbourhood: the tensor product of the
+// 1-D (h/6)(1, 4, 1) (2-point Gauss integrates phi_a phi_b exactly).
+template <typename T, int D>
+__device__ __forceinline__ T cmass(const T* u, T h)
+{
+    if constexpr (D == 2) {
+        T mx[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) mx[b] = (T)4 * u[1 + 3 * b] + u[3 * b] + u[2 + 3 * b];
+        return (mx[0] + (T)4 * mx[1] + mx[2]) * h * h * (T)(1.0 / 36.0);
+    } else {
+        T mm[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T mx[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T* r = u + 3 * b + 9 * c;
+                mx[b] = (T)4 * r[1] + r[0] + r[2];
+            }
+            mm[c] = mx[0] + (T)4 * mx[1] + mx[2];
+        }
+        return (mm[0] + (T)4 * mm[1] + mm[2]) * h * h * h * (T)(1.0 / 216.0);
+    }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ T stiff_diag(T h)
 {

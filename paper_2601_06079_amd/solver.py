@@ -26,6 +26,7 @@ class Problem:
     mobility: float = 1.0
     bc: int = A.PERIODIC
     mobility_eta: float = 0.0  # coupled model: M_eta
+    mass: int = A.MASS_LUMPED  # MASS_CONSISTENT: Gauss-integrated mass (implicit path)
 
     @property
     def dim(self):
@@ -45,7 +46,7 @@ class Problem:
     def c(self) -> A.pf_problem:
         n3 = [int(v) for v in self.n] + [1] * (3 - len(self.n))
         return A.pf_problem(self.dim, self.bc, self.model, self.fe,
-                            A.F64 if self.dtype == torch.float64 else A.F32, 0,
+                            A.F64 if self.dtype == torch.float64 else A.F32, int(self.mass),
                             (ct.c_int64 * 3)(*n3), float(self.h), float(self.W),
                             float(self.kappa), float(self.mobility), float(self.mobility_eta))
 

@@ -13,10 +13,10 @@ def L():
 
 
 def _prob(**kw):
-    d = dict(dim=2, bc=A.PERIODIC, model=A.CAHN_HILLIARD, fe=A.F_01, dtype=A.F32, reserved=0,
+    d = dict(dim=2, bc=A.PERIODIC, model=A.CAHN_HILLIARD, fe=A.F_01, dtype=A.F32, mass=0,
              n=(64, 48, 1), h=1.0, W=1.0, kappa=2.0, mobility=1.0)
     d.update(kw)
-    return A.pf_problem(d["dim"], d["bc"], d["model"], d["fe"], d["dtype"], d["reserved"],
+    return A.pf_problem(d["dim"], d["bc"], d["model"], d["fe"], d["dtype"], d["mass"],
                         (ct.c_int64 * 3)(*d["n"]), d["h"], d["W"], d["kappa"], d["mobility"])
 
 
@@ -33,7 +33,7 @@ def test_version(L):
 
 @pytest.mark.parametrize("bad,status", [
     (dict(dim=4), A.PF_EINVAL), (dict(model=7), A.PF_EINVAL), (dict(fe=9), A.PF_EINVAL),
-    (dict(dtype=3), A.PF_EINVAL), (dict(reserved=1), A.PF_EINVAL), (dict(n=(1, 8, 1)), A.PF_EINVAL),
+    (dict(dtype=3), A.PF_EINVAL), (dict(mass=2), A.PF_EINVAL), (dict(n=(1, 8, 1)), A.PF_EINVAL),
     (dict(h=0.0), A.PF_EINVAL), (dict(h=float("nan")), A.PF_EINVAL),
     (dict(kappa=float("inf")), A.PF_EINVAL), (dict(bc=5), A.PF_EINVAL)])
 def test_problem_validation(L, bad, status):
