@@ -21,7 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c"),
-        os.path.join(_HERE, "coupled_oracle.c"), os.path.join(_HERE, "elastic_oracle.c")]
+        os.path.join(_HERE, "coupled_oracle.c"), os.path.join(_HERE, "elastic_oracle.c"),
+        os.path.join(_HERE, "grain_oracle.c")]
 
 PERIODIC, NOFLUX = 0, 1
 AC, CH = 0, 1
@@ -120,6 +121,8 @@ def lib():
             _bind_coupled(_lib)
         if hasattr(_lib, "orc_el_apply"):
             _bind_elastic(_lib)
+        if hasattr(_lib, "orc_gg_residual"):
+            _bind_grain(_lib)
     return _lib
 
 
@@ -512,3 +515,91 @@ def el_objective(p: ElasticProblem, u, g=None) -> float:
 
 def el_eigen_integral(p: ElasticProblem) -> float:
     return lib().orc_el_eigen_integral(ct.byref(p._c()))
+
+
+# ---------------------------------------------------------------------------
+# Multi-order-parameter Allen-Cahn (grain growth): p order parameters, states
+# [eta_1 ; ... ; eta_p].  See grain_oracle.c.
+class _GgProblem(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
+                ("L", ct.c_double), ("kappa", ct.c_double), ("gamma", ct.c_double),
+                ("p", ct.c_int32), ("pad", ct.c_int32)]
+
+
+@dataclass
+class GrainProblem:
+    n: tuple
+    p: int = 4
+    bc: int = PERIODIC
+    h: float = 1.0
+    L: float = 1.0
+    kappa: float = 1.0
+    gamma: float = 1.5
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def nnodes(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def ndof(self) -> int:
+        return self.p * self.nnodes
+
+    def _c(self) -> _GgProblem:
+        n3 = list(self.n) + [1] * (3 - len(self.n))
+        return _GgProblem(self.dim, self.bc, (ct.c_int64 * 3)(*n3), self.h, self.L, self.kappa,
+                          self.gamma, self.p, 0)
+
+
+def _bind_grain(L):
+    P = ct.POINTER(_GgProblem)
+    D = ct.POINTER(ct.c_double)
+    for name, res, args in (("orc_gg_f", ct.c_double, [P, D]),
+                            ("orc_gg_df", None, [P, D, D]),
+                            ("orc_gg_lumped_mass", ct.c_int, [P, D]),
+                            ("orc_gg_residual", ct.c_int, [P, D, D]),
+                            ("orc_gg_explicit", ct.c_int, [P, ct.c_double, ct.c_int64, D]),
+                            ("orc_gg_energy", ct.c_double, [P, D])):
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = res, args
+
+
+def gg_f(p: GrainProblem, eta) -> float:
+    eta = _arr(eta, p.p)
+    return lib().orc_gg_f(ct.byref(p._c()), _d(eta))
+
+
+def gg_df(p: GrainProblem, eta) -> np.ndarray:
+    eta = _arr(eta, p.p)
+    out = np.zeros(p.p)
+    lib().orc_gg_df(ct.byref(p._c()), _d(eta), _d(out))
+    return out
+
+
+def gg_lumped_mass(p: GrainProblem) -> np.ndarray:
+    m = np.zeros(p.nnodes)
+    lib().orc_gg_lumped_mass(ct.byref(p._c()), _d(m))
+    return m
+
+
+def gg_residual(p: GrainProblem, U) -> np.ndarray:
+    U = _arr(U, p.ndof)
+    r = np.zeros(p.ndof)
+    if lib().orc_gg_residual(ct.byref(p._c()), _d(U), _d(r)) != 0:
+        raise ValueError("1 <= p <= 64 order parameters")
+    return r
+
+
+def gg_explicit(p: GrainProblem, U, dt: float, nsteps: int) -> np.ndarray:
+    U = _arr(U, p.ndof).copy()
+    if lib().orc_gg_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U)) != 0:
+        raise ValueError("1 <= p <= 64 order parameters")
+    return U
+
+
+def gg_energy(p: GrainProblem, U) -> float:
+    U = _arr(U, p.ndof)
+    return lib().orc_gg_energy(ct.byref(p._c()), _d(U))
