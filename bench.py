@@ -42,6 +42,9 @@ FLOPS_PER_NODE_STEP_COUPLED = 229  # sum-factorised Q1 split step, FMA = 2 flops
 # elasticity operator per node (FMA = 2): 3-D row sums 60, z-combinations 105, x-operator
 # sums 27, x-assembly 72; 2-D: z-combinations 40, sums 8, x-assembly 48
 FLOPS_PER_NODE_ELASTIC = {3: 264, 2: 96}
+# grain growth per node and order parameter (FMA = 2): Gauss-point values 24, S 8,
+# df/deta 20, projection onto the nodes 28, node sum + stiffness + update 21
+FLOPS_PER_NODE_FIELD_GRAIN = 101
 METRIC = "DOF-steps/sec + %HBM peak (explicit CH, 4.19M DOF); adjoint & surrogate speedup"
 
 
@@ -61,6 +64,9 @@ def parse():
     ap.add_argument("--implicit", type=int, default=0, metavar="STEPS",
                     help="only time STEPS backward-Euler Newton steps of the 128^3 Cahn-Hilliard "
                          "workload (4.19M DOF) and print their record")
+    ap.add_argument("--grain", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS explicit steps of the 20-order-parameter grain-growth "
+                         "workload (2048^2) and print its record")
     ap.add_argument("--eshelby", action="store_true",
                     help="only time the Eshelby-inclusion solves (129^3 and 1025^2) and print their records")
     ap.add_argument("--adjoint", action="store_true",
@@ -412,6 +418,42 @@ def eshelby_record(stream, n=(129, 129, 129), rtol=1e-6, reps=50):
                        "frac": upd_gbs / HBM_PEAK_GBS}}
 
 
+def grain_record(stream, n=2048, steps=200):
+    """Grain growth (p = 20 Allen-Cahn order parameters coupled by the multi-well
+    energy, gamma = 1.5, kappa = L = 1, h = 1, dt = 0.1; 60 Voronoi grains), FP32,
+    periodic: `steps` explicit steps in one call, all order parameters per launch."""
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    cfg = I.GRAIN
+    P = cfg["p"]
+    p = S.Problem(n=(n, n), model=A.GRAIN, dtype=torch.float32, h=1.0, kappa=cfg["kappa"],
+                  mobility=cfg["L"], nfields=P, gamma=cfg["gamma"])
+    U = torch.as_tensor(I.grain_state(n, P, cfg["grains"], seed=0, dtype="float32"), device="cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    S.step_explicit(p, U, cfg["dt"], 20, ws)  # warm-up
+    ms = _time_ms(lambda: S.step_explicit(p, U, cfg["dt"], steps, ws), stream)
+    kern_ms = ms / steps
+    N = n * n
+    dof = P * N
+    tflops = FLOPS_PER_NODE_FIELD_GRAIN * dof / (kern_ms * 1e-3) / 1e12
+    gbs = 8 * dof / (kern_ms * 1e-3) / 1e9
+    e = S.energy(p, U)
+    torch.cuda.synchronize()
+    del U, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"grain growth {n}x{n} periodic, {P} order parameters, 60 Voronoi grains, "
+                        f"gamma={cfg['gamma']}, kappa=L=1, FP32 explicit dt={cfg['dt']}",
+            "dof": dof, "steps": steps, "ms_per_step": kern_ms, "dof_steps_per_s": dof / (kern_ms * 1e-3),
+            "energy_after": float(e[0]),
+            "roofline": {"kernel": "k_gg_tile2d<float, step>", "bound": "alu",
+                         "flops_per_node_field": FLOPS_PER_NODE_FIELD_GRAIN, "achieved": tflops,
+                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
+                         "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}}
+
+
 def adjoint_record(stream, count=64, nsteps=2000, every=100):
     """Batched calibration workload (64 ragged Allen-Cahn samples, 128^2..512^2,
     2000 FP32 steps, dt = 0.05): forward plus the hand-written adjoint, against the
@@ -572,9 +614,12 @@ def implicit_record(steps, stream):
 
 def main():
     args = parse()
-    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby:
+    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby or args.grain:
         import torch
         stream = torch.cuda.current_stream()
+        if args.grain:
+            print(json.dumps(grain_record(stream, steps=args.grain)), flush=True)
+            print(json.dumps(grain_record(stream, n=1024, steps=args.grain)), flush=True)
         if args.eshelby:
             print(json.dumps(eshelby_record(stream)), flush=True)
             print(json.dumps(eshelby_record(stream, n=(1025, 1025))), flush=True)
@@ -713,6 +758,7 @@ def main():
         out["implicit_ch512_2d_consistent"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5,
                                                                 mass=A.MASS_CONSISTENT)
         out["eshelby_129"] = eshelby_record(stream)
+        out["grain_2048"] = grain_record(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -58,6 +58,17 @@ enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1,
                           * pf_residual, pf_step_explicit, pf_energy, pf_jvp and
                           * pf_newton_step (3x3 block-Jacobi); pf_vjp and the batch calls
                           * return PF_EUNSUPPORTED. */
+enum { PF_GRAIN = 3 };   /* grain growth: nfields order parameters eta_1..eta_p, each an
+                          * Allen-Cahn field (Eq. 1; mobility = L, kappa) coupled through the
+                          * multi-well energy of the grain-growth literature (the paper does
+                          * not print it):
+                          *   f = sum_i (eta_i^4/4 - eta_i^2/2) + gamma sum_{i<j} eta_i^2 eta_j^2 + 1/4;
+                          * all order parameters are updated in one launch (Sec. 2.4).
+                          * States [eta_1 (N) ; ... ; eta_p (N)].  2-D only; fe and W are
+                          * ignored; nfields <= 32 (PF_F32) or <= 16 (PF_F64).  Supported by
+                          * pf_residual, pf_step_explicit and pf_energy (out[1] = sum m
+                          * sum_i eta_i); the implicit, adjoint and batch calls return
+                          * PF_EUNSUPPORTED. */
 enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
        PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
 enum { PF_F32 = 0, PF_F64 = 1 };
@@ -91,6 +102,9 @@ typedef struct pf_problem {
     double kappa;     /* gradient-energy coefficient */
     double mobility;  /* L (Allen-Cahn) or M (Cahn-Hilliard); M_c (coupled) */
     double mobility_eta; /* coupled model: M_eta (ignored by the other models) */
+    int32_t nfields;  /* PF_GRAIN: number of order parameters (ignored by the other models) */
+    int32_t reserved2; /* must be 0 */
+    double gamma;     /* PF_GRAIN: pair coupling of the multi-well energy */
 } pf_problem;
 
 /* Operation codes for pf_workspace_size. */

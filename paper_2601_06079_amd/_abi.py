@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libpfhip.so")
 
 PF_OK, PF_EINVAL, PF_EDEVICE, PF_ENOCONV, PF_ENONFINITE, PF_EUNSUPPORTED = range(6)
 PERIODIC, NOFLUX = 0, 1
-ALLEN_CAHN, CAHN_HILLIARD, COUPLED = 0, 1, 2
+ALLEN_CAHN, CAHN_HILLIARD, COUPLED, GRAIN = 0, 1, 2, 3
 F_SYM, F_01 = 0, 1
 F32, F64 = 0, 1
 MASS_LUMPED, MASS_CONSISTENT = 0, 1
@@ -30,7 +30,8 @@ class pf_problem(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("model", ct.c_int32),
                 ("fe", ct.c_int32), ("dtype", ct.c_int32), ("mass", ct.c_int32),
                 ("n", ct.c_int64 * 3), ("h", ct.c_double), ("W", ct.c_double),
-                ("kappa", ct.c_double), ("mobility", ct.c_double), ("mobility_eta", ct.c_double)]
+                ("kappa", ct.c_double), ("mobility", ct.c_double), ("mobility_eta", ct.c_double),
+                ("nfields", ct.c_int32), ("reserved2", ct.c_int32), ("gamma", ct.c_double)]
 
 
 class pf_newton_opts(ct.Structure):

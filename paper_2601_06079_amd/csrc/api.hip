@@ -41,11 +41,21 @@ int validate(const pf_problem* p)
 {
     if (!p) return fail(PF_EINVAL, "problem is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(PF_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
-    if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD && p->model != PF_COUPLED)
+    if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD && p->model != PF_COUPLED &&
+        p->model != PF_GRAIN)
         return fail(PF_EINVAL, "unknown model %d", p->model);
+    if (p->reserved2 != 0) return fail(PF_EINVAL, "reserved2 must be 0");
+    if (p->model == PF_GRAIN) {
+        const int pmax = p->dtype == PF_F64 ? 16 : 32;
+        if (p->nfields < 1 || p->nfields > pmax)
+            return fail(PF_EINVAL, "grain growth: nfields must be in [1, %d] (got %d)", pmax, p->nfields);
+        if (!std::isfinite(p->gamma)) return fail(PF_EINVAL, "gamma must be finite");
+        if (p->dim != 2) return fail(PF_EUNSUPPORTED, "grain growth: 2-D grids only");
+        if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "grain growth: lumped mass only");
+    }
     if (p->model == PF_COUPLED && !std::isfinite(p->mobility_eta))
         return fail(PF_EINVAL, "mobility_eta must be finite");
-    if (p->model != PF_COUPLED && p->fe != PF_F_SYM && p->fe != PF_F_01)
+    if (p->model != PF_COUPLED && p->model != PF_GRAIN && p->fe != PF_F_SYM && p->fe != PF_F_01)
         return fail(PF_EINVAL, "unknown free energy %d", p->fe);
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
     if (p->mass != PF_MASS_LUMPED && p->mass != PF_MASS_CONSISTENT)
@@ -94,6 +104,7 @@ pfk::Geom geom_of(const pf_problem* p)
 long long ndof(const pf_problem* p)
 {
     const pfk::Geom g = geom_of(p);
+    if (p->model == PF_GRAIN) return (long long)p->nfields * g.N;
     return (p->model == PF_COUPLED ? 3 : p->model == PF_CAHN_HILLIARD ? 2 : 1) * g.N;
 }
 
@@ -137,10 +148,28 @@ int step_coupled_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, 
     return check_launch("coupled explicit step");
 }
 
+// grain growth: all order parameters per launch, ping-pong between U and ws
+template <typename T>
+int step_grain_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    T *cur = U, *other = ws;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        pfk::launch_gg_tile2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, dt, cur, other, 0, s);
+        std::swap(cur, other);
+    }
+    if (int rc = check_launch("grain step")) return rc;
+    if (cur != U &&
+        hipMemcpyAsync(U, cur, (size_t)p->nfields * g.N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return check_launch("grain step copy-back");
+    return check_launch("grain step");
+}
+
 template <typename T>
 int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
     if (p->model == PF_COUPLED) return step_coupled_t<T>(p, dt, nsteps, U, ws, s);
+    if (p->model == PF_GRAIN) return step_grain_t<T>(p, dt, nsteps, U, ws, s);
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     T* c = U;
@@ -205,11 +234,15 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
         case PF_OP_JVP: b = 0; break;
         case PF_OP_STEP_EXPLICIT:
             if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
-            b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : 1);
+            b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : p->model == PF_GRAIN ? p->nfields : 1);
             break;
         case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
-        case PF_OP_NEWTON: b = newton_workspace_bytes(p, 30); break;
+        case PF_OP_NEWTON:
+            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
+            b = newton_workspace_bytes(p, 30);
+            break;
         case PF_OP_VJP:
+            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
             if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: no adjoint in this build");
             b = vjp_workspace_bytes(p);
             break;
@@ -226,8 +259,17 @@ int pf_residual(const pf_problem* p, const void* U, void* r, void* stream)
     if (int rc = check_ptr(r, p, "r")) return rc;
     if (U == r) return fail(PF_EINVAL, "U and r must not alias");
     const pfk::Geom g = geom_of(p);
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_GRAIN) {
+        if (p->dtype == PF_F32)
+            pfk::launch_gg_tile2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0, (const float*)U,
+                                         (float*)r, 1, s);
+        else
+            pfk::launch_gg_tile2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0,
+                                          (const double*)U, (double*)r, 1, s);
+        return check_launch("pf_residual");
+    }
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     if (p->model == PF_COUPLED) {
         if (p->dtype == PF_F32)
             pfk::launch_cp_residual<float>(g, p->kappa, p->mobility, p->mobility_eta, (const float*)U,
@@ -268,8 +310,16 @@ int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* s
     if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
     if (!ws || reinterpret_cast<uintptr_t>(ws) % 8) return fail(PF_EINVAL, "ws is NULL or misaligned");
     const pfk::Geom g = geom_of(p);
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_GRAIN) {
+        if (p->dtype == PF_F32)
+            pfk::launch_gg_energy2d<float>(g, p->nfields, p->kappa, p->gamma, (const float*)U, (double*)ws, out, s);
+        else
+            pfk::launch_gg_energy2d<double>(g, p->nfields, p->kappa, p->gamma, (const double*)U, (double*)ws,
+                                            out, s);
+        return check_launch("pf_energy");
+    }
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     if (p->model == PF_COUPLED) {
         if (p->dtype == PF_F32)
             pfk::launch_cp_energy<float>(g, p->kappa, (const float*)U, (double*)ws, out, s);
@@ -292,6 +342,7 @@ int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, voi
     if (int rc = check_ptr(v, p, "v")) return rc;
     if (int rc = check_ptr(Jv, p, "Jv")) return rc;
     if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
+    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;

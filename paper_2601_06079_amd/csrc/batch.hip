@@ -33,7 +33,8 @@ int validate_base(const pf_problem* p)
 {
     if (!p) return fail(PF_EINVAL, "base problem is NULL");
     if (p->dim != 2) return fail(PF_EUNSUPPORTED, "batches support 2-D problems only");
-    if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "batches: coupled model not implemented");
+    if (p->model == PF_COUPLED || p->model == PF_GRAIN)
+        return fail(PF_EUNSUPPORTED, "batches: Allen-Cahn and Cahn-Hilliard only");
     if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD)
         return fail(PF_EINVAL, "unknown model %d", p->model);
     if (p->fe != PF_F_SYM && p->fe != PF_F_01) return fail(PF_EINVAL, "unknown free energy %d", p->fe);

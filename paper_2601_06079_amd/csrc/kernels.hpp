@@ -68,7 +68,18 @@ void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, dou
                 int acc = 0);
 // z-planes per block of launch_jvp3d set by pf_tune_set (0: automatic)
 int tune_jvp3d_planes();
-int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = automatic)
+int tune_el_planes();
+
+// grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
+// (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel
+size_t gg_tile_lds_bytes(int P, size_t esize);
+template <typename T>
+void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
+                      T* out, int residual, hipStream_t s);
+// out[0] = E_h, out[1] = sum m sum_i eta_i; partials: 2 * energy_blocks(g) doubles
+template <typename T>
+void launch_gg_energy2d(const Geom& g, int P, double kappa, double gamma, const T* U, double* part,
+                        double* out, hipStream_t s);  // z-planes per wave of the elasticity operator (0 = automatic)
 // 3-D Jv (acc = 0) by element-wise sum factorisation through z-marching LDS tiles
 template <typename T>
 void launch_jvp3d(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,

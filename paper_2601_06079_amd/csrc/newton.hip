@@ -494,6 +494,7 @@ int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
                    const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream)
 {
     if (int rc = validate(p)) return rc;
+    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
     if (int rc = check_ptr(U_old, p, "U_old")) return rc;
     if (int rc = check_ptr(U, p, "U")) return rc;
@@ -512,6 +513,7 @@ int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* 
 {
     if (int rc = validate(p)) return rc;
     if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_vjp: coupled model not implemented");
+    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "pf_vjp: grain growth not implemented");
     if (kind != PF_VJP_RESIDUAL && kind != PF_VJP_EXPLICIT_STEP && kind != PF_VJP_NEWTON_STEP)
         return fail(PF_EINVAL, "unknown vjp kind %d", kind);
     if (kind != PF_VJP_RESIDUAL && (!(dt > 0.0) || !std::isfinite(dt)))

@@ -83,3 +83,32 @@ def coupled_state(n, seed=0, dtype=np.float64):
     rng = np.random.default_rng(seed)
     c = 0.04 + 0.12 * eta + 0.005 * rng.standard_normal((n, n))
     return np.concatenate([c.ravel(), np.zeros(n * n), eta.ravel()]).astype(dtype)
+
+
+# Grain growth: p order parameters on an n x n grid (grid units, h = 1), grains from
+# a seeded Voronoi partition (nearest of `grains` uniform seeds on the periodic
+# square), grain g carried by order parameter g mod p; values 1 inside the
+# grain's order parameter, 0 elsewhere, plus U(-0.01, 0.01) noise.
+GRAIN = dict(p=20, grains=60, kappa=1.0, L=1.0, gamma=1.5, dt=0.1)
+
+
+def grain_state(n, p, grains=None, seed=0, dtype=np.float64):
+    """[eta_1 ; ... ; eta_p] on an n x n grid (see GRAIN)."""
+    rng = np.random.default_rng(seed)
+    grains = grains or 3 * p
+    seeds = rng.uniform(0, n, size=(grains, 2))
+    X, Y = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5)
+    best = np.full((n, n), np.inf)
+    owner = np.zeros((n, n), dtype=np.int64)
+    for g, (sx, sy) in enumerate(seeds):
+        dx = np.abs(X - sx)
+        dy = np.abs(Y - sy)
+        d = np.minimum(dx, n - dx) ** 2 + np.minimum(dy, n - dy) ** 2
+        closer = d < best
+        best[closer] = d[closer]
+        owner[closer] = g
+    U = np.zeros((p, n, n))
+    for k in range(p):
+        U[k][owner % p == k] = 1.0
+    U += rng.uniform(-0.01, 0.01, size=U.shape)
+    return U.reshape(-1).astype(dtype)

@@ -27,6 +27,8 @@ class Problem:
     bc: int = A.PERIODIC
     mobility_eta: float = 0.0  # coupled model: M_eta
     mass: int = A.MASS_LUMPED  # MASS_CONSISTENT: Gauss-integrated mass (implicit path)
+    nfields: int = 1  # GRAIN: order parameters
+    gamma: float = 1.5  # GRAIN: pair coupling
 
     @property
     def dim(self):
@@ -41,6 +43,8 @@ class Problem:
 
     @property
     def ndof(self):
+        if self.model == A.GRAIN:
+            return int(self.nfields) * self.nnodes
         return {A.CAHN_HILLIARD: 2, A.COUPLED: 3}.get(self.model, 1) * self.nnodes
 
     def c(self) -> A.pf_problem:
@@ -48,7 +52,8 @@ class Problem:
         return A.pf_problem(self.dim, self.bc, self.model, self.fe,
                             A.F64 if self.dtype == torch.float64 else A.F32, int(self.mass),
                             (ct.c_int64 * 3)(*n3), float(self.h), float(self.W),
-                            float(self.kappa), float(self.mobility), float(self.mobility_eta))
+                            float(self.kappa), float(self.mobility), float(self.mobility_eta),
+                            int(self.nfields), 0, float(self.gamma))
 
 
 def _stream():
