@@ -65,7 +65,7 @@ enum { PF_GRAIN = 3 };   /* grain growth: nfields order parameters eta_1..eta_p,
                           *   f = sum_i (eta_i^4/4 - eta_i^2/2) + gamma sum_{i<j} eta_i^2 eta_j^2 + 1/4;
                           * all order parameters are updated in one launch (Sec. 2.4).
                           * States [eta_1 (N) ; ... ; eta_p (N)].  2-D only; fe and W are
-                          * ignored; nfields <= 32 (PF_F32) or <= 16 (PF_F64).  Supported by
+                          * ignored; nfields <= 32 (PF_F32) or <= 12 (PF_F64).  Supported by
                           * pf_residual, pf_step_explicit and pf_energy (out[1] = sum m
                           * sum_i eta_i); the implicit, adjoint and batch calls return
                           * PF_EUNSUPPORTED. */

@@ -46,7 +46,7 @@ int validate(const pf_problem* p)
         return fail(PF_EINVAL, "unknown model %d", p->model);
     if (p->reserved2 != 0) return fail(PF_EINVAL, "reserved2 must be 0");
     if (p->model == PF_GRAIN) {
-        const int pmax = p->dtype == PF_F64 ? 16 : 32;
+        const int pmax = p->dtype == PF_F64 ? 12 : 32;  // LDS of the tile kernel <= 64 KB
         if (p->nfields < 1 || p->nfields > pmax)
             return fail(PF_EINVAL, "grain growth: nfields must be in [1, %d] (got %d)", pmax, p->nfields);
         if (!std::isfinite(p->gamma)) return fail(PF_EINVAL, "gamma must be finite");

@@ -7,14 +7,16 @@
 // not O(p^2)); all order parameters are updated together, which is the paper's
 // vectorisation across phase-field variables (Sec. 2.4).
 //
-// k_gg_tile2d: one 256-thread block per 16 x 16 tile of output nodes.
-//   A. all p fields of the 18 x 18 node patch (halo 1) are staged in LDS;
-//   B. each of the 17 x 17 patch elements forms S at its four Gauss points;
-//   C. per field: each element evaluates df/deta_i at its Gauss points and
-//      projects it onto its four nodes (LDS); each output node adds the shares
-//      of its four elements, the closed 9-point stiffness of the staged patch,
-//      and writes the step (or the residual).
-// Every field is read once (with the 1.27x halo of 18^2/16^2) and written once.
+// k_gg_tile2d: one 256-thread block per 15 x 15 tile of output nodes; thread t
+// owns element t of the 16 x 16 elements around the tile.
+//   A. all p fields of the 17 x 17 node patch (halo 1) are staged in LDS;
+//   B. each thread forms S at its element's four Gauss points (kept in registers);
+//   C. per field: each element evaluates df/deta_i at its Gauss points and forms
+//      its four nodal shares (the projection of df/deta_i plus the element
+//      stiffness row kappa (4 u_a - u_x - u_y - 2 u_diag)/6 of the 2-D Q1 element);
+//      each output node sums the shares of its four elements (LDS) and writes the
+//      step (or the residual); four fields share one pair of barriers.
+// Every field is read once (with the 1.28x halo of 17^2/15^2) and written once.
 // No-flux grids stage through the reflected indices; the update r/m needs no
 // correction and the residual rows are divided by 2^b (see device.hpp).
 #include <cmath>
@@ -25,10 +27,11 @@
 namespace pfk {
 namespace {
 
-constexpr int GT = 16;       // output nodes per tile side
+constexpr int GT = 15;       // output nodes per tile side
 constexpr int GS = GT + 2;   // staged patch side
-constexpr int GE = GT + 1;   // patch elements per side
-constexpr int GB = GT * GT;  // threads per block
+constexpr int GE = GT + 1;   // patch elements per side (one per thread)
+constexpr int GB = GE * GE;  // threads per block
+constexpr int FG = 1;        // fields per barrier round
 
 __device__ __forceinline__ int wrap_any(int i, int n)
 {
@@ -58,82 +61,85 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
 {
     extern __shared__ unsigned char smem_raw[];
     T* sf = reinterpret_cast<T*>(smem_raw);  // P * GS * GS
-    T* sS = sf + P * GS * GS;                 // GE * GE * 4
-    T* sE = sS + GE * GE * 4;                 // GE * GE * 4
+    T* sE = sf + P * GS * GS;                 // FG * GB * 4 nodal shares
     const int tid = threadIdx.x;
     const int nx = g.n[0], ny = g.n[1];
     const long long N = g.N;
     const int tx0 = (int)(blockIdx.x % tiles_x) * GT, ty0 = (int)(blockIdx.x / tiles_x) * GT;
 
-    // A. stage every field's patch
-    for (int k = tid; k < P * GS * GS; k += GB) {
-        const int f = k / (GS * GS), rem = k - f * (GS * GS);
-        const int py = rem / GS, px = rem - py * GS;
+    // A. stage every field's patch: each thread owns patch nodes tid and tid + GB
+    //    (the second only for tid < GS*GS - GB), their grid offsets computed once
+    long long off[2] = {0, 0};
+    const int nslot = tid + GB < GS * GS ? 2 : 1;
+    for (int k = 0; k < nslot; ++k) {
+        const int slot = tid + k * GB, py = slot / GS, px = slot - py * GS;
         int gx = tx0 - 1 + px, gy = ty0 - 1 + py;
         gx = g.bc ? reflect(gx, nx) : wrap_any(gx, nx);
         gy = g.bc ? reflect(gy, ny) : wrap_any(gy, ny);
-        sf[k] = in[(long long)f * N + (long long)gy * nx + gx];
+        off[k] = (long long)gy * nx + gx;
+    }
+    for (int f = 0; f < P; ++f) {
+        const T* src = in + (long long)f * N;
+        sf[f * GS * GS + tid] = src[off[0]];
+        if (nslot == 2) sf[f * GS * GS + tid + GB] = src[off[1]];
     }
     __syncthreads();
 
-    // B. S = sum_j eta_j^2 at the Gauss points of every patch element
-    for (int e = tid; e < GE * GE; e += GB) {
-        const int ex = e % GE, ey = e / GE;
-        T s[4] = {T(0), T(0), T(0), T(0)};
-        for (int f = 0; f < P; ++f) {
-            const T* b = sf + f * GS * GS + ey * GS + ex;
-            T q[4];
-            qvals(b[0], b[1], b[GS], b[GS + 1], q);
+    // B. S = sum_j eta_j^2 at the Gauss points of this thread's element
+    const int ex = tid % GE, ey = tid / GE;
+    const int eb = ey * GS + ex;  // the element's lower-left node in the patch
+    T S[4] = {T(0), T(0), T(0), T(0)};
+    for (int f = 0; f < P; ++f) {
+        const T* b = sf + f * GS * GS + eb;
+        T q[4];
+        qvals(b[0], b[1], b[GS], b[GS + 1], q);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) s[i] = fmaT(q[i], q[i], s[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sS[4 * e + i] = s[i];
+        for (int i = 0; i < 4; ++i) S[i] = fmaT(q[i], q[i], S[i]);
     }
-    __syncthreads();
 
     const T h = (T)g.h;
     const T detJ = (T)0.25 * h * h;
     const T c3 = (T)1 - (T)2 * gam, c1 = (T)2 * gam;
-    const int ox = tid % GT, oy = tid / GT;
-    const int gxo = tx0 + ox, gyo = ty0 + oy;
-    const bool valid = gxo < nx && gyo < ny;
+    const T ks = kappa * (T)(1.0 / 6.0);
+    // the output node of this thread (the upper-right node of its element)
+    const int gxo = tx0 + ex, gyo = ty0 + ey;
+    const bool valid = ex < GT && ey < GT && gxo < nx && gyo < ny;
     const T gp = (T)GP, gm = (T)GM;
-    // C. one field at a time
-    for (int f = 0; f < P; ++f) {
-        const T* F = sf + f * GS * GS;
-        for (int e = tid; e < GE * GE; e += GB) {
-            const int ex = e % GE, ey = e / GE;
-            const T* b = F + ey * GS + ex;
+    // C. FG fields per round: shares of FG fields to LDS, one barrier, node sums
+    for (int f0 = 0; f0 < P; f0 += FG) {
+        const int nf = min(FG, P - f0);
+        for (int j = 0; j < nf; ++j) {
+            const T* b = sf + (f0 + j) * GS * GS + eb;
+            const T u00 = b[0], u10 = b[1], u01 = b[GS], u11 = b[GS + 1];
             T q[4];
-            qvals(b[0], b[1], b[GS], b[GS + 1], q);
+            qvals(u00, u10, u01, u11, q);
             T d[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) d[i] = q[i] * fmaT(q[i] * q[i], c3, fmaT(c1, sS[4 * e + i], (T)-1));
-            // project onto the element's nodes: share_a = detJ sum_q phi_a(q) d_q (separable)
+            for (int i = 0; i < 4; ++i) d[i] = q[i] * fmaT(q[i] * q[i], c3, fmaT(c1, S[i], (T)-1));
+            // nodal shares: detJ sum_q phi_a(q) d_q (separable) + element stiffness row
             const T a00 = gp * d[0] + gm * d[1], a10 = gm * d[0] + gp * d[1];  // x-projection, qy = 0
             const T a01 = gp * d[2] + gm * d[3], a11 = gm * d[2] + gp * d[3];  // qy = 1
-            sE[4 * e + 0] = detJ * (gp * a00 + gm * a01);  // node (0, 0)
-            sE[4 * e + 1] = detJ * (gp * a10 + gm * a11);  // node (1, 0)
-            sE[4 * e + 2] = detJ * (gm * a00 + gp * a01);  // node (0, 1)
-            sE[4 * e + 3] = detJ * (gm * a10 + gp * a11);  // node (1, 1)
+            const T sum = (u00 + u10) + (u01 + u11);
+            T* e = sE + (j * GB + tid) * 4;
+            e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * u00 - u11 - sum));  // node (0, 0)
+            e[1] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * u10 - u01 - sum));  // node (1, 0)
+            e[2] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * u01 - u10 - sum));  // node (0, 1)
+            e[3] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * u11 - u00 - sum));  // node (1, 1)
         }
         __syncthreads();
         if (valid) {
-            const int e00 = ox + GE * oy;  // the element below-left of the node
-            const T Nn = sE[4 * e00 + 3] + sE[4 * (e00 + 1) + 2] + sE[4 * (e00 + GE) + 1] +
-                         sE[4 * (e00 + GE + 1) + 0];
-            T u[9];
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) u[dx + 3 * dy] = F[(oy + dy) * GS + ox + dx];
-            const T r = L * (Nn + kappa * stiff<T, 2>(u, h));
-            const long long o = (long long)f * N + (long long)gyo * nx + gxo;
-            if (MODE == 0) {
-                out[o] = u[4] - dtm * r;
-            } else {
-                out[o] = r / (T)bfactor<2>(g, gxo, gyo, 0);
+            for (int j = 0; j < nf; ++j) {
+                // node (ex + 1, ey + 1) of the patch: share 3 of this element, 2 of the one
+                // to the right, 1 of the one above, 0 of the one above-right
+                const T* e = sE + j * GB * 4;
+                const T r = L * ((e[4 * tid + 3] + e[4 * (tid + 1) + 2]) +
+                                 (e[4 * (tid + GE) + 1] + e[4 * (tid + GE + 1) + 0]));
+                const long long o = (long long)(f0 + j) * N + (long long)gyo * nx + gxo;
+                if (MODE == 0) {
+                    out[o] = sf[(f0 + j) * GS * GS + eb + GS + 1] - dtm * r;
+                } else {
+                    out[o] = r / (T)bfactor<2>(g, gxo, gyo, 0);
+                }
             }
         }
         __syncthreads();
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gg_energy2d(Geom g, int P, T kappa, T g
 
 }  // namespace
 
-size_t gg_tile_lds_bytes(int P, size_t esize) { return ((size_t)P * GS * GS + 2 * GE * GE * 4) * esize; }
+size_t gg_tile_lds_bytes(int P, size_t esize) { return ((size_t)P * GS * GS + FG * GB * 4) * esize; }
 
 template <typename T>
 void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,

@@ -22,7 +22,7 @@ def pair(n, p, dtype, bc=O.PERIODIC, h=1.0, L=1.0, kappa=1.0, gamma=1.5):
 
 
 CASES = [((16, 16), 3, O.PERIODIC), ((37, 21), 4, O.NOFLUX), ((5, 70), 2, O.PERIODIC),
-         ((3, 3), 5, O.PERIODIC), ((2, 2), 1, O.NOFLUX), ((50, 33), 8, O.PERIODIC), ((33, 17), 16, O.NOFLUX)]
+         ((3, 3), 5, O.PERIODIC), ((2, 2), 1, O.NOFLUX), ((50, 33), 8, O.PERIODIC), ((33, 17), 12, O.NOFLUX)]
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
@@ -44,6 +44,21 @@ def test_residual_steps_energy(n, p, bc, dtype):
     assert e[0] == pytest.approx(O.gg_energy(o, U), rel=1e-12 if dtype == F64 else 1e-6)
     m = O.gg_lumped_mass(o)
     assert e[1] == pytest.approx(float((np.tile(m, p) * U).sum()), rel=1e-12 if dtype == F64 else 1e-6)
+
+
+def test_thirty_two_fields_fp32():
+    """The largest supported field count (32 in FP32; 12 in FP64, where 13 is rejected)."""
+    announce("grain p=32")
+    g, o = pair((46, 31), 32, F32, bc=O.NOFLUX, h=1.1, kappa=0.7, gamma=1.5)
+    U = rounded(np.random.default_rng(5).uniform(-0.1, 1.1, o.ndof), F32)
+    Ug = dev(U, F32)
+    S.step_explicit(g, Ug, 0.02, 3)
+    ref = O.gg_explicit(o, U, 0.02, 3)
+    assert np.abs(host(Ug) - ref).max() <= 6e-6
+    bad = S.Problem(n=(16, 16), model=A.GRAIN, dtype=F64, nfields=13)
+    with pytest.raises(A.PFError) as e:
+        S.residual(bad, torch.zeros(bad.ndof, dtype=F64, device="cuda"))
+    assert e.value.status == A.PF_EINVAL
 
 
 def test_single_grain_matches_allen_cahn_path():
