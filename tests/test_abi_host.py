@@ -140,3 +140,33 @@ def test_elastic_validation_before_launch(L):
     assert L.pf_tune_set(EL.TUNE_EL_PLANES, 12) == A.PF_OK
     assert L.pf_tune_get(EL.TUNE_EL_PLANES, ct.byref(v)) == A.PF_OK and v.value == 12
     assert L.pf_tune_set(EL.TUNE_EL_PLANES, 0) == A.PF_OK
+
+
+def _grain(**kw):
+    d = dict(dim=2, bc=A.PERIODIC, model=A.GRAIN, fe=0, dtype=A.F32, mass=0, n=(40, 30, 1), h=1.0,
+             W=0.0, kappa=1.0, mobility=1.0, mobility_eta=0.0, nfields=6, reserved2=0, gamma=1.5)
+    d.update(kw)
+    return A.pf_problem(d["dim"], d["bc"], d["model"], d["fe"], d["dtype"], d["mass"],
+                        (ct.c_int64 * 3)(*d["n"]), d["h"], d["W"], d["kappa"], d["mobility"],
+                        d["mobility_eta"], d["nfields"], d["reserved2"], d["gamma"])
+
+
+def test_grain_model_entry_points(L):
+    """Grain growth: the explicit workspace holds all order parameters; the implicit,
+    adjoint and batch paths are rejected before anything is enqueued."""
+    nb = ct.c_size_t(0)
+    p = _grain()
+    assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == A.PF_OK
+    assert nb.value == 6 * 40 * 30 * 4
+    assert L.pf_workspace_size(ct.byref(p), A.OP_NEWTON, ct.byref(nb)) == A.PF_EUNSUPPORTED
+    assert L.pf_workspace_size(ct.byref(p), A.OP_VJP, ct.byref(nb)) == A.PF_EUNSUPPORTED
+    for bad, st in ((dict(nfields=0), A.PF_EINVAL), (dict(nfields=33), A.PF_EINVAL),
+                    (dict(dtype=A.F64, nfields=13), A.PF_EINVAL), (dict(gamma=float("nan")), A.PF_EINVAL),
+                    (dict(reserved2=1), A.PF_EINVAL), (dict(dim=3, n=(8, 8, 8)), A.PF_EUNSUPPORTED),
+                    (dict(mass=1), A.PF_EUNSUPPORTED)):
+        assert L.pf_workspace_size(ct.byref(_grain(**bad)), A.OP_RESIDUAL, ct.byref(nb)) == st, bad
+    fake = [ct.c_void_p(0x1000 * (i + 1)) for i in range(4)]
+    assert L.pf_jvp(ct.byref(p), 1.0, fake[0], fake[1], fake[2], None) == A.PF_EUNSUPPORTED
+    tb = (ct.c_double * 3)()
+    assert L.pf_vjp(ct.byref(p), A.VJP_RESIDUAL, 0.1, fake[0], fake[1], fake[2], tb, fake[3],
+                    None) == A.PF_EUNSUPPORTED
