@@ -562,7 +562,11 @@ def _bind_grain(L):
                             ("orc_gg_lumped_mass", ct.c_int, [P, D]),
                             ("orc_gg_residual", ct.c_int, [P, D, D]),
                             ("orc_gg_explicit", ct.c_int, [P, ct.c_double, ct.c_int64, D]),
-                            ("orc_gg_energy", ct.c_double, [P, D])):
+                            ("orc_gg_energy", ct.c_double, [P, D]),
+                            ("orc_gg_be_residual", ct.c_int, [P, ct.c_double, D, D, D]),
+                            ("orc_gg_jvp", ct.c_int, [P, ct.c_double, D, D, D]),
+                            ("orc_gg_newton_be", ct.c_int, [P, ct.c_double, D, D, ct.c_double, ct.c_int,
+                                                             ct.POINTER(ct.c_int)])):
         fn = getattr(L, name)
         fn.restype, fn.argtypes = res, args
 
@@ -603,3 +607,26 @@ def gg_explicit(p: GrainProblem, U, dt: float, nsteps: int) -> np.ndarray:
 def gg_energy(p: GrainProblem, U) -> float:
     U = _arr(U, p.ndof)
     return lib().orc_gg_energy(ct.byref(p._c()), _d(U))
+
+
+def gg_be_residual(p: GrainProblem, dt: float, Uold, U) -> np.ndarray:
+    Uold, U = _arr(Uold, p.ndof), _arr(U, p.ndof)
+    R = np.zeros(p.ndof)
+    lib().orc_gg_be_residual(ct.byref(p._c()), dt, _d(Uold), _d(U), _d(R))
+    return R
+
+
+def gg_jvp(p: GrainProblem, inv_dt: float, U, v) -> np.ndarray:
+    U, v = _arr(U, p.ndof), _arr(v, p.ndof)
+    Jv = np.zeros(p.ndof)
+    lib().orc_gg_jvp(ct.byref(p._c()), inv_dt, _d(U), _d(v), _d(Jv))
+    return Jv
+
+
+def gg_newton_be(p: GrainProblem, dt: float, Uold, U0=None, rtol=1e-12, maxit=30):
+    """One backward-Euler step by dense Newton (small grids). Returns (U, converged, its)."""
+    Uold = _arr(Uold, p.ndof)
+    U = (Uold if U0 is None else _arr(U0, p.ndof)).copy()
+    its = ct.c_int(0)
+    rc = lib().orc_gg_newton_be(ct.byref(p._c()), dt, _d(Uold), _d(U), rtol, maxit, ct.byref(its))
+    return U, rc == 0, its.value

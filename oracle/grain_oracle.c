@@ -221,3 +221,145 @@ double orc_gg_energy(const orc_gg_problem* p, const double* U)
     }
     return sum;
 }
+
+/* ------------------------------------------------------------------------ */
+/* backward Euler   [Eqs. 13-14]                                             */
+/* ------------------------------------------------------------------------ */
+
+/* second derivatives of f: H_ii = 3 eta_i^2 - 1 + 2 gamma sum_{j != i} eta_j^2,
+ * H_ij = 4 gamma eta_i eta_j (i != j); hv = H v */
+static void gg_hess_apply(const orc_gg_problem* p, const double* eta, const double* v, double* hv)
+{
+    for (int i = 0; i < p->p; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < p->p; ++j) {
+            if (j == i) {
+                double others = 0.0;
+                for (int k = 0; k < p->p; ++k)
+                    if (k != i) others += eta[k] * eta[k];
+                s += (3.0 * eta[i] * eta[i] - 1.0 + 2.0 * p->gamma * others) * v[i];
+            } else {
+                s += 4.0 * p->gamma * eta[i] * eta[j] * v[j];
+            }
+        }
+        hv[i] = s;
+    }
+}
+
+/* R = m (U - Uold)/dt + r(U) for every order parameter */
+int orc_gg_be_residual(const orc_gg_problem* p, double dt, const double* Uold, const double* U, double* R)
+{
+    const int64_t N = gg_nnodes(p);
+    double* m = (double*)malloc((size_t)N * sizeof(double));
+    orc_gg_lumped_mass(p, m);
+    int rc = orc_gg_residual(p, U, R);
+    for (int64_t k = 0; k < p->p * N; ++k) R[k] += m[k % N] * (U[k] - Uold[k]) / dt;
+    free(m);
+    return rc;
+}
+
+/* Jv = inv_dt m v + L [ sum_e sum_q detJ (H(eta_q) v_q)_i phi_a(q) + kappa K v_i ] */
+int orc_gg_jvp(const orc_gg_problem* p, double inv_dt, const double* U, const double* v, double* Jv)
+{
+    gg_ref R;
+    gg_ref_build(&R, p->dim, p->h);
+    const int64_t N = gg_nnodes(p);
+    const int P = p->p;
+    if (P < 1 || P > 64) return -1;
+    double eq[64], vq[64], gv[64][3], hv[64];
+    int64_t E[3], idx[8];
+    double* m = (double*)malloc((size_t)N * sizeof(double));
+    orc_gg_lumped_mass(p, m);
+    for (int64_t k = 0; k < P * N; ++k) Jv[k] = inv_dt * m[k % N] * v[k];
+    free(m);
+    GG_FOR_EACH_ELEMENT(p, E)
+    {
+        gg_elem_nodes(p, E, R.nv, idx);
+        for (int q = 0; q < R.nv; ++q) {
+            for (int i = 0; i < P; ++i) {
+                eq[i] = vq[i] = 0.0;
+                gv[i][0] = gv[i][1] = gv[i][2] = 0.0;
+                for (int a = 0; a < R.nv; ++a) {
+                    eq[i] += R.phi[q][a] * U[i * N + idx[a]];
+                    vq[i] += R.phi[q][a] * v[i * N + idx[a]];
+                    for (int k = 0; k < R.d; ++k) gv[i][k] += R.grad[q][a][k] * v[i * N + idx[a]];
+                }
+            }
+            gg_hess_apply(p, eq, vq, hv);
+            for (int i = 0; i < P; ++i)
+                for (int a = 0; a < R.nv; ++a) {
+                    double gg = 0.0;
+                    for (int k = 0; k < R.d; ++k) gg += gv[i][k] * R.grad[q][a][k];
+                    Jv[i * N + idx[a]] += p->L * R.detJ * (hv[i] * R.phi[q][a] + p->kappa * gg);
+                }
+        }
+    }
+    return 0;
+}
+
+/* one backward-Euler step by Newton with a dense Jacobian (columns from
+ * orc_gg_jvp) and Gaussian elimination with partial pivoting; small grids only.
+ * U holds the initial guess on entry.  Returns 0 on ||R|| <= rtol ||R_0||. */
+int orc_gg_newton_be(const orc_gg_problem* p, double dt, const double* Uold, double* U, double rtol,
+                     int maxit, int* its)
+{
+    const int64_t n = p->p * gg_nnodes(p);
+    double* A = (double*)malloc((size_t)(n * n) * sizeof(double));
+    double* Rv = (double*)malloc((size_t)n * sizeof(double));
+    double* e = (double*)calloc((size_t)n, sizeof(double));
+    double* col = (double*)malloc((size_t)n * sizeof(double));
+    double r0 = -1.0;
+    int k = 0, ok = 0;
+    for (;; ++k) {
+        orc_gg_be_residual(p, dt, Uold, U, Rv);
+        double rn = 0.0;
+        for (int64_t i = 0; i < n; ++i) rn += Rv[i] * Rv[i];
+        rn = sqrt(rn);
+        if (r0 < 0.0) r0 = rn;
+        if (rn <= rtol * r0 || rn == 0.0) {
+            ok = 1;
+            break;
+        }
+        if (k >= maxit) break;
+        for (int64_t j = 0; j < n; ++j) {
+            e[j] = 1.0;
+            orc_gg_jvp(p, 1.0 / dt, U, e, col);
+            e[j] = 0.0;
+            for (int64_t i = 0; i < n; ++i) A[i * n + j] = col[i];
+        }
+        /* solve A d = -R by elimination with partial pivoting */
+        for (int64_t i = 0; i < n; ++i) Rv[i] = -Rv[i];
+        for (int64_t c = 0; c < n; ++c) {
+            int64_t piv = c;
+            for (int64_t i = c + 1; i < n; ++i)
+                if (fabs(A[i * n + c]) > fabs(A[piv * n + c])) piv = i;
+            if (piv != c) {
+                for (int64_t j = 0; j < n; ++j) {
+                    const double t = A[c * n + j];
+                    A[c * n + j] = A[piv * n + j];
+                    A[piv * n + j] = t;
+                }
+                const double t = Rv[c];
+                Rv[c] = Rv[piv];
+                Rv[piv] = t;
+            }
+            for (int64_t i = c + 1; i < n; ++i) {
+                const double l = A[i * n + c] / A[c * n + c];
+                for (int64_t j = c; j < n; ++j) A[i * n + j] -= l * A[c * n + j];
+                Rv[i] -= l * Rv[c];
+            }
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = Rv[i];
+            for (int64_t j = i + 1; j < n; ++j) s -= A[i * n + j] * Rv[j];
+            Rv[i] = s / A[i * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) U[i] += Rv[i];
+    }
+    if (its) *its = k;
+    free(col);
+    free(e);
+    free(Rv);
+    free(A);
+    return ok ? 0 : -1;
+}

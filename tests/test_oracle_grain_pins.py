@@ -112,3 +112,40 @@ def test_explicit_steps_decrease_energy(orc):
         U = O.gg_explicit(g, U, 0.05, 5)
         E.append(O.gg_energy(g, U))
     assert all(b < a for a, b in zip(E, E[1:]))
+
+
+@pytest.mark.parametrize("n,bc,p", [((5, 4), O.PERIODIC, 3), ((4, 5), O.NOFLUX, 2), ((3, 4, 3), O.NOFLUX, 2)])
+def test_jvp_is_derivative_of_residual(orc, n, bc, p):
+    """The Jacobian product against central differences of the backward-Euler
+    residual, and its symmetry (the Hessian of the discrete energy plus a mass)."""
+    g = O.GrainProblem(n, p=p, bc=bc, h=0.8, L=1.3, kappa=0.9, gamma=1.5)
+    U = rng.uniform(0, 1, g.ndof)
+    Uold = rng.uniform(0, 1, g.ndof)
+    v = rng.standard_normal(g.ndof)
+    w = rng.standard_normal(g.ndof)
+    dt = 0.4
+    eps = 1e-6
+    fd = (O.gg_be_residual(g, dt, Uold, U + eps * v) - O.gg_be_residual(g, dt, Uold, U - eps * v)) / (2 * eps)
+    Jv = O.gg_jvp(g, 1 / dt, U, v)
+    assert _rel(Jv, fd) < 1e-8
+    assert w @ Jv == pytest.approx(v @ O.gg_jvp(g, 1 / dt, U, w), rel=1e-12)
+
+
+def test_backward_euler_single_grain_is_allen_cahn(orc):
+    g = O.GrainProblem((6, 5), p=1, h=1.0, L=1.1, kappa=0.8)
+    a = O.Problem(n=(6, 5), model=O.AC, fe=O.F_SYM, W=1.0, kappa=0.8, mob=1.1)
+    Uold = rng.uniform(-0.8, 0.8, g.nnodes)
+    U1, ok1, _ = O.gg_newton_be(g, 0.5, Uold)
+    U2, ok2, _, _ = O.newton_be(a, 0.5, Uold, rtol=1e-12, solver=0)
+    assert ok1 and ok2
+    assert _rel(U1, U2) < 1e-12
+
+
+def test_backward_euler_step_solves_the_residual(orc):
+    g = O.GrainProblem((5, 6), p=3, bc=O.NOFLUX, h=1.0, L=1.0, kappa=1.0)
+    Uold = rng.uniform(0, 1, g.ndof)
+    U, ok, its = O.gg_newton_be(g, 1.0, Uold, rtol=1e-13)
+    assert ok and its >= 2
+    R = O.gg_be_residual(g, 1.0, Uold, U)
+    assert np.max(np.abs(R)) < 1e-12 * max(1.0, np.max(np.abs(O.gg_residual(g, Uold))))
+    assert O.gg_energy(g, U) < O.gg_energy(g, Uold)
