@@ -66,9 +66,10 @@ enum { PF_GRAIN = 3 };   /* grain growth: nfields order parameters eta_1..eta_p,
                           * all order parameters are updated in one launch (Sec. 2.4).
                           * States [eta_1 (N) ; ... ; eta_p (N)].  2-D only; fe and W are
                           * ignored; nfields <= 32 (PF_F32) or <= 12 (PF_F64).  Supported by
-                          * pf_residual, pf_step_explicit and pf_energy (out[1] = sum m
-                          * sum_i eta_i); the implicit, adjoint and batch calls return
-                          * PF_EUNSUPPORTED. */
+                          * pf_residual, pf_step_explicit, pf_energy (out[1] = sum m
+                          * sum_i eta_i), and with nfields <= 24 (PF_F32) by pf_jvp and
+                          * pf_newton_step (point Jacobi over all p N unknowns); pf_vjp and
+                          * the batch calls return PF_EUNSUPPORTED. */
 enum { PF_F_SYM = 0,  /* f(c) = W (c^2 - 1)^2 / 4 */
        PF_F_01 = 1 }; /* f(c) = W c^2 (1 - c)^2  (Supp. Note 3: f' = 4c(c-1)(c-1/2) at W = 1) */
 enum { PF_F32 = 0, PF_F64 = 1 };

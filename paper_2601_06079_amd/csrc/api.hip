@@ -110,6 +110,15 @@ long long ndof(const pf_problem* p)
 
 size_t elem_size(const pf_problem* p) { return p->dtype == PF_F64 ? 8 : 4; }
 
+// the grain-growth Jacobian product stages two sets of fields in LDS (<= 64 KB)
+int grain_implicit_ok(const pf_problem* p)
+{
+    const int pmax = p->dtype == PF_F64 ? 12 : 24;
+    if (p->nfields > pmax)
+        return fail(PF_EUNSUPPORTED, "grain growth: the implicit path takes at most %d order parameters", pmax);
+    return PF_OK;
+}
+
 }  // namespace pfapi
 
 using namespace pfapi;
@@ -238,11 +247,12 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
             break;
         case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
         case PF_OP_NEWTON:
-            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
+            if (p->model == PF_GRAIN)
+                if (int rc = grain_implicit_ok(p)) return rc;
             b = newton_workspace_bytes(p, 30);
             break;
         case PF_OP_VJP:
-            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
+            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: no adjoint in this build");
             if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: no adjoint in this build");
             b = vjp_workspace_bytes(p);
             break;
@@ -342,10 +352,19 @@ int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, voi
     if (int rc = check_ptr(v, p, "v")) return rc;
     if (int rc = check_ptr(Jv, p, "Jv")) return rc;
     if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
-    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
     const pfk::Geom g = geom_of(p);
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     hipStream_t s = (hipStream_t)stream;
+    if (p->model == PF_GRAIN) {
+        if (int rc = grain_implicit_ok(p)) return rc;
+        if (p->dtype == PF_F32)
+            pfk::launch_gg_jvp2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt, (const float*)U,
+                                        (const float*)v, (float*)Jv, s);
+        else
+            pfk::launch_gg_jvp2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt,
+                                         (const double*)U, (const double*)v, (double*)Jv, s);
+        return check_launch("pf_jvp");
+    }
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     if (p->model == PF_COUPLED) {
         if (p->dtype == PF_F32)
             pfk::launch_cp_jvp<float>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, (const float*)U,

@@ -16,6 +16,7 @@ int check_ptr(const void* ptr, const pf_problem* p, const char* name);
 pfk::Geom geom_of(const pf_problem* p);
 long long ndof(const pf_problem* p);
 size_t elem_size(const pf_problem* p);
+int grain_implicit_ok(const pf_problem* p);
 
 // launch shape of the fused 2-D explicit kernel for this problem (tuning table):
 // steps fused per launch, rows per wave for a given fusion depth, prefetch depth

@@ -53,11 +53,13 @@ __device__ __forceinline__ void qvals(T v00, T v10, T v01, T v11, T q[4])
     q[3] = gm * l1 + gp * r1;
 }
 
-// MODE 0: out = eta - dtm * r (explicit step, dtm = dt / h^2); MODE 1: out = r
+// MODE 0: out = eta - dtm * r (explicit step, dtm = dt / h^2);
+// MODE 1: out = r, plus inv_dt m (eta - old) when old != nullptr (backward Euler);
+// MODE 2: out = 1 / diag(dR/dU) (point Jacobi; inv_dt m on the diagonal)
 template <typename T, int MODE>
 __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T gam, T dtm,
                                                   const T* __restrict__ in, T* __restrict__ out,
-                                                  int tiles_x)
+                                                  int tiles_x, const T* __restrict__ old, T inv_dt)
 {
     extern __shared__ unsigned char smem_raw[];
     T* sf = reinterpret_cast<T*>(smem_raw);  // P * GS * GS
@@ -114,13 +116,28 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
             T q[4];
             qvals(u00, u10, u01, u11, q);
             T d[4];
+            T* e = sE + (j * GB + tid) * 4;
+            if (MODE == 2) {
+                // diagonal: d2f/deta_i^2 = eta_i^2 (3 - 2 gamma) - 1 + 2 gamma S, projected
+                // with phi_a^2, plus the element stiffness diagonal 4/6
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[i] = fmaT(q[i] * q[i], c3 + (T)2, fmaT(c1, S[i], (T)-1));
+                const T p2 = gp * gp, m2 = gm * gm;
+                const T a00 = p2 * d[0] + m2 * d[1], a10 = m2 * d[0] + p2 * d[1];
+                const T a01 = p2 * d[2] + m2 * d[3], a11 = m2 * d[2] + p2 * d[3];
+                const T kd = ks * (T)4;
+                e[0] = fmaT(detJ, p2 * a00 + m2 * a01, kd);
+                e[1] = fmaT(detJ, p2 * a10 + m2 * a11, kd);
+                e[2] = fmaT(detJ, m2 * a00 + p2 * a01, kd);
+                e[3] = fmaT(detJ, m2 * a10 + p2 * a11, kd);
+                continue;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) d[i] = q[i] * fmaT(q[i] * q[i], c3, fmaT(c1, S[i], (T)-1));
             // nodal shares: detJ sum_q phi_a(q) d_q (separable) + element stiffness row
             const T a00 = gp * d[0] + gm * d[1], a10 = gm * d[0] + gp * d[1];  // x-projection, qy = 0
             const T a01 = gp * d[2] + gm * d[3], a11 = gm * d[2] + gp * d[3];  // qy = 1
             const T sum = (u00 + u10) + (u01 + u11);
-            T* e = sE + (j * GB + tid) * 4;
             e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * u00 - u11 - sum));  // node (0, 0)
             e[1] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * u10 - u01 - sum));  // node (1, 0)
             e[2] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * u01 - u10 - sum));  // node (0, 1)
@@ -135,12 +152,107 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
                 const T r = L * ((e[4 * tid + 3] + e[4 * (tid + 1) + 2]) +
                                  (e[4 * (tid + GE) + 1] + e[4 * (tid + GE + 1) + 0]));
                 const long long o = (long long)(f0 + j) * N + (long long)gyo * nx + gxo;
+                const T uc = sf[(f0 + j) * GS * GS + eb + GS + 1];
+                const T ib = (T)1 / (T)bfactor<2>(g, gxo, gyo, 0);
                 if (MODE == 0) {
-                    out[o] = sf[(f0 + j) * GS * GS + eb + GS + 1] - dtm * r;
+                    out[o] = uc - dtm * r;
+                } else if (MODE == 1) {
+                    // the reflected row and h^2 are both 2^b times the no-flux ones
+                    const T tt = old ? inv_dt * g.h * g.h * (uc - old[o]) : (T)0;
+                    out[o] = (r + tt) * ib;
                 } else {
-                    out[o] = r / (T)bfactor<2>(g, gxo, gyo, 0);
+                    out[o] = (T)bfactor<2>(g, gxo, gyo, 0) / (r + inv_dt * (T)(g.h * g.h));
                 }
             }
+        }
+        __syncthreads();
+    }
+}
+
+// Jv = inv_dt m v + L [ sum_e sum_q detJ (H(eta_q) v_q)_i phi_a(q) + kappa K v_i ] with
+// (H v)_i = v_i (eta_i^2 (3 - 6 gamma) - 1 + 2 gamma S) + 4 gamma eta_i T,
+// S = sum_j eta_j^2, T = sum_j eta_j v_j (the Hessian of the multi-well energy is
+// symmetric, so this is also the transpose product).  Same tiling as k_gg_tile2d
+// with U and V staged.
+template <typename T>
+__global__ __launch_bounds__(GB) void k_gg_jvp2d(Geom g, int P, T L, T kappa, T gam, T inv_dt,
+                                                 const T* __restrict__ U, const T* __restrict__ V,
+                                                 T* __restrict__ out, int tiles_x)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* su = reinterpret_cast<T*>(smem_raw);  // P * GS * GS
+    T* sv = su + P * GS * GS;                 // P * GS * GS
+    T* sE = sv + P * GS * GS;                 // GB * 4 nodal shares
+    const int tid = threadIdx.x;
+    const int nx = g.n[0], ny = g.n[1];
+    const long long N = g.N;
+    const int tx0 = (int)(blockIdx.x % tiles_x) * GT, ty0 = (int)(blockIdx.x / tiles_x) * GT;
+    long long off[2] = {0, 0};
+    const int nslot = tid + GB < GS * GS ? 2 : 1;
+    for (int k = 0; k < nslot; ++k) {
+        const int slot = tid + k * GB, py = slot / GS, px = slot - py * GS;
+        int gx = tx0 - 1 + px, gy = ty0 - 1 + py;
+        gx = g.bc ? reflect(gx, nx) : wrap_any(gx, nx);
+        gy = g.bc ? reflect(gy, ny) : wrap_any(gy, ny);
+        off[k] = (long long)gy * nx + gx;
+    }
+    for (int f = 0; f < P; ++f) {
+        const long long fo = (long long)f * N;
+        su[f * GS * GS + tid] = U[fo + off[0]];
+        sv[f * GS * GS + tid] = V[fo + off[0]];
+        if (nslot == 2) {
+            su[f * GS * GS + tid + GB] = U[fo + off[1]];
+            sv[f * GS * GS + tid + GB] = V[fo + off[1]];
+        }
+    }
+    __syncthreads();
+    const int ex = tid % GE, ey = tid / GE;
+    const int eb = ey * GS + ex;
+    T S[4] = {T(0), T(0), T(0), T(0)}, Tv[4] = {T(0), T(0), T(0), T(0)};
+    for (int f = 0; f < P; ++f) {
+        const T* b = su + f * GS * GS + eb;
+        const T* c = sv + f * GS * GS + eb;
+        T q[4], w[4];
+        qvals(b[0], b[1], b[GS], b[GS + 1], q);
+        qvals(c[0], c[1], c[GS], c[GS + 1], w);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            S[i] = fmaT(q[i], q[i], S[i]);
+            Tv[i] = fmaT(q[i], w[i], Tv[i]);
+        }
+    }
+    const T h = (T)g.h;
+    const T detJ = (T)0.25 * h * h;
+    const T c3 = (T)3 - (T)6 * gam, c1 = (T)2 * gam, c4 = (T)4 * gam;
+    const T ks = kappa * (T)(1.0 / 6.0);
+    const int gxo = tx0 + ex, gyo = ty0 + ey;
+    const bool valid = ex < GT && ey < GT && gxo < nx && gyo < ny;
+    const T gp = (T)GP, gm = (T)GM;
+    for (int f = 0; f < P; ++f) {
+        const T* b = su + f * GS * GS + eb;
+        const T* c = sv + f * GS * GS + eb;
+        const T v00 = c[0], v10 = c[1], v01 = c[GS], v11 = c[GS + 1];
+        T q[4], w[4];
+        qvals(b[0], b[1], b[GS], b[GS + 1], q);
+        qvals(v00, v10, v01, v11, w);
+        T d[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            d[i] = fmaT(w[i], fmaT(q[i] * q[i], c3, fmaT(c1, S[i], (T)-1)), c4 * q[i] * Tv[i]);
+        const T a00 = gp * d[0] + gm * d[1], a10 = gm * d[0] + gp * d[1];
+        const T a01 = gp * d[2] + gm * d[3], a11 = gm * d[2] + gp * d[3];
+        const T sum = (v00 + v10) + (v01 + v11);
+        T* e = sE + tid * 4;
+        e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * v00 - v11 - sum));
+        e[1] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * v10 - v01 - sum));
+        e[2] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * v01 - v10 - sum));
+        e[3] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * v11 - v00 - sum));
+        __syncthreads();
+        if (valid) {
+            const T r = L * ((sE[4 * tid + 3] + sE[4 * (tid + 1) + 2]) +
+                             (sE[4 * (tid + GE) + 1] + sE[4 * (tid + GE + 1) + 0]));
+            const long long o = (long long)f * N + (long long)gyo * nx + gxo;
+            out[o] = fmaT(inv_dt * h * h, v11, r) / (T)bfactor<2>(g, gxo, gyo, 0);
         }
         __syncthreads();
     }
@@ -209,17 +321,32 @@ size_t gg_tile_lds_bytes(int P, size_t esize) { return ((size_t)P * GS * GS + FG
 
 template <typename T>
 void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
-                      T* out, int residual, hipStream_t s)
+                      T* out, int mode, hipStream_t s, const T* old, double inv_dt)
 {
     const int tiles_x = (g.n[0] + GT - 1) / GT, tiles_y = (g.n[1] + GT - 1) / GT;
     const size_t lds = gg_tile_lds_bytes(P, sizeof(T));
     const T dtm = (T)(dt / (g.h * g.h));
-    if (residual)
-        k_gg_tile2d<T, 1><<<tiles_x * tiles_y, GB, lds, s>>>(g, P, (T)L, (T)kappa, (T)gamma, dtm, in, out,
-                                                            tiles_x);
+    const int nb = tiles_x * tiles_y;
+    if (mode == 1)
+        k_gg_tile2d<T, 1><<<nb, GB, lds, s>>>(g, P, (T)L, (T)kappa, (T)gamma, dtm, in, out, tiles_x, old,
+                                              (T)inv_dt);
+    else if (mode == 2)
+        k_gg_tile2d<T, 2><<<nb, GB, lds, s>>>(g, P, (T)L, (T)kappa, (T)gamma, dtm, in, out, tiles_x, nullptr,
+                                              (T)inv_dt);
     else
-        k_gg_tile2d<T, 0><<<tiles_x * tiles_y, GB, lds, s>>>(g, P, (T)L, (T)kappa, (T)gamma, dtm, in, out,
-                                                            tiles_x);
+        k_gg_tile2d<T, 0><<<nb, GB, lds, s>>>(g, P, (T)L, (T)kappa, (T)gamma, dtm, in, out, tiles_x, nullptr,
+                                              (T)0);
+}
+
+size_t gg_jvp_lds_bytes(int P, size_t esize) { return ((size_t)2 * P * GS * GS + GB * 4) * esize; }
+
+template <typename T>
+void launch_gg_jvp2d(const Geom& g, int P, double L, double kappa, double gamma, double inv_dt, const T* U,
+                     const T* V, T* Jv, hipStream_t s)
+{
+    const int tiles_x = (g.n[0] + GT - 1) / GT, tiles_y = (g.n[1] + GT - 1) / GT;
+    k_gg_jvp2d<T><<<tiles_x * tiles_y, GB, gg_jvp_lds_bytes(P, sizeof(T)), s>>>(
+        g, P, (T)L, (T)kappa, (T)gamma, (T)inv_dt, U, V, Jv, tiles_x);
 }
 
 template <typename T>
@@ -233,7 +360,9 @@ void launch_gg_energy2d(const Geom& g, int P, double kappa, double gamma, const 
 
 #define GG_INST(T)                                                                                         \
     template void launch_gg_tile2d<T>(const Geom&, int, double, double, double, double, const T*, T*, int,  \
-                                      hipStream_t);                                                         \
+                                      hipStream_t, const T*, double);                                       \
+    template void launch_gg_jvp2d<T>(const Geom&, int, double, double, double, double, const T*, const T*, \
+                                     T*, hipStream_t);                                                      \
     template void launch_gg_energy2d<T>(const Geom&, int, double, double, const T*, double*, double*,       \
                                         hipStream_t);
 GG_INST(float)

@@ -73,9 +73,17 @@ int tune_el_planes();
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel
 size_t gg_tile_lds_bytes(int P, size_t esize);
+// mode 0: one explicit step (dt); 1: the residual, with the backward-Euler time term
+// inv_dt m (U - old) when old != nullptr; 2: the point-Jacobi inverse diagonal of
+// dR/dU (inv_dt m + ...) into out
 template <typename T>
 void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
-                      T* out, int residual, hipStream_t s);
+                      T* out, int mode, hipStream_t s, const T* old = nullptr, double inv_dt = 0.0);
+// Jv = dR/dU v of the backward-Euler residual (symmetric); LDS bytes per block
+size_t gg_jvp_lds_bytes(int P, size_t esize);
+template <typename T>
+void launch_gg_jvp2d(const Geom& g, int P, double L, double kappa, double gamma, double inv_dt, const T* U,
+                     const T* V, T* Jv, hipStream_t s);
 // out[0] = E_h, out[1] = sum m sum_i eta_i; partials: 2 * energy_blocks(g) doubles
 template <typename T>
 void launch_gg_energy2d(const Geom& g, int P, double kappa, double gamma, const T* U, double* part,

@@ -61,8 +61,8 @@ NWS<T> layout(const pf_problem* p, void* base)
     L.z = (T*)take(n * sizeof(T));
     L.b = (T*)take(n * sizeof(T));
     L.V = (T*)take((size_t)(MAXM + 1) * L.ld * sizeof(T));
-    L.pinv = (T*)take((size_t)(p->model == PF_COUPLED ? 9 : p->model == PF_CAHN_HILLIARD ? 4 : 1) * g.N *
-                      sizeof(T));
+    L.pinv = (T*)take((size_t)(p->model == PF_COUPLED ? 9 : p->model == PF_CAHN_HILLIARD ? 4
+                               : p->model == PF_GRAIN ? p->nfields : 1) * g.N * sizeof(T));
     const long long nbp = std::max<long long>(pfk::krylov_blocks(n), (g.N + 255) / 256);
     L.part = (double*)take((size_t)(MAXM + 2) * nbp * sizeof(double) + 64);
     L.dev = (double*)take(4 * (MAXM + 8) * sizeof(double));
@@ -178,6 +178,8 @@ struct LinOp {
     {
         if (p->model == PF_COUPLED)
             pfk::launch_cp_jvp<T>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, U, v, out, s);
+        else if (p->model == PF_GRAIN)
+            pfk::launch_gg_jvp2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt, U, v, out, s);
         else
             pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, trans, 0);
     }
@@ -190,8 +192,10 @@ template <typename T>
 int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool prec,
           double bnorm, double tol_abs, int* its, double* res, hipStream_t s)
 {
-    const int model = A.p->model;
-    const long long Nn = A.g.N;
+    // grain growth: point Jacobi over all p N unknowns (the Krylov kernels' point model)
+    const bool grain = A.p->model == PF_GRAIN;
+    const int model = grain ? 0 : A.p->model;
+    const long long Nn = grain ? n : A.g.N;
     const T* pinv = prec ? L.pinv : nullptr;
     const int tr = A.trans;
     double* dh1 = L.dev + DEV_H1;
@@ -322,6 +326,9 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
     auto residual_norm = [&](double* out) -> int {
         if (p->model == PF_COUPLED)
             pfk::launch_cp_residual<T>(g, p->kappa, p->mobility, p->mobility_eta, U, L.R, s, Uold, inv_dt);
+        else if (p->model == PF_GRAIN)
+            pfk::launch_gg_tile2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0, U, L.R, 1, s, Uold,
+                                     inv_dt);
         else
             pfk::launch_residual<T>(g, p->model, f, p->kappa, p->mobility, U, L.R, s, Uold, inv_dt);
         pfk::kr_norm2<T>(L.R, nullptr, n, L.part, dnrm, s, rb->scal_dev());
@@ -354,6 +361,9 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
         if (o.precond == PF_PRECOND_JACOBI) {
             if (p->model == PF_COUPLED)
                 pfk::launch_cp_prec<T>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, U, L.pinv, s);
+            else if (p->model == PF_GRAIN)
+                pfk::launch_gg_tile2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0, U, L.pinv, 2, s,
+                                         nullptr, inv_dt);
             else
                 pfk::launch_prec<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, L.pinv, s);
         }
@@ -494,7 +504,8 @@ int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
                    const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream)
 {
     if (int rc = validate(p)) return rc;
-    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: explicit path only");
+    if (p->model == PF_GRAIN)
+        if (int rc = grain_implicit_ok(p)) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
     if (int rc = check_ptr(U_old, p, "U_old")) return rc;
     if (int rc = check_ptr(U, p, "U")) return rc;

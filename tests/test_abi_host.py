@@ -152,13 +152,15 @@ def _grain(**kw):
 
 
 def test_grain_model_entry_points(L):
-    """Grain growth: the explicit workspace holds all order parameters; the implicit,
-    adjoint and batch paths are rejected before anything is enqueued."""
+    """Grain growth: the explicit workspace holds all order parameters; the implicit
+    path takes at most 24 order parameters (FP32); adjoints are rejected before
+    anything is enqueued."""
     nb = ct.c_size_t(0)
     p = _grain()
     assert L.pf_workspace_size(ct.byref(p), A.OP_STEP_EXPLICIT, ct.byref(nb)) == A.PF_OK
     assert nb.value == 6 * 40 * 30 * 4
-    assert L.pf_workspace_size(ct.byref(p), A.OP_NEWTON, ct.byref(nb)) == A.PF_EUNSUPPORTED
+    assert L.pf_workspace_size(ct.byref(p), A.OP_NEWTON, ct.byref(nb)) == A.PF_OK
+    assert L.pf_workspace_size(ct.byref(_grain(nfields=25)), A.OP_NEWTON, ct.byref(nb)) == A.PF_EUNSUPPORTED
     assert L.pf_workspace_size(ct.byref(p), A.OP_VJP, ct.byref(nb)) == A.PF_EUNSUPPORTED
     for bad, st in ((dict(nfields=0), A.PF_EINVAL), (dict(nfields=33), A.PF_EINVAL),
                     (dict(dtype=A.F64, nfields=13), A.PF_EINVAL), (dict(gamma=float("nan")), A.PF_EINVAL),
@@ -166,7 +168,7 @@ def test_grain_model_entry_points(L):
                     (dict(mass=1), A.PF_EUNSUPPORTED)):
         assert L.pf_workspace_size(ct.byref(_grain(**bad)), A.OP_RESIDUAL, ct.byref(nb)) == st, bad
     fake = [ct.c_void_p(0x1000 * (i + 1)) for i in range(4)]
-    assert L.pf_jvp(ct.byref(p), 1.0, fake[0], fake[1], fake[2], None) == A.PF_EUNSUPPORTED
+    assert L.pf_jvp(ct.byref(_grain(nfields=25)), 1.0, fake[0], fake[1], fake[2], None) == A.PF_EUNSUPPORTED
     tb = (ct.c_double * 3)()
     assert L.pf_vjp(ct.byref(p), A.VJP_RESIDUAL, 0.1, fake[0], fake[1], fake[2], tb, fake[3],
                     None) == A.PF_EUNSUPPORTED
