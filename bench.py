@@ -355,8 +355,9 @@ def eshelby_record(stream, n=(129, 129, 129), rtol=1e-6, reps=50):
     """The Eshelby-inclusion benchmark (Eqs. 3-4, Eq. III.1): [0, 100]^dim with the
     given nodes per axis, E = 22.5, nu = 0.3, dilatational misfit m = 0.01 inside
     radius a = 20 (interface l = 0.5), symmetry planes through the origin and
-    traction-free outer faces; FP32 fields, CG (FP64 scalars) to rtol.  One solve,
-    its volume change and the adjoint (E, nu) sensitivities, plus the operator
+    traction-free outer faces; FP32 fields, multigrid-preconditioned CG (FP64
+    scalars) to rtol.  One solve, its volume change and the adjoint (E, nu)
+    sensitivities, the same solve by plain CG for comparison, plus the operator
     kernel alone (reps launches replayed from a HIP graph, timed with events on the
     stream)."""
     import torch
@@ -376,6 +377,21 @@ def eshelby_record(stream, n=(129, 129, 129), rtol=1e-6, reps=50):
     t0 = time.perf_counter()
     (O, dE, dnu), arep = EL.el_sensitivity(p, u, rtol=rtol, ws=ws)
     sens_s = time.perf_counter() - t0
+    # plain CG on the same problem (one level), for comparison
+    from paper_2601_06079_amd import _abi as A
+    L = A.lib()
+    L.pf_tune_set(EL.TUNE_EL_MG, 1)
+    try:
+        uc = torch.empty_like(u)
+        wsc = EL.workspace(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uc, crep = EL.el_solve(p, out=uc, rtol=rtol, ws=wsc)
+        torch.cuda.synchronize()
+        cg_s = time.perf_counter() - t0
+    finally:
+        L.pf_tune_set(EL.TUNE_EL_MG, 0)
+    del uc, wsc
     # the operator alone: `reps` launches captured in one HIP graph and replayed
     # (no host launch overhead between them), timed with events on the stream
     v = torch.randn(p.ndof, dtype=torch.float32, device="cuda")
@@ -396,26 +412,22 @@ def eshelby_record(stream, n=(129, 129, 129), rtol=1e-6, reps=50):
     tflops = FLOPS_PER_NODE_ELASTIC[dim] * N / (apply_ms * 1e-3) / 1e12
     apply_gbs = 2 * 4 * p.ndof / (apply_ms * 1e-3) / 1e9
     it_ms = 1e3 * solve_s / max(rep.iterations, 1)
-    upd_ms = max(it_ms - apply_ms, 1e-6)
-    upd_gbs = 36 * p.ndof / (upd_ms * 1e-3) / 1e9
     del ws, u, v, y
     torch.cuda.empty_cache()
     shape = "x".join(str(k) for k in n)
     return {"workload": f"Eshelby inclusion {shape} nodes on [0,100]^{dim}"
                         f"{' (plane strain)' if dim == 2 else ''}, E=22.5, nu=0.3, m=0.01, a=20, l=0.5, "
-                        f"symmetry + traction-free, FP32 fields, CG to rtol {rtol:g}",
+                        f"symmetry + traction-free, FP32 fields, multigrid-preconditioned CG to rtol {rtol:g}",
             "dof": p.ndof, "solve_ms": 1e3 * solve_s, "cg_iterations": rep.iterations,
-            "converged": bool(rep.converged), "ms_per_iteration": it_ms,
+            "mg_levels": rep.levels, "converged": bool(rep.converged), "ms_per_iteration": it_ms,
+            "plain_cg": {"solve_ms": 1e3 * cg_s, "iterations": crep.iterations,
+                         "converged": bool(crep.converged)},
             "volume_change": vol, "sensitivity": {"dV_dE": dE, "dV_dnu": dnu, "ms": 1e3 * sens_s,
                                                   "adjoint_iterations": arep.iterations},
             "operator": {"kernel": f"k_el_apply<float, {dim}>", "us_per_launch": 1e3 * apply_ms,
                          "bound": "alu", "flops_per_node": FLOPS_PER_NODE_ELASTIC[dim],
                          "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tflops / VALU_PEAK_TFLOPS, "hbm_gbs": apply_gbs},
-            "update": {"kernel": "k_el_cg_update<float> (per iteration minus the operator; "
-                                 "includes launch gaps)", "ms": upd_ms, "bound": "hbm",
-                       "bytes_per_dof": 36, "achieved": upd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": upd_gbs / HBM_PEAK_GBS}}
+                         "frac": tflops / VALU_PEAK_TFLOPS, "hbm_gbs": apply_gbs}}
 
 
 def grain_record(stream, n=2048, steps=200):

@@ -132,9 +132,10 @@ int pf_version(void);
  *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
  *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product;
- *   PF_TUNE_EL_PLANES:      z-planes (2-D: rows) per wave of the elasticity operator. */
+ *   PF_TUNE_EL_PLANES:      z-planes (2-D: rows) per wave of the elasticity operator;
+ *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid). */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
-       PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4 };
+       PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 /* The launch shape pf_step_explicit uses for p (2-D): steps fused per launch,
@@ -369,13 +370,15 @@ typedef struct pf_el_report {
     int32_t iterations; /* CG iterations */
     int32_t converged;  /* 1 if ||r|| <= rtol ||b|| (recursively updated residual) */
     int32_t status;     /* 1 converged, 2 iteration limit, 3 breakdown, 4 non-finite */
-    int32_t reserved;
+    int32_t levels;     /* multigrid levels of the preconditioner (1: plain CG) */
     double res_norm;    /* final ||r||_2 */
     double rhs_norm;    /* ||b||_2 */
 } pf_el_report;
 
 /* Workspace bytes for pf_el_solve, pf_el_objective and pf_el_sensitivity
- * (seven fields plus FP64 partial sums). */
+ * (seven fields plus FP64 partial sums; with multigrid also one more field,
+ * three fields per coarser grid (under 1/7 of a field in 2-D, 1/2 in 3-D, in
+ * total) and the 9^d eigenvalue-estimate vectors). */
 int pf_el_workspace_size(const pf_elastic* p, size_t* bytes);
 
 /* y = K u (the stiffness of Eqs. 3-4 with the identity rows above).  u, y
@@ -388,9 +391,17 @@ int pf_el_apply(const pf_elastic* p, const void* u, void* y, void* stream);
 int pf_el_rhs(const pf_elastic* p, void* f, void* stream);
 
 /* Solve K u = b by conjugate gradients from u = 0 until ||r|| <= rtol ||b||
- * or maxit iterations; b = NULL solves for the eigenstrain load.  b's entries
- * on the fixed components are copied into u.  Host-synchronous; returns PF_OK,
- * PF_ENOCONV (u holds the last iterate) or PF_ENONFINITE; rep may be NULL. */
+ * or maxit iterations; b = NULL solves for the eigenstrain load.  When every
+ * axis has an odd node count of at least 5, the CG is preconditioned by a
+ * geometric multigrid V-cycle: the grid halves while that holds (rep->levels
+ * grids), Q1 rediscretised at 2h, trilinear transfers, two damped-Jacobi sweeps
+ * before and after and sixteen on the coarsest grid, damping 1.6 / lambda_max
+ * of D^-1 K.  lambda_max depends on dim and nu only; the first solve of a
+ * (dim, nu) pair in the process estimates it by power iteration on a 9^d grid
+ * (about a millisecond).  Other grids, or pf_tune_set(PF_TUNE_EL_MG, 1), use
+ * plain CG.  The fixed components are identity rows of K (u there matches b to
+ * the tolerance).  Host-synchronous; returns PF_OK, PF_ENOCONV (u holds the
+ * last iterate) or PF_ENONFINITE; rep may be NULL. */
 int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,
                 pf_el_report* rep, void* ws, void* stream);
 

@@ -49,6 +49,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "../../include/pf.h"
 #include "api_internal.hpp"
@@ -195,19 +197,31 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh)
 
 struct CgArgs {
     double* part;        // 2 doubles per block of the apply
-    const double* state; // the CG state slot this iteration reads (S_DONE)
+    const double* state; // the CG state slot this iteration reads (S_DONE); may be null
 };
 
-// y = K u (ident: identity rows on the fixed components, else zero rows).
-// CG: u is the residual r, y is w = K r; each block stores its partial sums of
-// r.r and w.r (the update kernel reduces them).
-template <typename T, int D, bool CG>
+// Operator modes:
+//   EL_PLAIN   y = K u (ident: identity rows on the fixed components, else zero rows)
+//   EL_CG      y = K u, and per-block partial sums of u.u and y.u (CG; the update
+//              kernel reduces them)
+//   EL_RESID   y = b - K u
+//   EL_JACOBI  y = u + omega D^-1 (b - K u), D the diagonal of K (one damped
+//              Jacobi sweep; the multigrid smoother)
+//   EL_JACOBI_DOT  the same sweep, and per-block partial sums of y.b and b.b
+//              (the preconditioned CG's z.r and r.r from the last smoothing sweep)
+// In every mode the launch returns at once if cg.state says the solve is done.
+enum { EL_PLAIN = 0, EL_CG = 1, EL_RESID = 2, EL_JACOBI = 3, EL_JACOBI_DOT = 4 };
+template <typename T, int D, int MODE>
 __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T scale, int ident,
                                                       const T* __restrict__ u, T* __restrict__ y,
-                                                      int tz, int nseg, int nitems, CgArgs cg)
+                                                      int tz, int nseg, int nitems, CgArgs cg,
+                                                      const T* __restrict__ bvec, T omega)
 {
+    constexpr bool CG = MODE == EL_CG;
+    constexpr bool JAC = MODE == EL_JACOBI || MODE == EL_JACOBI_DOT;
+    constexpr bool PART = CG || MODE == EL_JACOBI_DOT;
     __shared__ double sh[2 * EL_WAVES];
-    if (CG && cg.state[S_DONE] != 0.0) return;
+    if (cg.state && cg.state[S_DONE] != 0.0) return;
     const int lane = threadIdx.x % WAVE;
     // wave-uniform work item (kept in scalar registers: plane loop, z-operators and
     // plane base addresses are then scalar)
@@ -347,7 +361,51 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T sc
             const T w2 = xsum(SA2, SM2, SR2, SC2);
             T w1 = T(0);
             if (D == 3) w1 = xsum(SA1, SM1, SR1, SC1);
-            if (out_lane) {
+            if (out_lane && (MODE == EL_RESID || JAC)) {
+                const long long o = (long long)k * P + q;
+                const T r0 = B_.raw[0], r1 = B_.raw[1], r2 = B_.raw[2];
+                const bool f0 = x == 0, f1 = yr == 0, f2 = k == 0;  // fixed components
+                const T k0v = f0 ? r0 : w0, k2v = f2 ? r2 : w2, k1v = f1 ? r1 : w1;
+                const long long o0 = (long long)g.coff[0] * N + o, o2 = (long long)g.coff[2] * N + o;
+                if (MODE == EL_RESID) {
+                    y[o0] = bvec[o0] - k0v;
+                    y[o2] = bvec[o2] - k2v;
+                    if (D == 3) y[(long long)g.coff[1] * N + o] = bvec[(long long)g.coff[1] * N + o] - k1v;
+                } else {
+                    // the diagonal from the same 1-D operators (centre entries)
+                    T d0, d1 = T(1), d2;
+                    if (D == 3) {
+                        const T pxx = fx.a[1] * fy.m[1] * fz.m[1], pyy = fx.m[1] * fy.a[1] * fz.m[1],
+                                pzz = fx.m[1] * fy.m[1] * fz.a[1];
+                        d0 = scale * (lm2 * pxx + mu * (pyy + pzz));
+                        d1 = scale * (lm2 * pyy + mu * (pxx + pzz));
+                        d2 = scale * (lm2 * pzz + mu * (pxx + pyy));
+                    } else {
+                        const T pxx = fx.a[1] * fz.m[1], pzz = fx.m[1] * fz.a[1];
+                        d0 = lm2 * pxx + mu * pzz;
+                        d2 = lm2 * pzz + mu * pxx;
+                    }
+                    d0 = f0 ? T(1) : d0;
+                    d1 = f1 ? T(1) : d1;
+                    d2 = f2 ? T(1) : d2;
+                    const T b0 = bvec[o0], b2 = bvec[o2];
+                    const T y0 = r0 + omega * (b0 - k0v) / d0;
+                    const T y2 = r2 + omega * (b2 - k2v) / d2;
+                    y[o0] = y0;
+                    y[o2] = y2;
+                    T y1 = T(0), b1 = T(0);
+                    if (D == 3) {
+                        const long long o1 = (long long)g.coff[1] * N + o;
+                        b1 = bvec[o1];
+                        y1 = r1 + omega * (b1 - k1v) / d1;
+                        y[o1] = y1;
+                    }
+                    if (PART) {
+                        pg += (double)y0 * b0 + (double)y2 * b2 + (D == 3 ? (double)y1 * b1 : 0.0);
+                        pd += (double)b0 * b0 + (double)b2 * b2 + (D == 3 ? (double)b1 * b1 : 0.0);
+                    }
+                }
+            } else if (out_lane) {
                 const long long o = (long long)k * P + q;
                 const T r0 = B_.raw[0], r1 = B_.raw[1], r2 = B_.raw[2];
                 const T y0 = x == 0 ? (ident ? r0 : T(0)) : w0;
@@ -389,7 +447,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_apply(Grid g, T lam, T mu, T sc
             emit(k + 2, pC, pA, pB);
         }
     }
-    if (!CG) return;
+    if (!PART) return;
     block_sum2<T>(pg, pd, sh);
     if (threadIdx.x == 0) {
         cg.part[2 * blockIdx.x] = pg;
@@ -498,48 +556,77 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_cg_update(long long n, const do
 
 // Eigenstrain load f_i(a) = sum over the node's elements and their Gauss points
 // of |J| coef e0(|x_q|) d_i phi_a(x_q), e0 of Eq. III.1; zero on fixed components.
+// A block owns a tile of nodes (8 x 8 x 4 in 3-D, 16 x 16 in 2-D): it first
+// evaluates |J| coef e0 once at every Gauss point of the elements touching the
+// tile (into LDS; the profile's tanh is the costly part, and each point serves
+// up to 2^D nodes), then every node sums its 2^D elements' points.
+template <int D>
+struct RhsTile {
+    static constexpr int TX = D == 3 ? 8 : 16, TY = D == 3 ? 8 : 16, TZ = D == 3 ? 4 : 1;
+    // Gauss points per axis over the tile's elements (tile + 1 elements, 2 each)
+    static constexpr int QX = 2 * (TX + 1), QY = 2 * (TY + 1), QZ = D == 3 ? 2 * (TZ + 1) : 1;
+    static constexpr int NQ = QX * QY * QZ;
+};
+
 template <typename T, int D>
 __global__ void __launch_bounds__(EL_BLOCK) k_el_rhs(Grid g, double coef, double m, double a, double l,
-                                                    T* __restrict__ f)
+                                                    T* __restrict__ f, int tiles_x, int tiles_y)
 {
-    const long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
-    if (i >= g.N) return;
-    int idx[3];
+    using RT = RhsTile<D>;
+    static_assert(RT::TX * RT::TY * RT::TZ == EL_BLOCK, "one node per thread");
+    __shared__ double wq[RT::NQ];
     int n[3];
     // problem axes (not kernel axes): 2-D uses (x, y), 3-D (x, y, z)
     n[0] = g.nx;
     n[1] = D == 3 ? g.ny : g.nz;
     n[2] = D == 3 ? g.nz : 1;
-    idx[0] = (int)(i % n[0]);
-    idx[1] = (int)((i / n[0]) % n[1]);
-    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
+    const int t0[3] = {bx * RT::TX, by * RT::TY, bz * RT::TZ};
     const double h = g.h;
     const double gq = 0.57735026918962576451;  // 1/sqrt(3)
     const double detJ = D == 3 ? 0.125 * h * h * h : 0.25 * h * h;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int e = 0; e < (1 << D); ++e) {
-        // element whose local node bit b_k (0 = lower, 1 = upper) on axis k is e's bit
-        int el[3];
+    // phase 1: the tile's Gauss-point weights; local point q on an axis belongs to
+    // element t0 - 1 + q / 2, at its lower (even q) or upper Gauss coordinate
+    for (int qi = threadIdx.x; qi < RT::NQ; qi += EL_BLOCK) {
+        const int q[3] = {qi % RT::QX, (qi / RT::QX) % RT::QY, qi / (RT::QX * RT::QY)};
+        double r2 = 0.0;
         bool ok = true;
         for (int k = 0; k < D; ++k) {
-            const int b = (e >> k) & 1;
-            el[k] = idx[k] - b;
-            if (el[k] < 0 || el[k] >= n[k] - 1) ok = false;
+            const int el = t0[k] - 1 + (q[k] >> 1);
+            ok = ok && el >= 0 && el < n[k] - 1;
+            const double xi = (q[k] & 1) ? gq : -gq;  // reference coordinate in [-1, 1]
+            const double xk = h * (el + 0.5 * (1.0 + xi));
+            r2 += xk * xk;
         }
-        if (!ok) continue;
+        wq[qi] = ok ? detJ * coef * (m * (0.5 - 0.5 * tanh(l * (sqrt(r2) - a)))) : 0.0;
+    }
+    __syncthreads();
+    // phase 2: one node per thread
+    const int lt[3] = {(int)(threadIdx.x % RT::TX), (int)((threadIdx.x / RT::TX) % RT::TY),
+                       (int)(threadIdx.x / (RT::TX * RT::TY))};
+    int idx[3];
+    bool inside = true;
+    for (int k = 0; k < 3; ++k) {
+        idx[k] = t0[k] + lt[k];
+        inside = inside && idx[k] < n[k];
+    }
+    if (!inside) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < (1 << D); ++e) {
+        // element whose local node bit b_k (0 = lower, 1 = upper) on axis k is e's
+        // bit: local element lt_k + 1 - b_k of the tile's range
         for (int qp = 0; qp < (1 << D); ++qp) {
-            double r2 = 0.0, val[3], der[3];
+            int qloc[3] = {0, 0, 0};
+            double val[3], der[3];
             for (int k = 0; k < D; ++k) {
                 const int qb = (qp >> k) & 1, b = (e >> k) & 1;
-                const double xi = qb ? gq : -gq;  // reference coordinate in [-1, 1]
-                const double xk = h * (el[k] + 0.5 * (1.0 + xi));
-                r2 += xk * xk;
+                qloc[k] = 2 * (lt[k] + 1 - b) + qb;
+                const double xi = qb ? gq : -gq;
                 const double sgn = b ? 1.0 : -1.0;
                 val[k] = 0.5 * (1.0 + sgn * xi);
                 der[k] = sgn / h;
             }
-            const double e0 = m * (0.5 - 0.5 * tanh(l * (sqrt(r2) - a)));
-            const double w = detJ * coef * e0;
+            const double w = wq[qloc[0] + RT::QX * (qloc[1] + RT::QY * qloc[2])];
             for (int c = 0; c < D; ++c) {
                 double gc = der[c];
                 for (int k = 0; k < D; ++k)
@@ -548,6 +635,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_rhs(Grid g, double coef, double
             }
         }
     }
+    const long long i = idx[0] + (long long)n[0] * (idx[1] + (long long)n[1] * idx[2]);
     for (int c = 0; c < D; ++c) f[c * g.N + i] = idx[c] == 0 ? T(0) : (T)acc[c];
 }
 
@@ -641,6 +729,263 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_weights(Grid g, const T* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Geometric multigrid (V-cycle) preconditioner and the preconditioned CG.
+// The Q1 spaces of the grids n, (n - 1)/2 + 1, ... are nested, and with one
+// homogeneous stiffness the Galerkin coarse operator P^T K P equals the Q1
+// stiffness rediscretised at 2h, so every level runs k_el_apply with its own
+// spacing.  Restriction is the transpose of the trilinear prolongation; the
+// symmetry-plane components stay fixed (zero) on every level.
+
+// PCG state (FP64, one slot; the done flag sits where k_el_apply looks for it)
+enum { P_RHO = 0, P_RHO_OLD = 1, P_TOL2 = 2, P_ITS = 3, P_DONE = 4, P_MAXIT = 5, P_RR = 6, P_RTOL2 = 7 };
+static_assert(P_DONE == S_DONE, "the operator's early exit reads the same done flag");
+
+template <int D>
+__device__ __forceinline__ void prob_axes(const Grid& g, int* n)
+{
+    n[0] = g.nx;
+    n[1] = D == 3 ? g.ny : g.nz;
+    n[2] = D == 3 ? g.nz : 1;
+}
+
+// The first smoothing sweep from x = 0: y = omega D^-1 b (no operator
+// needed), D the diagonal of K from the centre entries of the 1-D operators
+// (1 on the fixed components)
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_jacobi0(Grid g, T lam, T mu, T scale, const T* __restrict__ b,
+                                                        T* __restrict__ y, T omega, const double* __restrict__ st)
+{
+    if (st && st[P_DONE] != 0.0) return;
+    const long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
+    if (i >= g.N) return;
+    int n[3], idx[3];
+    prob_axes<D>(g, n);
+    idx[0] = (int)(i % n[0]);
+    idx[1] = (int)((i / n[0]) % n[1]);
+    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    T mc[3], ac[3];
+    for (int k = 0; k < D; ++k) {
+        const Fac<T> f = fac<T>(idx[k] > 0, idx[k] < n[k] - 1);
+        mc[k] = f.m[1];
+        ac[k] = f.a[1];
+    }
+    const T lm2 = lam + T(2) * mu;
+    for (int c = 0; c < D; ++c) {
+        // P_kk centre entry: a on axis k, m on the others
+        T diag = T(0);
+        for (int k = 0; k < D; ++k) {
+            T pkk = ac[k];
+            for (int j = 0; j < D; ++j)
+                if (j != k) pkk *= mc[j];
+            diag += (k == c ? lm2 : mu) * pkk;
+        }
+        diag *= scale;
+        const long long o = c * g.N + i;
+        y[o] = idx[c] == 0 ? omega * b[o] : omega * b[o] / diag;
+    }
+}
+
+// rc = P^T rf: coarse node I gathers the fine nodes 2I + o (|o_k| <= 1, inside the
+// grid) with weights prod_k (o_k == 0 ? 1 : 1/2); fixed coarse components are zero
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_restrict(Grid gf, Grid gc, const T* __restrict__ rf,
+                                                         T* __restrict__ rc, const double* __restrict__ st)
+{
+    if (st && st[P_DONE] != 0.0) return;
+    const long long I = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
+    if (I >= gc.N) return;
+    int nc[3], nf[3], ic[3];
+    prob_axes<D>(gc, nc);
+    prob_axes<D>(gf, nf);
+    ic[0] = (int)(I % nc[0]);
+    ic[1] = (int)((I / nc[0]) % nc[1]);
+    ic[2] = D == 3 ? (int)(I / ((long long)nc[0] * nc[1])) : 0;
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int fx = 2 * ic[0] + ox, fy = 2 * ic[1] + oy, fz = 2 * ic[2] + oz;
+                if (fx < 0 || fx >= nf[0] || fy < 0 || fy >= nf[1] || fz < 0 || fz >= nf[2]) continue;
+                const T w = (ox ? T(0.5) : T(1)) * (oy ? T(0.5) : T(1)) * (oz ? T(0.5) : T(1));
+                const long long fi = fx + (long long)nf[0] * (fy + (long long)nf[1] * fz);
+                for (int c = 0; c < D; ++c) acc[c] = pfk::fmaT(w, rf[c * gf.N + fi], acc[c]);
+            }
+    for (int c = 0; c < D; ++c) rc[c * gc.N + I] = ic[c] == 0 ? T(0) : acc[c];
+}
+
+// xf += P ec (trilinear interpolation of the coarse correction)
+template <typename T, int D>
+__global__ void __launch_bounds__(EL_BLOCK) k_el_prolong(Grid gc, Grid gf, const T* __restrict__ ec,
+                                                        T* __restrict__ xf, const double* __restrict__ st)
+{
+    if (st && st[P_DONE] != 0.0) return;
+    const long long F = blockIdx.x * (long long)EL_BLOCK + threadIdx.x;
+    if (F >= gf.N) return;
+    int nc[3], nf[3], f[3];
+    prob_axes<D>(gc, nc);
+    prob_axes<D>(gf, nf);
+    f[0] = (int)(F % nf[0]);
+    f[1] = (int)((F / nf[0]) % nf[1]);
+    f[2] = D == 3 ? (int)(F / ((long long)nf[0] * nf[1])) : 0;
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = f[k] >> 1;
+        hi[k] = (f[k] & 1) ? lo[k] + 1 : lo[k];
+    }
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int bz = 0; bz < (D == 3 ? 2 : 1); ++bz)
+        for (int by = 0; by < 2; ++by)
+            for (int bx = 0; bx < 2; ++bx) {
+                const int cx = bx ? hi[0] : lo[0], cy = by ? hi[1] : lo[1], cz = bz ? hi[2] : lo[2];
+                // a node on a coarse line takes its one coarse value once (weight 1)
+                const T w = ((f[0] & 1) ? T(0.5) : (bx ? T(0) : T(1))) * ((f[1] & 1) ? T(0.5) : (by ? T(0) : T(1))) *
+                            (D == 3 ? ((f[2] & 1) ? T(0.5) : (bz ? T(0) : T(1))) : T(1));
+                if (w == T(0)) continue;
+                const long long ci = cx + (long long)nc[0] * (cy + (long long)nc[1] * cz);
+                for (int c = 0; c < D; ++c) acc[c] = pfk::fmaT(w, ec[c * gc.N + ci], acc[c]);
+            }
+    for (int c = 0; c < D; ++c) xf[c * gf.N + F] += acc[c];
+}
+
+// reduce nparts (z.r, r.r) pairs in a fixed order (every block gets the same sums)
+__device__ __forceinline__ void reduce_pairs_block(const double* __restrict__ part, int nparts, double* sh,
+                                                   double& a, double& b)
+{
+    a = 0.0;
+    b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += EL_BLOCK) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    block_sum2<float>(a, b, sh);
+}
+
+// rho = z.r; stop on ||r||^2 <= rtol^2 ||b||^2, the iteration limit or a
+// non-positive rho; else beta = rho / rho_old (0 on the first iteration) and
+// p = z + beta p.  Block 0 records the state and the host mirror.
+template <typename T>
+__global__ void __launch_bounds__(EL_BLOCK) k_pcg_rho(long long n, const double* __restrict__ part, int nparts,
+                                                     double* st, double* host, const T* __restrict__ z,
+                                                     T* __restrict__ p)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    __shared__ double sc[2];
+    if (st[P_DONE] != 0.0) return;
+    double zr, rr;
+    reduce_pairs_block(part, nparts, sh, zr, rr);
+    if (threadIdx.x == 0) {
+        const double its = st[P_ITS];
+        const double tol2 = its == 0.0 ? st[P_RTOL2] * rr : st[P_TOL2];
+        double done = DONE_NO;
+        if (!(std::isfinite(zr) && std::isfinite(rr))) done = DONE_NONFINITE;
+        else if (rr <= tol2) done = DONE_CONVERGED;
+        else if (its >= st[P_MAXIT]) done = DONE_MAXIT;
+        else if (!(zr > 0.0)) done = DONE_BREAKDOWN;
+        sc[0] = done;
+        sc[1] = (done == DONE_NO && its > 0.0) ? zr / st[P_RHO_OLD] : 0.0;
+        if (blockIdx.x == 0) {
+            st[P_RHO] = zr;
+            st[P_RR] = rr;
+            if (its == 0.0) {
+                st[P_TOL2] = tol2;
+                __hip_atomic_store(&host[H_GAMMA0], rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __hip_atomic_store(&host[H_GAMMA], rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host[H_ITS], its, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host[H_DONE], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (done != DONE_NO) st[P_DONE] = done;
+        }
+    }
+    __syncthreads();
+    if (sc[0] != DONE_NO) return;
+    const T beta = (T)sc[1];
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride)
+        p[i] = pfk::fmaT(beta, p[i], z[i]);
+}
+
+// alpha = rho / (p . K p) from the operator's partials (second of each pair);
+// x += alpha p, r -= alpha q
+template <typename T>
+__global__ void __launch_bounds__(EL_BLOCK) k_pcg_alpha(long long n, const double* __restrict__ part, int nparts,
+                                                       double* st, double* host, T* __restrict__ x,
+                                                       T* __restrict__ r, const T* __restrict__ p,
+                                                       const T* __restrict__ q)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    __shared__ double sc[1];
+    if (st[P_DONE] != 0.0) return;
+    double pp, pq;
+    reduce_pairs_block(part, nparts, sh, pp, pq);
+    if (threadIdx.x == 0) {
+        const bool ok = pq > 0.0 && std::isfinite(pq);
+        sc[0] = ok ? st[P_RHO] / pq : 0.0;
+        if (blockIdx.x == 0) {
+            if (ok) {
+                st[P_RHO_OLD] = st[P_RHO];
+                st[P_ITS] = st[P_ITS] + 1.0;
+                __hip_atomic_store(&host[H_ITS], st[P_ITS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            } else {
+                st[P_DONE] = std::isfinite(pq) ? (double)DONE_BREAKDOWN : (double)DONE_NONFINITE;
+                __hip_atomic_store(&host[H_DONE], st[P_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
+    __syncthreads();
+    if (sc[0] == 0.0) return;
+    const T alpha = (T)sc[0];
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride) {
+        x[i] = pfk::fmaT(alpha, p[i], x[i]);
+        r[i] = pfk::fmaT(-alpha, q[i], r[i]);
+    }
+}
+
+__global__ void k_pcg_init(double* st, double* host, double rtol2, double maxit)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int i = 0; i < S_SLOT; ++i) st[i] = 0.0;
+        st[P_RTOL2] = rtol2;
+        st[P_MAXIT] = maxit;
+        for (int i = 0; i < H_COUNT; ++i)
+            __hip_atomic_store(&host[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Power iteration for the largest eigenvalue of D^-1 K (the smoother's damping).
+// Seed: a fixed pseudo-random vector in [-1, 1) (an integer hash of the index),
+// which has a component along the oscillatory top mode.
+__global__ void __launch_bounds__(EL_BLOCK) k_el_seed(long long n, double* __restrict__ v)
+{
+    const long long stride = (long long)gridDim.x * EL_BLOCK;
+    for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride) {
+        unsigned long long z = (unsigned long long)i + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+    }
+}
+
+// One block: out[0] = ||v||, then v /= ||v||
+__global__ void __launch_bounds__(EL_BLOCK) k_el_normalize(long long n, double* __restrict__ v,
+                                                          double* __restrict__ out)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    __shared__ double nrm;
+    double a = 0.0, b = 0.0;
+    for (long long i = threadIdx.x; i < n; i += EL_BLOCK) a += v[i] * v[i];
+    block_sum2<double>(a, b, sh);
+    if (threadIdx.x == 0) {
+        nrm = std::sqrt(a);
+        out[0] = nrm;
+    }
+    __syncthreads();
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (long long i = threadIdx.x; i < n; i += EL_BLOCK) v[i] *= inv;
+}
+
+// ---------------------------------------------------------------------------
 // host side
 
 struct ApplyShape {
@@ -690,39 +1035,52 @@ ApplyShape apply_shape(const Grid& g, int slots)
     return s;
 }
 
-template <typename T, int D, bool CG>
+template <typename T, int D, int MODE>
 ApplyShape apply_shape_for(const Grid& g)
 {
-    static const int slots = resident_waves(k_el_apply<T, D, CG>);
+    static const int slots = resident_waves(k_el_apply<T, D, MODE>);
     return apply_shape(g, slots);
+}
+
+// y = K u in the given mode (see k_el_apply); b and omega for EL_RESID / EL_JACOBI
+template <typename T>
+void launch_apply_mode(int mode, const Grid& g, double lam, double mu, int ident, const T* u, T* y,
+                       const CgArgs* cg, hipStream_t st, const T* b = nullptr, double omega = 0.0)
+{
+    const T scale = (T)(g.dim == 3 ? g.h : 1.0);
+    CgArgs a = cg ? *cg : CgArgs{nullptr, nullptr};
+    auto go = [&](auto kernel, const ApplyShape& s) {
+        kernel<<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz, s.nseg, s.nwaves, a, b,
+                                              (T)omega);
+    };
+#define EL_GO(DD, MM) go(k_el_apply<T, DD, MM>, apply_shape_for<T, DD, MM>(g))
+    if (g.dim == 3) {
+        if (mode == EL_CG) EL_GO(3, EL_CG);
+        else if (mode == EL_RESID) EL_GO(3, EL_RESID);
+        else if (mode == EL_JACOBI) EL_GO(3, EL_JACOBI);
+        else if (mode == EL_JACOBI_DOT) EL_GO(3, EL_JACOBI_DOT);
+        else EL_GO(3, EL_PLAIN);
+    } else {
+        if (mode == EL_CG) EL_GO(2, EL_CG);
+        else if (mode == EL_RESID) EL_GO(2, EL_RESID);
+        else if (mode == EL_JACOBI) EL_GO(2, EL_JACOBI);
+        else if (mode == EL_JACOBI_DOT) EL_GO(2, EL_JACOBI_DOT);
+        else EL_GO(2, EL_PLAIN);
+    }
+#undef EL_GO
 }
 
 template <typename T>
 void launch_apply(const Grid& g, double lam, double mu, int ident, const T* u, T* y, const CgArgs* cg,
                   hipStream_t st)
 {
-    const T scale = (T)(g.dim == 3 ? g.h : 1.0);
-    CgArgs a = cg ? *cg : CgArgs{nullptr, nullptr};
-    auto go = [&](auto kernel, const ApplyShape& s) {
-        kernel<<<s.blocks, EL_BLOCK, 0, st>>>(g, (T)lam, (T)mu, scale, ident, u, y, s.tz, s.nseg, s.nwaves, a);
-    };
-    if (g.dim == 3) {
-        if (cg)
-            go(k_el_apply<T, 3, true>, apply_shape_for<T, 3, true>(g));
-        else
-            go(k_el_apply<T, 3, false>, apply_shape_for<T, 3, false>(g));
-    } else {
-        if (cg)
-            go(k_el_apply<T, 2, true>, apply_shape_for<T, 2, true>(g));
-        else
-            go(k_el_apply<T, 2, false>, apply_shape_for<T, 2, false>(g));
-    }
+    launch_apply_mode<T>(cg ? EL_CG : EL_PLAIN, g, lam, mu, ident, u, y, cg, st);
 }
 
 template <typename T>
 ApplyShape cg_apply_shape(const Grid& g)
 {
-    return g.dim == 3 ? apply_shape_for<T, 3, true>(g) : apply_shape_for<T, 2, true>(g);
+    return g.dim == 3 ? apply_shape_for<T, 3, EL_CG>(g) : apply_shape_for<T, 2, EL_CG>(g);
 }
 
 int stream_blocks(long long n)
@@ -733,11 +1091,20 @@ int stream_blocks(long long n)
 template <typename T>
 void launch_rhs(const Grid& g, double coef, const pf_elastic* p, T* f, hipStream_t st)
 {
-    const int blocks = (int)((g.N + EL_BLOCK - 1) / EL_BLOCK);
-    if (g.dim == 3)
-        k_el_rhs<T, 3><<<blocks, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f);
-    else
-        k_el_rhs<T, 2><<<blocks, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f);
+    int n[3];
+    n[0] = g.nx;
+    n[1] = g.dim == 3 ? g.ny : g.nz;
+    n[2] = g.dim == 3 ? g.nz : 1;
+    if (g.dim == 3) {
+        using RT = RhsTile<3>;
+        const int tx = (n[0] + RT::TX - 1) / RT::TX, ty = (n[1] + RT::TY - 1) / RT::TY,
+                  tz = (n[2] + RT::TZ - 1) / RT::TZ;
+        k_el_rhs<T, 3><<<tx * ty * tz, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f, tx, ty);
+    } else {
+        using RT = RhsTile<2>;
+        const int tx = (n[0] + RT::TX - 1) / RT::TX, ty = (n[1] + RT::TY - 1) / RT::TY;
+        k_el_rhs<T, 2><<<tx * ty, EL_BLOCK, 0, st>>>(g, coef, p->m, p->a, p->l, f, tx, ty);
+    }
 }
 
 constexpr int DOT_BLOCKS = 1024;
@@ -800,7 +1167,47 @@ int check_vec(const void* v, const pf_elastic* p, const char* name)
     return PF_OK;
 }
 
-// workspace: CG vectors r, p, s, w, then (sensitivity) lambda, g, t; partials; CG state
+constexpr int MG_MAXL = 12;
+constexpr int MG_PRE = 2, MG_POST = 2;  // damped-Jacobi sweeps (even, >= 2: results land back in x)
+constexpr int MG_COARSE = 16;           // sweeps on the coarsest grid (even)
+// Jacobi damping omega = MG_SMOOTH / lambda_max(D^-1 K).  lambda_max depends on
+// the dimension and nu only (2.0 to 3.5 in 2-D, 2.2 to 6.2 in 3-D for nu in
+// [0, 0.49]; its modes sit at the free surfaces), and a 9^d grid already has the
+// large-grid value; MG_POWER power steps from a pseudo-random start come within
+// about 1.5 %, which keeps omega lambda_max well below 2.
+constexpr double MG_SMOOTH = 1.6;
+constexpr int MG_EIG_N = 9, MG_POWER = 64;
+
+struct Levels {
+    int nl = 1;
+    Grid g[MG_MAXL];
+    long long ndof[MG_MAXL];
+};
+
+// the grid hierarchy: halve every axis while all keep an odd node count >= 3
+// (pf_tune_set(PF_TUNE_EL_MG, 1) keeps one level: plain CG)
+Levels mg_levels(const pf_elastic* p)
+{
+    Levels L;
+    L.g[0] = grid_of(p);
+    L.ndof[0] = ndof(p);
+    if (pfk::tune_el_mg() == 1) return L;
+    pf_elastic q = *p;
+    while (L.nl < MG_MAXL) {
+        bool ok = true;
+        for (int k = 0; k < p->dim; ++k) ok = ok && (q.n[k] - 1) % 2 == 0 && q.n[k] >= 5;
+        if (!ok) break;
+        for (int k = 0; k < p->dim; ++k) q.n[k] = (q.n[k] - 1) / 2 + 1;
+        q.h *= 2.0;
+        L.g[L.nl] = grid_of(&q);
+        L.ndof[L.nl] = ndof(&q);
+        ++L.nl;
+    }
+    return L;
+}
+
+// workspace: CG vectors r, p, s, w, then (sensitivity) lambda, g, t; partials; CG
+// state; multigrid: a fine temporary and (x, b, t) on every coarser level
 struct Ws {
     void* r;
     void* p;
@@ -811,6 +1218,8 @@ struct Ws {
     void* t;
     double* part;
     double* scal;
+    void* mg[MG_MAXL][3];
+    double* eig;  // power iteration: two vectors and the zero load on a 9^d grid, then a norm
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -835,6 +1244,13 @@ size_t ws_bytes(const pf_elastic* p, Ws* out, void* base)
     w.t = take(vb);
     w.part = (double*)take(sizeof(double) * 2 * EL_MAX_PARTS);
     w.scal = (double*)take(sizeof(double) * (2 * S_SLOT + 8));
+    const Levels Lv = mg_levels(p);
+    if (Lv.nl > 1) {
+        w.eig = (double*)take(sizeof(double) * (3 * 3 * MG_EIG_N * MG_EIG_N * MG_EIG_N + 8));
+        w.mg[0][2] = take(vb);
+        for (int l = 1; l < Lv.nl; ++l)
+            for (int k = 0; k < 3; ++k) w.mg[l][k] = take(align256((size_t)Lv.ndof[l] * esz(p)));
+    }
     if (out) *out = w;
     return off;
 }
@@ -929,7 +1345,7 @@ int cg_solve(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol,
         rep->iterations = (int32_t)its;
         rep->converged = done == DONE_CONVERGED;
         rep->status = (int32_t)done;
-        rep->reserved = 0;
+        rep->levels = 1;
         rep->res_norm = std::sqrt(std::max(gam, 0.0));
         rep->rhs_norm = std::sqrt(std::max(gam0, 0.0));
     }
@@ -938,6 +1354,214 @@ int cg_solve(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol,
         return pfapi::fail(PF_ENOCONV, "CG stopped after %d iterations without reaching rtol (status %d)",
                            (int)its, (int)done);
     return PF_OK;
+}
+
+template <typename T>
+void launch_restrict(const Grid& gf, const Grid& gc, const T* rf, T* rc, const double* st, hipStream_t s)
+{
+    const int nb = (int)((gc.N + EL_BLOCK - 1) / EL_BLOCK);
+    if (gf.dim == 3)
+        k_el_restrict<T, 3><<<nb, EL_BLOCK, 0, s>>>(gf, gc, rf, rc, st);
+    else
+        k_el_restrict<T, 2><<<nb, EL_BLOCK, 0, s>>>(gf, gc, rf, rc, st);
+}
+
+template <typename T>
+void launch_prolong(const Grid& gc, const Grid& gf, const T* ec, T* xf, const double* st, hipStream_t s)
+{
+    const int nb = (int)((gf.N + EL_BLOCK - 1) / EL_BLOCK);
+    if (gf.dim == 3)
+        k_el_prolong<T, 3><<<nb, EL_BLOCK, 0, s>>>(gc, gf, ec, xf, st);
+    else
+        k_el_prolong<T, 2><<<nb, EL_BLOCK, 0, s>>>(gc, gf, ec, xf, st);
+}
+
+// x = V(b) on level l (x, t: this level's vectors): pre-smoothing from x = 0
+// (its first sweep pointwise), residual, restriction, the coarser cycle,
+// prolongation, post-smoothing; the coarsest level only smooths.  The cycle is
+// a fixed symmetric operator.  part != nullptr: the last sweep also leaves the
+// partial sums of x.b and b.b there.
+template <typename T>
+void launch_jacobi0(const Grid& g, double lam, double mu, const T* b, T* y, double omega, const double* st,
+                    hipStream_t s)
+{
+    const int nb = (int)((g.N + EL_BLOCK - 1) / EL_BLOCK);
+    const T scale = (T)(g.dim == 3 ? g.h : 1.0);
+    if (g.dim == 3)
+        k_el_jacobi0<T, 3><<<nb, EL_BLOCK, 0, s>>>(g, (T)lam, (T)mu, scale, b, y, (T)omega, st);
+    else
+        k_el_jacobi0<T, 2><<<nb, EL_BLOCK, 0, s>>>(g, (T)lam, (T)mu, scale, b, y, (T)omega, st);
+}
+
+template <typename T>
+void vcycle(const Levels& Lv, int l, const T* b, T* x, T* t, const Ws& W, double lam, double mu, double omega,
+            const double* st, double* part, hipStream_t s)
+{
+    const Grid& g = Lv.g[l];
+    const CgArgs ca{nullptr, st}, cd{part, st};
+    const bool coarsest = l == Lv.nl - 1;
+    // sweeps alternate between the two vectors; an odd count moves the result
+    auto sweeps = [&](T* cur, T* oth, int m, bool dot_last) {
+        for (int i = 0; i < m; ++i) {
+            const bool dot = dot_last && i == m - 1;
+            launch_apply_mode<T>(dot ? EL_JACOBI_DOT : EL_JACOBI, g, lam, mu, 1, cur, oth, dot ? &cd : &ca, s, b,
+                                 omega);
+            std::swap(cur, oth);
+        }
+    };
+    const int pre = coarsest ? MG_COARSE : MG_PRE;  // even: x0 -> t, then an odd count back to x
+    launch_jacobi0<T>(g, lam, mu, b, t, omega, st, s);
+    sweeps(t, x, pre - 1, coarsest && part);
+    if (coarsest) return;
+    launch_apply_mode<T>(EL_RESID, g, lam, mu, 1, x, t, &ca, s, b);
+    T* xc = (T*)W.mg[l + 1][0];
+    T* bc = (T*)W.mg[l + 1][1];
+    T* tc = (T*)W.mg[l + 1][2];
+    launch_restrict<T>(g, Lv.g[l + 1], t, bc, st, s);
+    vcycle<T>(Lv, l + 1, bc, xc, tc, W, lam, mu, omega, st, nullptr, s);
+    launch_prolong<T>(Lv.g[l + 1], g, xc, x, st, s);
+    sweeps(x, t, MG_POST, part != nullptr);
+}
+
+// lambda_max(D^-1 K) for this dimension and nu: power iteration on I + D^-1 K
+// (the Jacobi-mode operator with omega = -1 and a zero load) on a 9^d grid in
+// FP64, through the same operator kernel; cached per (dim, nu) for the process.
+int jacobi_lmax(const pf_elastic* p, const Ws& W, hipStream_t st, double* out)
+{
+    static std::mutex mtx;
+    static std::map<std::pair<int, double>, double> cache;
+    const std::pair<int, double> key(p->dim, p->nu);
+    {
+        std::lock_guard<std::mutex> lk(mtx);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *out = it->second;
+            return PF_OK;
+        }
+    }
+    pf_elastic q = *p;
+    for (int k = 0; k < 3; ++k) q.n[k] = k < p->dim ? MG_EIG_N : 1;
+    q.h = 1.0;
+    q.dtype = PF_F64;
+    const Grid g = grid_of(&q);
+    double lam, mu;
+    lame(&q, &lam, &mu);
+    const long long n = ndof(&q);
+    double* v = W.eig;
+    double* w = v + n;
+    double* zero = w + n;
+    double* nrm = zero + n;
+    k_el_seed<<<1, EL_BLOCK, 0, st>>>(n, v);
+    k_el_fill<double><<<1, EL_BLOCK, 0, st>>>(n, zero, nullptr);
+    k_el_normalize<<<1, EL_BLOCK, 0, st>>>(n, v, nrm);
+    for (int i = 0; i < MG_POWER; ++i) {
+        launch_apply_mode<double>(EL_JACOBI, g, lam, mu, 1, v, w, nullptr, st, zero, -1.0);
+        k_el_normalize<<<1, EL_BLOCK, 0, st>>>(n, w, nrm);
+        std::swap(v, w);
+    }
+    double h = 0.0;
+    if (hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return pfapi::check_launch("smoother eigenvalue estimate");
+    const double lmax = h - 1.0;
+    if (!(std::isfinite(lmax) && lmax > 0.5))
+        return pfapi::fail(PF_ENONFINITE, "smoother eigenvalue estimate failed (%g)", lmax);
+    std::lock_guard<std::mutex> lk(mtx);
+    cache[key] = lmax;
+    *out = lmax;
+    return PF_OK;
+}
+
+// Preconditioned CG (multigrid V-cycle) on K x = b (b already in W.r); x is
+// overwritten.  Per iteration: z = V(r) (its last sweep also sums z.r and
+// ||r||^2 for the stop test); p = z + beta p; q = K p with p.q; x += alpha p,
+// r -= alpha q.  Scalars
+// stay on the device; the host polls a pinned mirror.  Host-synchronous.
+template <typename T>
+int pcg_solve(const pf_elastic* p, const Levels& Lv, T* x, const Ws& W, double rtol, int maxit,
+              pf_el_report* rep, hipStream_t st)
+{
+    double lam, mu;
+    lame(p, &lam, &mu);
+    HostMirror* hm = nullptr;
+    if (int rc = host_mirror(&hm)) return rc;
+    const Grid& g = Lv.g[0];
+    const long long n = Lv.ndof[0];
+    const int sb = stream_blocks(n);
+    double* S = W.scal;
+    double lmax = 0.0;
+    if (int rc = jacobi_lmax(p, W, st, &lmax)) return rc;
+    const double omega = MG_SMOOTH / lmax;
+    k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, x, nullptr);
+    k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, (T*)W.p, nullptr);
+    k_pcg_init<<<1, 64, 0, st>>>(S, hm->dev, rtol * rtol, (double)maxit);
+    if (int rc = pfapi::check_launch("PCG setup")) return rc;
+    const ApplyShape shp = cg_apply_shape<T>(g);
+    const int jparts = g.dim == 3 ? apply_shape_for<T, 3, EL_JACOBI_DOT>(g).blocks
+                                  : apply_shape_for<T, 2, EL_JACOBI_DOT>(g).blocks;
+    if (shp.blocks > EL_MAX_PARTS || jparts > EL_MAX_PARTS)
+        return pfapi::fail(PF_EINVAL, "grid too large for the CG reduction");
+    const int db = std::min(sb, 1024);
+    // one iteration per poll: the host enqueues iteration k + 1 while k runs and
+    // reads k - 1's state, so at most one iteration is enqueued past convergence
+    const int batch = 1;
+    int enq = 0, slot = 0;
+    bool pending = false;
+    double done = 0.0;
+    for (;;) {
+        const int nb = std::min(batch, maxit + 1 - enq);
+        for (int i = 0; i < nb; ++i) {
+            vcycle<T>(Lv, 0, (const T*)W.r, (T*)W.s, (T*)W.mg[0][2], W, lam, mu, omega, S, W.part, st);
+            k_pcg_rho<T><<<db, EL_BLOCK, 0, st>>>(n, W.part, jparts, S, hm->dev, (const T*)W.s, (T*)W.p);
+            const CgArgs cg{W.part, S};
+            launch_apply<T>(g, lam, mu, 1, (const T*)W.p, (T*)W.w, &cg, st);
+            k_pcg_alpha<T><<<db, EL_BLOCK, 0, st>>>(n, W.part, shp.blocks, S, hm->dev, x, (T*)W.r,
+                                                   (const T*)W.p, (const T*)W.w);
+        }
+        enq += nb;
+        if (int rc = pfapi::check_launch("PCG iteration")) return rc;
+        if (hipEventRecord(hm->ev[slot], st) != hipSuccess) return pfapi::check_launch("PCG event");
+        if (pending) {
+            if (hipEventSynchronize(hm->ev[slot ^ 1]) != hipSuccess) return pfapi::check_launch("PCG wait");
+            done = *(volatile double*)&hm->host[H_DONE];
+            if (done != 0.0) break;
+        }
+        pending = true;
+        slot ^= 1;
+        if (enq > maxit) {
+            if (hipEventSynchronize(hm->ev[slot ^ 1]) != hipSuccess) return pfapi::check_launch("PCG wait");
+            break;
+        }
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return pfapi::check_launch("PCG sync");
+    done = *(volatile double*)&hm->host[H_DONE];
+    const double its = *(volatile double*)&hm->host[H_ITS];
+    const double gam = *(volatile double*)&hm->host[H_GAMMA];
+    const double gam0 = *(volatile double*)&hm->host[H_GAMMA0];
+    if (rep) {
+        rep->iterations = (int32_t)its;
+        rep->converged = done == DONE_CONVERGED;
+        rep->status = (int32_t)done;
+        rep->levels = Lv.nl;
+        rep->res_norm = std::sqrt(std::max(gam, 0.0));
+        rep->rhs_norm = std::sqrt(std::max(gam0, 0.0));
+    }
+    if (done == DONE_NONFINITE) return pfapi::fail(PF_ENONFINITE, "PCG met a non-finite value");
+    if (done != DONE_CONVERGED)
+        return pfapi::fail(PF_ENOCONV, "PCG stopped after %d iterations without reaching rtol (status %d)",
+                           (int)its, (int)done);
+    return PF_OK;
+}
+
+// the solver for K x = b (b in W.r): multigrid-preconditioned CG when the grid
+// coarsens, else plain CG
+template <typename T>
+int el_solve_any(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit,
+                 pf_el_report* rep, hipStream_t st)
+{
+    const Levels Lv = mg_levels(p);
+    if (Lv.nl > 1) return pcg_solve<T>(p, Lv, x, W, rtol, maxit, rep, st);
+    return cg_solve<T>(p, g, x, W, rtol, maxit, rep, st);
 }
 
 template <typename T>
@@ -952,7 +1576,7 @@ int solve_t(const pf_elastic* p, const void* b, void* u, double rtol, int maxit,
         k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)b);
     else
         launch_rhs<T>(g, p->dim * lam + 2.0 * mu, p, (T*)W.r, st);
-    return cg_solve<T>(p, g, (T*)u, W, rtol, maxit, rep, st);
+    return el_solve_any<T>(p, g, (T*)u, W, rtol, maxit, rep, st);
 }
 
 // Sensitivities of O = g . u with respect to (E, nu) at the equilibrium u:
@@ -973,7 +1597,7 @@ int sensitivity_t(const pf_elastic* p, const void* gw, const void* u, double* ou
         k_el_weights<T, 2><<<bl, EL_BLOCK, 0, st>>>(g, (const T*)gw, (T*)W.g);
     k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)W.g);
     if (int rc = pfapi::check_launch("adjoint set-up")) return rc;
-    if (int rc = cg_solve<T>(p, g, (T*)W.lam, W, rtol, maxit, rep, st)) return rc;
+    if (int rc = el_solve_any<T>(p, g, (T*)W.lam, W, rtol, maxit, rep, st)) return rc;
     double* dots = W.scal + 2 * S_SLOT;  // 4 device doubles after the CG state
     double* part = W.part;
     launch_dot<T>(g, (const T*)W.g, (const T*)u, part, dots + 0, st);

@@ -68,7 +68,8 @@ void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, dou
                 int acc = 0);
 // z-planes per block of launch_jvp3d set by pf_tune_set (0: automatic)
 int tune_jvp3d_planes();
-int tune_el_planes();
+int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = automatic)
+int tune_el_mg();      // 1: plain CG for the elasticity solves
 
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel

@@ -14,6 +14,7 @@ std::atomic<int> g_depth_override{0};
 std::atomic<int> g_fuse_override{0};
 std::atomic<int> g_jvp3d_planes{0};
 std::atomic<int> g_el_planes{0};
+std::atomic<int> g_el_mg{0};
 int g_simds = -1;
 std::mutex g_mu;
 
@@ -80,6 +81,7 @@ int stream2d_depth(const pf_problem* p)
 namespace pfk {
 int tune_jvp3d_planes() { return pfapi::g_jvp3d_planes.load(); }
 int tune_el_planes() { return pfapi::g_el_planes.load(); }
+int tune_el_mg() { return pfapi::g_el_mg.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -97,6 +99,8 @@ int pf_tune_set(int key, int value)
         g_jvp3d_planes.store(value);
     else if (key == PF_TUNE_EL_PLANES)
         g_el_planes.store(value);
+    else if (key == PF_TUNE_EL_MG)
+        g_el_mg.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -124,6 +128,8 @@ int pf_tune_get(int key, int* value)
         *value = g_jvp3d_planes.load();
     else if (key == PF_TUNE_EL_PLANES)
         *value = g_el_planes.load();
+    else if (key == PF_TUNE_EL_MG)
+        *value = g_el_mg.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

@@ -24,10 +24,11 @@ class pf_elastic(ct.Structure):
 
 class pf_el_report(ct.Structure):
     _fields_ = [("iterations", ct.c_int32), ("converged", ct.c_int32), ("status", ct.c_int32),
-                ("reserved", ct.c_int32), ("res_norm", ct.c_double), ("rhs_norm", ct.c_double)]
+                ("levels", ct.c_int32), ("res_norm", ct.c_double), ("rhs_norm", ct.c_double)]
 
 
 TUNE_EL_PLANES = 4
+TUNE_EL_MG = 5  # 1: plain CG (no multigrid)
 _L = None
 
 
