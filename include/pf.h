@@ -395,11 +395,11 @@ int pf_el_rhs(const pf_elastic* p, void* f, void* stream);
  * axis has an odd node count of at least 5, the CG is preconditioned by a
  * geometric multigrid V-cycle: the grid halves while that holds (rep->levels
  * grids), Q1 rediscretised at 2h, trilinear transfers, two damped-Jacobi sweeps
- * before and after and sixteen on the coarsest grid, damping 1.6 / lambda_max
- * of D^-1 K.  lambda_max depends on dim and nu only; the first solve of a
- * (dim, nu) pair in the process estimates it by power iteration on a 9^d grid
- * (about a millisecond).  Other grids, or pf_tune_set(PF_TUNE_EL_MG, 1), use
- * plain CG.  The fixed components are identity rows of K (u there matches b to
+ * before and after and 2 x (longest axis) on the coarsest grid (4 to 32),
+ * damping 1.6 / lambda_max of D^-1 K.  lambda_max depends on dim and nu
+ * only; the first solve of a (dim, nu) pair in the process estimates it by
+ * power iteration on a 9^d grid (about a millisecond).  Other grids, or
+ * pf_tune_set(PF_TUNE_EL_MG, 1), use plain CG.  The fixed components are identity rows of K (u there matches b to
  * the tolerance).  Host-synchronous; returns PF_OK, PF_ENOCONV (u holds the
  * last iterate) or PF_ENONFINITE; rep may be NULL. */
 int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,

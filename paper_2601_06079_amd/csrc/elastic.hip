@@ -639,6 +639,30 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_rhs(Grid g, double coef, double
     for (int c = 0; c < D; ++c) f[c * g.N + i] = idx[c] == 0 ? T(0) : (T)acc[c];
 }
 
+// Coordinates on the problem axes (n[0] fastest) of node i; 32-bit division when
+// the grid has fewer than 2^32 nodes (64-bit division is a long instruction
+// sequence on the GPU).
+template <int D>
+__device__ __forceinline__ void node_coords(long long i, const int* n, long long N, int* idx)
+{
+    if (N <= 0xffffffffll) {
+        const unsigned u = (unsigned)i, q = u / (unsigned)n[0];
+        idx[0] = (int)(u - q * (unsigned)n[0]);
+        if (D == 3) {
+            const unsigned q2 = q / (unsigned)n[1];
+            idx[1] = (int)(q - q2 * (unsigned)n[1]);
+            idx[2] = (int)q2;
+        } else {
+            idx[1] = (int)q;
+            idx[2] = 0;
+        }
+    } else {
+        idx[0] = (int)(i % n[0]);
+        idx[1] = (int)((i / n[0]) % n[1]);
+        idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    }
+}
+
 // volume-change weights: integral of d_i phi_a over the body, i.e. the outward
 // face normal times the face share of the node (nonzero on the far faces only)
 template <int D>
@@ -665,9 +689,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_dot(Grid g, const T* __restrict
     const long long stride = (long long)gridDim.x * EL_BLOCK;
     for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < g.N; i += stride) {
         int idx[3];
-        idx[0] = (int)(i % n[0]);
-        idx[1] = (int)((i / n[0]) % n[1]);
-        idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+        node_coords<D>(i, n, g.N, idx);
         for (int c = 0; c < D; ++c) {
             const double wc = gw ? (double)gw[c * g.N + i] : vol_weight<D>(idx, n, c, g.h);
             acc += wc * (double)u[c * g.N + i];
@@ -719,9 +741,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_weights(Grid g, const T* __rest
     n[0] = g.nx;
     n[1] = D == 3 ? g.ny : g.nz;
     n[2] = D == 3 ? g.nz : 1;
-    idx[0] = (int)(i % n[0]);
-    idx[1] = (int)((i / n[0]) % n[1]);
-    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    node_coords<D>(i, n, g.N, idx);
     for (int c = 0; c < D; ++c) {
         const long long o = c * g.N + i;
         dst[o] = idx[c] == 0 ? T(0) : (src ? src[o] : (T)vol_weight<D>(idx, n, c, g.h));
@@ -760,9 +780,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_jacobi0(Grid g, T lam, T mu, T 
     if (i >= g.N) return;
     int n[3], idx[3];
     prob_axes<D>(g, n);
-    idx[0] = (int)(i % n[0]);
-    idx[1] = (int)((i / n[0]) % n[1]);
-    idx[2] = D == 3 ? (int)(i / ((long long)n[0] * n[1])) : 0;
+    node_coords<D>(i, n, g.N, idx);
     T mc[3], ac[3];
     for (int k = 0; k < D; ++k) {
         const Fac<T> f = fac<T>(idx[k] > 0, idx[k] < n[k] - 1);
@@ -797,9 +815,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_restrict(Grid gf, Grid gc, cons
     int nc[3], nf[3], ic[3];
     prob_axes<D>(gc, nc);
     prob_axes<D>(gf, nf);
-    ic[0] = (int)(I % nc[0]);
-    ic[1] = (int)((I / nc[0]) % nc[1]);
-    ic[2] = D == 3 ? (int)(I / ((long long)nc[0] * nc[1])) : 0;
+    node_coords<D>(I, nc, gc.N, ic);
     T acc[3] = {T(0), T(0), T(0)};
     for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz)
         for (int oy = -1; oy <= 1; ++oy)
@@ -824,9 +840,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_prolong(Grid gc, Grid gf, const
     int nc[3], nf[3], f[3];
     prob_axes<D>(gc, nc);
     prob_axes<D>(gf, nf);
-    f[0] = (int)(F % nf[0]);
-    f[1] = (int)((F / nf[0]) % nf[1]);
-    f[2] = D == 3 ? (int)(F / ((long long)nf[0] * nf[1])) : 0;
+    node_coords<D>(F, nf, gf.N, f);
     int lo[3], hi[3];
     for (int k = 0; k < 3; ++k) {
         lo[k] = f[k] >> 1;
@@ -905,12 +919,12 @@ __global__ void __launch_bounds__(EL_BLOCK) k_pcg_rho(long long n, const double*
 }
 
 // alpha = rho / (p . K p) from the operator's partials (second of each pair);
-// x += alpha p, r -= alpha q
+// x += alpha p, r -= alpha q, and per-block partial sums of the new r.r (rpart)
 template <typename T>
 __global__ void __launch_bounds__(EL_BLOCK) k_pcg_alpha(long long n, const double* __restrict__ part, int nparts,
                                                        double* st, double* host, T* __restrict__ x,
                                                        T* __restrict__ r, const T* __restrict__ p,
-                                                       const T* __restrict__ q)
+                                                       const T* __restrict__ q, double* __restrict__ rpart)
 {
     __shared__ double sh[2 * EL_WAVES];
     __shared__ double sc[1];
@@ -935,9 +949,40 @@ __global__ void __launch_bounds__(EL_BLOCK) k_pcg_alpha(long long n, const doubl
     if (sc[0] == 0.0) return;
     const T alpha = (T)sc[0];
     const long long stride = (long long)gridDim.x * EL_BLOCK;
+    double rr = 0.0, dummy = 0.0;
     for (long long i = blockIdx.x * (long long)EL_BLOCK + threadIdx.x; i < n; i += stride) {
         x[i] = pfk::fmaT(alpha, p[i], x[i]);
-        r[i] = pfk::fmaT(-alpha, q[i], r[i]);
+        const T rv = pfk::fmaT(-alpha, q[i], r[i]);
+        r[i] = rv;
+        rr += (double)rv * rv;
+    }
+    __syncthreads();  // sh is reused
+    block_sum2<T>(rr, dummy, sh);
+    if (threadIdx.x == 0) rpart[blockIdx.x] = rr;
+}
+
+// The stop test on the updated residual, before the next V-cycle: one block
+// reduces k_pcg_alpha's partials; ||r||^2 <= rtol^2 ||b||^2, a non-finite value or
+// the iteration limit end the solve (every later launch then returns at once).
+__global__ void __launch_bounds__(EL_BLOCK) k_pcg_check(const double* __restrict__ rpart, int nparts, double* st,
+                                                       double* host)
+{
+    __shared__ double sh[2 * EL_WAVES];
+    if (st[P_DONE] != 0.0) return;
+    double rr = 0.0, dummy = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += EL_BLOCK) rr += rpart[i];
+    block_sum2<float>(rr, dummy, sh);
+    if (threadIdx.x == 0) {
+        double done = DONE_NO;
+        if (!std::isfinite(rr)) done = DONE_NONFINITE;
+        else if (rr <= st[P_TOL2]) done = DONE_CONVERGED;
+        else if (st[P_ITS] >= st[P_MAXIT]) done = DONE_MAXIT;
+        st[P_RR] = rr;
+        __hip_atomic_store(&host[H_GAMMA], rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (done != DONE_NO) {
+            st[P_DONE] = done;
+            __hip_atomic_store(&host[H_DONE], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -1169,7 +1214,8 @@ int check_vec(const void* v, const pf_elastic* p, const char* name)
 
 constexpr int MG_MAXL = 12;
 constexpr int MG_PRE = 2, MG_POST = 2;  // damped-Jacobi sweeps (even, >= 2: results land back in x)
-constexpr int MG_COARSE = 16;           // sweeps on the coarsest grid (even)
+// sweeps on the coarsest grid: twice its longest axis (even), within [4, 32]
+constexpr int MG_COARSE_MIN = 4, MG_COARSE_MAX = 32;
 // Jacobi damping omega = MG_SMOOTH / lambda_max(D^-1 K).  lambda_max depends on
 // the dimension and nu only (2.0 to 3.5 in 2-D, 2.2 to 6.2 in 3-D for nu in
 // [0, 0.49]; its modes sit at the free surfaces), and a 9^d grid already has the
@@ -1180,6 +1226,7 @@ constexpr int MG_EIG_N = 9, MG_POWER = 64;
 
 struct Levels {
     int nl = 1;
+    int coarse_sweeps = MG_COARSE_MIN;
     Grid g[MG_MAXL];
     long long ndof[MG_MAXL];
 };
@@ -1203,6 +1250,9 @@ Levels mg_levels(const pf_elastic* p)
         L.ndof[L.nl] = ndof(&q);
         ++L.nl;
     }
+    long long longest = 0;
+    for (int k = 0; k < p->dim; ++k) longest = std::max<long long>(longest, q.n[k]);
+    L.coarse_sweeps = (int)std::min<long long>(MG_COARSE_MAX, std::max<long long>(MG_COARSE_MIN, 2 * longest));
     return L;
 }
 
@@ -1218,6 +1268,7 @@ struct Ws {
     void* t;
     double* part;
     double* scal;
+    double* rpart;  // k_pcg_alpha's r.r partials
     void* mg[MG_MAXL][3];
     double* eig;  // power iteration: two vectors and the zero load on a 9^d grid, then a norm
 };
@@ -1247,6 +1298,7 @@ size_t ws_bytes(const pf_elastic* p, Ws* out, void* base)
     const Levels Lv = mg_levels(p);
     if (Lv.nl > 1) {
         w.eig = (double*)take(sizeof(double) * (3 * 3 * MG_EIG_N * MG_EIG_N * MG_EIG_N + 8));
+        w.rpart = (double*)take(sizeof(double) * EL_MAX_PARTS);
         w.mg[0][2] = take(vb);
         for (int l = 1; l < Lv.nl; ++l)
             for (int k = 0; k < 3; ++k) w.mg[l][k] = take(align256((size_t)Lv.ndof[l] * esz(p)));
@@ -1409,7 +1461,7 @@ void vcycle(const Levels& Lv, int l, const T* b, T* x, T* t, const Ws& W, double
             std::swap(cur, oth);
         }
     };
-    const int pre = coarsest ? MG_COARSE : MG_PRE;  // even: x0 -> t, then an odd count back to x
+    const int pre = coarsest ? Lv.coarse_sweeps : MG_PRE;  // even: x0 -> t, then an odd count back to x
     launch_jacobi0<T>(g, lam, mu, b, t, omega, st, s);
     sweeps(t, x, pre - 1, coarsest && part);
     if (coarsest) return;
@@ -1516,7 +1568,8 @@ int pcg_solve(const pf_elastic* p, const Levels& Lv, T* x, const Ws& W, double r
             const CgArgs cg{W.part, S};
             launch_apply<T>(g, lam, mu, 1, (const T*)W.p, (T*)W.w, &cg, st);
             k_pcg_alpha<T><<<db, EL_BLOCK, 0, st>>>(n, W.part, shp.blocks, S, hm->dev, x, (T*)W.r,
-                                                   (const T*)W.p, (const T*)W.w);
+                                                   (const T*)W.p, (const T*)W.w, W.rpart);
+            k_pcg_check<<<1, EL_BLOCK, 0, st>>>(W.rpart, db, S, hm->dev);
         }
         enq += nb;
         if (int rc = pfapi::check_launch("PCG iteration")) return rc;
