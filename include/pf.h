@@ -133,7 +133,11 @@ int pf_version(void);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
  *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product;
  *   PF_TUNE_EL_PLANES:      z-planes (2-D: rows) per wave of the elasticity operator;
- *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid). */
+ *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid);
+ *                           2 = multigrid with every level launched separately;
+ *                           v >= 3 = the multigrid's coarse grids of at most v
+ *                           nodes run in one workgroup (default: 1200 in 2-D,
+ *                           none in 3-D). */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
        PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5 };
 int pf_tune_set(int key, int value);

@@ -756,6 +756,18 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_weights(Grid g, const T* __rest
 // spacing.  Restriction is the transpose of the trilinear prolongation; the
 // symmetry-plane components stay fixed (zero) on every level.
 
+constexpr int MG_MAXL = 12;
+constexpr int MG_PRE = 2, MG_POST = 2;  // damped-Jacobi sweeps (even, >= 2: results land back in x)
+// sweeps on the coarsest grid: twice its longest axis (even), within [4, 32]
+constexpr int MG_COARSE_MIN = 4, MG_COARSE_MAX = 32;
+// Jacobi damping omega = MG_SMOOTH / lambda_max(D^-1 K).  lambda_max depends on
+// the dimension and nu only (2.0 to 3.5 in 2-D, 2.2 to 6.2 in 3-D for nu in
+// [0, 0.49]; its modes sit at the free surfaces), and a 9^d grid already has the
+// large-grid value; MG_POWER power steps from a pseudo-random start come within
+// about 1.5 %, which keeps omega lambda_max well below 2.
+constexpr double MG_SMOOTH = 1.6;
+constexpr int MG_EIG_N = 9, MG_POWER = 64;
+
 // PCG state (FP64, one slot; the done flag sits where k_el_apply looks for it)
 enum { P_RHO = 0, P_RHO_OLD = 1, P_TOL2 = 2, P_ITS = 3, P_DONE = 4, P_MAXIT = 5, P_RR = 6, P_RTOL2 = 7 };
 static_assert(P_DONE == S_DONE, "the operator's early exit reads the same done flag");
@@ -1031,6 +1043,241 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_normalize(long long n, double* 
 }
 
 // ---------------------------------------------------------------------------
+// The coarse end of the V-cycle in one workgroup.  On the smallest grids every
+// launch costs its fixed dispatch latency (3-5 us) for almost no work, so the
+// levels from a few hundred nodes down run inside one 1024-thread block with
+// all their vectors (x, b, t per level) in LDS: the same smoothing, residual,
+// transfer and coarsest-grid steps as the multi-launch cycle, with the operator
+// assembled per node from the same 1-D operators.
+
+constexpr int MG_BOTTOM_MAXL = 8;
+constexpr int MG_BOTTOM_THREADS = 1024;
+// nodes per level at most.  Measured: in 2-D the block with grids up to 33^2
+// makes a 1025^2 solve 1.3x faster (2.33 vs 3.04 ms) and a 257^2 one 1.5x; in
+// 3-D one block is slower than the launches it replaces (a 9^3 pass has 27
+// neighbours x 3 x 3 couplings per node on one CU), so 3-D keeps every launch.
+constexpr long long MG_BOTTOM_NODES_3D = 0, MG_BOTTOM_NODES_2D = 1200;
+constexpr size_t MG_BOTTOM_LDS = 48 * 1024;       // bytes of LDS for all its vectors
+
+template <typename T>
+struct BottomArgs {
+    int nl;             // levels run in the block (the first is the entry level)
+    int coarse_sweeps;  // smoothing sweeps on the coarsest level
+    int n[MG_BOTTOM_MAXL][3];
+    int N[MG_BOTTOM_MAXL];
+    int off[MG_BOTTOM_MAXL];  // LDS offset (elements) of the level's x; b and t follow
+    T scale[MG_BOTTOM_MAXL];  // the operator's row scale (h in 3-D, 1 in 2-D)
+    T lam, mu, omega;
+};
+
+// (K u) at node idx on one level, all D components, and the diagonal of K there;
+// K_cd(o) = lam P_cd + mu P_dc + mu delta_cd sum_k P_kk, each P a product of 1-D
+// operators (A on the differentiated axis, R / C on the two axes of a mixed
+// term, M elsewhere).  Fixed components: identity rows, masked columns.
+template <typename T, int D>
+__device__ void bottom_ku(const T* __restrict__ u, int N, const int* n, const int* idx, T lam, T mu, T scale,
+                          T* ku, T* dg)
+{
+    Fac<T> F[3];
+    for (int k = 0; k < D; ++k) F[k] = fac<T>(idx[k] > 0, idx[k] < n[k] - 1);
+    const T lm2 = lam + T(2) * mu;
+    T acc[3] = {T(0), T(0), T(0)};
+    const int i = idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
+    constexpr int NO = D == 3 ? 27 : 9;
+    for (int oi = 0; oi < NO; ++oi) {
+        const int o[3] = {oi % 3, (oi / 3) % 3, D == 3 ? oi / 9 : 1};
+        int nb[3] = {0, 0, 0};
+        bool inside = true;
+        for (int k = 0; k < D; ++k) {
+            nb[k] = idx[k] + o[k] - 1;
+            inside = inside && nb[k] >= 0 && nb[k] < n[k];
+        }
+        if (!inside) continue;  // the 1-D weights towards a missing neighbour are zero
+        // (selects rather than indexing by o: keeps the factors in registers)
+        auto pick = [](const T* w, int j) { return j == 0 ? w[0] : (j == 1 ? w[1] : w[2]); };
+        T m[3], a[3], r[3], c[3];
+        for (int k = 0; k < D; ++k) {
+            m[k] = pick(F[k].m, o[k]);
+            a[k] = pick(F[k].a, o[k]);
+            r[k] = pick(F[k].r, o[k]);
+            c[k] = pick(F[k].c, o[k]);
+        }
+        T pkk[3], sp = T(0);
+        for (int k = 0; k < D; ++k) {
+            T v = a[k];
+            for (int j = 0; j < D; ++j)
+                if (j != k) v *= m[j];
+            pkk[k] = v;
+            sp += v;
+        }
+        const int nbi = nb[0] + n[0] * (nb[1] + n[1] * nb[2]);
+        for (int cc = 0; cc < D; ++cc) {
+            for (int d = 0; d < D; ++d) {
+                if (nb[d] == 0) continue;  // the neighbour's component d is fixed (masked)
+                T coef;
+                if (cc == d) {
+                    coef = lm2 * pkk[cc] + mu * (sp - pkk[cc]);
+                } else {
+                    T rest = T(1);
+                    for (int j = 0; j < D; ++j)
+                        if (j != cc && j != d) rest *= m[j];
+                    coef = (lam * (r[cc] * c[d]) + mu * (r[d] * c[cc])) * rest;
+                }
+                acc[cc] += coef * u[d * N + nbi];
+            }
+            if (oi == NO / 2) dg[cc] = (lm2 * pkk[cc] + mu * (sp - pkk[cc])) * scale;
+        }
+    }
+    for (int cc = 0; cc < D; ++cc) {
+        const bool fixed = idx[cc] == 0;
+        ku[cc] = fixed ? u[cc * N + i] : acc[cc] * scale;
+        if (fixed) dg[cc] = T(1);
+    }
+}
+
+// the diagonal of K at node idx (1 on fixed components)
+template <typename T, int D>
+__device__ void bottom_dg(const int* n, const int* idx, T lam, T mu, T scale, T* dg)
+{
+    T mc[3], ac[3];
+    for (int k = 0; k < D; ++k) {
+        const Fac<T> f = fac<T>(idx[k] > 0, idx[k] < n[k] - 1);
+        mc[k] = f.m[1];
+        ac[k] = f.a[1];
+    }
+    const T lm2 = lam + T(2) * mu;
+    T pkk[3], sp = T(0);
+    for (int k = 0; k < D; ++k) {
+        T v = ac[k];
+        for (int j = 0; j < D; ++j)
+            if (j != k) v *= mc[j];
+        pkk[k] = v;
+        sp += v;
+    }
+    for (int c = 0; c < D; ++c) dg[c] = idx[c] == 0 ? T(1) : (lm2 * pkk[c] + mu * (sp - pkk[c])) * scale;
+}
+
+template <int D>
+__device__ __forceinline__ void bottom_coords(int i, const int* n, int* idx)
+{
+    idx[0] = i % n[0];
+    idx[1] = (i / n[0]) % n[1];
+    idx[2] = D == 3 ? i / (n[0] * n[1]) : 0;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(MG_BOTTOM_THREADS) k_el_bottom(BottomArgs<T> a, const T* __restrict__ bin,
+                                                                T* __restrict__ xout, const double* __restrict__ st)
+{
+    if (st && st[P_DONE] != 0.0) return;
+    extern __shared__ double bottom_smem[];
+    T* lds = reinterpret_cast<T*>(bottom_smem);
+    const int tid = threadIdx.x;
+    auto X = [&](int l) { return lds + a.off[l]; };
+    auto B = [&](int l) { return lds + a.off[l] + D * a.N[l]; };
+    auto Tt = [&](int l) { return lds + a.off[l] + 2 * D * a.N[l]; };
+    for (int i = tid; i < D * a.N[0]; i += MG_BOTTOM_THREADS) B(0)[i] = bin[i];
+    __syncthreads();
+    // y = u + omega D^-1 (b - K u) on level l (from_zero: y = omega D^-1 b);
+    // resid: y = b - K u
+    auto pass = [&](int l, const T* u, T* y, bool from_zero, bool resid) {
+        const T* b = B(l);
+        const int N = a.N[l];
+        for (int i = tid; i < N; i += MG_BOTTOM_THREADS) {
+            int idx[3];
+            bottom_coords<D>(i, a.n[l], idx);
+            T ku[3] = {T(0), T(0), T(0)}, dg[3] = {T(1), T(1), T(1)};
+            if (from_zero)
+                bottom_dg<T, D>(a.n[l], idx, a.lam, a.mu, a.scale[l], dg);
+            else
+                bottom_ku<T, D>(u, N, a.n[l], idx, a.lam, a.mu, a.scale[l], ku, dg);
+            for (int c = 0; c < D; ++c) {
+                const int o = c * N + i;
+                if (resid) y[o] = b[o] - ku[c];
+                else if (from_zero) y[o] = a.omega * b[o] / dg[c];
+                else y[o] = u[o] + a.omega * (b[o] - ku[c]) / dg[c];
+            }
+        }
+        __syncthreads();
+    };
+    // bit l of cur: which of (x, t) holds level l's iterate (1 = t)
+    unsigned cur = 0;
+    for (int l = 0; l < a.nl; ++l) {
+        const bool coarsest = l == a.nl - 1;
+        const int pre = coarsest ? a.coarse_sweeps : MG_PRE;
+        T* v[2] = {X(l), Tt(l)};
+        int c = 0;
+        pass(l, nullptr, v[c], true, false);
+        for (int s = 1; s < pre; ++s) {
+            pass(l, v[c], v[c ^ 1], false, false);
+            c ^= 1;
+        }
+        cur |= (unsigned)c << l;
+        if (coarsest) break;
+        // residual into the other vector, restricted into the next level's b
+        pass(l, v[c], v[c ^ 1], false, true);
+        const T* rf = v[c ^ 1];
+        T* rc = B(l + 1);
+        const int Nc = a.N[l + 1], Nf = a.N[l];
+        for (int I = tid; I < Nc; I += MG_BOTTOM_THREADS) {
+            int ic[3];
+            bottom_coords<D>(I, a.n[l + 1], ic);
+            T acc[3] = {T(0), T(0), T(0)};
+            for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz)
+                for (int oy = -1; oy <= 1; ++oy)
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int fx = 2 * ic[0] + ox, fy = 2 * ic[1] + oy, fz = 2 * ic[2] + oz;
+                        if (fx < 0 || fx >= a.n[l][0] || fy < 0 || fy >= a.n[l][1] || fz < 0 ||
+                            fz >= (D == 3 ? a.n[l][2] : 1))
+                            continue;
+                        const T w = (ox ? T(0.5) : T(1)) * (oy ? T(0.5) : T(1)) * (oz ? T(0.5) : T(1));
+                        const int fi = fx + a.n[l][0] * (fy + a.n[l][1] * fz);
+                        for (int cc = 0; cc < D; ++cc) acc[cc] += w * rf[cc * Nf + fi];
+                    }
+            for (int cc = 0; cc < D; ++cc) rc[cc * Nc + I] = ic[cc] == 0 ? T(0) : acc[cc];
+        }
+        __syncthreads();
+    }
+    for (int l = a.nl - 2; l >= 0; --l) {
+        T* v[2] = {X(l), Tt(l)};
+        int c = (cur >> l) & 1;
+        // prolongation of the coarser level's iterate into this level's
+        const T* ec = ((cur >> (l + 1)) & 1) ? Tt(l + 1) : X(l + 1);
+        const int Nc = a.N[l + 1], Nf = a.N[l];
+        for (int F = tid; F < Nf; F += MG_BOTTOM_THREADS) {
+            int f[3];
+            bottom_coords<D>(F, a.n[l], f);
+            int lo[3], hi[3];
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = f[k] >> 1;
+                hi[k] = (f[k] & 1) ? lo[k] + 1 : lo[k];
+            }
+            T acc[3] = {T(0), T(0), T(0)};
+            for (int bz = 0; bz < (D == 3 ? 2 : 1); ++bz)
+                for (int by = 0; by < 2; ++by)
+                    for (int bx = 0; bx < 2; ++bx) {
+                        const T w = ((f[0] & 1) ? T(0.5) : (bx ? T(0) : T(1))) *
+                                    ((f[1] & 1) ? T(0.5) : (by ? T(0) : T(1))) *
+                                    (D == 3 ? ((f[2] & 1) ? T(0.5) : (bz ? T(0) : T(1))) : T(1));
+                        if (w == T(0)) continue;
+                        const int cx = bx ? hi[0] : lo[0], cy = by ? hi[1] : lo[1], cz = bz ? hi[2] : lo[2];
+                        const int ci = cx + a.n[l + 1][0] * (cy + a.n[l + 1][1] * cz);
+                        for (int cc = 0; cc < D; ++cc) acc[cc] += w * ec[cc * Nc + ci];
+                    }
+            for (int cc = 0; cc < D; ++cc) v[c][cc * Nf + F] += acc[cc];
+        }
+        __syncthreads();
+        for (int s = 0; s < MG_POST; ++s) {
+            pass(l, v[c], v[c ^ 1], false, false);
+            c ^= 1;
+        }
+        cur = (cur & ~(1u << l)) | ((unsigned)c << l);
+    }
+    const T* res = (cur & 1) ? Tt(0) : X(0);
+    for (int i = tid; i < D * a.N[0]; i += MG_BOTTOM_THREADS) xout[i] = res[i];
+}
+
+// ---------------------------------------------------------------------------
 // host side
 
 struct ApplyShape {
@@ -1212,21 +1459,10 @@ int check_vec(const void* v, const pf_elastic* p, const char* name)
     return PF_OK;
 }
 
-constexpr int MG_MAXL = 12;
-constexpr int MG_PRE = 2, MG_POST = 2;  // damped-Jacobi sweeps (even, >= 2: results land back in x)
-// sweeps on the coarsest grid: twice its longest axis (even), within [4, 32]
-constexpr int MG_COARSE_MIN = 4, MG_COARSE_MAX = 32;
-// Jacobi damping omega = MG_SMOOTH / lambda_max(D^-1 K).  lambda_max depends on
-// the dimension and nu only (2.0 to 3.5 in 2-D, 2.2 to 6.2 in 3-D for nu in
-// [0, 0.49]; its modes sit at the free surfaces), and a 9^d grid already has the
-// large-grid value; MG_POWER power steps from a pseudo-random start come within
-// about 1.5 %, which keeps omega lambda_max well below 2.
-constexpr double MG_SMOOTH = 1.6;
-constexpr int MG_EIG_N = 9, MG_POWER = 64;
-
 struct Levels {
     int nl = 1;
     int coarse_sweeps = MG_COARSE_MIN;
+    int bottom = 1;  // first level run by k_el_bottom (nl: none)
     Grid g[MG_MAXL];
     long long ndof[MG_MAXL];
 };
@@ -1253,6 +1489,19 @@ Levels mg_levels(const pf_elastic* p)
     long long longest = 0;
     for (int k = 0; k < p->dim; ++k) longest = std::max<long long>(longest, q.n[k]);
     L.coarse_sweeps = (int)std::min<long long>(MG_COARSE_MAX, std::max<long long>(MG_COARSE_MIN, 2 * longest));
+    // the coarse end that fits one block's LDS (never the finest level: the PCG
+    // takes its dot products from the finest level's last sweep)
+    L.bottom = L.nl;
+    const int tm = pfk::tune_el_mg();
+    if (tm != 2) {
+        const long long cap = tm >= 3 ? tm : (p->dim == 3 ? MG_BOTTOM_NODES_3D : MG_BOTTOM_NODES_2D);
+        size_t bytes = 0;
+        for (int l = L.nl - 1; l >= 1 && L.nl - l <= MG_BOTTOM_MAXL; --l) {
+            bytes += 3 * (size_t)L.ndof[l] * esz(p);
+            if (L.g[l].N > cap || bytes > MG_BOTTOM_LDS) break;
+            L.bottom = l;
+        }
+    }
     return L;
 }
 
@@ -1445,11 +1694,45 @@ void launch_jacobi0(const Grid& g, double lam, double mu, const T* b, T* y, doub
         k_el_jacobi0<T, 2><<<nb, EL_BLOCK, 0, s>>>(g, (T)lam, (T)mu, scale, b, y, (T)omega, st);
 }
 
+// levels l .. nl-1 of the cycle in one block (k_el_bottom): b and x in global memory
+template <typename T>
+void launch_bottom(const Levels& Lv, int l0, const T* b, T* x, double lam, double mu, double omega,
+                   const double* st, hipStream_t s)
+{
+    BottomArgs<T> a{};
+    a.nl = Lv.nl - l0;
+    a.coarse_sweeps = Lv.coarse_sweeps;
+    a.lam = (T)lam;
+    a.mu = (T)mu;
+    a.omega = (T)omega;
+    const int D = Lv.g[l0].dim;
+    int off = 0;
+    for (int k = 0; k < a.nl; ++k) {
+        const Grid& g = Lv.g[l0 + k];
+        a.n[k][0] = g.nx;
+        a.n[k][1] = D == 3 ? g.ny : g.nz;
+        a.n[k][2] = D == 3 ? g.nz : 1;
+        a.N[k] = (int)g.N;
+        a.off[k] = off;
+        a.scale[k] = (T)(D == 3 ? g.h : 1.0);
+        off += 3 * D * (int)g.N;
+    }
+    const size_t bytes = (size_t)off * sizeof(T);
+    if (D == 3)
+        k_el_bottom<T, 3><<<1, MG_BOTTOM_THREADS, bytes, s>>>(a, b, x, st);
+    else
+        k_el_bottom<T, 2><<<1, MG_BOTTOM_THREADS, bytes, s>>>(a, b, x, st);
+}
+
 template <typename T>
 void vcycle(const Levels& Lv, int l, const T* b, T* x, T* t, const Ws& W, double lam, double mu, double omega,
             const double* st, double* part, hipStream_t s)
 {
     const Grid& g = Lv.g[l];
+    if (l == Lv.bottom && part == nullptr) {
+        launch_bottom<T>(Lv, l, b, x, lam, mu, omega, st, s);
+        return;
+    }
     const CgArgs ca{nullptr, st}, cd{part, st};
     const bool coarsest = l == Lv.nl - 1;
     // sweeps alternate between the two vectors; an odd count moves the result

@@ -28,7 +28,7 @@ class pf_el_report(ct.Structure):
 
 
 TUNE_EL_PLANES = 4
-TUNE_EL_MG = 5  # 1: plain CG (no multigrid)
+TUNE_EL_MG = 5  # 1: plain CG; 2: every multigrid level launched; v >= 3: one-block coarse grids up to v nodes
 _L = None
 
 

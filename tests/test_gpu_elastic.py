@@ -154,6 +154,31 @@ def test_multigrid_pcg_matches_plain_cg(n, levels):
     assert rep.res_norm <= 1e-12 * rep.rhs_norm
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [(129, 129), (65, 33), (33, 33, 33), (17, 17, 33), (9, 17, 9)])
+def test_multigrid_coarse_block(n, dtype):
+    """The smallest grids of the cycle can run in one workgroup (LDS; the
+    default in 2-D, forced here in 3-D too); the result matches the cycle with
+    every level launched separately: the same iteration count (to one) and the
+    same solution to the solver tolerance."""
+    announce("el mg coarse block", n, dtype)
+    g, o = pair(n, dtype, h=100.0 / (max(n) - 1))
+    rtol = 1e-10 if dtype == torch.float64 else 1e-5
+    L = A.lib()
+    try:
+        assert L.pf_tune_set(EL.TUNE_EL_MG, 1200) == A.PF_OK
+        u, rep = EL.el_solve(g, rtol=rtol)
+        assert L.pf_tune_set(EL.TUNE_EL_MG, 2) == A.PF_OK
+        us, reps = EL.el_solve(g, rtol=rtol)
+    finally:
+        L.pf_tune_set(EL.TUNE_EL_MG, 0)
+    assert rep.converged and reps.converged and rep.levels == reps.levels
+    assert abs(rep.iterations - reps.iterations) <= 1
+    assert rel_l2(host(u), host(us)) < (1e-8 if dtype == torch.float64 else 1e-4)
+    ref, _ = O.el_solve(o, rtol=1e-13)
+    assert rel_l2(host(u), ref) < (1e-8 if dtype == torch.float64 else 1e-4)
+
+
 @pytest.mark.parametrize("nu", [0.0, 0.45, 0.49])
 @pytest.mark.parametrize("n", [(33, 33, 33), (129, 129)])
 def test_multigrid_across_poisson_ratio(n, nu):
