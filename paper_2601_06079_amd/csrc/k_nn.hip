@@ -10,12 +10,13 @@
 //
 // Hidden layers and their input-gradient (dgrad) and weight-gradient (wgrad)
 // products run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
-//   forward/dgrad: a block stages an LDS tile of (CR+2) rows x (32+2) pixels;
-//     each of its 4 waves computes CR/4 rows of 32 pixels x 32 channels, its A
-//     operand (pixels x input channels of one tap) read from the tile, its B
-//     operand (the weights of that tap) held in registers for all its rows.
-//     K = 9 taps x Cin.  (CR = 4 measured fastest: 16-row tiles cut weight and
-//     halo traffic but raise register use and lower occupancy.)
+//   forward/dgrad: persistent blocks (as many as are resident) walk tiles of CR
+//     rows x 32 pixels; each stages the tile's (CR+2) x (32+2) halo in LDS (the
+//     next tile's loads in flight during this tile's MFMAs), and each of its 4
+//     waves computes CR/4 rows of 32 pixels x 32 channels, its A operand (pixels
+//     x input channels of one tap) read from the tile, its B operand (the
+//     weights of that tap) from a copy of the fragments the block made in LDS
+//     once.  K = 9 taps x Cin.
 //   wgrad: dW[tap] (Cin x Cout) = sum over pixels of a_in(p + tap) g_out(p)^T,
 //     K = pixels; every block accumulates a fixed stride of pixel tiles in
 //     registers (split-K) and writes one FP32 partial; a second kernel sums the
@@ -27,6 +28,7 @@
 // C[8 (i / 4) + 4 (l / 32) + (i % 4)][l % 32] in accumulator i = 0..15.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device.hpp"
@@ -82,62 +84,99 @@ __device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, i
 // MODE 0: out = bf16(relu(acc + bias))          (forward, hidden layers)
 // MODE 1: out = bf16(acc * (mask[p][co] > 0))    (dgrad: relu mask of the layer input)
 // wfrag: B fragments [9][CIN/16][64 lanes][8] bf16 for this layer/use
+// Persistent: the grid holds the resident blocks, each copies the weight
+// fragments into LDS once (18 KB; registers would cap occupancy) and walks the
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
+// issued into registers before the current tile's MFMAs, so staging overlaps
+// compute.  Every output is the same MFMA chain as with one tile per block.
 template <int CIN, int MODE>
 __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
                                                     const u16* __restrict__ wfrag,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ mask,
-                                                    u16* __restrict__ out, int B, int H, int W)
+                                                    u16* __restrict__ out, int B, int H, int W, int ntiles)
 {
     constexpr int KS = CIN / 16;
     constexpr int PS = Tile<CIN, CR>::PSTRIDE;
+    constexpr int CHUNKS = CIN * 2 / 16;  // 16-byte chunks per pixel
+    constexpr int TOTAL = (CR + 2) * (TW + 2) * CHUNKS;
+    constexpr int PER = (TOTAL + NBLK - 1) / NBLK;  // staged chunks per thread
     __shared__ __align__(16) unsigned char lds[Tile<CIN, CR>::BYTES];
+    __shared__ bf16x8 wl[9 * KS * 64];  // weight fragments [tap][k-slice][lane]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tiles_x = W / TW, tiles_y = (H + CR - 1) / CR;
-    int t = blockIdx.x;
-    const int tx = t % tiles_x;
-    t /= tiles_x;
-    const int ty = t % tiles_y;
-    const int b = t / tiles_y;
-    const int x0 = tx * TW, y0 = ty * CR;
-    stage_tile<CIN, CR>(in, b, H, W, y0, x0, lds);
-    // this lane's weight fragments for every (tap, k-slice), kept for all rows
-    bf16x8 bw[9 * KS];
-#pragma unroll
-    for (int q = 0; q < 9 * KS; ++q)
-        bw[q] = *reinterpret_cast<const bf16x8*>(wfrag + ((size_t)q * 64 + lane) * 8);
-    __syncthreads();
+    for (int q = threadIdx.x; q < 9 * KS * 64; q += NBLK)
+        wl[q] = *reinterpret_cast<const bf16x8*>(wfrag + (size_t)q * 8);
     const int m = lane & 31, kh = lane >> 5;
     const int co = m;
     const float bco = MODE == 0 ? bias[co] : 0.0f;
-    for (int j = 0; j < CR / 4; ++j) {
-        const int rt = wv + 4 * j;  // tile row of this wave's output row
-        const int y = y0 + rt;
-        if (y >= H) break;          // uniform per wave; later rows are further down
-        f32x16 acc = {};
+    // the halo tile of rows y0-1 .. y0+CR, pixels x0-1 .. x0+TW (periodic) of a tile,
+    // PER 16-byte chunks per thread (chunks past TOTAL load a valid dummy)
+    uint4 s0, s1, s2, s3;
+    static_assert(PER <= 4, "staging registers");
+#define PF_CONV_FETCH(T_)                                                                                   \
+    do {                                                                                                    \
+        const int tt_ = (T_);                                                                               \
+        const int tx_ = tt_ % tiles_x, ty_ = (tt_ / tiles_x) % tiles_y, b_ = tt_ / (tiles_x * tiles_y);     \
+        const int x0_ = tx_ * TW, y0_ = ty_ * CR;                                                           \
+        uint4* dst_[4] = {&s0, &s1, &s2, &s3};                                                              \
+        _Pragma("unroll") for (int q = 0; q < PER; ++q)                                                     \
+        {                                                                                                   \
+            int c = threadIdx.x + q * NBLK;                                                                 \
+            c = c < TOTAL ? c : TOTAL - 1;                                                                  \
+            const int ch = c % CHUNKS, pix = c / CHUNKS;                                                    \
+            const int px = pix % (TW + 2), ry = pix / (TW + 2);                                             \
+            const int gy = wrapi(y0_ - 1 + ry, H), gx = wrapi(x0_ - 1 + px, W);                             \
+            *dst_[q] = *reinterpret_cast<const uint4*>(in + (((size_t)b_ * H + gy) * W + gx) * CIN + ch * 8); \
+        }                                                                                                   \
+    } while (0)
+    int t = blockIdx.x;
+    if (t < ntiles) PF_CONV_FETCH(t);
+    for (; t < ntiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile's reads of the LDS tile are done
+        {
+            const uint4 src[4] = {s0, s1, s2, s3};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row rt + dy, pixel m + dx
-            const unsigned char* rowp = lds + ((rt + dy) * (TW + 2) + (m + dx)) * PS;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
+            for (int q = 0; q < PER; ++q) {
+                const int c = threadIdx.x + q * NBLK;
+                if (c < TOTAL) *reinterpret_cast<uint4*>(lds + (c / CHUNKS) * PS + (c % CHUNKS) * 16) = src[q];
             }
         }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) PF_CONV_FETCH(t + (int)gridDim.x);
+        const int tx = t % tiles_x, ty = (t / tiles_x) % tiles_y, b = t / (tiles_x * tiles_y);
+        const int x0 = tx * TW, y0 = ty * CR;
+        for (int j = 0; j < CR / 4; ++j) {
+            const int rt = wv + 4 * j;  // tile row of this wave's output row
+            const int y = y0 + rt;
+            if (y >= H) break;          // uniform per wave; later rows are further down
+            f32x16 acc = {};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
-            const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
-            float v = acc[i];
-            if (MODE == 0) {
-                v = fmaxf(v + bco, 0.0f);
-            } else {
-                v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row rt + dy, pixel m + dx
+                const unsigned char* rowp = lds + ((rt + dy) * (TW + 2) + (m + dx)) * PS;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wl[(tap * KS + ks) * 64 + lane], acc, 0, 0,
+                                                                  0);
+                }
             }
-            out[pidx * 32 + co] = bf16_bits(v);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
+                const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
+                float v = acc[i];
+                if (MODE == 0) {
+                    v = fmaxf(v + bco, 0.0f);
+                } else {
+                    v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
+                }
+                out[pidx * 32 + co] = bf16_bits(v);
+            }
         }
     }
+#undef PF_CONV_FETCH
 }
 
 // wgrad of a hidden layer: part[block][tap][ci][co] = sum over this block's pixel
@@ -611,6 +650,21 @@ int nn_wgrad_blocks(int B, int H, int W)
 
 int nn_conv_blocks(int B, int H, int W) { return B * ((H + CR - 1) / CR) * (W / TW); }
 
+// resident blocks of a conv kernel on the current device (queried once per kernel)
+template <int CIN, int MODE>
+int conv_resident_blocks()
+{
+    static const int n = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv_mfma<CIN, MODE>, NBLK, 0) != hipSuccess)
+            return 1024;
+        return std::max(1, cus * per);
+    }();
+    return n;
+}
+
 void nn_prep_weights(const float* params, u16* frag, u16* w4, hipStream_t s)
 {
     const NNFragOffsets fo = nn_frag_offsets();
@@ -628,13 +682,17 @@ void nn_pack_input(const float* c, const float* M, const float* kappa, u16* a0, 
 void nn_conv(int layer, int mode, const u16* in, const u16* frag, const float* bias, const u16* mask,
              u16* out, int B, int H, int W, hipStream_t s)
 {
-    const unsigned nb = (unsigned)nn_conv_blocks(B, H, W);
+    const int nt = nn_conv_blocks(B, H, W);
+    auto grid = [&](int resident) { return (unsigned)std::max(1, std::min(nt, resident)); };
     if (layer == 1)
-        k_conv_mfma<16, 0><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+        k_conv_mfma<16, 0><<<grid(conv_resident_blocks<16, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
+                                                                               W, nt);
     else if (mode == 0)
-        k_conv_mfma<32, 0><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+        k_conv_mfma<32, 0><<<grid(conv_resident_blocks<32, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
+                                                                               W, nt);
     else
-        k_conv_mfma<32, 1><<<nb, NBLK, 0, s>>>(in, frag, bias, mask, out, B, H, W);
+        k_conv_mfma<32, 1><<<grid(conv_resident_blocks<32, 1>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
+                                                                               W, nt);
 }
 
 void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb, int B, int H, int W,
