@@ -38,6 +38,7 @@ namespace pfk {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16;
 
@@ -57,10 +58,12 @@ __device__ __forceinline__ float bf16_val(u16 b) { return __uint_as_float((unsig
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// LDS tile: (ROWS + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by 8 bytes
+// LDS tile: (ROWS + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by
+// 16 bytes: a stride of 4k banks with k odd (k = 5 for 32 channels, 3 for 16) puts
+// the 16-byte reads of 8 consecutive pixels on 8 disjoint bank quads
 template <int CIN, int ROWS = TR>
 struct Tile {
-    static constexpr int PSTRIDE = CIN * 2 + 8;  // bytes per pixel in LDS
+    static constexpr int PSTRIDE = CIN * 2 + 16;  // bytes per pixel in LDS
     static constexpr int BYTES = (ROWS + 2) * (TW + 2) * PSTRIDE;
 };
 
@@ -83,33 +86,47 @@ __device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, i
 
 // MODE 0: out = bf16(relu(acc + bias))          (forward, hidden layers)
 // MODE 1: out = bf16(acc * (mask[p][co] > 0))    (dgrad: relu mask of the layer input)
+// MODE 2: as MODE 0 for the first layer, its input channels (bf16 c, M, kappa, then
+//         zeros) formed while staging instead of read from a packed a0
 // wfrag: B fragments [9][CIN/16][64 lanes][8] bf16 for this layer/use
-// Persistent: the grid holds the resident blocks, each copies the weight
-// fragments into LDS once (18 KB; registers would cap occupancy) and walks the
-// tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
+// Persistent: the grid holds the resident blocks, each loads its weight fragments
+// into registers once (LDS then carries only the A operands) and walks the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
 // issued into registers before the current tile's MFMAs, so staging overlaps
 // compute.  Every output is the same MFMA chain as with one tile per block.
+struct InPlanes {
+    const float* c;      // [B][H][W]
+    const float* M;      // [B]
+    const float* kappa;  // [B]
+};
+
 template <int CIN, int MODE>
 __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
                                                     const u16* __restrict__ wfrag,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ mask,
-                                                    u16* __restrict__ out, int B, int H, int W, int ntiles)
+                                                    u16* __restrict__ out, int B, int H, int W, int ntiles,
+                                                    InPlanes ip)
 {
+    static_assert(MODE != 2 || CIN == 16, "the planes feed the 16-channel first layer");
     constexpr int KS = CIN / 16;
     constexpr int PS = Tile<CIN, CR>::PSTRIDE;
     constexpr int CHUNKS = CIN * 2 / 16;  // 16-byte chunks per pixel
     constexpr int TOTAL = (CR + 2) * (TW + 2) * CHUNKS;
     constexpr int PER = (TOTAL + NBLK - 1) / NBLK;  // staged chunks per thread
-    __shared__ __align__(16) unsigned char lds[Tile<CIN, CR>::BYTES];
-    __shared__ bf16x8 wl[9 * KS * 64];  // weight fragments [tap][k-slice][lane]
+    constexpr int OST = 80;  // bytes per pixel row of the epilogue transpose (64 + 16: no bank overlap)
+    constexpr int LB = Tile<CIN, CR>::BYTES > 4 * TW * OST ? Tile<CIN, CR>::BYTES : 4 * TW * OST;
+    __shared__ __align__(16) unsigned char lds[LB];  // the halo tile, then the transpose
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tiles_x = W / TW, tiles_y = (H + CR - 1) / CR;
-    for (int q = threadIdx.x; q < 9 * KS * 64; q += NBLK)
-        wl[q] = *reinterpret_cast<const bf16x8*>(wfrag + (size_t)q * 8);
+    // this lane's weight fragments for every (tap, k-slice), kept for all tiles
+    bf16x8 bw[9 * KS];
+#pragma unroll
+    for (int q = 0; q < 9 * KS; ++q)
+        bw[q] = *reinterpret_cast<const bf16x8*>(wfrag + ((size_t)q * 64 + lane) * 8);
     const int m = lane & 31, kh = lane >> 5;
     const int co = m;
-    const float bco = MODE == 0 ? bias[co] : 0.0f;
+    const float bco = MODE != 1 ? bias[co] : 0.0f;
     // the halo tile of rows y0-1 .. y0+CR, pixels x0-1 .. x0+TW (periodic) of a tile,
     // PER 16-byte chunks per thread (chunks past TOTAL load a valid dummy)
     uint4 s0, s1, s2, s3;
@@ -127,7 +144,17 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
             const int ch = c % CHUNKS, pix = c / CHUNKS;                                                    \
             const int px = pix % (TW + 2), ry = pix / (TW + 2);                                             \
             const int gy = wrapi(y0_ - 1 + ry, H), gx = wrapi(x0_ - 1 + px, W);                             \
-            *dst_[q] = *reinterpret_cast<const uint4*>(in + (((size_t)b_ * H + gy) * W + gx) * CIN + ch * 8); \
+            const size_t gp_ = ((size_t)b_ * H + gy) * W + gx;                                              \
+            if (MODE == 2) {                                                                                \
+                uint4 v_ = make_uint4(0u, 0u, 0u, 0u);                                                      \
+                if (ch == 0) {                                                                              \
+                    v_.x = (unsigned)bf16_bits(ip.c[gp_]) | ((unsigned)bf16_bits(ip.M[b_]) << 16);          \
+                    v_.y = (unsigned)bf16_bits(ip.kappa[b_]);                                               \
+                }                                                                                           \
+                *dst_[q] = v_;                                                                              \
+            } else {                                                                                        \
+                *dst_[q] = *reinterpret_cast<const uint4*>(in + gp_ * CIN + ch * 8);                        \
+            }                                                                                               \
         }                                                                                                   \
     } while (0)
     int t = blockIdx.x;
@@ -146,11 +173,11 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         if (t + (int)gridDim.x < ntiles) PF_CONV_FETCH(t + (int)gridDim.x);
         const int tx = t % tiles_x, ty = (t / tiles_x) % tiles_y, b = t / (tiles_x * tiles_y);
         const int x0 = tx * TW, y0 = ty * CR;
-        for (int j = 0; j < CR / 4; ++j) {
-            const int rt = wv + 4 * j;  // tile row of this wave's output row
-            const int y = y0 + rt;
-            if (y >= H) break;          // uniform per wave; later rows are further down
-            f32x16 acc = {};
+        static_assert(CR == 4, "one output row per wave");
+        const int rt = wv;  // tile row of this wave's output row
+        const int y = y0 + rt;
+        f32x16 acc = {};
+        if (y < H) {
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap % 3;  // tile coordinates: row rt + dy, pixel m + dx
@@ -158,22 +185,46 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wl[(tap * KS + ks) * 64 + lane], acc, 0, 0,
-                                                                  0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
                 }
             }
+        }
+        // epilogue: the wave's 32 pixels x 32 channels go through LDS (the tile is
+        // free once every wave has its products) so that each lane stores whole
+        // 16-byte channel groups: lane l writes pixel l / 2, channels 16 (l % 2) ...
+        __syncthreads();
+        unsigned char* ot = lds + wv * TW * OST;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
-                const size_t pidx = ((size_t)b * H + y) * W + x0 + px;
-                float v = acc[i];
-                if (MODE == 0) {
-                    v = fmaxf(v + bco, 0.0f);
-                } else {
-                    v = bf16_val(mask[pidx * 32 + co]) > 0.0f ? v : 0.0f;
-                }
-                out[pidx * 32 + co] = bf16_bits(v);
+        for (int i = 0; i < 16; ++i) {
+            const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
+            const float v = MODE != 1 ? fmaxf(acc[i] + bco, 0.0f) : acc[i];
+            *reinterpret_cast<u16*>(ot + px * OST + co * 2) = bf16_bits(v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (y < H) {
+            const int p = lane >> 1, half = lane & 1;
+            uint4 v0 = *reinterpret_cast<const uint4*>(ot + p * OST + half * 32);
+            uint4 v1 = *reinterpret_cast<const uint4*>(ot + p * OST + half * 32 + 16);
+            const size_t pidx = ((size_t)b * H + y) * W + x0 + p;
+            if (MODE == 1) {
+                // dgrad: keep the entries whose layer input was positive
+                const uint4* mk = reinterpret_cast<const uint4*>(mask + pidx * 32 + half * 16);
+                const uint4 m0 = mk[0], m1 = mk[1];
+                // a bf16 is > 0 iff its sign bit is clear and it lies in (0, +inf]
+                auto pos = [](unsigned h) { return h != 0u && h <= 0x7f80u; };
+                auto gate = [&](unsigned g, unsigned mword) {
+                    const unsigned lo = pos(mword & 0xffffu) ? 0xffffu : 0u;
+                    const unsigned hi = pos(mword >> 16) ? 0xffff0000u : 0u;
+                    return g & (lo | hi);
+                };
+                v0 = make_uint4(gate(v0.x, m0.x), gate(v0.y, m0.y), gate(v0.z, m0.z), gate(v0.w, m0.w));
+                v1 = make_uint4(gate(v1.x, m1.x), gate(v1.y, m1.y), gate(v1.z, m1.z), gate(v1.w, m1.w));
             }
+            uint4* dst = reinterpret_cast<uint4*>(out + pidx * 32 + half * 16);
+            dst[0] = v0;
+            dst[1] = v1;
         }
     }
 #undef PF_CONV_FETCH
@@ -346,29 +397,46 @@ __global__ __launch_bounds__(NBLK) void k_prep_weights(const float* __restrict__
 }
 
 // output layer forward: d[p] = b4 + sum_tap sum_ci W4[tap][ci] a3[p + tap][ci]  (fp32)
+// Output layer (32 -> 1): a block stages the a3 halo tile of OR rows x 32 pixels
+// in LDS (the conflict-free stride of the hidden layers) and each thread forms one
+// pixel's 288-term sum with the packed bf16 dot instruction (two products per
+// step, FP32 accumulation), the weights broadcast from LDS.
+constexpr int OR = NBLK / TW;  // 8 rows: one pixel per thread
 __global__ __launch_bounds__(NBLK) void k_out_fwd(const u16* __restrict__ a3, const u16* __restrict__ w4,
                                                   const float* __restrict__ params, NNOffsets off,
                                                   float* __restrict__ d, int B, int H, int W)
 {
-    __shared__ float sw[9 * 32];
-    for (int i = threadIdx.x; i < 9 * 32; i += NBLK) sw[i] = bf16_val(w4[i]);
+    constexpr int PS = Tile<32, OR>::PSTRIDE;
+    __shared__ __align__(16) unsigned char la[Tile<32, OR>::BYTES];
+    __shared__ uint4 sw[9 * 4];  // weights as bf16 pairs [tap][16 pairs]
+    const int tiles_x = W / TW, tiles_y = (H + OR - 1) / OR;
+    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
+    const int x0 = tx * TW, y0 = ty * OR;
+    if (threadIdx.x < 9 * 4) sw[threadIdx.x] = reinterpret_cast<const uint4*>(w4)[threadIdx.x];
+    stage_tile<32, OR>(a3, b, H, W, y0, x0, la);
     __syncthreads();
-    const size_t p = (size_t)blockIdx.x * NBLK + threadIdx.x;
-    const size_t HW = (size_t)H * W;
-    if (p >= (size_t)B * HW) return;
-    const int b = (int)(p / HW), r = (int)(p % HW), y = r / W, x = r % W;
-    float s = params[off.b4];
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = wrapi(y + tap / 3 - 1, H), xx = wrapi(x + tap % 3 - 1, W);
-        const u16* ap = a3 + (((size_t)b * H + yy) * W + xx) * 32;
-        for (int ci = 0; ci < 32; ci += 8) {
-            const uint4 v = *reinterpret_cast<const uint4*>(ap + ci);
-            const u16* e = reinterpret_cast<const u16*>(&v);
+    const int r = threadIdx.x / TW, m = threadIdx.x % TW;
+    const int y = y0 + r;
+    if (y >= H) return;
+    auto dot8 = [](const uint4& a, const uint4& w, float acc) {
+        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a.x), __builtin_bit_cast(bf16x2, w.x), acc,
+                                              false);
+        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a.y), __builtin_bit_cast(bf16x2, w.y), acc,
+                                              false);
+        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a.z), __builtin_bit_cast(bf16x2, w.z), acc,
+                                              false);
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a.w), __builtin_bit_cast(bf16x2, w.w),
+                                               acc, false);
+    };
+    float sum = params[off.b4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s = fmaf(sw[tap * 32 + ci + j], bf16_val(e[j]), s);
-        }
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        const uint4* ap = reinterpret_cast<const uint4*>(la + ((r + dy) * (TW + 2) + (m + dx)) * PS);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum = dot8(ap[q], sw[tap * 4 + q], sum);
     }
-    d[p] = s;
+    d[((size_t)b * H + y) * W + x0 + m] = sum;
 }
 
 // per-sample partial sums of x over blocks of NBLK pixels: part[b * nbs + blk]
@@ -684,15 +752,24 @@ void nn_conv(int layer, int mode, const u16* in, const u16* frag, const float* b
 {
     const int nt = nn_conv_blocks(B, H, W);
     auto grid = [&](int resident) { return (unsigned)std::max(1, std::min(nt, resident)); };
+    const InPlanes none{nullptr, nullptr, nullptr};
     if (layer == 1)
         k_conv_mfma<16, 0><<<grid(conv_resident_blocks<16, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt);
+                                                                               W, nt, none);
     else if (mode == 0)
         k_conv_mfma<32, 0><<<grid(conv_resident_blocks<32, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt);
+                                                                               W, nt, none);
     else
         k_conv_mfma<32, 1><<<grid(conv_resident_blocks<32, 1>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt);
+                                                                               W, nt, none);
+}
+
+void nn_conv1_planes(const float* c, const float* M, const float* kappa, const u16* frag, const float* bias,
+                     u16* out, int B, int H, int W, hipStream_t s)
+{
+    const int nt = nn_conv_blocks(B, H, W);
+    const unsigned g = (unsigned)std::max(1, std::min(nt, conv_resident_blocks<16, 2>()));
+    k_conv_mfma<16, 2><<<g, NBLK, 0, s>>>(nullptr, frag, bias, nullptr, out, B, H, W, nt, InPlanes{c, M, kappa});
 }
 
 void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb, int B, int H, int W,
@@ -713,8 +790,8 @@ void nn_sum_partials(const float* part, int nb, int n, float* out, hipStream_t s
 void nn_out_fwd(const u16* a3, const u16* w4, const float* params, float* d, int B, int H, int W,
                 hipStream_t s)
 {
-    const size_t n = (size_t)B * H * W;
-    k_out_fwd<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(a3, w4, params, nn_offsets(), d, B, H, W);
+    const unsigned nb = (unsigned)B * (unsigned)((H + OR - 1) / OR) * (unsigned)(W / TW);
+    k_out_fwd<<<nb, NBLK, 0, s>>>(a3, w4, params, nn_offsets(), d, B, H, W);
 }
 
 void nn_sample_mean(const float* x, double* part, double* mean, int B, int HW, hipStream_t s)

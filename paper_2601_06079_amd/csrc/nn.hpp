@@ -27,6 +27,10 @@ void nn_pack_input(const float* c, const float* M, const float* kappa, unsigned 
 void nn_conv(int layer, int mode, const unsigned short* in, const unsigned short* frag,
              const float* bias, const unsigned short* mask, unsigned short* out, int B, int H, int W,
              hipStream_t s);
+// the first layer with its input channels formed from the c, M, kappa planes
+// (bitwise the packed a0 path; forward only, where a0 is not kept)
+void nn_conv1_planes(const float* c, const float* M, const float* kappa, const unsigned short* frag,
+                     const float* bias, unsigned short* out, int B, int H, int W, hipStream_t s);
 // weight gradient partials of hidden layer `layer` (part: blocks x 9 x 32 x 32, partb: blocks x 32)
 void nn_wgrad(int layer, const unsigned short* ain, const unsigned short* g, float* part, float* partb,
               int B, int H, int W, hipStream_t s);

@@ -62,16 +62,20 @@ int check_shape(int B, int H, int W)
     return PF_OK;
 }
 
-// the forward pass, leaving a0..a3 and d in the workspace
+// the forward pass, leaving a1..a3 and d (and a0 if keep_a0) in the workspace
 void forward(const float* params, int B, int H, int W, const float* c, const float* M,
-             const float* kappa, const float* target, NNWS& L, hipStream_t s)
+             const float* kappa, const float* target, NNWS& L, hipStream_t s, bool keep_a0)
 {
     const pfk::NNOffsets o = pfk::nn_offsets();
     const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
     const int HW = H * W;
     pfk::nn_prep_weights(params, L.frag, L.w4, s);
-    pfk::nn_pack_input(c, M, kappa, L.a0, B, HW, s);
-    pfk::nn_conv(1, 0, L.a0, L.frag + fo.f1, params + o.b1, nullptr, L.a1, B, H, W, s);
+    if (keep_a0) {  // the first layer's weight gradient reads a0
+        pfk::nn_pack_input(c, M, kappa, L.a0, B, HW, s);
+        pfk::nn_conv(1, 0, L.a0, L.frag + fo.f1, params + o.b1, nullptr, L.a1, B, H, W, s);
+    } else {
+        pfk::nn_conv1_planes(c, M, kappa, L.frag + fo.f1, params + o.b1, L.a1, B, H, W, s);
+    }
     pfk::nn_conv(2, 0, L.a1, L.frag + fo.f2, params + o.b2, nullptr, L.a2, B, H, W, s);
     pfk::nn_conv(3, 0, L.a2, L.frag + fo.f3, params + o.b3, nullptr, L.a3, B, H, W, s);
     pfk::nn_out_fwd(L.a3, L.w4, params, L.d, B, H, W, s);
@@ -104,7 +108,7 @@ int pf_nn_forward(const float* params, int B, int H, int W, const float* c, cons
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     NNWS L = nn_layout(B, H, W, ws);
-    forward(params, B, H, W, c, M, kappa, nullptr, L, s);
+    forward(params, B, H, W, c, M, kappa, nullptr, L, s, false);
     if (hipMemcpyAsync(chat, L.chat, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return check_launch("pf_nn_forward copy");
     return check_launch("pf_nn_forward");
@@ -123,7 +127,7 @@ int pf_nn_backward(const float* params, int B, int H, int W, const float* c, con
     const pfk::NNOffsets o = pfk::nn_offsets();
     const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
     const int HW = H * W;
-    forward(params, B, H, W, c, M, kappa, target, L, s);
+    forward(params, B, H, W, c, M, kappa, target, L, s, true);
     if (loss) pfk::nn_sample_mean(L.r2, L.spart, loss, B, HW, s);  // per-sample MSE
     // backward of the mass projection: g <- g - mean(g)
     pfk::nn_sample_mean(L.g, L.spart, L.mean2, B, HW, s);
