@@ -63,7 +63,7 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
 {
     extern __shared__ unsigned char smem_raw[];
     T* sf = reinterpret_cast<T*>(smem_raw);  // P * GS * GS
-    T* sE = sf + P * GS * GS;                 // FG * GB * 4 nodal shares
+    T* sE = sf + P * GS * GS;                 // FG * 4 * GB nodal shares, [field][share][element]
     const int tid = threadIdx.x;
     const int nx = g.n[0], ny = g.n[1];
     const long long N = g.N;
@@ -116,7 +116,9 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
             T q[4];
             qvals(u00, u10, u01, u11, q);
             T d[4];
-            T* e = sE + (j * GB + tid) * 4;
+            // share c of this element at e[c * GB] (element-minor: the writes and the
+            // node sums below touch consecutive words across lanes, no bank conflicts)
+            T* e = sE + j * 4 * GB + tid;
             if (MODE == 2) {
                 // diagonal: d2f/deta_i^2 = eta_i^2 (3 - 2 gamma) - 1 + 2 gamma S, projected
                 // with phi_a^2, plus the element stiffness diagonal 4/6
@@ -127,9 +129,9 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
                 const T a01 = p2 * d[2] + m2 * d[3], a11 = m2 * d[2] + p2 * d[3];
                 const T kd = ks * (T)4;
                 e[0] = fmaT(detJ, p2 * a00 + m2 * a01, kd);
-                e[1] = fmaT(detJ, p2 * a10 + m2 * a11, kd);
-                e[2] = fmaT(detJ, m2 * a00 + p2 * a01, kd);
-                e[3] = fmaT(detJ, m2 * a10 + p2 * a11, kd);
+                e[GB] = fmaT(detJ, p2 * a10 + m2 * a11, kd);
+                e[2 * GB] = fmaT(detJ, m2 * a00 + p2 * a01, kd);
+                e[3 * GB] = fmaT(detJ, m2 * a10 + p2 * a11, kd);
                 continue;
             }
 #pragma unroll
@@ -138,19 +140,19 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
             const T a00 = gp * d[0] + gm * d[1], a10 = gm * d[0] + gp * d[1];  // x-projection, qy = 0
             const T a01 = gp * d[2] + gm * d[3], a11 = gm * d[2] + gp * d[3];  // qy = 1
             const T sum = (u00 + u10) + (u01 + u11);
-            e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * u00 - u11 - sum));  // node (0, 0)
-            e[1] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * u10 - u01 - sum));  // node (1, 0)
-            e[2] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * u01 - u10 - sum));  // node (0, 1)
-            e[3] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * u11 - u00 - sum));  // node (1, 1)
+            e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * u00 - u11 - sum));       // node (0, 0)
+            e[GB] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * u10 - u01 - sum));      // node (1, 0)
+            e[2 * GB] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * u01 - u10 - sum));  // node (0, 1)
+            e[3 * GB] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * u11 - u00 - sum));  // node (1, 1)
         }
         __syncthreads();
         if (valid) {
             for (int j = 0; j < nf; ++j) {
                 // node (ex + 1, ey + 1) of the patch: share 3 of this element, 2 of the one
                 // to the right, 1 of the one above, 0 of the one above-right
-                const T* e = sE + j * GB * 4;
-                const T r = L * ((e[4 * tid + 3] + e[4 * (tid + 1) + 2]) +
-                                 (e[4 * (tid + GE) + 1] + e[4 * (tid + GE + 1) + 0]));
+                const T* e = sE + j * 4 * GB;
+                const T r = L * ((e[3 * GB + tid] + e[2 * GB + tid + 1]) +
+                                 (e[GB + tid + GE] + e[tid + GE + 1]));
                 const long long o = (long long)(f0 + j) * N + (long long)gyo * nx + gxo;
                 const T uc = sf[(f0 + j) * GS * GS + eb + GS + 1];
                 const T ib = (T)1 / (T)bfactor<2>(g, gxo, gyo, 0);
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(GB) void k_gg_jvp2d(Geom g, int P, T L, T kappa, T 
     extern __shared__ unsigned char smem_raw[];
     T* su = reinterpret_cast<T*>(smem_raw);  // P * GS * GS
     T* sv = su + P * GS * GS;                 // P * GS * GS
-    T* sE = sv + P * GS * GS;                 // GB * 4 nodal shares
+    T* sE = sv + P * GS * GS;                 // 4 * GB nodal shares, [share][element]
     const int tid = threadIdx.x;
     const int nx = g.n[0], ny = g.n[1];
     const long long N = g.N;
@@ -242,15 +244,15 @@ __global__ __launch_bounds__(GB) void k_gg_jvp2d(Geom g, int P, T L, T kappa, T 
         const T a00 = gp * d[0] + gm * d[1], a10 = gm * d[0] + gp * d[1];
         const T a01 = gp * d[2] + gm * d[3], a11 = gm * d[2] + gp * d[3];
         const T sum = (v00 + v10) + (v01 + v11);
-        T* e = sE + tid * 4;
+        T* e = sE + tid;
         e[0] = fmaT(detJ, gp * a00 + gm * a01, ks * ((T)5 * v00 - v11 - sum));
-        e[1] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * v10 - v01 - sum));
-        e[2] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * v01 - v10 - sum));
-        e[3] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * v11 - v00 - sum));
+        e[GB] = fmaT(detJ, gp * a10 + gm * a11, ks * ((T)5 * v10 - v01 - sum));
+        e[2 * GB] = fmaT(detJ, gm * a00 + gp * a01, ks * ((T)5 * v01 - v10 - sum));
+        e[3 * GB] = fmaT(detJ, gm * a10 + gp * a11, ks * ((T)5 * v11 - v00 - sum));
         __syncthreads();
         if (valid) {
-            const T r = L * ((sE[4 * tid + 3] + sE[4 * (tid + 1) + 2]) +
-                             (sE[4 * (tid + GE) + 1] + sE[4 * (tid + GE + 1) + 0]));
+            const T r = L * ((sE[3 * GB + tid] + sE[2 * GB + tid + 1]) +
+                             (sE[GB + tid + GE] + sE[tid + GE + 1]));
             const long long o = (long long)f * N + (long long)gyo * nx + gxo;
             out[o] = fmaT(inv_dt * h * h, v11, r) / (T)bfactor<2>(g, gxo, gyo, 0);
         }
