@@ -269,7 +269,7 @@ def coupled_record(stream, n=1024, steps=2000):
                          "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
 
 
-def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0):
+def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0, krylov=0):
     """The paper's 2-D implicit benchmark shapes (backward Euler, Newton + GMRES(30)
     with block Jacobi, FP32 fields): [0, 100]^2 with n^2 nodes, no-flux,
     f' = 4c(c-1)(c-1/2) (W = 1), M = 1, kappa = 2 (Allen-Cahn) or 1.5 (Cahn-Hilliard);
@@ -289,15 +289,16 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0):
     if ch:
         S.step_explicit(S.Problem(**{**p.__dict__, "mass": 0}), U, 1e-30, 0)  # mu0 (lumped row)
     ws = S.workspace(p, A.OP_NEWTON)
+    opts = S.newton_opts(krylov=krylov)
     Uold = torch.empty_like(U)
     Uold.copy_(U)
-    S.newton_step(p, dt, Uold, U, ws=ws)  # warm-up (not timed)
+    S.newton_step(p, dt, Uold, U, opts, ws=ws)  # warm-up (not timed)
     torch.cuda.synchronize()
     newton, gmres, ok = [], [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
         Uold.copy_(U)
-        rep = S.newton_step(p, dt, Uold, U, ws=ws)
+        rep = S.newton_step(p, dt, Uold, U, opts, ws=ws)
         newton.append(rep.newton_its)
         gmres.append(rep.gmres_its)
         ok += int(rep.converged)
@@ -306,8 +307,9 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0):
     name = "Cahn-Hilliard" if ch else "Allen-Cahn"
     dof = n * n
     mname = "consistent mass (all terms Gauss-integrated)" if mass else "lumped mass"
+    lin = "CG with point Jacobi" if krylov == A.KRYLOV_CG else "GMRES(30) with block-Jacobi"
     return {"workload": f"2D {name} {n}x{n} on [0,100]^2, no-flux, backward Euler dt={dt}, {mname}, "
-                        "Newton + GMRES(30) with block-Jacobi, FP32 fields",
+                        f"Newton + {lin}, FP32 fields",
             "dof": dof, "steps": steps, "converged_steps": ok, "ms_per_step": 1e3 * el / steps,
             "dof_steps_per_s": dof * steps / el, "newton_its_per_step": float(np.mean(newton)),
             "gmres_its_per_newton": float(np.sum(gmres) / max(np.sum(newton), 1))}
@@ -683,6 +685,7 @@ def main():
             print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
             from paper_2601_06079_amd import _abi as A
             print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048)), flush=True)
+            print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048, krylov=A.KRYLOV_CG)), flush=True)
             print(json.dumps(implicit2d_record(stream, A.CAHN_HILLIARD, 512)), flush=True)
             print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5,
                                                mass=A.MASS_CONSISTENT)), flush=True)
@@ -808,6 +811,8 @@ def main():
         out["coupled_implicit_512"] = coupled_implicit_record(stream)
         from paper_2601_06079_amd import _abi as A
         out["implicit_ac2048_2d"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5)
+        out["implicit_ac2048_2d_cg"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5,
+                                                         krylov=A.KRYLOV_CG)
         out["implicit_ch512_2d"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5)
         out["implicit_ch512_2d_consistent"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5,
                                                                 mass=A.MASS_CONSISTENT)

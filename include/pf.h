@@ -203,6 +203,12 @@ int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, voi
 /* Backward-Euler Newton step (Eqs. 13-14, Sec. 2.3)                        */
 /* ---------------------------------------------------------------------- */
 enum { PF_PRECOND_NONE = 0, PF_PRECOND_JACOBI = 1 /* point (AC) / 2x2 block (CH) */ };
+/* Linear solver of each Newton correction.  PF_KRYLOV_CG (preconditioned
+ * conjugate gradients, device-resident scalars) needs a symmetric positive
+ * definite Jacobian: Allen-Cahn only, and dt * mobility * W < 1 (then
+ * (m/dt) M + L (N'(eta) + kappa K) is positive definite for every eta, since
+ * f'' >= -W for both double wells); otherwise pf_newton_step returns PF_EINVAL. */
+enum { PF_KRYLOV_GMRES = 0, PF_KRYLOV_CG = 1 };
 
 typedef struct pf_newton_opts {
     double rtol;            /* stop when ||R||_2 <= rtol ||R(U_initial)||_2 (default 1e-8) */
@@ -214,12 +220,13 @@ typedef struct pf_newton_opts {
     double lin_rtol_max;    /* inexact-Newton forcing: linear rtol = clamp(0.1 ||R_k||/||R_0||, */
     double lin_rtol_min;    /*   lin_rtol_min, lin_rtol_max) (defaults 1e-2, 1e-6) */
     int32_t stagnation;     /* 1: also stop when the FP32 rounding floor is reached (see report) */
-    int32_t reserved;
+    int32_t krylov;         /* PF_KRYLOV_GMRES (default) or PF_KRYLOV_CG; gmres_restart is
+                             * ignored by CG, gmres_max_its bounds its iterations */
 } pf_newton_opts;
 
 typedef struct pf_newton_report {
     int32_t newton_its;      /* corrections applied */
-    int32_t gmres_its;       /* Arnoldi steps over all corrections */
+    int32_t gmres_its;       /* Krylov iterations over all corrections (Arnoldi steps or CG) */
     int32_t converged;       /* 1 if a stop test passed */
     int32_t reason;          /* 0 rtol, 1 atol, 2 rounding floor, -1 max_newton, -2 non-finite */
     double res_norm[33];     /* ||R||_2 per iterate (FP64), entries 0..newton_its (<= 32 kept) */
@@ -232,7 +239,8 @@ void pf_newton_default_opts(pf_newton_opts* o);
  * Newton-Raphson with matrix-free Jacobian-vector products inside restarted,
  * right-preconditioned GMRES (classical Gram-Schmidt with one
  * re-orthogonalisation; FP64 dot products and Hessenberg even for PF_F32
- * fields).  U holds the initial guess on entry and the last iterate on exit.
+ * fields), or, with opts->krylov = PF_KRYLOV_CG (Allen-Cahn, dt L W < 1),
+ * Jacobi-preconditioned conjugate gradients with FP64 scalars.  U holds the initial guess on entry and the last iterate on exit.
  * U_old is not modified.  ws: pf_workspace_size(PF_OP_NEWTON) bytes.
  * Host-synchronous: returns when the step is done (PF_OK or PF_ENOCONV /
  * PF_ENONFINITE with rep filled).  rep may be NULL. */

@@ -34,12 +34,15 @@ class pf_problem(ct.Structure):
                 ("nfields", ct.c_int32), ("reserved2", ct.c_int32), ("gamma", ct.c_double)]
 
 
+KRYLOV_GMRES, KRYLOV_CG = 0, 1
+
+
 class pf_newton_opts(ct.Structure):
     _fields_ = [("rtol", ct.c_double), ("atol", ct.c_double), ("max_newton", ct.c_int32),
                 ("gmres_restart", ct.c_int32), ("gmres_max_its", ct.c_int32),
                 ("precond", ct.c_int32), ("lin_rtol_max", ct.c_double),
                 ("lin_rtol_min", ct.c_double), ("stagnation", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("krylov", ct.c_int32)]
 
 
 class pf_newton_report(ct.Structure):

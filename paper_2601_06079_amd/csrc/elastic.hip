@@ -873,6 +873,17 @@ __global__ void __launch_bounds__(EL_BLOCK) k_el_prolong(Grid gc, Grid gf, const
     for (int c = 0; c < D; ++c) xf[c * gf.N + F] += acc[c];
 }
 
+// The done flag as one block-wide decision: block 0 of k_pcg_rho / k_pcg_alpha
+// may set it while other blocks start, and a block whose waves disagreed would
+// split at its barriers.
+__device__ __forceinline__ bool pcg_block_done(const double* st)
+{
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = st[P_DONE] != 0.0;
+    __syncthreads();
+    return flag != 0;
+}
+
 // reduce nparts (z.r, r.r) pairs in a fixed order (every block gets the same sums)
 __device__ __forceinline__ void reduce_pairs_block(const double* __restrict__ part, int nparts, double* sh,
                                                    double& a, double& b)
@@ -896,7 +907,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_pcg_rho(long long n, const double*
 {
     __shared__ double sh[2 * EL_WAVES];
     __shared__ double sc[2];
-    if (st[P_DONE] != 0.0) return;
+    if (pcg_block_done(st)) return;
     double zr, rr;
     reduce_pairs_block(part, nparts, sh, zr, rr);
     if (threadIdx.x == 0) {
@@ -940,7 +951,7 @@ __global__ void __launch_bounds__(EL_BLOCK) k_pcg_alpha(long long n, const doubl
 {
     __shared__ double sh[2 * EL_WAVES];
     __shared__ double sc[1];
-    if (st[P_DONE] != 0.0) return;
+    if (pcg_block_done(st)) return;
     double pp, pq;
     reduce_pairs_block(part, nparts, sh, pp, pq);
     if (threadIdx.x == 0) {

@@ -505,6 +505,173 @@ __global__ __launch_bounds__(KB) void k_max_pairs(const double* __restrict__ par
     }
 }
 
+// ---- preconditioned conjugate gradients ---------------------------------------
+
+// sums of nb (a, b) pairs in a fixed order, the same in every block
+__device__ __forceinline__ void cg_reduce_pairs(const double* __restrict__ part, int nb, double& a, double& b)
+{
+    __shared__ double res[2];
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += KB) {
+        v[0] += part[2 * i];
+        v[1] += part[2 * i + 1];
+    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        res[0] = v[0];
+        res[1] = v[1];
+    }
+    __syncthreads();
+    a = res[0];
+    b = res[1];
+}
+
+// The done flag as one block-wide decision: block 0 of a step kernel may set it
+// while other blocks start, and a block whose waves disagreed would split at
+// its barriers.
+__device__ __forceinline__ bool cg_block_done(const double* st)
+{
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = st[CG_DONE] != 0.0;
+    __syncthreads();
+    return flag != 0;
+}
+
+__device__ __forceinline__ void cg_host_store(double* host, int i, double v)
+{
+    __hip_atomic_store(&host[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T>
+__global__ __launch_bounds__(KB) void k_cg_start(const T* __restrict__ b, const T* __restrict__ pinv,
+                                                 T* __restrict__ r, T* __restrict__ z, T* __restrict__ p,
+                                                 T* __restrict__ x, long long n, double* __restrict__ part,
+                                                 double* __restrict__ st, double* __restrict__ host,
+                                                 double tol2, double maxit)
+{
+    double v[2] = {0.0, 0.0};
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+        const T bv = b[e];
+        const T zv = pinv ? pinv[e] * bv : bv;
+        r[e] = bv;
+        z[e] = zv;
+        p[e] = T(0);
+        x[e] = T(0);
+        v[0] += (double)bv * (double)zv;
+        v[1] += (double)bv * (double)bv;
+    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+        if (blockIdx.x == 0) {
+            for (int i = 0; i < CG_NSTATE; ++i) st[i] = 0.0;
+            st[CG_TOL2] = tol2;
+            st[CG_MAXIT] = maxit;
+            for (int i = 0; i < 3; ++i) cg_host_store(host, i, 0.0);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(KB) void k_cg_dir(const T* __restrict__ z, T* __restrict__ p, long long n,
+                                               const double* __restrict__ part, int nb, double* st,
+                                               double* __restrict__ host)
+{
+    __shared__ double sc[2];
+    if (cg_block_done(st)) return;
+    double rz, rr;
+    cg_reduce_pairs(part, nb, rz, rr);
+    if (threadIdx.x == 0) {
+        const double its = st[CG_ITS];
+        double done = 0.0;
+        if (!(std::isfinite(rz) && std::isfinite(rr))) done = CG_NONFINITE;
+        else if (rr <= st[CG_TOL2]) done = CG_CONVERGED;
+        else if (its >= st[CG_MAXIT]) done = CG_MAXITS;
+        else if (!(rz > 0.0)) done = CG_BREAKDOWN;
+        sc[0] = done;
+        sc[1] = (done == 0.0 && its > 0.0) ? rz / st[CG_RZOLD] : 0.0;
+        if (blockIdx.x == 0) {
+            st[CG_RZ] = rz;
+            st[CG_RR] = rr;
+            cg_host_store(host, CG_H_RR, rr);
+            cg_host_store(host, CG_H_ITS, its);
+            if (done != 0.0) {
+                st[CG_DONE] = done;
+                cg_host_store(host, CG_H_DONE, done);
+            }
+        }
+    }
+    __syncthreads();
+    if (sc[0] != 0.0) return;
+    const T beta = (T)sc[1];
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB)
+        p[e] = fmaT(beta, p[e], z[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(KB) void k_cg_pq(const T* __restrict__ p, const T* __restrict__ q, long long n,
+                                              double* __restrict__ part2, const double* __restrict__ st)
+{
+    if (cg_block_done(st)) return;
+    double v[1] = {0.0};
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB)
+        v[0] += (double)p[e] * (double)q[e];
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part2[blockIdx.x] = v[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(KB) void k_cg_alpha(T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                                 const T* __restrict__ p, const T* __restrict__ q,
+                                                 const T* __restrict__ pinv, long long n,
+                                                 const double* __restrict__ part2, int nb,
+                                                 double* __restrict__ part, double* st, double* __restrict__ host)
+{
+    __shared__ double sc[1];
+    __shared__ double red[1];
+    if (cg_block_done(st)) return;
+    double v1[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += KB) v1[0] += part2[i];
+    block_sum<1>(v1);
+    if (threadIdx.x == 0) red[0] = v1[0];
+    __syncthreads();
+    const double pq = red[0];
+    if (threadIdx.x == 0) {
+        const bool ok = pq > 0.0 && std::isfinite(pq);
+        sc[0] = ok ? st[CG_RZ] / pq : 0.0;
+        if (blockIdx.x == 0) {
+            if (ok) {
+                st[CG_RZOLD] = st[CG_RZ];
+                st[CG_ITS] = st[CG_ITS] + 1.0;
+                cg_host_store(host, CG_H_ITS, st[CG_ITS]);
+            } else {
+                // p.q <= 0: the operator is not positive definite along p
+                st[CG_DONE] = std::isfinite(pq) ? (double)CG_BREAKDOWN : (double)CG_NONFINITE;
+                cg_host_store(host, CG_H_DONE, st[CG_DONE]);
+            }
+        }
+    }
+    __syncthreads();
+    if (sc[0] == 0.0) return;
+    const T alpha = (T)sc[0];
+    double v[2] = {0.0, 0.0};
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+        x[e] = fmaT(alpha, p[e], x[e]);
+        const T rv = fmaT(-alpha, q[e], r[e]);
+        const T zv = pinv ? pinv[e] * rv : rv;
+        r[e] = rv;
+        z[e] = zv;
+        v[0] += (double)rv * (double)zv;
+        v[1] += (double)rv * (double)rv;
+    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
 inline unsigned grid1(long long n) { return (unsigned)((n + KB - 1) / KB); }
 
 }  // namespace
@@ -667,5 +834,42 @@ void kr_add_maxabs(T* x, const T* y, long long n, double* part, double* out, hip
     template void kr_add_maxabs<T>(T*, const T*, long long, double*, double*, hipStream_t, double*);
 INST_KR(float)
 INST_KR(double)
+
+int cg_blocks(long long n) { return krylov_blocks(n); }
+
+template <typename T>
+void cg_start(const T* b, const T* pinv, T* r, T* z, T* p, T* x, long long n, double* part, double* st,
+              double* host, double tol2, int maxit, hipStream_t s)
+{
+    k_cg_start<T><<<cg_blocks(n), KB, 0, s>>>(b, pinv, r, z, p, x, n, part, st, host, tol2, (double)maxit);
+}
+template <typename T>
+void cg_dir(const T* z, T* p, long long n, const double* part, double* st, double* host, hipStream_t s)
+{
+    const int nb = cg_blocks(n);
+    k_cg_dir<T><<<nb, KB, 0, s>>>(z, p, n, part, nb, st, host);
+}
+template <typename T>
+void cg_pq(const T* p, const T* q, long long n, double* part2, const double* st, hipStream_t s)
+{
+    k_cg_pq<T><<<cg_blocks(n), KB, 0, s>>>(p, q, n, part2, st);
+}
+template <typename T>
+void cg_alpha(T* x, T* r, T* z, const T* p, const T* q, const T* pinv, long long n, const double* part2,
+              double* part, double* st, double* host, hipStream_t s)
+{
+    const int nb = cg_blocks(n);
+    k_cg_alpha<T><<<nb, KB, 0, s>>>(x, r, z, p, q, pinv, n, part2, nb, part, st, host);
+}
+#define PF_CG_INST(T)                                                                                      \
+    template void cg_start<T>(const T*, const T*, T*, T*, T*, T*, long long, double*, double*, double*,    \
+                              double, int, hipStream_t);                                                   \
+    template void cg_dir<T>(const T*, T*, long long, const double*, double*, double*, hipStream_t);        \
+    template void cg_pq<T>(const T*, const T*, long long, double*, const double*, hipStream_t);            \
+    template void cg_alpha<T>(T*, T*, T*, const T*, const T*, const T*, long long, const double*, double*, \
+                              double*, double*, hipStream_t);
+PF_CG_INST(float)
+PF_CG_INST(double)
+#undef PF_CG_INST
 
 }  // namespace pfk

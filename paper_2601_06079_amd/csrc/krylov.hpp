@@ -51,4 +51,30 @@ template <typename T>
 void kr_add_maxabs(T* x, const T* y, long long n, double* part, double* out, hipStream_t s,
                    double* host = nullptr);
 
+// ---- preconditioned conjugate gradients (symmetric positive definite J) ----
+// Scalars live on the device (state: CG_NSTATE doubles); every block of a step
+// kernel reduces the previous kernel's partial sums in the same fixed order, so
+// all blocks agree on alpha and beta without a separate reduction launch.  The
+// host reads a pinned mirror (its, done, r.r) once per iteration.
+enum { CG_RZ = 0, CG_RZOLD = 1, CG_TOL2 = 2, CG_ITS = 3, CG_DONE = 4, CG_MAXIT = 5, CG_RR = 6, CG_NSTATE = 8 };
+enum { CG_H_ITS = 0, CG_H_DONE = 1, CG_H_RR = 2 };
+enum { CG_CONVERGED = 1, CG_MAXITS = 2, CG_BREAKDOWN = 3, CG_NONFINITE = 4 };
+// partial-sum blocks of the CG kernels for n unknowns (2 doubles each in part)
+int cg_blocks(long long n);
+// x = 0, r = b, z = P^-1 b, p = 0; partials (r.z, r.r); state reset (stop when
+// r.r <= tol2 or after maxit iterations); host mirror cleared
+template <typename T>
+void cg_start(const T* b, const T* pinv, T* r, T* z, T* p, T* x, long long n, double* part, double* st,
+              double* host, double tol2, int maxit, hipStream_t s);
+// the stop tests on (r.z, r.r); beta; p = z + beta p
+template <typename T>
+void cg_dir(const T* z, T* p, long long n, const double* part, double* st, double* host, hipStream_t s);
+// partials of p.q (q = J p)
+template <typename T>
+void cg_pq(const T* p, const T* q, long long n, double* part2, const double* st, hipStream_t s);
+// alpha = r.z / p.q; x += alpha p, r -= alpha q, z = P^-1 r; partials (r.z, r.r)
+template <typename T>
+void cg_alpha(T* x, T* r, T* z, const T* p, const T* q, const T* pinv, long long n, const double* part2,
+              double* part, double* st, double* host, hipStream_t s);
+
 }  // namespace pfk

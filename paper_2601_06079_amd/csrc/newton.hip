@@ -122,7 +122,7 @@ int col_readback(ColReadback** out)
 
 struct Opts {
     double rtol, atol, lmin, lmax;
-    int max_newton, m, max_its, precond, stagnation;
+    int max_newton, m, max_its, precond, stagnation, krylov;
 };
 
 Opts resolve(const pf_newton_opts* o)
@@ -140,6 +140,7 @@ Opts resolve(const pf_newton_opts* o)
     r.max_its = o->gmres_max_its;
     r.precond = o->precond;
     r.stagnation = o->stagnation;
+    r.krylov = o->krylov;
     return r;
 }
 
@@ -154,6 +155,21 @@ int check_opts(const Opts& o)
         return fail(PF_EINVAL, "unknown preconditioner");
     if (!(o.lmin > 0.0) || !(o.lmax >= o.lmin) || !(o.lmax < 1.0))
         return fail(PF_EINVAL, "need 0 < lin_rtol_min <= lin_rtol_max < 1");
+    if (o.krylov != PF_KRYLOV_GMRES && o.krylov != PF_KRYLOV_CG) return fail(PF_EINVAL, "unknown krylov solver");
+    return PF_OK;
+}
+
+// CG needs a symmetric positive definite Jacobian.  Allen-Cahn's is
+// (m/dt) M + L (N'(eta) + kappa K) with N'(eta) >= -W M_c (f'' >= -W for both
+// double wells) and M_c <= the lumped mass, so dt L W < 1 makes it positive
+// definite for every eta; the other models are not symmetric (or not definite).
+int check_cg(const pf_problem* p, double dt, const Opts& o)
+{
+    if (o.krylov != PF_KRYLOV_CG) return PF_OK;
+    if (p->model != PF_ALLEN_CAHN) return fail(PF_EINVAL, "krylov = CG needs the Allen-Cahn model");
+    if (!(dt * p->mobility * p->W < 1.0))
+        return fail(PF_EINVAL, "krylov = CG needs dt L W < 1 (got %g): the Jacobian may be indefinite",
+                    dt * p->mobility * p->W);
     return PF_OK;
 }
 
@@ -302,6 +318,57 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
     return check_launch("gmres");
 }
 
+// Preconditioned CG on J x = b (x overwritten, starting from 0) to
+// ||b - J x|| <= tol_abs, for a symmetric positive definite J (check_cg).  The
+// scalars stay on the device; the host reads the pinned mirror one iteration
+// behind the GPU.  Returns PF status; *its: iterations, *res: ||r||.
+template <typename T>
+int pcg(const LinOp<T>& A, NWS<T>& L, long long n, int max_its, bool prec, double bnorm, double tol_abs,
+        int* its, double* res, hipStream_t s)
+{
+    *its = 0;
+    *res = bnorm;
+    ColReadback* rb = nullptr;
+    if (int rc = col_readback(&rb)) return rc;
+    const T* pinv = prec ? L.pinv : nullptr;
+    T* r = L.V;
+    T* pdir = L.V + L.ld;
+    T* q = L.V + 2 * L.ld;
+    double* part = L.part;
+    double* part2 = L.part + 2 * pfk::cg_blocks(n);
+    double* st = L.dev + DEV_MISC;
+    double* hdev = rb->scal_dev();
+    const double* h = rb->scal();
+    pfk::cg_start<T>(L.b, pinv, r, L.z, pdir, L.x, n, part, st, hdev, tol_abs * tol_abs, max_its, s);
+    if (bnorm <= tol_abs) return check_launch("CG start");
+    int enq = 0, slot = 0;
+    bool pending = false;
+    for (;;) {
+        pfk::cg_dir<T>(L.z, pdir, n, part, st, hdev, s);
+        A.apply(pdir, q, s);
+        pfk::cg_pq<T>(pdir, q, n, part2, st, s);
+        pfk::cg_alpha<T>(L.x, r, L.z, pdir, q, pinv, n, part2, part, st, hdev, s);
+        ++enq;
+        if (int rc = check_launch("CG iteration")) return rc;
+        if (hipEventRecord(rb->ev[slot], s) != hipSuccess) return check_launch("CG event");
+        if (pending) {
+            if (hipEventSynchronize(rb->ev[slot ^ 1]) != hipSuccess) return check_launch("CG wait");
+            if (*(volatile const double*)&h[pfk::CG_H_DONE] != 0.0) break;
+        }
+        pending = true;
+        slot ^= 1;
+        if (enq > max_its) break;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return check_launch("CG sync");
+    const double done = *(volatile const double*)&h[pfk::CG_H_DONE];
+    *its = (int)*(volatile const double*)&h[pfk::CG_H_ITS];
+    *res = std::sqrt(std::max((double)*(volatile const double*)&h[pfk::CG_H_RR], 0.0));
+    if (done == pfk::CG_NONFINITE) return fail(PF_ENONFINITE, "CG met a non-finite value");
+    if (done == pfk::CG_BREAKDOWN)
+        return fail(PF_ENOCONV, "CG breakdown after %d iterations (Jacobian not positive definite)", *its);
+    return PF_OK;  // converged, or the iteration limit (an inexact correction, as GMRES)
+}
+
 template <typename T>
 double eps_of()
 {
@@ -371,8 +438,10 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
         const double lin = std::min(o.lmax, std::max(o.lmin, 0.1 * rk / r0));
         int its = 0;
         double lres = 0.0;
-        if (int rc = gmres<T>(A, L, n, o.m, o.max_its, o.precond == PF_PRECOND_JACOBI, rk, lin * rk,
-                              &its, &lres, s)) {
+        const bool jac = o.precond == PF_PRECOND_JACOBI;
+        if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(A, L, n, o.max_its, jac, rk, lin * rk, &its, &lres, s)
+                                              : gmres<T>(A, L, n, o.m, o.max_its, jac, rk, lin * rk, &its, &lres,
+                                                         s)) {
             status = rc;
             R.reason = -2;
             break;
@@ -454,8 +523,10 @@ int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, 
     double res = 0.0;
     // the adjoint solve is taken to the field-precision floor, not an inexact-Newton tolerance
     const double tol = (sizeof(T) == 4 ? 1e-6 : 1e-12) * bn;
-    if (int rc = gmres<T>(At, L, n, o.m, o.max_its * 4, o.precond == PF_PRECOND_JACOBI, bn, tol,
-                          &its, &res, s))
+    const bool jac = o.precond == PF_PRECOND_JACOBI;
+    // (Allen-Cahn's Jacobian is symmetric: CG solves the transposed system as well)
+    if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(At, L, n, o.max_its * 4, jac, bn, tol, &its, &res, s)
+                                          : gmres<T>(At, L, n, o.m, o.max_its * 4, jac, bn, tol, &its, &res, s))
         return rc;
     // Ubar (mass rows) += (m/dt) lambda ; theta_bar -= (dr/dtheta)^T lambda
     pfk::launch_mass_axpy<T>(g, inv_dt, L.x, Ubar, s);
@@ -513,6 +584,7 @@ int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
     if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
     const Opts o = resolve(opts);
     if (int rc = check_opts(o)) return rc;
+    if (int rc = check_cg(p, dt, o)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == PF_F32)
         return newton_t<float>(p, dt, (const float*)U_old, (float*)U, o, rep, ws, s);

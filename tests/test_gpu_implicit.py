@@ -46,6 +46,65 @@ def test_newton_step_matches_oracle(model, n, dtype):
         assert abs(host(Ug)[:N].sum() - Uold[:N].sum()) < (1e-10 if dtype == F64 else 1e-4) * N
 
 
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("n,bc,mass", [((12, 10), O.PERIODIC, 0), ((20, 17), O.NOFLUX, 0), ((16, 13), O.NOFLUX, 1),
+                                       ((5, 6, 4), O.PERIODIC, 0), ((7, 6, 5), O.NOFLUX, 1)])
+def test_newton_cg_matches_oracle_and_gmres(n, bc, mass, dtype):
+    """Allen-Cahn with conjugate gradients as the Newton linear solver (dt L W = 0.5
+    < 1: the Jacobian is symmetric positive definite): the same root as GMRES and as
+    the oracle's Newton step, lumped and consistent mass, periodic and no-flux."""
+    announce("newton cg", n, bc, mass, dtype)
+    g, o = pair(n, O.AC, O.F_SYM, dtype, W=1.0, kappa=1.0, mob=1.0, bc=bc)
+    g.mass = mass
+    o.mass = mass
+    Uold = rounded(I.uniform_field(n, -0.5, 0.5, seed=3), dtype)
+    dt = 0.5
+    rtol = 1e-11 if dtype == F64 else 1e-8
+    Uc = dev(Uold, dtype)
+    repc = S.newton_step(g, dt, dev(Uold, dtype), Uc, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8, krylov=A.KRYLOV_CG))
+    Ug = dev(Uold, dtype)
+    repg = S.newton_step(g, dt, dev(Uold, dtype), Ug, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8))
+    assert repc.converged and repg.converged, (repc, repg)
+    assert repc.gmres_its > 0
+    tol = 1e-9 if dtype == F64 else 1e-5
+    assert rel_l2(host(Uc), host(Ug)) < tol
+    Uo, conv, _, _ = O.newton_be(o, dt, Uold, rtol=1e-13, maxit=30, solver=0)
+    assert conv
+    assert rel_l2(host(Uc), Uo) < tol
+
+
+def test_newton_cg_full_size_2048():
+    """The implicit Allen-Cahn workload's shape (2048^2 on [0, 100]^2, no-flux, dt =
+    0.05): CG and GMRES reach the same step; every Newton correction's CG solve
+    converges, in as many iterations as GMRES needs Arnoldi steps or fewer."""
+    announce("newton cg 2048^2")
+    n = 2048
+    g = S.Problem(n=(n, n), model=A.ALLEN_CAHN, fe=A.F_01, dtype=F32, W=1.0, kappa=2.0, mobility=1.0,
+                  h=100.0 / (n - 1), bc=A.NOFLUX)
+    c0 = I.uniform_field((n, n), -0.05, 0.05, seed=0, base=0.5).astype(np.float32)
+    ws = S.workspace(g, A.OP_NEWTON)
+    Uc, Ug = dev(c0, F32), dev(c0, F32)
+    repc = S.newton_step(g, 0.05, dev(c0, F32), Uc, S.newton_opts(krylov=A.KRYLOV_CG), ws=ws)
+    repg = S.newton_step(g, 0.05, dev(c0, F32), Ug, ws=ws)
+    assert repc.converged and repg.converged
+    assert repc.gmres_its <= repg.gmres_its * 1.2 + 2
+    assert rel_l2(host(Uc), host(Ug)) < 1e-6
+
+
+def test_newton_cg_rejects_unsupported():
+    """CG needs Allen-Cahn with dt L W < 1 (else the Jacobian may be indefinite)."""
+    g, _ = pair((8, 8), O.AC, O.F_SYM, F32, W=1.0, kappa=1.0, mob=1.0)
+    U0 = dev(I.uniform_field((8, 8), -0.5, 0.5, seed=1), F32)
+    with pytest.raises(A.PFError):
+        S.newton_step(g, 1.0, U0, U0.clone(), S.newton_opts(krylov=A.KRYLOV_CG))
+    with pytest.raises(A.PFError):
+        S.newton_step(g, 0.5, U0, U0.clone(), S.newton_opts(krylov=7))
+    gc, oc = pair((8, 8), O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    Uc = dev(_ch_state(oc, 0.4, 0.05, 4), F32)
+    with pytest.raises(A.PFError):
+        S.newton_step(gc, 0.1, Uc, Uc.clone(), S.newton_opts(krylov=A.KRYLOV_CG))
+
+
 def test_newton_linear_mode_closed_form():
     """f == 0 Allen-Cahn: backward Euler damps a Fourier mode by 1/(1 + dt L kappa lambda_K)."""
     n, k, h, dt = (16, 12), (3, 2), 1.0, 0.7
