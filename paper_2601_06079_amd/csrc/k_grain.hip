@@ -269,6 +269,7 @@ __global__ __launch_bounds__(256) void k_gg_energy2d(Geom g, int P, T kappa, T g
     const int nx = g.n[0], ny = g.n[1];
     const long long N = g.N;
     const double h = g.h, detJ = 0.25 * h * h;
+    const double ih2 = 1.0 / (h * h);  // the gradients are summed unscaled (no divide per point)
     double en = 0.0, ms = 0.0;
     for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < N; idx += (long long)gridDim.x * 256) {
         const int i = (int)(idx % nx), j = (int)(idx / nx);
@@ -288,8 +289,8 @@ __global__ __launch_bounds__(256) void k_gg_energy2d(Geom g, int P, T kappa, T g
             const double wy[2][2] = {{GP, GM}, {GM, GP}};  // [qy][bottom, top]
             for (int k = 0; k < 4; ++k) {
                 const int qx = k & 1, qy = k >> 1;
-                const double gx = (wy[qy][0] * (v10 - v00) + wy[qy][1] * (v11 - v01)) / h;
-                const double gy = (wy[qx][0] * (v01 - v00) + wy[qx][1] * (v11 - v10)) / h;
+                const double gx = wy[qy][0] * (v10 - v00) + wy[qy][1] * (v11 - v01);  // h d/dx
+                const double gy = wy[qx][0] * (v01 - v00) + wy[qx][1] * (v11 - v10);  // h d/dy
                 const double q2 = q[k] * q[k];
                 S[k] += q2;
                 Q4[k] += q2 * q2;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gg_energy2d(Geom g, int P, T kappa, T g
             }
         }
         for (int k = 0; k < 4; ++k)
-            en += detJ * (A[k] + 0.5 * (double)gam * (S[k] * S[k] - Q4[k]) + 0.25 + 0.5 * (double)kappa * G[k]);
+            en += detJ * (A[k] + 0.5 * (double)gam * (S[k] * S[k] - Q4[k]) + 0.25 + 0.5 * (double)kappa * G[k] * ih2);
     }
     __shared__ double se[256], sm[256];
     se[threadIdx.x] = en;
