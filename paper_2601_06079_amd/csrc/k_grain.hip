@@ -107,6 +107,8 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
     const int gxo = tx0 + ex, gyo = ty0 + ey;
     const bool valid = ex < GT && ey < GT && gxo < nx && gyo < ny;
     const T gp = (T)GP, gm = (T)GM;
+    // 2^-b of the output node's no-flux faces (1 on periodic grids), once per node
+    const T ib = valid ? (T)1 / (T)bfactor<2>(g, gxo, gyo, 0) : (T)1;
     // C. FG fields per round: shares of FG fields to LDS, one barrier, node sums
     for (int f0 = 0; f0 < P; f0 += FG) {
         const int nf = min(FG, P - f0);
@@ -155,7 +157,6 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
                                  (e[GB + tid + GE] + e[tid + GE + 1]));
                 const long long o = (long long)(f0 + j) * N + (long long)gyo * nx + gxo;
                 const T uc = sf[(f0 + j) * GS * GS + eb + GS + 1];
-                const T ib = (T)1 / (T)bfactor<2>(g, gxo, gyo, 0);
                 if (MODE == 0) {
                     out[o] = uc - dtm * r;
                 } else if (MODE == 1) {
@@ -230,6 +231,7 @@ __global__ __launch_bounds__(GB) void k_gg_jvp2d(Geom g, int P, T L, T kappa, T 
     const int gxo = tx0 + ex, gyo = ty0 + ey;
     const bool valid = ex < GT && ey < GT && gxo < nx && gyo < ny;
     const T gp = (T)GP, gm = (T)GM;
+    const T ib = valid ? (T)1 / (T)bfactor<2>(g, gxo, gyo, 0) : (T)1;  // 2^-b, once per node
     for (int f = 0; f < P; ++f) {
         const T* b = su + f * GS * GS + eb;
         const T* c = sv + f * GS * GS + eb;
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(GB) void k_gg_jvp2d(Geom g, int P, T L, T kappa, T 
             const T r = L * ((sE[3 * GB + tid] + sE[2 * GB + tid + 1]) +
                              (sE[GB + tid + GE] + sE[tid + GE + 1]));
             const long long o = (long long)f * N + (long long)gyo * nx + gxo;
-            out[o] = fmaT(inv_dt * h * h, v11, r) / (T)bfactor<2>(g, gxo, gyo, 0);
+            out[o] = fmaT(inv_dt * h * h, v11, r) * ib;
         }
         __syncthreads();
     }
