@@ -91,6 +91,29 @@ def test_newton_cg_full_size_2048():
     assert rel_l2(host(Uc), host(Ug)) < 1e-6
 
 
+def test_newton_cg_unpreconditioned_and_capped():
+    """CG without a preconditioner reaches the same root; with the iterations per
+    correction capped at 3 each correction is inexact, Newton takes more of them
+    and still converges (or reports that it did not, never a wrong 'converged')."""
+    n = (24, 19)
+    g, o = pair(n, O.AC, O.F_SYM, F64, W=1.0, kappa=1.0, mob=1.0, bc=O.NOFLUX)
+    Uold = I.uniform_field(n, -0.5, 0.5, seed=5)
+    dt = 0.5
+    U1 = dev(Uold, F64)
+    r1 = S.newton_step(g, dt, dev(Uold, F64), U1,
+                       S.newton_opts(rtol=1e-11, lin_rtol_min=1e-8, krylov=A.KRYLOV_CG, precond=A.PRECOND_NONE))
+    assert r1.converged
+    Uo, conv, _, _ = O.newton_be(o, dt, Uold, rtol=1e-13, maxit=30, solver=0)
+    assert conv and rel_l2(host(U1), Uo) < 1e-9
+    U2 = dev(Uold, F64)
+    r2 = S.newton_step(g, dt, dev(Uold, F64), U2,
+                       S.newton_opts(rtol=1e-9, gmres_max_its=3, max_newton=60, krylov=A.KRYLOV_CG))
+    assert r2.gmres_its <= 3 * r2.newton_its
+    if r2.converged:
+        assert r2.newton_its > r1.newton_its
+        assert rel_l2(host(U2), Uo) < 1e-7
+
+
 def test_newton_cg_rejects_unsupported():
     """CG needs Allen-Cahn with dt L W < 1 (else the Jacobian may be indefinite)."""
     g, _ = pair((8, 8), O.AC, O.F_SYM, F32, W=1.0, kappa=1.0, mob=1.0)
