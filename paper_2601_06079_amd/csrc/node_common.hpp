@@ -312,6 +312,21 @@ template <int D>
 __device__ __forceinline__ bool node_of(const Geom& g, long long idx, int& i, int& j, int& k)
 {
     if (idx >= g.N) return false;
+    if (g.N <= 0xffffffffll) {
+        // 32-bit division (a 64-bit one is a long instruction sequence on the GPU)
+        const unsigned u = (unsigned)idx, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
+        const unsigned r = u / n0;
+        i = (int)(u - r * n0);
+        if (D == 3) {
+            const unsigned r2 = r / n1;
+            j = (int)(r - r2 * n1);
+            k = (int)r2;
+        } else {
+            j = (int)r;
+            k = 0;
+        }
+        return true;
+    }
     i = (int)(idx % g.n[0]);
     long long r = idx / g.n[0];
     j = (int)(r % g.n[1]);
