@@ -708,8 +708,8 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build (--gpus must be 1)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no "
+                                   "multi-GPU path (--gpus must be 1)"}))
         sys.exit(2)
     import torch
 

@@ -43,7 +43,7 @@ typedef enum pf_status {
     PF_EDEVICE = 2,     /* a HIP runtime call failed (message in pf_last_error) */
     PF_ENOCONV = 3,     /* Newton did not converge; U holds the last iterate */
     PF_ENONFINITE = 4,  /* a non-finite residual norm was met */
-    PF_EUNSUPPORTED = 5 /* valid request this build does not implement */
+    PF_EUNSUPPORTED = 5 /* valid request the library does not implement */
 } pf_status;
 
 enum { PF_PERIODIC = 0, PF_NOFLUX = 1 };       /* boundary condition (Supp. Note 3) */

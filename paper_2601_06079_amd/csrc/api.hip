@@ -252,8 +252,8 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
             b = newton_workspace_bytes(p, 30);
             break;
         case PF_OP_VJP:
-            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: no adjoint in this build");
-            if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: no adjoint in this build");
+            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: the adjoint is not implemented");
+            if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: the adjoint is not implemented");
             b = vjp_workspace_bytes(p);
             break;
         default: return fail(PF_EINVAL, "unknown op %d", op);
