@@ -195,6 +195,32 @@ def test_multigrid_across_poisson_ratio(n, nu):
     assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(f)
 
 
+@pytest.mark.parametrize("n,dtype", [((257, 129), torch.float32), ((65, 65, 33), torch.float32),
+                                     ((129, 65), torch.float64)])
+def test_multigrid_deterministic_and_nearly_incompressible(n, dtype):
+    """Two solves on fresh workspaces give the same bits (fixed-order reductions
+    everywhere, including the one-workgroup coarse end in 2-D) for a nearly
+    incompressible material (nu = 0.49, lam / mu = 49).  The FP64 solve's true
+    residual through the oracle's operator meets its tolerance (the oracle's own
+    plain CG is too slow at this conditioning); the FP32 solution is within 2e-3 of
+    that FP64 one: K is ill-conditioned here, so a residual of 1e-6 bounds the
+    error only up to cond(K) (measured 4e-4 at 257 x 129)."""
+    announce("el mg determinism", n, dtype)
+    g, o = pair(n, dtype, h=100.0 / (max(n) - 1), nu=0.49)
+    rtol = 1e-6 if dtype == torch.float32 else 1e-10
+    u1, r1 = EL.el_solve(g, rtol=rtol, maxit=400)
+    u2, r2 = EL.el_solve(g, rtol=rtol, maxit=400)
+    assert r1.converged and r2.converged and r1.levels >= 3
+    assert r1.iterations == r2.iterations and torch.equal(u1, u2)
+    g64, _ = pair(n, torch.float64, h=100.0 / (max(n) - 1), nu=0.49)
+    u64 = u1 if dtype == torch.float64 else EL.el_solve(g64, rtol=1e-10, maxit=400)[0]
+    f = O.el_rhs(o)
+    res = O.el_apply(o, host(u64)) - f
+    assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(f)
+    if dtype == torch.float32:
+        assert rel_l2(host(u1), host(u64)) < 2e-3
+
+
 def test_multigrid_edge_cases():
     g, o = pair((33, 17), torch.float64, h=2.0)
     rng = np.random.default_rng(5)
