@@ -14,6 +14,15 @@
  *     (x fastest).  Cahn-Hilliard states U hold the c plane at offset 0 and
  *     the mu plane at offset N (N = number of nodes).  Element type is
  *     float (PF_F32) or double (PF_F64) as pf_problem.dtype says.
+ *   - Every call that enqueues device work takes a context (pf_ctx, made by
+ *     pf_create for one device) and must be made with that device current.
+ *     The context holds what persists between calls: the device properties
+ *     the launchers size their grids with, the pinned host slots the Newton,
+ *     GMRES and CG kernels store their scalars into (allocated by pf_create,
+ *     never inside a compute call), the elasticity smoother's eigenvalue cache
+ *     and the batch autotuner's results.  Calls that share a context must not
+ *     run concurrently on different host threads (one context per thread, or
+ *     external locking).
  *   - The caller owns every buffer.  The library allocates no device memory
  *     on any compute path and never frees caller memory.  Scratch needs are
  *     reported by pf_workspace_size and passed in as `ws` (device memory,
@@ -23,7 +32,8 @@
  *     stated otherwise.
  *   - Return value is a pf_status.  PF_EINVAL is returned before anything is
  *     enqueued for a malformed problem or argument; pf_last_error() then
- *     gives a thread-local message.  No C++ exception crosses this ABI.
+ *     gives a thread-local message.  No C++ exception crosses this ABI: a
+ *     host allocation that fails inside a call returns PF_EDEVICE.
  *   - Thread safety: calls on different streams from different host threads
  *     are independent; concurrent calls that share buffers race.
  */
@@ -45,6 +55,10 @@ typedef enum pf_status {
     PF_ENONFINITE = 4,  /* a non-finite residual norm was met */
     PF_EUNSUPPORTED = 5 /* valid request the library does not implement */
 } pf_status;
+
+/* Per-device context (opaque).  See pf_create. */
+typedef struct pf_ctx pf_ctx;
+enum { PF_HOST_ONLY = -1 }; /* pf_create device: a context for sizing and validation only */
 
 enum { PF_PERIODIC = 0, PF_NOFLUX = 1 };       /* boundary condition (Supp. Note 3) */
 enum { PF_ALLEN_CAHN = 0, PF_CAHN_HILLIARD = 1,
@@ -124,6 +138,26 @@ const char* pf_last_error(void);
 /* Library ABI version (major * 100 + minor). */
 int pf_version(void);
 
+/* Make a context for device `device` (a HIP device ordinal): queries its
+ * properties and allocates the pinned host slots that the Newton/GMRES, CG and
+ * elasticity solvers read their scalars from.  The current device is left as it
+ * was.  device = PF_HOST_ONLY makes a context without a device, accepted by the
+ * host-only queries (pf_workspace_size, pf_launch_shape, pf_el_workspace_size)
+ * and by argument validation; calls that enqueue device work return PF_EINVAL
+ * with it.  *out receives the context (NULL on failure).  PF_EDEVICE if the
+ * device does not exist or an allocation fails. */
+int pf_create(int device, pf_ctx** out);
+/* Free a context and everything it owns (NULL is accepted).  No call may be
+ * using it; work already enqueued with it need not have finished. */
+int pf_destroy(pf_ctx* ctx);
+/* The device ordinal of a context (PF_HOST_ONLY for a host-only one). */
+int pf_ctx_device(const pf_ctx* ctx, int* device);
+
+/* Copy `bytes` (a multiple of 16; src, dst 16-byte aligned, not overlapping)
+ * with 16-byte loads and stores: the practical HBM (or Infinity Cache)
+ * bandwidth against which the stencil kernels are measured.  Asynchronous. */
+int pf_stream_copy(pf_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream);
+
 /* Launch-shape overrides, process-global (value 0 restores the automatic
  * choice).  Used by the autotuner; results never depend on them, except that on
  * no-flux grids the steps fused per launch change boundary-adjacent values in
@@ -133,22 +167,25 @@ int pf_version(void);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
  *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product;
  *   PF_TUNE_EL_PLANES:      z-planes (2-D: rows) per wave of the elasticity operator;
+ *   PF_TUNE_STREAM2D_SEAM:  1 = fused 2-D launches recompute the rows where chunks meet
+ *                           (each wave alone); 0 = the waves of a workgroup share them
+ *                           through LDS where the chunk plan allows (periodic grids);
  *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid);
  *                           2 = multigrid with every level launched separately;
  *                           v >= 3 = the multigrid's coarse grids of at most v
  *                           nodes run in one workgroup (default: 1200 in 2-D,
  *                           none in 3-D). */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
-       PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5 };
+       PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5, PF_TUNE_STREAM2D_SEAM = 6 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
-/* The launch shape pf_step_explicit uses for p (2-D): steps fused per launch,
- * rows per wavefront, prefetch depth.  Host-only. */
-int pf_launch_shape(const pf_problem* p, int* ks, int* ty, int* depth);
+/* The launch shape pf_step_explicit uses for p (2-D) on the context's device:
+ * steps fused per launch, rows per wavefront, prefetch depth.  Host-only. */
+int pf_launch_shape(const pf_ctx* ctx, const pf_problem* p, int* ks, int* ty, int* depth);
 
 /* Bytes of device scratch `ws` that operation `op` needs for problem p
  * (0 when none).  Host-only; enqueues nothing. */
-int pf_workspace_size(const pf_problem* p, int op, size_t* bytes);
+int pf_workspace_size(const pf_ctx* ctx, const pf_problem* p, int op, size_t* bytes);
 
 /* r = r(U, theta) of Eq. 11 (no mass/time term).
  *   Allen-Cahn:     r = L [ N(eta) + kappa K eta ]
@@ -161,8 +198,10 @@ int pf_workspace_size(const pf_problem* p, int op, size_t* bytes);
  *   Coupled (Eq. 7):  r_c   = M_c K mu
  *                     r_mu  = m mu - sum_e sum_q |J| [f_a'(c_q)(1 - h(eta_q)) + f_b'(c_q) h(eta_q)] phi_a
  *                     r_eta = M_eta [ sum_e sum_q |J| (f_b - f_a)(c_q) h'(eta_q) phi_a + kappa K eta ]
- * U and r: device, ndof elements (N, 2N or 3N), must not alias.  Asynchronous. */
-int pf_residual(const pf_problem* p, const void* U, void* r, void* stream);
+ * U and r: device, ndof elements (N, 2N or 3N), must not alias.  ws: the
+ * pf_workspace_size(PF_OP_RESIDUAL) scratch, which is 0 bytes (NULL is
+ * accepted).  Asynchronous. */
+int pf_residual(pf_ctx* ctx, const pf_problem* p, const void* U, void* r, void* ws, void* stream);
 
 /* nsteps forward-Euler steps of Eq. 12 with the lumped mass, in place on U:
  *   Allen-Cahn:     eta <- eta - dt r(eta) / m
@@ -176,7 +215,7 @@ int pf_residual(const pf_problem* p, const void* U, void* r, void* stream);
  * ws: device scratch of pf_workspace_size(PF_OP_STEP_EXPLICIT) bytes (one
  * ping-pong field; two for the coupled model).  nsteps >= 0, dt > 0.
  * Asynchronous. */
-int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
+int pf_step_explicit(pf_ctx* ctx, const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
                      void* stream);
 
 /* out[0] = E_h(U) = sum_e sum_q |J| [ f(c_q) + kappa/2 |grad c_q|^2 ]  (Eqs. 5-6)
@@ -186,7 +225,7 @@ int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, vo
  * out: device pointer to 2 doubles; accumulation in FP64 with a fixed
  * reduction order (bitwise reproducible).  ws: pf_workspace_size(PF_OP_ENERGY).
  * Asynchronous. */
-int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* stream);
+int pf_energy(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void* ws, void* stream);
 
 /* Jv = (dR/dU) v for R = inv_dt M (U - U_old) + r(U) (Eq. 14; inv_dt = 0
  * gives dr/dU):
@@ -196,7 +235,7 @@ int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* s
  * N'(u) v = sum_e sum_q |J| f''(u_q) v_q phi_a(q).  Matrix-free (the Jacobian
  * of Sec. 2.3 is never formed).  U, v, Jv: device, ndof elements; Jv must not
  * alias U or v.  Asynchronous. */
-int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv,
+int pf_jvp(pf_ctx* ctx, const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv,
            void* stream);
 
 /* ---------------------------------------------------------------------- */
@@ -244,7 +283,7 @@ void pf_newton_default_opts(pf_newton_opts* o);
  * U_old is not modified.  ws: pf_workspace_size(PF_OP_NEWTON) bytes.
  * Host-synchronous: returns when the step is done (PF_OK or PF_ENOCONV /
  * PF_ENONFINITE with rep filled).  rep may be NULL. */
-int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
+int pf_newton_step(pf_ctx* ctx, const pf_problem* p, double dt, const void* U_old, void* U,
                    const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream);
 
 /* ---------------------------------------------------------------------- */
@@ -252,9 +291,17 @@ int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
 /* ---------------------------------------------------------------------- */
 enum { PF_VJP_RESIDUAL = 0, PF_VJP_EXPLICIT_STEP = 1, PF_VJP_NEWTON_STEP = 2 };
 
+enum { PF_VJP_THETA_HOST = 1 }; /* pf_vjp flags: theta_bar is a host pointer */
 /* Vector-Jacobian products of one building block, accumulated into Ubar and
- * theta_bar (device pointer to 3 doubles: mobility, kappa, W):
- *   PF_VJP_RESIDUAL:       Ubar += (dr/dU)^T vbar,   theta_bar += (dr/dtheta)^T vbar   at U
+ * theta_bar (3 doubles: mobility, kappa, W; a device pointer, or a host pointer
+ * with flags = PF_VJP_THETA_HOST, which makes the call host-synchronous):
+ *   PF_VJP_RESIDUAL:       U_old == NULL: the residual r of Eq. 11:
+ *                            Ubar += (dr/dU)^T vbar, theta_bar += (dr/dtheta)^T vbar at U;
+ *                          U_old != NULL: the backward-Euler residual of Eq. 14,
+ *                            R = M (U - U_old)/dt + r(U): Ubar += (dR/dU)^T vbar
+ *                            = (M/dt) vbar + (dr/dU)^T vbar (M symmetric), theta_bar as
+ *                            above (U_old enters R linearly and its values are not
+ *                            needed; dt must be > 0)
  *   PF_VJP_EXPLICIT_STEP:  for S(U) = one pf_step_explicit step from U:
  *                          Ubar += (dS/dU)^T vbar,  theta_bar += (dS/dtheta)^T vbar
  *                          (Cahn-Hilliard: c planes only; mu is a derived output)
@@ -262,17 +309,21 @@ enum { PF_VJP_RESIDUAL = 0, PF_VJP_EXPLICIT_STEP = 1, PF_VJP_NEWTON_STEP = 2 };
  *                          solve (dR/dU)^T lambda = vbar (GMRES, same opts as
  *                          the forward step), then Ubar(U_old) += (M/dt) lambda,
  *                          theta_bar -= (dr/dtheta)^T lambda   (II.5-II.6).
+ * U_old is read only by PF_VJP_RESIDUAL (see there) and may be NULL otherwise.
  * theta_bar accumulates in FP64 with a fixed reduction order.  dt is ignored
- * for PF_VJP_RESIDUAL.  ws: pf_workspace_size(PF_OP_VJP).  Asynchronous,
- * except PF_VJP_NEWTON_STEP which is host-synchronous like pf_newton_step. */
-int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* vbar,
-           void* Ubar, double* theta_bar, void* ws, void* stream);
+ * for PF_VJP_RESIDUAL without U_old.  ws: pf_workspace_size(PF_OP_VJP).
+ * Asynchronous, except PF_VJP_NEWTON_STEP (host-synchronous like
+ * pf_newton_step) and PF_VJP_THETA_HOST. */
+int pf_vjp(pf_ctx* ctx, const pf_problem* p, int kind, double dt, const void* U, const void* U_old,
+           const void* vbar, void* Ubar, double* theta_bar, int flags, void* ws, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Ragged batches of independent 2-D problems (many samples in one launch) */
 /* ---------------------------------------------------------------------- */
 /* One sample of a batch: its own grid and material parameters.  All samples
- * share the base problem's model, free energy, dtype and (periodic) boundary. */
+ * share the base problem's model, free energy, dtype and (periodic) boundary.
+ * A batch holds 1 .. PF_BATCH_MAX_COUNT samples. */
+enum { PF_BATCH_MAX_COUNT = 1 << 20 };
 typedef struct pf_batch_sample {
     int64_t offset; /* element offset of this sample's field in the packed arrays */
     int64_t n[3];   /* nodes per axis (n[2] ignored); each sample < 2 GiB */
@@ -301,7 +352,7 @@ int pf_batch_plan_size(const pf_problem* base, const pf_batch_sample* samples, i
  * autotuned choice for this batch shape if pf_batch_autotune ran, else the
  * defaults.  Sample ranges must not overlap.  Host-synchronous (waits for the
  * copy).  base supplies dim (2), bc (periodic), model, fe and dtype only. */
-int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+int pf_batch_plan(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                   int ks, int ty, int depth, void* plan_dev, size_t plan_bytes,
                   pf_batch_info* info, void* stream);
 
@@ -317,8 +368,8 @@ int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes);
  * ks >= 2 each launch advances two steps and writes both states (bitwise those
  * of single steps).
  * Allen-Cahn and the Cahn-Hilliard c plane (mu is not produced).  Asynchronous. */
-int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps, void* U,
-                             void* ws, void* traj, void* stream);
+int pf_step_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void* plan, int64_t nsteps,
+                             void* U, void* ws, void* traj, void* stream);
 
 /* Adjoint of nsteps batched Allen-Cahn explicit steps (Supp. Note 2 applied
  * step by step).  states + k * info->total holds the input of step k+1
@@ -336,16 +387,17 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
  * PF_EUNSUPPORTED.  ws: pf_batch_workspace_size(PF_OP_VJP) of the same info,
  * kept between the calls of one trajectory.  Asynchronous. */
 enum { PF_VJP_BEGIN = 1, PF_VJP_END = 2 };
-int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
+int pf_vjp_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void* plan, int64_t nsteps,
                             const void* states, void* lam, double* theta_bar, void* ws, int flags,
                             void* stream);
 
 /* Launch-shape autotuner: times the batched explicit kernel for every
  * (ks, ty, depth) candidate with HIP events on U_scratch (overwritten) and ws,
- * keeps the fastest per step, records it for later pf_batch_plan calls with
- * zero shape arguments, and leaves its plan in plan_dev / *best.
+ * keeps the fastest per step, records it in the context for later
+ * pf_batch_plan calls with zero shape arguments, and leaves its plan in
+ * plan_dev / *best.
  * plan_bytes should be pf_batch_plan_size(..., 3, 16, ...).  Host-synchronous. */
-int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+int pf_batch_autotune(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                       void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
                       pf_batch_info* best, double* best_us_per_step, void* stream);
 
@@ -391,16 +443,16 @@ typedef struct pf_el_report {
  * (seven fields plus FP64 partial sums; with multigrid also one more field,
  * three fields per coarser grid (under 1/7 of a field in 2-D, 1/2 in 3-D, in
  * total) and the 9^d eigenvalue-estimate vectors). */
-int pf_el_workspace_size(const pf_elastic* p, size_t* bytes);
+int pf_el_workspace_size(const pf_ctx* ctx, const pf_elastic* p, size_t* bytes);
 
 /* y = K u (the stiffness of Eqs. 3-4 with the identity rows above).  u, y
  * device, distinct.  Asynchronous. */
-int pf_el_apply(const pf_elastic* p, const void* u, void* y, void* stream);
+int pf_el_apply(pf_ctx* ctx, const pf_elastic* p, const void* u, void* y, void* stream);
 
 /* f = the eigenstrain load: f_i(a) = sum over elements and Gauss points of
  * |J| (dim lam + 2 mu) e0(|x_q|) d_i phi_a(x_q); 0 on the fixed components.
  * Evaluated in FP64.  Asynchronous. */
-int pf_el_rhs(const pf_elastic* p, void* f, void* stream);
+int pf_el_rhs(pf_ctx* ctx, const pf_elastic* p, void* f, void* stream);
 
 /* Solve K u = b by conjugate gradients from u = 0 until ||r|| <= rtol ||b||
  * or maxit iterations; b = NULL solves for the eigenstrain load.  When every
@@ -409,19 +461,19 @@ int pf_el_rhs(const pf_elastic* p, void* f, void* stream);
  * grids), Q1 rediscretised at 2h, trilinear transfers, two damped-Jacobi sweeps
  * before and after and 2 x (longest axis) on the coarsest grid (4 to 32),
  * damping 1.6 / lambda_max of D^-1 K.  lambda_max depends on dim and nu
- * only; the first solve of a (dim, nu) pair in the process estimates it by
+ * only; the first solve of a (dim, nu) pair on a context estimates it by
  * power iteration on a 9^d grid (about a millisecond).  Other grids, or
  * pf_tune_set(PF_TUNE_EL_MG, 1), use plain CG.  The fixed components are identity rows of K (u there matches b to
  * the tolerance).  Host-synchronous; returns PF_OK, PF_ENOCONV (u holds the
  * last iterate) or PF_ENONFINITE; rep may be NULL. */
-int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,
+int pf_el_solve(pf_ctx* ctx, const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,
                 pf_el_report* rep, void* ws, void* stream);
 
 /* out[0] (device double) = g . u, accumulated in FP64 in a fixed order;
  * g = NULL selects the volume change int div u dV of Eq. 21 (the outward
  * face-normal component of u weighted by each node's face share).
  * Asynchronous. */
-int pf_el_objective(const pf_elastic* p, const void* g, const void* u, double* out, void* ws,
+int pf_el_objective(pf_ctx* ctx, const pf_elastic* p, const void* g, const void* u, double* out, void* ws,
                     void* stream);
 
 /* Sensitivities of O = g . u (g = NULL: the volume change) at the equilibrium u
@@ -429,8 +481,8 @@ int pf_el_objective(const pf_elastic* p, const void* g, const void* u, double* o
  * method of Eq. 18: solve K lambda = g (fixed components of g ignored), then
  * dO/dtheta = lambda . (df/dtheta - dK/dtheta u).  out (host, 3 doubles) =
  * {O, dO/dE, dO/dnu}.  Host-synchronous; the adjoint solve uses rtol / maxit. */
-int pf_el_sensitivity(const pf_elastic* p, const void* g, const void* u, double* out, double rtol,
-                      int32_t maxit, pf_el_report* rep, void* ws, void* stream);
+int pf_el_sensitivity(pf_ctx* ctx, const pf_elastic* p, const void* g, const void* u, double* out,
+                      double rtol, int32_t maxit, pf_el_report* rep, void* ws, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Learned K-step surrogate for 2-D Cahn-Hilliard (added by this library;  */

@@ -7,6 +7,7 @@ no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as ct
 import os
 
@@ -14,6 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpfhip.so")
 
 PF_OK, PF_EINVAL, PF_EDEVICE, PF_ENOCONV, PF_ENONFINITE, PF_EUNSUPPORTED = range(6)
+HOST_ONLY = -1  # pf_create: a context without a device (sizing and validation)
+VJP_THETA_HOST = 1  # pf_vjp flags: theta_bar is a host pointer
+BATCH_MAX_COUNT = 1 << 20
 PERIODIC, NOFLUX = 0, 1
 ALLEN_CAHN, CAHN_HILLIARD, COUPLED, GRAIN = 0, 1, 2, 3
 F_SYM, F_01 = 0, 1
@@ -21,6 +25,7 @@ F32, F64 = 0, 1
 MASS_LUMPED, MASS_CONSISTENT = 0, 1
 OP_RESIDUAL, OP_STEP_EXPLICIT, OP_ENERGY, OP_NEWTON, OP_VJP, OP_JVP = range(6)
 TUNE_STREAM2D_ROWS, TUNE_STREAM2D_DEPTH, TUNE_STREAM2D_FUSE, TUNE_JVP3D_PLANES = 0, 1, 2, 3
+TUNE_STREAM2D_SEAM = 6
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 VJP_RESIDUAL, VJP_EXPLICIT_STEP, VJP_NEWTON_STEP = 0, 1, 2
 VJP_BEGIN, VJP_END = 1, 2  # flags of pf_vjp_explicit_batched
@@ -84,20 +89,25 @@ def lib():
     L = ct.CDLL(LIB_PATH)
     P = ct.POINTER(pf_problem)
     vp, i32, i64, f64 = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_double
+    ip = ct.POINTER(ct.c_int)
     sig = {
         "pf_last_error": (ct.c_char_p, []),
         "pf_version": (i32, []),
+        "pf_create": (i32, [i32, ct.POINTER(vp)]),
+        "pf_destroy": (i32, [vp]),
+        "pf_ctx_device": (i32, [vp, ip]),
         "pf_tune_set": (i32, [i32, i32]),
-        "pf_tune_get": (i32, [i32, ct.POINTER(ct.c_int)]),
-        "pf_workspace_size": (i32, [P, i32, ct.POINTER(ct.c_size_t)]),
-        "pf_residual": (i32, [P, vp, vp, vp]),
-        "pf_step_explicit": (i32, [P, f64, i64, vp, vp, vp]),
-        "pf_energy": (i32, [P, vp, vp, vp, vp]),
-        "pf_jvp": (i32, [P, f64, vp, vp, vp, vp]),
+        "pf_tune_get": (i32, [i32, ip]),
+        "pf_launch_shape": (i32, [vp, P, ip, ip, ip]),
+        "pf_workspace_size": (i32, [vp, P, i32, ct.POINTER(ct.c_size_t)]),
+        "pf_residual": (i32, [vp, P, vp, vp, vp, vp]),
+        "pf_step_explicit": (i32, [vp, P, f64, i64, vp, vp, vp]),
+        "pf_energy": (i32, [vp, P, vp, vp, vp, vp]),
+        "pf_jvp": (i32, [vp, P, f64, vp, vp, vp, vp]),
         "pf_newton_default_opts": (None, [ct.POINTER(pf_newton_opts)]),
-        "pf_newton_step": (i32, [P, f64, vp, vp, ct.POINTER(pf_newton_opts),
+        "pf_newton_step": (i32, [vp, P, f64, vp, vp, ct.POINTER(pf_newton_opts),
                                  ct.POINTER(pf_newton_report), vp, vp]),
-        "pf_vjp": (i32, [P, i32, f64, vp, vp, vp, vp, vp, vp]),
+        "pf_vjp": (i32, [vp, P, i32, f64, vp, vp, vp, vp, vp, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -105,6 +115,43 @@ def lib():
         fn.argtypes = args
     _lib = L
     return L
+
+
+_ctxs = {}
+
+
+def ctx(device=None) -> ct.c_void_p:
+    """The library's default context for a device (torch's current device when
+    None): made by pf_create on first use, freed by pf_destroy at exit."""
+    if device is None or getattr(device, "type", None) == "cuda":
+        index = getattr(device, "index", None)
+        if index is None:
+            import torch
+            index = torch.cuda.current_device()
+        device = index
+    device = int(device)
+    h = _ctxs.get(device)
+    if h is None:
+        h = ct.c_void_p()
+        check(lib().pf_create(device, ct.byref(h)))
+        _ctxs[device] = h
+    return h
+
+
+def host_ctx() -> ct.c_void_p:
+    """A context without a device: size queries and argument validation only."""
+    return ctx(HOST_ONLY)
+
+
+def _destroy_contexts():
+    if _lib is None:
+        return
+    for h in _ctxs.values():
+        _lib.pf_destroy(h)
+    _ctxs.clear()
+
+
+atexit.register(_destroy_contexts)
 
 
 def bind_optional(name, restype, argtypes):

@@ -22,11 +22,11 @@ def _bind():
     vp, i32, i64, f64 = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_double
     sig = {
         "pf_batch_plan_size": (i32, [P, S, i32, i32, i32, ct.POINTER(ct.c_size_t)]),
-        "pf_batch_plan": (i32, [P, S, i32, f64, i32, i32, i32, vp, ct.c_size_t, I, vp]),
+        "pf_batch_plan": (i32, [vp, P, S, i32, f64, i32, i32, i32, vp, ct.c_size_t, I, vp]),
         "pf_batch_workspace_size": (i32, [I, i32, ct.POINTER(ct.c_size_t)]),
-        "pf_step_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp]),
-        "pf_vjp_explicit_batched": (i32, [I, vp, i64, vp, vp, vp, vp, i32, vp]),
-        "pf_batch_autotune": (i32, [P, S, i32, f64, vp, vp, vp, ct.c_size_t, I,
+        "pf_step_explicit_batched": (i32, [vp, I, vp, i64, vp, vp, vp, vp]),
+        "pf_vjp_explicit_batched": (i32, [vp, I, vp, i64, vp, vp, vp, vp, i32, vp]),
+        "pf_batch_autotune": (i32, [vp, P, S, i32, f64, vp, vp, vp, ct.c_size_t, I,
                                     ct.POINTER(ct.c_double), vp]),
     }
     for name, (res, args) in sig.items():
@@ -84,13 +84,13 @@ class Batch:
                                           ct.byref(nb)))
         self.plan = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         self.info = A.pf_batch_info()
-        A.check(self.L.pf_batch_plan(ct.byref(self.base), self.samples, self.count, self.dt, ks, ty,
+        A.check(self.L.pf_batch_plan(A.ctx(self.device), ct.byref(self.base), self.samples, self.count, self.dt, ks, ty,
                                      depth, ct.c_void_p(self.plan.data_ptr()), self.plan.numel(),
                                      ct.byref(self.info), _stream()))
         # a single-step plan for trajectory mode and step counts that are not a multiple of ks
         self.info1 = A.pf_batch_info()
         self.plan1 = torch.empty_like(self.plan)
-        A.check(self.L.pf_batch_plan(ct.byref(self.base), self.samples, self.count, self.dt, 1,
+        A.check(self.L.pf_batch_plan(A.ctx(self.device), ct.byref(self.base), self.samples, self.count, self.dt, 1,
                                      self.info.ty, self.info.depth,
                                      ct.c_void_p(self.plan1.data_ptr()), self.plan1.numel(),
                                      ct.byref(self.info1), _stream()))
@@ -123,7 +123,7 @@ class Batch:
         if ws is None:
             ws = self.workspace(A.OP_STEP_EXPLICIT)
         if traj is not None:  # the fused plan: two states per launch when ks >= 2
-            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info),
+            A.check(self.L.pf_step_explicit_batched(A.ctx(self.device), ct.byref(self.info),
                                                     ct.c_void_p(self.plan.data_ptr()), int(nsteps),
                                                     ct.c_void_p(U.data_ptr()), None,
                                                     ct.c_void_p(traj.data_ptr()), _stream()))
@@ -131,11 +131,11 @@ class Batch:
         ks = int(self.info.ks)
         main = (int(nsteps) // ks) * ks
         if main:
-            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
+            A.check(self.L.pf_step_explicit_batched(A.ctx(self.device), ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
                                                     main, ct.c_void_p(U.data_ptr()),
                                                     ct.c_void_p(ws.data_ptr()), None, _stream()))
         if nsteps - main:
-            A.check(self.L.pf_step_explicit_batched(ct.byref(self.info1),
+            A.check(self.L.pf_step_explicit_batched(A.ctx(self.device), ct.byref(self.info1),
                                                     ct.c_void_p(self.plan1.data_ptr()), int(nsteps - main),
                                                     ct.c_void_p(U.data_ptr()), ct.c_void_p(ws.data_ptr()),
                                                     None, _stream()))
@@ -150,7 +150,7 @@ class Batch:
             ws = self.workspace(A.OP_VJP)
         flags = (A.VJP_BEGIN if begin else 0) | (A.VJP_END if end else 0)
         # the fused plan: two adjoint steps per launch when it was built for ks >= 2
-        A.check(self.L.pf_vjp_explicit_batched(ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
+        A.check(self.L.pf_vjp_explicit_batched(A.ctx(self.device), ct.byref(self.info), ct.c_void_p(self.plan.data_ptr()),
                                                int(nsteps), ct.c_void_p(states.data_ptr()),
                                                ct.c_void_p(lam.data_ptr()),
                                                ct.c_void_p(theta_bar.data_ptr()),
@@ -161,7 +161,7 @@ class Batch:
         ws = self.workspace(A.OP_STEP_EXPLICIT)
         us = ct.c_double(0.0)
         info = A.pf_batch_info()
-        A.check(self.L.pf_batch_autotune(ct.byref(self.base), self.samples, self.count, self.dt,
+        A.check(self.L.pf_batch_autotune(A.ctx(self.device), ct.byref(self.base), self.samples, self.count, self.dt,
                                          ct.c_void_p(U_scratch.data_ptr()), ct.c_void_p(ws.data_ptr()),
                                          ct.c_void_p(self.plan.data_ptr()), self.plan.numel(),
                                          ct.byref(info), ct.byref(us), _stream()))

@@ -2,14 +2,15 @@
 //
 // Every entry point validates its arguments on the host before anything is
 // enqueued, converts the problem statement into kernel parameters and
-// launches on the caller's stream.  No exception crosses the ABI; errors are
-// reported as pf_status plus a thread-local message.
+// launches on the caller's stream.  No exception crosses the ABI (each body runs
+// inside guarded()); errors are reported as pf_status plus a thread-local
+// message held in a fixed buffer, so reporting an error never allocates.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <memory>
 
 #include "../../include/pf.h"
 #include "api_internal.hpp"
@@ -17,17 +18,32 @@
 
 namespace pfapi {
 
-thread_local std::string g_last_error;
+thread_local char g_last_error[512];
 
 int fail(int status, const char* fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return status;
+}
+
+int check_ctx(const pf_ctx* ctx)
+{
+    if (!ctx) return fail(PF_EINVAL, "ctx is NULL (make one with pf_create)");
+    return PF_OK;
+}
+
+int require_device(const pf_ctx* ctx)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (ctx->device < 0) return fail(PF_EINVAL, "a host-only context cannot enqueue device work");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return check_launch("hipGetDevice");
+    if (cur != ctx->device)
+        return fail(PF_EINVAL, "the context belongs to device %d but device %d is current", ctx->device, cur);
+    return PF_OK;
 }
 
 int check_launch(const char* what)
@@ -127,7 +143,7 @@ namespace {
 
 // coupled model: node-centric path, ws = [c ping-pong field | eta ping-pong field]
 template <typename T>
-int step_coupled_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+int step_coupled_t(const pf_problem* p, int cus, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
     const pfk::Geom g = geom_of(p);
     T* c = U;
@@ -136,7 +152,7 @@ int step_coupled_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, 
     T *cc = c, *co = ws, *ec = eta, *eo = ws + g.N;
     // 2-D: the fused streaming kernel (32-bit buffer offsets); else node-centric kernels
     const bool fused2d = p->dim == 2 && (size_t)g.N * sizeof(T) < (size_t(1) << 31);
-    const int rows = stream2d_rows(p, 1);
+    const int rows = stream2d_rows(p, 1, cus);
     for (int64_t st = 0; st < nsteps; ++st) {
         if (fused2d) {
             pfk::launch_cp_explicit2d<T>(g, p->kappa, p->mobility, p->mobility_eta, dt, cc, ec, co, eo,
@@ -175,9 +191,9 @@ int step_grain_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hi
 }
 
 template <typename T>
-int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+int step_explicit_t(const pf_problem* p, int cus, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
-    if (p->model == PF_COUPLED) return step_coupled_t<T>(p, dt, nsteps, U, ws, s);
+    if (p->model == PF_COUPLED) return step_coupled_t<T>(p, cus, dt, nsteps, U, ws, s);
     if (p->model == PF_GRAIN) return step_grain_t<T>(p, dt, nsteps, U, ws, s);
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
@@ -189,8 +205,8 @@ int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws,
     if (fused2d) {
         // launches of ks fused steps, then the remainder one step at a time
         const int ks = stream2d_fuse(p);
-        pfk::Stream2DConfig cfg{stream2d_rows(p, ks), stream2d_depth(p), ks};
-        pfk::Stream2DConfig one{stream2d_rows(p, 1), stream2d_depth(p), 1};
+        pfk::Stream2DConfig cfg{stream2d_rows(p, ks, cus), stream2d_depth(p), ks};
+        pfk::Stream2DConfig one{stream2d_rows(p, 1, cus), stream2d_depth(p), 1};
         int64_t st = 0;
         for (; ks > 1 && st + ks <= nsteps; st += ks) {
             pfk::launch_explicit2d<T>(g, p->model, f, p->kappa, p->mobility, dt, cur, other, cfg, s);
@@ -223,164 +239,287 @@ int step_explicit_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws,
     return check_launch("explicit step");
 }
 
+// energy and sum m c of U, partial sums in `part` (energy_blocks(g) pairs)
+int energy_t(const pf_problem* p, const void* U, double* out, double* part, hipStream_t s)
+{
+    const pfk::Geom g = geom_of(p);
+    if (p->model == PF_GRAIN) {
+        if (p->dtype == PF_F32)
+            pfk::launch_gg_energy2d<float>(g, p->nfields, p->kappa, p->gamma, (const float*)U, part, out, s);
+        else
+            pfk::launch_gg_energy2d<double>(g, p->nfields, p->kappa, p->gamma, (const double*)U, part, out, s);
+        return check_launch("pf_energy");
+    }
+    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+    if (p->model == PF_COUPLED) {
+        if (p->dtype == PF_F32)
+            pfk::launch_cp_energy<float>(g, p->kappa, (const float*)U, part, out, s);
+        else
+            pfk::launch_cp_energy<double>(g, p->kappa, (const double*)U, part, out, s);
+        return check_launch("pf_energy");
+    }
+    if (p->dtype == PF_F32)
+        pfk::launch_energy<float>(g, f, p->kappa, (const float*)U, part, out, s);
+    else
+        pfk::launch_energy<double>(g, f, p->kappa, (const double*)U, part, out, s);
+    return check_launch("pf_energy");
+}
+
+}  // namespace
+
+namespace {
+
+int make_slots(pfapi::PinnedSlots* sl, size_t doubles, int events)
+{
+    double* h = nullptr;
+    hipError_t e = hipHostMalloc((void**)&h, doubles * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(PF_EDEVICE, "pinned host slots: %s", hipGetErrorString(e));
+    sl->host = h;
+    std::memset(h, 0, doubles * sizeof(double));
+    e = hipHostGetDevicePointer((void**)&sl->dev, h, 0);
+    if (e != hipSuccess) return fail(PF_EDEVICE, "pinned host slots mapping: %s", hipGetErrorString(e));
+    for (int i = 0; i < events; ++i) {
+        e = hipEventCreateWithFlags(&sl->ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return fail(PF_EDEVICE, "readback event: %s", hipGetErrorString(e));
+    }
+    return PF_OK;
+}
+
+void free_slots(pfapi::PinnedSlots* sl)
+{
+    for (hipEvent_t& ev : sl->ev)
+        if (ev) {
+            (void)hipEventDestroy(ev);
+            ev = nullptr;
+        }
+    if (sl->host) (void)hipHostFree(sl->host);
+    sl->host = sl->dev = nullptr;
+}
+
+void free_ctx(pf_ctx* c)
+{
+    if (!c) return;
+    if (c->device >= 0) {
+        int prev = -1;
+        const bool had = hipGetDevice(&prev) == hipSuccess;
+        if (hipSetDevice(c->device) == hipSuccess) {
+            free_slots(&c->gmres);
+            free_slots(&c->cg);
+        }
+        if (had) (void)hipSetDevice(prev);
+        (void)hipGetLastError();
+    }
+    delete c;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* pf_last_error(void) { return g_last_error.c_str(); }
+const char* pf_last_error(void) { return g_last_error; }
 
-int pf_version(void) { return 100; }
+int pf_version(void) { return 200; }
 
-int pf_workspace_size(const pf_problem* p, int op, size_t* bytes)
+int pf_create(int device, pf_ctx** out)
 {
-    if (int rc = validate(p)) return rc;
-    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
-    const pfk::Geom g = geom_of(p);
-    const size_t es = elem_size(p);
-    size_t b = 0;
-    switch (op) {
-        case PF_OP_RESIDUAL:
-        case PF_OP_JVP: b = 0; break;
-        case PF_OP_STEP_EXPLICIT:
-            if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
-            b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : p->model == PF_GRAIN ? p->nfields : 1);
-            break;
-        case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
-        case PF_OP_NEWTON:
-            if (p->model == PF_GRAIN)
-                if (int rc = grain_implicit_ok(p)) return rc;
-            b = newton_workspace_bytes(p, 30);
-            break;
-        case PF_OP_VJP:
-            if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: the adjoint is not implemented");
-            if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: the adjoint is not implemented");
-            b = vjp_workspace_bytes(p);
-            break;
-        default: return fail(PF_EINVAL, "unknown op %d", op);
-    }
-    *bytes = b;
+    return guarded("pf_create", [&]() -> int {
+        if (!out) return fail(PF_EINVAL, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<pf_ctx> c(new pf_ctx());
+        if (device == PF_HOST_ONLY) {
+            *out = c.release();
+            return PF_OK;
+        }
+        if (device < 0) return fail(PF_EINVAL, "device must be >= 0 or PF_HOST_ONLY (got %d)", device);
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess) count = 0;
+        (void)hipGetLastError();
+        if (device >= count) return fail(PF_EDEVICE, "device %d is not available (%d visible)", device, count);
+        int prev = -1;
+        if (hipGetDevice(&prev) != hipSuccess) return check_launch("hipGetDevice");
+        if (hipSetDevice(device) != hipSuccess) return check_launch("hipSetDevice");
+        c->device = device;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            c->cus = cus;
+        int rc = make_slots(&c->gmres, newton_pinned_doubles(), 3);
+        if (rc == PF_OK) rc = make_slots(&c->cg, elastic_pinned_doubles(), 2);
+        (void)hipSetDevice(prev);
+        if (rc != PF_OK) {
+            free_ctx(c.release());
+            return rc;
+        }
+        *out = c.release();
+        return PF_OK;
+    });
+}
+
+int pf_destroy(pf_ctx* ctx)
+{
+    return guarded("pf_destroy", [&]() -> int {
+        free_ctx(ctx);
+        return PF_OK;
+    });
+}
+
+int pf_ctx_device(const pf_ctx* ctx, int* device)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!device) return fail(PF_EINVAL, "device is NULL");
+    *device = ctx->device;
     return PF_OK;
 }
 
-int pf_residual(const pf_problem* p, const void* U, void* r, void* stream)
+int pf_workspace_size(const pf_ctx* ctx, const pf_problem* p, int op, size_t* bytes)
 {
-    if (int rc = validate(p)) return rc;
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (int rc = check_ptr(r, p, "r")) return rc;
-    if (U == r) return fail(PF_EINVAL, "U and r must not alias");
-    const pfk::Geom g = geom_of(p);
-    hipStream_t s = (hipStream_t)stream;
-    if (p->model == PF_GRAIN) {
-        if (p->dtype == PF_F32)
-            pfk::launch_gg_tile2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0, (const float*)U,
-                                         (float*)r, 1, s);
-        else
-            pfk::launch_gg_tile2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0,
-                                          (const double*)U, (double*)r, 1, s);
-        return check_launch("pf_residual");
-    }
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
-    if (p->model == PF_COUPLED) {
-        if (p->dtype == PF_F32)
-            pfk::launch_cp_residual<float>(g, p->kappa, p->mobility, p->mobility_eta, (const float*)U,
-                                           (float*)r, s);
-        else
-            pfk::launch_cp_residual<double>(g, p->kappa, p->mobility, p->mobility_eta,
-                                            (const double*)U, (double*)r, s);
-        return check_launch("pf_residual");
-    }
-    if (p->dtype == PF_F32)
-        pfk::launch_residual<float>(g, p->model, f, p->kappa, p->mobility, (const float*)U,
-                                    (float*)r, s);
-    else
-        pfk::launch_residual<double>(g, p->model, f, p->kappa, p->mobility, (const double*)U,
-                                     (double*)r, s);
-    return check_launch("pf_residual");
+    return guarded("pf_workspace_size", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+        const pfk::Geom g = geom_of(p);
+        const size_t es = elem_size(p);
+        size_t b = 0;
+        switch (op) {
+            case PF_OP_RESIDUAL:
+            case PF_OP_JVP: b = 0; break;
+            case PF_OP_STEP_EXPLICIT:
+                if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
+                b = (size_t)g.N * es * (p->model == PF_COUPLED ? 2 : p->model == PF_GRAIN ? p->nfields : 1);
+                break;
+            case PF_OP_ENERGY: b = (size_t)pfk::energy_blocks(g) * 2 * sizeof(double); break;
+            case PF_OP_NEWTON:
+                if (p->model == PF_GRAIN)
+                    if (int rc = grain_implicit_ok(p)) return rc;
+                b = newton_workspace_bytes(p, 30);
+                break;
+            case PF_OP_VJP:
+                if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "grain growth: the adjoint is not implemented");
+                if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "coupled model: the adjoint is not implemented");
+                b = vjp_workspace_bytes(p);
+                break;
+            default: return fail(PF_EINVAL, "unknown op %d", op);
+        }
+        *bytes = b;
+        return PF_OK;
+    });
 }
 
-int pf_step_explicit(const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
+int pf_residual(pf_ctx* ctx, const pf_problem* p, const void* U, void* r, void* ws, void* stream)
+{
+    (void)ws;  // the residual needs no scratch (pf_workspace_size(PF_OP_RESIDUAL) is 0)
+    return guarded("pf_residual", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (int rc = check_ptr(r, p, "r")) return rc;
+        if (U == r) return fail(PF_EINVAL, "U and r must not alias");
+        if (int rc = require_device(ctx)) return rc;
+        const pfk::Geom g = geom_of(p);
+        hipStream_t s = (hipStream_t)stream;
+        if (p->model == PF_GRAIN) {
+            if (p->dtype == PF_F32)
+                pfk::launch_gg_tile2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0, (const float*)U,
+                                             (float*)r, 1, s);
+            else
+                pfk::launch_gg_tile2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, 0.0,
+                                              (const double*)U, (double*)r, 1, s);
+            return check_launch("pf_residual");
+        }
+        const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+        if (p->model == PF_COUPLED) {
+            if (p->dtype == PF_F32)
+                pfk::launch_cp_residual<float>(g, p->kappa, p->mobility, p->mobility_eta, (const float*)U,
+                                               (float*)r, s);
+            else
+                pfk::launch_cp_residual<double>(g, p->kappa, p->mobility, p->mobility_eta,
+                                                (const double*)U, (double*)r, s);
+            return check_launch("pf_residual");
+        }
+        if (p->dtype == PF_F32)
+            pfk::launch_residual<float>(g, p->model, f, p->kappa, p->mobility, (const float*)U,
+                                        (float*)r, s);
+        else
+            pfk::launch_residual<double>(g, p->model, f, p->kappa, p->mobility, (const double*)U,
+                                         (double*)r, s);
+        return check_launch("pf_residual");
+    });
+}
+
+int pf_step_explicit(pf_ctx* ctx, const pf_problem* p, double dt, int64_t nsteps, void* U, void* ws,
                      void* stream)
 {
-    if (int rc = validate(p)) return rc;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
-    if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (int rc = check_ptr(ws, p, "ws")) return rc;
-    if (p->mass != PF_MASS_LUMPED)
-        return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass (a consistent mass needs a solve)");
-    hipStream_t s = (hipStream_t)stream;
-    if (p->dtype == PF_F32) return step_explicit_t<float>(p, dt, nsteps, (float*)U, (float*)ws, s);
-    return step_explicit_t<double>(p, dt, nsteps, (double*)U, (double*)ws, s);
+    return guarded("pf_step_explicit", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
+        if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (int rc = check_ptr(ws, p, "ws")) return rc;
+        if (p->mass != PF_MASS_LUMPED)
+            return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass (a consistent mass needs a solve)");
+        if (int rc = require_device(ctx)) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        if (p->dtype == PF_F32) return step_explicit_t<float>(p, ctx->cus, dt, nsteps, (float*)U, (float*)ws, s);
+        return step_explicit_t<double>(p, ctx->cus, dt, nsteps, (double*)U, (double*)ws, s);
+    });
 }
 
-int pf_energy(const pf_problem* p, const void* U, double* out, void* ws, void* stream)
+int pf_energy(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void* ws, void* stream)
 {
-    if (int rc = validate(p)) return rc;
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 8) return fail(PF_EINVAL, "ws is NULL or misaligned");
-    const pfk::Geom g = geom_of(p);
-    hipStream_t s = (hipStream_t)stream;
-    if (p->model == PF_GRAIN) {
-        if (p->dtype == PF_F32)
-            pfk::launch_gg_energy2d<float>(g, p->nfields, p->kappa, p->gamma, (const float*)U, (double*)ws, out, s);
-        else
-            pfk::launch_gg_energy2d<double>(g, p->nfields, p->kappa, p->gamma, (const double*)U, (double*)ws,
-                                            out, s);
-        return check_launch("pf_energy");
-    }
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
-    if (p->model == PF_COUPLED) {
-        if (p->dtype == PF_F32)
-            pfk::launch_cp_energy<float>(g, p->kappa, (const float*)U, (double*)ws, out, s);
-        else
-            pfk::launch_cp_energy<double>(g, p->kappa, (const double*)U, (double*)ws, out, s);
-        return check_launch("pf_energy");
-    }
-    if (p->dtype == PF_F32)
-        pfk::launch_energy<float>(g, f, p->kappa, (const float*)U, (double*)ws, out, s);
-    else
-        pfk::launch_energy<double>(g, f, p->kappa, (const double*)U, (double*)ws, out, s);
-    return check_launch("pf_energy");
+    return guarded("pf_energy", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 8) return fail(PF_EINVAL, "ws is NULL or misaligned");
+        if (int rc = require_device(ctx)) return rc;
+        return energy_t(p, U, out, (double*)ws, (hipStream_t)stream);
+    });
 }
 
-int pf_jvp(const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv, void* stream)
+int pf_jvp(pf_ctx* ctx, const pf_problem* p, double inv_dt, const void* U, const void* v, void* Jv,
+           void* stream)
 {
-    if (int rc = validate(p)) return rc;
-    if (!std::isfinite(inv_dt) || inv_dt < 0.0) return fail(PF_EINVAL, "inv_dt must be finite and >= 0");
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (int rc = check_ptr(v, p, "v")) return rc;
-    if (int rc = check_ptr(Jv, p, "Jv")) return rc;
-    if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
-    const pfk::Geom g = geom_of(p);
-    hipStream_t s = (hipStream_t)stream;
-    if (p->model == PF_GRAIN) {
-        if (int rc = grain_implicit_ok(p)) return rc;
+    return guarded("pf_jvp", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (!std::isfinite(inv_dt) || inv_dt < 0.0) return fail(PF_EINVAL, "inv_dt must be finite and >= 0");
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (int rc = check_ptr(v, p, "v")) return rc;
+        if (int rc = check_ptr(Jv, p, "Jv")) return rc;
+        if (Jv == U || Jv == v) return fail(PF_EINVAL, "Jv must not alias U or v");
+        if (p->model == PF_GRAIN)
+            if (int rc = grain_implicit_ok(p)) return rc;
+        if (int rc = require_device(ctx)) return rc;
+        const pfk::Geom g = geom_of(p);
+        hipStream_t s = (hipStream_t)stream;
+        if (p->model == PF_GRAIN) {
+            if (p->dtype == PF_F32)
+                pfk::launch_gg_jvp2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt, (const float*)U,
+                                            (const float*)v, (float*)Jv, s);
+            else
+                pfk::launch_gg_jvp2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt,
+                                             (const double*)U, (const double*)v, (double*)Jv, s);
+            return check_launch("pf_jvp");
+        }
+        const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
+        if (p->model == PF_COUPLED) {
+            if (p->dtype == PF_F32)
+                pfk::launch_cp_jvp<float>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, (const float*)U,
+                                          (const float*)v, (float*)Jv, s);
+            else
+                pfk::launch_cp_jvp<double>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt,
+                                           (const double*)U, (const double*)v, (double*)Jv, s);
+            return check_launch("pf_jvp");
+        }
         if (p->dtype == PF_F32)
-            pfk::launch_gg_jvp2d<float>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt, (const float*)U,
-                                        (const float*)v, (float*)Jv, s);
+            pfk::launch_jvp<float>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const float*)U,
+                                   (const float*)v, (float*)Jv, s);
         else
-            pfk::launch_gg_jvp2d<double>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt,
-                                         (const double*)U, (const double*)v, (double*)Jv, s);
+            pfk::launch_jvp<double>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const double*)U,
+                                    (const double*)v, (double*)Jv, s);
         return check_launch("pf_jvp");
-    }
-    const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
-    if (p->model == PF_COUPLED) {
-        if (p->dtype == PF_F32)
-            pfk::launch_cp_jvp<float>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt, (const float*)U,
-                                      (const float*)v, (float*)Jv, s);
-        else
-            pfk::launch_cp_jvp<double>(g, p->kappa, p->mobility, p->mobility_eta, inv_dt,
-                                       (const double*)U, (const double*)v, (double*)Jv, s);
-        return check_launch("pf_jvp");
-    }
-    if (p->dtype == PF_F32)
-        pfk::launch_jvp<float>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const float*)U,
-                               (const float*)v, (float*)Jv, s);
-    else
-        pfk::launch_jvp<double>(g, p->model, f, p->kappa, p->mobility, inv_dt, (const double*)U,
-                                (const double*)v, (double*)Jv, s);
-    return check_launch("pf_jvp");
+    });
 }
 
 }  // extern "C"

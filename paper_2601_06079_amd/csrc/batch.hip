@@ -54,6 +54,7 @@ int count_plan(const pf_problem* base, const pf_batch_sample* s, int count, int 
                Counts* c)
 {
     if (count < 1) return fail(PF_EINVAL, "count must be >= 1");
+    if (count > PF_BATCH_MAX_COUNT) return fail(PF_EINVAL, "count %d exceeds PF_BATCH_MAX_COUNT", count);
     if (!s) return fail(PF_EINVAL, "samples is NULL");
     if (ks < 1 || ks > 4) return fail(PF_EINVAL, "ks must be in 1..4");
     if (ty < 1) return fail(PF_EINVAL, "ty must be >= 1");
@@ -103,22 +104,10 @@ int auto_ty(const pf_problem* base, const pf_batch_sample* s, int count, int ks)
     return ty;
 }
 
-// autotune results, keyed by a signature of the batch shape
-struct TuneKey {
-    int model, dtype, count;
-    long long cells, maxn;
-    bool operator<(const TuneKey& o) const
-    {
-        return std::tie(model, dtype, count, cells, maxn) <
-               std::tie(o.model, o.dtype, o.count, o.cells, o.maxn);
-    }
-};
-std::map<TuneKey, std::array<int, 3>> g_tuned;
-std::mutex g_tuned_mu;
-
-TuneKey key_of(const pf_problem* base, const pf_batch_sample* s, int count)
+// the signature of a batch shape under which the autotuner files its result
+BatchShapeKey key_of(const pf_problem* base, const pf_batch_sample* s, int count)
 {
-    TuneKey k{base->model, base->dtype, count, 0, 0};
+    BatchShapeKey k{base->model, base->dtype, count, 0, 0};
     for (int i = 0; i < count; ++i) {
         k.cells += s[i].n[0] * s[i].n[1];
         k.maxn = std::max<long long>(k.maxn, std::max(s[i].n[0], s[i].n[1]));
@@ -136,30 +125,35 @@ extern "C" {
 int pf_batch_plan_size(const pf_problem* base, const pf_batch_sample* samples, int count, int ks,
                        int ty, size_t* bytes)
 {
-    if (int rc = validate_base(base)) return rc;
-    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
-    if (ks == 0) ks = 4;  // narrowest strips: the worst case of the automatic choice
-    if (ty == 0) ty = 8;  // shortest chunks
-    Counts c;
-    if (int rc = count_plan(base, samples, count, ks, ty, &c)) return rc;
-    *bytes = plan_bytes_of(count, c);
-    return PF_OK;
+    return guarded("pf_batch_plan_size", [&]() -> int {
+        if (int rc = validate_base(base)) return rc;
+        if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+        if (ks == 0) ks = 4;  // narrowest strips: the worst case of the automatic choice
+        if (ty == 0) ty = 8;  // shortest chunks
+        Counts c;
+        if (int rc = count_plan(base, samples, count, ks, ty, &c)) return rc;
+        *bytes = plan_bytes_of(count, c);
+        return PF_OK;
+    });
 }
 
-int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
-                  int ks, int ty, int depth, void* plan_dev, size_t plan_bytes,
-                  pf_batch_info* info, void* stream)
+int pf_batch_plan(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+                  int ks, int ty, int depth, void* plan_dev, size_t plan_bytes, pf_batch_info* info,
+                  void* stream)
 {
+    return guarded("pf_batch_plan", [&]() -> int {
+    if (int rc = check_ctx(ctx)) return rc;
     if (int rc = validate_base(base)) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
     if (!plan_dev || reinterpret_cast<uintptr_t>(plan_dev) % 256)
         return fail(PF_EINVAL, "plan must be a 256-byte aligned device pointer");
     if (!info) return fail(PF_EINVAL, "info is NULL");
     if (depth < 0 || ks < 0 || ty < 0) return fail(PF_EINVAL, "negative launch-shape value");
-    if (ks == 0 || ty == 0 || depth == 0) {
-        std::lock_guard<std::mutex> lk(g_tuned_mu);
-        auto it = g_tuned.find(key_of(base, samples, count));
-        if (it != g_tuned.end()) {
+    if (count > PF_BATCH_MAX_COUNT) return fail(PF_EINVAL, "count %d exceeds PF_BATCH_MAX_COUNT", count);
+    if ((ks == 0 || ty == 0 || depth == 0) && samples && count >= 1) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->tuned.find(key_of(base, samples, count));
+        if (it != ctx->tuned.end()) {
             if (ks == 0) ks = it->second[0];
             if (ty == 0) ty = it->second[1];
             if (depth == 0) depth = it->second[2];
@@ -213,6 +207,7 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
     const size_t o_s = 0, o_i = align256(sizeof(pfk::BatchSample) * count);
     std::memcpy(host.data() + o_s, smp.data(), sizeof(pfk::BatchSample) * count);
     std::memcpy(host.data() + o_i, items.data(), sizeof(pfk::BatchItem) * items.size());
+    if (int rc = require_device(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(plan_dev, host.data(), need, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -232,11 +227,13 @@ int pf_batch_plan(const pf_problem* base, const pf_batch_sample* samples, int co
     I.off_items = (int64_t)o_i;
     *info = I;
     return PF_OK;
+    });
 }
 
 int pf_batch_workspace_size(const pf_batch_info* info, int op, size_t* bytes)
 {
     if (!info || !bytes) return fail(PF_EINVAL, "info or bytes is NULL");
+    if (info->total < 1 || info->n_items < 0) return fail(PF_EINVAL, "info does not describe a plan");
     const size_t es = info->dtype == PF_F64 ? 8 : 4;
     const size_t field = align256((size_t)info->total * es);
     if (op == PF_OP_STEP_EXPLICIT)
@@ -337,9 +334,11 @@ int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, c
 
 extern "C" {
 
-int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps, void* U,
+int pf_step_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void* plan, int64_t nsteps, void* U,
                              void* ws, void* traj, void* stream)
 {
+    return guarded("pf_step_explicit_batched", [&]() -> int {
+    if (int rc = check_ctx(ctx)) return rc;
     if (int rc = check_info(info, plan)) return rc;
     if (nsteps < 0) return fail(PF_EINVAL, "nsteps must be >= 0");
     if (!U) return fail(PF_EINVAL, "U is NULL");
@@ -349,16 +348,20 @@ int pf_step_explicit_batched(const pf_batch_info* info, const void* plan, int64_
         if (nsteps % info->ks) return fail(PF_EINVAL, "nsteps must be a multiple of the plan's ks (%d)", info->ks);
         if (!ws) return fail(PF_EINVAL, "ws is NULL");
     }
+    if (int rc = require_device(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (info->dtype == PF_F32)
         return batched_steps_t<float>(info, plan, nsteps, (float*)U, (float*)ws, (float*)traj, s);
     return batched_steps_t<double>(info, plan, nsteps, (double*)U, (double*)ws, (double*)traj, s);
+    });
 }
 
-int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t nsteps,
+int pf_vjp_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void* plan, int64_t nsteps,
                             const void* states, void* lam, double* theta_bar, void* ws, int flags,
                             void* stream)
 {
+    return guarded("pf_vjp_explicit_batched", [&]() -> int {
+    if (int rc = check_ctx(ctx)) return rc;
     if (int rc = check_info(info, plan)) return rc;
     if (info->model != PF_ALLEN_CAHN)
         return fail(PF_EUNSUPPORTED, "batched adjoint is implemented for Allen-Cahn");
@@ -366,20 +369,27 @@ int pf_vjp_explicit_batched(const pf_batch_info* info, const void* plan, int64_t
     if (!states || !lam || !ws || !theta_bar) return fail(PF_EINVAL, "NULL pointer argument");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
     if (flags & ~(PF_VJP_BEGIN | PF_VJP_END)) return fail(PF_EINVAL, "unknown flags");
+    if (int rc = require_device(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (info->dtype == PF_F32)
         return batched_vjp_t<float>(info, plan, nsteps, (const float*)states, (float*)lam, theta_bar,
                                     ws, flags, s);
     return batched_vjp_t<double>(info, plan, nsteps, (const double*)states, (double*)lam, theta_bar,
                                  ws, flags, s);
+    });
 }
 
-int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
+int pf_batch_autotune(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                       void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
                       pf_batch_info* best, double* best_us_per_step, void* stream)
 {
+    return guarded("pf_batch_autotune", [&]() -> int {
+    if (int rc = check_ctx(ctx)) return rc;
     if (int rc = validate_base(base)) return rc;
     if (!U_scratch || !ws || !best) return fail(PF_EINVAL, "NULL pointer argument");
+    if (count < 1 || count > PF_BATCH_MAX_COUNT || !samples)
+        return fail(PF_EINVAL, "count must be in 1..PF_BATCH_MAX_COUNT with samples given");
+    if (int rc = require_device(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -397,15 +407,16 @@ int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, in
                 const int HK = (base->model == PF_CAHN_HILLIARD ? 2 : 1) * ks;
                 const int tya = ty - (ty + 2 * HK) % 4;
                 pf_batch_info I;
-                int rc = pf_batch_plan(base, samples, count, dt, ks, tya, depth, plan_dev, plan_bytes, &I, stream);
+                int rc = pf_batch_plan(ctx, base, samples, count, dt, ks, tya, depth, plan_dev, plan_bytes, &I,
+                                       stream);
                 if (rc == PF_EINVAL) continue;  // this candidate's plan does not fit the buffer
                 if (rc) { status = rc; goto done; }
                 const int64_t steps = 2 * ks;
-                if ((rc = pf_step_explicit_batched(&I, plan_dev, steps, U_scratch, ws, nullptr, stream))) { status = rc; goto done; }
+                if ((rc = pf_step_explicit_batched(ctx, &I, plan_dev, steps, U_scratch, ws, nullptr, stream))) { status = rc; goto done; }
                 hipEventRecord(e0, s);
                 const int reps = 3;
                 for (int r = 0; r < reps; ++r)
-                    if ((rc = pf_step_explicit_batched(&I, plan_dev, steps, U_scratch, ws, nullptr, stream))) { status = rc; goto done; }
+                    if ((rc = pf_step_explicit_batched(ctx, &I, plan_dev, steps, U_scratch, ws, nullptr, stream))) { status = rc; goto done; }
                 hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) { status = check_launch("autotune timing"); goto done; }
                 float ms = 0.f;
@@ -420,15 +431,16 @@ int pf_batch_autotune(const pf_problem* base, const pf_batch_sample* samples, in
             }
     if (best_t < 0) { status = fail(PF_EINVAL, "plan buffer too small for every candidate"); goto done; }
     {
-        std::lock_guard<std::mutex> lk(g_tuned_mu);
-        g_tuned[key_of(base, samples, count)] = {bk, bt, bd};
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[key_of(base, samples, count)] = {bk, bt, bd};
     }
-    status = pf_batch_plan(base, samples, count, dt, bk, bt, bd, plan_dev, plan_bytes, best, stream);
+    status = pf_batch_plan(ctx, base, samples, count, dt, bk, bt, bd, plan_dev, plan_bytes, best, stream);
     if (best_us_per_step) *best_us_per_step = best_t * 1e3;
 done:
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return status;
+    });
 }
 
 }  // extern "C"

@@ -1567,46 +1567,33 @@ size_t ws_bytes(const pf_elastic* p, Ws* out, void* base)
     return off;
 }
 
+// The pinned mirror the CG kernels store their scalars into (owned by the
+// context, made by pf_create) with its two events; this is a view of it.
 struct HostMirror {
     double* host = nullptr;
     double* dev = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-int host_mirror(HostMirror** out)
+HostMirror host_mirror(const pf_ctx* ctx)
 {
-    thread_local HostMirror hm[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-        return pfapi::fail(PF_EDEVICE, "no usable current device for the CG readback");
-    HostMirror& m = hm[dev];
-    if (!m.host) {
-        double* h = nullptr;
-        hipError_t e = hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocDefault);
-        if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "pinned CG readback: %s", hipGetErrorString(e));
-        for (int i = 0; i < 2; ++i) {
-            e = hipEventCreateWithFlags(&m.ev[i], hipEventDisableTiming);
-            if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "CG readback event: %s", hipGetErrorString(e));
-        }
-        double* d = nullptr;
-        e = hipHostGetDevicePointer((void**)&d, h, 0);
-        if (e != hipSuccess) return pfapi::fail(PF_EDEVICE, "CG readback mapping: %s", hipGetErrorString(e));
-        m.host = h;
-        m.dev = d;
-    }
-    *out = &m;
-    return PF_OK;
+    HostMirror m;
+    m.host = ctx->cg.host;
+    m.dev = ctx->cg.dev;
+    m.ev[0] = ctx->cg.ev[0];
+    m.ev[1] = ctx->cg.ev[1];
+    return m;
 }
 
 // CG on K x = b (b already in W.r); x is overwritten.  Host-synchronous.
 template <typename T>
-int cg_solve(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit, pf_el_report* rep,
-             hipStream_t st)
+int cg_solve(const pf_ctx* ctx, const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit,
+             pf_el_report* rep, hipStream_t st)
 {
     double lam, mu;
     lame(p, &lam, &mu);
-    HostMirror* hm = nullptr;
-    if (int rc = host_mirror(&hm)) return rc;
+    const HostMirror hmv = host_mirror(ctx);
+    const HostMirror* hm = &hmv;
     const long long n = ndof(p);
     const int sb = stream_blocks(n);
     k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, x, nullptr);
@@ -1771,16 +1758,14 @@ void vcycle(const Levels& Lv, int l, const T* b, T* x, T* t, const Ws& W, double
 
 // lambda_max(D^-1 K) for this dimension and nu: power iteration on I + D^-1 K
 // (the Jacobi-mode operator with omega = -1 and a zero load) on a 9^d grid in
-// FP64, through the same operator kernel; cached per (dim, nu) for the process.
-int jacobi_lmax(const pf_elastic* p, const Ws& W, hipStream_t st, double* out)
+// FP64, through the same operator kernel; cached per (dim, nu) in the context.
+int jacobi_lmax(pf_ctx* ctx, const pf_elastic* p, const Ws& W, hipStream_t st, double* out)
 {
-    static std::mutex mtx;
-    static std::map<std::pair<int, double>, double> cache;
     const std::pair<int, double> key(p->dim, p->nu);
     {
-        std::lock_guard<std::mutex> lk(mtx);
-        auto it = cache.find(key);
-        if (it != cache.end()) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->el_lmax.find(key);
+        if (it != ctx->el_lmax.end()) {
             *out = it->second;
             return PF_OK;
         }
@@ -1812,8 +1797,8 @@ int jacobi_lmax(const pf_elastic* p, const Ws& W, hipStream_t st, double* out)
     const double lmax = h - 1.0;
     if (!(std::isfinite(lmax) && lmax > 0.5))
         return pfapi::fail(PF_ENONFINITE, "smoother eigenvalue estimate failed (%g)", lmax);
-    std::lock_guard<std::mutex> lk(mtx);
-    cache[key] = lmax;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->el_lmax[key] = lmax;
     *out = lmax;
     return PF_OK;
 }
@@ -1824,19 +1809,19 @@ int jacobi_lmax(const pf_elastic* p, const Ws& W, hipStream_t st, double* out)
 // r -= alpha q.  Scalars
 // stay on the device; the host polls a pinned mirror.  Host-synchronous.
 template <typename T>
-int pcg_solve(const pf_elastic* p, const Levels& Lv, T* x, const Ws& W, double rtol, int maxit,
+int pcg_solve(pf_ctx* ctx, const pf_elastic* p, const Levels& Lv, T* x, const Ws& W, double rtol, int maxit,
               pf_el_report* rep, hipStream_t st)
 {
     double lam, mu;
     lame(p, &lam, &mu);
-    HostMirror* hm = nullptr;
-    if (int rc = host_mirror(&hm)) return rc;
+    const HostMirror hmv = host_mirror(ctx);
+    const HostMirror* hm = &hmv;
     const Grid& g = Lv.g[0];
     const long long n = Lv.ndof[0];
     const int sb = stream_blocks(n);
     double* S = W.scal;
     double lmax = 0.0;
-    if (int rc = jacobi_lmax(p, W, st, &lmax)) return rc;
+    if (int rc = jacobi_lmax(ctx, p, W, st, &lmax)) return rc;
     const double omega = MG_SMOOTH / lmax;
     k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, x, nullptr);
     k_el_fill<T><<<sb, EL_BLOCK, 0, st>>>(n, (T*)W.p, nullptr);
@@ -1903,16 +1888,16 @@ int pcg_solve(const pf_elastic* p, const Levels& Lv, T* x, const Ws& W, double r
 // the solver for K x = b (b in W.r): multigrid-preconditioned CG when the grid
 // coarsens, else plain CG
 template <typename T>
-int el_solve_any(const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit,
+int el_solve_any(pf_ctx* ctx, const pf_elastic* p, const Grid& g, T* x, const Ws& W, double rtol, int maxit,
                  pf_el_report* rep, hipStream_t st)
 {
     const Levels Lv = mg_levels(p);
-    if (Lv.nl > 1) return pcg_solve<T>(p, Lv, x, W, rtol, maxit, rep, st);
-    return cg_solve<T>(p, g, x, W, rtol, maxit, rep, st);
+    if (Lv.nl > 1) return pcg_solve<T>(ctx, p, Lv, x, W, rtol, maxit, rep, st);
+    return cg_solve<T>(ctx, p, g, x, W, rtol, maxit, rep, st);
 }
 
 template <typename T>
-int solve_t(const pf_elastic* p, const void* b, void* u, double rtol, int maxit, pf_el_report* rep,
+int solve_t(pf_ctx* ctx, const pf_elastic* p, const void* b, void* u, double rtol, int maxit, pf_el_report* rep,
             const Ws& W, hipStream_t st)
 {
     const Grid g = grid_of(p);
@@ -1923,7 +1908,7 @@ int solve_t(const pf_elastic* p, const void* b, void* u, double rtol, int maxit,
         k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)b);
     else
         launch_rhs<T>(g, p->dim * lam + 2.0 * mu, p, (T*)W.r, st);
-    return el_solve_any<T>(p, g, (T*)u, W, rtol, maxit, rep, st);
+    return el_solve_any<T>(ctx, p, g, (T*)u, W, rtol, maxit, rep, st);
 }
 
 // Sensitivities of O = g . u with respect to (E, nu) at the equilibrium u:
@@ -1932,8 +1917,8 @@ int solve_t(const pf_elastic* p, const void* b, void* u, double rtol, int maxit,
 //   dO/dlam = lam_a . (d f1 - K_l u),   dO/dmu = lam_a . (2 f1 - K_m u),
 // mapped to (E, nu) by the chain rule.
 template <typename T>
-int sensitivity_t(const pf_elastic* p, const void* gw, const void* u, double* out, double rtol, int maxit,
-                  pf_el_report* rep, const Ws& W, hipStream_t st)
+int sensitivity_t(pf_ctx* ctx, const pf_elastic* p, const void* gw, const void* u, double* out, double rtol,
+                  int maxit, pf_el_report* rep, const Ws& W, hipStream_t st)
 {
     const Grid g = grid_of(p);
     const long long n = ndof(p);
@@ -1944,7 +1929,7 @@ int sensitivity_t(const pf_elastic* p, const void* gw, const void* u, double* ou
         k_el_weights<T, 2><<<bl, EL_BLOCK, 0, st>>>(g, (const T*)gw, (T*)W.g);
     k_el_fill<T><<<stream_blocks(n), EL_BLOCK, 0, st>>>(n, (T*)W.r, (const T*)W.g);
     if (int rc = pfapi::check_launch("adjoint set-up")) return rc;
-    if (int rc = el_solve_any<T>(p, g, (T*)W.lam, W, rtol, maxit, rep, st)) return rc;
+    if (int rc = el_solve_any<T>(ctx, p, g, (T*)W.lam, W, rtol, maxit, rep, st)) return rc;
     double* dots = W.scal + 2 * S_SLOT;  // 4 device doubles after the CG state
     double* part = W.part;
     launch_dot<T>(g, (const T*)W.g, (const T*)u, part, dots + 0, st);
@@ -1973,101 +1958,129 @@ int sensitivity_t(const pf_elastic* p, const void* gw, const void* u, double* ou
 using namespace pfel;
 using pfapi::fail;
 
+namespace pfapi {
+size_t elastic_pinned_doubles() { return 64; }
+}  // namespace pfapi
+
 extern "C" {
 
-int pf_el_workspace_size(const pf_elastic* p, size_t* bytes)
+int pf_el_workspace_size(const pf_ctx* ctx, const pf_elastic* p, size_t* bytes)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
-    *bytes = ws_bytes(p, nullptr, nullptr);
-    return PF_OK;
+    return pfapi::guarded("pf_el_workspace_size", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+        *bytes = ws_bytes(p, nullptr, nullptr);
+        return PF_OK;
+    });
 }
 
-int pf_el_apply(const pf_elastic* p, const void* u, void* y, void* stream)
+int pf_el_apply(pf_ctx* ctx, const pf_elastic* p, const void* u, void* y, void* stream)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (int rc = check_vec(u, p, "u")) return rc;
-    if (int rc = check_vec(y, p, "y")) return rc;
-    if (u == y) return fail(PF_EINVAL, "u and y must not alias");
-    const Grid g = grid_of(p);
-    double lam, mu;
-    lame(p, &lam, &mu);
-    hipStream_t st = (hipStream_t)stream;
-    if (p->dtype == PF_F32)
-        launch_apply<float>(g, lam, mu, 1, (const float*)u, (float*)y, nullptr, st);
-    else
-        launch_apply<double>(g, lam, mu, 1, (const double*)u, (double*)y, nullptr, st);
-    return pfapi::check_launch("pf_el_apply");
+    return pfapi::guarded("pf_el_apply", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (int rc = check_vec(u, p, "u")) return rc;
+        if (int rc = check_vec(y, p, "y")) return rc;
+        if (u == y) return fail(PF_EINVAL, "u and y must not alias");
+        if (int rc = pfapi::require_device(ctx)) return rc;
+        const Grid g = grid_of(p);
+        double lam, mu;
+        lame(p, &lam, &mu);
+        hipStream_t st = (hipStream_t)stream;
+        if (p->dtype == PF_F32)
+            launch_apply<float>(g, lam, mu, 1, (const float*)u, (float*)y, nullptr, st);
+        else
+            launch_apply<double>(g, lam, mu, 1, (const double*)u, (double*)y, nullptr, st);
+        return pfapi::check_launch("pf_el_apply");
+    });
 }
 
-int pf_el_rhs(const pf_elastic* p, void* f, void* stream)
+int pf_el_rhs(pf_ctx* ctx, const pf_elastic* p, void* f, void* stream)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (int rc = check_vec(f, p, "f")) return rc;
-    const Grid g = grid_of(p);
-    double lam, mu;
-    lame(p, &lam, &mu);
-    hipStream_t st = (hipStream_t)stream;
-    if (p->dtype == PF_F32)
-        launch_rhs<float>(g, p->dim * lam + 2.0 * mu, p, (float*)f, st);
-    else
-        launch_rhs<double>(g, p->dim * lam + 2.0 * mu, p, (double*)f, st);
-    return pfapi::check_launch("pf_el_rhs");
+    return pfapi::guarded("pf_el_rhs", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (int rc = check_vec(f, p, "f")) return rc;
+        if (int rc = pfapi::require_device(ctx)) return rc;
+        const Grid g = grid_of(p);
+        double lam, mu;
+        lame(p, &lam, &mu);
+        hipStream_t st = (hipStream_t)stream;
+        if (p->dtype == PF_F32)
+            launch_rhs<float>(g, p->dim * lam + 2.0 * mu, p, (float*)f, st);
+        else
+            launch_rhs<double>(g, p->dim * lam + 2.0 * mu, p, (double*)f, st);
+        return pfapi::check_launch("pf_el_rhs");
+    });
 }
 
-int pf_el_solve(const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit, pf_el_report* rep,
-                void* ws, void* stream)
+int pf_el_solve(pf_ctx* ctx, const pf_elastic* p, const void* b, void* u, double rtol, int32_t maxit,
+                pf_el_report* rep, void* ws, void* stream)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (b)
-        if (int rc = check_vec(b, p, "b")) return rc;
-    if (int rc = check_vec(u, p, "u")) return rc;
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
-    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
-    if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
-    if (b == u) return fail(PF_EINVAL, "b and u must not alias");
-    Ws W;
-    ws_bytes(p, &W, ws);
-    hipStream_t st = (hipStream_t)stream;
-    if (p->dtype == PF_F32) return solve_t<float>(p, b, u, rtol, maxit, rep, W, st);
-    return solve_t<double>(p, b, u, rtol, maxit, rep, W, st);
+    return pfapi::guarded("pf_el_solve", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (b)
+            if (int rc = check_vec(b, p, "b")) return rc;
+        if (int rc = check_vec(u, p, "u")) return rc;
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
+        if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
+        if (b == u) return fail(PF_EINVAL, "b and u must not alias");
+        if (int rc = pfapi::require_device(ctx)) return rc;
+        Ws W;
+        ws_bytes(p, &W, ws);
+        hipStream_t st = (hipStream_t)stream;
+        if (p->dtype == PF_F32) return solve_t<float>(ctx, p, b, u, rtol, maxit, rep, W, st);
+        return solve_t<double>(ctx, p, b, u, rtol, maxit, rep, W, st);
+    });
 }
 
-int pf_el_objective(const pf_elastic* p, const void* gw, const void* u, double* out, void* ws, void* stream)
+int pf_el_objective(pf_ctx* ctx, const pf_elastic* p, const void* gw, const void* u, double* out, void* ws,
+                    void* stream)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (gw)
-        if (int rc = check_vec(gw, p, "g")) return rc;
-    if (int rc = check_vec(u, p, "u")) return rc;
-    if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
-    Ws W;
-    ws_bytes(p, &W, ws);
-    const Grid g = grid_of(p);
-    hipStream_t st = (hipStream_t)stream;
-    if (p->dtype == PF_F32)
-        launch_dot<float>(g, (const float*)gw, (const float*)u, W.part, out, st);
-    else
-        launch_dot<double>(g, (const double*)gw, (const double*)u, W.part, out, st);
-    return pfapi::check_launch("pf_el_objective");
+    return pfapi::guarded("pf_el_objective", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (gw)
+            if (int rc = check_vec(gw, p, "g")) return rc;
+        if (int rc = check_vec(u, p, "u")) return rc;
+        if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+        if (int rc = pfapi::require_device(ctx)) return rc;
+        Ws W;
+        ws_bytes(p, &W, ws);
+        const Grid g = grid_of(p);
+        hipStream_t st = (hipStream_t)stream;
+        if (p->dtype == PF_F32)
+            launch_dot<float>(g, (const float*)gw, (const float*)u, W.part, out, st);
+        else
+            launch_dot<double>(g, (const double*)gw, (const double*)u, W.part, out, st);
+        return pfapi::check_launch("pf_el_objective");
+    });
 }
 
-int pf_el_sensitivity(const pf_elastic* p, const void* gw, const void* u, double* out, double rtol, int32_t maxit,
-                      pf_el_report* rep, void* ws, void* stream)
+int pf_el_sensitivity(pf_ctx* ctx, const pf_elastic* p, const void* gw, const void* u, double* out, double rtol,
+                      int32_t maxit, pf_el_report* rep, void* ws, void* stream)
 {
-    if (int rc = pfel::validate(p)) return rc;
-    if (gw)
-        if (int rc = check_vec(gw, p, "g")) return rc;
-    if (int rc = check_vec(u, p, "u")) return rc;
-    if (!out) return fail(PF_EINVAL, "out is NULL");
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
-    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
-    if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
-    Ws W;
-    ws_bytes(p, &W, ws);
-    hipStream_t st = (hipStream_t)stream;
-    if (p->dtype == PF_F32) return sensitivity_t<float>(p, gw, u, out, rtol, maxit, rep, W, st);
-    return sensitivity_t<double>(p, gw, u, out, rtol, maxit, rep, W, st);
+    return pfapi::guarded("pf_el_sensitivity", [&]() -> int {
+        if (int rc = pfapi::check_ctx(ctx)) return rc;
+        if (int rc = pfel::validate(p)) return rc;
+        if (gw)
+            if (int rc = check_vec(gw, p, "g")) return rc;
+        if (int rc = check_vec(u, p, "u")) return rc;
+        if (!out) return fail(PF_EINVAL, "out is NULL");
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws is NULL or not 256-byte aligned");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PF_EINVAL, "rtol must be finite and > 0");
+        if (maxit < 1) return fail(PF_EINVAL, "maxit must be >= 1");
+        if (int rc = pfapi::require_device(ctx)) return rc;
+        Ws W;
+        ws_bytes(p, &W, ws);
+        hipStream_t st = (hipStream_t)stream;
+        if (p->dtype == PF_F32) return sensitivity_t<float>(ctx, p, gw, u, out, rtol, maxit, rep, W, st);
+        return sensitivity_t<double>(ctx, p, gw, u, out, rtol, maxit, rep, W, st);
+    });
 }
 
 }  // extern "C"

@@ -16,8 +16,8 @@
 // from the true residual b - J x.  Inexact Newton: the linear tolerance is
 // clamp(0.1 ||R_k|| / ||R_0||, lin_rtol_min, lin_rtol_max) relative to ||R_k||.
 #include <cmath>
+#include <array>
 #include <cstring>
-#include <vector>
 
 #include "api_internal.hpp"
 #include "kernels.hpp"
@@ -36,6 +36,7 @@ struct NWS {
     T *R, *x, *w, *z, *b, *V, *pinv;
     long long ld;
     double *part, *dev;  // dev: [h1(MAXM+1) | h2(MAXM+1) | nrm(2) | y(MAXM) | misc(8)]
+    double* theta;       // device copy of a host theta_bar (pf_vjp with PF_VJP_THETA_HOST)
     size_t bytes;
 };
 
@@ -66,6 +67,7 @@ NWS<T> layout(const pf_problem* p, void* base)
     const long long nbp = std::max<long long>(pfk::krylov_blocks(n), (g.N + 255) / 256);
     L.part = (double*)take((size_t)(MAXM + 2) * nbp * sizeof(double) + 64);
     L.dev = (double*)take(4 * (MAXM + 8) * sizeof(double));
+    L.theta = (double*)take(4 * sizeof(double));
     L.bytes = off;
     return L;
 }
@@ -73,9 +75,9 @@ NWS<T> layout(const pf_problem* p, void* base)
 enum { DEV_H1 = 0, DEV_H2 = MAXM + 1, DEV_NRM = 2 * (MAXM + 1), DEV_Y = 2 * (MAXM + 1) + 2,
        DEV_MISC = 3 * (MAXM + 1) + 2 };
 
-// Pinned host slots for the Hessenberg columns, two per host thread and device
-// (allocated on first use and kept until the process ends; the Gram-Schmidt
-// kernels store into them directly), and the events that mark each slot's step.
+// Pinned host slots for the Hessenberg columns (two, used alternately) and the
+// scalars the kernels store directly, with the events that mark each slot's step.
+// The memory belongs to the context (made by pf_create); this is a view of it.
 // Layout (doubles): [slot 0: DEV_Y | slot 1: DEV_Y | y: MAXM | scalars: 8].
 struct ColReadback {
     double* host = nullptr;      // host address of the slots
@@ -94,30 +96,14 @@ struct ColReadback {
 };
 constexpr size_t RB_DOUBLES = 2 * DEV_Y + MAXM + 8;
 
-int col_readback(ColReadback** out)
+ColReadback col_readback(const pf_ctx* ctx)
 {
     static_assert(MAXM <= pfk::KR_MAXK, "restart length beyond the Gram-Schmidt kernels");
-    thread_local ColReadback rb[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-        return fail(PF_EDEVICE, "no usable current device for the GMRES readback");
-    ColReadback& r = rb[dev];
-    if (!r.host) {
-        double* h = nullptr;
-        hipError_t e = hipHostMalloc((void**)&h, RB_DOUBLES * sizeof(double), hipHostMallocDefault);
-        if (e != hipSuccess) return fail(PF_EDEVICE, "pinned GMRES readback buffer: %s", hipGetErrorString(e));
-        for (int i = 0; i < 3; ++i) {
-            e = hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming);
-            if (e != hipSuccess) return fail(PF_EDEVICE, "GMRES readback event: %s", hipGetErrorString(e));
-        }
-        double* hd = nullptr;
-        e = hipHostGetDevicePointer((void**)&hd, h, 0);
-        if (e != hipSuccess) return fail(PF_EDEVICE, "GMRES readback mapping: %s", hipGetErrorString(e));
-        r.host = h;
-        r.host_dev = hd;
-    }
-    *out = &r;
-    return PF_OK;
+    ColReadback r;
+    r.host = ctx->gmres.host;
+    r.host_dev = ctx->gmres.dev;
+    for (int i = 0; i < 3; ++i) r.ev[i] = ctx->gmres.ev[i];
+    return r;
 }
 
 struct Opts {
@@ -167,6 +153,11 @@ int check_cg(const pf_problem* p, double dt, const Opts& o)
 {
     if (o.krylov != PF_KRYLOV_CG) return PF_OK;
     if (p->model != PF_ALLEN_CAHN) return fail(PF_EINVAL, "krylov = CG needs the Allen-Cahn model");
+    // positive definiteness below rests on L > 0, kappa >= 0 (K is positive
+    // semi-definite) and W >= 0 (f'' >= -W for both double wells)
+    if (!(p->mobility > 0.0)) return fail(PF_EINVAL, "krylov = CG needs mobility > 0 (got %g)", p->mobility);
+    if (!(p->kappa >= 0.0)) return fail(PF_EINVAL, "krylov = CG needs kappa >= 0 (got %g)", p->kappa);
+    if (!(p->W >= 0.0)) return fail(PF_EINVAL, "krylov = CG needs W >= 0 (got %g)", p->W);
     if (!(dt * p->mobility * p->W < 1.0))
         return fail(PF_EINVAL, "krylov = CG needs dt L W < 1 (got %g): the Jacobian may be indefinite",
                     dt * p->mobility * p->W);
@@ -205,7 +196,7 @@ struct LinOp {
 // The preconditioner (if any) must already be in L.pinv.  Returns PF status;
 // *its receives the Arnoldi steps taken, *res the last residual estimate.
 template <typename T>
-int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool prec,
+int gmres(const ColReadback* rb, const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool prec,
           double bnorm, double tol_abs, int* its, double* res, hipStream_t s)
 {
     // grain growth: point Jacobi over all p N unknowns (the Krylov kernels' point model)
@@ -219,9 +210,9 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
     double* dnrm = L.dev + DEV_NRM;
     double* dy = L.dev + DEV_Y;
     if (hipMemsetAsync(L.x, 0, (size_t)n * sizeof(T), s) != hipSuccess) return check_launch("gmres init");
-    std::vector<double> H((MAXM + 1) * MAXM), cs(MAXM), sn(MAXM), gv(MAXM + 1), y(MAXM);
-    ColReadback* rb = nullptr;
-    if (int rc = col_readback(&rb)) return rc;
+    std::array<double, (MAXM + 1) * MAXM> H{};
+    std::array<double, MAXM> cs{}, sn{}, y{};
+    std::array<double, MAXM + 1> gv{};
     int total = 0;
     double beta = bnorm;
     bool first = true;
@@ -323,13 +314,11 @@ int gmres(const LinOp<T>& A, NWS<T>& L, long long n, int m, int max_its, bool pr
 // scalars stay on the device; the host reads the pinned mirror one iteration
 // behind the GPU.  Returns PF status; *its: iterations, *res: ||r||.
 template <typename T>
-int pcg(const LinOp<T>& A, NWS<T>& L, long long n, int max_its, bool prec, double bnorm, double tol_abs,
-        int* its, double* res, hipStream_t s)
+int pcg(const ColReadback* rb, const LinOp<T>& A, NWS<T>& L, long long n, int max_its, bool prec, double bnorm,
+        double tol_abs, int* its, double* res, hipStream_t s)
 {
     *its = 0;
     *res = bnorm;
-    ColReadback* rb = nullptr;
-    if (int rc = col_readback(&rb)) return rc;
     const T* pinv = prec ? L.pinv : nullptr;
     T* r = L.V;
     T* pdir = L.V + L.ld;
@@ -376,7 +365,7 @@ double eps_of()
 }
 
 template <typename T>
-int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
+int newton_t(const pf_ctx* ctx, const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
              pf_newton_report* rep, void* ws, hipStream_t s)
 {
     const pfk::Geom g = geom_of(p);
@@ -387,8 +376,8 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
     double* dnrm = L.dev + DEV_NRM;
     double* dmisc = L.dev + DEV_MISC;
     pf_newton_report R{};
-    ColReadback* rb = nullptr;
-    if (int rc = col_readback(&rb)) return rc;
+    const ColReadback rbv = col_readback(ctx);
+    const ColReadback* rb = &rbv;
     // ||R(U)||, read back together with whatever scalars were queued before it
     auto residual_norm = [&](double* out) -> int {
         if (p->model == PF_COUPLED)
@@ -439,9 +428,9 @@ int newton_t(const pf_problem* p, double dt, const T* Uold, T* U, const Opts& o,
         int its = 0;
         double lres = 0.0;
         const bool jac = o.precond == PF_PRECOND_JACOBI;
-        if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(A, L, n, o.max_its, jac, rk, lin * rk, &its, &lres, s)
-                                              : gmres<T>(A, L, n, o.m, o.max_its, jac, rk, lin * rk, &its, &lres,
-                                                         s)) {
+        if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(rb, A, L, n, o.max_its, jac, rk, lin * rk, &its, &lres, s)
+                                              : gmres<T>(rb, A, L, n, o.m, o.max_its, jac, rk, lin * rk, &its,
+                                                         &lres, s)) {
             status = rc;
             R.reason = -2;
             break;
@@ -478,7 +467,7 @@ size_t newton_workspace_bytes(const pf_problem* p, int)
 size_t vjp_workspace_bytes(const pf_problem* p) { return newton_workspace_bytes(p, MAXM); }
 
 template <typename T>
-int vjp_simple_t(const pf_problem* p, int kind, double dt, const T* U, const T* vbar, T* Ubar,
+int vjp_simple_t(const pf_problem* p, int kind, double dt, bool be, const T* U, const T* vbar, T* Ubar,
                  double* theta_bar, void* ws, hipStream_t s)
 {
     const pfk::Geom g = geom_of(p);
@@ -487,6 +476,9 @@ int vjp_simple_t(const pf_problem* p, int kind, double dt, const T* U, const T* 
     if (kind == PF_VJP_RESIDUAL) {
         // Ubar += (dr/dU)^T vbar : the transpose Jacobian product with no time term
         pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, 0.0, U, vbar, Ubar, s, 1, 1);
+        // backward-Euler residual R = M (U - U_old)/dt + r (Eq. 14): M is symmetric,
+        // so its transposed time term adds (M/dt) vbar on the mass rows
+        if (be) pfk::launch_mass_axpy<T>(g, 1.0 / dt, vbar, Ubar, s);
         pfk::launch_dtheta<T>(g, p->model, f, p->kappa, p->mobility, U, vbar, 1.0, L.part,
                               theta_bar, s);
     } else {
@@ -501,9 +493,10 @@ int vjp_simple_t(const pf_problem* p, int kind, double dt, const T* U, const T* 
 // rows and theta_bar -= (dr/dtheta)^T lambda.  lambda is left in the
 // workspace's x vector.
 template <typename T>
-int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, T* Ubar,
+int newton_adjoint_t(const pf_ctx* ctx, const pf_problem* p, double dt, const T* U, const T* vbar, T* Ubar,
                      double* theta_bar, const Opts& o, void* ws, hipStream_t s)
 {
+    const ColReadback rbv = col_readback(ctx);
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     const long long n = ndof(p);
@@ -525,8 +518,9 @@ int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, 
     const double tol = (sizeof(T) == 4 ? 1e-6 : 1e-12) * bn;
     const bool jac = o.precond == PF_PRECOND_JACOBI;
     // (Allen-Cahn's Jacobian is symmetric: CG solves the transposed system as well)
-    if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(At, L, n, o.max_its * 4, jac, bn, tol, &its, &res, s)
-                                          : gmres<T>(At, L, n, o.m, o.max_its * 4, jac, bn, tol, &its, &res, s))
+    if (int rc = o.krylov == PF_KRYLOV_CG ? pcg<T>(&rbv, At, L, n, o.max_its * 4, jac, bn, tol, &its, &res, s)
+                                          : gmres<T>(&rbv, At, L, n, o.m, o.max_its * 4, jac, bn, tol, &its, &res,
+                                                     s))
         return rc;
     // Ubar (mass rows) += (m/dt) lambda ; theta_bar -= (dr/dtheta)^T lambda
     pfk::launch_mass_axpy<T>(g, inv_dt, L.x, Ubar, s);
@@ -534,21 +528,18 @@ int newton_adjoint_t(const pf_problem* p, double dt, const T* U, const T* vbar, 
     return check_launch("newton adjoint");
 }
 
-template int newton_adjoint_t<float>(const pf_problem*, double, const float*, const float*, float*,
-                                     double*, const Opts&, void*, hipStream_t);
-template int newton_adjoint_t<double>(const pf_problem*, double, const double*, const double*,
-                                      double*, double*, const Opts&, void*, hipStream_t);
-
-int newton_adjoint(const pf_problem* p, double dt, const void* U, const void* vbar, void* Ubar,
+int newton_adjoint(const pf_ctx* ctx, const pf_problem* p, double dt, const void* U, const void* vbar, void* Ubar,
                    double* theta_bar, void* ws, hipStream_t s)
 {
     const Opts o = resolve(nullptr);
     if (p->dtype == PF_F32)
-        return newton_adjoint_t<float>(p, dt, (const float*)U, (const float*)vbar, (float*)Ubar,
+        return newton_adjoint_t<float>(ctx, p, dt, (const float*)U, (const float*)vbar, (float*)Ubar,
                                        theta_bar, o, ws, s);
-    return newton_adjoint_t<double>(p, dt, (const double*)U, (const double*)vbar, (double*)Ubar,
+    return newton_adjoint_t<double>(ctx, p, dt, (const double*)U, (const double*)vbar, (double*)Ubar,
                                     theta_bar, o, ws, s);
 }
+
+size_t newton_pinned_doubles() { return RB_DOUBLES; }
 
 }  // namespace pfapi
 
@@ -571,52 +562,78 @@ void pf_newton_default_opts(pf_newton_opts* o)
     o->stagnation = 1;
 }
 
-int pf_newton_step(const pf_problem* p, double dt, const void* U_old, void* U,
+int pf_newton_step(pf_ctx* ctx, const pf_problem* p, double dt, const void* U_old, void* U,
                    const pf_newton_opts* opts, pf_newton_report* rep, void* ws, void* stream)
 {
-    if (int rc = validate(p)) return rc;
-    if (p->model == PF_GRAIN)
-        if (int rc = grain_implicit_ok(p)) return rc;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
-    if (int rc = check_ptr(U_old, p, "U_old")) return rc;
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (U == U_old) return fail(PF_EINVAL, "U and U_old must not alias");
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
-    const Opts o = resolve(opts);
-    if (int rc = check_opts(o)) return rc;
-    if (int rc = check_cg(p, dt, o)) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    if (p->dtype == PF_F32)
-        return newton_t<float>(p, dt, (const float*)U_old, (float*)U, o, rep, ws, s);
-    return newton_t<double>(p, dt, (const double*)U_old, (double*)U, o, rep, ws, s);
+    return guarded("pf_newton_step", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (p->model == PF_GRAIN)
+            if (int rc = grain_implicit_ok(p)) return rc;
+        if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PF_EINVAL, "dt must be finite and > 0");
+        if (int rc = check_ptr(U_old, p, "U_old")) return rc;
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (U == U_old) return fail(PF_EINVAL, "U and U_old must not alias");
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+        const Opts o = resolve(opts);
+        if (int rc = check_opts(o)) return rc;
+        if (int rc = check_cg(p, dt, o)) return rc;
+        if (int rc = require_device(ctx)) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        if (p->dtype == PF_F32)
+            return newton_t<float>(ctx, p, dt, (const float*)U_old, (float*)U, o, rep, ws, s);
+        return newton_t<double>(ctx, p, dt, (const double*)U_old, (double*)U, o, rep, ws, s);
+    });
 }
 
-int pf_vjp(const pf_problem* p, int kind, double dt, const void* U, const void* vbar, void* Ubar,
-           double* theta_bar, void* ws, void* stream)
+int pf_vjp(pf_ctx* ctx, const pf_problem* p, int kind, double dt, const void* U, const void* U_old,
+           const void* vbar, void* Ubar, double* theta_bar, int flags, void* ws, void* stream)
 {
-    if (int rc = validate(p)) return rc;
-    if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_vjp: coupled model not implemented");
-    if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "pf_vjp: grain growth not implemented");
-    if (kind != PF_VJP_RESIDUAL && kind != PF_VJP_EXPLICIT_STEP && kind != PF_VJP_NEWTON_STEP)
-        return fail(PF_EINVAL, "unknown vjp kind %d", kind);
-    if (kind != PF_VJP_RESIDUAL && (!(dt > 0.0) || !std::isfinite(dt)))
-        return fail(PF_EINVAL, "dt must be finite and > 0");
-    if (kind == PF_VJP_EXPLICIT_STEP && p->mass != PF_MASS_LUMPED)
-        return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
-    if (int rc = check_ptr(U, p, "U")) return rc;
-    if (int rc = check_ptr(vbar, p, "vbar")) return rc;
-    if (int rc = check_ptr(Ubar, p, "Ubar")) return rc;
-    if (Ubar == U || Ubar == vbar) return fail(PF_EINVAL, "Ubar must not alias U or vbar");
-    if (!theta_bar || reinterpret_cast<uintptr_t>(theta_bar) % 8)
-        return fail(PF_EINVAL, "theta_bar is NULL or misaligned");
-    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    if (kind == PF_VJP_NEWTON_STEP) return newton_adjoint(p, dt, U, vbar, Ubar, theta_bar, ws, s);
-    if (p->dtype == PF_F32)
-        return vjp_simple_t<float>(p, kind, dt, (const float*)U, (const float*)vbar, (float*)Ubar,
-                                   theta_bar, ws, s);
-    return vjp_simple_t<double>(p, kind, dt, (const double*)U, (const double*)vbar, (double*)Ubar,
-                                theta_bar, ws, s);
+    return guarded("pf_vjp", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_vjp: coupled model not implemented");
+        if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "pf_vjp: grain growth not implemented");
+        if (kind != PF_VJP_RESIDUAL && kind != PF_VJP_EXPLICIT_STEP && kind != PF_VJP_NEWTON_STEP)
+            return fail(PF_EINVAL, "unknown vjp kind %d", kind);
+        if (flags & ~PF_VJP_THETA_HOST) return fail(PF_EINVAL, "unknown flags 0x%x", flags);
+        const bool be = kind == PF_VJP_RESIDUAL && U_old != nullptr;
+        if ((kind != PF_VJP_RESIDUAL || be) && (!(dt > 0.0) || !std::isfinite(dt)))
+            return fail(PF_EINVAL, "dt must be finite and > 0");
+        if (kind == PF_VJP_EXPLICIT_STEP && p->mass != PF_MASS_LUMPED)
+            return fail(PF_EUNSUPPORTED, "explicit steps need the lumped mass");
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (U_old)
+            if (int rc = check_ptr(U_old, p, "U_old")) return rc;
+        if (int rc = check_ptr(vbar, p, "vbar")) return rc;
+        if (int rc = check_ptr(Ubar, p, "Ubar")) return rc;
+        if (Ubar == U || Ubar == vbar) return fail(PF_EINVAL, "Ubar must not alias U or vbar");
+        if (!theta_bar || reinterpret_cast<uintptr_t>(theta_bar) % 8)
+            return fail(PF_EINVAL, "theta_bar is NULL or misaligned");
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+        if (int rc = require_device(ctx)) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        const bool host_theta = (flags & PF_VJP_THETA_HOST) != 0;
+        double* tb = theta_bar;
+        if (host_theta) {  // accumulate into a device copy, then return it to the host
+            tb = p->dtype == PF_F32 ? layout<float>(p, ws).theta : layout<double>(p, ws).theta;
+            if (hipMemcpyAsync(tb, theta_bar, 3 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+                return check_launch("theta_bar upload");
+        }
+        int rc;
+        if (kind == PF_VJP_NEWTON_STEP)
+            rc = newton_adjoint(ctx, p, dt, U, vbar, Ubar, tb, ws, s);
+        else if (p->dtype == PF_F32)
+            rc = vjp_simple_t<float>(p, kind, dt, be, (const float*)U, (const float*)vbar, (float*)Ubar, tb, ws, s);
+        else
+            rc = vjp_simple_t<double>(p, kind, dt, be, (const double*)U, (const double*)vbar, (double*)Ubar, tb,
+                                      ws, s);
+        if (rc != PF_OK || !host_theta) return rc;
+        if (hipMemcpyAsync(theta_bar, tb, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return check_launch("theta_bar download");
+        return PF_OK;
+    });
 }
 
 }  // extern "C"

@@ -94,87 +94,97 @@ int pf_nn_param_count(void) { return pfk::nn_offsets().total; }
 
 int pf_nn_workspace_size(int B, int H, int W, size_t* bytes)
 {
-    if (int rc = check_shape(B, H, W)) return rc;
-    if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
-    *bytes = nn_layout(B, H, W, nullptr).bytes;
-    return PF_OK;
+    return guarded("pf_nn_workspace_size", [&]() -> int {
+        if (int rc = check_shape(B, H, W)) return rc;
+        if (!bytes) return fail(PF_EINVAL, "bytes is NULL");
+        *bytes = nn_layout(B, H, W, nullptr).bytes;
+        return PF_OK;
+    });
 }
 
 int pf_nn_forward(const float* params, int B, int H, int W, const float* c, const float* M,
                   const float* kappa, float* chat, void* ws, void* stream)
 {
-    if (int rc = check_shape(B, H, W)) return rc;
-    if (!params || !c || !M || !kappa || !chat || !ws) return fail(PF_EINVAL, "NULL pointer argument");
-    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    NNWS L = nn_layout(B, H, W, ws);
-    forward(params, B, H, W, c, M, kappa, nullptr, L, s, false);
-    if (hipMemcpyAsync(chat, L.chat, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return check_launch("pf_nn_forward copy");
-    return check_launch("pf_nn_forward");
+    return guarded("pf_nn_forward", [&]() -> int {
+        if (int rc = check_shape(B, H, W)) return rc;
+        if (!params || !c || !M || !kappa || !chat || !ws) return fail(PF_EINVAL, "NULL pointer argument");
+        if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        NNWS L = nn_layout(B, H, W, ws);
+        forward(params, B, H, W, c, M, kappa, nullptr, L, s, false);
+        if (hipMemcpyAsync(chat, L.chat, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return check_launch("pf_nn_forward copy");
+        return check_launch("pf_nn_forward");
+    });
 }
 
 int pf_nn_backward(const float* params, int B, int H, int W, const float* c, const float* M,
                    const float* kappa, const float* target, double* loss, float* grad, void* ws,
                    void* stream)
 {
-    if (int rc = check_shape(B, H, W)) return rc;
-    if (!params || !c || !M || !kappa || !target || !grad || !ws)
-        return fail(PF_EINVAL, "NULL pointer argument");
-    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    NNWS L = nn_layout(B, H, W, ws);
-    const pfk::NNOffsets o = pfk::nn_offsets();
-    const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
-    const int HW = H * W;
-    forward(params, B, H, W, c, M, kappa, target, L, s, true);
-    if (loss) pfk::nn_sample_mean(L.r2, L.spart, loss, B, HW, s);  // per-sample MSE
-    // backward of the mass projection: g <- g - mean(g)
-    pfk::nn_sample_mean(L.g, L.spart, L.mean2, B, HW, s);
-    pfk::nn_center(L.g, L.mean2, B, HW, s);
-    // output layer
-    pfk::nn_out_bwd(L.a3, L.w4, L.g, L.ga, L.part, B, H, W, s);
-    pfk::nn_sum_partials(L.part, pfk::nn_out_wgrad_blocks(B, H, W), 289, grad + o.w4, s);
-    const int nwg = pfk::nn_wgrad_blocks(B, H, W);
-    // layer 3: ga = d pre3
-    pfk::nn_wgrad(3, L.a2, L.ga, L.part, L.partb, B, H, W, s);
-    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w3, s);
-    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b3, s);
-    pfk::nn_conv(3, 1, L.ga, L.frag + fo.d3, nullptr, L.a2, L.gb, B, H, W, s);  // gb = d pre2
-    // layer 2
-    pfk::nn_wgrad(2, L.a1, L.gb, L.part, L.partb, B, H, W, s);
-    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w2, s);
-    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b2, s);
-    pfk::nn_conv(2, 1, L.gb, L.frag + fo.d2, nullptr, L.a1, L.ga, B, H, W, s);  // ga = d pre1
-    // layer 1 (input channels padded 3 -> 16)
-    pfk::nn_wgrad(1, L.a0, L.ga, L.part, L.partb, B, H, W, s);
-    pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, L.tile, s);
-    pfk::nn_extract_w1(L.tile, grad + o.w1, s);
-    pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b1, s);
-    return check_launch("pf_nn_backward");
+    return guarded("pf_nn_backward", [&]() -> int {
+        if (int rc = check_shape(B, H, W)) return rc;
+        if (!params || !c || !M || !kappa || !target || !grad || !ws)
+            return fail(PF_EINVAL, "NULL pointer argument");
+        if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        NNWS L = nn_layout(B, H, W, ws);
+        const pfk::NNOffsets o = pfk::nn_offsets();
+        const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
+        const int HW = H * W;
+        forward(params, B, H, W, c, M, kappa, target, L, s, true);
+        if (loss) pfk::nn_sample_mean(L.r2, L.spart, loss, B, HW, s);  // per-sample MSE
+        // backward of the mass projection: g <- g - mean(g)
+        pfk::nn_sample_mean(L.g, L.spart, L.mean2, B, HW, s);
+        pfk::nn_center(L.g, L.mean2, B, HW, s);
+        // output layer
+        pfk::nn_out_bwd(L.a3, L.w4, L.g, L.ga, L.part, B, H, W, s);
+        pfk::nn_sum_partials(L.part, pfk::nn_out_wgrad_blocks(B, H, W), 289, grad + o.w4, s);
+        const int nwg = pfk::nn_wgrad_blocks(B, H, W);
+        // layer 3: ga = d pre3
+        pfk::nn_wgrad(3, L.a2, L.ga, L.part, L.partb, B, H, W, s);
+        pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w3, s);
+        pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b3, s);
+        pfk::nn_conv(3, 1, L.ga, L.frag + fo.d3, nullptr, L.a2, L.gb, B, H, W, s);  // gb = d pre2
+        // layer 2
+        pfk::nn_wgrad(2, L.a1, L.gb, L.part, L.partb, B, H, W, s);
+        pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, grad + o.w2, s);
+        pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b2, s);
+        pfk::nn_conv(2, 1, L.gb, L.frag + fo.d2, nullptr, L.a1, L.ga, B, H, W, s);  // ga = d pre1
+        // layer 1 (input channels padded 3 -> 16)
+        pfk::nn_wgrad(1, L.a0, L.ga, L.part, L.partb, B, H, W, s);
+        pfk::nn_sum_partials(L.part, nwg, 9 * 32 * 32, L.tile, s);
+        pfk::nn_extract_w1(L.tile, grad + o.w1, s);
+        pfk::nn_sum_partials(L.partb, nwg, 32, grad + o.b1, s);
+        return check_launch("pf_nn_backward");
+    });
 }
 
 int pf_nn_check(int B, int H, int W, const float* chat, const float* c_prev, const float* c_step,
                 double K_dt, double dt, double* out, void* ws, void* stream)
 {
-    if (int rc = check_shape(B, H, W)) return rc;
-    if (!chat || !c_prev || !c_step || !out || !ws) return fail(PF_EINVAL, "NULL pointer argument");
-    if (!(K_dt > 0.0) || !(dt > 0.0)) return fail(PF_EINVAL, "K_dt and dt must be > 0");
-    NNWS L = nn_layout(B, H, W, ws);
-    pfk::nn_check(chat, c_prev, c_step, B, H * W, K_dt, dt, L.spart, out, (hipStream_t)stream);
-    return check_launch("pf_nn_check");
+    return guarded("pf_nn_check", [&]() -> int {
+        if (int rc = check_shape(B, H, W)) return rc;
+        if (!chat || !c_prev || !c_step || !out || !ws) return fail(PF_EINVAL, "NULL pointer argument");
+        if (!(K_dt > 0.0) || !(dt > 0.0)) return fail(PF_EINVAL, "K_dt and dt must be > 0");
+        NNWS L = nn_layout(B, H, W, ws);
+        pfk::nn_check(chat, c_prev, c_step, B, H * W, K_dt, dt, L.spart, out, (hipStream_t)stream);
+        return check_launch("pf_nn_check");
+    });
 }
 
 int pf_nn_adam(float* params, float* m, float* v, const float* grad, int t, double lr, double beta1,
                double beta2, double eps, void* stream)
 {
-    if (!params || !m || !v || !grad) return fail(PF_EINVAL, "NULL pointer argument");
-    if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
-        !(eps > 0.0))
-        return fail(PF_EINVAL, "bad Adam hyper-parameters");
-    pfk::nn_adam(params, m, v, grad, pfk::nn_offsets().total, t, lr, beta1, beta2, eps,
-                 (hipStream_t)stream);
-    return check_launch("pf_nn_adam");
+    return guarded("pf_nn_adam", [&]() -> int {
+        if (!params || !m || !v || !grad) return fail(PF_EINVAL, "NULL pointer argument");
+        if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+            !(eps > 0.0))
+            return fail(PF_EINVAL, "bad Adam hyper-parameters");
+        pfk::nn_adam(params, m, v, grad, pfk::nn_offsets().total, t, lr, beta1, beta2, eps,
+                     (hipStream_t)stream);
+        return check_launch("pf_nn_adam");
+    });
 }
 
 }  // extern "C"

@@ -3,7 +3,6 @@
 // measurements on MI355X; pf_tune_set overrides them (the autotuner uses it).
 #include <algorithm>
 #include <atomic>
-#include <mutex>
 
 #include "api_internal.hpp"
 
@@ -15,24 +14,7 @@ std::atomic<int> g_fuse_override{0};
 std::atomic<int> g_jvp3d_planes{0};
 std::atomic<int> g_el_planes{0};
 std::atomic<int> g_el_mg{0};
-int g_simds = -1;
-std::mutex g_mu;
-
-int device_simds()
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (g_simds < 0) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            int v = 0;
-            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-                v > 0)
-                cus = v;
-        }
-        g_simds = 4 * cus;
-    }
-    return g_simds;
-}
+std::atomic<int> g_seam{0};
 }  // namespace
 
 int stream2d_fuse(const pf_problem* p)
@@ -44,14 +26,14 @@ int stream2d_fuse(const pf_problem* p)
     return ov > 0 ? std::min(ov, 4) : 2;
 }
 
-int stream2d_rows(const pf_problem* p, int ks)
+int stream2d_rows(const pf_problem* p, int ks, int cus)
 {
     const int ov = g_rows_override.load();
     if (ov > 0) return ov;
     const int HK = (p->model == PF_ALLEN_CAHN ? 1 : 2) * ks;  // Cahn-Hilliard and coupled: 2 per step
     const long long nx = p->n[0], ny = p->n[1];
     const long long strips = (nx + (64 - 2 * HK) - 1) / (64 - 2 * HK);
-    const long long S = device_simds();
+    const long long S = 4LL * (cus > 0 ? cus : 256);  // SIMDs
     // The launch splits each strip into balanced chunks (sizes differ by at most
     // one row).  Measured on MI355X: enough chunks for about four waves per SIMD
     // hide latency, and stopping just below a whole number of waves per SIMD
@@ -82,6 +64,7 @@ namespace pfk {
 int tune_jvp3d_planes() { return pfapi::g_jvp3d_planes.load(); }
 int tune_el_planes() { return pfapi::g_el_planes.load(); }
 int tune_el_mg() { return pfapi::g_el_mg.load(); }
+int tune_stream2d_seam() { return pfapi::g_seam.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -101,18 +84,23 @@ int pf_tune_set(int key, int value)
         g_el_planes.store(value);
     else if (key == PF_TUNE_EL_MG)
         g_el_mg.store(value);
+    else if (key == PF_TUNE_STREAM2D_SEAM)
+        g_seam.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
 }
-int pf_launch_shape(const pf_problem* p, int* ks, int* ty, int* depth)
+int pf_launch_shape(const pf_ctx* ctx, const pf_problem* p, int* ks, int* ty, int* depth)
 {
-    if (int rc = validate(p)) return rc;
-    if (!ks || !ty || !depth) return fail(PF_EINVAL, "NULL output pointer");
-    *ks = stream2d_fuse(p);
-    *ty = stream2d_rows(p, *ks);
-    *depth = stream2d_depth(p);
-    return PF_OK;
+    return guarded("pf_launch_shape", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (!ks || !ty || !depth) return fail(PF_EINVAL, "NULL output pointer");
+        *ks = stream2d_fuse(p);
+        *ty = stream2d_rows(p, *ks, ctx->cus);
+        *depth = stream2d_depth(p);
+        return PF_OK;
+    });
 }
 
 int pf_tune_get(int key, int* value)
@@ -130,6 +118,8 @@ int pf_tune_get(int key, int* value)
         *value = g_el_planes.load();
     else if (key == PF_TUNE_EL_MG)
         *value = g_el_mg.load();
+    else if (key == PF_TUNE_STREAM2D_SEAM)
+        *value = g_seam.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

@@ -39,12 +39,12 @@ def _lib():
         P = ct.POINTER(pf_elastic)
         R = ct.POINTER(pf_el_report)
         vp, i32, f64 = ct.c_void_p, ct.c_int32, ct.c_double
-        for name, res, args in (("pf_el_workspace_size", i32, [P, ct.POINTER(ct.c_size_t)]),
-                                ("pf_el_apply", i32, [P, vp, vp, vp]),
-                                ("pf_el_rhs", i32, [P, vp, vp]),
-                                ("pf_el_solve", i32, [P, vp, vp, f64, i32, R, vp, vp]),
-                                ("pf_el_objective", i32, [P, vp, vp, vp, vp, vp]),
-                                ("pf_el_sensitivity", i32, [P, vp, vp, ct.POINTER(ct.c_double), f64,
+        for name, res, args in (("pf_el_workspace_size", i32, [vp, P, ct.POINTER(ct.c_size_t)]),
+                                ("pf_el_apply", i32, [vp, P, vp, vp, vp]),
+                                ("pf_el_rhs", i32, [vp, P, vp, vp]),
+                                ("pf_el_solve", i32, [vp, P, vp, vp, f64, i32, R, vp, vp]),
+                                ("pf_el_objective", i32, [vp, P, vp, vp, vp, vp, vp]),
+                                ("pf_el_sensitivity", i32, [vp, P, vp, vp, ct.POINTER(ct.c_double), f64,
                                                             i32, R, vp, vp])):
             fn = getattr(L, name)
             fn.restype, fn.argtypes = res, args
@@ -104,7 +104,7 @@ def _ptr(t, p: ElasticProblem, name):
 
 def workspace(p: ElasticProblem, device=None) -> torch.Tensor:
     nb = ct.c_size_t(0)
-    A.check(_lib().pf_el_workspace_size(ct.byref(p.c()), ct.byref(nb)))
+    A.check(_lib().pf_el_workspace_size(A.ctx(), ct.byref(p.c()), ct.byref(nb)))
     return torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=device or torch.device("cuda"))
 
 
@@ -115,13 +115,13 @@ def _ws_ptr(ws: torch.Tensor):
 
 def el_apply(p: ElasticProblem, u: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
     y = torch.empty_like(u) if out is None else out
-    A.check(_lib().pf_el_apply(ct.byref(p.c()), _ptr(u, p, "u"), _ptr(y, p, "y"), _stream()))
+    A.check(_lib().pf_el_apply(A.ctx(), ct.byref(p.c()), _ptr(u, p, "u"), _ptr(y, p, "y"), _stream()))
     return y
 
 
 def el_rhs(p: ElasticProblem, out: torch.Tensor = None, device=None) -> torch.Tensor:
     f = torch.empty(p.ndof, dtype=p.dtype, device=device or torch.device("cuda")) if out is None else out
-    A.check(_lib().pf_el_rhs(ct.byref(p.c()), _ptr(f, p, "f"), _stream()))
+    A.check(_lib().pf_el_rhs(A.ctx(), ct.byref(p.c()), _ptr(f, p, "f"), _stream()))
     return f
 
 
@@ -132,7 +132,7 @@ def el_solve(p: ElasticProblem, b: torch.Tensor = None, out: torch.Tensor = None
     u = torch.empty(p.ndof, dtype=p.dtype, device=dev) if out is None else out
     ws = workspace(p, dev) if ws is None else ws
     rep = pf_el_report()
-    st = _lib().pf_el_solve(ct.byref(p.c()), _ptr(b, p, "b"), _ptr(u, p, "u"), float(rtol), int(maxit),
+    st = _lib().pf_el_solve(A.ctx(), ct.byref(p.c()), _ptr(b, p, "b"), _ptr(u, p, "u"), float(rtol), int(maxit),
                             ct.byref(rep), _ws_ptr(ws), _stream())
     A.check(st, allow=(A.PF_ENOCONV,) if allow_noconv else ())
     return u, rep
@@ -143,7 +143,7 @@ def el_objective(p: ElasticProblem, u: torch.Tensor, g: torch.Tensor = None,
     """Device float64 scalar g . u (g = None: the volume change)."""
     ws = workspace(p, u.device) if ws is None else ws
     out = torch.empty(1, dtype=torch.float64, device=u.device)
-    A.check(_lib().pf_el_objective(ct.byref(p.c()), _ptr(g, p, "g"), _ptr(u, p, "u"),
+    A.check(_lib().pf_el_objective(A.ctx(), ct.byref(p.c()), _ptr(g, p, "g"), _ptr(u, p, "u"),
                                    ct.c_void_p(out.data_ptr()), _ws_ptr(ws), _stream()))
     return out
 
@@ -154,6 +154,6 @@ def el_sensitivity(p: ElasticProblem, u: torch.Tensor, g: torch.Tensor = None, r
     ws = workspace(p, u.device) if ws is None else ws
     out = (ct.c_double * 3)()
     rep = pf_el_report()
-    A.check(_lib().pf_el_sensitivity(ct.byref(p.c()), _ptr(g, p, "g"), _ptr(u, p, "u"), out,
+    A.check(_lib().pf_el_sensitivity(A.ctx(), ct.byref(p.c()), _ptr(g, p, "g"), _ptr(u, p, "u"), out,
                                      float(rtol), int(maxit), ct.byref(rep), _ws_ptr(ws), _stream()))
     return (out[0], out[1], out[2]), rep

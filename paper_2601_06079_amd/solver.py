@@ -74,15 +74,15 @@ def _ptr(t: torch.Tensor, p: Problem = None, n: int = None, name="tensor"):
 
 def workspace(p: Problem, op: int, device=None) -> torch.Tensor:
     nb = ct.c_size_t(0)
-    A.check(A.lib().pf_workspace_size(ct.byref(p.c()), op, ct.byref(nb)))
+    A.check(A.lib().pf_workspace_size(A.ctx(device), ct.byref(p.c()), op, ct.byref(nb)))
     return torch.empty(max(int(nb.value), 8), dtype=torch.uint8,
                        device=device or torch.device("cuda"))
 
 
 def residual(p: Problem, U: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
     r = torch.empty_like(U) if out is None else out
-    A.check(A.lib().pf_residual(ct.byref(p.c()), _ptr(U, p, p.ndof, "U"), _ptr(r, p, p.ndof, "r"),
-                                _stream()))
+    A.check(A.lib().pf_residual(A.ctx(), ct.byref(p.c()), _ptr(U, p, p.ndof, "U"),
+                                _ptr(r, p, p.ndof, "r"), None, _stream()))
     return r
 
 
@@ -91,7 +91,7 @@ def step_explicit(p: Problem, U: torch.Tensor, dt: float, nsteps: int,
     """nsteps explicit steps in place on U; returns U."""
     if ws is None:
         ws = workspace(p, A.OP_STEP_EXPLICIT, U.device)
-    A.check(A.lib().pf_step_explicit(ct.byref(p.c()), float(dt), int(nsteps),
+    A.check(A.lib().pf_step_explicit(A.ctx(), ct.byref(p.c()), float(dt), int(nsteps),
                                      _ptr(U, p, p.ndof, "U"), ct.c_void_p(ws.data_ptr()),
                                      _stream()))
     return U
@@ -104,7 +104,7 @@ def energy(p: Problem, U: torch.Tensor, ws: torch.Tensor = None,
         ws = workspace(p, A.OP_ENERGY, U.device)
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=U.device)
-    A.check(A.lib().pf_energy(ct.byref(p.c()), _ptr(U, p, p.ndof, "U"),
+    A.check(A.lib().pf_energy(A.ctx(), ct.byref(p.c()), _ptr(U, p, p.ndof, "U"),
                               ct.c_void_p(out.data_ptr()), ct.c_void_p(ws.data_ptr()), _stream()))
     return out
 
@@ -112,7 +112,7 @@ def energy(p: Problem, U: torch.Tensor, ws: torch.Tensor = None,
 def jvp(p: Problem, inv_dt: float, U: torch.Tensor, v: torch.Tensor,
         out: torch.Tensor = None) -> torch.Tensor:
     Jv = torch.empty_like(U) if out is None else out
-    A.check(A.lib().pf_jvp(ct.byref(p.c()), float(inv_dt), _ptr(U, p, p.ndof, "U"),
+    A.check(A.lib().pf_jvp(A.ctx(), ct.byref(p.c()), float(inv_dt), _ptr(U, p, p.ndof, "U"),
                            _ptr(v, p, p.ndof, "v"), _ptr(Jv, p, p.ndof, "Jv"), _stream()))
     return Jv
 
@@ -141,7 +141,7 @@ def newton_step(p: Problem, dt: float, U_old: torch.Tensor, U: torch.Tensor, opt
         ws = workspace(p, A.OP_NEWTON, U.device)
     o = opts if opts is not None else newton_opts()
     rep = A.pf_newton_report()
-    st = A.lib().pf_newton_step(ct.byref(p.c()), float(dt), _ptr(U_old, p, p.ndof, "U_old"),
+    st = A.lib().pf_newton_step(A.ctx(), ct.byref(p.c()), float(dt), _ptr(U_old, p, p.ndof, "U_old"),
                                 _ptr(U, p, p.ndof, "U"), ct.byref(o), ct.byref(rep),
                                 ct.c_void_p(ws.data_ptr()), _stream())
     allow = () if raise_on_noconv else (A.PF_ENOCONV, A.PF_ENONFINITE)
@@ -152,16 +152,29 @@ def newton_step(p: Problem, dt: float, U_old: torch.Tensor, U: torch.Tensor, opt
 
 
 def vjp(p: Problem, kind: int, dt: float, U: torch.Tensor, vbar: torch.Tensor,
-        Ubar: torch.Tensor, theta_bar: torch.Tensor, ws: torch.Tensor = None):
-    """Accumulate vector-Jacobian products into Ubar and theta_bar (float64[3])."""
+        Ubar: torch.Tensor, theta_bar: torch.Tensor, ws: torch.Tensor = None,
+        U_old: torch.Tensor = None):
+    """Accumulate vector-Jacobian products into Ubar and theta_bar (float64[3], on the
+    device or, making the call host-synchronous, on the host).  U_old (VJP_RESIDUAL
+    only) selects the backward-Euler residual M (U - U_old)/dt + r(U)."""
     if ws is None:
         ws = workspace(p, A.OP_VJP, U.device)
-    if theta_bar.dtype != torch.float64 or theta_bar.numel() != 3 or not theta_bar.is_cuda:
-        raise ValueError("theta_bar must be a float64 device tensor of 3 entries")
-    A.check(A.lib().pf_vjp(ct.byref(p.c()), int(kind), float(dt), _ptr(U, p, p.ndof, "U"),
-                           _ptr(vbar, p, None, "vbar"), _ptr(Ubar, p, None, "Ubar"),
-                           ct.c_void_p(theta_bar.data_ptr()), ct.c_void_p(ws.data_ptr()),
+    if theta_bar.dtype != torch.float64 or theta_bar.numel() != 3 or not theta_bar.is_contiguous():
+        raise ValueError("theta_bar must be a contiguous float64 tensor of 3 entries")
+    flags = 0 if theta_bar.is_cuda else A.VJP_THETA_HOST
+    uold = None if U_old is None else _ptr(U_old, p, p.ndof, "U_old")
+    A.check(A.lib().pf_vjp(A.ctx(), ct.byref(p.c()), int(kind), float(dt), _ptr(U, p, p.ndof, "U"),
+                           uold, _ptr(vbar, p, None, "vbar"), _ptr(Ubar, p, None, "Ubar"),
+                           ct.c_void_p(theta_bar.data_ptr()), flags, ct.c_void_p(ws.data_ptr()),
                            _stream()))
+
+
+def launch_shape(p: Problem):
+    """(steps fused per launch, rows per wave, prefetch depth) that step_explicit
+    uses for the 2-D problem p."""
+    ks, ty, dp = ct.c_int(0), ct.c_int(0), ct.c_int(0)
+    A.check(A.lib().pf_launch_shape(A.ctx(), ct.byref(p.c()), ct.byref(ks), ct.byref(ty), ct.byref(dp)))
+    return int(ks.value), int(ty.value), int(dp.value)
 
 
 def tune_set(key: int, value: int):
@@ -183,7 +196,10 @@ class CheckpointedRun(torch.autograd.Function):
     theta = (mobility, kappa, W) as a float64 tensor of 3.  Forward keeps a
     snapshot every `every` steps; backward walks the segments in reverse,
     recomputes each segment's states from its snapshot (bitwise the forward's:
-    every kernel is deterministic) and applies the step adjoint of the library
+    every kernel is deterministic, and both passes advance with the same launches:
+    fused launches are bitwise single steps on periodic grids, and no-flux grids,
+    where a fused stage rounds the reflected rows differently, take single-step
+    launches in the forward pass too) and applies the step adjoint of the library
     (pf_vjp: explicit-step VJP, or the transposed Newton solve at each root),
     accumulating the gradient of theta in FP64.  For Cahn-Hilliard explicit
     runs only the c plane of U_N is differentiated (mu is recomputed from c).
@@ -198,9 +214,14 @@ class CheckpointedRun(torch.autograd.Function):
         U = U0.detach().clone()
         ws = workspace(q, A.OP_NEWTON if implicit else A.OP_STEP_EXPLICIT, U.device)
         snaps = []
+        single = q.bc == A.NOFLUX  # match the single-step recomputation bitwise
         for _ in range(nsteps // every):
             snaps.append(U.clone())
-            _advance(q, U, dt, every, implicit, opts, ws)
+            if single:
+                for _ in range(every):
+                    _advance(q, U, dt, 1, implicit, opts, ws)
+            else:
+                _advance(q, U, dt, every, implicit, opts, ws)
         ctx.q, ctx.dt, ctx.every, ctx.implicit, ctx.opts = q, dt, every, implicit, opts
         ctx.snaps, ctx.theta_device = snaps, theta.device
         return U

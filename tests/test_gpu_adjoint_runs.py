@@ -43,6 +43,32 @@ def test_explicit_run_gradient_matches_oracle_adjoint(model):
     assert rel_l2(host(ub)[:N], uref) < 1e-10
 
 
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+def test_explicit_run_noflux_gradient_matches_oracle_adjoint(model):
+    """No-flux grid (the paper's benchmark boundary): the checkpointed explicit run's
+    gradient against the oracle's discrete adjoint, and independent of the checkpoint
+    interval bitwise (both passes advance with single-step launches there)."""
+    announce("checkpointed explicit run, no-flux, vs oracle", model)
+    fe = O.F_SYM if model == O.AC else O.F_01
+    theta = np.array([1.1, 0.9, 1.2])
+    g, o = pair((14, 11), model, fe, F64, W=theta[2], kappa=theta[1], mob=theta[0], bc=O.NOFLUX)
+    rng = np.random.default_rng(17)
+    N = o.nnodes
+    c0 = rng.uniform(0.2, 0.8, N) if model == O.CH else rng.uniform(-0.5, 0.5, N)
+    U0 = np.concatenate([c0, np.zeros(N)]) if model == O.CH else c0
+    w = rng.standard_normal(o.ndof)
+    if model == O.CH:
+        w[N:] = 0.0
+    dt, nsteps = (0.01, 12) if model == O.CH else (0.05, 12)
+    tb, ub, UN = _grads(g, theta, U0, dt, nsteps, 4, w)
+    assert rel_l2(host(UN)[:N], O.explicit(o, U0, dt, nsteps)[:N]) < 1e-12
+    tref, uref = O.explicit_adjoint(o, dt, nsteps, U0, w[:N])
+    np.testing.assert_allclose(host(tb), tref, rtol=1e-9, atol=1e-13)
+    assert rel_l2(host(ub)[:N], uref) < 1e-10
+    tb2, ub2, _ = _grads(g, theta, U0, dt, nsteps, 12, w)
+    assert torch.equal(tb, tb2) and torch.equal(ub, ub2)
+
+
 def _oracle_implicit_adjoint(o, dt, nsteps, U0, w):
     """Chain of the oracle's one-step BE adjoints along its own roots."""
     states = [np.asarray(U0, float)]

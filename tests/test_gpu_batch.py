@@ -98,7 +98,7 @@ def test_batched_vjp_independent_of_plan_shape():
         ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
         lam = lam0.clone()
         tb = torch.zeros(b.count * 3, dtype=F64, device="cuda")
-        A.check(b.L.pf_vjp_explicit_batched(ct.byref(info), ct.c_void_p(plan.data_ptr()), nsteps,
+        A.check(b.L.pf_vjp_explicit_batched(A.ctx(), ct.byref(info), ct.c_void_p(plan.data_ptr()), nsteps,
                                             ct.c_void_p(states.data_ptr()), ct.c_void_p(lam.data_ptr()),
                                             ct.c_void_p(tb.data_ptr()), ct.c_void_p(ws.data_ptr()),
                                             A.VJP_BEGIN | A.VJP_END,

@@ -137,6 +137,29 @@ def test_cahn_hilliard_2048_full_size_one_step():
     assert rel_l2(ug[:N] - U0[:N], uo[:N] - U0[:N]) < 2e-3
 
 
+def test_cahn_hilliard_2048_benchmark_plan_10_steps():
+    """The benchmark's own launch plan at full size: 2048^2 with the default shape
+    (two fused steps per launch, balanced chunks), 10 steps = 5 fused launches and
+    the chemical-potential epilogue, element by element against the FP64 oracle.
+
+    Tolerances: c to the benchmark spec's 1e-5 relative L2 (FP32 fields).  The mu plane
+    is formed from 9 c - box(c) with c near 0.5, where FP32 cancellation leaves an
+    absolute error of a few ulp(4.5) ~ 1e-6 against mu values of RMS ~ 3e-2, so mu is
+    held to 1e-4.  The update c_n - c_0 (a far stricter measure: it removes the
+    uniform 0.5) is held to 2e-3, as for one step."""
+    cfg = I.CH2048
+    announce("CH2048 fp32 benchmark plan, 10 steps")
+    g, o = pair(cfg["n"], O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    ks, ty, depth = S.launch_shape(g)
+    assert ks == 2, (ks, ty, depth)  # the plan the benchmark times
+    U0 = rounded(I.initial_state(cfg, seed=0), F32)
+    ug, uo = _run_explicit(g, o, U0, cfg["dt"], 10, F32)
+    N = o.nnodes
+    assert rel_l2(ug[:N], uo[:N]) < 1e-5
+    assert rel_l2(ug[N:], uo[N:]) < 1e-4
+    assert rel_l2(ug[:N] - U0[:N], uo[:N] - U0[:N]) < 2e-3
+
+
 def test_cahn_hilliard_2048_mass_and_energy_over_steps():
     cfg = I.CH2048
     announce("CH2048 invariants")
@@ -192,27 +215,91 @@ def test_explicit_launch_shapes_agree(rows):
     assert torch.equal(ref, t)
 
 
+def _fused_vs_single(g, U0, dt, nsteps, ks, dtype):
+    """(single-step launches, launches fusing ks steps) from the same state."""
+    out = []
+    for fuse in (1, ks):
+        try:
+            S.tune_set(A.TUNE_STREAM2D_FUSE, fuse)
+            t = dev(U0, dtype)
+            S.step_explicit(g, t, dt, nsteps)
+        finally:
+            S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+        out.append(t)
+    return out
+
+
 @pytest.mark.parametrize("ks", [2, 3, 4])
 @pytest.mark.parametrize("dtype", [F32, F64])
 @pytest.mark.parametrize("model,n", [(O.AC, (128, 128)), (O.CH, (200, 150)), (O.CH, (61, 37)),
                                      (O.AC, (5, 7)), (O.CH, (2048, 64))])
 def test_explicit_temporal_blocking_bitwise(ks, dtype, model, n):
-    """ks fused steps per launch give bitwise the field of ks single-step launches."""
+    """ks fused steps per launch give bitwise the field of ks single-step launches
+    (the reference runs with fusion switched off)."""
     announce("fused", ks, dtype, model, n)
     fe = O.F_01 if model == O.CH else O.F_SYM
     g, o = pair(n, model, fe, dtype, W=1.0, kappa=2.0 if model == O.CH else 1.0, mob=1.0)
     base = 0.5 if model == O.CH else 0.0
     U0 = _rand_state(o, -0.05, 0.05, 12, base=base)
     dt = 0.01 if model == O.CH else 0.1
-    ref = dev(U0, dtype)
-    S.step_explicit(g, ref, dt, 2 * ks + 1)
-    try:
-        S.tune_set(A.TUNE_STREAM2D_FUSE, ks)
-        t = dev(U0, dtype)
-        S.step_explicit(g, t, dt, 2 * ks + 1)
-    finally:
-        S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+    ref, t = _fused_vs_single(g, U0, dt, 2 * ks + 1, ks, dtype)
     assert torch.equal(ref, t)
+
+
+def _seam_plan_applies(n, model, ks, rows):
+    """The chunk plan of the LDS seam-sharing fused kernel: chunks rounded to whole
+    workgroups of 4, the shortest balanced chunk long enough for the barrier."""
+    H = 1 if model == O.AC else 2
+    nch = -(-n[1] // rows)
+    nch = -(-nch // 4) * 4
+    first = -(-(2 * H * ks) // 4) * 4
+    return n[1] // nch >= max(first + 4, 8)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model,n,ks,rows", [(O.CH, (512, 600), 2, 19), (O.CH, (512, 600), 2, 40),
+                                             (O.CH, (200, 333), 3, 24), (O.CH, (130, 640), 4, 32),
+                                             (O.AC, (300, 512), 2, 12), (O.AC, (97, 401), 4, 24),
+                                             (O.CH, (64, 97), 2, 25)])
+def test_explicit_seam_kernel_bitwise(dtype, model, n, ks, rows):
+    """Fused launches whose workgroups share the chunk seams through LDS (the plan
+    applies to every case here): bitwise the single-step launches, and bitwise the
+    fused kernel that recomputes the seams."""
+    announce("seam", dtype, model, n, ks, rows)
+    assert _seam_plan_applies(n, model, ks, rows)
+    fe = O.F_01 if model == O.CH else O.F_SYM
+    g, o = pair(n, model, fe, dtype, W=1.0, kappa=2.0 if model == O.CH else 1.0, mob=1.0)
+    U0 = _rand_state(o, -0.05, 0.05, 31, base=0.5 if model == O.CH else 0.0)
+    dt = 0.01 if model == O.CH else 0.1
+    try:
+        S.tune_set(A.TUNE_STREAM2D_ROWS, rows)
+        ref, t = _fused_vs_single(g, U0, dt, 3 * ks + 1, ks, dtype)
+        assert torch.equal(ref, t)
+        S.tune_set(A.TUNE_STREAM2D_SEAM, 1)
+        _, t2 = _fused_vs_single(g, U0, dt, 3 * ks + 1, ks, dtype)
+        assert torch.equal(t, t2)
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_SEAM, 0)
+        S.tune_set(A.TUNE_STREAM2D_ROWS, 0)
+
+
+def test_explicit_temporal_blocking_bitwise_benchmark_shape():
+    """The 2048^2 Cahn-Hilliard workload: its default fused plan against single-step
+    launches, bitwise, over 6 steps (3 fused launches)."""
+    announce("fused 2048^2 vs single steps")
+    cfg = I.CH2048
+    g, o = pair(cfg["n"], O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    ks, rows, _ = S.launch_shape(g)
+    assert ks >= 2 and _seam_plan_applies(cfg["n"], O.CH, ks, rows)
+    U0 = I.initial_state(cfg, seed=1, dtype=np.float32)
+    ref, t = _fused_vs_single(g, U0, cfg["dt"], 3 * ks, ks, F32)
+    assert torch.equal(ref, t)
+    try:  # the fused kernel that recomputes the seams gives the same bits
+        S.tune_set(A.TUNE_STREAM2D_SEAM, 1)
+        _, t2 = _fused_vs_single(g, U0, cfg["dt"], 3 * ks, ks, F32)
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_SEAM, 0)
+    assert torch.equal(t, t2)
 
 
 @pytest.mark.parametrize("planes", [1, 3, 7, 40])

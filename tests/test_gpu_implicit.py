@@ -122,6 +122,11 @@ def test_newton_cg_rejects_unsupported():
         S.newton_step(g, 1.0, U0, U0.clone(), S.newton_opts(krylov=A.KRYLOV_CG))
     with pytest.raises(A.PFError):
         S.newton_step(g, 0.5, U0, U0.clone(), S.newton_opts(krylov=7))
+    # the positive-definiteness argument needs L > 0, kappa >= 0 and W >= 0
+    for bad in (dict(mobility=-1.0), dict(kappa=-0.5), dict(W=-1.0)):
+        q = S.Problem(**{**g.__dict__, **bad})
+        with pytest.raises(A.PFError):
+            S.newton_step(q, 0.5, U0, U0.clone(), S.newton_opts(krylov=A.KRYLOV_CG))
     gc, oc = pair((8, 8), O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
     Uc = dev(_ch_state(oc, 0.4, 0.05, 4), F32)
     with pytest.raises(A.PFError):
@@ -164,8 +169,102 @@ def test_newton_3d_ch_32_cubed_several_steps():
     assert abs(host(Ug)[:N].mean() - U0[:N].mean()) < 1e-6
 
 
+def _ch3d_start(n, seed=0):
+    """The 3-D implicit workload's initial state on an n grid: c0 = 0.4 + U(-0.02, 0.02)
+    rounded to FP32, mu0 = [N(c0) + kappa K c0]/m from the oracle (FP64)."""
+    cfg = I.CH3D128
+    o = O.Problem(n=n, model=O.CH, fe=O.F_01, W=1.0, kappa=2.0, mob=1.0)
+    c0 = rounded(I.uniform_field(n, cfg["lo"], cfg["hi"], seed=seed, base=cfg["base"]), F32)
+    return O.explicit(o, np.concatenate([c0, np.zeros_like(c0)]), 1.0, 0)
+
+
+def test_newton_3d_ch_64_cubed_one_step_fieldwise():
+    """One backward-Euler step of the 3-D Cahn-Hilliard workload at 64^3 (524 288
+    unknowns), both planes element by element against the oracle's Newton step
+    (GMRES to 1e-8 inside, root to 1e-9: its error is ~1e-10, far below FP32).  The
+    the benchmark spec's per-step tolerance 1e-5 holds for c and for mu (a Newton unknown
+    here, of size ~0.1, not a small difference)."""
+    cfg = I.CH3D128
+    n = (64, 64, 64)
+    announce("newton 3d 64^3 fieldwise")
+    g, o = pair(n, O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U0 = rounded(_ch3d_start(n), F32)
+    Ug = dev(U0, F32)
+    rep = S.newton_step(g, cfg["dt"], dev(U0, F32), Ug)
+    assert rep.converged, rep
+    Uo, conv, _, _ = O.newton_be(o, cfg["dt"], U0, rtol=1e-9, maxit=30, solver=1, lin_rtol=1e-8)
+    assert conv
+    N = o.nnodes
+    got = host(Ug)
+    assert rel_l2(got[:N], Uo[:N]) < 1e-5
+    assert rel_l2(got[N:], Uo[N:]) < 1e-5
+    # the step itself (c_1 - c_0), far smaller than c
+    assert rel_l2(got[:N] - U0[:N], Uo[:N] - U0[:N]) < 1e-3
+    assert abs(got[:N].mean() - U0[:N].mean()) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def ch3d_32_run():
+    """State shared by the segments of the 200-step 32^3 run (oracle and GPU)."""
+    cfg = I.CH3D128
+    n = (32, 32, 32)
+    g, o = pair(n, O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U0 = rounded(_ch3d_start(n), F32)
+    return dict(cfg=cfg, g=g, o=o, U0=U0, Uo=U0.copy(), Ufree=dev(U0, F32), k=0,
+                ws=S.workspace(g, A.OP_NEWTON))
+
+
+@pytest.mark.parametrize("segment", range(5))
+def test_newton_3d_ch_32_cubed_200_steps(ch3d_32_run, segment):
+    """The 3-D implicit workload's 200 backward-Euler steps (t = 100) at 32^3, in five
+    segments of 40 steps on one trajectory.  The spinodal instability grows the
+    fluctuations of c from std 1e-3 (the fastest mode at M f''(0.4)^2 / (4 kappa) =
+    0.097 per unit time) to domains of both phases (std > 0.05) within the run, so it
+    covers the linear regime, domain formation and the start of coarsening.  Two
+    comparisons with the oracle's trajectory:
+      - per step: the GPU step taken from the oracle's state k (rounded to FP32)
+        against the oracle's state k + 1, both planes, at the north star's 1e-5;
+      - free-running: the GPU's own trajectory against the oracle's.  Their
+        difference starts at FP32 rounding (~1e-7) and grows at most like the
+        instability (e^(0.097 t)), saturating once domains form; held to 1e-3 (the
+        the benchmark spec's long-run field tolerance), with mass conserved to 1e-6."""
+    r = ch3d_32_run
+    assert r["k"] == 40 * segment, "segments run in order on one trajectory"
+    cfg, g, o, ws = r["cfg"], r["g"], r["o"], r["ws"]
+    N = o.nnodes
+    m0 = r["U0"][:N].mean()
+    announce("newton 3d 32^3, steps", r["k"], "..", r["k"] + 40)
+    for _ in range(40):
+        k = r["k"]
+        Uk = dev(rounded(r["Uo"], F32), F32)  # the GPU step from the oracle's state k
+        Ug = Uk.clone()
+        rep = S.newton_step(g, cfg["dt"], Uk, Ug, ws=ws)
+        assert rep.converged, (k, rep)
+        Uprev = r["Ufree"].clone()  # the free-running GPU trajectory
+        rep = S.newton_step(g, cfg["dt"], Uprev, r["Ufree"], ws=ws)
+        assert rep.converged, (k, rep)
+        Uo, conv, _, _ = O.newton_be(o, cfg["dt"], r["Uo"], rtol=1e-8, maxit=30, solver=1, lin_rtol=1e-6)
+        assert conv, k
+        r["Uo"] = Uo
+        r["k"] = k + 1
+        one, free = host(Ug), host(r["Ufree"])
+        e_step = max(rel_l2(one[:N], Uo[:N]), rel_l2(one[N:], Uo[N:]))
+        e_free = rel_l2(free[:N], Uo[:N])
+        assert e_step < 1e-5, (k, e_step)
+        assert e_free < 1e-3, (k, e_free)
+        assert abs(free[:N].mean() - m0) < 1e-6, k
+    print(f"[gpu-case] 32^3 step {r['k']}: one-step {e_step:.2e}, free-running {e_free:.2e}, "
+          f"std(c) {Uo[:N].std():.3e}", flush=True)
+    if r["k"] == 200:  # the run has left the near-uniform state: domains of both phases
+        assert Uo[:N].std() > 0.05, Uo[:N].std()
+
+
 def test_newton_3d_ch_128_cubed_full_size_one_step():
-    """Full-size 128^3 (4.19M DOF) step: the oracle checks the root through its own residual."""
+    """Full-size 128^3 (4.19M DOF) step.  The oracle cannot afford the root at this
+    size, so the check is a property that holds at any size: the oracle's FP64
+    residual of Eq. 14 at the GPU's FP32 root is at the floor that FP32 storage of
+    the root itself imposes, i.e. no larger than a few times ||J d|| for d a
+    perturbation of one rounding unit (2^-24 |U|, random signs) of the same root."""
     cfg = I.CH3D128
     n = cfg["n"]
     announce("newton 3d 128^3")
@@ -179,7 +278,11 @@ def test_newton_3d_ch_128_cubed_full_size_one_step():
     U1 = host(Ug)
     R0 = np.linalg.norm(O.be_residual(o, cfg["dt"], Uold, Uold))
     R1 = np.linalg.norm(O.be_residual(o, cfg["dt"], Uold, U1))
-    assert R1 < 1e-3 * R0, (R1, R0, rep)
+    sgn = np.where(np.random.default_rng(5).random(U1.size) < 0.5, -1.0, 1.0)
+    d = sgn * np.abs(U1) * 2.0 ** -24
+    floor = np.linalg.norm(O.jvp(o, 1.0 / cfg["dt"], U1, d))
+    print(f"[gpu-case] 128^3 |R(U1)| = {R1:.3e}, rounding floor {floor:.3e}, |R0| = {R0:.3e}", flush=True)
+    assert R1 < 4.0 * floor, (R1, floor, R0, rep)
     N = o.nnodes
     assert abs(U1[:N].astype(np.float64).mean() - Uold[:N].astype(np.float64).mean()) < 1e-6
 
@@ -219,6 +322,59 @@ def test_vjp_residual(model, n, dtype):
     tol = 1e-11 if dtype == F64 else 1e-5
     assert rel_l2(host(Ub), O.jvp_t(o, 0.0, U, w)) < tol
     np.testing.assert_allclose(host(tb), O.dr_dtheta(o, U, w), rtol=tol * 10)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("model,n,mass", [(O.AC, (20, 17), 0), (O.CH, (16, 13), 0), (O.CH, (5, 6, 7), 0),
+                                          (O.AC, (9, 8), 1), (O.CH, (7, 6), 1)])
+def test_vjp_backward_euler_residual_host_theta(model, n, mass, dtype):
+    """pf_vjp of the backward-Euler residual R = M (U - U_old)/dt + r(U) (U_old given):
+    Ubar = (dR/dU)^T w (the oracle's transposed Jacobian product with the time term),
+    with theta_bar accumulated into host memory (added to what it held)."""
+    announce("vjp BE residual, host theta", model, n, mass, dtype)
+    g, o = pair(n, model, O.F_01, dtype, W=1.2, kappa=0.8, mob=1.3)
+    g.mass = o.mass = mass
+    dt = 0.3
+    U = rounded(np.random.default_rng(12).uniform(0.2, 0.8, o.ndof), dtype)
+    Uold = rounded(np.random.default_rng(13).uniform(0.2, 0.8, o.ndof), dtype)
+    w = rounded(np.random.default_rng(14).standard_normal(o.ndof), dtype)
+    Ub = torch.zeros(o.ndof, dtype=dtype, device="cuda")
+    tb = torch.tensor([0.5, -0.25, 2.0], dtype=F64)  # host, accumulated into
+    S.vjp(g, A.VJP_RESIDUAL, dt, dev(U, dtype), dev(w, dtype), Ub, tb, U_old=dev(Uold, dtype))
+    tol = 1e-11 if dtype == F64 else 1e-5
+    assert rel_l2(host(Ub), O.jvp_t(o, 1.0 / dt, U, w)) < tol
+    np.testing.assert_allclose(tb.numpy() - [0.5, -0.25, 2.0], O.dr_dtheta(o, U, w), rtol=tol * 10)
+
+
+def test_context_lifecycle_on_device():
+    """A device context made and freed through the ABI: calls with it run, two
+    contexts on one device give the same results, a missing device is an error."""
+    import ctypes as ct
+    L = A.lib()
+    g, o = pair((40, 33), O.CH, O.F_01, F32, W=1.0, kappa=2.0, mob=1.0)
+    U = dev(I.initial_state(dict(I.CH2048, n=(40, 33)), seed=2, dtype=np.float32), F32)
+    h = ct.c_void_p()
+    assert L.pf_create(torch.cuda.current_device(), ct.byref(h)) == A.PF_OK and h.value
+    d = ct.c_int(-9)
+    assert L.pf_ctx_device(h, ct.byref(d)) == A.PF_OK and d.value == torch.cuda.current_device()
+    r1 = torch.empty_like(U)
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.pf_residual(h, ct.byref(g.c()), ct.c_void_p(U.data_ptr()), ct.c_void_p(r1.data_ptr()), None,
+                         stream) == A.PF_OK
+    r2 = S.residual(g, U)  # the binding's default context
+    assert torch.equal(r1, r2)
+    Uold = U.clone()
+    U2 = U.clone()
+    ws = S.workspace(g, A.OP_NEWTON)
+    rep = A.pf_newton_report()
+    assert L.pf_newton_step(h, ct.byref(g.c()), 0.5, ct.c_void_p(Uold.data_ptr()), ct.c_void_p(U2.data_ptr()),
+                            None, ct.byref(rep), ct.c_void_p(ws.data_ptr()), stream) == A.PF_OK
+    assert rep.converged
+    assert L.pf_destroy(h) == A.PF_OK
+    U3 = U.clone()
+    S.newton_step(g, 0.5, Uold, U3)
+    assert torch.equal(U2, U3)
+    assert L.pf_create(torch.cuda.device_count(), ct.byref(h)) == A.PF_EDEVICE
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])

@@ -157,6 +157,80 @@ def test_backward_matches_oracle(shape):
         off += n
 
 
+@pytest.mark.parametrize("shape", [(2, 8, 64), (1, 16, 32)])
+def test_backward_exact_dyadic(shape):
+    """Exact arithmetic through the whole backward pass (pins every index of the
+    weight and data gradients).  The forward is exact (dyadic weights and inputs, see
+    _dyadic); with H W = 512 every c_hat is a multiple of 2^-23 below 2 in magnitude,
+    so FP32 holds it exactly on both sides.  The target is c_hat minus a zero-mean
+    offset delta of +-2^-6 on a few pixels, so dL/dc_hat = 2 delta / (H W) = +-2^-14,
+    its mean is exactly 0 and the data gradients stay multiples of 2^-24 whose sums
+    fit FP32's 24 bits (9 x 2^-24 after the output layer, below 2^-12 after layer 3,
+    below 2^-3.8 after layer 2): each side rounds the same exact values to bf16.
+    The weight gradients are FP32 sums over pixels in different orders on the two
+    sides, so they agree to accumulation rounding (held to 1e-6); the output bias
+    has an exactly zero gradient on both sides."""
+    announce("nn backward exact", shape)
+    Bn, H, W = shape
+    HW = H * W
+    assert HW == 512
+    c, M, k, p = _dyadic(31 + H, Bn, H, W)
+    assert _exact_bound(p) < 2.0 ** 24
+    Mb, kb = M[:, None, None] * np.ones_like(c), k[:, None, None] * np.ones_like(c)
+    ref, _, _ = O.nn(c, Mb, kb, p, round_bf16=True)
+    r = np.random.default_rng(7 + H)
+    delta = np.zeros((Bn, H, W))
+    for b in range(Bn):
+        idx = r.choice(HW, 12, replace=False)
+        delta[b].flat[idx[:6]] = 2.0 ** -6
+        delta[b].flat[idx[6:]] = -2.0 ** -6
+    t = ref - delta
+    assert np.array_equal(t.astype(np.float32).astype(np.float64), t)
+    model = NN.Surrogate(params=p)
+    cd, Md, kd = _dev(c.astype(np.float32)), _dev(M.astype(np.float32)), _dev(k.astype(np.float32))
+    got = host(model.forward(cd, Md, kd))
+    assert np.array_equal(got, ref)  # the forward is exact
+    loss, grad = model.loss_and_grad(cd, Md, kd, _dev(t.astype(np.float32)))
+    _, lref, gref = O.nn(c, Mb, kb, p, target=t, round_bf16=True, grad=True)
+    assert lref == Bn * 12 * 2.0 ** -12 / HW
+    assert float(host(loss).sum()) == lref
+    g = host(grad)
+    off = 0
+    for name, shp in NN.LAYOUT:
+        n = int(np.prod(shp))
+        if name == "b4":
+            assert g[off] == 0.0 and gref[off] == 0.0
+        else:
+            assert np.linalg.norm(gref[off:off + n]) > 0, name
+            err = rel_l2(g[off:off + n], gref[off:off + n])
+            assert err < 1e-6, (name, err)
+        off += n
+
+
+def test_backward_matches_oracle_8192_pixels():
+    """Random weights on 2 x 64 x 64 = 8192 pixels: the rounding flips of single
+    activations (see test_forward_matches_oracle) average out over this many pixels,
+    so every layer's gradient is held to 1e-3 relative L2."""
+    announce("nn backward 8192 px")
+    Bn, H, W = 2, 64, 64
+    c, M, k, t = _inputs(Bn, H, W, 13)
+    p = _params(14)
+    model = NN.Surrogate(params=p)
+    loss, grad = model.loss_and_grad(_dev(c), _dev(M), _dev(k), _dev(t))
+    _, lref, gref = O.nn(c.astype(np.float64), M[:, None, None].astype(np.float64),
+                         k[:, None, None].astype(np.float64), p, target=t.astype(np.float64),
+                         round_bf16=True, grad=True)
+    assert float(host(loss).sum()) == pytest.approx(lref, rel=1e-4)
+    g = host(grad)
+    off = 0
+    for name, shp in NN.LAYOUT:
+        n = int(np.prod(shp))
+        if name != "b4":
+            err = rel_l2(g[off:off + n], gref[off:off + n])
+            assert err < 1e-3, (name, err)
+        off += n
+
+
 def test_adam_matches_oracle():
     model = NN.Surrogate(seed=5)
     p0 = host(model.params).astype(np.float64)

@@ -101,14 +101,16 @@ def test_explicit_noflux_fused_matches_single_steps(ks, model, n):
     g, o = pair(n, model, fe, F32, W=1.0, kappa=2.0 if model == O.CH else 1.0, mob=1.0, bc=NF)
     U0 = _state(o, -0.05, 0.05, 12, base=0.5 if model == O.CH else 0.0)
     dt = 0.01 if model == O.CH else 0.1
-    ref = dev(U0, F32)
-    S.step_explicit(g, ref, dt, 2 * ks + 1)
-    try:
-        S.tune_set(A.TUNE_STREAM2D_FUSE, ks)
-        t = dev(U0, F32)
-        S.step_explicit(g, t, dt, 2 * ks + 1)
-    finally:
-        S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+    out = []
+    for fuse in (1, ks):  # single-step launches, then ks fused steps per launch
+        try:
+            S.tune_set(A.TUNE_STREAM2D_FUSE, fuse)
+            t = dev(U0, F32)
+            S.step_explicit(g, t, dt, 2 * ks + 1)
+        finally:
+            S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+        out.append(t)
+    ref, t = out
     N = o.nnodes
     assert rel_l2(host(t)[:N] - U0[:N], host(ref)[:N] - U0[:N]) < 1e-5
     assert rel_l2(host(t)[:N], O.explicit(o, rounded(U0, F32), dt, 2 * ks + 1)[:N]) < 1e-5
