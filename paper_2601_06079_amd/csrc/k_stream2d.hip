@@ -208,6 +208,121 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     stream_item<T, MODEL, PF, KS, false, MIRROR>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
 }
 
+// Fused steps with the chunk seams shared through LDS (periodic grids).
+//
+// A workgroup holds SEAM_NW consecutive chunks of one strip, one per wave.  Stage s
+// of the chunk with rows [y0, y1) produces rows [y0 + s H, y1 + s H): the stages
+// form a parallelogram in (row, step).  Stage s >= 1 then consumes stage s-1's rows
+// [y0 + (s-1) H, y1 + (s+1) H); the top 2H of them are the first 2H rows the chunk
+// above produces at stage s-1.  Every wave leaves those first rows of each stage
+// but the last in LDS; after one barrier, the wave below pushes them through its
+// next stage at the end of its sweep instead of computing them again.  The top wave
+// of a workgroup has no neighbour above in LDS and computes its rows itself.
+//
+// Per chunk and KS steps a wave pushes KS (ty + 2H) rows (the top wave of the
+// workgroup H KS (KS - 1) more), against KS (ty + 2 H KS) for k_explicit2d.  Every
+// stage runs exactly the arithmetic of a single step on the same inputs, so the
+// result is bitwise that of KS single-step launches.
+//
+// Loop index t = 0 .. ty + 2 KS H - 1: input row y0 - H + t enters stage 0; stage
+// s emits row y0 - (s + 2) H + t, valid once t >= 2 H (s + 1).  Must be launched
+// with whole workgroups (nchunks a multiple of SEAM_NW): every wave reaches the one
+// barrier.
+constexpr int SEAM_NW = 4;  // waves (chunks) per workgroup
+
+template <typename T, int MODEL, int KS>
+__global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                                         int ny, int nchunks, int nblocks, unsigned bytes,
+                                                         Coef<T> k)
+{
+    constexpr int PF = 4;
+    constexpr int H = MODEL == 0 ? 1 : 2;
+    constexpr int HK = H * KS;
+    constexpr int OUTW = WAVE - 2 * HK;
+    constexpr int FILL = 2 * H * KS;                     // first loop index of a valid output
+    constexpr int FIRST = (FILL + PF - 1) / PF * PF;     // seam rows are all in LDS after these
+    static_assert(KS >= 2, "seam kernel: fused steps only");
+    __shared__ T seam[SEAM_NW][KS - 1][2 * H][WAVE];
+
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous range of
+    // workgroups, so that the rows neighbouring chunks share stay in one L2
+    const int b = (int)blockIdx.x, xcd = b % 8, per = nblocks / 8, rem = nblocks % 8;
+    const int blk = xcd * per + min(xcd, rem) + b / 8;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int wave = blk * SEAM_NW + wv;
+    const int strip = wave / nchunks, chunk = wave % nchunks;
+    const bool top = wv == SEAM_NW - 1;  // no neighbour above in this workgroup
+    const int y0 = (int)((long long)chunk * ny / nchunks);
+    const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
+    const int ty = y1 - y0;
+    const int iters = ty + FILL;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int xl = strip * OUTW - HK + lane;
+    int x = xl % nx;
+    if (x < 0) x += nx;
+    const bool out_lane = lane >= HK && lane < WAVE - HK && xl < nx;
+    const int rowb = nx * (int)sizeof(T);
+    const int vx = x * (int)sizeof(T);
+    const auto rin = make_rsrc(in, bytes);
+    const auto rout = make_rsrc(out, bytes);
+
+    Stage<T, MODEL> st[KS];
+    T ring[PF];
+    // input rows y0 - H .. (the top wave reads 2 H (KS - 1) rows further)
+    int rl = y0 - H;
+    while (rl < 0) rl += ny;
+    int rlast = y0 - H + (top ? iters : ty + 2 * H) - 1;
+    while (rlast >= ny) rlast -= ny;
+    int ro = y0 + (KS - 1) * H;  // first output row (the last stage's), wraps
+    while (ro >= ny) ro -= ny;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        ring[u] = bload<T>(rin, vx, rl * rowb);
+        if (++rl == ny) rl = 0;
+    }
+    const int need = (top ? iters : ty + 2 * H);  // input rows this wave reads
+    auto body = [&](int t, int u) {
+        T v = ring[u];
+        ring[u] = bload<T>(rin, vx, rl * rowb);
+        if (t + PF + 1 < need) {
+            if (++rl == ny) rl = 0;
+        } else {
+            rl = rlast;
+        }
+        // stage s pushes from t = 2 H s; a wave below the top of its workgroup stops
+        // stage s (all but the last) at row y1 + s H (t = own) and hands the next
+        // stage the 2H rows the wave above left in LDS instead
+        T o = v;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int lo = 2 * H * s, own = ty + 2 * H * (s + 1);
+            if (t >= lo) {
+                if (top || s == KS - 1 || t < own)
+                    o = st[s].push(o, k);
+                else if (t < own + 2 * H)
+                    o = seam[wv + 1][s][t - own][lane];
+                if (s < KS - 1 && t >= lo + 2 * H && t < lo + 4 * H) seam[wv][s][t - lo - 2 * H][lane] = o;
+            }
+        }
+        if (t >= FILL) {
+            if (out_lane) bstore(o, rout, vx, ro * rowb);
+            if (++ro == ny) ro = 0;
+        }
+    };
+    // the first FIRST rows write every seam row this wave owes the wave below (the
+    // launcher guarantees iters >= FIRST + PF and that no seam row is read before)
+    for (int t0 = 0; t0 < FIRST; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) body(t0 + u, u);
+    }
+    __syncthreads();
+    for (int t0 = FIRST; t0 < iters; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (t0 + u < iters) body(t0 + u, u);
+    }
+}
+
 // Ragged batch: wave w processes work item items[w] = (sample, strip, chunk)
 // of a batch of independent problems packed in one array (see BatchSample).
 template <typename T, int MODEL, int PF, int KS, bool MID = false>
@@ -240,6 +355,30 @@ void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int
         k_explicit2d<T, MODEL, 8, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     else
         k_explicit2d<T, MODEL, 16, KS><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+}
+
+// The seam kernel for a periodic grid when its chunk plan fits (nchunks a multiple
+// of SEAM_NW, chunks long enough that no seam row is read before the barrier).
+// Returns false (nothing launched) otherwise.
+template <typename T, int MODEL>
+bool launch_seam(int ks, int ty, hipStream_t s, const T* in, T* out, int nx, int ny, int nstrips,
+                 unsigned bytes, const Coef<T>& k)
+{
+    constexpr int H = MODEL == 0 ? 1 : 2;
+    if (ks < 2 || ks > 4 || tune_stream2d_seam() == 1) return false;
+    int nch = (ny + ty - 1) / ty;
+    nch = (nch + SEAM_NW - 1) / SEAM_NW * SEAM_NW;
+    const int fill = 2 * H * ks, first = (fill + 3) / 4 * 4;
+    if (ny / nch < first + 4 || ny / nch < 8) return false;  // shortest balanced chunk
+    const long long waves = (long long)nstrips * nch;
+    if (waves / SEAM_NW > (1ll << 30)) return false;
+    const int nblocks = (int)(waves / SEAM_NW);
+    switch (ks) {
+        case 2: k_explicit2d_seam<T, MODEL, 2><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+        case 3: k_explicit2d_seam<T, MODEL, 3><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+        default: k_explicit2d_seam<T, MODEL, 4><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+    }
+    return true;
 }
 
 template <typename T, int MODEL>
@@ -321,13 +460,15 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
         const double sc = dt * mob * detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
+        if (g.bc || cfg.depth > 4 || !launch_seam<T, 0>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k))
+            launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
     } else {
         const double sc = detJ / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
         k.beta = (T)(kappa / (3.0 * m));
         k.gamma = (T)(dt * mob / (3.0 * m));
-        launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
+        if (g.bc || cfg.depth > 4 || !launch_seam<T, 1>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k))
+            launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
     }
 }
 
