@@ -18,7 +18,14 @@ Prints ONE JSON line (rank 0):
   adjoint: wall time of the checkpointed batched adjoint gradient vs the six
     forward runs central differences need (64 ragged Allen-Cahn samples),
   surrogate: cost of one checked surrogate jump vs the K = 20 plain steps it replaces,
-  cpu_baseline: the FP64 CPU reference timed on a bounded sample.
+  cpu_baseline: the FP64 CPU reference timed on a bounded sample: one core (the
+    oracle as the tests use it), all host cores (its OpenMP timing build), and
+    bounded legs of the other workloads.
+
+Before the W warm-up steps the step runs untimed for --settle-ms: a per-launch
+kernel trace of a cold process shows the first ~500 launches (about 10 ms of work)
+running about 10% slower than the steady state (the device's clocks ramping up
+from idle); the timed K steps then measure the steady state however small W is.
 """
 from __future__ import annotations
 
@@ -56,6 +63,10 @@ def parse():
     # (clock ramp); the warm-up is untimed
     ap.add_argument("--warmup", type=int, default=3000)
     ap.add_argument("--n", type=int, default=2048, help="grid side (default: the 2048^2 workload)")
+    ap.add_argument("--settle-ms", type=float, default=300.0,
+                    help="untimed run of the step before the warm-up steps (clock ramp), milliseconds")
+    ap.add_argument("--fuse", type=int, default=0,
+                    help="steps fused per launch (0: the library's choice; for profiling one kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--coupled", type=int, default=0, metavar="STEPS",
@@ -146,8 +157,34 @@ def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
     print(json.dumps(rec))
 
 
+def _host():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(n, steps):
-    """FP64 oracle on the same workload: `steps` explicit split steps at full size."""
+    """The FP64 oracle on the workload's host cores, on bounded samples:
+      - value: `steps` explicit split steps of the n^2 workload, single-threaded (the
+        oracle the tests use);
+      - all_cores: the same steps with the oracle's OpenMP timing build (element
+        colours in parallel) on every thread OMP_NUM_THREADS allows;
+      - legs: bounded runs of the other workloads, each extrapolated (labelled) to the
+        full run: the 128^2 FP64 Allen-Cahn run (whole), one 64^3 backward-Euler
+        Cahn-Hilliard step, 4 of the 64 calibration samples for 100 of 2000 steps, and
+        the 20 plain steps one 512^2 surrogate jump replaces."""
     import numpy as np
 
     import oracle as O
@@ -159,9 +196,70 @@ def cpu_baseline(n, steps):
     t0 = time.perf_counter()
     O.explicit(o, U0, cfg["dt"], steps)
     el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, threads = O.explicit_threaded(o, U0, cfg["dt"], steps)
+    el_mt = time.perf_counter() - t0
+    legs = {}
+    # 128^2 Allen-Cahn, FP64, 1000 steps: the whole run
+    c1 = I.AC128
+    o1 = O.Problem(n=c1["n"], model=O.AC, fe=O.F_SYM, W=1.0, kappa=1.0, mob=1.0)
+    t0 = time.perf_counter()
+    O.explicit(o1, I.initial_state(c1, seed=0), c1["dt"], c1["steps"])
+    e1 = time.perf_counter() - t0
+    legs["ac128_fp64"] = {"sample": f"the whole run: {c1['steps']} steps", "seconds": e1,
+                          "dof_steps_per_s": 128 * 128 * c1["steps"] / e1}
+    # one backward-Euler step of 3-D Cahn-Hilliard at 64^3 (the 128^3 workload is 8x the nodes)
+    c3 = I.CH3D128
+    o3 = O.Problem(n=(64, 64, 64), model=O.CH, fe=O.F_01, W=1.0, kappa=2.0, mob=1.0)
+    cc = I.uniform_field((64, 64, 64), c3["lo"], c3["hi"], seed=0, base=c3["base"])
+    U3 = O.explicit(o3, np.concatenate([cc, np.zeros_like(cc)]), 1.0, 0)
+    t0 = time.perf_counter()
+    _, conv, its, _ = O.newton_be(o3, c3["dt"], U3, rtol=1e-8, maxit=30, solver=1, lin_rtol=1e-6)
+    e3 = time.perf_counter() - t0
+    legs["implicit_ch3d"] = {"sample": "one 64^3 backward-Euler step (Newton + block-Jacobi GMRES, rtol 1e-8)",
+                             "seconds": e3, "newton_its": its, "converged": bool(conv),
+                             "extrapolated_s_per_128cubed_step": 8 * e3,
+                             "extrapolated_s_200_steps_128cubed": 8 * e3 * 200}
+    # calibration batch: 4 of the 64 samples, 100 of the 2000 steps, FP64
+    sizes, theta, _, fields = I.batch_samples(count=64, seed=0)
+    t0 = time.perf_counter()
+    nodes4 = 0
+    for i in range(4):
+        nn_ = int(sizes[i])
+        oi = O.Problem(n=(nn_, nn_), model=O.AC, fe=O.F_SYM, W=float(theta[i][2]), kappa=float(theta[i][1]),
+                       mob=float(theta[i][0]))
+        O.explicit(oi, np.asarray(fields[i], dtype=np.float64).ravel(), 0.05, 100)
+        nodes4 += nn_ * nn_
+    e4 = time.perf_counter() - t0
+    nodes64 = int(sum(int(v) ** 2 for v in sizes))
+    fwd = e4 * (nodes64 / nodes4) * (2000 / 100)
+    legs["calibration_batch"] = {"sample": "4 of 64 samples, 100 of 2000 steps", "seconds": e4,
+                                 "extrapolated_forward_s": fwd, "extrapolated_central_fd_s": 6 * fwd}
+    # the 20 plain steps one surrogate jump replaces, 512^2 Cahn-Hilliard
+    o5 = O.Problem(n=(512, 512), model=O.CH, fe=O.F_01, W=1.0, kappa=1.0, mob=1.0)
+    U5 = I.initial_state(dict(I.CH2048, n=(512, 512)), seed=0, dtype=np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    O.explicit(o5, U5, 0.01, 20)
+    e5 = time.perf_counter() - t0
+    legs["surrogate_plain_20_steps_512"] = {"sample": "20 explicit steps, one 512^2 sample", "seconds": e5}
     return {"value": n * n * steps / el, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} explicit split steps of the {n}x{n} workload, single-threaded "
-                      f"FP64 element loop ({el:.1f} s)"}
+                      f"FP64 element loop ({el:.1f} s)",
+            "all_cores": {"value": n * n * steps / el_mt, "unit": "DOF-steps/s", "cores": threads,
+                          "kind": "oracle (OpenMP timing build, 2^d element colours)",
+                          "sample": f"the same {steps} steps ({el_mt:.1f} s)"},
+            "host": _host(), "legs": legs}
+
+
+def _settle(p, U, dt, ws, ms):
+    """Run the step untimed until `ms` milliseconds of device work have passed."""
+    import torch
+
+    from paper_2601_06079_amd import solver as S
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        S.step_explicit(p, U, dt, 100, ws)
+        torch.cuda.synchronize()
 
 
 def _events():
@@ -218,6 +316,29 @@ def single_step_hbm(n, steps, stream):
     torch.cuda.empty_cache()
     return {"n": n, "kernel_ms": kern_ms, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "field_bytes": 4 * n * n}
+
+
+def copy_ceiling(mib, stream, reps=20):
+    """The library's 16-byte stream copy of `mib` MiB: read + write bytes over time."""
+    import ctypes as ct
+
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    L = A.lib()
+    L.pf_stream_copy.restype = ct.c_int
+    L.pf_stream_copy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    nb = mib * 2 ** 20
+    x = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    args = (A.ctx(), ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr()), nb, ct.c_void_p(stream.cuda_stream))
+    for _ in range(3):
+        A.check(L.pf_stream_copy(*args))
+    ms = _time_ms(lambda: [L.pf_stream_copy(*args) for _ in range(reps)], stream) / reps
+    assert torch.equal(x, y)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"mib": mib, "ms": ms, "gbs": 2 * nb / (ms * 1e-3) / 1e9, "kernel": "k_stream_copy (16-byte loads/stores)"}
 
 
 def ac128_record(stream, steps=1000):
@@ -728,16 +849,25 @@ def main():
     dt = cfg["dt"]
     stream = torch.cuda.current_stream()
 
+    if args.fuse:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, args.fuse)
+    _settle(p, U, dt, ws, args.settle_ms)
     S.step_explicit(p, U, dt, args.warmup, ws)
     torch.cuda.synchronize()
 
-    # timed region: K steps in one call (the library enqueues the fused launches)
+    # timed region: K steps in one call (the library enqueues the fused launches);
+    # the call's arguments are marshalled beforehand
+    L = A.lib()
+    call = (A.ctx(), ct.byref(p.c()), dt)
+    uptr, wptr = ct.c_void_p(U.data_ptr()), ct.c_void_p(ws.data_ptr())
+    sptr = ct.c_void_p(stream.cuda_stream)
     e0, e1 = _events()
     torch.cuda.synchronize()
     e0.record(stream)
-    S.step_explicit(p, U, dt, args.steps, ws)
+    rc = L.pf_step_explicit(*call, args.steps, uptr, wptr, sptr)
     e1.record(stream)
     torch.cuda.synchronize()
+    A.check(rc)
     ms_total = e0.elapsed_time(e1)
     ms_per_step = ms_total / args.steps
     value = N * args.steps / (ms_total * 1e-3)
@@ -746,10 +876,10 @@ def main():
     # the K steps ran as back-to-back launches of the fused kernel (ks steps each)
     # plus one chemical-potential epilogue, measured separately and subtracted.
     ks_, ty_, dp_ = ct.c_int(0), ct.c_int(0), ct.c_int(0)
-    A.check(A.lib().pf_launch_shape(ct.byref(p.c()), ct.byref(ks_), ct.byref(ty_), ct.byref(dp_)))
+    A.check(A.lib().pf_launch_shape(A.ctx(), ct.byref(p.c()), ct.byref(ks_), ct.byref(ty_), ct.byref(dp_)))
     ks = ks_.value
     import numpy as np
-    epi = float(np.median([_time_ms(lambda: S.step_explicit(p, U, dt, 0, ws), stream)
+    epi = float(np.median([_time_ms(lambda: L.pf_step_explicit(*call, 0, uptr, wptr, sptr), stream)
                            for _ in range(11)]))
     launches = args.steps // ks + args.steps % ks
     kern_ms = max(ms_total - epi, 1e-6) / launches
@@ -797,12 +927,17 @@ def main():
         "config": {"workload": f"2D Cahn-Hilliard spinodal, {n}x{n} periodic, explicit split step, "
                                "dt=0.01, W=1, kappa=2, M=1", "dof": N, "parallelism": "single GPU"},
         "roofline": roof,
+        "settle_ms": args.settle_ms,
     }
+    if args.fuse:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
     del U, ws
     torch.cuda.empty_cache()
     if not args.no_extras:
         out["hbm"] = {"single_step_launch": single_step_hbm(n, 1000, stream),
-                      "single_step_launch_16384": single_step_hbm(16384, 40, stream)}
+                      "single_step_launch_16384": single_step_hbm(16384, 40, stream),
+                      "copy_ceiling_1gib": copy_ceiling(1024, stream),
+                      "copy_ceiling_32mib": copy_ceiling(32, stream)}
         out["ac128_fp64"] = ac128_record(stream)
         out["adjoint"] = adjoint_record(stream)
         out["surrogate"] = surrogate_record(stream)

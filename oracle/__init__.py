@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")  # timing build (benchmark CPU baseline only)
 _SRC = [os.path.join(_HERE, "pf_oracle.c"), os.path.join(_HERE, "conv_oracle.c"),
         os.path.join(_HERE, "coupled_oracle.c"), os.path.join(_HERE, "elastic_oracle.c"),
         os.path.join(_HERE, "grain_oracle.c")]
@@ -30,14 +31,17 @@ F_SYM, F_01 = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (no fast-math, no FMA contraction), and the
+    timing build of its explicit step (OpenMP over element colours, -DORC_OMP) that
+    only the benchmark's CPU baseline loads."""
     if not force and os.path.exists(_SO):
         return _SO
     srcs = [s for s in _SRC if os.path.exists(s)]
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared",
-           "-fPIC", "-o", _SO + ".tmp"] + srcs + ["-lm"]
-    subprocess.run(cmd, check=True)
+    base = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-fPIC"]
+    subprocess.run(base + ["-o", _SO + ".tmp"] + srcs + ["-lm"], check=True)
     os.replace(_SO + ".tmp", _SO)
+    subprocess.run(base + ["-fopenmp", "-DORC_OMP", "-o", _SO_OMP + ".tmp", _SRC[0], "-lm"], check=True)
+    os.replace(_SO_OMP + ".tmp", _SO_OMP)
     return _SO
 
 
@@ -45,10 +49,11 @@ class _Problem(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("bc", ct.c_int32), ("model", ct.c_int32),
                 ("fe", ct.c_int32), ("n", ct.c_int64 * 3), ("h", ct.c_double),
                 ("W", ct.c_double), ("kappa", ct.c_double), ("mob", ct.c_double),
-                ("mass", ct.c_int32), ("pad", ct.c_int32)]
+                ("mass", ct.c_int32), ("quad", ct.c_int32)]
 
 
 LUMPED, CONSISTENT = 0, 1
+GAUSS, LOBATTO = 0, 1  # 2-point Gauss-Legendre or Gauss-Lobatto (nodal) quadrature per axis
 
 
 @dataclass
@@ -63,6 +68,7 @@ class Problem:
     kappa: float = 1.0
     mob: float = 1.0
     mass: int = LUMPED  # CONSISTENT: Gauss-integrated mass in the implicit path
+    quad: int = GAUSS  # LOBATTO: nodal quadrature for every integral
 
     @property
     def dim(self) -> int:
@@ -79,7 +85,7 @@ class Problem:
     def _c(self) -> _Problem:
         n3 = list(self.n) + [1] * (3 - len(self.n))
         return _Problem(self.dim, self.bc, self.model, self.fe, (ct.c_int64 * 3)(*n3),
-                        self.h, self.W, self.kappa, self.mob, self.mass, 0)
+                        self.h, self.W, self.kappa, self.mob, self.mass, self.quad)
 
 
 _lib = None
@@ -168,6 +174,29 @@ def explicit(p: Problem, U, dt: float, nsteps: int) -> np.ndarray:
     if lib().orc_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U)) != 0:
         raise ValueError("explicit steps need the lumped mass")
     return U
+
+
+_lib_omp = None
+
+
+def explicit_threaded(p: Problem, U, dt: float, nsteps: int):
+    """`explicit` from the OpenMP timing build (element colours in parallel; the
+    same arithmetic summed in another order).  For the benchmark's CPU baseline
+    only, never for parity.  Returns (new array, threads used)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_SO_OMP):
+            build()
+        L = ct.CDLL(_SO_OMP)
+        L.orc_explicit.restype = ct.c_int
+        L.orc_explicit.argtypes = [ct.POINTER(_Problem), ct.c_double, ct.c_int64, ct.POINTER(ct.c_double)]
+        L.orc_threads.restype = ct.c_int
+        L.orc_threads.argtypes = []
+        _lib_omp = L
+    U = _arr(U, p.ndof).copy()
+    if _lib_omp.orc_explicit(ct.byref(p._c()), dt, int(nsteps), _d(U)) != 0:
+        raise ValueError("explicit steps need the lumped mass")
+    return U, int(_lib_omp.orc_threads())
 
 
 def be_residual(p: Problem, dt: float, Uold, U) -> np.ndarray:

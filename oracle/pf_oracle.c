@@ -19,7 +19,9 @@
  * Discretisation (the paper fixes "standard Lagrange" elements on a mesh; the
  * readings below are the ones this project adopts):
  *   - Q1 (bi/tri-linear) elements on a uniform grid of spacing h,
- *   - 2-point Gauss-Legendre quadrature per axis for every integral,
+ *   - 2-point Gauss-Legendre quadrature per axis for every integral, or (quad = 1)
+ *     the 2-point Gauss-Lobatto rule per axis, whose points are the element's
+ *     nodes (nodal quadrature: every integral, the energy and the mass included),
  *   - row-sum lumped mass everywhere M appears, or (mass = 1, implicit path only)
  *     the consistent mass M_ab = sum_e sum_q detJ phi_a(q) phi_b(q) in the time
  *     term and the Cahn-Hilliard mu-row (every term Gauss-integrated),
@@ -54,7 +56,7 @@ typedef struct {
     double kappa;  /* gradient-energy coefficient */
     double mob;    /* mobility: L (Allen-Cahn) or M (Cahn-Hilliard) */
     int32_t mass;  /* 0: lumped mass; 1: consistent mass (implicit path only) */
-    int32_t pad;
+    int32_t quad;  /* 0: 2-point Gauss-Legendre per axis; 1: 2-point Gauss-Lobatto */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -67,9 +69,13 @@ typedef struct {
     double grad[8][8][3]; /* grad[q][a][k]: d phi_a / d x_k at q (physical) */
 } orc_ref;
 
-static void ref_build(orc_ref* R, int d, double h)
+/* Quadrature points xi_k = +-g per axis, weight 1 each: g = 1/sqrt(3) for
+ * Gauss-Legendre, g = 1 for Gauss-Lobatto (the points are the nodes). */
+static void ref_build(orc_ref* R, const orc_problem* pr)
 {
-    const double g = 1.0 / sqrt(3.0);
+    const int d = pr->dim;
+    const double h = pr->h;
+    const double g = pr->quad ? 1.0 : 1.0 / sqrt(3.0);
     R->d = d;
     R->nv = 1 << d;
     R->detJ = pow(0.5 * h, d);
@@ -150,31 +156,70 @@ static double fe_d2f(int fe, double W, double c)
 /* element-loop assemblies                                                    */
 /* ------------------------------------------------------------------------ */
 
+/* element E's share of assemble_first (below), added into out */
+static void assemble_first_elem(const orc_problem* p, const orc_ref* R, double W, const double* u,
+                                double cf, double ck, const int64_t E[3], double* out)
+{
+    int64_t idx[8];
+    elem_nodes(p, E, R->nv, idx);
+    for (int q = 0; q < R->nv; ++q) {
+        double uq = 0.0, gq[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < R->nv; ++a) {
+            uq += R->phi[q][a] * u[idx[a]];
+            for (int k = 0; k < R->d; ++k) gq[k] += R->grad[q][a][k] * u[idx[a]];
+        }
+        double fq = (cf != 0.0) ? cf * fe_df(p->fe, W, uq) : 0.0;
+        for (int a = 0; a < R->nv; ++a) {
+            double gg = 0.0;
+            for (int k = 0; k < R->d; ++k) gg += gq[k] * R->grad[q][a][k];
+            out[idx[a]] += R->detJ * (fq * R->phi[q][a] + ck * gg);
+        }
+    }
+}
+
+#ifdef ORC_OMP
+/* Timing build only (compiled with -fopenmp -DORC_OMP; the test-suite's oracle is the
+ * serial build).  Elements whose lower-corner indices have the same parity on every
+ * axis share no node when every periodic axis has an even node count (no-flux grids
+ * have no wrap), so the 2^d colours run one after another, each colour's elements in
+ * parallel.  Each node then sums its element shares in colour order, not element
+ * order: results differ from the serial build in the last bits only. */
+static int colourable(const orc_problem* p)
+{
+    if (p->bc != ORC_PERIODIC) return 1;
+    for (int k = 0; k < p->dim; ++k)
+        if (p->n[k] % 2) return 0;
+    return 1;
+}
+#endif
+
 /* out_a += sum_e sum_q detJ * ( cf * f'(u_q) phi_a(q) + ck * grad u_q . grad phi_a(q) )
  * The first variation of  int cf*f(u) + ck/2 |grad u|^2  (Eqs. 5-6). */
 static void assemble_first(const orc_problem* p, double W, const double* u, double cf,
                            double ck, double* out)
 {
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
-    int64_t E[3], idx[8];
-    FOR_EACH_ELEMENT(p, E)
-    {
-        elem_nodes(p, E, R.nv, idx);
-        for (int q = 0; q < R.nv; ++q) {
-            double uq = 0.0, gq[3] = {0.0, 0.0, 0.0};
-            for (int a = 0; a < R.nv; ++a) {
-                uq += R.phi[q][a] * u[idx[a]];
-                for (int k = 0; k < R.d; ++k) gq[k] += R.grad[q][a][k] * u[idx[a]];
-            }
-            double fq = (cf != 0.0) ? cf * fe_df(p->fe, W, uq) : 0.0;
-            for (int a = 0; a < R.nv; ++a) {
-                double gg = 0.0;
-                for (int k = 0; k < R.d; ++k) gg += gq[k] * R.grad[q][a][k];
-                out[idx[a]] += R.detJ * (fq * R.phi[q][a] + ck * gg);
+    ref_build(&R, p);
+#ifdef ORC_OMP
+    if (colourable(p)) {
+        const int64_t ne[3] = {elems_on_axis(p, 0), elems_on_axis(p, 1), elems_on_axis(p, 2)};
+        for (int col = 0; col < (1 << p->dim); ++col) {
+            const int64_t o[3] = {col & 1, (col >> 1) & 1, (col >> 2) & 1};
+            const int64_t m[3] = {(ne[0] - o[0] + 1) / 2, (ne[1] - o[1] + 1) / 2,
+                                  p->dim == 3 ? (ne[2] - o[2] + 1) / 2 : 1};
+#pragma omp parallel for schedule(static)
+            for (int64_t t = 0; t < m[0] * m[1] * m[2]; ++t) {
+                const int64_t E[3] = {o[0] + 2 * (t % m[0]), o[1] + 2 * ((t / m[0]) % m[1]),
+                                      p->dim == 3 ? o[2] + 2 * (t / (m[0] * m[1])) : 0};
+                assemble_first_elem(p, &R, W, u, cf, ck, E, out);
             }
         }
+        return;
     }
+#endif
+    int64_t E[3];
+    FOR_EACH_ELEMENT(p, E)
+    assemble_first_elem(p, &R, W, u, cf, ck, E, out);
 }
 
 /* out_a += sum_e sum_q detJ * ( cf * f''(u_q) v_q phi_a(q) + ck * grad v_q . grad phi_a(q) )
@@ -184,7 +229,7 @@ static void assemble_second(const orc_problem* p, double W, const double* u, con
                             double cf, double ck, double* out)
 {
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
+    ref_build(&R, p);
     int64_t E[3], idx[8];
     FOR_EACH_ELEMENT(p, E)
     {
@@ -211,7 +256,7 @@ static void assemble_second_diag(const orc_problem* p, const double* u, double c
                                  double* out)
 {
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
+    ref_build(&R, p);
     int64_t E[3], idx[8];
     FOR_EACH_ELEMENT(p, E)
     {
@@ -233,6 +278,14 @@ static void assemble_second_diag(const orc_problem* p, const double* u, double c
 /* exported: mass, energy, residual                                           */
 /* ------------------------------------------------------------------------ */
 
+/* threads the timing build's parallel loops use (1 in the serial build) */
+#ifdef ORC_OMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif
+
 int64_t orc_ndof(const orc_problem* p)
 {
     return (p->model == ORC_CH ? 2 : 1) * orc_nnodes(p);
@@ -242,7 +295,7 @@ int64_t orc_ndof(const orc_problem* p)
 int orc_lumped_mass(const orc_problem* p, double* m)
 {
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
+    ref_build(&R, p);
     int64_t N = orc_nnodes(p), E[3], idx[8];
     memset(m, 0, (size_t)N * sizeof(double));
     FOR_EACH_ELEMENT(p, E)
@@ -268,7 +321,7 @@ static void apply_mass(const orc_problem* p, const double* v, double* out)
         return;
     }
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
+    ref_build(&R, p);
     int64_t E[3], idx[8];
     memset(out, 0, (size_t)N * sizeof(double));
     FOR_EACH_ELEMENT(p, E)
@@ -286,7 +339,7 @@ static void apply_mass(const orc_problem* p, const double* v, double* out)
 double orc_energy(const orc_problem* p, const double* U)
 {
     orc_ref R;
-    ref_build(&R, p->dim, p->h);
+    ref_build(&R, p);
     int64_t E[3], idx[8];
     double sum = 0.0;
     FOR_EACH_ELEMENT(p, E)
@@ -366,6 +419,7 @@ int orc_explicit(const orc_problem* p, double dt, int64_t nsteps, double* U)
         for (int64_t s = 0; s < nsteps; ++s) {
             memset(t, 0, (size_t)N * sizeof(double));
             assemble_first(p, p->W, U, p->mob, p->mob * p->kappa, t);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) U[i] -= dt * t[i] / m[i];
         }
     } else {
@@ -374,10 +428,12 @@ int orc_explicit(const orc_problem* p, double dt, int64_t nsteps, double* U)
         for (int64_t s = 0; s <= nsteps; ++s) {
             memset(t, 0, (size_t)N * sizeof(double));
             assemble_first(p, p->W, c, 1.0, p->kappa, t);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) mu[i] = t[i] / m[i];
             if (s == nsteps) break;
             memset(t, 0, (size_t)N * sizeof(double));
             assemble_first(p, p->W, mu, 0.0, p->mob, t);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) c[i] -= dt * t[i] / m[i];
         }
     }
