@@ -98,6 +98,17 @@ enum { PF_F32 = 0, PF_F64 = 1 };
  * PF_EUNSUPPORTED.  Energies and sum m c are the same for both (the row sums of
  * the consistent mass are the lumped mass). */
 enum { PF_MASS_LUMPED = 0, PF_MASS_CONSISTENT = 1 };
+/* Quadrature of every element integral (Sec. 2.2 leaves it open).
+ * PF_QUAD_GAUSS: 2-point Gauss-Legendre per axis (the default).
+ * PF_QUAD_LOBATTO: 2-point Gauss-Lobatto per axis, whose points are the element's
+ * nodes (nodal quadrature): the nonlinear term becomes m_a f'(c_a), the Q1
+ * stiffness the 5-point stencil 4 c_i - (axis neighbours) in 2-D and
+ * h (6 c_i - axis neighbours) in 3-D, the energy sum_a m_a f(c_a) + kappa/2 c.Kc,
+ * and the mass diagonal (PF_MASS_CONSISTENT then equals PF_MASS_LUMPED).
+ * Allen-Cahn and Cahn-Hilliard, 2-D and 3-D, periodic and no-flux: pf_residual,
+ * pf_step_explicit, pf_energy, pf_jvp and pf_newton_step; pf_vjp, the batches and
+ * the coupled and grain models return PF_EUNSUPPORTED. */
+enum { PF_QUAD_GAUSS = 0, PF_QUAD_LOBATTO = 1 };
 
 /* Problem statement: grid, boundary condition, model, free energy and the
  * material parameters theta = (mobility, kappa, W) of Eqs. 1, 5-6, 9-10.
@@ -118,7 +129,7 @@ typedef struct pf_problem {
     double mobility;  /* L (Allen-Cahn) or M (Cahn-Hilliard); M_c (coupled) */
     double mobility_eta; /* coupled model: M_eta (ignored by the other models) */
     int32_t nfields;  /* PF_GRAIN: number of order parameters (ignored by the other models) */
-    int32_t reserved2; /* must be 0 */
+    int32_t quad;     /* PF_QUAD_GAUSS (0) or PF_QUAD_LOBATTO (see below) */
     double gamma;     /* PF_GRAIN: pair coupling of the multi-well energy */
 } pf_problem;
 

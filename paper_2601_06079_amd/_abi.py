@@ -23,6 +23,7 @@ ALLEN_CAHN, CAHN_HILLIARD, COUPLED, GRAIN = 0, 1, 2, 3
 F_SYM, F_01 = 0, 1
 F32, F64 = 0, 1
 MASS_LUMPED, MASS_CONSISTENT = 0, 1
+QUAD_GAUSS, QUAD_LOBATTO = 0, 1
 OP_RESIDUAL, OP_STEP_EXPLICIT, OP_ENERGY, OP_NEWTON, OP_VJP, OP_JVP = range(6)
 TUNE_STREAM2D_ROWS, TUNE_STREAM2D_DEPTH, TUNE_STREAM2D_FUSE, TUNE_JVP3D_PLANES = 0, 1, 2, 3
 TUNE_STREAM2D_SEAM = 6
@@ -36,7 +37,7 @@ class pf_problem(ct.Structure):
                 ("fe", ct.c_int32), ("dtype", ct.c_int32), ("mass", ct.c_int32),
                 ("n", ct.c_int64 * 3), ("h", ct.c_double), ("W", ct.c_double),
                 ("kappa", ct.c_double), ("mobility", ct.c_double), ("mobility_eta", ct.c_double),
-                ("nfields", ct.c_int32), ("reserved2", ct.c_int32), ("gamma", ct.c_double)]
+                ("nfields", ct.c_int32), ("quad", ct.c_int32), ("gamma", ct.c_double)]
 
 
 KRYLOV_GMRES, KRYLOV_CG = 0, 1

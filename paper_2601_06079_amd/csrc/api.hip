@@ -60,7 +60,10 @@ int validate(const pf_problem* p)
     if (p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD && p->model != PF_COUPLED &&
         p->model != PF_GRAIN)
         return fail(PF_EINVAL, "unknown model %d", p->model);
-    if (p->reserved2 != 0) return fail(PF_EINVAL, "reserved2 must be 0");
+    if (p->quad != PF_QUAD_GAUSS && p->quad != PF_QUAD_LOBATTO)
+        return fail(PF_EINVAL, "unknown quadrature %d", p->quad);
+    if (p->quad == PF_QUAD_LOBATTO && p->model != PF_ALLEN_CAHN && p->model != PF_CAHN_HILLIARD)
+        return fail(PF_EUNSUPPORTED, "Gauss-Lobatto quadrature: Allen-Cahn and Cahn-Hilliard only");
     if (p->model == PF_GRAIN) {
         const int pmax = p->dtype == PF_F64 ? 12 : 32;  // LDS of the tile kernel <= 64 KB
         if (p->nfields < 1 || p->nfields > pmax)
@@ -113,7 +116,9 @@ pfk::Geom geom_of(const pf_problem* p)
     }
     g.h = p->h;
     g.bc = p->bc == PF_NOFLUX ? 1 : 0;
-    g.cm = p->mass == PF_MASS_CONSISTENT ? 1 : 0;
+    g.quad = p->quad == PF_QUAD_LOBATTO ? 1 : 0;
+    // nodal quadrature makes the Gauss-integrated mass the lumped one
+    g.cm = p->mass == PF_MASS_CONSISTENT && !g.quad ? 1 : 0;
     return g;
 }
 

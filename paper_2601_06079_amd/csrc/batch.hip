@@ -41,6 +41,7 @@ int validate_base(const pf_problem* p)
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_EINVAL, "unknown dtype %d", p->dtype);
     if (p->bc != PF_PERIODIC) return fail(PF_EUNSUPPORTED, "batches support periodic grids only");
     if (p->mass != PF_MASS_LUMPED) return fail(PF_EUNSUPPORTED, "batches use the lumped mass only");
+    if (p->quad != PF_QUAD_GAUSS) return fail(PF_EUNSUPPORTED, "batches use Gauss quadrature only");
     return PF_OK;
 }
 

@@ -2,6 +2,8 @@
 // residual (Eq. 11) and backward-Euler residual (Eq. 14), Jacobian products,
 // preconditioner, chemical potential, node-centric explicit updates, energy.
 // The shared device helpers and the quadrature scheme are in node_common.hpp.
+// g.quad selects Gauss-Lobatto (nodal) quadrature: N(u)_a = m f'(u_a), the 5/7-point
+// stiffness stencil and the lumped mass (the branch is uniform over the grid).
 #include <cmath>
 
 #include "node_common.hpp"
@@ -25,8 +27,8 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const
     T u[NB<D>::K];
     gather<T, D>(U, g, i, j, k, u);
     const T h = (T)g.h;
-    const T Nn = detJ * quad_sum<T, D, false>(u, u, F);
-    const T Ku = stiff<T, D>(u, h);
+    const T Nn = g.quad ? m * F(u[NB<D>::K / 2], (T)0) : detJ * quad_sum<T, D, false>(u, u, F);
+    const T Ku = stiff_q<T, D>(g, u, h);
     T tt = (T)0;
     if (Uold) {
         if (g.cm) {
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const
     } else {
         T w[NB<D>::K];
         gather<T, D>(U + g.N, g, i, j, k, w);
-        r[idx] = (mob * stiff<T, D>(w, h) + tt) * ib;
+        r[idx] = (mob * stiff_q<T, D>(g, w, h) + tt) * ib;
         const T mw = g.cm ? cmass<T, D>(w, h) : m * w[NB<D>::K / 2];
         r[g.N + idx] = (mw - (Nn + kappa * Ku)) * ib;
     }
@@ -64,8 +66,8 @@ __global__ __launch_bounds__(256) void k_prec(const T* __restrict__ U, T* __rest
     if (!node_of<D>(g, idx, i, j, k)) return;
     T u[NB<D>::K];
     gather<T, D>(U, g, i, j, k, u);
-    const double nd = (double)(detJ * quad_sum_sq<T, D>(u, F));
-    const double kd = (double)stiff_diag<T, D>((T)g.h);
+    const double nd = g.quad ? (double)(m * F(u[NB<D>::K / 2], (T)1)) : (double)(detJ * quad_sum_sq<T, D>(u, F));
+    const double kd = g.quad ? (double)stiff_lob_diag<T, D>((T)g.h) : (double)stiff_diag<T, D>((T)g.h);
     const double ib = 1.0 / bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
         pinv[idx] = (T)(1.0 / (ib * ((double)inv_dt * m + (double)mob * (nd + (double)kappa * kd))));
@@ -101,8 +103,8 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
     const T ib = (T)1 / (T)bfactor<D>(g, i, j, k);  // no-flux rows (1 on periodic grids)
     if constexpr (MODEL == 0) {
         gather<T, D>(V, g, i, j, k, v);
-        const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
-        const T Kv = stiff<T, D>(v, h);
+        const T Nv = g.quad ? m * F(u[NB<D>::K / 2], v[NB<D>::K / 2]) : detJ * quad_sum<T, D, true>(u, v, F);
+        const T Kv = stiff_q<T, D>(g, v, h);
         const T mv = g.cm ? cmass<T, D>(v, h) : m * v[NB<D>::K / 2];
         const T out = (inv_dt * mv + mob * (Nv + kappa * Kv)) * ib;
         Jv[idx] = ACC ? Jv[idx] + out : out;
@@ -113,14 +115,15 @@ __global__ __launch_bounds__(256) void k_jvp(const T* __restrict__ U, const T* _
         T oc, om;
         const T mv = g.cm ? cmass<T, D>(v, h) : m * v[NB<D>::K / 2];
         const T mw = g.cm ? cmass<T, D>(w, h) : m * w[NB<D>::K / 2];
+        const T uc = u[NB<D>::K / 2];
         if constexpr (TRANS == 0) {
-            const T Nv = detJ * quad_sum<T, D, true>(u, v, F);
-            oc = inv_dt * mv + mob * stiff<T, D>(w, h);
-            om = mw - (Nv + kappa * stiff<T, D>(v, h));
+            const T Nv = g.quad ? m * F(uc, v[NB<D>::K / 2]) : detJ * quad_sum<T, D, true>(u, v, F);
+            oc = inv_dt * mv + mob * stiff_q<T, D>(g, w, h);
+            om = mw - (Nv + kappa * stiff_q<T, D>(g, v, h));
         } else {
-            const T Nw = detJ * quad_sum<T, D, true>(u, w, F);
-            oc = inv_dt * mv - (Nw + kappa * stiff<T, D>(w, h));
-            om = mob * stiff<T, D>(v, h) + mw;
+            const T Nw = g.quad ? m * F(uc, w[NB<D>::K / 2]) : detJ * quad_sum<T, D, true>(u, w, F);
+            oc = inv_dt * mv - (Nw + kappa * stiff_q<T, D>(g, w, h));
+            om = mob * stiff_q<T, D>(g, v, h) + mw;
         }
         oc *= ib;
         om *= ib;
@@ -138,7 +141,9 @@ __global__ __launch_bounds__(256) void k_chem(const T* __restrict__ c, T* __rest
     if (!node_of<D>(g, idx, i, j, k)) return;
     T u[NB<D>::K];
     gather<T, D>(c, g, i, j, k, u);
-    mu[idx] = (detJ * quad_sum<T, D, false>(u, u, F) + kappa * stiff<T, D>(u, (T)g.h)) * inv_m;
+    const T h = (T)g.h, m = D == 2 ? h * h : h * h * h;  // interior nodal mass h^D
+    const T Nn = g.quad ? m * F(u[NB<D>::K / 2], (T)0) : detJ * quad_sum<T, D, false>(u, u, F);
+    mu[idx] = (Nn + kappa * stiff_q<T, D>(g, u, h)) * inv_m;
 }
 
 template <typename T, int D>
@@ -150,7 +155,7 @@ __global__ __launch_bounds__(256) void k_ch_update(const T* __restrict__ c, cons
     if (!node_of<D>(g, idx, i, j, k)) return;
     T w[NB<D>::K];
     gather<T, D>(mu, g, i, j, k, w);
-    cout[idx] = c[idx] - dtM_over_m * stiff<T, D>(w, (T)g.h);
+    cout[idx] = c[idx] - dtM_over_m * stiff_q<T, D>(g, w, (T)g.h);
 }
 
 template <typename T, int D>
@@ -162,7 +167,9 @@ __global__ __launch_bounds__(256) void k_ac_step(const T* __restrict__ eta, T* _
     if (!node_of<D>(g, idx, i, j, k)) return;
     T u[NB<D>::K];
     gather<T, D>(eta, g, i, j, k, u);
-    const T r = detJ * quad_sum<T, D, false>(u, u, F) + kappa * stiff<T, D>(u, (T)g.h);
+    const T h = (T)g.h, m = D == 2 ? h * h : h * h * h;  // interior nodal mass h^D
+    const T Nn = g.quad ? m * F(u[NB<D>::K / 2], (T)0) : detJ * quad_sum<T, D, false>(u, u, F);
+    const T r = Nn + kappa * stiff_q<T, D>(g, u, h);
     out[idx] = u[NB<D>::K / 2] - dtL_over_m * r;
 }
 
@@ -190,7 +197,10 @@ __global__ __launch_bounds__(EBLK) void k_energy(const T* __restrict__ c, double
     int i, j, k;
     if (node_of<D>(g, idx, i, j, k)) {
         const double h = g.h;
-        const double B[2][2] = {{GP, GM}, {GM, GP}};
+        // 1-D shape functions at the quadrature points: Gauss (GP, GM), or
+        // Gauss-Lobatto (the points are the nodes: the identity)
+        const double bp = g.quad ? 1.0 : GP, bm = g.quad ? 0.0 : GM;
+        const double B[2][2] = {{bp, bm}, {bm, bp}};
         const int i1 = wrap(i + 1, g.n[0]), j1 = wrap(j + 1, g.n[1]);
         if constexpr (D == 2) {
             double u[2][2];  // [ay][ax]
@@ -344,7 +354,7 @@ template <typename T>
 void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
                 double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, int trans, int acc)
 {
-    if (g.dim == 3 && !acc && !g.cm) {
+    if (g.dim == 3 && !acc && !g.cm && !g.quad) {
         launch_jvp3d<T>(g, model, f, kappa, mob, inv_dt, U, v, Jv, s, trans);
         return;
     }

@@ -19,6 +19,8 @@
 //   N(x, r-1) = sum_qx B[qx][1] Hsum(x-1)[qx] + B[qx][0] Hsum(x)[qx]   (x-scatter)
 // with B = [[GP, GM], [GM, GP]].  The gradient term is the closed Q1 stencil
 // K c = (9 c - sum_{3x3} c) / 3 (2-D, h-independent).
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "stream2d.hpp"
@@ -41,7 +43,7 @@ struct Coef {
 //   MODEL 1: Cahn-Hilliard mu  = [|J|/m] N'(c) + [kappa/(3m)] (9c - box c)
 //                          out = c - [dt M/(3m)] (9 mu - box mu)
 // N' is the quadrature sum with the scaled cubic (a1, a2, a3); box = 3x3 sum.
-template <typename T, int MODEL>
+template <typename T, int MODEL, bool LOB = false>
 struct Stage {
     T c_m1 = 0, c_m2 = 0;        // c at rows r-1, r-2
     T s3_m1 = 0, s3_m2 = 0;      // 3-point x-sums of c at rows r-1, r-2
@@ -95,6 +97,35 @@ struct Stage {
     }
 };
 
+// The same pipeline with Gauss-Lobatto (nodal) quadrature: the nonlinear term is
+// m f'(c) at the node and the stiffness the 5-point stencil (4 c - axis neighbours,
+// h-free in 2-D), so no interpolation or scatter remains:
+//   MODEL 0: out = c - [dt L] f'(c) - [dt L kappa/m] (4c - nbrs c)
+//   MODEL 1: mu  = f'(c) + [kappa/m] (4c - nbrs c);  out = c - [dt M/m] (4 mu - nbrs mu)
+template <typename T, int MODEL>
+struct Stage<T, MODEL, true> {
+    T c_m1 = 0, c_m2 = 0;    // c at rows r-1, r-2
+    T mu_m1 = 0, mu_m2 = 0;  // CH: mu at rows r-2, r-3
+
+    __device__ __forceinline__ T push(T cc, const Coef<T>& k)
+    {
+        const T lap = fmaT((T)4, c_m1, -((from_left(c_m1) + from_right(c_m1)) + (c_m2 + cc)));  // row r-1
+        T v;
+        if constexpr (MODEL == 0) {
+            v = c_m1 - cubic(c_m1, k.a1, k.a2, k.a3) - k.beta * lap;
+        } else {
+            const T mu = fmaT(k.beta, lap, cubic(c_m1, k.a1, k.a2, k.a3));  // mu at row r-1
+            const T lapmu = fmaT((T)4, mu_m1, -((from_left(mu_m1) + from_right(mu_m1)) + (mu_m2 + mu)));
+            v = c_m2 - k.gamma * lapmu;  // row r-2
+            mu_m2 = mu_m1;
+            mu_m1 = mu;
+        }
+        c_m2 = c_m1;
+        c_m1 = cc;
+        return v;
+    }
+};
+
 // KS explicit steps of one (strip, chunk) work item (temporal blocking):
 // stage s consumes the rows stage s-1 produces, so a row is read from memory
 // once and written once per KS steps.  Each stage performs exactly the
@@ -104,7 +135,7 @@ struct Stage {
 // MIRROR: no-flux grid, read through the even extension about the end rows and
 // columns (reflect); the lumped update r/m of a boundary node is then exactly the
 // interior formula (see reflect in device.hpp), for every fused stage.
-template <typename T, int MODEL, int PF, int KS, bool MID = false, bool MIRROR = false>
+template <typename T, int MODEL, int PF, int KS, bool MID = false, bool MIRROR = false, bool LOB = false>
 __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restrict__ out, int nx,
                                             int ny, int strip, int y0, int y1, unsigned bytes,
                                             const Coef<T>& k, T* __restrict__ mid = nullptr)
@@ -130,7 +161,7 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     const auto rout = make_rsrc(out, bytes);
     const auto rmid = make_rsrc(MID ? mid : out, bytes);
 
-    Stage<T, MODEL> st[KS];
+    Stage<T, MODEL, LOB> st[KS];
 
     // prefetch ring: slot (t mod PF) holds row y0 - HK + t.  Every row runs the
     // pipeline unconditionally (rows past the chunk compute values nobody
@@ -168,33 +199,41 @@ __device__ __forceinline__ void stream_item(const T* __restrict__ in, T* __restr
     } else {
         while (rlast >= ny) rlast -= ny;
     }
-    for (int t0 = 0; t0 < iters; t0 += PF) {
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int t = t0 + u;
-            T v = ring[u];
-            ring[u] = bload<T>(rin, vx, rl * rowb);
-            if (t + PF + 1 < iters) {
-                advance();
-            } else {
-                rl = rlast;
-            }
-            v = st[0].push(v, k);
-            if constexpr (MID) {
-                // trajectory mode: the first stage's row y0 - HK - H + t is the state
-                // after one step (bitwise a single-step launch's)
-                if (t >= HK + H && t < HK + H + (y1 - y0) && out_lane)
-                    bstore(v, rmid, vx, (y0 - HK - H + t) * rowb);
-            }
-#pragma unroll
-            for (int sidx = 1; sidx < KS; ++sidx) v = st[sidx].push(v, k);
-            // the last stage just finished row y0 - 2 HK + t
-            if (t >= 2 * HK && t < iters && out_lane) bstore(v, rout, vx, (y0 - 2 * HK + t) * rowb);
+    // stage s >= 1 receives only pipeline fill (garbage) before t = 2 H s: it skips
+    // those pushes (its window then starts from zeros, which the 2H pushes before
+    // its first valid output overwrite), which the first FIRST iterations handle
+    // with compile-time loop indices; the steady loop pushes every stage
+    constexpr int FIRST = (2 * H * (KS - 1) + PF - 1) / PF * PF;  // <= 2 HK <= iters
+    auto row = [&](int t, int u, bool head) {
+        T v = ring[u];
+        ring[u] = bload<T>(rin, vx, rl * rowb);
+        if (t + PF + 1 < iters) {
+            advance();
+        } else {
+            rl = rlast;
         }
+        v = st[0].push(v, k);
+        if constexpr (MID) {
+            // trajectory mode: the first stage's row y0 - HK - H + t is the state
+            // after one step (bitwise a single-step launch's)
+            if (t >= HK + H && t < HK + H + (y1 - y0) && out_lane)
+                bstore(v, rmid, vx, (y0 - HK - H + t) * rowb);
+        }
+#pragma unroll
+        for (int sidx = 1; sidx < KS; ++sidx)
+            if (!head || t >= 2 * H * sidx) v = st[sidx].push(v, k);
+        // the last stage just finished row y0 - 2 HK + t
+        if (t >= 2 * HK && t < iters && out_lane) bstore(v, rout, vx, (y0 - 2 * HK + t) * rowb);
+    };
+#pragma unroll
+    for (int t = 0; t < FIRST; ++t) row(t, t % PF, true);
+    for (int t0 = FIRST; t0 < iters; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) row(t0 + u, u, false);
     }
 }
 
-template <typename T, int MODEL, int PF, int KS, bool MIRROR = false>
+template <typename T, int MODEL, int PF, int KS, bool MIRROR = false, bool LOB = false>
 __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T* __restrict__ out,
                                                     int nx, int ny, int nstrips, int nwaves, int nchunks,
                                                     unsigned bytes, Coef<T> k)
@@ -205,7 +244,7 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
     const int chunk = wave / nstrips;
     const int y0 = (int)((long long)chunk * ny / nchunks);
     const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
-    stream_item<T, MODEL, PF, KS, false, MIRROR>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
+    stream_item<T, MODEL, PF, KS, false, MIRROR, LOB>(in, out, nx, ny, wave % nstrips, y0, y1, bytes, k);
 }
 
 // Fused steps with the chunk seams shared through LDS (periodic grids).
@@ -230,7 +269,7 @@ __global__ __launch_bounds__(256) void k_explicit2d(const T* __restrict__ in, T*
 // barrier.
 constexpr int SEAM_NW = 4;  // waves (chunks) per workgroup
 
-template <typename T, int MODEL, int KS>
+template <typename T, int MODEL, int KS, bool LOB>
 __global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ in, T* __restrict__ out, int nx,
                                                          int ny, int nchunks, int nblocks, unsigned bytes,
                                                          Coef<T> k)
@@ -252,8 +291,14 @@ __global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ i
     const int wave = blk * SEAM_NW + wv;
     const int strip = wave / nchunks, chunk = wave % nchunks;
     const bool top = wv == SEAM_NW - 1;  // no neighbour above in this workgroup
-    const int y0 = (int)((long long)chunk * ny / nchunks);
-    const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
+    // the workgroups of a strip take balanced row ranges; inside one, the top chunk is
+    // H (KS - 1) rows shorter, as its wave pushes H KS (KS - 1) more rows, so that
+    // every wave of the workgroup does the same work
+    const int nwg = nchunks / SEAM_NW, grp = chunk / SEAM_NW;
+    const int Y0 = (int)((long long)grp * ny / nwg), Y1 = (int)((long long)(grp + 1) * ny / nwg);
+    const int span = Y1 - Y0 + H * (KS - 1);
+    const int y0 = Y0 + wv * span / SEAM_NW;
+    const int y1 = top ? Y1 : Y0 + (wv + 1) * span / SEAM_NW;
     const int ty = y1 - y0;
     const int iters = ty + FILL;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -266,7 +311,7 @@ __global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ i
     const auto rin = make_rsrc(in, bytes);
     const auto rout = make_rsrc(out, bytes);
 
-    Stage<T, MODEL> st[KS];
+    Stage<T, MODEL, LOB> st[KS];
     T ring[PF];
     // input rows y0 - H .. (the top wave reads 2 H (KS - 1) rows further)
     int rl = y0 - H;
@@ -281,7 +326,7 @@ __global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ i
         if (++rl == ny) rl = 0;
     }
     const int need = (top ? iters : ty + 2 * H);  // input rows this wave reads
-    auto body = [&](int t, int u) {
+    auto fetch = [&](int t, int u) {
         T v = ring[u];
         ring[u] = bload<T>(rin, vx, rl * rowb);
         if (t + PF + 1 < need) {
@@ -289,37 +334,59 @@ __global__ __launch_bounds__(256) void k_explicit2d_seam(const T* __restrict__ i
         } else {
             rl = rlast;
         }
-        // stage s pushes from t = 2 H s; a wave below the top of its workgroup stops
-        // stage s (all but the last) at row y1 + s H (t = own) and hands the next
-        // stage the 2H rows the wave above left in LDS instead
-        T o = v;
+        return v;
+    };
+    auto store = [&](T o) {
+        if (out_lane) bstore(o, rout, vx, ro * rowb);
+        if (++ro == ny) ro = 0;
+    };
+    // Three phases, each with its stage set known at compile time:
+    //  warm-up (t < FIRST): stage s pushes from t = 2 H s; every stage but the last
+    //    leaves its first 2H valid rows (t in [2H (s+1), 2H (s+2))) in LDS;
+    //  steady (FIRST <= t < tend): every stage pushes its own rows, one output row;
+    //    tend = ty + 2H below the top of the workgroup, iters for the top wave;
+    //  seam tail (below the top only): segment j takes the 2H rows stage j of the
+    //    wave above left in LDS and pushes them through stages j+1 .. KS-1.
+    // The launcher guarantees ty + 2H >= FIRST + PF, so no stage of the warm-up
+    // reaches its own end and no seam row is read before the barrier.
+    auto warm = [&](int t) {  // t is a constant once the warm-up loop is unrolled
+        T o = fetch(t, t % PF);
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const int lo = 2 * H * s, own = ty + 2 * H * (s + 1);
-            if (t >= lo) {
-                if (top || s == KS - 1 || t < own)
-                    o = st[s].push(o, k);
-                else if (t < own + 2 * H)
-                    o = seam[wv + 1][s][t - own][lane];
-                if (s < KS - 1 && t >= lo + 2 * H && t < lo + 4 * H) seam[wv][s][t - lo - 2 * H][lane] = o;
-            }
+            if (t >= 2 * H * s) o = st[s].push(o, k);
+            if (s < KS - 1 && t >= 2 * H * (s + 1) && t < 2 * H * (s + 2))
+                seam[wv][s][t - 2 * H * (s + 1)][lane] = o;
         }
-        if (t >= FILL) {
-            if (out_lane) bstore(o, rout, vx, ro * rowb);
-            if (++ro == ny) ro = 0;
-        }
+        if (t >= FILL) store(o);
     };
-    // the first FIRST rows write every seam row this wave owes the wave below (the
-    // launcher guarantees iters >= FIRST + PF and that no seam row is read before)
-    for (int t0 = 0; t0 < FIRST; t0 += PF) {
+    auto steady = [&](int t, int u) {
+        T o = fetch(t, u);
 #pragma unroll
-        for (int u = 0; u < PF; ++u) body(t0 + u, u);
-    }
+        for (int s = 0; s < KS; ++s) o = st[s].push(o, k);
+        store(o);
+    };
+#pragma unroll
+    for (int t = 0; t < FIRST; ++t) warm(t);
     __syncthreads();
-    for (int t0 = FIRST; t0 < iters; t0 += PF) {
+    const int tend = top ? iters : ty + 2 * H;
+    const int t2 = FIRST + (tend - FIRST) / PF * PF;
+    for (int t0 = FIRST; t0 < t2; t0 += PF) {
 #pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (t0 + u < iters) body(t0 + u, u);
+        for (int u = 0; u < PF; ++u) steady(t0 + u, u);
+    }
+#pragma unroll
+    for (int u = 0; u < PF - 1; ++u)
+        if (t2 + u < tend) steady(t2 + u, u);
+    if (top) return;
+#pragma unroll
+    for (int j = 0; j < KS - 1; ++j) {
+#pragma unroll
+        for (int r = 0; r < 2 * H; ++r) {
+            T o = seam[wv + 1][j][r][lane];
+#pragma unroll
+            for (int s = j + 1; s < KS; ++s) o = st[s].push(o, k);
+            store(o);
+        }
     }
 }
 
@@ -345,8 +412,15 @@ __global__ __launch_bounds__(256) void k_explicit2d_batched(const T* __restrict_
 
 template <typename T, int MODEL, int KS>
 void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-                  int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc)
+                  int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc, int quad)
 {
+    if (quad) {  // Gauss-Lobatto: one prefetch depth
+        if (bc)
+            k_explicit2d<T, MODEL, 4, KS, true, true><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+        else
+            k_explicit2d<T, MODEL, 4, KS, false, true><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
+        return;
+    }
     if (bc)  // no-flux grids: one prefetch depth
         k_explicit2d<T, MODEL, 4, KS, true><<<blocks, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k);
     else if (depth <= 4)
@@ -360,7 +434,7 @@ void launch_depth(int depth, int blocks, hipStream_t s, const T* in, T* out, int
 // The seam kernel for a periodic grid when its chunk plan fits (nchunks a multiple
 // of SEAM_NW, chunks long enough that no seam row is read before the barrier).
 // Returns false (nothing launched) otherwise.
-template <typename T, int MODEL>
+template <typename T, int MODEL, bool LOB>
 bool launch_seam(int ks, int ty, hipStream_t s, const T* in, T* out, int nx, int ny, int nstrips,
                  unsigned bytes, const Coef<T>& k)
 {
@@ -369,27 +443,31 @@ bool launch_seam(int ks, int ty, hipStream_t s, const T* in, T* out, int nx, int
     int nch = (ny + ty - 1) / ty;
     nch = (nch + SEAM_NW - 1) / SEAM_NW * SEAM_NW;
     const int fill = 2 * H * ks, first = (fill + 3) / 4 * 4;
-    if (ny / nch < first + 4 || ny / nch < 8) return false;  // shortest balanced chunk
+    // shortest chunk: the top one of the smallest workgroup range (rows
+    // [Y0 + 3 span / 4, Y1) with span = Y1 - Y0 + H (ks - 1); no longer for a longer range)
+    const int rmin = ny / (nch / SEAM_NW), sh = H * (ks - 1);
+    const int shortest = rmin - (SEAM_NW - 1) * (rmin + sh) / SEAM_NW;
+    if (shortest < first + 4 - 2 * H || shortest < 8) return false;
     const long long waves = (long long)nstrips * nch;
     if (waves / SEAM_NW > (1ll << 30)) return false;
     const int nblocks = (int)(waves / SEAM_NW);
     switch (ks) {
-        case 2: k_explicit2d_seam<T, MODEL, 2><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
-        case 3: k_explicit2d_seam<T, MODEL, 3><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
-        default: k_explicit2d_seam<T, MODEL, 4><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+        case 2: k_explicit2d_seam<T, MODEL, 2, LOB><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+        case 3: k_explicit2d_seam<T, MODEL, 3, LOB><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
+        default: k_explicit2d_seam<T, MODEL, 4, LOB><<<nblocks, 256, 0, s>>>(in, out, nx, ny, nch, nblocks, bytes, k); break;
     }
     return true;
 }
 
 template <typename T, int MODEL>
 void launch_ks(int ks, int depth, int blocks, hipStream_t s, const T* in, T* out, int nx, int ny,
-               int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc)
+               int nstrips, int nwaves, int nchunks, unsigned bytes, const Coef<T>& k, int bc, int quad)
 {
     switch (ks) {
-        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
-        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
-        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
-        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc); break;
+        case 1: launch_depth<T, MODEL, 1>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc, quad); break;
+        case 2: launch_depth<T, MODEL, 2>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc, quad); break;
+        case 3: launch_depth<T, MODEL, 3>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc, quad); break;
+        default: launch_depth<T, MODEL, 4>(depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, bc, quad); break;
     }
 }
 
@@ -456,19 +534,31 @@ void launch_explicit2d(const Geom& g, int model, const FreeEnergy& f, double kap
     const int blocks = (nwaves + 3) / 4;
     const unsigned bytes = (unsigned)((size_t)g.N * sizeof(T));  // caller guarantees < 2^31
     Coef<T> k{};
+    // Gauss: the quadrature sum N carries detJ and the box stencil (9c - box)/3;
+    // Gauss-Lobatto: N = m f'(c) and the 5-point stencil 4c - nbrs (both h-free in 2-D).
+    // (The products keep the association the batched plans use, so a sample there is
+    // bitwise the same problem stepped alone.)
+    const double nsc = g.quad ? m : detJ, kd = g.quad ? m : 3.0 * m;
+    auto seam_or_halo = [&](auto model_tag) {
+        constexpr int MODEL = decltype(model_tag)::value;
+        const bool seam = !g.bc && (cfg.depth <= 4 || g.quad) &&
+                          (g.quad ? launch_seam<T, MODEL, true>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k)
+                                  : launch_seam<T, MODEL, false>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k));
+        if (!seam)
+            launch_ks<T, MODEL>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc,
+                                g.quad);
+    };
     if (model == 0) {
-        const double sc = dt * mob * detJ / m;
+        const double sc = dt * mob * nsc / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
-        k.beta = (T)(dt * mob * kappa / (3.0 * m));
-        if (g.bc || cfg.depth > 4 || !launch_seam<T, 0>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k))
-            launch_ks<T, 0>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
+        k.beta = (T)(dt * mob * kappa / kd);
+        seam_or_halo(std::integral_constant<int, 0>{});
     } else {
-        const double sc = detJ / m;
+        const double sc = nsc / m;
         k.a1 = (T)(sc * f.a1); k.a2 = (T)(sc * f.a2); k.a3 = (T)(sc * f.a3);
-        k.beta = (T)(kappa / (3.0 * m));
-        k.gamma = (T)(dt * mob / (3.0 * m));
-        if (g.bc || cfg.depth > 4 || !launch_seam<T, 1>(ks, ty, s, in, out, nx, ny, nstrips, bytes, k))
-            launch_ks<T, 1>(ks, cfg.depth, blocks, s, in, out, nx, ny, nstrips, nwaves, nchunks, bytes, k, g.bc);
+        k.beta = (T)(kappa / kd);
+        k.gamma = (T)(dt * mob / kd);
+        seam_or_halo(std::integral_constant<int, 1>{});
     }
 }
 

@@ -14,6 +14,7 @@ struct Geom {
     double h;
     int bc;
     int cm;  // 1: consistent mass in the implicit-path kernels (residual, JVP, adjoint)
+    int quad;  // 1: Gauss-Lobatto (nodal) quadrature; 0: 2-point Gauss-Legendre
 };
 
 // Free-energy polynomials with W folded in.

@@ -594,6 +594,7 @@ int pf_vjp(pf_ctx* ctx, const pf_problem* p, int kind, double dt, const void* U,
         if (int rc = validate(p)) return rc;
         if (p->model == PF_COUPLED) return fail(PF_EUNSUPPORTED, "pf_vjp: coupled model not implemented");
         if (p->model == PF_GRAIN) return fail(PF_EUNSUPPORTED, "pf_vjp: grain growth not implemented");
+        if (p->quad != PF_QUAD_GAUSS) return fail(PF_EUNSUPPORTED, "pf_vjp: Gauss-Lobatto quadrature not implemented");
         if (kind != PF_VJP_RESIDUAL && kind != PF_VJP_EXPLICIT_STEP && kind != PF_VJP_NEWTON_STEP)
             return fail(PF_EINVAL, "unknown vjp kind %d", kind);
         if (flags & ~PF_VJP_THETA_HOST) return fail(PF_EINVAL, "unknown flags 0x%x", flags);

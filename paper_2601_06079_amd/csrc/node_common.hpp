@@ -308,6 +308,32 @@ __device__ __forceinline__ T stiff_diag(T h)
     return D == 2 ? (T)(8.0 / 3.0) : (T)(8.0 / 3.0) * h;
 }
 
+// Gauss-Lobatto (nodal) quadrature: the quadrature points are the nodes, so the
+// nonlinear term is m f'(u_a) at the node and the Q1 stiffness integrated at the
+// nodes is the unit 5-point stencil (2-D, h-free) or h times the 7-point one (3-D).
+template <typename T, int D>
+__device__ __forceinline__ T stiff_lob(const T* u, T h)
+{
+    if constexpr (D == 2) {
+        return (T)4 * u[4] - ((u[3] + u[5]) + (u[1] + u[7]));
+    } else {
+        return ((T)6 * u[13] - ((u[12] + u[14]) + (u[10] + u[16]) + (u[4] + u[22]))) * h;
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T stiff_lob_diag(T h)
+{
+    return D == 2 ? (T)4 : (T)6 * h;
+}
+
+// the stiffness row of the grid's quadrature
+template <typename T, int D>
+__device__ __forceinline__ T stiff_q(const Geom& g, const T* u, T h)
+{
+    return g.quad ? stiff_lob<T, D>(u, h) : stiff<T, D>(u, h);
+}
+
 template <int D>
 __device__ __forceinline__ bool node_of(const Geom& g, long long idx, int& i, int& j, int& k)
 {

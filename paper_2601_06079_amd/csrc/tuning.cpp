@@ -19,11 +19,12 @@ std::atomic<int> g_seam{0};
 
 int stream2d_fuse(const pf_problem* p)
 {
-    (void)p;
     const int ov = g_fuse_override.load();
-    // two fused steps measured fastest on MI355X at 2048^2 and 8192^2 (three and
-    // four add more halo recomputation than they save in launches and traffic)
-    return ov > 0 ? std::min(ov, 4) : 2;
+    if (ov > 0) return std::min(ov, 4);
+    // Measured on MI355X with the seam-sharing kernel: Cahn-Hilliard is fastest with
+    // three fused steps at 2048^2 to 8192^2 (7.7 against 8.1 us/step for two at 2048^2;
+    // two lose 10% at 8192^2); Allen-Cahn keeps two.
+    return p->model == PF_CAHN_HILLIARD ? 3 : 2;
 }
 
 int stream2d_rows(const pf_problem* p, int ks, int cus)

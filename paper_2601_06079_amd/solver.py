@@ -29,6 +29,7 @@ class Problem:
     mass: int = A.MASS_LUMPED  # MASS_CONSISTENT: Gauss-integrated mass (implicit path)
     nfields: int = 1  # GRAIN: order parameters
     gamma: float = 1.5  # GRAIN: pair coupling
+    quad: int = A.QUAD_GAUSS  # QUAD_LOBATTO: nodal quadrature
 
     @property
     def dim(self):
@@ -53,7 +54,7 @@ class Problem:
                             A.F64 if self.dtype == torch.float64 else A.F32, int(self.mass),
                             (ct.c_int64 * 3)(*n3), float(self.h), float(self.W),
                             float(self.kappa), float(self.mobility), float(self.mobility_eta),
-                            int(self.nfields), 0, float(self.gamma))
+                            int(self.nfields), int(self.quad), float(self.gamma))
 
 
 def _stream():

@@ -200,11 +200,11 @@ def test_elastic_validation_before_launch(L, C):
 
 def _grain(**kw):
     d = dict(dim=2, bc=A.PERIODIC, model=A.GRAIN, fe=0, dtype=A.F32, mass=0, n=(40, 30, 1), h=1.0,
-             W=0.0, kappa=1.0, mobility=1.0, mobility_eta=0.0, nfields=6, reserved2=0, gamma=1.5)
+             W=0.0, kappa=1.0, mobility=1.0, mobility_eta=0.0, nfields=6, quad=0, gamma=1.5)
     d.update(kw)
     return A.pf_problem(d["dim"], d["bc"], d["model"], d["fe"], d["dtype"], d["mass"],
                         (ct.c_int64 * 3)(*d["n"]), d["h"], d["W"], d["kappa"], d["mobility"],
-                        d["mobility_eta"], d["nfields"], d["reserved2"], d["gamma"])
+                        d["mobility_eta"], d["nfields"], d["quad"], d["gamma"])
 
 
 def test_grain_model_entry_points(L, C):
@@ -220,7 +220,8 @@ def test_grain_model_entry_points(L, C):
     assert L.pf_workspace_size(C, ct.byref(p), A.OP_VJP, ct.byref(nb)) == A.PF_EUNSUPPORTED
     for bad, st in ((dict(nfields=0), A.PF_EINVAL), (dict(nfields=33), A.PF_EINVAL),
                     (dict(dtype=A.F64, nfields=13), A.PF_EINVAL), (dict(gamma=float("nan")), A.PF_EINVAL),
-                    (dict(reserved2=1), A.PF_EINVAL), (dict(dim=3, n=(8, 8, 8)), A.PF_EUNSUPPORTED),
+                    (dict(quad=2), A.PF_EINVAL), (dict(quad=1), A.PF_EUNSUPPORTED),
+                    (dict(dim=3, n=(8, 8, 8)), A.PF_EUNSUPPORTED),
                     (dict(mass=1), A.PF_EUNSUPPORTED)):
         assert L.pf_workspace_size(C, ct.byref(_grain(**bad)), A.OP_RESIDUAL, ct.byref(nb)) == st, bad
     fake = [ct.c_void_p(0x1000 * (i + 1)) for i in range(4)]

@@ -1,0 +1,179 @@
+"""Gauss-Lobatto (nodal) quadrature on the GPU against the oracle's Lobatto
+variant: residual, Jacobian product, energy, explicit steps (2-D streaming and
+fused kernels, 3-D node kernels), and the backward-Euler Newton step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2601_06079_amd import _abi as A
+from paper_2601_06079_amd import inputs as I
+from paper_2601_06079_amd import solver as S
+from tests.gpu_util import announce, dev, host, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+F32, F64 = torch.float32, torch.float64
+TOL = {F32: 1e-5, F64: 1e-12}
+
+
+def lpair(n, model, fe, dtype, h=1.0, W=1.0, kappa=1.0, mob=1.0, bc=O.PERIODIC, mass=0):
+    g = S.Problem(n=tuple(n), model=model, fe=fe, dtype=dtype, h=h, W=W, kappa=kappa, mobility=mob,
+                  bc=A.NOFLUX if bc == O.NOFLUX else A.PERIODIC, quad=A.QUAD_LOBATTO, mass=mass)
+    o = O.Problem(n=tuple(n), model=model, fe=fe, h=h, W=W, kappa=kappa, mob=mob, bc=bc, quad=O.LOBATTO,
+                  mass=mass)
+    return g, o
+
+
+def _state(o, lo, hi, seed, base=0.0):
+    c = I.uniform_field(o.n, lo, hi, seed=seed, base=base)
+    if o.model == O.CH:
+        return np.concatenate([c, I.uniform_field(o.n, -0.5, 0.5, seed=seed + 1)])
+    return c
+
+
+SHAPES = [((2, 2), O.PERIODIC), ((3, 5), O.PERIODIC), ((130, 97), O.PERIODIC), ((61, 200), O.NOFLUX),
+          ((17, 9, 12), O.PERIODIC), ((9, 11, 7), O.NOFLUX)]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+@pytest.mark.parametrize("n,bc", SHAPES)
+def test_lobatto_residual(n, bc, model, dtype):
+    announce("lobatto residual", n, bc, model, dtype)
+    g, o = lpair(n, model, O.F_01 if model == O.CH else O.F_SYM, dtype, h=0.7, W=1.3, kappa=0.9, mob=1.1, bc=bc)
+    U = rounded(_state(o, -1.0, 1.0, 3), dtype)
+    assert rel_l2(host(S.residual(g, dev(U, dtype))), O.residual(o, U)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+@pytest.mark.parametrize("n,bc", [((5, 7), O.PERIODIC), ((96, 70), O.NOFLUX), ((3, 4, 5), O.PERIODIC),
+                                  ((12, 10, 9), O.NOFLUX), ((40, 36, 33), O.PERIODIC)])
+def test_lobatto_jvp(n, bc, model, dtype):
+    announce("lobatto jvp", n, bc, model, dtype)
+    g, o = lpair(n, model, O.F_01, dtype, W=1.0, kappa=2.0, mob=0.8, bc=bc)
+    U = rounded(_state(o, 0.2, 0.8, 5), dtype)
+    v = rounded(np.random.default_rng(9).standard_normal(o.ndof), dtype)
+    for inv_dt in (0.0, 2.0):
+        Jv = host(S.jvp(g, inv_dt, dev(U, dtype), dev(v, dtype)))
+        assert rel_l2(Jv, O.jvp(o, inv_dt, U, v)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("n,fe,bc", [((7, 5), O.F_SYM, O.PERIODIC), ((128, 96), O.F_01, O.NOFLUX),
+                                     ((4, 5, 6), O.F_01, O.PERIODIC), ((20, 16, 12), O.F_SYM, O.NOFLUX)])
+def test_lobatto_energy(n, fe, bc, dtype):
+    announce("lobatto energy", n, fe, bc, dtype)
+    g, o = lpair(n, O.AC, fe, dtype, h=0.8, W=1.2, kappa=1.7, bc=bc)
+    U = rounded(I.uniform_field(n, -1, 1, seed=11), dtype)
+    out = host(S.energy(g, dev(U, dtype)))
+    assert out[0] == pytest.approx(O.energy(o, U), rel=1e-12)
+    assert out[1] == pytest.approx(O.total_mass(o, U), rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+@pytest.mark.parametrize("n,bc", SHAPES)
+def test_lobatto_explicit_steps(n, bc, model, dtype):
+    """One step (field and update) and 20 steps; 2-D grids run the streaming kernels
+    (fused launches included), 3-D the node kernels.  Nodal quadrature widens the
+    spectrum of M^-1 K to 4 d / h^2 (Gauss: 4 / h^2), so explicit Cahn-Hilliard with
+    kappa = 2 is stable for dt < 2 / (lambda (kappa lambda + 2 W)) = 0.0139 in 2-D but
+    only 0.0064 in 3-D: the 3-D cases step at dt = 0.004."""
+    announce("lobatto explicit", n, bc, model, dtype)
+    if model == O.AC:
+        g, o = lpair(n, O.AC, O.F_SYM, dtype, W=1.0, kappa=1.0, mob=1.0, bc=bc)
+        U0 = rounded(_state(o, -0.05, 0.05, 1), dtype)
+        dt = 0.1
+    else:
+        g, o = lpair(n, O.CH, O.F_01, dtype, W=1.0, kappa=2.0, mob=1.0, bc=bc)
+        U0 = rounded(_state(o, -0.01, 0.01, 2, base=0.5), dtype)
+        dt = 0.01 if len(n) == 2 else 0.004
+    N = o.nnodes
+    for steps in (1, 20):
+        Ug = dev(U0, dtype)
+        S.step_explicit(g, Ug, dt, steps)
+        ug, uo = host(Ug), O.explicit(o, U0, dt, steps)
+        assert rel_l2(ug[:N], uo[:N]) < TOL[dtype] * steps
+        if steps == 1:
+            assert rel_l2(ug[:N] - U0[:N], uo[:N] - U0[:N]) < (2e-3 if dtype == F32 else 1e-9)
+        if model == O.CH:
+            assert rel_l2(ug[N:], uo[N:]) < (1e-4 if dtype == F32 else 1e-11)
+
+
+@pytest.mark.parametrize("ks", [2, 3])
+@pytest.mark.parametrize("model,n,bc,rows", [(O.CH, (2048, 2048), O.PERIODIC, 0), (O.CH, (512, 600), O.PERIODIC, 19),
+                                             (O.AC, (300, 512), O.PERIODIC, 12), (O.CH, (200, 150), O.NOFLUX, 0),
+                                             (O.AC, (61, 37), O.PERIODIC, 0)])
+def test_lobatto_fused_equals_single_steps(ks, model, n, bc, rows):
+    """Fused launches (with shared seams where the plan allows) give bitwise the
+    field of single-step launches on periodic grids; on no-flux grids, to rounding."""
+    announce("lobatto fused", ks, model, n, bc, rows)
+    fe = O.F_01 if model == O.CH else O.F_SYM
+    g, o = lpair(n, model, fe, F32, W=1.0, kappa=2.0 if model == O.CH else 1.0, mob=1.0, bc=bc)
+    U0 = _state(o, -0.05, 0.05, 12, base=0.5 if model == O.CH else 0.0)
+    dt = 0.01 if model == O.CH else 0.1
+    out = []
+    try:
+        S.tune_set(A.TUNE_STREAM2D_ROWS, rows)
+        for fuse in (1, ks):
+            S.tune_set(A.TUNE_STREAM2D_FUSE, fuse)
+            t = dev(U0, F32)
+            S.step_explicit(g, t, dt, 3 * ks + 1)
+            out.append(t)
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, 0)
+        S.tune_set(A.TUNE_STREAM2D_ROWS, 0)
+    if bc == O.PERIODIC:
+        assert torch.equal(out[0], out[1])
+    else:
+        N = o.nnodes
+        assert rel_l2(host(out[1])[:N], host(out[0])[:N]) < 1e-6
+    N = o.nnodes
+    ref = O.explicit(o, rounded(U0, F32), dt, 3 * ks + 1)
+    assert rel_l2(host(out[1])[:N], ref[:N]) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("model,n,bc", [(O.AC, (12, 10), O.PERIODIC), (O.CH, (9, 8), O.NOFLUX),
+                                        (O.CH, (6, 5, 4), O.PERIODIC), (O.AC, (5, 6, 4), O.NOFLUX)])
+def test_lobatto_newton_step(model, n, bc, dtype):
+    """Backward-Euler Newton step (GMRES with (block) Jacobi from the nodal diagonal)
+    against the oracle's dense-LU Newton; the consistent-mass option gives the same
+    step (nodal quadrature makes the mass diagonal)."""
+    announce("lobatto newton", model, n, bc, dtype)
+    fe = O.F_SYM if model == O.AC else O.F_01
+    g, o = lpair(n, model, fe, dtype, W=1.0, kappa=1.0 if model == O.AC else 2.0, mob=1.0, bc=bc)
+    if model == O.AC:
+        Uold = I.uniform_field(n, -0.5, 0.5, seed=3)
+    else:
+        c = I.uniform_field(n, -0.05, 0.05, seed=4, base=0.4)
+        Uold = O.explicit(o, np.concatenate([c, np.zeros_like(c)]), 1.0, 0)
+    Uold = rounded(Uold, dtype)
+    rtol = 1e-11 if dtype == F64 else 1e-8
+    Ug = dev(Uold, dtype)
+    rep = S.newton_step(g, 0.5, dev(Uold, dtype), Ug, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8))
+    assert rep.converged, rep
+    Uo, conv, _, _ = O.newton_be(o, 0.5, Uold, rtol=1e-13, maxit=30, solver=0)
+    assert conv
+    tol = 1e-9 if dtype == F64 else 1e-5
+    assert rel_l2(host(Ug), Uo) < tol
+    gc = S.Problem(**{**g.__dict__, "mass": A.MASS_CONSISTENT})
+    Uc = dev(Uold, dtype)
+    repc = S.newton_step(gc, 0.5, dev(Uold, dtype), Uc, S.newton_opts(rtol=rtol, lin_rtol_min=1e-8))
+    assert repc.converged and torch.equal(Uc, Ug)
+
+
+def test_lobatto_unsupported_calls():
+    """The adjoint, batches, and the coupled and grain models reject nodal quadrature."""
+    g, o = lpair((16, 12), O.AC, O.F_SYM, F32)
+    U = dev(I.uniform_field((16, 12), -0.5, 0.5, seed=1), F32)
+    Ub = torch.zeros_like(U)
+    tb = torch.zeros(3, dtype=F64, device="cuda")
+    with pytest.raises(A.PFError) as e:
+        S.vjp(g, A.VJP_RESIDUAL, 0.1, U, U.clone(), Ub, tb)
+    assert e.value.status == A.PF_EUNSUPPORTED
+    q = S.Problem(n=(16, 12), model=A.COUPLED, dtype=F32, quad=A.QUAD_LOBATTO)
+    with pytest.raises(A.PFError) as e:
+        S.workspace(q, A.OP_RESIDUAL)
+    assert e.value.status == A.PF_EUNSUPPORTED
