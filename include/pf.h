@@ -238,6 +238,15 @@ int pf_step_explicit(pf_ctx* ctx, const pf_problem* p, double dt, int64_t nsteps
  * Asynchronous. */
 int pf_energy(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void* ws, void* stream);
 
+/* pf_energy without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, loops that forbid allocation): the same result,
+ * bitwise, with the reduction's partial sums kept in a static array of the library
+ * (1 MiB per device, held until the process ends).  Grids of at most 2^24 nodes;
+ * larger ones return PF_EINVAL before anything is enqueued.  Calls that overlap on
+ * one device share that array and race; serialise them (one stream, or events).
+ * Allocates nothing.  Asynchronous. */
+int pf_energy_noalloc(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void* stream);
+
 /* Jv = (dR/dU) v for R = inv_dt M (U - U_old) + r(U) (Eq. 14; inv_dt = 0
  * gives dr/dU):
  *   Allen-Cahn:     Jv = inv_dt m v + L [ N'(eta) v + kappa K v ]

@@ -274,6 +274,15 @@ int energy_t(const pf_problem* p, const void* U, double* out, double* part, hipS
 
 namespace {
 
+// Device scratch of pf_energy_noalloc: the per-block FP64 partial sums of the
+// energy reduction (a pair per block of 256 nodes), for callers that cannot
+// allocate.  Each device the library runs on holds its own copy until the
+// process ends; pf_create looks up its address on that device.  Calls that
+// overlap on one device race on it.  Every partial is written before it is read,
+// so nothing needs clearing between calls.
+constexpr size_t NOALLOC_ENERGY_DOUBLES = size_t(1) << 17;  // 1 MiB: up to 2^24 nodes
+static __device__ __align__(256) double scratch[NOALLOC_ENERGY_DOUBLES];
+
 int make_slots(pfapi::PinnedSlots* sl, size_t doubles, int events)
 {
     double* h = nullptr;
@@ -349,6 +358,13 @@ int pf_create(int device, pf_ctx** out)
             c->cus = cus;
         int rc = make_slots(&c->gmres, newton_pinned_doubles(), 3);
         if (rc == PF_OK) rc = make_slots(&c->cg, elastic_pinned_doubles(), 2);
+        if (rc == PF_OK) {  // this device's copy of the static scratch (device current here)
+            void* sp = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !sp)
+                rc = fail(PF_EDEVICE, "static scratch address: %s", hipGetErrorString(e));
+            c->scratch = static_cast<double*>(sp);
+        }
         (void)hipSetDevice(prev);
         if (rc != PF_OK) {
             free_ctx(c.release());
@@ -479,6 +495,24 @@ int pf_energy(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void
         if (!ws || reinterpret_cast<uintptr_t>(ws) % 8) return fail(PF_EINVAL, "ws is NULL or misaligned");
         if (int rc = require_device(ctx)) return rc;
         return energy_t(p, U, out, (double*)ws, (hipStream_t)stream);
+    });
+}
+
+int pf_energy_noalloc(pf_ctx* ctx, const pf_problem* p, const void* U, double* out, void* stream)
+{
+    return guarded("pf_energy_noalloc", [&]() -> int {
+        if (int rc = check_ctx(ctx)) return rc;
+        if (int rc = validate(p)) return rc;
+        if (int rc = check_ptr(U, p, "U")) return rc;
+        if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(PF_EINVAL, "out is NULL or misaligned");
+        const pfk::Geom g = geom_of(p);
+        const size_t need = (size_t)pfk::energy_blocks(g) * 2;
+        if (need > NOALLOC_ENERGY_DOUBLES)
+            return fail(PF_EINVAL, "pf_energy_noalloc: %lld nodes exceed the static scratch (at most %lld)",
+                        (long long)g.N, (long long)(NOALLOC_ENERGY_DOUBLES / 2 * 256));
+        if (int rc = require_device(ctx)) return rc;
+        if (!ctx->scratch) return fail(PF_EDEVICE, "the context has no static scratch address");
+        return energy_t(p, U, out, ctx->scratch, (hipStream_t)stream);
     });
 }
 

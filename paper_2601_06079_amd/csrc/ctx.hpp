@@ -51,6 +51,7 @@ struct pf_ctx {
     std::mutex mu;
     std::map<std::pair<int, double>, double> el_lmax;  // lambda_max(D^-1 K) per (dim, nu)
     std::map<pfapi::BatchShapeKey, std::array<int, 3>> tuned;  // (ks, ty, depth) per batch shape
+    double* scratch = nullptr;  // this device's address of the library's static energy scratch
 };
 
 namespace pfapi {
