@@ -145,11 +145,14 @@ def summarize_counters(step_dir, copy_dir, copy_mib, n=2048):
     cw = [v for (k, c), v in cp.items() if c == "WRITE_SIZE" and v * 1024 > 0.5 * nbytes]
     f_scale = nbytes / (max(cf) * 1024) if cf else 1.0
     w_scale = nbytes / (max(cw) * 1024) if cw else 1.0
-    names = [k for (k, c) in step if _step_kernel(k)]
-    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and _step_kernel(k)]
-    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and _step_kernel(k)]
-    ks = _step_kernel(names[0])[1] if names else None
-    rec = {"n": n, "ks": ks, "kernel": names[0] if names else None, "kernel_src_sha256_16": kernel_hash(),
+    # the dominant step kernel: the one fusing the most steps (a run whose step count
+    # is not a multiple of the fusion depth also holds single-step launches)
+    names = sorted({k for (k, c) in step if _step_kernel(k)}, key=lambda k: -_step_kernel(k)[1])
+    name = names[0] if names else None
+    kf = [v for (k, c), v in step.items() if c == "FETCH_SIZE" and k == name]
+    kw = [v for (k, c), v in step.items() if c == "WRITE_SIZE" and k == name]
+    ks = _step_kernel(name)[1] if name else None
+    rec = {"n": n, "ks": ks, "kernel": name, "kernel_src_sha256_16": kernel_hash(),
            "fetch_kib_raw": kf[0] if kf else None, "write_kib_raw": kw[0] if kw else None,
            "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
     if kf and kw:
@@ -357,6 +360,27 @@ def copy_ceiling(mib, stream, reps=20):
     del x, y
     torch.cuda.empty_cache()
     return {"mib": mib, "ms": ms, "gbs": 2 * nb / (ms * 1e-3) / 1e9, "kernel": "k_stream_copy (16-byte loads/stores)"}
+
+
+def fma_ceiling(stream, blocks=8192, iters=4096, reps=5):
+    """The library's FMA probe: independent non-packed FP32 FMA chains on every SIMD
+    (blocks of 256 threads; 8192 blocks = 32 waves per SIMD), TFLOP/s."""
+    import ctypes as ct
+
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    L = A.lib()
+    L.pf_fma_probe.restype = ct.c_int
+    L.pf_fma_probe.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    args = (A.ctx(), blocks, iters, ct.c_void_p(out.data_ptr()), ct.c_void_p(stream.cuda_stream))
+    A.check(L.pf_fma_probe(*args))
+    ms = min(_time_ms(lambda: L.pf_fma_probe(*args), stream) for _ in range(reps))
+    flops = 16.0 * iters * blocks * 256
+    return {"blocks": blocks, "waves_per_simd": blocks * 4 / 1024, "ms": ms,
+            "tflops": flops / (ms * 1e-3) / 1e12, "peak": VALU_PEAK_TFLOPS,
+            "kernel": "k_fma_probe (8 independent FMA chains per thread)"}
 
 
 def ac128_record(stream, steps=1000):
@@ -964,6 +988,9 @@ def main():
                       "single_step_launch_16384": single_step_hbm(16384, 40, stream),
                       "copy_ceiling_1gib": copy_ceiling(1024, stream),
                       "copy_ceiling_32mib": copy_ceiling(32, stream)}
+        out["valu_ceiling"] = fma_ceiling(stream)
+        if out["roofline"]["bound"] == "alu":  # the same work against the measured FMA rate
+            out["roofline"]["frac_of_fma_probe"] = out["roofline"]["achieved"] / out["valu_ceiling"]["tflops"]
         out["ac128_fp64"] = ac128_record(stream)
         out["adjoint"] = adjoint_record(stream)
         out["surrogate"] = surrogate_record(stream)

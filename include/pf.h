@@ -168,6 +168,11 @@ int pf_ctx_device(const pf_ctx* ctx, int* device);
  * with 16-byte loads and stores: the practical HBM (or Infinity Cache)
  * bandwidth against which the stencil kernels are measured.  Asynchronous. */
 int pf_stream_copy(pf_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream);
+/* `blocks` blocks of 256 threads, each running 8 independent non-packed FP32 FMA
+ * chains for `iters` rounds (16 iters flops per thread) and writing one float to
+ * out[block * 256 + thread] (device, 256 blocks floats): the practical FP32 VALU
+ * ceiling of the explicit step.  Asynchronous. */
+int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
 
 /* Launch-shape overrides, process-global (value 0 restores the automatic
  * choice).  Used by the autotuner; results never depend on them, except that on
