@@ -7,13 +7,18 @@
 // output summing the partials in index order), so results are bitwise
 // reproducible run to run.
 //
-// Classical Gram-Schmidt with one re-orthogonalisation (CGS2) is fused into
+// Classical Gram-Schmidt with selective re-orthogonalisation is fused into two or
 // three sweeps over the Krylov basis V (k vectors, leading dimension ld):
-//   k_dots            h1 = V^T w
+//   k_dots            h1 = V^T w and ||w||^2
 //   k_axpy_dots       w <- w - V h1 and, in the same sweep, h2 = V^T w, ||w||^2
 //   k_axpy_normalize  w <- w - V h2, whose norm is sqrt(||w||^2 - ||h2||^2)
 //                     without another pass; the normalised vector is stored
 //                     as the next basis vector and the preconditioner applied.
+// When the first projection keeps at least half of ||w||^2 (||w - V h1||^2 =
+// ||w||^2 - ||h1||^2 >= ||w||^2 / 2), one projection is enough (the Kahan-Parlett
+// criterion, "twice is enough"): k_axpy_dots and the reduction after it return at
+// once and k_axpy_normalize projects w with h1.  Every kernel takes that decision
+// from the same reduced values in the same order, so all agree; the host sees h2 = 0.
 #include <algorithm>
 #include <cmath>
 
@@ -90,15 +95,27 @@ __device__ __forceinline__ void store_partials(double (&acc)[NV], int cnt, doubl
     }
 }
 
-// part[i * nb + block] = this block's share of V_i . w  (i < k <= KMAX)
+// The re-orthogonalisation test on the first pass's reduced values h1[0..k)
+// (= V^T w) and h1[k] (= ||w||^2): true when one projection is enough.  nn
+// receives ||w - V h1||^2 = ||w||^2 - ||h1||^2.
+__device__ __forceinline__ bool cgs_one_pass(const double* __restrict__ h1, int k, double& nn)
+{
+    double hsq = 0.0;
+    for (int i = 0; i < k; ++i) hsq = fma(h1[i], h1[i], hsq);
+    nn = h1[k] - hsq;
+    return nn >= 0.5 * h1[k];
+}
+
+// part[i * nb + block] = this block's share of V_i . w  (i < k <= KMAX),
+// part[k * nb + block] = its share of ||w||^2
 template <typename T, int KMAX, int VW>
 __global__ __launch_bounds__(KB) void k_dots(const T* __restrict__ V, long long ld, int k,
                                              const T* __restrict__ w, long long n,
                                              double* __restrict__ part)
 {
-    double acc[KMAX];
+    double acc[KMAX + 1];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= KMAX; ++i) acc[i] = 0.0;
     const long long nv = n / VW;
     for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
         const Pack<T, VW> wv = ldp<T, VW>(w + e * VW);
@@ -109,16 +126,25 @@ __global__ __launch_bounds__(KB) void k_dots(const T* __restrict__ V, long long 
         for (int i = 0; i < KMAX; ++i)
 #pragma unroll
             for (int l = 0; l < VW; ++l) acc[i] = fma((double)vv[i].v[l], (double)wv.v[l], acc[i]);
+#pragma unroll
+        for (int l = 0; l < VW; ++l) acc[KMAX] = fma((double)wv.v[l], (double)wv.v[l], acc[KMAX]);
     }
-    store_partials<KMAX>(acc, k, part);
+    // ||w||^2 to slot k so that the partial columns are contiguous
+    double out[KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= KMAX; ++i) out[i] = i < k ? acc[i] : (i == k ? acc[KMAX] : 0.0);
+    store_partials<KMAX + 1>(out, k + 1, part);
 }
 
 // w <- w - V h ; part[i * nb + block] = share of V_i . w (i < k), part[k * nb + block] = share of ||w||^2
+// (returns at once when one projection is enough: see cgs_one_pass)
 template <typename T, int KMAX, int VW>
 __global__ __launch_bounds__(KB) void k_axpy_dots(const T* __restrict__ V, long long ld, int k,
                                                   const double* __restrict__ h, T* __restrict__ w,
                                                   long long n, double* __restrict__ part)
 {
+    double nn1;
+    if (cgs_one_pass(h, k, nn1)) return;  // uniform over the grid
     double hh[KMAX], acc[KMAX + 1];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
@@ -169,21 +195,28 @@ __device__ __forceinline__ void axpy_chunk(const T* __restrict__ V, long long ld
         for (int i = 0; i < KMAX; ++i) x[l] = fma(-hh[i], (double)vv[i].v[l], x[l]);
 }
 
-// Last CGS2 sweep fused with the normalisation and the preconditioner:
-//   w'' = w - V h  (h: the k second-pass coefficients; sums[k] = ||w||^2),
+// Last Gram-Schmidt sweep fused with the normalisation and the preconditioner:
+//   w'' = w - V h  (h: the second-pass coefficients h2, sums2[k] = ||w||^2 after
+//   the first pass; or, when one projection is enough, h1 on the untouched w),
 //   ||w''||^2 = ||w||^2 - ||h||^2  (h is the projection of w on V),
 //   v = w'' / ||w''||  -> vnext,   z = P^-1 v.
-// nrm2[0] receives ||w''||^2.  Node-indexed: VW nodes per lane, planes at
-// offset N (MODEL 1: the c and mu planes with per-node 2x2 blocks; MODEL 2: the
-// three planes of the coupled model with 3x3 blocks).
+// nrm2[0] receives ||w''||^2.  With one projection the second-pass outputs h2 are
+// set to 0 (device and host copies) for the Hessenberg column.  Node-indexed: VW
+// nodes per lane, planes at offset N (MODEL 1: the c and mu planes with per-node
+// 2x2 blocks; MODEL 2: the three planes of the coupled model with 3x3 blocks).
 template <typename T, int KMAX, int VW, int MODEL>
 __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, long long ld, int k,
-                                                       const double* __restrict__ sums,
+                                                       const double* __restrict__ sums1,
+                                                       double* __restrict__ sums2,
+                                                       double* __restrict__ sums2_host,
                                                        const T* __restrict__ w, T* __restrict__ vnext,
                                                        T* __restrict__ z, const T* __restrict__ pinv,
                                                        long long N, int tr, double* __restrict__ nrm2,
                                                        double* __restrict__ nrm2_host)
 {
+    double nn;
+    const bool one = cgs_one_pass(sums1, k, nn);
+    const double* sums = one ? sums1 : sums2;
     double hh[KMAX];
     double hsq = 0.0;
 #pragma unroll
@@ -191,11 +224,16 @@ __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, 
         hh[i] = i < k ? sums[i] : 0.0;
         hsq = fma(hh[i], hh[i], hsq);
     }
-    const double nn = sums[k] - hsq;
+    if (!one) nn = sums[k] - hsq;
     const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         nrm2[0] = nn > 0.0 ? nn : 0.0;
         if (nrm2_host) __hip_atomic_store(nrm2_host, nn > 0.0 ? nn : 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (one)
+            for (int i = 0; i <= k; ++i) {
+                sums2[i] = 0.0;
+                if (sums2_host) __hip_atomic_store(sums2_host + i, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
     }
     const long long nv = N / VW;
     for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < nv; e += (long long)gridDim.x * KB) {
@@ -303,12 +341,19 @@ __global__ __launch_bounds__(KB) void k_norm2(const T* __restrict__ a, const T* 
 // out[i] (op)= sum_b part[i * nb + b], one block per i, fixed order
 // (host: optional host-mapped copy of out, written with system-scope stores so
 // that the host reads it once the kernel has completed)
+// (skip_h1: the first-pass values of a Gram-Schmidt step; when one projection is
+// enough there -- see cgs_one_pass -- there is nothing to reduce)
 __global__ __launch_bounds__(KB) void k_reduce_cols(const double* __restrict__ part, int nb, int k,
                                                     double* __restrict__ out, int accumulate,
-                                                    double* __restrict__ host = nullptr)
+                                                    double* __restrict__ host = nullptr,
+                                                    const double* __restrict__ skip_h1 = nullptr, int skip_k = 0)
 {
     const int i = blockIdx.x;
     if (i >= k) return;
+    if (skip_h1) {
+        double nn;
+        if (cgs_one_pass(skip_h1, skip_k, nn)) return;  // uniform over the grid
+    }
     double a[1] = {0.0};
     for (int b = threadIdx.x; b < nb; b += KB) a[0] += part[(long long)i * nb + b];
     block_sum<1>(a);
@@ -721,19 +766,19 @@ void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
     const int nb = krylov_blocks(n);
     const int nb1 = std::min(nb, cap_dots), nb2 = std::min(nb, cap_axpy);
     k_dots<T, KMAX, VW><<<nb1, KB, 0, s>>>(V, ld, k, w, n, part);
-    k_reduce_cols<<<k, KB, 0, s>>>(part, nb1, k, o.h1, 0, o.host_h1);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb1, k + 1, o.h1, 0, o.host_h1);
     k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, o.h1, w, n, part);
-    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, o.h2, 0, o.host_h2);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, o.h2, 0, o.host_h2, o.h1, k);
     const long long chunks = (N / VW + KB - 1) / KB;
     const int nbn = (int)std::max<long long>(1, std::min<long long>(chunks, cap_norm));
     if (model == 0)
-        k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+        k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
                                                             o.nrm2, o.host_nrm2);
     else if (model == 1)
-        k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+        k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
                                                             o.nrm2, o.host_nrm2);
     else
-        k_axpy_normalize<T, KMAX, VW, 2><<<nbn, KB, 0, s>>>(V, ld, k, o.h2, w, vnext, z, pinv, N, tr,
+        k_axpy_normalize<T, KMAX, VW, 2><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
                                                             o.nrm2, o.host_nrm2);
 }
 

@@ -16,12 +16,17 @@ struct KrOut {
     double *h1, *h2, *nrm2;
     double *host_h1, *host_h2, *host_nrm2;
 };
-// One Arnoldi orthogonalisation (CGS2) of w against the k basis vectors V
-// (N nodes, 1 plane for model 0, 2 for model 1, 3 for model 2; leading dimension ld):
-//   h1[0..k) = V^T w, w <- w - V h1, h2[0..k) = V^T w, h2[k] = ||w||^2,
-//   nrm2[0] = ||w - V h2||^2, vnext = (w - V h2) / sqrt(nrm2[0]) (0 if that is 0),
-//   z = P^-1 vnext.  w is left after the first correction.  part: (k + 1) *
-//   krylov_blocks(n) doubles.  Returns -1 (nothing launched) for k outside 1..KR_MAXK.
+// One Arnoldi orthogonalisation of w against the k basis vectors V (N nodes, 1
+// plane for model 0, 2 for model 1, 3 for model 2; leading dimension ld),
+// classical Gram-Schmidt with selective re-orthogonalisation:
+//   h1[0..k) = V^T w, h1[k] = ||w||^2;
+//   if ||w||^2 - ||h1||^2 >= ||w||^2 / 2 (one projection is enough): h2 = 0,
+//     nrm2[0] = ||w - V h1||^2, vnext = (w - V h1) / sqrt(nrm2[0]), w untouched;
+//   else: w <- w - V h1, h2[0..k) = V^T w, h2[k] = ||w||^2,
+//     nrm2[0] = ||w - V h2||^2, vnext = (w - V h2) / sqrt(nrm2[0]);
+//   (vnext = 0 if nrm2[0] is 0), z = P^-1 vnext.  The Hessenberg column is h1 + h2.
+//   part: (k + 1) * krylov_blocks(n) doubles.  Returns -1 (nothing launched) for k
+//   outside 1..KR_MAXK.
 template <typename T>
 int kr_cgs2(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, const T* pinv,
             long long N, double* part, const KrOut& o, hipStream_t s, int tr = 0);
