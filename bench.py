@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--surrogate-gain", type=int, default=0, metavar="ITERS",
                     help="only train the surrogate for ITERS iterations on 512^2 Cahn-Hilliard "
                          "and print the matched-error gain record")
+    ap.add_argument("--nn-backward", type=int, default=0, metavar="ITERS",
+                    help="only time ITERS surrogate training iterations (forward + backward + "
+                         "Adam) on 16 x 512^2 and print their record")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the hbm / adjoint / surrogate records (the step alone)")
     ap.add_argument("--traffic", default=None,
@@ -381,6 +384,28 @@ def fma_ceiling(stream, blocks=8192, iters=4096, reps=5):
     return {"blocks": blocks, "waves_per_simd": blocks * 4 / 1024, "ms": ms,
             "tflops": flops / (ms * 1e-3) / 1e12, "peak": VALU_PEAK_TFLOPS,
             "kernel": "k_fma_probe (8 independent FMA chains per thread)"}
+
+
+def nn_train_record(stream, iters=10, n=512, Bn=16):
+    """Surrogate training iterations (forward, backward, Adam) on Bn random n^2
+    fields: time per iteration, samples/s, and the BF16 rate of the network's flops
+    (forward once, backward twice the forward: 3 x 39 168 flop per pixel)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import nn as NN
+    r = np.random.default_rng(0)
+    c = torch.as_tensor((0.5 + 0.1 * r.standard_normal((Bn, n, n))).astype(np.float32), device="cuda")
+    M = torch.as_tensor(r.uniform(0.5, 2, Bn).astype(np.float32), device="cuda")
+    k = torch.as_tensor(r.uniform(0.5, 2, Bn).astype(np.float32), device="cuda")
+    tgt = c + 0.01
+    model = NN.Surrogate(seed=0)
+    model.train_step(c, M, k, tgt)
+    ms = _time_ms(lambda: [model.train_step(c, M, k, tgt) for _ in range(iters)], stream) / iters
+    flop = 3 * 39168.0 * Bn * n * n
+    return {"workload": f"surrogate training iteration, {Bn} x {n}^2", "iters": iters, "ms_per_iter": ms,
+            "samples_per_s": Bn / (ms * 1e-3), "tflops": flop / (ms * 1e-3) / 1e12,
+            "frac_of_bf16_peak": flop / (ms * 1e-3) / 2.5e15}
 
 
 def ac128_record(stream, steps=1000):
@@ -832,7 +857,8 @@ def implicit_record(steps, stream):
 
 def main():
     args = parse()
-    if args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby or args.grain:
+    if (args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby or args.grain
+            or args.nn_backward):
         import torch
         stream = torch.cuda.current_stream()
         if args.grain:
@@ -857,6 +883,8 @@ def main():
         if args.coupled:
             print(json.dumps(coupled_record(stream, steps=args.coupled)), flush=True)
             print(json.dumps(coupled_implicit_record(stream)), flush=True)
+        if args.nn_backward:
+            print(json.dumps(nn_train_record(stream, iters=args.nn_backward)), flush=True)
         if args.surrogate_gain:
             from paper_2601_06079_amd import nn as NN
             rec = NN.gain_experiment(train_iters=args.surrogate_gain,

@@ -532,52 +532,88 @@ __global__ __launch_bounds__(NBLK) void k_out_dgrad(const u16* __restrict__ a3, 
     for (int q = 0; q < 4; ++q) dst[q] = *reinterpret_cast<uint4*>(&outv[8 * q]);
 }
 
-// output layer wgrad: part[block][tap * 32 + ci] = sum over the block's pixel
-// tiles of a3(p + tap)[ci] g(p), part[block][288] = sum g(p).  Each tile's a3
-// halo and g are staged in LDS; thread t owns output t and (t < 33) t + 256.
+// Output layer's weight gradient: part[block][tap * 32 + ci] = sum over this block's
+// pixels p of a3(p + tap)[ci] g(p), part[block][288] = sum g(p).  Written per pixel q
+// of a3 instead: a3(q)[ci] times g at the 3 x 3 neighbourhood of q, an outer product
+// of 32 channels and 9 taps.  A block walks tiles of OWR rows x 32 pixels (a fixed
+// stride of them: split-K over pixels); thread (pixel px, channel group cg) reads its
+// 4 channels of a3 (8 bytes, 64 contiguous bytes per pixel, one coalesced read of
+// a3 per launch) and keeps 9 x 4 FP32 sums; g's (OWR + 2) x 34 neighbourhood tile
+// sits in LDS.  The sums are reduced over the block's 32 pixel lanes at the end.
+constexpr int OWR = 8;  // rows per tile of k_out_wgrad
 __global__ __launch_bounds__(NBLK) void k_out_wgrad(const u16* __restrict__ a3, const float* __restrict__ g,
                                                     float* __restrict__ part, int B, int H, int W)
 {
-    __shared__ __align__(16) unsigned char la[Tile<32>::BYTES];
-    __shared__ float lg[TR * TW];
-    const int tiles_x = W / TW, tiles_y = (H + TR - 1) / TR;
+    __shared__ float gl[OWR + 2][TW + 2];
+    __shared__ float red[NBLK / 64][8][37];
+    const int tiles_x = W / TW, tiles_y = (H + OWR - 1) / OWR;
     const int ntiles = tiles_x * tiles_y * B;
-    const int o0 = threadIdx.x, o1 = threadIdx.x + NBLK;  // o0 < 256: tap 0..7; o1: tap 8 or db4
-    const int dy0 = (o0 / 32) / 3, dx0 = (o0 / 32) % 3, ci0 = o0 % 32;
-    const int ci1 = o1 % 32;
-    float acc0 = 0.0f, acc1 = 0.0f;
+    const int px = threadIdx.x >> 3, cg = threadIdx.x & 7;
+    float acc[9][4];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[tap][c] = 0.0f;
+    float db = 0.0f;
     for (int t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
         int t = t0;
         const int tx = t % tiles_x;
         t /= tiles_x;
         const int ty = t % tiles_y;
         const int b = t / tiles_y;
-        const int x0 = tx * TW, y0 = ty * TR;
-        __syncthreads();
-        stage_tile<32>(a3, b, H, W, y0, x0, la);
-        for (int q = threadIdx.x; q < TR * TW; q += NBLK) {
-            const int r = q / TW, px = q % TW;
-            lg[q] = y0 + r < H ? g[((size_t)b * H + y0 + r) * W + x0 + px] : 0.0f;  // rows past H add 0
+        const int x0 = tx * TW, y0 = ty * OWR;
+        __syncthreads();  // the previous tile's reads of gl are done
+        for (int q = threadIdx.x; q < (OWR + 2) * (TW + 2); q += NBLK) {
+            const int r = q / (TW + 2), cx = q % (TW + 2);
+            const int gy = ((y0 - 1 + r) % H + H) % H, gx = wrapi(x0 - 1 + cx, W);  // H may be < OWR
+            gl[r][cx] = g[((size_t)b * H + gy) * W + gx];
         }
         __syncthreads();
-        const unsigned char* b0 = la + (dy0 * (TW + 2) + dx0) * Tile<32>::PSTRIDE + ci0 * 2;
-        const unsigned char* b1 = la + (2 * (TW + 2) + 2) * Tile<32>::PSTRIDE + ci1 * 2;
-        for (int r = 0; r < TR; ++r) {
-            const unsigned char* r0 = b0 + r * (TW + 2) * Tile<32>::PSTRIDE;
-            const unsigned char* r1 = b1 + r * (TW + 2) * Tile<32>::PSTRIDE;
-#pragma unroll 8
-            for (int px = 0; px < TW; ++px) {
-                const float gp = lg[r * TW + px];
-                acc0 = fmaf(bf16_val(*reinterpret_cast<const u16*>(r0 + px * Tile<32>::PSTRIDE)), gp, acc0);
-                if (o1 < 288)
-                    acc1 = fmaf(bf16_val(*reinterpret_cast<const u16*>(r1 + px * Tile<32>::PSTRIDE)), gp, acc1);
-                else
-                    acc1 += gp;  // o1 == 288: db4 (threads past 288 never store acc1)
+        const int rows = min(OWR, H - y0);
+        for (int r = 0; r < rows; ++r) {
+            const uint2 av = *reinterpret_cast<const uint2*>(
+                a3 + (((size_t)b * H + y0 + r) * W + x0 + px) * 32 + cg * 4);
+            const float a[4] = {bf16_val((u16)(av.x & 0xffffu)), bf16_val((u16)(av.x >> 16)),
+                                bf16_val((u16)(av.y & 0xffffu)), bf16_val((u16)(av.y >> 16))};
+            // tap (dy, dx) pairs a3(p + (dy - 1, dx - 1)) with g(p): for a3 at q that is
+            // g(q + (1 - dy, 1 - dx)), tile entry (r + 2 - dy, px + 2 - dx)
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const float gv = gl[r + 2 - tap / 3][px + 2 - tap % 3];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[tap][c] = fmaf(a[c], gv, acc[tap][c]);
             }
+            if (cg == 0) db += gl[r + 1][px + 1];
         }
     }
-    part[(size_t)blockIdx.x * 289 + o0] = acc0;
-    if (o1 < 289) part[(size_t)blockIdx.x * 289 + o1] = acc1;
+    // sum over the 8 pixel lanes of each wave (lane = 8 p + cg), then over the waves
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[tap][c] += __shfl_xor(acc[tap][c], off, 64);
+        db += __shfl_xor(db, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane < 8) {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[wv][lane][tap * 4 + c] = acc[tap][c];
+        red[wv][lane][36] = db;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < 289; o += NBLK) {
+        float v = 0.0f;
+        if (o < 288) {
+            const int tap = o / 32, ci = o % 32;
+            for (int w = 0; w < NBLK / 64; ++w) v += red[w][ci / 4][tap * 4 + ci % 4];
+        } else {
+            for (int w = 0; w < NBLK / 64; ++w) v += red[w][0][36];
+        }
+        part[(size_t)blockIdx.x * 289 + o] = v;
+    }
 }
 
 // Adam on FP32 masters (bias-corrected; Kingma & Ba)
@@ -814,7 +850,11 @@ void nn_center(float* g, const double* mean, int B, int HW, hipStream_t s)
     k_center<<<(unsigned)((n + NBLK - 1) / NBLK), NBLK, 0, s>>>(g, mean, B, HW);
 }
 
-int nn_out_wgrad_blocks(int B, int H, int W) { return nn_wgrad_blocks(B, H, W); }
+int nn_out_wgrad_blocks(int B, int H, int W)
+{
+    const long long tiles = (long long)B * ((H + OWR - 1) / OWR) * (W / TW);
+    return (int)(tiles < 1024 ? tiles : 1024);
+}
 
 void nn_out_bwd(const u16* a3, const u16* w4, const float* g, u16* ga3, float* part, int B, int H,
                 int W, hipStream_t s)

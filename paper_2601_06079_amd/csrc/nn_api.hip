@@ -111,9 +111,24 @@ int pf_nn_forward(const float* params, int B, int H, int W, const float* c, cons
         if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PF_EINVAL, "ws must be 256-byte aligned");
         hipStream_t s = (hipStream_t)stream;
         NNWS L = nn_layout(B, H, W, ws);
-        forward(params, B, H, W, c, M, kappa, nullptr, L, s, false);
-        if (hipMemcpyAsync(chat, L.chat, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return check_launch("pf_nn_forward copy");
+        // Groups of samples whose 32-channel BF16 activation (64 B per pixel) stays
+        // within 128 MiB, so that a layer's input and output share the 256 MB Infinity
+        // Cache (measured on MI355X for 16 x 512^2: 0.477 ms in groups of 8 against
+        // 0.495 ms in one; groups of 4 or fewer leave the matrix cores short of work).
+        // Every group runs the same per-sample kernels, so the result does not depend
+        // on the grouping.
+        const long long HW = (long long)H * W;
+        int G = pfk::tune_nn_group();
+        if (G <= 0) G = (int)std::max<long long>(1, (128ll << 20) / (HW * 64));
+        G = std::min(G, B);
+        for (int b0 = 0; b0 < B; b0 += G) {
+            const int nb = std::min(G, B - b0);
+            const long long o = (long long)b0 * HW;
+            // c and chat are B x H x W; M and kappa hold one value per sample
+            forward(params, nb, H, W, c + o, M + b0, kappa + b0, nullptr, L, s, false);
+            if (hipMemcpyAsync(chat + o, L.chat, (size_t)nb * HW * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return check_launch("pf_nn_forward copy");
+        }
         return check_launch("pf_nn_forward");
     });
 }

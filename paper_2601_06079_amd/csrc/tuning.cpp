@@ -15,6 +15,7 @@ std::atomic<int> g_jvp3d_planes{0};
 std::atomic<int> g_el_planes{0};
 std::atomic<int> g_el_mg{0};
 std::atomic<int> g_seam{0};
+std::atomic<int> g_nn_group{0};
 }  // namespace
 
 int stream2d_fuse(const pf_problem* p)
@@ -66,6 +67,7 @@ int tune_jvp3d_planes() { return pfapi::g_jvp3d_planes.load(); }
 int tune_el_planes() { return pfapi::g_el_planes.load(); }
 int tune_el_mg() { return pfapi::g_el_mg.load(); }
 int tune_stream2d_seam() { return pfapi::g_seam.load(); }
+int tune_nn_group() { return pfapi::g_nn_group.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -87,6 +89,8 @@ int pf_tune_set(int key, int value)
         g_el_mg.store(value);
     else if (key == PF_TUNE_STREAM2D_SEAM)
         g_seam.store(value);
+    else if (key == PF_TUNE_NN_GROUP)
+        g_nn_group.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -121,6 +125,8 @@ int pf_tune_get(int key, int* value)
         *value = g_el_mg.load();
     else if (key == PF_TUNE_STREAM2D_SEAM)
         *value = g_seam.load();
+    else if (key == PF_TUNE_NN_GROUP)
+        *value = g_nn_group.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

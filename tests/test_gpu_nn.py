@@ -8,6 +8,7 @@ import torch
 import oracle as O
 from paper_2601_06079_amd import _abi as A
 from paper_2601_06079_amd import nn as NN
+from paper_2601_06079_amd import solver as S
 from tests.gpu_util import announce, host, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -128,6 +129,29 @@ def test_forward_matches_oracle(shape):
     assert rel_l2(got - c, ref - c) < (1e-3 if Bn * H * W >= 8192 else 5e-3)
     # exact mass per sample (the projection), to FP32 rounding of the field
     assert np.max(np.abs(got.mean(axis=(1, 2)) - c.astype(np.float64).mean(axis=(1, 2)))) < 1e-6
+
+
+@pytest.mark.parametrize("group", [1, 2, 3])
+def test_forward_sample_groups_bitwise(group):
+    """The forward pass runs in groups of samples (each with its own M, kappa): every
+    grouping gives the bits of the single-group pass, and the single-group pass
+    matches the oracle."""
+    announce("nn forward groups", group)
+    Bn, H, W = 5, 8, 64
+    c, M, k, _ = _inputs(Bn, H, W, 7)
+    p = _params(3)
+    model = NN.Surrogate(params=p)
+    try:
+        S.tune_set(A.TUNE_NN_GROUP, Bn)
+        ref = model.forward(_dev(c), _dev(M), _dev(k)).clone()
+        S.tune_set(A.TUNE_NN_GROUP, group)
+        got = model.forward(_dev(c), _dev(M), _dev(k))
+    finally:
+        S.tune_set(A.TUNE_NN_GROUP, 0)
+    assert torch.equal(got, ref)
+    o, _, _ = O.nn(c.astype(np.float64), M[:, None, None].astype(np.float64),
+                   k[:, None, None].astype(np.float64), p, round_bf16=True)
+    assert rel_l2(host(ref) - c, o - c) < 5e-3
 
 
 @pytest.mark.parametrize("shape", [(2, 8, 32), (2, 12, 64)])
