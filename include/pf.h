@@ -360,7 +360,7 @@ typedef struct pf_batch_sample {
 
 /* Host-side description of a device plan (filled by pf_batch_plan). */
 typedef struct pf_batch_info {
-    int32_t count, n_items, reserved0; /* samples, work items (sample, strip, chunk); 0 */
+    int32_t count, n_items, fe;        /* samples, work items (sample, strip, chunk), free energy */
     int32_t ks, ty, depth;             /* fused steps, rows per wave, prefetch depth */
     int32_t model, dtype;
     int64_t total;                     /* elements of each packed array (max offset + nodes) */

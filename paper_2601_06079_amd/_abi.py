@@ -64,7 +64,7 @@ class pf_batch_sample(ct.Structure):
 
 
 class pf_batch_info(ct.Structure):
-    _fields_ = [("count", ct.c_int32), ("n_items", ct.c_int32), ("reserved0", ct.c_int32),
+    _fields_ = [("count", ct.c_int32), ("n_items", ct.c_int32), ("fe", ct.c_int32),
                 ("ks", ct.c_int32), ("ty", ct.c_int32), ("depth", ct.c_int32),
                 ("model", ct.c_int32), ("dtype", ct.c_int32), ("total", ct.c_int64),
                 ("plan_bytes", ct.c_int64), ("dt", ct.c_double), ("off_samples", ct.c_int64),

@@ -220,6 +220,7 @@ int pf_batch_plan(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* sa
     I.ty = ty;
     I.depth = depth;
     I.model = base->model;
+    I.fe = base->fe;
     I.dtype = base->dtype;
     I.total = c.total;
     I.plan_bytes = (int64_t)need;
@@ -320,7 +321,7 @@ int batched_vjp_t(const pf_batch_info* info, const void* plan, int64_t nsteps, c
         const int two = hk >= 2 && k >= 1;
         pfk::launch_vjp2d_batched<T>(states + k * total, states + (two ? k - 1 : k) * total, cur,
                                      other, smp, items, info->n_items, info->ty, hk, info->depth,
-                                     two ? 2 : 1, part, s);
+                                     two ? 2 : 1, info->fe == PF_F_SYM, part, s);
         std::swap(cur, other);
         k -= two ? 2 : 1;
     }

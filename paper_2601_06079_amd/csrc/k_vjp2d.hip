@@ -13,9 +13,11 @@
 // (Supp. Note 2, Eqs. II.5-II.6 for one step).  The step's parameter
 // sensitivities lam'^T d(eta')/d(L, kappa, W) need only two sums per sample:
 // sum_i lam'_i N(eta)_i equals the quadrature of f'(eta_q) lam'_q (lam'_q the
-// interpolated adjoint), and sum_i lam'_i (K eta)_i is a dot product, so with
+// interpolated adjoint), and sum_i lam'_i (K eta)_i is a dot product, which K's
+// symmetry on the periodic grid turns into sum_i eta_i (K lam')_i -- and K lam' the
+// step needs anyway -- so with
 //   A = sum_q f'_1(eta_q) lam'_q          (f'_1: f' at W = 1)
-//   B = sum_i lam'_i (9 eta_i - box3x3(eta)_i)       (= 3 lam'^T K eta in 2-D)
+//   B = sum_i eta_i (9 lam'_i - box3x3(lam')_i)      (= 3 eta^T K lam' = 3 lam'^T K eta)
 // the gradient contributions are
 //   dL     = -(dt/m) (W |J| A + kappa B / 3)
 //   dkappa = -(dt/m) L B / 3
@@ -39,12 +41,13 @@ struct VjpCoef {
 
 // push(eta_r, lam'_r) takes row r and returns lam of row r - 1.  a: the 4
 // quadrature points of this lane's element (x, x+1) x (r-1, r), summed
-// f'_1(eta_q) lam'_q; b: lam'(x, r-1) (9 eta - box eta)(x, r-1).
-template <typename T>
+// f'_1(eta_q) lam'_q; b: eta(x, r-1) (9 lam' - box lam')(x, r-1).  SYM: the
+// symmetric double well (f'' = b0 + b2 q^2, f'_1 = q (a1 + a3 q^2)), whose two
+// polynomials share q^2.
+template <typename T, bool SYM>
 struct VjpStage {
     T l_m1 = 0, e_m1 = 0;          // lam', eta at row r-1
     T s3l_m1 = 0, s3l_m2 = 0;      // 3-point x-sums of lam' at rows r-1, r-2
-    T s3e_m1 = 0, s3e_m2 = 0;      // 3-point x-sums of eta at rows r-1, r-2
     T exl_m1 = 0, exr_m1 = 0;      // x-interpolated eta of row r-1
     T lxl_m1 = 0, lxr_m1 = 0;      // x-interpolated lam' of row r-1
     T guL_m1 = 0, guR_m1 = 0;      // upward scatter of element row (r-2, r-1)
@@ -52,9 +55,9 @@ struct VjpStage {
     __device__ __forceinline__ T push(T ec, T lc, const VjpCoef<T>& k, T& a, T& b)
     {
         const T gp = (T)GP, gm = (T)GM;
-        const T el = from_left(ec), er = from_right(ec);
+        const T er = from_right(ec);
         const T ll = from_left(lc), lr = from_right(lc);
-        const T s3e = el + ec + er, s3l = ll + lc + lr;
+        const T s3l = ll + lc + lr;
         const T de = er - ec, dl = lr - lc;
         const T exl = fmaT(gm, de, ec), exr = fmaT(gp, de, ec);
         const T lxl = fmaT(gm, dl, lc), lxr = fmaT(gp, dl, lc);
@@ -65,14 +68,27 @@ struct VjpStage {
         const T qR0 = fmaT(gm, e1, exr_m1), qR1 = fmaT(gp, e1, exr_m1);
         const T pL0 = fmaT(gm, f0, lxl_m1), pL1 = fmaT(gp, f0, lxl_m1);
         const T pR0 = fmaT(gm, f1, lxr_m1), pR1 = fmaT(gp, f1, lxr_m1);
-        const T PL0 = fmaT(fmaT(k.b2, qL0, k.b1), qL0, k.b0) * pL0;
-        const T PL1 = fmaT(fmaT(k.b2, qL1, k.b1), qL1, k.b0) * pL1;
-        const T PR0 = fmaT(fmaT(k.b2, qR0, k.b1), qR0, k.b0) * pR0;
-        const T PR1 = fmaT(fmaT(k.b2, qR1, k.b1), qR1, k.b0) * pR1;
-        T s = cubic(qL0, k.a1, k.a2, k.a3) * pL0;
-        s = fmaT(cubic(qL1, k.a1, k.a2, k.a3), pL1, s);
-        s = fmaT(cubic(qR0, k.a1, k.a2, k.a3), pR0, s);
-        a = fmaT(cubic(qR1, k.a1, k.a2, k.a3), pR1, s);
+        T PL0, PL1, PR0, PR1;
+        if constexpr (SYM) {
+            const T sL0 = qL0 * qL0, sL1 = qL1 * qL1, sR0 = qR0 * qR0, sR1 = qR1 * qR1;
+            PL0 = fmaT(k.b2, sL0, k.b0) * pL0;
+            PL1 = fmaT(k.b2, sL1, k.b0) * pL1;
+            PR0 = fmaT(k.b2, sR0, k.b0) * pR0;
+            PR1 = fmaT(k.b2, sR1, k.b0) * pR1;
+            T s = fmaT(k.a3, sL0, k.a1) * (qL0 * pL0);
+            s = fmaT(fmaT(k.a3, sL1, k.a1), qL1 * pL1, s);
+            s = fmaT(fmaT(k.a3, sR0, k.a1), qR0 * pR0, s);
+            a = fmaT(fmaT(k.a3, sR1, k.a1), qR1 * pR1, s);
+        } else {
+            PL0 = fmaT(fmaT(k.b2, qL0, k.b1), qL0, k.b0) * pL0;
+            PL1 = fmaT(fmaT(k.b2, qL1, k.b1), qL1, k.b0) * pL1;
+            PR0 = fmaT(fmaT(k.b2, qR0, k.b1), qR0, k.b0) * pR0;
+            PR1 = fmaT(fmaT(k.b2, qR1, k.b1), qR1, k.b0) * pR1;
+            T s = cubic(qL0, k.a1, k.a2, k.a3) * pL0;
+            s = fmaT(cubic(qL1, k.a1, k.a2, k.a3), pL1, s);
+            s = fmaT(cubic(qR0, k.a1, k.a2, k.a3), pR0, s);
+            a = fmaT(cubic(qR1, k.a1, k.a2, k.a3), pR1, s);
+        }
         // scatter of f'' lam' to the nodes, as the forward scatters f'
         const T dL = PL0 - PL1, dR = PR0 - PR1;
         const T gdL = fmaT(gp, dL, PL1), guL = fmaT(gm, dL, PL1);
@@ -82,15 +98,12 @@ struct VjpStage {
         const T pl = fmaT(gp, dH, HR), pr = fmaT(gm, dH, HR);
         const T N2 = pl + from_left(pr);
         const T lapl = fmaT((T)9, l_m1, -(s3l_m2 + s3l_m1 + s3l));
-        const T lape = fmaT((T)9, e_m1, -(s3e_m2 + s3e_m1 + s3e));
         const T out = l_m1 - N2 - k.beta * lapl;
-        b = l_m1 * lape;
+        b = e_m1 * lapl;
         l_m1 = lc;
         e_m1 = ec;
         s3l_m2 = s3l_m1;
         s3l_m1 = s3l;
-        s3e_m2 = s3e_m1;
-        s3e_m1 = s3e;
         exl_m1 = exl;
         exr_m1 = exr;
         lxl_m1 = lxl;
@@ -115,7 +128,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // row behind, so lam_k never leaves registers (temporal blocking in reverse).
 // hk: the plan's strip halo (its strips output 64 - 2 hk columns; hk >= KS).
 // Must be called by a whole wave with wave-uniform arguments.
-template <typename T, int PF, int KS>
+template <typename T, int PF, int KS, bool SYM>
 __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* __restrict__ eta_lo,
                                          const T* __restrict__ lam_in, T* __restrict__ lam_out,
                                          int nx, int ny, int strip, int chunk, int ty, int hk,
@@ -135,7 +148,7 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
     const auto rlo = make_rsrc(KS == 2 ? eta_lo : eta_hi, bytes);
     const auto rl = make_rsrc(lam_in, bytes);
     const auto ro = make_rsrc(lam_out, bytes);
-    VjpStage<T> st[KS];
+    VjpStage<T, SYM> st[KS];
     T ringh[PF], ringl[PF], ringo[PF];
     int row = y0 - KS;
     while (row < 0) row += ny;
@@ -191,7 +204,7 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
     B = out_lane ? accB : 0.0;
 }
 
-template <typename T, int PF, int KS>
+template <typename T, int PF, int KS, bool SYM>
 __global__ __launch_bounds__(256) void k_vjp2d_batched(const T* __restrict__ eta_hi,
                                                        const T* __restrict__ eta_lo,
                                                        const T* __restrict__ lam_in,
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(256) void k_vjp2d_batched(const T* __restrict__ eta
                        (T)f1.a3, (T)(sm.dt * sm.mob * sm.kappa / (3.0 * m))};
     const unsigned bytes = (unsigned)((long long)sm.nx * sm.ny * (long long)sizeof(T));
     double A, B;
-    vjp_item<T, PF, KS>(eta_hi + sm.offset, eta_lo + sm.offset, lam_in + sm.offset,
+    vjp_item<T, PF, KS, SYM>(eta_hi + sm.offset, eta_lo + sm.offset, lam_in + sm.offset,
                         lam_out + sm.offset, sm.nx, sm.ny, it.strip, it.chunk, ty, hk, bytes, k, A, B);
     A = wave_sum(A);
     B = wave_sum(B);
@@ -260,11 +273,18 @@ __global__ __launch_bounds__(RB) void k_vjp2d_reduce(const double* __restrict__ 
 template <typename T>
 void launch_vjp2d_batched(const T* eta_hi, const T* eta_lo, const T* lam_in, T* lam_out,
                           const BatchSample* smp, const BatchItem* items, int n_items, int ty, int hk,
-                          int depth, int ksteps, double* part, hipStream_t s)
+                          int depth, int ksteps, bool sym, double* part, hipStream_t s)
 {
     const int blocks = (n_items + 3) / 4;
-#define VJP_LAUNCH(PF, KS) \
-    k_vjp2d_batched<T, PF, KS><<<blocks, 256, 0, s>>>(eta_hi, eta_lo, lam_in, lam_out, smp, items, n_items, ty, hk, part)
+#define VJP_LAUNCH(PF, KS)                                                                                  \
+    do {                                                                                                    \
+        if (sym)                                                                                            \
+            k_vjp2d_batched<T, PF, KS, true><<<blocks, 256, 0, s>>>(eta_hi, eta_lo, lam_in, lam_out, smp,   \
+                                                                    items, n_items, ty, hk, part);          \
+        else                                                                                                \
+            k_vjp2d_batched<T, PF, KS, false><<<blocks, 256, 0, s>>>(eta_hi, eta_lo, lam_in, lam_out, smp,  \
+                                                                     items, n_items, ty, hk, part);         \
+    } while (0)
     if (ksteps == 2) {
         // three streamed fields: a 2-row ring keeps enough loads in flight and
         // the register count low enough for four waves per SIMD
@@ -287,9 +307,9 @@ void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, 
 
 template void launch_vjp2d_batched<float>(const float*, const float*, const float*, float*,
                                           const BatchSample*, const BatchItem*, int, int, int, int,
-                                          int, double*, hipStream_t);
+                                          int, bool, double*, hipStream_t);
 template void launch_vjp2d_batched<double>(const double*, const double*, const double*, double*,
                                            const BatchSample*, const BatchItem*, int, int, int, int,
-                                           int, double*, hipStream_t);
+                                           int, bool, double*, hipStream_t);
 
 }  // namespace pfk

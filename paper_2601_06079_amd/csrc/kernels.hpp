@@ -187,11 +187,12 @@ void launch_explicit2d_batched(int model, const T* in, T* out, const BatchSample
 // ksteps (1 or 2 <= hk) steps per launch: lam_out = S_lo^T S_hi^T lam_in with
 // S^T lam = lam - (dt L/m) J_r(eta)^T lam at eta_hi (= eta_k) and, for two
 // steps, eta_lo (= eta_{k-1}); part[2 w .. 2 w + 2) += (A, B) of work item w
-// (see k_vjp2d.hip); hk: the plan's strip halo (H ks)
+// (see k_vjp2d.hip); hk: the plan's strip halo (H ks); sym: every sample has the
+// symmetric double well W (c^2 - 1)^2 / 4
 template <typename T>
 void launch_vjp2d_batched(const T* eta_hi, const T* eta_lo, const T* lam_in, T* lam_out,
                           const BatchSample* smp, const BatchItem* items, int n_items, int ty, int hk,
-                          int depth, int ksteps, double* part, hipStream_t s);
+                          int depth, int ksteps, bool sym, double* part, hipStream_t s);
 // theta_bar[s][0..3) += the gradient of sample s's accumulated (A, B) (fixed order)
 void launch_vjp2d_reduce(const double* part, const BatchSample* smp, int count, int ty,
                          double* theta_bar, hipStream_t s);
