@@ -14,11 +14,13 @@
 //   k_axpy_normalize  w <- w - V h2, whose norm is sqrt(||w||^2 - ||h2||^2)
 //                     without another pass; the normalised vector is stored
 //                     as the next basis vector and the preconditioner applied.
-// When the first projection keeps at least half of ||w||^2 (||w - V h1||^2 =
-// ||w||^2 - ||h1||^2 >= ||w||^2 / 2), one projection is enough (the Kahan-Parlett
-// criterion, "twice is enough"): k_axpy_dots and the reduction after it return at
-// once and k_axpy_normalize projects w with h1.  Every kernel takes that decision
-// from the same reduced values in the same order, so all agree; the host sees h2 = 0.
+// When the first projection keeps at least a tenth of ||w||^2 (||w - V h1||^2 =
+// ||w||^2 - ||h1||^2 >= ||w||^2 / 10), one projection is enough (selective
+// re-orthogonalisation in the manner of Daniel, Gragg, Kaufman and Stewart: the
+// orthogonality a projection loses grows with ||w|| / ||w - V h1||, here at most
+// sqrt(10)): k_axpy_dots and the reduction after it return at once and
+// k_axpy_normalize projects w with h1.  Every kernel takes that decision from the same
+// reduced values in the same order, so all agree; the host sees h2 = 0.
 #include <algorithm>
 #include <cmath>
 
@@ -98,12 +100,13 @@ __device__ __forceinline__ void store_partials(double (&acc)[NV], int cnt, doubl
 // The re-orthogonalisation test on the first pass's reduced values h1[0..k)
 // (= V^T w) and h1[k] (= ||w||^2): true when one projection is enough.  nn
 // receives ||w - V h1||^2 = ||w||^2 - ||h1||^2.
-__device__ __forceinline__ bool cgs_one_pass(const double* __restrict__ h1, int k, double& nn)
+// thr: the share of ||w||^2 one projection must keep (default 0.1)
+__device__ __forceinline__ bool cgs_one_pass(const double* __restrict__ h1, int k, double thr, double& nn)
 {
     double hsq = 0.0;
     for (int i = 0; i < k; ++i) hsq = fma(h1[i], h1[i], hsq);
     nn = h1[k] - hsq;
-    return nn >= 0.5 * h1[k];
+    return nn >= thr * h1[k];
 }
 
 // part[i * nb + block] = this block's share of V_i . w  (i < k <= KMAX),
@@ -141,10 +144,10 @@ __global__ __launch_bounds__(KB) void k_dots(const T* __restrict__ V, long long 
 template <typename T, int KMAX, int VW>
 __global__ __launch_bounds__(KB) void k_axpy_dots(const T* __restrict__ V, long long ld, int k,
                                                   const double* __restrict__ h, T* __restrict__ w,
-                                                  long long n, double* __restrict__ part)
+                                                  long long n, double* __restrict__ part, double thr)
 {
     double nn1;
-    if (cgs_one_pass(h, k, nn1)) return;  // uniform over the grid
+    if (cgs_one_pass(h, k, thr, nn1)) return;  // uniform over the grid
     double hh[KMAX], acc[KMAX + 1];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
@@ -212,10 +215,10 @@ __global__ __launch_bounds__(KB) void k_axpy_normalize(const T* __restrict__ V, 
                                                        const T* __restrict__ w, T* __restrict__ vnext,
                                                        T* __restrict__ z, const T* __restrict__ pinv,
                                                        long long N, int tr, double* __restrict__ nrm2,
-                                                       double* __restrict__ nrm2_host)
+                                                       double* __restrict__ nrm2_host, double thr)
 {
     double nn;
-    const bool one = cgs_one_pass(sums1, k, nn);
+    const bool one = cgs_one_pass(sums1, k, thr, nn);
     const double* sums = one ? sums1 : sums2;
     double hh[KMAX];
     double hsq = 0.0;
@@ -346,13 +349,14 @@ __global__ __launch_bounds__(KB) void k_norm2(const T* __restrict__ a, const T* 
 __global__ __launch_bounds__(KB) void k_reduce_cols(const double* __restrict__ part, int nb, int k,
                                                     double* __restrict__ out, int accumulate,
                                                     double* __restrict__ host = nullptr,
-                                                    const double* __restrict__ skip_h1 = nullptr, int skip_k = 0)
+                                                    const double* __restrict__ skip_h1 = nullptr, int skip_k = 0,
+                                                    double skip_thr = 0.0)
 {
     const int i = blockIdx.x;
     if (i >= k) return;
     if (skip_h1) {
         double nn;
-        if (cgs_one_pass(skip_h1, skip_k, nn)) return;  // uniform over the grid
+        if (cgs_one_pass(skip_h1, skip_k, skip_thr, nn)) return;  // uniform over the grid
     }
     double a[1] = {0.0};
     for (int b = threadIdx.x; b < nb; b += KB) a[0] += part[(long long)i * nb + b];
@@ -767,19 +771,21 @@ void cgs2_k(int model, const T* V, long long ld, int k, T* w, T* vnext, T* z, co
     const int nb1 = std::min(nb, cap_dots), nb2 = std::min(nb, cap_axpy);
     k_dots<T, KMAX, VW><<<nb1, KB, 0, s>>>(V, ld, k, w, n, part);
     k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb1, k + 1, o.h1, 0, o.host_h1);
-    k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, o.h1, w, n, part);
-    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, o.h2, 0, o.host_h2, o.h1, k);
+    const int tv = tune_gs_reorth();
+    const double thr = tv == 0 ? 0.1 : (tv - 1) / 1000.0;
+    k_axpy_dots<T, KMAX, VW><<<nb2, KB, 0, s>>>(V, ld, k, o.h1, w, n, part, thr);
+    k_reduce_cols<<<k + 1, KB, 0, s>>>(part, nb2, k + 1, o.h2, 0, o.host_h2, o.h1, k, thr);
     const long long chunks = (N / VW + KB - 1) / KB;
     const int nbn = (int)std::max<long long>(1, std::min<long long>(chunks, cap_norm));
     if (model == 0)
         k_axpy_normalize<T, KMAX, VW, 0><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
-                                                            o.nrm2, o.host_nrm2);
+                                                            o.nrm2, o.host_nrm2, thr);
     else if (model == 1)
         k_axpy_normalize<T, KMAX, VW, 1><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
-                                                            o.nrm2, o.host_nrm2);
+                                                            o.nrm2, o.host_nrm2, thr);
     else
         k_axpy_normalize<T, KMAX, VW, 2><<<nbn, KB, 0, s>>>(V, ld, k, o.h1, o.h2, o.host_h2, w, vnext, z, pinv, N, tr,
-                                                            o.nrm2, o.host_nrm2);
+                                                            o.nrm2, o.host_nrm2, thr);
 }
 
 template <typename T, int VW>

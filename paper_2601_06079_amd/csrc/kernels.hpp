@@ -72,7 +72,8 @@ int tune_jvp3d_planes();
 int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = automatic)
 int tune_el_mg();      // 1: plain CG for the elasticity solves
 int tune_stream2d_seam();
-int tune_nn_group();  // samples per forward group of the surrogate (0: automatic)  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
+int tune_nn_group();  // samples per forward group of the surrogate (0: automatic)
+int tune_gs_reorth();  // Gram-Schmidt re-orthogonalisation threshold (0: default)  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
 
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel

@@ -20,7 +20,7 @@ struct KrOut {
 // plane for model 0, 2 for model 1, 3 for model 2; leading dimension ld),
 // classical Gram-Schmidt with selective re-orthogonalisation:
 //   h1[0..k) = V^T w, h1[k] = ||w||^2;
-//   if ||w||^2 - ||h1||^2 >= ||w||^2 / 2 (one projection is enough): h2 = 0,
+//   if ||w||^2 - ||h1||^2 >= ||w||^2 / 10 (one projection is enough): h2 = 0,
 //     nrm2[0] = ||w - V h1||^2, vnext = (w - V h1) / sqrt(nrm2[0]), w untouched;
 //   else: w <- w - V h1, h2[0..k) = V^T w, h2[k] = ||w||^2,
 //     nrm2[0] = ||w - V h2||^2, vnext = (w - V h2) / sqrt(nrm2[0]);

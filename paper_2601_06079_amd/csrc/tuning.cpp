@@ -16,6 +16,7 @@ std::atomic<int> g_el_planes{0};
 std::atomic<int> g_el_mg{0};
 std::atomic<int> g_seam{0};
 std::atomic<int> g_nn_group{0};
+std::atomic<int> g_gs_reorth{0};
 }  // namespace
 
 int stream2d_fuse(const pf_problem* p)
@@ -68,6 +69,7 @@ int tune_el_planes() { return pfapi::g_el_planes.load(); }
 int tune_el_mg() { return pfapi::g_el_mg.load(); }
 int tune_stream2d_seam() { return pfapi::g_seam.load(); }
 int tune_nn_group() { return pfapi::g_nn_group.load(); }
+int tune_gs_reorth() { return pfapi::g_gs_reorth.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -91,6 +93,8 @@ int pf_tune_set(int key, int value)
         g_seam.store(value);
     else if (key == PF_TUNE_NN_GROUP)
         g_nn_group.store(value);
+    else if (key == PF_TUNE_GS_REORTH)
+        g_gs_reorth.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -127,6 +131,8 @@ int pf_tune_get(int key, int* value)
         *value = g_seam.load();
     else if (key == PF_TUNE_NN_GROUP)
         *value = g_nn_group.load();
+    else if (key == PF_TUNE_GS_REORTH)
+        *value = g_gs_reorth.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
