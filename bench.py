@@ -650,7 +650,7 @@ def grain_record(stream, n=2048, steps=200):
                         f"gamma={cfg['gamma']}, kappa=L=1, FP32 explicit dt={cfg['dt']}",
             "dof": dof, "steps": steps, "ms_per_step": kern_ms, "dof_steps_per_s": dof / (kern_ms * 1e-3),
             "energy_after": float(e[0]),
-            "roofline": {"kernel": "k_gg_tile2d<float, step>", "bound": "alu",
+            "roofline": {"kernel": f"k_gg_stream2d<float, {P}>", "bound": "alu",
                          "flops_per_node_field": FLOPS_PER_NODE_FIELD_GRAIN, "achieved": tflops,
                          "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
                          "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}}

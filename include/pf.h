@@ -191,6 +191,8 @@ int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
  *   PF_TUNE_GS_REORTH:      v >= 1: GMRES re-orthogonalises (a second Gram-Schmidt
  *                           pass) when one projection keeps less than (v - 1) / 1000
  *                           of ||w||^2 (1: never, 2001: always); 0: 1/10 (default);
+ *   PF_TUNE_GG_STREAM:      1 = explicit grain-growth steps on the LDS tile kernel; 0 =
+ *                           the row-streaming kernel where it applies (default);
  *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid);
  *                           2 = multigrid with every level launched separately;
  *                           v >= 3 = the multigrid's coarse grids of at most v
@@ -198,7 +200,7 @@ int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
  *                           none in 3-D). */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
        PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5, PF_TUNE_STREAM2D_SEAM = 6,
-       PF_TUNE_NN_GROUP = 7, PF_TUNE_GS_REORTH = 8 };
+       PF_TUNE_NN_GROUP = 7, PF_TUNE_GS_REORTH = 8, PF_TUNE_GG_STREAM = 9 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 /* The launch shape pf_step_explicit uses for p (2-D) on the context's device:

@@ -180,12 +180,13 @@ int step_coupled_t(const pf_problem* p, int cus, double dt, int64_t nsteps, T* U
 
 // grain growth: all order parameters per launch, ping-pong between U and ws
 template <typename T>
-int step_grain_t(const pf_problem* p, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
+int step_grain_t(const pf_problem* p, int cus, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
     const pfk::Geom g = geom_of(p);
     T *cur = U, *other = ws;
     for (int64_t st = 0; st < nsteps; ++st) {
-        pfk::launch_gg_tile2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, dt, cur, other, 0, s);
+        if (!pfk::launch_gg_stream2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, dt, cur, other, cus, s))
+            pfk::launch_gg_tile2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, dt, cur, other, 0, s);
         std::swap(cur, other);
     }
     if (int rc = check_launch("grain step")) return rc;
@@ -199,7 +200,7 @@ template <typename T>
 int step_explicit_t(const pf_problem* p, int cus, double dt, int64_t nsteps, T* U, T* ws, hipStream_t s)
 {
     if (p->model == PF_COUPLED) return step_coupled_t<T>(p, cus, dt, nsteps, U, ws, s);
-    if (p->model == PF_GRAIN) return step_grain_t<T>(p, dt, nsteps, U, ws, s);
+    if (p->model == PF_GRAIN) return step_grain_t<T>(p, cus, dt, nsteps, U, ws, s);
     const pfk::Geom g = geom_of(p);
     const pfk::FreeEnergy f = pfk::make_free_energy(p->fe, p->W);
     T* c = U;

@@ -19,10 +19,13 @@
 // Every field is read once (with the 1.28x halo of 17^2/15^2) and written once.
 // No-flux grids stage through the reflected indices; the update r/m needs no
 // correction and the residual rows are divided by 2^b (see device.hpp).
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "node_common.hpp"
+#include "stream2d.hpp"
 
 namespace pfk {
 namespace {
@@ -169,6 +172,123 @@ __global__ __launch_bounds__(GB) void k_gg_tile2d(Geom g, int P, T L, T kappa, T
             }
         }
         __syncthreads();
+    }
+}
+
+// The explicit step streamed row by row (the work layout of k_explicit2d): one
+// 64-lane wave per strip of 62 output columns (lane = column, x-neighbours by DPP)
+// and chunk of rows; every order parameter keeps its row window in registers:
+// c of the previous row, its x-sums of the previous two rows, and the upward
+// scatter of the element row below, with the next row's value in flight.  Per input
+// row r, pass 1 forms S = sum_j eta_j^2 at the four Gauss points of element row
+// (r-1, r) from all fields, pass 2 evaluates df/deta_i there, scatters it to the
+// nodes (sum-factorised, as k_explicit2d's stage) and writes node row r-1:
+//   out = eta - A N'(eta) - B (9 eta - box3x3 eta),  A = dt L |J| / m,  B = dt L kappa / (3 m)
+// (the Q1 stiffness of a node is (9 u - box u) / 3 in 2-D).  Every field is read
+// once (with a 64/62 column and (ty + 2)/ty row halo) and written once.
+// No-flux grids read through the reflection of rows and columns, as the tile
+// kernel does.  P is a template parameter: the field loops are unrolled without a
+// branch, so the scheduler interleaves the fields' independent chains.
+template <typename T>
+struct GGCoef {
+    T A, B;    // scales of the quadrature sum and of the stiffness
+    T c3, c1;  // df/deta = q (q^2 c3 + c1 S - 1)
+};
+
+template <typename T, int P, bool MIRROR>
+__global__ __launch_bounds__(256, 2) void k_gg_stream2d(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                                     int ny, int nstrips, int nwaves, int nchunks,
+                                                     int fbytes, unsigned bytes, GGCoef<T> k)
+{
+    constexpr int OUTW = WAVE - 2;
+    const int wave = uniform_wave();
+    if (wave >= nwaves) return;  // uniform per wave
+    const int chunk = wave / nstrips, strip = wave % nstrips;
+    const int y0 = (int)((long long)chunk * ny / nchunks);
+    const int y1 = (int)((long long)(chunk + 1) * ny / nchunks);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int xl = strip * OUTW - 1 + lane;
+    const int x = MIRROR ? reflect(xl, nx) : wrap_any(xl, nx);
+    const bool out_lane = lane >= 1 && lane < WAVE - 1 && xl < nx;
+    const int vx = x * (int)sizeof(T);
+    const int rowb = nx * (int)sizeof(T);
+    const auto rin = make_rsrc(in, bytes);
+    const auto rout = make_rsrc(out, bytes);
+    const T gp = (T)GP, gm = (T)GM;
+    T cur[P], c_m1[P], s3_m1[P], s3_m2[P], gu_l[P], gu_r[P];
+#pragma unroll
+    for (int f = 0; f < P; ++f) {
+        cur[f] = c_m1[f] = s3_m1[f] = s3_m2[f] = gu_l[f] = gu_r[f] = (T)0;
+    }
+    auto phys = [&](int r) { return MIRROR ? reflect(r, ny) : wrap_any(r, ny); };
+    {
+        const int r0 = phys(y0 - 1);
+#pragma unroll
+        for (int f = 0; f < P; ++f) cur[f] = bload<T>(rin, vx, f * fbytes + r0 * rowb);
+    }
+    const int iters = (y1 - y0) + 2;  // input rows y0 - 1 .. y1
+    for (int t = 0; t < iters; ++t) {
+        // the next input row (past the last one the last row is read again)
+        const int rn = phys(min(y0 + t, y1));
+        // pass 1: S at the Gauss points of element row (r-1, r), r = y0 - 1 + t
+        T S[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int f = 0; f < P; ++f) {
+            const T cc = cur[f], cm = c_m1[f];
+            const T d0 = from_right(cc) - cc, d1 = from_right(cm) - cm;
+            const T xl0 = fmaT(gm, d0, cc), xr0 = fmaT(gp, d0, cc);
+            const T xl1 = fmaT(gm, d1, cm), xr1 = fmaT(gp, d1, cm);
+            const T e0 = xl0 - xl1, e1 = xr0 - xr1;
+            const T q0 = fmaT(gm, e0, xl1), q1 = fmaT(gp, e0, xl1);
+            const T q2 = fmaT(gm, e1, xr1), q3 = fmaT(gp, e1, xr1);
+            S[0] = fmaT(q0, q0, S[0]);
+            S[1] = fmaT(q1, q1, S[1]);
+            S[2] = fmaT(q2, q2, S[2]);
+            S[3] = fmaT(q3, q3, S[3]);
+        }
+        T tq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tq[i] = fmaT(k.c1, S[i], (T)-1);
+        // pass 2: df/deta_i at the Gauss points, scatter, node row r-1 (stored after
+        // the loop, so that the fields' chains share one block for the scheduler)
+        T vo[P];
+#pragma unroll
+        for (int f = 0; f < P; ++f) {
+            {
+                const T cc = cur[f], cm = c_m1[f];
+                const T d0 = from_right(cc) - cc, d1 = from_right(cm) - cm;
+                const T xl0 = fmaT(gm, d0, cc), xr0 = fmaT(gp, d0, cc);
+                const T xl1 = fmaT(gm, d1, cm), xr1 = fmaT(gp, d1, cm);
+                const T e0 = xl0 - xl1, e1 = xr0 - xr1;
+                const T q0 = fmaT(gm, e0, xl1), q1 = fmaT(gp, e0, xl1);
+                const T q2 = fmaT(gm, e1, xr1), q3 = fmaT(gp, e1, xr1);
+                // left column: points 0 (nearer row r-1) and 1; right column: 2 and 3
+                const T F0 = q0 * fmaT(q0 * q0, k.c3, tq[0]), F1 = q1 * fmaT(q1 * q1, k.c3, tq[1]);
+                const T F2 = q2 * fmaT(q2 * q2, k.c3, tq[2]), F3 = q3 * fmaT(q3 * q3, k.c3, tq[3]);
+                const T dL = F0 - F1, dR = F2 - F3;
+                const T gdL = fmaT(gp, dL, F1), guL = fmaT(gm, dL, F1);
+                const T gdR = fmaT(gp, dR, F3), guR = fmaT(gm, dR, F3);
+                const T HL = gu_l[f] + gdL, HR = gu_r[f] + gdR;  // node row r-1 complete
+                const T dH = HL - HR;
+                const T pl = fmaT(gp, dH, HR), pr = fmaT(gm, dH, HR);
+                const T Nn = pl + from_left(pr);
+                const T s3 = from_left(cc) + cc + from_right(cc);
+                const T box = s3_m2[f] + s3_m1[f] + s3;
+                const T lap = fmaT((T)9, cm, -box);
+                vo[f] = fmaT(-k.A, Nn, fmaT(-k.B, lap, cm));
+                s3_m2[f] = s3_m1[f];
+                s3_m1[f] = s3;
+                gu_l[f] = guL;
+                gu_r[f] = guR;
+                c_m1[f] = cc;
+                cur[f] = bload<T>(rin, vx, f * fbytes + rn * rowb);  // next row in flight
+            }
+        }
+        if (t >= 2 && out_lane) {
+            const int ro = (y0 - 2 + t) * rowb;
+#pragma unroll
+            for (int f = 0; f < P; ++f) bstore(vo[f], rout, vx, f * fbytes + ro);
+        }
     }
 }
 
@@ -343,6 +463,75 @@ void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma
                                               (T)0);
 }
 
+// one launch of k_gg_stream2d<T, P, MIRROR>: chunks sized so that strips x chunks
+// just fills the waves the kernel's occupancy keeps resident (at least 8 rows each)
+template <typename T, int P, bool MIRROR>
+void gg_stream_launch(const Geom& g, const GGCoef<T>& k, const T* in, T* out, int cus, hipStream_t s)
+{
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_gg_stream2d<T, P, MIRROR>, 256, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            b = 2;
+        }
+        return b < 1 ? 1 : b;
+    }();
+    const int nx = g.n[0], ny = g.n[1];
+    const int nstrips = (nx + WAVE - 3) / (WAVE - 2);
+    const long long resident = 4ll * per_cu * (cus > 0 ? cus : 256);  // waves: 4 per block
+    long long nch = std::max<long long>(1, resident / nstrips);
+    nch = std::min<long long>(nch, std::max(1, ny / 8));
+    const int nchunks = (int)nch;
+    const int nwaves = nstrips * nchunks;
+    const int fbytes = (int)(g.N * sizeof(T));
+    const unsigned bytes = (unsigned)((double)P * g.N * sizeof(T));
+    k_gg_stream2d<T, P, MIRROR><<<(nwaves + 3) / 4, 256, 0, s>>>(in, out, nx, ny, nstrips, nwaves, nchunks,
+                                                                  fbytes, bytes, k);
+}
+
+// The streamed explicit step when it applies (2-D, every field addressable with
+// 32-bit offsets, P one of the instantiated field counts: 1-6 and 8 and, in FP32,
+// 10, 12, 16, 20 -- larger counts would spill registers); returns false (nothing
+// launched) otherwise.
+template <typename T>
+bool launch_gg_stream2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
+                        T* out, int cus, hipStream_t s)
+{
+    if (g.dim != 2 || P < 1 || tune_gg_stream() == 1) return false;
+    if ((double)P * (double)g.N * sizeof(T) >= 2147483647.0) return false;
+    const double m = g.h * g.h, detJ = 0.25 * g.h * g.h;
+    const GGCoef<T> k{(T)(dt * L * detJ / m), (T)(dt * L * kappa / (3.0 * m)), (T)(1.0 - 2.0 * gamma),
+                      (T)(2.0 * gamma)};
+    auto go = [&](auto pc) {
+        constexpr int PC = decltype(pc)::value;
+        if (g.bc)
+            gg_stream_launch<T, PC, true>(g, k, in, out, cus, s);
+        else
+            gg_stream_launch<T, PC, false>(g, k, in, out, cus, s);
+        return true;
+    };
+    switch (P) {
+        case 1: return go(std::integral_constant<int, 1>{});
+        case 2: return go(std::integral_constant<int, 2>{});
+        case 3: return go(std::integral_constant<int, 3>{});
+        case 4: return go(std::integral_constant<int, 4>{});
+        case 5: return go(std::integral_constant<int, 5>{});
+        case 6: return go(std::integral_constant<int, 6>{});
+        case 8: return go(std::integral_constant<int, 8>{});
+        default: break;
+    }
+    if constexpr (sizeof(T) == 4) {
+        switch (P) {
+            case 10: return go(std::integral_constant<int, 10>{});
+            case 12: return go(std::integral_constant<int, 12>{});
+            case 16: return go(std::integral_constant<int, 16>{});
+            case 20: return go(std::integral_constant<int, 20>{});
+            default: break;
+        }
+    }
+    return false;
+}
+
 size_t gg_jvp_lds_bytes(int P, size_t esize) { return ((size_t)2 * P * GS * GS + GB * 4) * esize; }
 
 template <typename T>
@@ -366,6 +555,8 @@ void launch_gg_energy2d(const Geom& g, int P, double kappa, double gamma, const 
 #define GG_INST(T)                                                                                         \
     template void launch_gg_tile2d<T>(const Geom&, int, double, double, double, double, const T*, T*, int,  \
                                       hipStream_t, const T*, double);                                       \
+    template bool launch_gg_stream2d<T>(const Geom&, int, double, double, double, double, const T*, T*, int, \
+                                        hipStream_t);                                                       \
     template void launch_gg_jvp2d<T>(const Geom&, int, double, double, double, double, const T*, const T*, \
                                      T*, hipStream_t);                                                      \
     template void launch_gg_energy2d<T>(const Geom&, int, double, double, const T*, double*, double*,       \

@@ -73,7 +73,8 @@ int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = auto
 int tune_el_mg();      // 1: plain CG for the elasticity solves
 int tune_stream2d_seam();
 int tune_nn_group();  // samples per forward group of the surrogate (0: automatic)
-int tune_gs_reorth();  // Gram-Schmidt re-orthogonalisation threshold (0: default)  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
+int tune_gs_reorth();  // Gram-Schmidt re-orthogonalisation threshold (0: default)
+int tune_gg_stream();  // 1: grain steps on the tile kernel  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
 
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel
@@ -84,6 +85,12 @@ size_t gg_tile_lds_bytes(int P, size_t esize);
 template <typename T>
 void launch_gg_tile2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
                       T* out, int mode, hipStream_t s, const T* old = nullptr, double inv_dt = 0.0);
+// one explicit step streamed row by row (k_gg_stream2d) when it applies: 2-D, P in
+// 1-6, 8 (and 10, 12, 16, 20 in FP32), P N elements addressable with 32-bit offsets, not
+// switched off by PF_TUNE_GG_STREAM; false (nothing launched) otherwise
+template <typename T>
+bool launch_gg_stream2d(const Geom& g, int P, double L, double kappa, double gamma, double dt, const T* in,
+                        T* out, int cus, hipStream_t s);
 // Jv = dR/dU v of the backward-Euler residual (symmetric); LDS bytes per block
 size_t gg_jvp_lds_bytes(int P, size_t esize);
 template <typename T>

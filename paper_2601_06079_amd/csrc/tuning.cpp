@@ -17,6 +17,7 @@ std::atomic<int> g_el_mg{0};
 std::atomic<int> g_seam{0};
 std::atomic<int> g_nn_group{0};
 std::atomic<int> g_gs_reorth{0};
+std::atomic<int> g_gg_stream{0};
 }  // namespace
 
 int stream2d_fuse(const pf_problem* p)
@@ -70,6 +71,7 @@ int tune_el_mg() { return pfapi::g_el_mg.load(); }
 int tune_stream2d_seam() { return pfapi::g_seam.load(); }
 int tune_nn_group() { return pfapi::g_nn_group.load(); }
 int tune_gs_reorth() { return pfapi::g_gs_reorth.load(); }
+int tune_gg_stream() { return pfapi::g_gg_stream.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -95,6 +97,8 @@ int pf_tune_set(int key, int value)
         g_nn_group.store(value);
     else if (key == PF_TUNE_GS_REORTH)
         g_gs_reorth.store(value);
+    else if (key == PF_TUNE_GG_STREAM)
+        g_gg_stream.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -133,6 +137,8 @@ int pf_tune_get(int key, int* value)
         *value = g_nn_group.load();
     else if (key == PF_TUNE_GS_REORTH)
         *value = g_gs_reorth.load();
+    else if (key == PF_TUNE_GG_STREAM)
+        *value = g_gg_stream.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
