@@ -132,6 +132,25 @@ def test_tuning_roundtrip(L):
     assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, 0) == A.PF_OK
     assert L.pf_tune_set(A.TUNE_STREAM2D_ROWS, -3) == A.PF_EINVAL
     assert L.pf_tune_set(77, 1) == A.PF_EINVAL
+    # every declared key round-trips and resets to its default (0)
+    for key in (A.TUNE_STREAM2D_DEPTH, A.TUNE_STREAM2D_FUSE, A.TUNE_JVP3D_PLANES, A.TUNE_STREAM2D_SEAM,
+                A.TUNE_NN_GROUP, A.TUNE_GS_REORTH, A.TUNE_GG_STREAM):
+        assert L.pf_tune_set(key, 3) == A.PF_OK
+        assert L.pf_tune_get(key, ct.byref(v)) == A.PF_OK and v.value == 3
+        assert L.pf_tune_set(key, 0) == A.PF_OK
+
+
+def test_launch_shape_defaults(L, C):
+    """The default fused plan of the 2048^2 Cahn-Hilliard benchmark: three steps per
+    launch, chunks for about four waves per SIMD (host-only context: 256 CUs)."""
+    p = A.pf_problem(2, A.PERIODIC, A.CAHN_HILLIARD, A.F_01, A.F32, 0, (ct.c_int64 * 3)(2048, 2048, 1),
+                     1.0, 1.0, 2.0, 1.0, 0.0, 1, 0, 1.5)
+    ks, ty, dp = ct.c_int(), ct.c_int(), ct.c_int()
+    assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
+    assert (ks.value, ty.value, dp.value) == (3, 21, 4)
+    p.model = A.ALLEN_CAHN
+    assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
+    assert ks.value == 2
 
 
 def test_noflux_problem_accepted(L, C):
