@@ -24,10 +24,13 @@ int stream2d_fuse(const pf_problem* p)
 {
     const int ov = g_fuse_override.load();
     if (ov > 0) return std::min(ov, 4);
-    // Measured on MI355X with the seam-sharing kernel: Cahn-Hilliard is fastest with
-    // three fused steps at 2048^2 to 8192^2 (7.7 against 8.1 us/step for two at 2048^2;
-    // two lose 10% at 8192^2); Allen-Cahn keeps two.
-    return p->model == PF_CAHN_HILLIARD ? 3 : 2;
+    // Measured on MI355X: four fused steps are fastest for Allen-Cahn from 128^2 to
+    // 2048^2 (128^2 FP64: 1.9 against 2.4 us/step for two; 2048^2: 5.8 against 6.8) and
+    // for Cahn-Hilliard below 2048^2, where launches dominate; at 2048^2 and above
+    // Cahn-Hilliard on the seam-sharing kernel is fastest with three or four (7.7
+    // us/step at 2048^2; two: 8.1, and 10% slower than three at 8192^2).
+    if (p->model == PF_CAHN_HILLIARD && p->n[0] * p->n[1] >= (1ll << 22)) return 3;
+    return 4;
 }
 
 int stream2d_rows(const pf_problem* p, int ks, int cus)
@@ -48,6 +51,9 @@ int stream2d_rows(const pf_problem* p, int ks, int cus)
     // light on registers)
     const long long waves = p->model == PF_COUPLED ? 6 : 4;
     long long nch = std::max<long long>(1, waves * S / strips);
+    // periodic fused launches run on the seam-sharing kernel, which rounds the chunks
+    // up to whole workgroups of 4: round down here so that the total stays in one round
+    if (!p->bc && ks >= 2 && p->model != PF_COUPLED) nch = std::max<long long>(4, nch / 4 * 4);
     nch = std::min(nch, std::max<long long>(1, ny / 8));
     long long ty = (ny + nch - 1) / nch;
     const long long tmax = ks == 1 ? 32 : 48;

@@ -142,15 +142,16 @@ def test_tuning_roundtrip(L):
 
 def test_launch_shape_defaults(L, C):
     """The default fused plan of the 2048^2 Cahn-Hilliard benchmark: three steps per
-    launch, chunks for about four waves per SIMD (host-only context: 256 CUs)."""
+    launch, chunks for just under four waves per SIMD in whole workgroups of four
+    (host-only context: 256 CUs)."""
     p = A.pf_problem(2, A.PERIODIC, A.CAHN_HILLIARD, A.F_01, A.F32, 0, (ct.c_int64 * 3)(2048, 2048, 1),
                      1.0, 1.0, 2.0, 1.0, 0.0, 1, 0, 1.5)
     ks, ty, dp = ct.c_int(), ct.c_int(), ct.c_int()
     assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
     assert (ks.value, ty.value, dp.value) == (3, 21, 4)
-    p.model = A.ALLEN_CAHN
+    p.model = A.ALLEN_CAHN  # Allen-Cahn: four steps, 37 strips x 108 chunks of 19 rows
     assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
-    assert ks.value == 2
+    assert (ks.value, ty.value) == (4, 19)
 
 
 def test_noflux_problem_accepted(L, C):
