@@ -178,7 +178,8 @@ int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
  * choice).  Used by the autotuner; results never depend on them, except that on
  * no-flux grids the steps fused per launch change boundary-adjacent values in
  * the last bits (a fused stage evaluates the reflected ghost rows).
- *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel;
+ *   PF_TUNE_STREAM2D_ROWS:  rows per wavefront of the fused 2-D explicit kernel and of
+ *                           the row-streaming 2-D Jacobian product;
  *   PF_TUNE_STREAM2D_DEPTH: rows it keeps in flight per wavefront (<=4, <=8, else 16);
  *   PF_TUNE_STREAM2D_FUSE:  explicit steps fused per launch by temporal blocking (1..4);
  *   PF_TUNE_JVP3D_PLANES:   z-planes per block of the 3-D Jacobian product;
@@ -193,6 +194,10 @@ int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
  *                           of ||w||^2 (1: never, 2001: always); 0: 1/10 (default);
  *   PF_TUNE_GG_STREAM:      1 = explicit grain-growth steps on the LDS tile kernel; 0 =
  *                           the row-streaming kernel where it applies (default);
+ *   PF_TUNE_JVP2D_STREAM:   1 = 2-D Jacobian products (pf_jvp, the Newton Krylov
+ *                           solves) on the node-centric kernel; 0 = the row-streaming
+ *                           kernel where it applies (default: Gauss quadrature,
+ *                           lumped mass, Allen-Cahn and Cahn-Hilliard);
  *   PF_TUNE_EL_MG:          1 = plain CG for the elasticity solves (no multigrid);
  *                           2 = multigrid with every level launched separately;
  *                           v >= 3 = the multigrid's coarse grids of at most v
@@ -200,7 +205,8 @@ int pf_fma_probe(pf_ctx* ctx, int blocks, int iters, float* out, void* stream);
  *                           none in 3-D). */
 enum { PF_TUNE_STREAM2D_ROWS = 0, PF_TUNE_STREAM2D_DEPTH = 1, PF_TUNE_STREAM2D_FUSE = 2,
        PF_TUNE_JVP3D_PLANES = 3, PF_TUNE_EL_PLANES = 4, PF_TUNE_EL_MG = 5, PF_TUNE_STREAM2D_SEAM = 6,
-       PF_TUNE_NN_GROUP = 7, PF_TUNE_GS_REORTH = 8, PF_TUNE_GG_STREAM = 9 };
+       PF_TUNE_NN_GROUP = 7, PF_TUNE_GS_REORTH = 8, PF_TUNE_GG_STREAM = 9,
+       PF_TUNE_JVP2D_STREAM = 10 };
 int pf_tune_set(int key, int value);
 int pf_tune_get(int key, int* value);
 /* The launch shape pf_step_explicit uses for p (2-D) on the context's device:

@@ -30,6 +30,7 @@ TUNE_STREAM2D_SEAM = 6
 TUNE_NN_GROUP = 7
 TUNE_GS_REORTH = 8
 TUNE_GG_STREAM = 9
+TUNE_JVP2D_STREAM = 10
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 VJP_RESIDUAL, VJP_EXPLICIT_STEP, VJP_NEWTON_STEP = 0, 1, 2
 VJP_BEGIN, VJP_END = 1, 2  # flags of pf_vjp_explicit_batched

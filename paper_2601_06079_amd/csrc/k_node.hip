@@ -358,6 +358,9 @@ void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, dou
         launch_jvp3d<T>(g, model, f, kappa, mob, inv_dt, U, v, Jv, s, trans);
         return;
     }
+    // Allen-Cahn's Jacobian is symmetric, so its transpose product is the product
+    if (!acc && (model == 0 || !trans) && launch_jvp2d_stream<T>(g, model, f, kappa, mob, inv_dt, U, v, Jv, s))
+        return;
     const double detJ = std::pow(0.5 * g.h, g.dim), m = std::pow(g.h, g.dim);
     Lin<T> F{(T)f.b0, (T)f.b1, (T)f.b2};
 #define JVP_L(MODEL, TR, AC)                                                                    \

@@ -71,10 +71,18 @@ void launch_jvp(const Geom& g, int model, const FreeEnergy& f, double kappa, dou
 int tune_jvp3d_planes();
 int tune_el_planes();  // z-planes per wave of the elasticity operator (0 = automatic)
 int tune_el_mg();      // 1: plain CG for the elasticity solves
-int tune_stream2d_seam();
-int tune_nn_group();  // samples per forward group of the surrogate (0: automatic)
-int tune_gs_reorth();  // Gram-Schmidt re-orthogonalisation threshold (0: default)
-int tune_gg_stream();  // 1: grain steps on the tile kernel  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
+int tune_stream2d_seam();  // 1: fused 2-D launches recompute chunk seams (no LDS sharing)
+int tune_nn_group();       // samples per forward group of the surrogate (0: automatic)
+int tune_gs_reorth();      // Gram-Schmidt re-orthogonalisation threshold (0: default)
+int tune_gg_stream();      // 1: grain steps on the tile kernel
+int tune_jvp2d_stream();   // 1: 2-D Jacobian products on the node-centric kernel
+int tune_stream2d_rows();  // rows per wave of the 2-D streaming kernels (0: automatic)
+// Row-streaming 2-D Jacobian product (k_jvp2d.hip): Gauss quadrature, lumped
+// mass, periodic or no-flux; the non-transposed product, which for Allen-Cahn is
+// also its transpose.  Returns false (nothing launched) where it does not apply.
+template <typename T>
+bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
+                         double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s);
 
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel

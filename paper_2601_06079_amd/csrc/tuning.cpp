@@ -18,6 +18,7 @@ std::atomic<int> g_seam{0};
 std::atomic<int> g_nn_group{0};
 std::atomic<int> g_gs_reorth{0};
 std::atomic<int> g_gg_stream{0};
+std::atomic<int> g_jvp2d_stream{0};
 }  // namespace
 
 int stream2d_fuse(const pf_problem* p)
@@ -78,6 +79,8 @@ int tune_stream2d_seam() { return pfapi::g_seam.load(); }
 int tune_nn_group() { return pfapi::g_nn_group.load(); }
 int tune_gs_reorth() { return pfapi::g_gs_reorth.load(); }
 int tune_gg_stream() { return pfapi::g_gg_stream.load(); }
+int tune_jvp2d_stream() { return pfapi::g_jvp2d_stream.load(); }
+int tune_stream2d_rows() { return pfapi::g_rows_override.load(); }
 }  // namespace pfk
 
 using namespace pfapi;
@@ -105,6 +108,8 @@ int pf_tune_set(int key, int value)
         g_gs_reorth.store(value);
     else if (key == PF_TUNE_GG_STREAM)
         g_gg_stream.store(value);
+    else if (key == PF_TUNE_JVP2D_STREAM)
+        g_jvp2d_stream.store(value);
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;
@@ -145,6 +150,8 @@ int pf_tune_get(int key, int* value)
         *value = g_gs_reorth.load();
     else if (key == PF_TUNE_GG_STREAM)
         *value = g_gg_stream.load();
+    else if (key == PF_TUNE_JVP2D_STREAM)
+        *value = g_jvp2d_stream.load();
     else
         return fail(PF_EINVAL, "unknown tuning key %d", key);
     return PF_OK;

@@ -134,7 +134,7 @@ def test_tuning_roundtrip(L):
     assert L.pf_tune_set(77, 1) == A.PF_EINVAL
     # every declared key round-trips and resets to its default (0)
     for key in (A.TUNE_STREAM2D_DEPTH, A.TUNE_STREAM2D_FUSE, A.TUNE_JVP3D_PLANES, A.TUNE_STREAM2D_SEAM,
-                A.TUNE_NN_GROUP, A.TUNE_GS_REORTH, A.TUNE_GG_STREAM):
+                A.TUNE_NN_GROUP, A.TUNE_GS_REORTH, A.TUNE_GG_STREAM, A.TUNE_JVP2D_STREAM):
         assert L.pf_tune_set(key, 3) == A.PF_OK
         assert L.pf_tune_get(key, ct.byref(v)) == A.PF_OK and v.value == 3
         assert L.pf_tune_set(key, 0) == A.PF_OK

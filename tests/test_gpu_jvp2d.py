@@ -1,0 +1,80 @@
+"""The row-streaming 2-D Jacobian product (Eq. 14 linearised, Sec. 2.3) against the
+FP64 oracle, element by element: one and several strips (62 output columns) and
+chunks with ragged tails, periodic and no-flux grids, both models, both
+precisions; the node-centric kernel gives the same product to rounding; and the
+benchmark's full 2048^2 no-flux shape."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2601_06079_amd import _abi as A
+from paper_2601_06079_amd import inputs as I
+from paper_2601_06079_amd import solver as S
+from tests.gpu_util import announce, dev, host, pair, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+TOL = {F32: 1e-5, F64: 1e-12}
+# 1 strip with lanes past the grid, exactly one strip (62), several strips with a
+# ragged last one; chunks of 8 rows and more with a ragged last chunk
+SHAPES = [(2, 2), (3, 5), (62, 9), (63, 17), (130, 97), (61, 200), (517, 300)]
+
+
+def _state(o, seed):
+    c = I.uniform_field(o.n, 0.1, 0.9, seed=seed)
+    if o.model == O.CH:
+        return np.concatenate([c, I.uniform_field(o.n, -0.5, 0.5, seed=seed + 1)])
+    return c
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+@pytest.mark.parametrize("n", SHAPES)
+def test_stream_jvp_matches_oracle(n, model, bc, dtype):
+    announce("jvp2d stream", n, model, bc, dtype)
+    fe = O.F_01 if model == O.CH else O.F_SYM
+    g, o = pair(n, model, fe, dtype, h=0.9, W=1.2, kappa=1.7, mob=0.8, bc=bc)
+    U = rounded(_state(o, 21), dtype)
+    v = rounded(np.random.default_rng(22).standard_normal(o.ndof), dtype)
+    for inv_dt in (0.0, 3.0):
+        Jv = host(S.jvp(g, inv_dt, dev(U, dtype), dev(v, dtype)))
+        assert rel_l2(Jv, O.jvp(o, inv_dt, U, v)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+def test_stream_and_node_kernels_agree(model, bc, dtype):
+    announce("jvp2d stream vs node", model, bc, dtype)
+    g, o = pair((300, 257), model, O.F_01, dtype, h=1.0, W=1.0, kappa=2.0, mob=1.3, bc=bc)
+    U = dev(rounded(_state(o, 31), dtype), dtype)
+    v = dev(rounded(np.random.default_rng(32).standard_normal(o.ndof), dtype), dtype)
+    old = S.tune_get(A.TUNE_JVP2D_STREAM)
+    try:
+        S.tune_set(A.TUNE_JVP2D_STREAM, 1)
+        ref = host(S.jvp(g, 2.0, U, v))
+        S.tune_set(A.TUNE_JVP2D_STREAM, 0)
+        got = host(S.jvp(g, 2.0, U, v))
+    finally:
+        S.tune_set(A.TUNE_JVP2D_STREAM, old)
+    assert rel_l2(got, ref) < (1e-6 if dtype == F32 else 1e-14)
+
+
+def test_stream_jvp_full_size_2048_noflux():
+    """The implicit Allen-Cahn benchmark's shape: 2048^2 nodes on [0, 100]^2, no-flux,
+    at the backward-Euler time term of dt = 0.05, against the oracle at every node."""
+    announce("jvp2d stream 2048^2 noflux")
+    n = (2048, 2048)
+    g, o = pair(n, O.AC, O.F_01, F32, h=100.0 / 2047, W=1.0, kappa=2.0, mob=1.0, bc=O.NOFLUX)
+    U = rounded(I.uniform_field(n, -1.0, 1.0, seed=41), F32)
+    v = rounded(np.random.default_rng(42).standard_normal(o.ndof), F32)
+    Jv = host(S.jvp(g, 20.0, dev(U, F32), dev(v, F32)))
+    ref = O.jvp(o, 20.0, U, v)
+    assert rel_l2(Jv, ref) < TOL[F32]
+    # the boundary rows (their masses are halved and quartered) node by node
+    J2, R2 = Jv.reshape(2048, 2048), ref.reshape(2048, 2048)
+    for edge in (J2[0] - R2[0], J2[-1] - R2[-1], J2[:, 0] - R2[:, 0], J2[:, -1] - R2[:, -1]):
+        assert np.max(np.abs(edge)) <= 1e-5 * np.max(np.abs(ref))
