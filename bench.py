@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--nn-backward", type=int, default=0, metavar="ITERS",
                     help="only time ITERS surrogate training iterations (forward + backward + "
                          "Adam) on 16 x 512^2 and print their record")
+    ap.add_argument("--nn-forward", type=int, default=0, metavar="ITERS",
+                    help="only time ITERS surrogate inference passes on 16 x 512^2 and print their record")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the hbm / adjoint / surrogate records (the step alone)")
     ap.add_argument("--traffic", default=None,
@@ -406,6 +408,25 @@ def nn_train_record(stream, iters=10, n=512, Bn=16):
     return {"workload": f"surrogate training iteration, {Bn} x {n}^2", "iters": iters, "ms_per_iter": ms,
             "samples_per_s": Bn / (ms * 1e-3), "tflops": flop / (ms * 1e-3) / 1e12,
             "frac_of_bf16_peak": flop / (ms * 1e-3) / 2.5e15}
+
+
+def nn_forward_record(stream, iters=20, n=512, Bn=16):
+    """Surrogate inference (pf_nn_forward: c, M, kappa -> c_hat) on Bn random n^2 fields:
+    time per pass and the BF16 rate of the network's 39 168 flop per pixel."""
+    import numpy as np
+    import torch
+
+    from paper_2601_06079_amd import nn as NN
+    r = np.random.default_rng(0)
+    c = torch.as_tensor((0.5 + 0.1 * r.standard_normal((Bn, n, n))).astype(np.float32), device="cuda")
+    M = torch.as_tensor(r.uniform(0.5, 2, Bn).astype(np.float32), device="cuda")
+    k = torch.as_tensor(r.uniform(0.5, 2, Bn).astype(np.float32), device="cuda")
+    model = NN.Surrogate(seed=0)
+    model.forward(c, M, k)
+    ms = min(_time_ms(lambda: [model.forward(c, M, k) for _ in range(iters)], stream) / iters for _ in range(3))
+    flop = 39168.0 * Bn * n * n
+    return {"workload": f"surrogate inference, {Bn} x {n}^2", "iters": iters, "ms_per_forward": ms,
+            "tflops": flop / (ms * 1e-3) / 1e12, "frac_of_bf16_peak": flop / (ms * 1e-3) / 2.5e15}
 
 
 def ac128_record(stream, steps=1000):
@@ -858,7 +879,7 @@ def implicit_record(steps, stream):
 def main():
     args = parse()
     if (args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby or args.grain
-            or args.nn_backward):
+            or args.nn_backward or args.nn_forward):
         import torch
         stream = torch.cuda.current_stream()
         if args.grain:
@@ -885,6 +906,8 @@ def main():
             print(json.dumps(coupled_implicit_record(stream)), flush=True)
         if args.nn_backward:
             print(json.dumps(nn_train_record(stream, iters=args.nn_backward)), flush=True)
+        if args.nn_forward:
+            print(json.dumps(nn_forward_record(stream, iters=args.nn_forward)), flush=True)
         if args.surrogate_gain:
             from paper_2601_06079_amd import nn as NN
             rec = NN.gain_experiment(train_iters=args.surrogate_gain,

@@ -21,7 +21,10 @@
 //     K = pixels; every block accumulates a fixed stride of pixel tiles in
 //     registers (split-K) and writes one FP32 partial; a second kernel sums the
 //     partials in block order (bitwise reproducible).
-// The 32 -> 1 output layer (2.9% of the flops) runs on the VALU.
+// The 32 -> 1 output layer (2.9% of the flops) runs on the VALU in training.
+// Inference fuses: the first layer into the second's tiles (MODE 4: a1 never
+// reaches memory), and the output layer's channel sums into the third's epilogue
+// (MODE 3: 9 FP32 tap planes, then a gather, k_out_taps).
 //
 // MFMA operand layout (32x32x16): lane l supplies A[l % 32][8 (l / 32) + j] and
 // B[8 (l / 32) + j][l % 32] for j = 0..7, and receives
@@ -57,6 +60,16 @@ __device__ __forceinline__ u16 bf16_bits(float f)
 __device__ __forceinline__ float bf16_val(u16 b) { return __uint_as_float((unsigned)b << 16); }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// Row of a tile's halo, i in [-2, n + 9]: periodic for i <= n + 1; rows further out
+// (only when n is below the tile's reach) feed only outputs past the grid, which are
+// never stored, so they are clamped to the last row (every read stays in the sample).
+__device__ __forceinline__ int halo_row(int i, int n)
+{
+    int r = i < 0 ? i + n : i;
+    r = r < 0 ? r + n : r;  // n = 1
+    r = r >= n ? r - n : r;
+    return r < n ? r : n - 1;
+}
 
 // LDS tile: (ROWS + 2) rows x (TW + 2) pixels, CIN channels, pixel stride padded by
 // 16 bytes: a stride of 4k banks with k odd (k = 5 for 32 channels, 3 for 16) puts
@@ -77,7 +90,7 @@ __device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, i
     for (int t = threadIdx.x; t < TOTAL; t += NBLK) {
         const int ch = t % CHUNKS, pix = t / CHUNKS;
         const int px = pix % (TW + 2), ry = pix / (TW + 2);
-        const int gy = wrapi(y0 - 1 + ry, H), gx = wrapi(x0 - 1 + px, W);
+        const int gy = halo_row(y0 - 1 + ry, H), gx = wrapi(x0 - 1 + px, W);
         const uint4 v = *reinterpret_cast<const uint4*>(
             act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
         *reinterpret_cast<uint4*>(lds + (ry * (TW + 2) + px) * Tile<CIN, ROWS>::PSTRIDE + ch * 16) = v;
@@ -86,18 +99,34 @@ __device__ __forceinline__ void stage_tile(const u16* __restrict__ act, int b, i
 
 // MODE 0: out = bf16(relu(acc + bias))          (forward, hidden layers)
 // MODE 1: out = bf16(acc * (mask[p][co] > 0))    (dgrad: relu mask of the layer input)
-// MODE 2: as MODE 0 for the first layer, its input channels (bf16 c, M, kappa, then
-//         zeros) formed while staging instead of read from a packed a0
+// MODE 4: the second layer with the first computed while staging (forward only):
+//         the tile reads the c plane only, and forms its 6 x 34 halo of
+//         a1 = bf16(relu(sum_tap W1[tap][0] bf16(c(p + tap)) + beff)) on the matrix
+//         cores, one MFMA per 32 pixels (A = the 9 taps of c, zero-padded to 16).
+//         M and kappa are constant over a sample, so their channels reduce to the
+//         bias beff = b1 + bf16(M) sum_tap W1[tap][1] + bf16(kappa) sum_tap W1[tap][2];
+//         a1 never reaches memory
+// MODE 3: as MODE 0 for the last hidden layer, followed by the output layer's
+//         channel contraction: instead of a3 it stores the 9 planes
+//         P[tap][p] = sum_ci W4[tap][ci] a3[p][ci] (FP32), which a gather sums over
+//         the taps' neighbours (forward only; training keeps a3 for the gradients)
 // wfrag: B fragments [9][CIN/16][64 lanes][8] bf16 for this layer/use
 // Persistent: the grid holds the resident blocks, each loads its weight fragments
 // into registers once (LDS then carries only the A operands) and walks the tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
 // issued into registers before the current tile's MFMAs, so staging overlaps
 // compute.  Every output is the same MFMA chain as with one tile per block.
-struct InPlanes {
+struct InPlanes {  // MODE 4 only
     const float* c;      // [B][H][W]
     const float* M;      // [B]
     const float* kappa;  // [B]
+    const float* w1;     // FP32 W1 [9][3][32]
+    const float* b1;     // FP32 b1 [32]
+};
+struct TapPlanes {
+    const u16* w4;    // bf16 W4 [9][32]
+    float* P;         // [9][B][H][W]
+    long long plane;  // B H W
 };
 
 template <int CIN, int MODE>
@@ -106,9 +135,9 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ mask,
                                                     u16* __restrict__ out, int B, int H, int W, int ntiles,
-                                                    InPlanes ip)
+                                                    InPlanes ip, TapPlanes tp)
 {
-    static_assert(MODE != 2 || CIN == 16, "the planes feed the 16-channel first layer");
+    static_assert(MODE != 4 || CIN == 32, "the fused first layer feeds the second");
     constexpr int KS = CIN / 16;
     constexpr int PS = Tile<CIN, CR>::PSTRIDE;
     constexpr int CHUNKS = CIN * 2 / 16;  // 16-byte chunks per pixel
@@ -127,6 +156,38 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
     const int m = lane & 31, kh = lane >> 5;
     const int co = m;
     const float bco = MODE != 1 ? bias[co] : 0.0f;
+    // MODE 3: W4 as the A operand of the contraction, A[tap][k = ci] = W4[tap][16 ks + k]
+    // (rows 9..31 zero), kept in LDS (rows of 40 bf16: conflict-free 16-byte reads);
+    // lane l reads tap l % 32, channels 16 ks + 8 (l / 32) + j
+    constexpr int W4S = 40;
+    __shared__ __align__(16) u16 sw4[MODE == 3 ? 32 * W4S : 1];
+    if constexpr (MODE == 3) {
+        for (int i = threadIdx.x; i < 32 * 32; i += NBLK) {
+            const int tap = i / 32, ci = i % 32;
+            sw4[tap * W4S + ci] = tap < 9 ? tp.w4[tap * 32 + ci] : (u16)0;
+        }
+    }
+    // MODE 4: the first layer's B fragment (B[k = tap][co] = W1[tap][0][co], k < 9),
+    // the per-sample bias terms and the c patch (rows y0-2 .. y0+CR+1, pixels
+    // x0-2 .. x0+TW+1) in LDS as bf16
+    constexpr int CPW = TW + 4, CPN = (CR + 4) * CPW;  // 36 x 8 = 288 values
+    bf16x8 l1f = {};
+    float l1s1 = 0.0f, l1s2 = 0.0f, l1b = 0.0f;
+    float cs0 = 0.0f, cs1 = 0.0f;  // the next tile's c values (2 per thread)
+    __shared__ u16 cpt[MODE == 4 ? CPN : 1];
+    if constexpr (MODE == 4) {
+        static_assert(CPN <= 2 * NBLK, "two c values per thread");
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * kh + j;
+            l1f[j] = __builtin_bit_cast(__bf16, k < 9 ? bf16_bits(ip.w1[(k * 3) * 32 + co]) : (u16)0);
+        }
+        for (int tap = 0; tap < 9; ++tap) {
+            l1s1 += bf16_val(bf16_bits(ip.w1[(tap * 3 + 1) * 32 + co]));
+            l1s2 += bf16_val(bf16_bits(ip.w1[(tap * 3 + 2) * 32 + co]));
+        }
+        l1b = ip.b1[co];
+    }
     // the halo tile of rows y0-1 .. y0+CR, pixels x0-1 .. x0+TW (periodic) of a tile,
     // PER 16-byte chunks per thread (chunks past TOTAL load a valid dummy)
     uint4 s0, s1, s2, s3;
@@ -136,6 +197,17 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         const int tt_ = (T_);                                                                               \
         const int tx_ = tt_ % tiles_x, ty_ = (tt_ / tiles_x) % tiles_y, b_ = tt_ / (tiles_x * tiles_y);     \
         const int x0_ = tx_ * TW, y0_ = ty_ * CR;                                                           \
+        if (MODE == 4) {                                                                                    \
+            float* cdst_[2] = {&cs0, &cs1};                                                                 \
+            _Pragma("unroll") for (int q = 0; q < 2; ++q)                                                   \
+            {                                                                                               \
+                int i_ = threadIdx.x + q * NBLK;                                                            \
+                i_ = i_ < CPN ? i_ : CPN - 1;                                                               \
+                const int gy = halo_row(y0_ - 2 + i_ / CPW, H), gx = wrapi(x0_ - 2 + i_ % CPW, W);         \
+                *cdst_[q] = ip.c[((size_t)b_ * H + gy) * W + gx];                                           \
+            }                                                                                               \
+            break;                                                                                          \
+        }                                                                                                   \
         uint4* dst_[4] = {&s0, &s1, &s2, &s3};                                                              \
         _Pragma("unroll") for (int q = 0; q < PER; ++q)                                                     \
         {                                                                                                   \
@@ -143,25 +215,19 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
             c = c < TOTAL ? c : TOTAL - 1;                                                                  \
             const int ch = c % CHUNKS, pix = c / CHUNKS;                                                    \
             const int px = pix % (TW + 2), ry = pix / (TW + 2);                                             \
-            const int gy = wrapi(y0_ - 1 + ry, H), gx = wrapi(x0_ - 1 + px, W);                             \
+            const int gy = halo_row(y0_ - 1 + ry, H), gx = wrapi(x0_ - 1 + px, W);                          \
             const size_t gp_ = ((size_t)b_ * H + gy) * W + gx;                                              \
-            if (MODE == 2) {                                                                                \
-                uint4 v_ = make_uint4(0u, 0u, 0u, 0u);                                                      \
-                if (ch == 0) {                                                                              \
-                    v_.x = (unsigned)bf16_bits(ip.c[gp_]) | ((unsigned)bf16_bits(ip.M[b_]) << 16);          \
-                    v_.y = (unsigned)bf16_bits(ip.kappa[b_]);                                               \
-                }                                                                                           \
-                *dst_[q] = v_;                                                                              \
-            } else {                                                                                        \
-                *dst_[q] = *reinterpret_cast<const uint4*>(in + gp_ * CIN + ch * 8);                        \
-            }                                                                                               \
+            *dst_[q] = *reinterpret_cast<const uint4*>(in + gp_ * CIN + ch * 8);                            \
         }                                                                                                   \
     } while (0)
     int t = blockIdx.x;
     if (t < ntiles) PF_CONV_FETCH(t);
     for (; t < ntiles; t += gridDim.x) {
         __syncthreads();  // the previous tile's reads of the LDS tile are done
-        {
+        if constexpr (MODE == 4) {
+            cpt[threadIdx.x] = bf16_bits(cs0);
+            if (threadIdx.x + NBLK < CPN) cpt[threadIdx.x + NBLK] = bf16_bits(cs1);
+        } else {
             const uint4 src[4] = {s0, s1, s2, s3};
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
@@ -173,6 +239,37 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         if (t + (int)gridDim.x < ntiles) PF_CONV_FETCH(t + (int)gridDim.x);
         const int tx = t % tiles_x, ty = (t / tiles_x) % tiles_y, b = t / (tiles_x * tiles_y);
         const int x0 = tx * TW, y0 = ty * CR;
+        if constexpr (MODE == 4) {
+            // the first layer on the (CR+2) x (TW+2) = 204 halo pixels, 32 per MFMA:
+            // wave wv takes groups wv and wv + 4; tile pixel s = 34 ry + px sits at
+            // c patch rows ry .. ry+2, pixels px .. px+2
+            constexpr int NPX = (CR + 2) * (TW + 2);
+            const float beff = l1b + bf16_val(bf16_bits(ip.M[b])) * l1s1 + bf16_val(bf16_bits(ip.kappa[b])) * l1s2;
+#pragma unroll
+            for (int gq = 0; gq < 2; ++gq) {
+                const int grp = wv + 4 * gq;
+                if (32 * grp < NPX) {
+                    const int sp = min(32 * grp + m, NPX - 1);
+                    const int ry = sp / (TW + 2), px = sp % (TW + 2);
+                    bf16x8 a;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = 8 * kh + j;
+                        const u16 bits = k < 9 ? cpt[(ry + k / 3) * CPW + px + k % 3] : (u16)0;
+                        a[j] = __builtin_bit_cast(__bf16, bits);
+                    }
+                    f32x16 a1 = {};
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, l1f, a1, 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int s = 32 * grp + 8 * (i >> 2) + 4 * kh + (i & 3);
+                        if (s < NPX)
+                            *reinterpret_cast<u16*>(lds + s * PS + co * 2) = bf16_bits(fmaxf(a1[i] + beff, 0.0f));
+                    }
+                }
+            }
+            __syncthreads();
+        }
         static_assert(CR == 4, "one output row per wave");
         const int rt = wv;  // tile row of this wave's output row
         const int y = y0 + rt;
@@ -203,7 +300,25 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (y < H) {
+        if constexpr (MODE == 3) {
+            // P^T = W4 a3^T on the matrix cores: B[k = ci][n = pixel] is the wave's bf16
+            // a3 row read back from the transpose (pixel m, channels 16 ks + 8 kh ...);
+            // lane l then holds pixel l % 32, taps 4 (l / 32) + i (i < 4) and, for
+            // l < 32, tap 8 in accumulator 4
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ot + m * OST + kh * 16);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(ot + m * OST + 32 + kh * 16);
+            const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(sw4 + m * W4S + kh * 8);
+            const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sw4 + m * W4S + 16 + kh * 8);
+            f32x16 pacc = {};
+            pacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, a0, pacc, 0, 0, 0);
+            pacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, a1, pacc, 0, 0, 0);
+            if (y < H) {
+                float* dst = tp.P + ((size_t)b * H + y) * W + x0 + m;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dst[(size_t)(4 * kh + r) * tp.plane] = pacc[r];
+                if (kh == 0) dst[(size_t)8 * tp.plane] = pacc[4];
+            }
+        } else if (y < H) {
             const int p = lane >> 1, half = lane & 1;
             uint4 v0 = *reinterpret_cast<const uint4*>(ot + p * OST + half * 32);
             uint4 v1 = *reinterpret_cast<const uint4*>(ot + p * OST + half * 32 + 16);
@@ -437,6 +552,41 @@ __global__ __launch_bounds__(NBLK) void k_out_fwd(const u16* __restrict__ a3, co
         for (int q = 0; q < 4; ++q) sum = dot8(ap[q], sw[tap * 4 + q], sum);
     }
     d[((size_t)b * H + y) * W + x0 + m] = sum;
+}
+
+// Output layer from the tap planes of MODE 3: d[p] = b4 + sum_tap P[tap][p + tap]
+// (periodic neighbours, taps in order), and the per-sample partial sums of d that
+// k_sample_sum would form (same blocks, same reduction tree): part[b * nbs + blk].
+__global__ __launch_bounds__(NBLK) void k_out_taps(const float* __restrict__ P, long long plane,
+                                                   const float* __restrict__ params, NNOffsets off,
+                                                   float* __restrict__ d, double* __restrict__ part, int H,
+                                                   int W)
+{
+    const int HW = H * W, nbs = (HW + NBLK - 1) / NBLK;
+    const int b = blockIdx.x / nbs, blk = blockIdx.x % nbs;
+    const int i = blk * NBLK + threadIdx.x;
+    double v = 0.0;
+    if (i < HW) {
+        const int y = i / W, x = i % W;
+        const int ym = y == 0 ? H - 1 : y - 1, yp = y == H - 1 ? 0 : y + 1;
+        const int xm = x == 0 ? W - 1 : x - 1, xp = x == W - 1 ? 0 : x + 1;
+        const int rows[3] = {ym, y, yp}, cols[3] = {xm, x, xp};
+        const float* Pb = P + (size_t)b * HW;
+        float s = params[off.b4];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            s += Pb[(size_t)tap * plane + (size_t)rows[tap / 3] * W + cols[tap % 3]];
+        d[(size_t)b * HW + i] = s;
+        v = (double)s;
+    }
+    __shared__ double sh[NBLK];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = NBLK / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 // per-sample partial sums of x over blocks of NBLK pixels: part[b * nbs + blk]
@@ -788,24 +938,44 @@ void nn_conv(int layer, int mode, const u16* in, const u16* frag, const float* b
 {
     const int nt = nn_conv_blocks(B, H, W);
     auto grid = [&](int resident) { return (unsigned)std::max(1, std::min(nt, resident)); };
-    const InPlanes none{nullptr, nullptr, nullptr};
+    const InPlanes none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    const TapPlanes np{nullptr, nullptr, 0};
     if (layer == 1)
         k_conv_mfma<16, 0><<<grid(conv_resident_blocks<16, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt, none);
+                                                                               W, nt, none, np);
     else if (mode == 0)
         k_conv_mfma<32, 0><<<grid(conv_resident_blocks<32, 0>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt, none);
+                                                                               W, nt, none, np);
     else
         k_conv_mfma<32, 1><<<grid(conv_resident_blocks<32, 1>()), NBLK, 0, s>>>(in, frag, bias, mask, out, B, H,
-                                                                               W, nt, none);
+                                                                               W, nt, none, np);
 }
 
-void nn_conv1_planes(const float* c, const float* M, const float* kappa, const u16* frag, const float* bias,
-                     u16* out, int B, int H, int W, hipStream_t s)
+void nn_conv12_planes(const float* c, const float* M, const float* kappa, const float* w1, const float* b1,
+                      const u16* frag2, const float* bias2, u16* out, int B, int H, int W, hipStream_t s)
 {
     const int nt = nn_conv_blocks(B, H, W);
-    const unsigned g = (unsigned)std::max(1, std::min(nt, conv_resident_blocks<16, 2>()));
-    k_conv_mfma<16, 2><<<g, NBLK, 0, s>>>(nullptr, frag, bias, nullptr, out, B, H, W, nt, InPlanes{c, M, kappa});
+    const unsigned g = (unsigned)std::max(1, std::min(nt, conv_resident_blocks<32, 4>()));
+    k_conv_mfma<32, 4><<<g, NBLK, 0, s>>>(nullptr, frag2, bias2, nullptr, out, B, H, W, nt,
+                                          InPlanes{c, M, kappa, w1, b1}, TapPlanes{nullptr, nullptr, 0});
+}
+
+void nn_conv3_taps(const u16* in, const u16* frag, const float* bias, const u16* w4, float* P, int B, int H, int W,
+                   hipStream_t s)
+{
+    const int nt = nn_conv_blocks(B, H, W);
+    const unsigned g = (unsigned)std::max(1, std::min(nt, conv_resident_blocks<32, 3>()));
+    k_conv_mfma<32, 3><<<g, NBLK, 0, s>>>(in, frag, bias, nullptr, nullptr, B, H, W, nt,
+                                          InPlanes{nullptr, nullptr, nullptr, nullptr, nullptr},
+                                          TapPlanes{w4, P, (long long)B * H * W});
+}
+
+void nn_out_taps(const float* P, const float* params, float* d, double* part, double* mean, int B, int H, int W,
+                 hipStream_t s)
+{
+    const int HW = H * W, nbs = (HW + NBLK - 1) / NBLK;
+    k_out_taps<<<(unsigned)(B * nbs), NBLK, 0, s>>>(P, (long long)B * HW, params, nn_offsets(), d, part, H, W);
+    k_sample_mean<<<B, NBLK, 0, s>>>(part, nbs, HW, mean);
 }
 
 void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb, int B, int H, int W,

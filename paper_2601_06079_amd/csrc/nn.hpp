@@ -27,10 +27,18 @@ void nn_pack_input(const float* c, const float* M, const float* kappa, unsigned 
 void nn_conv(int layer, int mode, const unsigned short* in, const unsigned short* frag,
              const float* bias, const unsigned short* mask, unsigned short* out, int B, int H, int W,
              hipStream_t s);
-// the first layer with its input channels formed from the c, M, kappa planes
-// (bitwise the packed a0 path; forward only, where a0 is not kept)
-void nn_conv1_planes(const float* c, const float* M, const float* kappa, const unsigned short* frag,
-                     const float* bias, unsigned short* out, int B, int H, int W, hipStream_t s);
+// the first two layers (forward) from the c, M, kappa planes, the first computed
+// inside the second's tiles (a1 is not stored); w1, b1: the FP32 W1, b1
+void nn_conv12_planes(const float* c, const float* M, const float* kappa, const float* w1, const float* b1,
+                      const unsigned short* frag2, const float* bias2, unsigned short* out, int B, int H,
+                      int W, hipStream_t s);
+// the last hidden layer (forward) followed by the output layer's channel contraction:
+// P[tap][p] = sum_ci W4[tap][ci] a3[p][ci] (FP32, 9 planes of B H W); a3 is not stored
+void nn_conv3_taps(const unsigned short* in, const unsigned short* frag, const float* bias,
+                   const unsigned short* w4, float* P, int B, int H, int W, hipStream_t s);
+// d = b4 + sum_tap P[tap][p + tap] and the per-sample means of d (part: B ceil(H W / 256))
+void nn_out_taps(const float* P, const float* params, float* d, double* part, double* mean, int B, int H,
+                 int W, hipStream_t s);
 // weight gradient partials of hidden layer `layer` (part: blocks x 9 x 32 x 32, partb: blocks x 32)
 void nn_wgrad(int layer, const unsigned short* ain, const unsigned short* g, float* part, float* partb,
               int B, int H, int W, hipStream_t s);

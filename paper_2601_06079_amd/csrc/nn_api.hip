@@ -62,25 +62,31 @@ int check_shape(int B, int H, int W)
     return PF_OK;
 }
 
-// the forward pass, leaving a1..a3 and d (and a0 if keep_a0) in the workspace
+// the forward pass (the weight fragments already prepared in L.frag, L.w4) into
+// chat; training (keep_a0) leaves a0..a3 and d in the workspace
 void forward(const float* params, int B, int H, int W, const float* c, const float* M,
-             const float* kappa, const float* target, NNWS& L, hipStream_t s, bool keep_a0)
+             const float* kappa, const float* target, float* chat, NNWS& L, hipStream_t s, bool keep_a0)
 {
     const pfk::NNOffsets o = pfk::nn_offsets();
     const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
     const int HW = H * W;
-    pfk::nn_prep_weights(params, L.frag, L.w4, s);
-    if (keep_a0) {  // the first layer's weight gradient reads a0
+    if (keep_a0) {  // training: the weight gradients read a0, a1, a2 and a3
         pfk::nn_pack_input(c, M, kappa, L.a0, B, HW, s);
         pfk::nn_conv(1, 0, L.a0, L.frag + fo.f1, params + o.b1, nullptr, L.a1, B, H, W, s);
+        pfk::nn_conv(2, 0, L.a1, L.frag + fo.f2, params + o.b2, nullptr, L.a2, B, H, W, s);
+        pfk::nn_conv(3, 0, L.a2, L.frag + fo.f3, params + o.b3, nullptr, L.a3, B, H, W, s);
+        pfk::nn_out_fwd(L.a3, L.w4, params, L.d, B, H, W, s);
+        pfk::nn_sample_mean(L.d, L.spart, L.mean, B, HW, s);
     } else {
-        pfk::nn_conv1_planes(c, M, kappa, L.frag + fo.f1, params + o.b1, L.a1, B, H, W, s);
+        // inference: the first layer runs inside the second's tiles (a1 is never
+        // stored), and the output layer's channel sums leave the third as 9 tap planes
+        pfk::nn_conv12_planes(c, M, kappa, params + o.w1, params + o.b1, L.frag + fo.f2, params + o.b2, L.a2, B,
+                              H, W, s);
+        float* P = reinterpret_cast<float*>(L.a3);  // 36 of a3's 64 bytes per pixel
+        pfk::nn_conv3_taps(L.a2, L.frag + fo.f3, params + o.b3, L.w4, P, B, H, W, s);
+        pfk::nn_out_taps(P, params, L.d, L.spart, L.mean, B, H, W, s);
     }
-    pfk::nn_conv(2, 0, L.a1, L.frag + fo.f2, params + o.b2, nullptr, L.a2, B, H, W, s);
-    pfk::nn_conv(3, 0, L.a2, L.frag + fo.f3, params + o.b3, nullptr, L.a3, B, H, W, s);
-    pfk::nn_out_fwd(L.a3, L.w4, params, L.d, B, H, W, s);
-    pfk::nn_sample_mean(L.d, L.spart, L.mean, B, HW, s);
-    pfk::nn_project(c, L.d, L.mean, target, L.chat, L.g, L.r2, B, HW, s);
+    pfk::nn_project(c, L.d, L.mean, target, chat, L.g, L.r2, B, HW, s);
 }
 
 }  // namespace
@@ -121,13 +127,12 @@ int pf_nn_forward(const float* params, int B, int H, int W, const float* c, cons
         int G = pfk::tune_nn_group();
         if (G <= 0) G = (int)std::max<long long>(1, (128ll << 20) / (HW * 64));
         G = std::min(G, B);
+        pfk::nn_prep_weights(params, L.frag, L.w4, s);
         for (int b0 = 0; b0 < B; b0 += G) {
             const int nb = std::min(G, B - b0);
             const long long o = (long long)b0 * HW;
             // c and chat are B x H x W; M and kappa hold one value per sample
-            forward(params, nb, H, W, c + o, M + b0, kappa + b0, nullptr, L, s, false);
-            if (hipMemcpyAsync(chat + o, L.chat, (size_t)nb * HW * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return check_launch("pf_nn_forward copy");
+            forward(params, nb, H, W, c + o, M + b0, kappa + b0, nullptr, chat + o, L, s, false);
         }
         return check_launch("pf_nn_forward");
     });
@@ -147,7 +152,8 @@ int pf_nn_backward(const float* params, int B, int H, int W, const float* c, con
         const pfk::NNOffsets o = pfk::nn_offsets();
         const pfk::NNFragOffsets fo = pfk::nn_frag_offsets();
         const int HW = H * W;
-        forward(params, B, H, W, c, M, kappa, target, L, s, true);
+        pfk::nn_prep_weights(params, L.frag, L.w4, s);
+        forward(params, B, H, W, c, M, kappa, target, L.chat, L, s, true);
         if (loss) pfk::nn_sample_mean(L.r2, L.spart, loss, B, HW, s);  // per-sample MSE
         // backward of the mass projection: g <- g - mean(g)
         pfk::nn_sample_mean(L.g, L.spart, L.mean2, B, HW, s);

@@ -79,7 +79,7 @@ def _exact_bound(p):
     return worst
 
 
-@pytest.mark.parametrize("shape", [(2, 8, 64), (1, 5, 32), (3, 4, 96), (1, 13, 160)])
+@pytest.mark.parametrize("shape", [(2, 8, 64), (1, 5, 32), (3, 4, 96), (1, 13, 160), (2, 1, 32), (3, 2, 64)])
 def test_forward_exact_dyadic(shape):
     """Exact arithmetic on both sides: the GPU forward equals the oracle's up to the
     final FP32 rounding of c_hat (pins every tap, channel and tile index)."""
@@ -112,7 +112,7 @@ def test_forward_exact_dyadic_full_size():
     assert np.max(np.abs((got - c) - (ref - c))) <= 4e-7 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("shape", [(2, 8, 32), (1, 13, 64), (3, 4, 96), (2, 64, 128)])
+@pytest.mark.parametrize("shape", [(2, 8, 32), (1, 13, 64), (3, 4, 96), (2, 64, 128), (3, 1, 32), (2, 2, 96)])
 def test_forward_matches_oracle(shape):
     """Random weights: the two sides sum in different orders, so an activation that
     lies within FP32 noise of a bf16 rounding boundary can round one ulp apart (one
