@@ -58,6 +58,12 @@ __device__ __forceinline__ u16 bf16_bits(float f)
     return (u16)(u >> 16);
 }
 __device__ __forceinline__ float bf16_val(u16 b) { return __uint_as_float((unsigned)b << 16); }
+// two fp32 -> packed bf16 bits (lo, hi), round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned bf16_pair(float lo, float hi)
+{
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(unsigned, v);
+}
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 // Row of a tile's halo, i in [-2, n + 9]: periodic for i <= n + 1; rows further out
@@ -130,7 +136,7 @@ struct TapPlanes {
 };
 
 template <int CIN, int MODE>
-__global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
+__global__ __launch_bounds__(NBLK, 3) void k_conv_mfma(const u16* __restrict__ in,
                                                     const u16* __restrict__ wfrag,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ mask,
@@ -155,7 +161,8 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         bw[q] = *reinterpret_cast<const bf16x8*>(wfrag + ((size_t)q * 64 + lane) * 8);
     const int m = lane & 31, kh = lane >> 5;
     const int co = m;
-    const float bco = MODE != 1 ? bias[co] : 0.0f;
+    __shared__ __align__(16) float sbias[32];
+    if (MODE != 1 && threadIdx.x < 32) sbias[threadIdx.x] = bias[threadIdx.x];  // read after the loop's barrier
     // MODE 3: W4 as the A operand of the contraction, A[tap][k = ci] = W4[tap][16 ks + k]
     // (rows 9..31 zero), kept in LDS (rows of 40 bf16: conflict-free 16-byte reads);
     // lane l reads tap l % 32, channels 16 ks + 8 (l / 32) + j
@@ -175,6 +182,7 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
     float l1s1 = 0.0f, l1s2 = 0.0f, l1b = 0.0f;
     float cs0 = 0.0f, cs1 = 0.0f;  // the next tile's c values (2 per thread)
     __shared__ u16 cpt[MODE == 4 ? CPN : 1];
+    __shared__ __align__(16) float sbeff[MODE == 4 ? 32 : 1];  // the tile's sample's beff per channel
     if constexpr (MODE == 4) {
         static_assert(CPN <= 2 * NBLK, "two c values per thread");
 #pragma unroll
@@ -227,6 +235,10 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         if constexpr (MODE == 4) {
             cpt[threadIdx.x] = bf16_bits(cs0);
             if (threadIdx.x + NBLK < CPN) cpt[threadIdx.x + NBLK] = bf16_bits(cs1);
+            if (threadIdx.x < 32) {
+                const int bt = t / (tiles_x * tiles_y);
+                sbeff[co] = l1b + bf16_val(bf16_bits(ip.M[bt])) * l1s1 + bf16_val(bf16_bits(ip.kappa[bt])) * l1s2;
+            }
         } else {
             const uint4 src[4] = {s0, s1, s2, s3};
 #pragma unroll
@@ -242,9 +254,10 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         if constexpr (MODE == 4) {
             // the first layer on the (CR+2) x (TW+2) = 204 halo pixels, 32 per MFMA:
             // wave wv takes groups wv and wv + 4; tile pixel s = 34 ry + px sits at
-            // c patch rows ry .. ry+2, pixels px .. px+2
+            // c patch rows ry .. ry+2, pixels px .. px+2.  W1 is the A operand, so the
+            // product is transposed: lane l holds pixel 32 grp + l % 32, channels
+            // 8 g + 4 (l / 32) + r in accumulator 4 g + r, stored 4 channels at a time
             constexpr int NPX = (CR + 2) * (TW + 2);
-            const float beff = l1b + bf16_val(bf16_bits(ip.M[b])) * l1s1 + bf16_val(bf16_bits(ip.kappa[b])) * l1s2;
 #pragma unroll
             for (int gq = 0; gq < 2; ++gq) {
                 const int grp = wv + 4 * gq;
@@ -259,12 +272,17 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
                         a[j] = __builtin_bit_cast(__bf16, bits);
                     }
                     f32x16 a1 = {};
-                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, l1f, a1, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l1f, a, a1, 0, 0, 0);
+                    const int s = 32 * grp + m;
+                    if (s < NPX) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int s = 32 * grp + 8 * (i >> 2) + 4 * kh + (i & 3);
-                        if (s < NPX)
-                            *reinterpret_cast<u16*>(lds + s * PS + co * 2) = bf16_bits(fmaxf(a1[i] + beff, 0.0f));
+                        for (int g4 = 0; g4 < 4; ++g4) {
+                            const float4 be = *reinterpret_cast<const float4*>(sbeff + 8 * g4 + 4 * kh);
+                            const uint2 o = make_uint2(
+                                bf16_pair(fmaxf(a1[4 * g4] + be.x, 0.0f), fmaxf(a1[4 * g4 + 1] + be.y, 0.0f)),
+                                bf16_pair(fmaxf(a1[4 * g4 + 2] + be.z, 0.0f), fmaxf(a1[4 * g4 + 3] + be.w, 0.0f)));
+                            *reinterpret_cast<uint2*>(lds + s * PS + (8 * g4 + 4 * kh) * 2) = o;
+                        }
                     }
                 }
             }
@@ -282,7 +300,9 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const bf16x8 a = *reinterpret_cast<const bf16x8*>(rowp + (ks * 16 + kh * 8) * 2);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[tap * KS + ks], acc, 0, 0, 0);
+                    // the weights as the A operand: the product is transposed, so the
+                    // epilogue packs whole channel groups of a pixel
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[tap * KS + ks], a, acc, 0, 0, 0);
                 }
             }
         }
@@ -290,12 +310,23 @@ __global__ __launch_bounds__(NBLK) void k_conv_mfma(const u16* __restrict__ in,
         // free once every wave has its products) so that each lane stores whole
         // 16-byte channel groups: lane l writes pixel l / 2, channels 16 (l % 2) ...
         __syncthreads();
+        // lane l holds pixel l % 32, channels 8 g + 4 (l / 32) + r in accumulator 4 g + r:
+        // four channels (8 bytes) per write into the wave's [pixel][channel] transpose
         unsigned char* ot = lds + wv * TW * OST;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int px = 8 * (i >> 2) + 4 * kh + (i & 3);
-            const float v = MODE != 1 ? fmaxf(acc[i] + bco, 0.0f) : acc[i];
-            *reinterpret_cast<u16*>(ot + px * OST + co * 2) = bf16_bits(v);
+        for (int g4 = 0; g4 < 4; ++g4) {
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = acc[4 * g4 + r];
+            if constexpr (MODE != 1) {
+                const float4 bg = *reinterpret_cast<const float4*>(sbias + 8 * g4 + 4 * kh);
+                v[0] = fmaxf(v[0] + bg.x, 0.0f);
+                v[1] = fmaxf(v[1] + bg.y, 0.0f);
+                v[2] = fmaxf(v[2] + bg.z, 0.0f);
+                v[3] = fmaxf(v[3] + bg.w, 0.0f);
+            }
+            *reinterpret_cast<uint2*>(ot + m * OST + (8 * g4 + 4 * kh) * 2) =
+                make_uint2(bf16_pair(v[0], v[1]), bf16_pair(v[2], v[3]));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
