@@ -420,6 +420,7 @@ __global__ __launch_bounds__(NBLK) void k_wgrad_mfma(const u16* __restrict__ ain
             for (int j = 0; j < 8; ++j) {
                 const u16 bits = lg[(k0 + 8 * kh + j) * 32 + m];
                 bg[j] = __builtin_bit_cast(__bf16, bits);
+                if (wv == 0) db += bf16_val(bits);  // the bias gradient: lane (co, kh) sums its half
             }
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
@@ -441,9 +442,9 @@ __global__ __launch_bounds__(NBLK) void k_wgrad_mfma(const u16* __restrict__ ain
                 }
             }
         }
-        if (wv == 0 && lane < 32)
-            for (int p = 0; p < TR * TW; ++p) db += bf16_val(lg[p * 32 + lane]);
     }
+    // lanes co and co + 32 of wave 0 hold the two halves of the pixels
+    db += __shfl_down(db, 32);
     // write this block's partial: C[ci][co] tile per tap
     float* pb = part + (size_t)blockIdx.x * 9 * 32 * 32;
 #pragma unroll
