@@ -96,77 +96,93 @@ constexpr int JPF = 4;  // rows in flight per field
 
 // wave -> (strip, chunk), strips fastest (neighbouring waves share their rows);
 // chunk c holds rows [c ty, min(ny, (c + 1) ty)).  bytes: one plane.
-template <typename T, int MODEL, bool MIRROR>
+// PQ (Allen-Cahn, for conjugate gradients): also pq[block] = the block's share of
+// v . Jv in FP64 (every node is stored by exactly one lane), fixed order.
+template <typename T, int MODEL, bool MIRROR, bool PQ = false>
 __global__ __launch_bounds__(256) void k_jvp2d(const T* __restrict__ U, const T* __restrict__ V,
                                                T* __restrict__ Jv, int nx, int ny, int nstrips, int nwaves,
-                                               int ty, unsigned bytes, JCoef<T> k)
+                                               int ty, unsigned bytes, JCoef<T> k, double* __restrict__ pq)
 {
+    static_assert(!PQ || MODEL == 0, "v . Jv for the Allen-Cahn product");
     constexpr int OUTW = WAVE - 2;
     const int wid = uniform_wave();
-    if (wid >= nwaves) return;
-    const int strip = wid % nstrips, chunk = wid / nstrips;
-    const int y0 = chunk * ty, y1 = min(ny, y0 + ty);
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int xl = strip * OUTW - 1 + lane;
-    int x;
-    if constexpr (MIRROR) {
-        x = reflect(xl, nx);
-    } else {
-        x = xl % nx;
-        if (x < 0) x += nx;
-    }
-    const bool out_lane = lane >= 1 && lane < WAVE - 1 && xl < nx;
-    T xs = (T)1;  // no-flux: 1 / 2 on the first and last columns
-    if constexpr (MIRROR) xs = (x == 0 || x == nx - 1) ? (T)0.5 : (T)1;
-    const int iters = (y1 - y0) + 2;  // rows y0-1 .. y1
-    const int rowb = nx * (int)sizeof(T);
-    const int vx = x * (int)sizeof(T);
-    const auto ru = make_rsrc(U, bytes);
-    const auto rv = make_rsrc(V, bytes);
-    const auto rw = make_rsrc(MODEL == 1 ? V + (size_t)nx * ny : V, bytes);
-    const auto r0 = make_rsrc(Jv, bytes);
-    const auto r1 = make_rsrc(MODEL == 1 ? Jv + (size_t)nx * ny : Jv, bytes);
-    // the rows read lie in [-1, ny]: one wrap (periodic) or one reflection about
-    // the end row (no-flux; ny >= 2) maps them onto the grid
-    auto row_off = [&](int t) {
-        int r = min(y0 - 1 + t, y1);  // past the chunk the last row is read again (a cache hit)
+    double pqs = 0.0;
+    if (!PQ && wid >= nwaves) return;
+    if (wid < nwaves) {
+        const int strip = wid % nstrips, chunk = wid / nstrips;
+        const int y0 = chunk * ty, y1 = min(ny, y0 + ty);
+        const int lane = threadIdx.x & (WAVE - 1);
+        const int xl = strip * OUTW - 1 + lane;
+        int x;
         if constexpr (MIRROR) {
-            r = r < 0 ? -r : (r >= ny ? 2 * (ny - 1) - r : r);
+            x = reflect(xl, nx);
         } else {
-            r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+            x = xl % nx;
+            if (x < 0) x += nx;
         }
-        return r * rowb;
-    };
-    T ru_[JPF], rv_[JPF], rw_[JPF];
-#pragma unroll
-    for (int u = 0; u < JPF; ++u) {
-        const int off = row_off(u);
-        ru_[u] = bload<T>(ru, vx, off);
-        rv_[u] = bload<T>(rv, vx, off);
-        rw_[u] = MODEL == 1 ? bload<T>(rw, vx, off) : (T)0;
-    }
-    JStage<T, MODEL> st;
-    // the pipeline runs whole groups of JPF rows: the pushes past the chunk compute
-    // rows nobody stores, so neither the loads nor the pushes need a branch
-    for (int t0 = 0; t0 < iters; t0 += JPF) {
-#pragma unroll
+        const bool out_lane = lane >= 1 && lane < WAVE - 1 && xl < nx;
+        T xs = (T)1;  // no-flux: 1 / 2 on the first and last columns
+        if constexpr (MIRROR) xs = (x == 0 || x == nx - 1) ? (T)0.5 : (T)1;
+        const int iters = (y1 - y0) + 2;  // rows y0-1 .. y1
+        const int rowb = nx * (int)sizeof(T);
+        const int vx = x * (int)sizeof(T);
+        const auto ru = make_rsrc(U, bytes);
+        const auto rv = make_rsrc(V, bytes);
+        const auto rw = make_rsrc(MODEL == 1 ? V + (size_t)nx * ny : V, bytes);
+        const auto r0 = make_rsrc(Jv, bytes);
+        const auto r1 = make_rsrc(MODEL == 1 ? Jv + (size_t)nx * ny : Jv, bytes);
+        // the rows read lie in [-1, ny]: one wrap (periodic) or one reflection about
+        // the end row (no-flux; ny >= 2) maps them onto the grid
+        auto row_off = [&](int t) {
+            int r = min(y0 - 1 + t, y1);  // past the chunk the last row is read again (a cache hit)
+            if constexpr (MIRROR) {
+                r = r < 0 ? -r : (r >= ny ? 2 * (ny - 1) - r : r);
+            } else {
+                r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+            }
+            return r * rowb;
+        };
+        T ru_[JPF], rv_[JPF], rw_[JPF];
+    #pragma unroll
         for (int u = 0; u < JPF; ++u) {
-            const int t = t0 + u;
-            const T cu = ru_[u], cv = rv_[u], cw = rw_[u];
-            const int off = row_off(t + JPF);
+            const int off = row_off(u);
             ru_[u] = bload<T>(ru, vx, off);
             rv_[u] = bload<T>(rv, vx, off);
-            if constexpr (MODEL == 1) rw_[u] = bload<T>(rw, vx, off);
-            T o0, o1;
-            st.push(cu, cv, cw, k, o0, o1);
-            if (t >= 2 && t < iters && out_lane) {
-                const int yo = y0 - 2 + t;  // output row
-                T sc = xs;
-                if constexpr (MIRROR) sc = (yo == 0 || yo == ny - 1) ? xs * (T)0.5 : xs;
-                bstore(MIRROR ? o0 * sc : o0, r0, vx, yo * rowb);
-                if constexpr (MODEL == 1) bstore(MIRROR ? o1 * sc : o1, r1, vx, yo * rowb);
+            rw_[u] = MODEL == 1 ? bload<T>(rw, vx, off) : (T)0;
+        }
+        JStage<T, MODEL> st;
+        // the pipeline runs whole groups of JPF rows: the pushes past the chunk compute
+        // rows nobody stores, so neither the loads nor the pushes need a branch
+        for (int t0 = 0; t0 < iters; t0 += JPF) {
+    #pragma unroll
+            for (int u = 0; u < JPF; ++u) {
+                const int t = t0 + u;
+                const T cu = ru_[u], cv = rv_[u], cw = rw_[u];
+                const int off = row_off(t + JPF);
+                ru_[u] = bload<T>(ru, vx, off);
+                rv_[u] = bload<T>(rv, vx, off);
+                if constexpr (MODEL == 1) rw_[u] = bload<T>(rw, vx, off);
+                const T vprev = st.v1;  // v at the output row
+                T o0, o1;
+                st.push(cu, cv, cw, k, o0, o1);
+                if (t >= 2 && t < iters && out_lane) {
+                    const int yo = y0 - 2 + t;  // output row
+                    T sc = xs;
+                    if constexpr (MIRROR) sc = (yo == 0 || yo == ny - 1) ? xs * (T)0.5 : xs;
+                    const T q0 = MIRROR ? o0 * sc : o0;
+                    bstore(q0, r0, vx, yo * rowb);
+                    if constexpr (MODEL == 1) bstore(MIRROR ? o1 * sc : o1, r1, vx, yo * rowb);
+                    if constexpr (PQ) pqs += (double)vprev * (double)q0;
+                }
             }
         }
+    }
+    if constexpr (PQ) {
+        for (int off = WAVE / 2; off > 0; off >>= 1) pqs += __shfl_down(pqs, off, WAVE);
+        __shared__ double sh[4];
+        if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = pqs;
+        __syncthreads();
+        if (threadIdx.x == 0) pq[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     }
 }
 
@@ -186,9 +202,11 @@ int device_cus()
 
 template <typename T>
 bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                         double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s)
+                         double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, double* pq, int* pq_blocks,
+                         int pq_max)
 {
     if (g.dim != 2 || g.cm || g.quad || tune_jvp2d_stream() == 1) return false;
+    if (pq && model != 0) return false;
     const int nx = g.n[0], ny = g.n[1];
     // buffer offsets are 32-bit: one plane must stay below 2^31 bytes
     if ((size_t)g.N * sizeof(T) >= (size_t(1) << 31)) return false;
@@ -218,21 +236,25 @@ bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double k
     const long long nwaves = (long long)nstrips * nchunks;
     if (nwaves > (1ll << 30)) return false;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
+    if (pq && (int)blocks > pq_max) return false;
     const unsigned bytes = (unsigned)((size_t)g.N * sizeof(T));
-#define JVP2D(MODEL, MIR) \
-    k_jvp2d<T, MODEL, MIR><<<blocks, 256, 0, s>>>(U, v, Jv, nx, ny, nstrips, (int)nwaves, ty, bytes, k)
-    if (model == 0) {
-        if (g.bc) JVP2D(0, true); else JVP2D(0, false);
+#define JVP2D(MODEL, MIR, PQ) \
+    k_jvp2d<T, MODEL, MIR, PQ><<<blocks, 256, 0, s>>>(U, v, Jv, nx, ny, nstrips, (int)nwaves, ty, bytes, k, pq)
+    if (pq) {
+        if (g.bc) JVP2D(0, true, true); else JVP2D(0, false, true);
+        *pq_blocks = (int)blocks;
+    } else if (model == 0) {
+        if (g.bc) JVP2D(0, true, false); else JVP2D(0, false, false);
     } else {
-        if (g.bc) JVP2D(1, true); else JVP2D(1, false);
+        if (g.bc) JVP2D(1, true, false); else JVP2D(1, false, false);
     }
 #undef JVP2D
     return true;
 }
 
 template bool launch_jvp2d_stream<float>(const Geom&, int, const FreeEnergy&, double, double, double,
-                                         const float*, const float*, float*, hipStream_t);
+                                         const float*, const float*, float*, hipStream_t, double*, int*, int);
 template bool launch_jvp2d_stream<double>(const Geom&, int, const FreeEnergy&, double, double, double,
-                                          const double*, const double*, double*, hipStream_t);
+                                          const double*, const double*, double*, hipStream_t, double*, int*, int);
 
 }  // namespace pfk

@@ -674,14 +674,14 @@ template <typename T>
 __global__ __launch_bounds__(KB) void k_cg_alpha(T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
                                                  const T* __restrict__ p, const T* __restrict__ q,
                                                  const T* __restrict__ pinv, long long n,
-                                                 const double* __restrict__ part2, int nb,
+                                                 const double* __restrict__ part2, int nb2,
                                                  double* __restrict__ part, double* st, double* __restrict__ host)
 {
     __shared__ double sc[1];
     __shared__ double red[1];
     if (cg_block_done(st)) return;
     double v1[1] = {0.0};
-    for (int i = threadIdx.x; i < nb; i += KB) v1[0] += part2[i];
+    for (int i = threadIdx.x; i < nb2; i += KB) v1[0] += part2[i];
     block_sum<1>(v1);
     if (threadIdx.x == 0) red[0] = v1[0];
     __syncthreads();
@@ -907,10 +907,10 @@ void cg_pq(const T* p, const T* q, long long n, double* part2, const double* st,
 }
 template <typename T>
 void cg_alpha(T* x, T* r, T* z, const T* p, const T* q, const T* pinv, long long n, const double* part2,
-              double* part, double* st, double* host, hipStream_t s)
+              double* part, double* st, double* host, hipStream_t s, int nb2)
 {
     const int nb = cg_blocks(n);
-    k_cg_alpha<T><<<nb, KB, 0, s>>>(x, r, z, p, q, pinv, n, part2, nb, part, st, host);
+    k_cg_alpha<T><<<nb, KB, 0, s>>>(x, r, z, p, q, pinv, n, part2, nb2 > 0 ? nb2 : nb, part, st, host);
 }
 #define PF_CG_INST(T)                                                                                      \
     template void cg_start<T>(const T*, const T*, T*, T*, T*, T*, long long, double*, double*, double*,    \
@@ -918,7 +918,7 @@ void cg_alpha(T* x, T* r, T* z, const T* p, const T* q, const T* pinv, long long
     template void cg_dir<T>(const T*, T*, long long, const double*, double*, double*, hipStream_t);        \
     template void cg_pq<T>(const T*, const T*, long long, double*, const double*, hipStream_t);            \
     template void cg_alpha<T>(T*, T*, T*, const T*, const T*, const T*, long long, const double*, double*, \
-                              double*, double*, hipStream_t);
+                              double*, double*, hipStream_t, int);
 PF_CG_INST(float)
 PF_CG_INST(double)
 #undef PF_CG_INST

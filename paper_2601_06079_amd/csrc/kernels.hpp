@@ -80,9 +80,12 @@ int tune_stream2d_rows();  // rows per wave of the 2-D streaming kernels (0: aut
 // Row-streaming 2-D Jacobian product (k_jvp2d.hip): Gauss quadrature, lumped
 // mass, periodic or no-flux; the non-transposed product, which for Allen-Cahn is
 // also its transpose.  Returns false (nothing launched) where it does not apply.
+// pq (Allen-Cahn only): also the per-block FP64 partial sums of v . Jv, at most
+// pq_max of them, their count in *pq_blocks.
 template <typename T>
 bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double kappa, double mob,
-                         double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s);
+                         double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, double* pq = nullptr,
+                         int* pq_blocks = nullptr, int pq_max = 0);
 
 // grain growth (PF_GRAIN, 2-D): one explicit step (residual = 0) or the residual
 // (residual = 1) of all P order parameters; LDS bytes per block of the tile kernel

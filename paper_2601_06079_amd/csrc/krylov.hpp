@@ -77,9 +77,10 @@ void cg_dir(const T* z, T* p, long long n, const double* part, double* st, doubl
 // partials of p.q (q = J p)
 template <typename T>
 void cg_pq(const T* p, const T* q, long long n, double* part2, const double* st, hipStream_t s);
-// alpha = r.z / p.q; x += alpha p, r -= alpha q, z = P^-1 r; partials (r.z, r.r)
+// alpha = r.z / p.q; x += alpha p, r -= alpha q, z = P^-1 r; partials (r.z, r.r).
+// nb2: the number of p.q partials in part2 (0: cg_blocks(n), as cg_pq writes them)
 template <typename T>
 void cg_alpha(T* x, T* r, T* z, const T* p, const T* q, const T* pinv, long long n, const double* part2,
-              double* part, double* st, double* host, hipStream_t s);
+              double* part, double* st, double* host, hipStream_t s, int nb2 = 0);
 
 }  // namespace pfk

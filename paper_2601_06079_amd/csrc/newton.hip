@@ -36,6 +36,7 @@ struct NWS {
     T *R, *x, *w, *z, *b, *V, *pinv;
     long long ld;
     double *part, *dev;  // dev: [h1(MAXM+1) | h2(MAXM+1) | nrm(2) | y(MAXM) | misc(8)]
+    long long part_len;  // doubles in part
     double* theta;       // device copy of a host theta_bar (pf_vjp with PF_VJP_THETA_HOST)
     size_t bytes;
 };
@@ -66,6 +67,7 @@ NWS<T> layout(const pf_problem* p, void* base)
                                : p->model == PF_GRAIN ? p->nfields : 1) * g.N * sizeof(T));
     const long long nbp = std::max<long long>(pfk::krylov_blocks(n), (g.N + 255) / 256);
     L.part = (double*)take((size_t)(MAXM + 2) * nbp * sizeof(double) + 64);
+    L.part_len = (long long)(MAXM + 2) * nbp;
     L.dev = (double*)take(4 * (MAXM + 8) * sizeof(double));
     L.theta = (double*)take(4 * sizeof(double));
     L.bytes = off;
@@ -189,6 +191,15 @@ struct LinOp {
             pfk::launch_gg_jvp2d<T>(g, p->nfields, p->mobility, p->kappa, p->gamma, inv_dt, U, v, out, s);
         else
             pfk::launch_jvp<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, trans, 0);
+    }
+    // out = J v with the per-block partial sums of v . out in part2 (at most max_blocks),
+    // their count in *nb; false (nothing launched) where the operator has no such fused
+    // form (then apply and a separate sum are needed)
+    bool apply_pq(const T* v, T* out, double* part2, int* nb, int max_blocks, hipStream_t s) const
+    {
+        if (p->model != PF_ALLEN_CAHN) return false;
+        return pfk::launch_jvp2d_stream<T>(g, p->model, f, p->kappa, p->mobility, inv_dt, U, v, out, s, part2, nb,
+                                           max_blocks);
     }
 };
 
@@ -325,6 +336,8 @@ int pcg(const ColReadback* rb, const LinOp<T>& A, NWS<T>& L, long long n, int ma
     T* q = L.V + 2 * L.ld;
     double* part = L.part;
     double* part2 = L.part + 2 * pfk::cg_blocks(n);
+    // room for part2 in the workspace's partial-sum area (MAXM + 2 rows of nbp)
+    const int pq_max = (int)std::min<long long>(INT_MAX, L.part_len - 2 * pfk::cg_blocks(n));
     double* st = L.dev + DEV_MISC;
     double* hdev = rb->scal_dev();
     const double* h = rb->scal();
@@ -334,9 +347,13 @@ int pcg(const ColReadback* rb, const LinOp<T>& A, NWS<T>& L, long long n, int ma
     bool pending = false;
     for (;;) {
         pfk::cg_dir<T>(L.z, pdir, n, part, st, hdev, s);
-        A.apply(pdir, q, s);
-        pfk::cg_pq<T>(pdir, q, n, part2, st, s);
-        pfk::cg_alpha<T>(L.x, r, L.z, pdir, q, pinv, n, part2, part, st, hdev, s);
+        int nb2 = 0;  // the Jacobian product may leave the p . q partials itself
+        if (!A.apply_pq(pdir, q, part2, &nb2, pq_max, s)) {
+            A.apply(pdir, q, s);
+            pfk::cg_pq<T>(pdir, q, n, part2, st, s);
+            nb2 = 0;
+        }
+        pfk::cg_alpha<T>(L.x, r, L.z, pdir, q, pinv, n, part2, part, st, hdev, s, nb2);
         ++enq;
         if (int rc = check_launch("CG iteration")) return rc;
         if (hipEventRecord(rb->ev[slot], s) != hipSuccess) return check_launch("CG event");
