@@ -111,6 +111,16 @@ class Batch:
     def views(self, U):
         return [U[o:o + nx * ny] for (nx, ny), o in zip(self.sizes, self.offsets)]
 
+    def mse_weights(self):
+        """FP64 weights of the packed layout: 1 / (nx ny) on sample s's nodes, 0 on the
+        padding between samples (built once)."""
+        if getattr(self, "_mse_w", None) is None:
+            w = torch.zeros(self.total, dtype=torch.float64, device=self.device)
+            for (nx, ny), o in zip(self.sizes, self.offsets):
+                w[o:o + nx * ny] = 1.0 / (nx * ny)
+            self._mse_w = w
+        return self._mse_w
+
     def workspace(self, op):
         """Workspace of step or vjp on the fused plan."""
         info = self.info
@@ -246,8 +256,9 @@ def explicit_run(theta, U0, batch, nsteps, every="auto"):
 
 
 def per_sample_mse(batch, U, targets):
-    """sum over samples of mean over nodes (U_s - target_s)^2 (FP64 accumulation)."""
-    tot = 0.0
-    for u, t in zip(batch.views(U), batch.views(targets)):
-        tot = tot + ((u.double() - t.double()) ** 2).mean()
-    return tot
+    """sum over samples of mean over nodes (U_s - target_s)^2 (FP64 accumulation), as
+    one weighted sum over the packed batch (a handful of launches, not several per
+    sample); the padding between samples has weight 0 and is masked, whatever it holds."""
+    w = batch.mse_weights()
+    d = torch.where(w > 0, U.double() - targets.double(), 0.0)
+    return (w * d * d).sum()
