@@ -434,8 +434,10 @@ int pf_vjp_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void* 
  * (ks, ty, depth) candidate with HIP events on U_scratch (overwritten) and ws,
  * keeps the fastest per step, records it in the context for later
  * pf_batch_plan calls with zero shape arguments, and leaves its plan in
- * plan_dev / *best.
- * plan_bytes should be pf_batch_plan_size(..., 3, 16, ...).  Host-synchronous. */
+ * plan_dev / *best.  Candidates: ks 1..4, ty 16..48, depth 4 or 8; a candidate whose
+ * plan does not fit plan_bytes is skipped, so plan_bytes should be
+ * pf_batch_plan_size(..., 4, 16, ...) (the narrowest strips, shortest chunks).
+ * Host-synchronous. */
 int pf_batch_autotune(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample* samples, int count, double dt,
                       void* U_scratch, void* ws, void* plan_dev, size_t plan_bytes,
                       pf_batch_info* best, double* best_us_per_step, void* stream);

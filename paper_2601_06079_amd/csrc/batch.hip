@@ -396,7 +396,7 @@ int pf_batch_autotune(pf_ctx* ctx, const pf_problem* base, const pf_batch_sample
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return check_launch("autotune events");
-    const int kss[] = {1, 2, 3};
+    const int kss[] = {1, 2, 3, 4};
     const int tys[] = {16, 24, 32, 48};
     const int depths[] = {4, 8};
     double best_t = -1.0;
