@@ -211,7 +211,7 @@ def test_autotune_picks_a_valid_shape_with_identical_results():
     ref = U0.clone()
     b.step(ref, 12)
     res = b.autotune(U0.clone())
-    assert res["ks"] in (1, 2, 3) and res["us_per_step"] > 0
+    assert res["ks"] in (1, 2, 3, 4) and res["us_per_step"] > 0
     U = U0.clone()
     b.step(U, 12)
     for a, c in zip(b.views(U), b.views(ref)):
