@@ -822,9 +822,11 @@ def surrogate_record(stream, n=512, Bn=16, K=20, dt=0.01):
 
     jump()
     ens.batch.step(U, K, ens.ws)
-    t_fwd = _time_ms(lambda: [model.forward(c, ens.Mt, ens.kt) for _ in range(reps)], stream) / reps
-    t_jump = _time_ms(lambda: [jump() for _ in range(reps)], stream) / reps
-    t_plain = _time_ms(lambda: [ens.batch.step(U, K, ens.ws) for _ in range(reps)], stream) / reps
+    # each: the best of three windows of `reps` calls
+    best = lambda fn: min(_time_ms(lambda: [fn() for _ in range(reps)], stream) for _ in range(3)) / reps
+    t_fwd = best(lambda: model.forward(c, ens.Mt, ens.kt))
+    t_jump = best(jump)
+    t_plain = best(lambda: ens.batch.step(U, K, ens.ws))
     flop = 39168.0 * Bn * n * n
     return {"workload": f"{Bn} x {n}^2 Cahn-Hilliard, K = {K} steps of dt = {dt}",
             "network_forward_ms": t_fwd, "checked_jump_ms": t_jump, "plain_K_steps_ms": t_plain,
