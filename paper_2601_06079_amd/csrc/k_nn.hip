@@ -673,6 +673,36 @@ __global__ __launch_bounds__(NBLK) void k_project(const float* __restrict__ c, c
     }
 }
 
+// Inference: c_hat = c + d - mean(d), the mean reduced by every block from the sample's
+// partials exactly as k_sample_mean does (so bitwise its value); 4 pixels per thread,
+// blockIdx.y = sample.  Needs HW % 4 == 0 and 16-byte aligned c, d, c_hat.
+__global__ __launch_bounds__(NBLK) void k_project_mean(const float* __restrict__ c, const float* __restrict__ d,
+                                                       const double* __restrict__ part, int nbs,
+                                                       float* __restrict__ chat, int HW)
+{
+    const int b = blockIdx.y;
+    __shared__ double sh[NBLK];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nbs; i += NBLK) a += part[(size_t)b * nbs + i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = NBLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double mean = sh[0] / (double)HW;
+    const int i4 = (blockIdx.x * NBLK + threadIdx.x) * 4;
+    if (i4 >= HW) return;
+    const size_t p = (size_t)b * HW + i4;
+    const float4 cv = *reinterpret_cast<const float4*>(c + p), dv = *reinterpret_cast<const float4*>(d + p);
+    float4 o;
+    o.x = cv.x + (float)((double)dv.x - mean);
+    o.y = cv.y + (float)((double)dv.y - mean);
+    o.z = cv.z + (float)((double)dv.z - mean);
+    o.w = cv.w + (float)((double)dv.w - mean);
+    *reinterpret_cast<float4*>(chat + p) = o;
+}
+
 // g <- g - mean(g) (backward of the mass projection)
 __global__ __launch_bounds__(NBLK) void k_center(float* __restrict__ g, const double* __restrict__ mean,
                                                  int B, int HW)
@@ -1002,12 +1032,20 @@ void nn_conv3_taps(const u16* in, const u16* frag, const float* bias, const u16*
                                           TapPlanes{w4, P, (long long)B * H * W});
 }
 
-void nn_out_taps(const float* P, const float* params, float* d, double* part, double* mean, int B, int H, int W,
-                 hipStream_t s)
+void nn_out_taps_project(const float* P, const float* params, const float* c, float* d, double* part,
+                         double* mean, float* chat, int B, int H, int W, hipStream_t s)
 {
     const int HW = H * W, nbs = (HW + NBLK - 1) / NBLK;
     k_out_taps<<<(unsigned)(B * nbs), NBLK, 0, s>>>(P, (long long)B * HW, params, nn_offsets(), d, part, H, W);
-    k_sample_mean<<<B, NBLK, 0, s>>>(part, nbs, HW, mean);
+    const bool vec = HW % 4 == 0 && ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(d) |
+                                      reinterpret_cast<uintptr_t>(chat)) & 15) == 0;
+    if (vec) {
+        k_project_mean<<<dim3((unsigned)((HW / 4 + NBLK - 1) / NBLK), (unsigned)B), NBLK, 0, s>>>(c, d, part, nbs,
+                                                                                                chat, HW);
+    } else {
+        k_sample_mean<<<B, NBLK, 0, s>>>(part, nbs, HW, mean);
+        nn_project(c, d, mean, nullptr, chat, nullptr, nullptr, B, HW, s);
+    }
 }
 
 void nn_wgrad(int layer, const u16* ain, const u16* g, float* part, float* partb, int B, int H, int W,

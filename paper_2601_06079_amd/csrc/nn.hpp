@@ -36,9 +36,11 @@ void nn_conv12_planes(const float* c, const float* M, const float* kappa, const 
 // P[tap][p] = sum_ci W4[tap][ci] a3[p][ci] (FP32, 9 planes of B H W); a3 is not stored
 void nn_conv3_taps(const unsigned short* in, const unsigned short* frag, const float* bias,
                    const unsigned short* w4, float* P, int B, int H, int W, hipStream_t s);
-// d = b4 + sum_tap P[tap][p + tap] and the per-sample means of d (part: B ceil(H W / 256))
-void nn_out_taps(const float* P, const float* params, float* d, double* part, double* mean, int B, int H,
-                 int W, hipStream_t s);
+// d = b4 + sum_tap P[tap][p + tap], then c_hat = c + d - mean(d) per sample
+// (part: B ceil(H W / 256) doubles; mean: B doubles, used where c, d, c_hat are not
+// 16-byte aligned)
+void nn_out_taps_project(const float* P, const float* params, const float* c, float* d, double* part,
+                         double* mean, float* chat, int B, int H, int W, hipStream_t s);
 // weight gradient partials of hidden layer `layer` (part: blocks x 9 x 32 x 32, partb: blocks x 32)
 void nn_wgrad(int layer, const unsigned short* ain, const unsigned short* g, float* part, float* partb,
               int B, int H, int W, hipStream_t s);

@@ -84,7 +84,8 @@ void forward(const float* params, int B, int H, int W, const float* c, const flo
                               H, W, s);
         float* P = reinterpret_cast<float*>(L.a3);  // 36 of a3's 64 bytes per pixel
         pfk::nn_conv3_taps(L.a2, L.frag + fo.f3, params + o.b3, L.w4, P, B, H, W, s);
-        pfk::nn_out_taps(P, params, L.d, L.spart, L.mean, B, H, W, s);
+        pfk::nn_out_taps_project(P, params, c, L.d, L.spart, L.mean, chat, B, H, W, s);
+        return;
     }
     pfk::nn_project(c, L.d, L.mean, target, chat, L.g, L.r2, B, HW, s);
 }

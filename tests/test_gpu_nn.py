@@ -154,6 +154,27 @@ def test_forward_sample_groups_bitwise(group):
     assert rel_l2(host(ref) - c, o - c) < 5e-3
 
 
+def test_forward_unaligned_buffers_bitwise():
+    """c and c_hat at a 4-byte offset take the projection's scalar path; it gives the
+    bits of the vectorised one (the same mean and the same per-pixel formula)."""
+    announce("nn forward unaligned")
+    Bn, H, W = 3, 8, 64
+    c, M, k, _ = _inputs(Bn, H, W, 17)
+    p = _params(18)
+    model = NN.Surrogate(params=p)
+    Md, kd = _dev(M), _dev(k)  # kept alive until the asynchronous call has read them
+    ref = model.forward(_dev(c), Md, kd).clone()
+    n = Bn * H * W
+    cbuf = torch.zeros(n + 1, dtype=F32, device="cuda")
+    cbuf[1:] = _dev(c).reshape(-1)
+    obuf = torch.zeros(n + 1, dtype=F32, device="cuda")
+    cu, ou = cbuf[1:].view(Bn, H, W), obuf[1:].view(Bn, H, W)
+    A.check(model.L.pf_nn_forward(NN._p(model.params), Bn, H, W, NN._p(cu), NN._p(Md), NN._p(kd),
+                                  NN._p(ou), NN._p(model.workspace(Bn, H, W)), NN._stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(ou, ref)
+
+
 @pytest.mark.parametrize("shape", [(2, 8, 32), (2, 12, 64)])
 def test_backward_matches_oracle(shape):
     announce("nn backward", shape)
