@@ -121,6 +121,12 @@ class Batch:
             self._mse_w = w
         return self._mse_w
 
+    def side_stream(self):
+        """A second stream (default priority) for work that overlaps the caller's."""
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        return self._side
+
     def workspace(self, op):
         """Workspace of step or vjp on the fused plan."""
         info = self.info
@@ -229,13 +235,31 @@ class BatchedExplicitRun(torch.autograd.Function):
                 b.vjp(ctx.traj, lam, tb, ctx.nsteps, ws, begin=True, end=True)
             ctx.traj = None
             return tb.view(b.count, 3), lam, None, None, None
-        seg = torch.empty((every, b.total), dtype=b.dtype, device=b.device)
-        nseg = len(ctx.snaps)
-        for i, snap in enumerate(reversed(ctx.snaps)):
-            seg[0].copy_(snap)
+        snaps = ctx.snaps[::-1]
+        nseg = len(snaps)
+        # two segment buffers: while the adjoint walks segment i on the caller's
+        # stream, a second stream recomputes segment i + 1 from its snapshot, so
+        # each launch's tail is filled by the other kernel
+        seg = [torch.empty((every, b.total), dtype=b.dtype, device=b.device)
+               for _ in range(min(nseg, 2))]
+        main = torch.cuda.current_stream(b.device)
+        side = b.side_stream()
+
+        def recompute(j):
+            buf = seg[j % 2]
+            buf[0].copy_(snaps[j])
             if every > 1:
-                b.step(seg[0], every - 1, traj=seg[1])
-            b.vjp(seg, lam, tb, every, ws, begin=(i == 0), end=(i == nseg - 1))
+                b.step(buf[0], every - 1, traj=buf[1])
+
+        recompute(0)
+        for i in range(nseg):
+            if i + 1 < nseg:
+                side.wait_stream(main)  # the adjoint of segment i - 1 has released its buffer
+                with torch.cuda.stream(side):
+                    recompute(i + 1)
+            b.vjp(seg[i % 2], lam, tb, every, ws, begin=(i == 0), end=(i == nseg - 1))
+            if i + 1 < nseg:
+                main.wait_stream(side)
         return tb.view(b.count, 3), lam, None, None, None
 
 
