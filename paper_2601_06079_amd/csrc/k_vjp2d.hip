@@ -114,6 +114,20 @@ struct VjpStage {
     }
 };
 
+// 1 or 0 from a wave-uniform condition, selected in a scalar register
+template <typename T>
+__device__ __forceinline__ T unit_if(bool c);
+template <>
+__device__ __forceinline__ float unit_if<float>(bool c)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(c ? 0x3f800000 : 0));
+}
+template <>
+__device__ __forceinline__ double unit_if<double>(bool c)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(c ? 0x3ff00000 : 0), 0);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -162,7 +176,9 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
     int rlast = y1 + KS - 1;
     while (rlast >= ny) rlast -= ny;
     T elo_prev = 0;  // eta_lo of the row before the current one (KS = 2)
-    double accA = 0.0, accB = 0.0;
+    // the lane's sums down the chunk in the field's precision (FP64 from the
+    // wave sum on); rows outside the chunk enter with a wave-uniform weight 0
+    T accA = 0, accB = 0;
     for (int t0 = 0; t0 < iters; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -184,24 +200,22 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
             // stage 0 finishes row y0 - KS - 1 + t (and the element row above it)
             T a, b;
             T v = st[0].push(vh, vl, k, a, b);
-            if (t >= KS + 1 && t < (y1 - y0) + KS + 1) {
-                accA += (double)a;
-                accB += (double)b;
-            }
+            const T w0 = unit_if<T>(t >= KS + 1 && t < (y1 - y0) + KS + 1);
+            accA = fmaT(w0, a, accA);
+            accB = fmaT(w0, b, accB);
             if constexpr (KS == 2) {
                 // stage 1 finishes row y0 - 4 + t from lam_k of row y0 - 3 + t
                 v = st[1].push(elo_prev, v, k, a, b);
                 elo_prev = vo;
-                if (t >= 4 && t < iters) {
-                    accA += (double)a;
-                    accB += (double)b;
-                }
+                const T w1 = unit_if<T>(t >= 4 && t < iters);
+                accA = fmaT(w1, a, accA);
+                accB = fmaT(w1, b, accB);
             }
             if (t >= 2 * KS && t < iters && out_lane) bstore(v, ro, vx, (y0 - 2 * KS + t) * rowb);
         }
     }
-    A = out_lane ? accA : 0.0;
-    B = out_lane ? accB : 0.0;
+    A = out_lane ? (double)accA : 0.0;
+    B = out_lane ? (double)accB : 0.0;
 }
 
 // The two-step FP32 kernel holds about 100 VGPRs when the compiler is free to
