@@ -189,9 +189,10 @@ class Batch:
 class BatchedExplicitRun(torch.autograd.Function):
     """U_N = S^N(U_0; theta) for a batch, with a hand-written adjoint.
 
-    every = k: forward keeps a snapshot every k steps; backward walks the segments
-    in reverse, recomputes each segment's states from its snapshot (trajectory
-    mode) and applies the batched step adjoint to them.
+    every = k: forward keeps a snapshot every k steps and the last segment's states;
+    backward walks the segments in reverse, applies the batched step adjoint to
+    each, and meanwhile recomputes the next one's states from its snapshot
+    (trajectory mode) on a second stream.
     every = None: forward writes the whole trajectory (N states) in device memory
     as it runs (trajectory mode), and backward applies the adjoint to it directly,
     with no recomputation; on a 288 GB device this holds, e.g., 2000 states of a
@@ -218,11 +219,21 @@ class BatchedExplicitRun(torch.autograd.Function):
         ws = batch.workspace(A.OP_STEP_EXPLICIT)
         U = U0.detach().clone()
         snaps = []
-        for _ in range(nsteps // every):
+        nseg = nsteps // every
+        ctx.snaps, ctx.last = [], None
+        if nseg == 0:
+            return U
+        for _ in range(nseg - 1):
             snaps.append(U.clone())
             batch.step(U, every, ws)
         ctx.snaps = snaps
-        return U
+        # the last segment runs in trajectory mode: the backward pass starts on
+        # its states without recomputing them
+        last = torch.empty((every + 1, batch.total), dtype=batch.dtype, device=U0.device)
+        last[0].copy_(U)
+        batch.step(last[0], every, traj=last[1])
+        ctx.last = last
+        return last[every].clone()
 
     @staticmethod
     def backward(ctx, gU):
@@ -231,17 +242,26 @@ class BatchedExplicitRun(torch.autograd.Function):
         tb = torch.zeros(b.count * 3, dtype=torch.float64, device=b.device)
         ws = b.workspace(A.OP_VJP)
         if every is None:
+            if ctx.traj is None:
+                raise RuntimeError("the batched adjoint's states were released by an earlier backward")
             if ctx.nsteps:
                 b.vjp(ctx.traj, lam, tb, ctx.nsteps, ws, begin=True, end=True)
             ctx.traj = None
             return tb.view(b.count, 3), lam, None, None, None
-        snaps = ctx.snaps[::-1]
+        if ctx.last is None:
+            if ctx.snaps is None:
+                raise RuntimeError("the batched adjoint's states were released by an earlier backward")
+            return tb.view(b.count, 3), lam, None, None, None  # no steps
+        # segments in reverse; the last one's states were kept by the forward pass
+        snaps = [None] + ctx.snaps[::-1]
         nseg = len(snaps)
         # two segment buffers: while the adjoint walks segment i on the caller's
         # stream, a second stream recomputes segment i + 1 from its snapshot, so
         # each launch's tail is filled by the other kernel
-        seg = [torch.empty((every, b.total), dtype=b.dtype, device=b.device)
-               for _ in range(min(nseg, 2))]
+        seg = [ctx.last]
+        if nseg > 1:
+            seg.append(torch.empty((every, b.total), dtype=b.dtype, device=b.device))
+        ctx.last = ctx.snaps = None
         main = torch.cuda.current_stream(b.device)
         side = b.side_stream()
 
@@ -251,7 +271,6 @@ class BatchedExplicitRun(torch.autograd.Function):
             if every > 1:
                 b.step(buf[0], every - 1, traj=buf[1])
 
-        recompute(0)
         for i in range(nseg):
             if i + 1 < nseg:
                 side.wait_stream(main)  # the adjoint of segment i - 1 has released its buffer

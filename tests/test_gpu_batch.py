@@ -185,6 +185,26 @@ def test_calibration_workload_adjoint_vs_central_fd_fp64():
         assert np.max(rel1) < 1e-3, (k, np.max(rel1))
 
 
+def test_checkpointed_run_zero_steps_and_released_states():
+    """No steps: the output is the input and theta gets a zero gradient.  A second
+    backward through the same run finds its states released and says so."""
+    sizes = [(64, 48)]
+    b = _batch(sizes, [[1.0, 1.1, 0.9]], F32)
+    U0 = b.pack([I.uniform_field(sizes[0], -0.05, 0.05, seed=1)])
+    tgt = b.pack([I.uniform_field(sizes[0], -0.5, 0.5, seed=2)])
+    th = torch.tensor([[1.0, 1.1, 0.9]], dtype=F64, device="cuda", requires_grad=True)
+    UN = B.explicit_run(th, U0, b, 0, every=10)
+    assert torch.equal(UN, U0)
+    B.per_sample_mse(b, UN, tgt).backward()
+    assert torch.count_nonzero(th.grad) == 0
+    for every in (10, None):
+        th.grad = None
+        loss = B.per_sample_mse(b, B.explicit_run(th, U0, b, 20, every=every), tgt)
+        loss.backward(retain_graph=True)
+        with pytest.raises(RuntimeError, match="released"):
+            loss.backward()
+
+
 def test_batched_vjp_fp32_matches_oracle_adjoint():
     """FP32 fields (their sums down a chunk kept in FP32, FP64 from the wave sum on)
     against the FP64 discrete adjoint of the same FP32-rounded start, on grids of
