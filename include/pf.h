@@ -417,7 +417,8 @@ int pf_step_explicit_batched(pf_ctx* ctx, const pf_batch_info* info, const void*
  * steps per launch when the plan was built for ks >= 2 (paired from the last
  * step; lam is bitwise that of single steps), else one.  Sensitivities of
  * theta = (mobility, kappa, W)
- * accumulate per work item in FP64 slots kept in ws; with PF_VJP_BEGIN the
+ * accumulate per work item in FP64 slots kept in ws (each lane's terms summed
+ * down its chunk in the field precision first); with PF_VJP_BEGIN the
  * slots are zeroed first, with PF_VJP_END they are summed (fixed order) into
  * theta_bar (device, count x 3 doubles).  A trajectory processed in segments
  * (checkpointing) with BEGIN on the first call and END on the last gives

@@ -22,9 +22,10 @@
 //   dL     = -(dt/m) (W |J| A + kappa B / 3)
 //   dkappa = -(dt/m) L B / 3
 //   dW     = -(dt/m) L |J| A.
-// Each work item (sample, strip, chunk) adds its A and B to its own FP64 slot,
-// so successive launches accumulate a whole trajectory in a fixed order
-// without atomics; one reduction per sample turns the slots into gradients.
+// A lane sums its terms down the chunk in the field's precision; the wave sums
+// them in FP64 and each work item (sample, strip, chunk) adds its A and B to its
+// own FP64 slot, so successive launches accumulate a whole trajectory in a fixed
+// order without atomics; one reduction per sample turns the slots into gradients.
 #include "device.hpp"
 #include "kernels.hpp"
 #include "stream2d.hpp"
