@@ -46,6 +46,9 @@ BYTES_PER_NODE_STEP = 8  # read c, write c (FP32) per launch; mu never leaves th
 # stiffness stencils and the updates; the per-unit figure the roofline is priced with
 # (the sum-factorised kernel itself executes 69)
 FLOPS_PER_NODE_STEP_CH = 80
+# the same split step with Gauss-Lobatto (nodal) quadrature: f' at the node (5), two
+# 5-point stencils (5 each), mu (2) and the update (2)
+FLOPS_PER_NODE_STEP_CH_LOBATTO = 19
 # coupled model, per node-step with every Gauss point evaluated once (FMA = 2):
 # interpolation of c and eta 30, the two sources at 4 points 144 (f_a 8, f_a' 6, f_b 4,
 # f_b' 2, h 7, h' 4, combinations 5), scatters 36, mu/eta'/c' updates 19
@@ -94,6 +97,9 @@ def parse():
                          "Adam) on 16 x 512^2 and print their record")
     ap.add_argument("--nn-forward", type=int, default=0, metavar="ITERS",
                     help="only time ITERS surrogate inference passes on 16 x 512^2 and print their record")
+    ap.add_argument("--lobatto", action="store_true",
+                    help="only the Gauss-Lobatto records (explicit 2048^2 CH at every fusion depth, "
+                         "implicit 2048^2 AC)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the hbm / adjoint / surrogate records (the step alone)")
     ap.add_argument("--traffic", default=None,
@@ -478,7 +484,43 @@ def coupled_record(stream, n=1024, steps=2000):
                          "hbm_gbs": 16 * n * n * steps / (ms * 1e-3) / 1e9}}
 
 
-def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0, krylov=0):
+def lobatto_record(stream, n=2048, steps=2000):
+    """The explicit benchmark workload (Cahn-Hilliard 2048^2 periodic, dt = 0.01, W = 1,
+    kappa = 2, M = 1, h = 1) with Gauss-Lobatto (nodal) quadrature, at every fusion
+    depth (tuning key STREAM2D_FUSE) and at the library's default."""
+    import torch
+
+    from paper_2601_06079_amd import _abi as A
+    from paper_2601_06079_amd import inputs as I
+    from paper_2601_06079_amd import solver as S
+    p = ch_problem(n)
+    p.quad = A.QUAD_LOBATTO
+    c0 = torch.as_tensor(I.uniform_field((n, n), -0.05, 0.05, seed=0, base=0.5), dtype=torch.float32)
+    U0 = torch.cat([c0, torch.zeros_like(c0)]).to("cuda")
+    ws = S.workspace(p, A.OP_STEP_EXPLICIT)
+    old = S.tune_get(A.TUNE_STREAM2D_FUSE)
+    by_ks = {}
+    try:
+        for ks in (0, 1, 2, 3, 4):
+            S.tune_set(A.TUNE_STREAM2D_FUSE, ks)
+            U = U0.clone()
+            S.step_explicit(p, U, 0.01, 240, ws)  # warm-up
+            ms = min(_time_ms(lambda: S.step_explicit(p, U, 0.01, steps, ws), stream) for _ in range(3))
+            by_ks["default" if ks == 0 else f"ks{ks}"] = ms / steps
+    finally:
+        S.tune_set(A.TUNE_STREAM2D_FUSE, old)
+    best = min(by_ks, key=by_ks.get)
+    ms = by_ks["default"]
+    N = n * n
+    return {"workload": f"2D Cahn-Hilliard {n}x{n} periodic, explicit split step, Gauss-Lobatto "
+                        "(nodal) quadrature, dt=0.01, W=1, kappa=2, M=1, FP32", "dof": N,
+            "steps": steps, "ms_per_step": ms, "dof_steps_per_s": N / (ms * 1e-3),
+            "ms_per_step_by_fusion": by_ks, "best": best,
+            "tflops": FLOPS_PER_NODE_STEP_CH_LOBATTO * N / (ms * 1e-3) / 1e12,
+            "flops_per_node_step": FLOPS_PER_NODE_STEP_CH_LOBATTO}
+
+
+def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0, krylov=0, quad=0):
     """The paper's 2-D implicit benchmark shapes (backward Euler, Newton + GMRES(30)
     with block Jacobi, FP32 fields): [0, 100]^2 with n^2 nodes, no-flux,
     f' = 4c(c-1)(c-1/2) (W = 1), M = 1, kappa = 2 (Allen-Cahn) or 1.5 (Cahn-Hilliard);
@@ -492,7 +534,8 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0, krylov=0):
     from paper_2601_06079_amd import solver as S
     ch = model == A.CAHN_HILLIARD
     p = S.Problem(n=(n, n), model=model, fe=A.F_01, dtype=torch.float32, W=1.0,
-                  kappa=1.5 if ch else 2.0, mobility=1.0, h=100.0 / (n - 1), bc=A.NOFLUX, mass=mass)
+                  kappa=1.5 if ch else 2.0, mobility=1.0, h=100.0 / (n - 1), bc=A.NOFLUX, mass=mass,
+                  quad=quad)
     c0 = I.uniform_field((n, n), -0.05, 0.05, seed=0, base=0.5).astype(np.float32)
     U = torch.as_tensor(np.concatenate([c0, np.zeros_like(c0)]) if ch else c0, device="cuda")
     if ch:
@@ -516,6 +559,8 @@ def implicit2d_record(stream, model, n, steps=10, dt=0.05, mass=0, krylov=0):
     name = "Cahn-Hilliard" if ch else "Allen-Cahn"
     dof = n * n
     mname = "consistent mass (all terms Gauss-integrated)" if mass else "lumped mass"
+    if quad == A.QUAD_LOBATTO:
+        mname = "Gauss-Lobatto (nodal) quadrature"
     lin = "CG with point Jacobi" if krylov == A.KRYLOV_CG else "GMRES(30) with block-Jacobi"
     return {"workload": f"2D {name} {n}x{n} on [0,100]^2, no-flux, backward Euler dt={dt}, {mname}, "
                         f"Newton + {lin}, FP32 fields",
@@ -881,7 +926,7 @@ def implicit_record(steps, stream):
 def main():
     args = parse()
     if (args.implicit or args.surrogate_gain or args.adjoint or args.coupled or args.eshelby or args.grain
-            or args.nn_backward or args.nn_forward):
+            or args.nn_backward or args.nn_forward or args.lobatto):
         import torch
         stream = torch.cuda.current_stream()
         if args.grain:
@@ -893,6 +938,11 @@ def main():
             print(json.dumps(eshelby_record(stream, n=(1025, 1025))), flush=True)
         if args.adjoint:
             print(json.dumps(adjoint_record(stream)), flush=True)
+        if args.lobatto:
+            from paper_2601_06079_amd import _abi as A
+            print(json.dumps(lobatto_record(stream)), flush=True)
+            print(json.dumps(implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5,
+                                               quad=A.QUAD_LOBATTO)), flush=True)
         if args.implicit:
             print(json.dumps(implicit_record(args.implicit, stream)), flush=True)
             from paper_2601_06079_amd import _abi as A
@@ -1057,6 +1107,9 @@ def main():
         out["implicit_ch512_2d"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5)
         out["implicit_ch512_2d_consistent"] = implicit2d_record(stream, A.CAHN_HILLIARD, 512, steps=5,
                                                                 mass=A.MASS_CONSISTENT)
+        out["lobatto_ch2048"] = lobatto_record(stream)
+        out["implicit_ac2048_2d_lobatto"] = implicit2d_record(stream, A.ALLEN_CAHN, 2048, steps=5,
+                                                              quad=A.QUAD_LOBATTO)
         out["eshelby_129"] = eshelby_record(stream)
         out["grain_2048"] = grain_record(stream)
         out["grain_implicit_1024"] = grain_implicit_record(stream)

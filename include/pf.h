@@ -297,7 +297,10 @@ typedef struct pf_newton_opts {
     int32_t precond;        /* PF_PRECOND_* (default PF_PRECOND_JACOBI) */
     double lin_rtol_max;    /* inexact-Newton forcing: linear rtol = clamp(0.1 ||R_k||/||R_0||, */
     double lin_rtol_min;    /*   lin_rtol_min, lin_rtol_max) (defaults 1e-2, 1e-6) */
-    int32_t stagnation;     /* 1: also stop when the FP32 rounding floor is reached (see report) */
+    int32_t stagnation;     /* 1: also stop at the field precision's rounding floor: after
+                             * >= 2 corrections ||R_k|| > ||R_{k-1}||/2 while the last
+                             * correction is <= 8 eps max|U|, or ||R_k|| > 0.9 ||R_{k-1}||
+                             * after a correction <= sqrt(eps) max|U| */
     int32_t krylov;         /* PF_KRYLOV_GMRES (default) or PF_KRYLOV_CG; gmres_restart is
                              * ignored by CG, gmres_max_its bounds its iterations */
 } pf_newton_opts;

@@ -425,7 +425,15 @@ int newton_t(const pf_ctx* ctx, const pf_problem* p, double dt, const T* Uold, T
     while (status == PF_OK) {
         if (rk <= o.rtol * r0) { R.converged = 1; R.reason = 0; break; }
         if (rk <= o.atol) { R.converged = 1; R.reason = 1; break; }
-        if (o.stagnation && k >= 2 && rk > 0.5 * rprev && dmax <= 8.0 * eps_of<T>() * umax) {
+        // rounding floor: the residual stopped falling, and either the last correction
+        // was within a few units in the last place of the field, or it left the
+        // residual where it was (within 10%) although it was too small (at most
+        // sqrt(eps) of the field) for the nonlinearity to undo a converged linear
+        // solve -- the residual was rounding noise, whose correction can stay well
+        // above the field's last place
+        if (o.stagnation && k >= 2 && rk > 0.5 * rprev &&
+            (dmax <= 8.0 * eps_of<T>() * umax ||
+             (rk > 0.9 * rprev && dmax <= std::sqrt(eps_of<T>()) * umax))) {
             R.converged = 1;
             R.reason = 2;  // rounding floor of the field precision reached
             break;

@@ -29,8 +29,11 @@ int stream2d_fuse(const pf_problem* p)
     // 2048^2 (128^2 FP64: 1.9 against 2.4 us/step for two; 2048^2: 5.8 against 6.8) and
     // for Cahn-Hilliard below 2048^2, where launches dominate; at 2048^2 and above
     // Cahn-Hilliard on the seam-sharing kernel is fastest with three or four (7.7
-    // us/step at 2048^2; two: 8.1, and 10% slower than three at 8192^2).
-    if (p->model == PF_CAHN_HILLIARD && p->n[0] * p->n[1] >= (1ll << 22)) return 3;
+    // us/step at 2048^2; two: 8.1, and 10% slower than three at 8192^2).  With nodal
+    // quadrature the step is a third of the arithmetic and four are fastest there too
+    // (2048^2: 3.9 us/step; three 4.1, two 4.9).
+    if (p->model == PF_CAHN_HILLIARD && p->quad == PF_QUAD_GAUSS && p->n[0] * p->n[1] >= (1ll << 22))
+        return 3;
     return 4;
 }
 

@@ -149,6 +149,10 @@ def test_launch_shape_defaults(L, C):
     ks, ty, dp = ct.c_int(), ct.c_int(), ct.c_int()
     assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
     assert (ks.value, ty.value, dp.value) == (3, 21, 4)
+    p.quad = A.QUAD_LOBATTO  # nodal quadrature: four steps, 43 strips x 92 chunks of 23 rows
+    assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
+    assert (ks.value, ty.value) == (4, 23)
+    p.quad = A.QUAD_GAUSS
     p.model = A.ALLEN_CAHN  # Allen-Cahn: four steps, 37 strips x 108 chunks of 19 rows
     assert L.pf_launch_shape(C, ct.byref(p), ct.byref(ks), ct.byref(ty), ct.byref(dp)) == A.PF_OK
     assert (ks.value, ty.value) == (4, 19)

@@ -164,6 +164,29 @@ def test_lobatto_newton_step(model, n, bc, dtype):
     assert repc.converged and torch.equal(Uc, Ug)
 
 
+def test_lobatto_newton_full_size_2048_noflux():
+    """The implicit Allen-Cahn shape (2048^2 on [0, 100]^2, no-flux, dt = 0.05) with nodal
+    quadrature in FP32: Newton stops at the FP32 rounding floor.  The oracle's FP64
+    backward-Euler residual of the result is at most 1e-5 of the initial one (the floor
+    is about 1e-6 of it, the FP32 rounding of the field adds about 2e-6), and the field
+    matches the FP64 step within 1e-4 (the floor residual over the Jacobian's smallest
+    eigenvalue h^2 (1/dt - 1) bounds the difference by about 1e-5)."""
+    announce("lobatto newton 2048^2 noflux")
+    n, dt = (2048, 2048), 0.05
+    g, o = lpair(n, O.AC, O.F_01, F32, h=100.0 / 2047, W=1.0, kappa=2.0, mob=1.0, bc=O.NOFLUX)
+    c0 = rounded(I.uniform_field(n, -0.05, 0.05, seed=0, base=0.5), F32)
+    U = dev(c0, F32)
+    rep = S.newton_step(g, dt, dev(c0, F32), U, S.newton_opts())
+    assert rep.converged and rep.reason == 2 and rep.newton_its <= 6, rep
+    g64 = S.Problem(**{**g.__dict__, "dtype": F64})
+    U64 = dev(c0, F64)
+    assert S.newton_step(g64, dt, dev(c0, F64), U64, S.newton_opts()).converged
+    u = host(U).astype(np.float64)
+    r0 = np.linalg.norm(O.be_residual(o, dt, c0, c0))
+    assert np.linalg.norm(O.be_residual(o, dt, c0, u)) <= 1e-5 * r0
+    assert rel_l2(u, host(U64)) < 1e-4
+
+
 def test_lobatto_unsupported_calls():
     """The adjoint, batches, and the coupled and grain models reject nodal quadrature."""
     g, o = lpair((16, 12), O.AC, O.F_SYM, F32)
