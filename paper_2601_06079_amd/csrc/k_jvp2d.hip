@@ -17,6 +17,8 @@
 // No-flux grids read through the even extension about the end nodes; the row
 // of a node on b boundary faces is then 2^b times the no-flux row, so the output
 // is divided by 2^b (the node-centric kernel does the same).
+// With nodal (Gauss-Lobatto) quadrature N'(u) v = m f''(u_a) v_a at the node and K
+// is the 5-point stencil 4 v - (axis neighbours) (h-free in 2-D).
 #include <algorithm>
 
 #include "device.hpp"
@@ -30,15 +32,16 @@ template <typename T>
 struct JCoef {
     T b0, b1, b2;  // f''(q) = b0 + q (b1 + b2 q)
     T mv;          // inv_dt m: the time term of the first row
-    T nq;          // AC: L |J|; CH: |J|
-    T kv;          // AC: L kappa / 3; CH: kappa / 3
-    T kw;          // CH: M / 3
+    T nq;          // AC: L |J|; CH: |J|  (nodal quadrature: L m; m)
+    T kv;          // AC: L kappa / 3; CH: kappa / 3  (nodal: L kappa; kappa)
+    T kw;          // CH: M / 3  (nodal: M)
     T mw;          // CH: m
 };
 
 // One row of the pipeline: push the newest row r of u, v (and w = v_mu for
-// Cahn-Hilliard) and get the output row r - 1.
-template <typename T, int MODEL>
+// Cahn-Hilliard) and get the output row r - 1.  v1 holds v of the output row
+// until the push.
+template <typename T, int MODEL, bool LOB = false>
 struct JStage {
     T xlu = 0, xru = 0, xlv = 0, xrv = 0;  // x-interpolants of row r-1
     T guL = 0, guR = 0;                    // upward scatter of element row (r-2, r-1)
@@ -92,13 +95,40 @@ struct JStage {
     }
 };
 
+// Nodal quadrature: f''(u) v at the node and the 5-point stencil, no interpolation
+// or scatter; the output row is r - 1 as above.
+template <typename T, int MODEL>
+struct JStage<T, MODEL, true> {
+    T u1 = 0, v1 = 0, v2 = 0;  // u and v at row r-1, v at row r-2
+    T w1 = 0, w2 = 0;          // Cahn-Hilliard: w at rows r-1, r-2
+
+    __device__ __forceinline__ void push(T u, T v, T w, const JCoef<T>& k, T& o0, T& o1)
+    {
+        const T fv = fmaT(fmaT(k.b2, u1, k.b1), u1, k.b0) * v1;
+        const T lapv = fmaT((T)4, v1, -((from_left(v1) + from_right(v1)) + (v2 + v)));
+        if constexpr (MODEL == 0) {
+            o0 = fmaT(k.mv, v1, fmaT(k.nq, fv, k.kv * lapv));
+            o1 = (T)0;
+        } else {
+            const T lapw = fmaT((T)4, w1, -((from_left(w1) + from_right(w1)) + (w2 + w)));
+            o0 = fmaT(k.mv, v1, k.kw * lapw);
+            o1 = fmaT(k.mw, w1, -fmaT(k.nq, fv, k.kv * lapv));
+            w2 = w1;
+            w1 = w;
+        }
+        u1 = u;
+        v2 = v1;
+        v1 = v;
+    }
+};
+
 constexpr int JPF = 4;  // rows in flight per field
 
 // wave -> (strip, chunk), strips fastest (neighbouring waves share their rows);
 // chunk c holds rows [c ty, min(ny, (c + 1) ty)).  bytes: one plane.
 // PQ (Allen-Cahn, for conjugate gradients): also pq[block] = the block's share of
 // v . Jv in FP64 (every node is stored by exactly one lane), fixed order.
-template <typename T, int MODEL, bool MIRROR, bool PQ = false>
+template <typename T, int MODEL, bool MIRROR, bool PQ = false, bool LOB = false>
 __global__ __launch_bounds__(256) void k_jvp2d(const T* __restrict__ U, const T* __restrict__ V,
                                                T* __restrict__ Jv, int nx, int ny, int nstrips, int nwaves,
                                                int ty, unsigned bytes, JCoef<T> k, double* __restrict__ pq)
@@ -150,7 +180,7 @@ __global__ __launch_bounds__(256) void k_jvp2d(const T* __restrict__ U, const T*
             rv_[u] = bload<T>(rv, vx, off);
             rw_[u] = MODEL == 1 ? bload<T>(rw, vx, off) : (T)0;
         }
-        JStage<T, MODEL> st;
+        JStage<T, MODEL, LOB> st;
         // the pipeline runs whole groups of JPF rows: the pushes past the chunk compute
         // rows nobody stores, so neither the loads nor the pushes need a branch
         for (int t0 = 0; t0 < iters; t0 += JPF) {
@@ -205,7 +235,7 @@ bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double k
                          double inv_dt, const T* U, const T* v, T* Jv, hipStream_t s, double* pq, int* pq_blocks,
                          int pq_max)
 {
-    if (g.dim != 2 || g.cm || g.quad || tune_jvp2d_stream() == 1) return false;
+    if (g.dim != 2 || g.cm || tune_jvp2d_stream() == 1) return false;
     if (pq && model != 0) return false;
     const int nx = g.n[0], ny = g.n[1];
     // buffer offsets are 32-bit: one plane must stay below 2^31 bytes
@@ -216,13 +246,15 @@ bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double k
     k.b1 = (T)f.b1;
     k.b2 = (T)f.b2;
     k.mv = (T)(inv_dt * m);
+    // Gauss: |J| weights and the (9 v - box v) / 3 stencil; nodal: m and 4 v - nbrs
+    const double wq = g.quad ? m : detJ, ks = g.quad ? 1.0 : 1.0 / 3.0;
     if (model == 0) {
-        k.nq = (T)(mob * detJ);
-        k.kv = (T)(mob * kappa / 3.0);
+        k.nq = (T)(mob * wq);
+        k.kv = (T)(mob * kappa * ks);
     } else {
-        k.nq = (T)detJ;
-        k.kv = (T)(kappa / 3.0);
-        k.kw = (T)(mob / 3.0);
+        k.nq = (T)wq;
+        k.kv = (T)(kappa * ks);
+        k.kw = (T)(mob * ks);
         k.mw = (T)m;
     }
     // chunks for about four waves per SIMD, never shorter than 8 rows
@@ -238,8 +270,15 @@ bool launch_jvp2d_stream(const Geom& g, int model, const FreeEnergy& f, double k
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
     if (pq && (int)blocks > pq_max) return false;
     const unsigned bytes = (unsigned)((size_t)g.N * sizeof(T));
-#define JVP2D(MODEL, MIR, PQ) \
-    k_jvp2d<T, MODEL, MIR, PQ><<<blocks, 256, 0, s>>>(U, v, Jv, nx, ny, nstrips, (int)nwaves, ty, bytes, k, pq)
+#define JVP2D(MODEL, MIR, PQ)                                                                             \
+    do {                                                                                                  \
+        if (g.quad)                                                                                       \
+            k_jvp2d<T, MODEL, MIR, PQ, true>                                                              \
+                <<<blocks, 256, 0, s>>>(U, v, Jv, nx, ny, nstrips, (int)nwaves, ty, bytes, k, pq);        \
+        else                                                                                              \
+            k_jvp2d<T, MODEL, MIR, PQ, false>                                                             \
+                <<<blocks, 256, 0, s>>>(U, v, Jv, nx, ny, nstrips, (int)nwaves, ty, bytes, k, pq);        \
+    } while (0)
     if (pq) {
         if (g.bc) JVP2D(0, true, true); else JVP2D(0, false, true);
         *pq_blocks = (int)blocks;

@@ -1,8 +1,10 @@
 """The row-streaming 2-D Jacobian product (Eq. 14 linearised, Sec. 2.3) against the
 FP64 oracle, element by element: one and several strips (62 output columns) and
 chunks with ragged tails, periodic and no-flux grids, both models, both
-precisions; the node-centric kernel gives the same product to rounding; and the
-benchmark's full 2048^2 no-flux shape."""
+precisions, Gauss and nodal (Gauss-Lobatto) quadrature; the node-centric kernel
+gives the same product to rounding; and the benchmark's full 2048^2 no-flux shape."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -44,12 +46,35 @@ def test_stream_jvp_matches_oracle(n, model, bc, dtype):
         assert rel_l2(Jv, O.jvp(o, inv_dt, U, v)) < TOL[dtype]
 
 
+def _lobatto(g, o):
+    return dataclasses.replace(g, quad=A.QUAD_LOBATTO), dataclasses.replace(o, quad=O.LOBATTO)
+
+
 @pytest.mark.parametrize("dtype", [F32, F64])
 @pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
 @pytest.mark.parametrize("model", [O.AC, O.CH])
-def test_stream_and_node_kernels_agree(model, bc, dtype):
-    announce("jvp2d stream vs node", model, bc, dtype)
+@pytest.mark.parametrize("n", [(2, 2), (3, 5), (63, 17), (130, 97), (517, 300)])
+def test_stream_jvp_nodal_quadrature_matches_oracle(n, model, bc, dtype):
+    """Nodal quadrature: f''(u) v at the node and the 5-point stencil."""
+    announce("jvp2d stream lobatto", n, model, bc, dtype)
+    fe = O.F_01 if model == O.CH else O.F_SYM
+    g, o = _lobatto(*pair(n, model, fe, dtype, h=0.9, W=1.2, kappa=1.7, mob=0.8, bc=bc))
+    U = rounded(_state(o, 23), dtype)
+    v = rounded(np.random.default_rng(24).standard_normal(o.ndof), dtype)
+    for inv_dt in (0.0, 3.0):
+        Jv = host(S.jvp(g, inv_dt, dev(U, dtype), dev(v, dtype)))
+        assert rel_l2(Jv, O.jvp(o, inv_dt, U, v)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.NOFLUX])
+@pytest.mark.parametrize("model", [O.AC, O.CH])
+@pytest.mark.parametrize("quad", [A.QUAD_GAUSS, A.QUAD_LOBATTO])
+def test_stream_and_node_kernels_agree(quad, model, bc, dtype):
+    announce("jvp2d stream vs node", quad, model, bc, dtype)
     g, o = pair((300, 257), model, O.F_01, dtype, h=1.0, W=1.0, kappa=2.0, mob=1.3, bc=bc)
+    if quad == A.QUAD_LOBATTO:
+        g, o = _lobatto(g, o)
     U = dev(rounded(_state(o, 31), dtype), dtype)
     v = dev(rounded(np.random.default_rng(32).standard_normal(o.ndof), dtype), dtype)
     old = S.tune_get(A.TUNE_JVP2D_STREAM)
