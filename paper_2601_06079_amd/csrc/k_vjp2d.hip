@@ -220,8 +220,9 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
 }
 
 // The two-step FP32 kernel holds about 100 VGPRs when the compiler is free to
-// choose; capped at 96 it runs five waves per SIMD instead of four (one value
-// spilled outside the row loop) and the adjoint step takes 8% less time.
+// choose; capped at 96 it runs five waves per SIMD instead of four and the
+// adjoint step takes 8% less time.  The symmetric-well variant then spills three
+// values, one of which is stored and reloaded once per two rows.
 template <typename T, int PF, int KS, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 2 && sizeof(T) == 4 ? 5 : 1)))
 void k_vjp2d_batched(const T* __restrict__ eta_hi,
