@@ -225,14 +225,9 @@ __device__ __forceinline__ void vjp_item(const T* __restrict__ eta_hi, const T* 
 // values, one of which is stored and reloaded once per two rows.
 template <typename T, int PF, int KS, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 2 && sizeof(T) == 4 ? 5 : 1)))
-void k_vjp2d_batched(const T* __restrict__ eta_hi,
-                                                       const T* __restrict__ eta_lo,
-                                                       const T* __restrict__ lam_in,
-                                                       T* __restrict__ lam_out,
-                                                       const BatchSample* __restrict__ smp,
-                                                       const BatchItem* __restrict__ items,
-                                                       int n_items, int ty, int hk,
-                                                       double* __restrict__ part)
+void k_vjp2d_batched(const T* __restrict__ eta_hi, const T* __restrict__ eta_lo, const T* __restrict__ lam_in,
+                     T* __restrict__ lam_out, const BatchSample* __restrict__ smp,
+                     const BatchItem* __restrict__ items, int n_items, int ty, int hk, double* __restrict__ part)
 {
     const int wave = uniform_wave();
     if (wave >= n_items) return;
